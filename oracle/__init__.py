@@ -1,0 +1,6 @@
+"""FP64 CPU oracle for greedy adaptive TT cross -- test infrastructure only.
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this package.  It shares no code with the GPU library.
+"""
+from .oracle import Oracle, fn_eval, splitmix64, sample_indices, matrix_residual, tt_eval  # noqa: F401

@@ -1,0 +1,789 @@
+/*
+ * tt_oracle.c -- plain, slow FP64 CPU oracle for greedy adaptive TT cross.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or helper with the GPU library; the two are compared against
+ * each other on the same seeded inputs.
+ *
+ * What it computes (Shi, Hayes, Qiu, "Distributed memory parallel adaptive
+ * tensor-train cross approximation"):
+ *   - the tensor is a black box evaluated entry by entry (Sec. 5 intro);
+ *   - pivots for every unfolding k = 1..d-1 are found on the superblock
+ *     X_k(I_{<=k-1} x [n_k], [n_{k+1}] x J_{>k+1}) (Alg. 2) by the greedy
+ *     largest-|residual| rule (Alg. 1, full search);
+ *   - the residual on a superblock is obtained from the raw entries by the
+ *     rank-1 recursion of eq. (aca_approx_E) in residual form
+ *       R_{z+1} = R_z - R_z(:,j) R_z(i,:) / R_z(i,j)
+ *     (the paper's last line writes E = A~ - A with a "+": with that sign
+ *     convention the update must be subtracted; the derivation line before it
+ *     fixes the sign);
+ *   - all unfoldings search on the same snapshot of the index sets and commit
+ *     together ("dimension parallel", Sec. 2.3 and Sec. 3.2.3);
+ *   - cores are built from the final pivots by Alg. 4 (eq. aca_approx_T) on the
+ *     sliced fibers X(I_{<=k-1}, :, J_{>k}) and reshaped per eq. (corereshape);
+ *   - accuracy is measured by the sampled relative error of Sec. 5 (reported
+ *     as the square root of the printed ratio) or, on tiny tensors, by brute
+ *     force over every entry (eq. FrobeniusNorm).
+ *
+ * Readings where the paper is silent (stated once here, used below):
+ *   - stop: a sweep in which no unfolding finds |residual| > tau proposes
+ *     nothing and ends the run; tau = eps * rms, with rms taken over N_s seeded
+ *     sample entries;  a k at the rank cap proposes nothing;
+ *   - initial pivot: the sample with the largest |value| (first one on ties),
+ *     replicated as pivot 1 of every unfolding (Alg. 1 starts from samples);
+ *   - tie-break: lowest (row position, column position), where row position =
+ *     p * n_k + i_k with p the insertion index of the prefix in I_{<=k-1} and
+ *     column position = q * n_{k+1} + i_{k+1} with q the insertion index of
+ *     the suffix in J_{>k+1};
+ *   - rows and columns that already hold a pivot are excluded from the search;
+ *   - arithmetic: IEEE double, explicit fma for every multiply-subtract of the
+ *     recursion, plain division, sums in ascending index order; the file is
+ *     compiled with -ffp-contract=off.
+ *
+ * Indices are 0-based at this interface; the generating functions apply the
+ * paper's 1-based formulas internally.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MAX_D 16
+
+enum { ORC_FN_HILBERT = 1, ORC_FN_MAXWELL = 2, ORC_FN_BIMAXWELL = 3, ORC_FN_SEPSUM = 4,
+       ORC_FN_MAXWELL_2D2V = 5, ORC_FN_MAXWELL_3D3V = 6 };
+
+enum { ORC_OK = 0, ORC_NOT_CONVERGED = 1, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_ESINGULAR = -4,
+       ORC_EFN = -6 };
+
+/* ------------------------------------------------------------------------ */
+/* SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): state advances by the golden */
+/* gamma, output is the variant-13 finaliser of the new state.               */
+/* ------------------------------------------------------------------------ */
+static uint64_t orc_sm64(uint64_t *state)
+{
+    uint64_t z = (*state += 0x9E3779B97F4A7C15ULL);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+uint64_t orc_splitmix64_draw(uint64_t seed, int64_t count, uint64_t *out)
+{
+    uint64_t s = seed;
+    for (int64_t t = 0; t < count; ++t) out[t] = orc_sm64(&s);
+    return s;
+}
+
+/* Seeded multi-indices: coordinate j of sample s is draw mod n_j, draws taken */
+/* in (s, j) order from one stream.                                            */
+void orc_sample_indices(int d, const int *n, uint64_t seed, int64_t count, int *idx)
+{
+    uint64_t s = seed;
+    for (int64_t t = 0; t < count; ++t)
+        for (int j = 0; j < d; ++j) idx[t * d + j] = (int)(orc_sm64(&s) % (uint64_t)n[j]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Generating functions.                                                      */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int fn_id;
+    int d;
+    int n[ORC_MAX_D];
+    const double *params;
+    int nparams;
+} orc_fn;
+
+static const double ORC_PI = 3.14159265358979323846;
+
+/* Hilbert tensor, eq. (HilbertTensor): 1 / (sum_j i_j + shift) with 1-based
+ * i_j.  The paper's tensor has shift = 1 - d; params[0] overrides it. */
+static double orc_hilbert(const orc_fn *F, const int *idx)
+{
+    double shift = (F->nparams >= 1) ? F->params[0] : (double)(1 - F->d);
+    long long s = 0;
+    for (int j = 0; j < F->d; ++j) s += (long long)idx[j] + 1;
+    return 1.0 / ((double)s + shift);
+}
+
+/* Velocity grid: cell centres of [-vmax, vmax] split into n cells. */
+static double orc_vel(int i, int n, double vmax)
+{
+    return -vmax + ((double)i + 0.5) * (2.0 * vmax / (double)n);
+}
+
+/* Single 3d3v Maxwellian, modes x1,x2,x3,v1,v2,v3; x on the periodic grid
+ * i/n of [0,1), v cell-centred on [-vmax,vmax].
+ *   f = rho(x) (2 pi T)^{-3/2} exp(-|v - u(x)|^2 / (2T)),
+ *   rho = 1 + a sin(2 pi x1) cos(2 pi x2),  u = (b sin(2 pi x3), 0, 0).
+ * params: [a=0.5, b=0.3, T=1, vmax=8]. */
+static double orc_maxwell(const orc_fn *F, const int *idx)
+{
+    double a = 0.5, b = 0.3, T = 1.0, vmax = 8.0;
+    if (F->nparams >= 4) { a = F->params[0]; b = F->params[1]; T = F->params[2]; vmax = F->params[3]; }
+    double x1 = (double)idx[0] / F->n[0];
+    double x2 = (double)idx[1] / F->n[1];
+    double x3 = (double)idx[2] / F->n[2];
+    double v1 = orc_vel(idx[3], F->n[3], vmax);
+    double v2 = orc_vel(idx[4], F->n[4], vmax);
+    double v3 = orc_vel(idx[5], F->n[5], vmax);
+    double rho = 1.0 + a * sin(2.0 * ORC_PI * x1) * cos(2.0 * ORC_PI * x2);
+    double ux = b * sin(2.0 * ORC_PI * x3);
+    double q = (v1 - ux) * (v1 - ux) + v2 * v2 + v3 * v3;
+    return rho * pow(2.0 * ORC_PI * T, -1.5) * exp(-q / (2.0 * T));
+}
+
+/* Sum of two spatially uniform 3v Maxwellians; the d-3 leading modes are
+ * spatial and f does not depend on them; the last three are v1,v2,v3.
+ * params: [rho1,u1x,u1y,u1z,T1, rho2,u2x,u2y,u2z,T2, vmax=8]. */
+static double orc_bimaxwell(const orc_fn *F, const int *idx)
+{
+    const double *P = F->params;
+    double vmax = (F->nparams >= 11) ? P[10] : 8.0;
+    int d = F->d;
+    double v[3];
+    for (int c = 0; c < 3; ++c) v[c] = orc_vel(idx[d - 3 + c], F->n[d - 3 + c], vmax);
+    double f = 0.0;
+    for (int m = 0; m < 2; ++m) {
+        const double *Q = P + 5 * m;
+        double T = Q[4];
+        double q = 0.0;
+        for (int c = 0; c < 3; ++c) q += (v[c] - Q[1 + c]) * (v[c] - Q[1 + c]);
+        f += Q[0] * pow(2.0 * ORC_PI * T, -1.5) * exp(-q / (2.0 * T));
+    }
+    return f;
+}
+
+/* Sum of r separable products: f = sum_m prod_j g_{m,j}(i_j).
+ * params: [r, g...] with g_{m,j}(i) at 1 + m * sum(n) + (n_0 + .. + n_{j-1}) + i. */
+static double orc_sepsum(const orc_fn *F, const int *idx)
+{
+    int r = (int)F->params[0];
+    int total = 0;
+    for (int j = 0; j < F->d; ++j) total += F->n[j];
+    double f = 0.0;
+    for (int m = 0; m < r; ++m) {
+        double prod = 1.0;
+        int off = 1 + m * total;
+        for (int j = 0; j < F->d; ++j) { prod *= F->params[off + idx[j]]; off += F->n[j]; }
+        f += prod;
+    }
+    return f;
+}
+
+/* The paper's kinetic examples (Sec. 5.2, eq. 2d2vFunction): modes x, v_x, y,
+ * v_y (and z, v_z), x in [-1/2,1/2] and v in [-3,3]; grid points are the cell
+ * centres of those intervals (the paper does not state the grid).
+ *   rho(w) = 1 + 0.875 sin(2 pi w),  T(w) = 0.5 + 0.4 sin(2 pi w),
+ *   f = sum_w rho(w)/(2 sqrt(2 pi T(w))) * [exp(-sum_w b_w^-) + exp(-sum_w b_w^+)],
+ *   b_w^{+-} = |v_w +- 0.75|^2 / (2 T(w)).
+ * For 3d3v the z and v_z terms are added to the spatial sum and to both
+ * exponents (the paper only says "with the addition of z and v_z terms"). */
+static double orc_cell(int i, int n, double lo, double hi)
+{
+    return lo + ((double)i + 0.5) * ((hi - lo) / (double)n);
+}
+
+static double orc_kinetic(const orc_fn *F, const int *idx, int ndim)
+{
+    double pre = 0.0, em = 0.0, ep = 0.0;
+    for (int w = 0; w < ndim; ++w) {
+        double x = orc_cell(idx[2 * w], F->n[2 * w], -0.5, 0.5);
+        double v = orc_cell(idx[2 * w + 1], F->n[2 * w + 1], -3.0, 3.0);
+        double rho = 1.0 + 0.875 * sin(2.0 * ORC_PI * x);
+        double T = 0.5 + 0.4 * sin(2.0 * ORC_PI * x);
+        pre += rho / (2.0 * sqrt(2.0 * ORC_PI * T));
+        em += (v - 0.75) * (v - 0.75) / (2.0 * T);
+        ep += (v + 0.75) * (v + 0.75) / (2.0 * T);
+    }
+    return pre * (exp(-em) + exp(-ep));
+}
+
+static double orc_eval(const orc_fn *F, const int *idx)
+{
+    switch (F->fn_id) {
+    case ORC_FN_HILBERT: return orc_hilbert(F, idx);
+    case ORC_FN_MAXWELL: return orc_maxwell(F, idx);
+    case ORC_FN_BIMAXWELL: return orc_bimaxwell(F, idx);
+    case ORC_FN_SEPSUM: return orc_sepsum(F, idx);
+    case ORC_FN_MAXWELL_2D2V: return orc_kinetic(F, idx, 2);
+    case ORC_FN_MAXWELL_3D3V: return orc_kinetic(F, idx, 3);
+    }
+    return NAN;
+}
+
+static int orc_fn_check(int fn_id, int d, const int *n, const double *params, int nparams)
+{
+    if (d < 2 || d > ORC_MAX_D) return ORC_EINVAL;
+    for (int j = 0; j < d; ++j) if (n[j] < 1) return ORC_EINVAL;
+    switch (fn_id) {
+    case ORC_FN_HILBERT: {
+        double shift = (nparams >= 1) ? params[0] : (double)(1 - d);
+        if ((double)d + shift <= 0.0) return ORC_EFN;    /* smallest denominator */
+        return ORC_OK;
+    }
+    case ORC_FN_MAXWELL: return (d == 6 && (nparams == 0 || nparams >= 4)) ? ORC_OK : ORC_EFN;
+    case ORC_FN_BIMAXWELL: return (d >= 3 && nparams >= 10) ? ORC_OK : ORC_EFN;
+    case ORC_FN_SEPSUM: {
+        if (nparams < 1) return ORC_EFN;
+        int r = (int)params[0], total = 0;
+        for (int j = 0; j < d; ++j) total += n[j];
+        return (r >= 1 && nparams >= 1 + r * total) ? ORC_OK : ORC_EFN;
+    }
+    case ORC_FN_MAXWELL_2D2V: return d == 4 ? ORC_OK : ORC_EFN;
+    case ORC_FN_MAXWELL_3D3V: return d == 6 ? ORC_OK : ORC_EFN;
+    }
+    return ORC_EFN;
+}
+
+/* Evaluate m entries (idx is m x d). */
+int orc_fn_eval(int fn_id, int d, const int *n, const double *params, int nparams,
+                int64_t m, const int *idx, double *out)
+{
+    int st = orc_fn_check(fn_id, d, n, params, nparams);
+    if (st) return st;
+    orc_fn F = { fn_id, d, {0}, params, nparams };
+    for (int j = 0; j < d; ++j) F.n[j] = n[j];
+    for (int64_t t = 0; t < m; ++t) out[t] = orc_eval(&F, idx + t * d);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Solver state.                                                              */
+/* Unfoldings are numbered k = 1..d-1 as in the paper.  I[k] holds the       */
+/* pivot row tuples (i_1..i_k) of X_k, J[k] the column tuples (i_{k+1}..i_d); */
+/* I[0] and J[d] are the single empty tuple.                                  */
+/* ------------------------------------------------------------------------ */
+typedef struct orc_state {
+    orc_fn F;
+    double *params_copy;
+    double eps;
+    uint64_t seed;
+    int r_max, n_samples;
+    int d;
+    int n[ORC_MAX_D];
+    int r[ORC_MAX_D + 1];            /* r[0] = r[d] = 1 */
+    int *I[ORC_MAX_D + 1];           /* I[k]: r_max x k */
+    int *J[ORC_MAX_D + 1];           /* J[k]: r_max x (d-k) */
+    int64_t *rho[ORC_MAX_D + 1];     /* pivot row positions in superblock k */
+    int64_t *gam[ORC_MAX_D + 1];     /* pivot column positions */
+    double *piv[ORC_MAX_D + 1];      /* pivot residuals p_z */
+    double *best_hist[ORC_MAX_D + 1];/* per sweep: largest unmasked |residual| */
+    int sweeps, hist_cap;
+    double rms, tau;
+    int i0[ORC_MAX_D];
+    int64_t evaluated, pivoted;
+    double min_rel_gap;              /* smallest (best - runner up)/best seen */
+    int status;
+    int ran;
+    double *cores;                   /* G_1..G_d concatenated */
+    int64_t cores_len;
+} orc_state;
+
+static void orc_free_state(orc_state *S)
+{
+    if (!S) return;
+    for (int k = 0; k <= ORC_MAX_D; ++k) {
+        free(S->I[k]); free(S->J[k]); free(S->rho[k]); free(S->gam[k]); free(S->piv[k]);
+        free(S->best_hist[k]);
+    }
+    free(S->params_copy);
+    free(S->cores);
+    free(S);
+}
+
+void orc_destroy(orc_state *S) { orc_free_state(S); }
+
+orc_state *orc_create(int d, const int *n, double eps, int fn_id, const double *params, int nparams,
+                      uint64_t seed, int r_max, int n_samples)
+{
+    if (orc_fn_check(fn_id, d, n, params, nparams) != ORC_OK) return NULL;
+    if (!(eps >= 0.0) || r_max < 1 || n_samples < 1) return NULL;
+    orc_state *S = (orc_state *)calloc(1, sizeof(orc_state));
+    if (!S) return NULL;
+    S->d = d;
+    for (int j = 0; j < d; ++j) S->n[j] = n[j];
+    S->eps = eps; S->seed = seed; S->r_max = r_max; S->n_samples = n_samples;
+    if (nparams > 0) {
+        S->params_copy = (double *)malloc(sizeof(double) * nparams);
+        memcpy(S->params_copy, params, sizeof(double) * nparams);
+    }
+    S->F.fn_id = fn_id; S->F.d = d; S->F.params = S->params_copy; S->F.nparams = nparams;
+    for (int j = 0; j < d; ++j) S->F.n[j] = n[j];
+    S->hist_cap = (d - 1) * r_max + 2;
+    for (int k = 1; k <= d - 1; ++k) {
+        S->I[k] = (int *)calloc((size_t)r_max * k, sizeof(int));
+        S->J[k] = (int *)calloc((size_t)r_max * (d - k), sizeof(int));
+        S->rho[k] = (int64_t *)calloc(r_max, sizeof(int64_t));
+        S->gam[k] = (int64_t *)calloc(r_max, sizeof(int64_t));
+        S->piv[k] = (double *)calloc(r_max, sizeof(double));
+        S->best_hist[k] = (double *)calloc(S->hist_cap, sizeof(double));
+        if (!S->I[k] || !S->J[k] || !S->rho[k] || !S->gam[k] || !S->piv[k] || !S->best_hist[k]) {
+            orc_free_state(S);
+            return NULL;
+        }
+    }
+    return S;
+}
+
+/* Multi-index of superblock entry (row, col) of unfolding k (1-based k):
+ * row = p * n_k + i_k with prefix I[k-1][p]; col = q * n_{k+1} + i_{k+1} with
+ * suffix J[k+1][q]. */
+static void orc_entry_index(const orc_state *S, int k, int64_t row, int64_t col, int *idx)
+{
+    int d = S->d;
+    int nk = S->n[k - 1], nk1 = S->n[k];
+    int64_t p = row / nk, q = col / nk1;
+    for (int j = 0; j < k - 1; ++j) idx[j] = S->I[k - 1][p * (k - 1) + j];
+    idx[k - 1] = (int)(row % nk);
+    idx[k] = (int)(col % nk1);
+    int sl = d - k - 1;                                  /* length of J_{>k+1} tuples */
+    for (int j = 0; j < sl; ++j) idx[k + 1 + j] = S->J[k + 1][q * sl + j];
+}
+
+/* One greedy search on superblock k from the raw entries, with the current
+ * pivots eliminated in insertion order.  Returns 1 and the position of the
+ * largest unmasked |residual| if one exists. */
+static int orc_search(orc_state *S, int k, const int *rs, int64_t *row_out, int64_t *col_out,
+                      double *val_out, double *runner_out)
+{
+    int d = S->d;
+    int64_t nrow = (int64_t)rs[k - 1] * S->n[k - 1];
+    int64_t ncol = (int64_t)S->n[k] * rs[k + 1];
+    int nz = rs[k];
+    double *E = (double *)malloc(sizeof(double) * nrow * ncol);
+    double *u = (double *)malloc(sizeof(double) * ncol);
+    double *w = (double *)malloc(sizeof(double) * nrow);
+    unsigned char *rmask = (unsigned char *)calloc(nrow, 1);
+    unsigned char *cmask = (unsigned char *)calloc(ncol, 1);
+    int idx[ORC_MAX_D];
+    if (!E || !u || !w || !rmask || !cmask) {
+        free(E); free(u); free(w); free(rmask); free(cmask);
+        S->status = ORC_ENOMEM;
+        return -1;
+    }
+    /* raw entries X(R_k, C_k) */
+    for (int64_t i = 0; i < nrow; ++i)
+        for (int64_t j = 0; j < ncol; ++j) {
+            orc_entry_index(S, k, i, j, idx);
+            E[i * ncol + j] = orc_eval(&S->F, idx);
+        }
+    (void)d;
+    /* residual: eliminate pivots z = 1..r_k in insertion order */
+    for (int z = 0; z < nz; ++z) {
+        int64_t pr = S->rho[k][z], pc = S->gam[k][z];
+        double p = E[pr * ncol + pc];
+        for (int64_t j = 0; j < ncol; ++j) u[j] = E[pr * ncol + j] / p;
+        for (int64_t i = 0; i < nrow; ++i) w[i] = E[i * ncol + pc];
+        for (int64_t i = 0; i < nrow; ++i)
+            for (int64_t j = 0; j < ncol; ++j)
+                E[i * ncol + j] = fma(-w[i], u[j], E[i * ncol + j]);
+        rmask[pr] = 1;
+        cmask[pc] = 1;
+    }
+    /* argmax |E| over unmasked entries; row-major scan with strict '>' keeps
+     * the lowest (row, col) among equal values */
+    int found = 0;
+    double best = -1.0;
+    int64_t br = -1, bc = -1;
+    for (int64_t i = 0; i < nrow; ++i) {
+        if (rmask[i]) continue;
+        for (int64_t j = 0; j < ncol; ++j) {
+            if (cmask[j]) continue;
+            double a = fabs(E[i * ncol + j]);
+            if (!found || a > best) { best = a; br = i; bc = j; found = 1; }
+        }
+    }
+    double runner = 0.0;
+    if (found) {
+        for (int64_t i = 0; i < nrow; ++i) {
+            if (rmask[i]) continue;
+            for (int64_t j = 0; j < ncol; ++j) {
+                if (cmask[j]) continue;
+                double a = fabs(E[i * ncol + j]);
+                if (a != best && a > runner) runner = a;
+            }
+        }
+        *val_out = E[br * ncol + bc];
+    }
+    *row_out = br;
+    *col_out = bc;
+    *runner_out = runner;
+    S->pivoted += nrow * ncol;
+    free(E); free(u); free(w); free(rmask); free(cmask);
+    return found;
+}
+
+int orc_run(orc_state *S)
+{
+    if (!S) return ORC_EINVAL;
+    if (S->ran) return S->status;
+    int d = S->d;
+    /* samples: rms for the stop threshold and the initial pivot */
+    int *sidx = (int *)malloc(sizeof(int) * (size_t)S->n_samples * d);
+    if (!sidx) return S->status = ORC_ENOMEM;
+    orc_sample_indices(d, S->n, S->seed, S->n_samples, sidx);
+    double sumsq = 0.0, bestv = -1.0;
+    int64_t bests = 0;
+    for (int64_t s = 0; s < S->n_samples; ++s) {
+        double v = orc_eval(&S->F, sidx + s * d);
+        if (!isfinite(v)) { free(sidx); return S->status = ORC_EFN; }
+        sumsq += v * v;
+        if (fabs(v) > bestv) { bestv = fabs(v); bests = s; }
+    }
+    S->rms = sqrt(sumsq / (double)S->n_samples);
+    S->tau = S->eps * S->rms;
+    for (int j = 0; j < d; ++j) S->i0[j] = sidx[bests * d + j];
+    free(sidx);
+    double p0 = orc_eval(&S->F, S->i0);
+    if (p0 == 0.0) return S->status = ORC_ESINGULAR;
+
+    /* initial pivot, replicated for every unfolding (nested by construction) */
+    S->r[0] = 1; S->r[d] = 1;
+    for (int k = 1; k <= d - 1; ++k) {
+        for (int j = 0; j < k; ++j) S->I[k][j] = S->i0[j];
+        for (int j = 0; j < d - k; ++j) S->J[k][j] = S->i0[k + j];
+        S->rho[k][0] = S->i0[k - 1];     /* prefix position 0 */
+        S->gam[k][0] = S->i0[k];         /* suffix position 0 */
+        S->piv[k][0] = p0;
+        S->r[k] = 1;
+    }
+    S->min_rel_gap = INFINITY;
+    S->status = ORC_OK;
+
+    int rs[ORC_MAX_D + 1];
+    int64_t prow[ORC_MAX_D + 1], pcol[ORC_MAX_D + 1];
+    double pval[ORC_MAX_D + 1];
+    int prop[ORC_MAX_D + 1];
+    for (;;) {
+        for (int k = 0; k <= d; ++k) rs[k] = S->r[k];      /* sweep snapshot */
+        int any = 0, capped = 0;
+        S->evaluated = 0;
+        for (int k = 1; k <= d - 1; ++k) {
+            int64_t br, bc;
+            double bv = 0.0, runner = 0.0;
+            S->evaluated += (int64_t)rs[k - 1] * S->n[k - 1] * (int64_t)S->n[k] * rs[k + 1];
+            int found = orc_search(S, k, rs, &br, &bc, &bv, &runner);
+            if (found < 0) return S->status;
+            prop[k] = 0;
+            double a = found ? fabs(bv) : 0.0;
+            if (S->sweeps < S->hist_cap) S->best_hist[k][S->sweeps] = a;
+            if (found && a > S->tau) {
+                if (a > 0.0) {
+                    double g = (a - runner) / a;
+                    if (g < S->min_rel_gap) S->min_rel_gap = g;
+                }
+                if (rs[k] < S->r_max) {
+                    prop[k] = 1; prow[k] = br; pcol[k] = bc; pval[k] = bv; any = 1;
+                } else {
+                    capped = 1;
+                }
+            }
+        }
+        S->sweeps++;
+        if (capped) S->status = ORC_NOT_CONVERGED;
+        if (!any) break;
+        /* commit all proposals (append-only, so positions stay valid) */
+        for (int k = 1; k <= d - 1; ++k) {
+            if (!prop[k]) continue;
+            int z = S->r[k];
+            int nk = S->n[k - 1], nk1 = S->n[k];
+            int64_t p = prow[k] / nk, q = pcol[k] / nk1;
+            for (int j = 0; j < k - 1; ++j) S->I[k][z * k + j] = S->I[k - 1][p * (k - 1) + j];
+            S->I[k][z * k + k - 1] = (int)(prow[k] % nk);
+            int sl = d - k - 1;
+            S->J[k][z * (d - k)] = (int)(pcol[k] % nk1);
+            for (int j = 0; j < sl; ++j) S->J[k][z * (d - k) + 1 + j] = S->J[k + 1][q * sl + j];
+            S->rho[k][z] = prow[k];
+            S->gam[k][z] = pcol[k];
+            S->piv[k][z] = pval[k];
+            S->r[k] = z + 1;
+        }
+    }
+    if (!isfinite(S->min_rel_gap)) S->min_rel_gap = 1.0;
+    S->ran = 1;
+
+    /* cores by Alg. 4 on the sliced fibers */
+    int64_t total = 0;
+    for (int k = 1; k <= d; ++k) total += (int64_t)S->r[k - 1] * S->n[k - 1] * S->r[k];
+    S->cores = (double *)malloc(sizeof(double) * total);
+    if (!S->cores) return S->status = ORC_ENOMEM;
+    S->cores_len = total;
+    int64_t off = 0;
+    int idx[ORC_MAX_D];
+    for (int k = 1; k <= d - 1; ++k) {
+        int64_t nrow = (int64_t)S->r[k - 1] * S->n[k - 1];
+        int rk = S->r[k];
+        double *A = (double *)malloc(sizeof(double) * nrow * rk);
+        double *Trho = (double *)malloc(sizeof(double) * rk);
+        double *a = (double *)malloc(sizeof(double) * rk);
+        double *s = (double *)malloc(sizeof(double) * nrow);
+        double *T = S->cores + off;
+        if (!A || !Trho || !a || !s) {
+            free(A); free(Trho); free(a); free(s);
+            return S->status = ORC_ENOMEM;
+        }
+        /* A = X(I_{<=k-1} x [n_k], J_{>k}); column z is the z-th column tuple */
+        for (int64_t i = 0; i < nrow; ++i) {
+            int64_t p = i / S->n[k - 1];
+            for (int z = 0; z < rk; ++z) {
+                for (int j = 0; j < k - 1; ++j) idx[j] = S->I[k - 1][p * (k - 1) + j];
+                idx[k - 1] = (int)(i % S->n[k - 1]);
+                for (int j = 0; j < d - k; ++j) idx[k + j] = S->J[k][z * (d - k) + j];
+                A[i * rk + z] = orc_eval(&S->F, idx);
+            }
+        }
+        /* T_1 = A(:, j_1) / A(i_1, j_1) */
+        double a11 = A[S->rho[k][0] * rk + 0];
+        for (int64_t i = 0; i < nrow; ++i) {
+            for (int z = 0; z < rk; ++z) T[i * rk + z] = 0.0;
+            T[i * rk + 0] = A[i * rk + 0] / a11;
+        }
+        for (int z = 1; z < rk; ++z) {
+            int64_t iz = S->rho[k][z];
+            for (int zz = 0; zz < z; ++zz) a[zz] = A[S->rho[k][zz] * rk + z];   /* A(I_z, j_z) */
+            /* s = T A(I_z, j_z) - A(:, j_z), dot products in ascending order */
+            for (int64_t i = 0; i < nrow; ++i) {
+                double dot = 0.0;
+                for (int zz = 0; zz < z; ++zz) dot = fma(T[i * rk + zz], a[zz], dot);
+                s[i] = dot - A[i * rk + z];
+            }
+            /* delta^{-1} = A(i_z, j_z) - T(i_z,:) A(I_z, j_z) = -s(i_z) */
+            double dinv = -s[iz];
+            if (dinv == 0.0) {
+                free(A); free(Trho); free(a); free(s);
+                return S->status = ORC_ESINGULAR;
+            }
+            double delta = 1.0 / dinv;
+            for (int zz = 0; zz < z; ++zz) Trho[zz] = T[iz * rk + zz];
+            /* T = [T + delta s T(i_z,:), -delta s] */
+            for (int64_t i = 0; i < nrow; ++i) {
+                double c = delta * s[i];
+                for (int zz = 0; zz < z; ++zz) T[i * rk + zz] = fma(c, Trho[zz], T[i * rk + zz]);
+                T[i * rk + z] = -c;
+            }
+        }
+        free(A); free(Trho); free(a); free(s);
+        off += nrow * rk;
+    }
+    /* G_d = X(I_{<=d-1}, :) */
+    {
+        int rd = S->r[d - 1];
+        for (int p = 0; p < rd; ++p)
+            for (int i = 0; i < S->n[d - 1]; ++i) {
+                for (int j = 0; j < d - 1; ++j) idx[j] = S->I[d - 1][p * (d - 1) + j];
+                idx[d - 1] = i;
+                S->cores[off + (int64_t)p * S->n[d - 1] + i] = orc_eval(&S->F, idx);
+            }
+    }
+    return S->status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Accessors.                                                                 */
+/* ------------------------------------------------------------------------ */
+int orc_get_ranks(const orc_state *S, int *ranks)
+{
+    if (!S || !S->ran) return ORC_EINVAL;
+    for (int k = 0; k <= S->d; ++k) ranks[k] = S->r[k];
+    return ORC_OK;
+}
+
+/* rows: r_k x k tuples, cols: r_k x (d-k) tuples, rho/gam: superblock
+ * positions, piv: pivot residuals; any output may be NULL. */
+int orc_get_pivots(const orc_state *S, int k, int *rows, int *cols, int64_t *rho, int64_t *gam,
+                   double *piv)
+{
+    if (!S || !S->ran || k < 1 || k > S->d - 1) return ORC_EINVAL;
+    int rk = S->r[k];
+    if (rows) memcpy(rows, S->I[k], sizeof(int) * rk * k);
+    if (cols) memcpy(cols, S->J[k], sizeof(int) * rk * (S->d - k));
+    if (rho) memcpy(rho, S->rho[k], sizeof(int64_t) * rk);
+    if (gam) memcpy(gam, S->gam[k], sizeof(int64_t) * rk);
+    if (piv) memcpy(piv, S->piv[k], sizeof(double) * rk);
+    return rk;
+}
+
+/* stats: [rms, tau, evaluated, pivoted, sweeps, min_rel_gap, status] */
+int orc_get_stats(const orc_state *S, double *out, int *i0)
+{
+    if (!S || !S->ran) return ORC_EINVAL;
+    out[0] = S->rms; out[1] = S->tau; out[2] = (double)S->evaluated; out[3] = (double)S->pivoted;
+    out[4] = S->sweeps; out[5] = S->min_rel_gap; out[6] = S->status;
+    if (i0) for (int j = 0; j < S->d; ++j) i0[j] = S->i0[j];
+    return ORC_OK;
+}
+
+/* best |residual| of unfolding k in each sweep */
+int orc_get_history(const orc_state *S, int k, double *out, int cap)
+{
+    if (!S || !S->ran || k < 1 || k > S->d - 1) return ORC_EINVAL;
+    int m = S->sweeps < cap ? S->sweeps : cap;
+    if (m > S->hist_cap) m = S->hist_cap;
+    memcpy(out, S->best_hist[k], sizeof(double) * m);
+    return m;
+}
+
+int64_t orc_get_cores(const orc_state *S, double *out, int64_t cap)
+{
+    if (!S || !S->ran || !S->cores) return ORC_EINVAL;
+    if (out) {
+        if (cap < S->cores_len) return ORC_EINVAL;
+        memcpy(out, S->cores, sizeof(double) * S->cores_len);
+    }
+    return S->cores_len;
+}
+
+/* Value of the TT at a multi-index: G_1(i_1) G_2(i_2) ... G_d(i_d), each
+ * product accumulated in ascending order of the contracted index. */
+static double orc_tt_value(int d, const int *n, const int *ranks, const double *cores, const int *idx,
+                           double *v, double *vn)
+{
+    int64_t off = 0;
+    v[0] = 1.0;
+    for (int k = 0; k < d; ++k) {
+        int ra = ranks[k], rb = ranks[k + 1];
+        const double *G = cores + off;                    /* ra x n_k x rb */
+        for (int b = 0; b < rb; ++b) {
+            double acc = 0.0;
+            for (int a = 0; a < ra; ++a)
+                acc = fma(v[a], G[((int64_t)a * n[k] + idx[k]) * rb + b], acc);
+            vn[b] = acc;
+        }
+        for (int b = 0; b < rb; ++b) v[b] = vn[b];
+        off += (int64_t)ra * n[k] * rb;
+    }
+    return v[0];
+}
+
+int orc_tt_eval(int d, const int *n, const int *ranks, const double *cores, int64_t m, const int *idx,
+                double *out)
+{
+    int rmax = 1;
+    for (int k = 0; k <= d; ++k) if (ranks[k] > rmax) rmax = ranks[k];
+    double *v = (double *)malloc(sizeof(double) * rmax);
+    double *vn = (double *)malloc(sizeof(double) * rmax);
+    if (!v || !vn) { free(v); free(vn); return ORC_ENOMEM; }
+    for (int64_t t = 0; t < m; ++t) out[t] = orc_tt_value(d, n, ranks, cores, idx + t * d, v, vn);
+    free(v); free(vn);
+    return ORC_OK;
+}
+
+int orc_state_tt_eval(const orc_state *S, int64_t m, const int *idx, double *out)
+{
+    if (!S || !S->ran) return ORC_EINVAL;
+    return orc_tt_eval(S->d, S->n, S->r, S->cores, m, idx, out);
+}
+
+/* Sampled relative error of Sec. 5 on R seeded indices (stream seed): the
+ * square root of sum (X - X~)^2 / sum X^2, sums in sample order. */
+int orc_sampled_error(const orc_state *S, int64_t R, uint64_t seed, double *err)
+{
+    if (!S || !S->ran) return ORC_EINVAL;
+    int d = S->d;
+    int idx[ORC_MAX_D];
+    int rmax = 1;
+    for (int k = 0; k <= d; ++k) if (S->r[k] > rmax) rmax = S->r[k];
+    double *v = (double *)malloc(sizeof(double) * rmax);
+    double *vn = (double *)malloc(sizeof(double) * rmax);
+    if (!v || !vn) { free(v); free(vn); return ORC_ENOMEM; }
+    uint64_t st = seed;
+    double num = 0.0, den = 0.0;
+    for (int64_t t = 0; t < R; ++t) {
+        for (int j = 0; j < d; ++j) idx[j] = (int)(orc_sm64(&st) % (uint64_t)S->n[j]);
+        double x = orc_eval(&S->F, idx);
+        double y = orc_tt_value(d, S->n, S->r, S->cores, idx, v, vn);
+        num += (x - y) * (x - y);
+        den += x * x;
+    }
+    free(v); free(vn);
+    *err = den > 0.0 ? sqrt(num / den) : sqrt(num);
+    return ORC_OK;
+}
+
+/* Brute force over every entry (eq. FrobeniusNorm); tiny tensors only. */
+int orc_full_error(const orc_state *S, double *err, double *max_abs_err)
+{
+    if (!S || !S->ran) return ORC_EINVAL;
+    int d = S->d;
+    int64_t N = 1;
+    for (int j = 0; j < d; ++j) N *= S->n[j];
+    if (N > (int64_t)200000000) return ORC_EINVAL;
+    int idx[ORC_MAX_D] = {0};
+    int rmax = 1;
+    for (int k = 0; k <= d; ++k) if (S->r[k] > rmax) rmax = S->r[k];
+    double *v = (double *)malloc(sizeof(double) * rmax);
+    double *vn = (double *)malloc(sizeof(double) * rmax);
+    if (!v || !vn) { free(v); free(vn); return ORC_ENOMEM; }
+    double num = 0.0, den = 0.0, mx = 0.0;
+    for (int64_t t = 0; t < N; ++t) {
+        double x = orc_eval(&S->F, idx);
+        double y = orc_tt_value(d, S->n, S->r, S->cores, idx, v, vn);
+        num += (x - y) * (x - y);
+        den += x * x;
+        if (fabs(x - y) > mx) mx = fabs(x - y);
+        for (int j = d - 1; j >= 0; --j) {                 /* odometer, last index fastest */
+            if (++idx[j] < S->n[j]) break;
+            idx[j] = 0;
+        }
+    }
+    free(v); free(vn);
+    *err = den > 0.0 ? sqrt(num / den) : sqrt(num);
+    if (max_abs_err) *max_abs_err = mx;
+    return ORC_OK;
+}
+
+/* Residual of superblock k after its current pivots, from the raw entries,
+ * for inspection by tests (nrow x ncol, row-major).  Returns nrow*ncol. */
+int64_t orc_superblock_residual(orc_state *S, int k, double *out, int64_t cap, int64_t *nrow_out,
+                                int64_t *ncol_out)
+{
+    if (!S || !S->ran || k < 1 || k > S->d - 1) return ORC_EINVAL;
+    int64_t nrow = (int64_t)S->r[k - 1] * S->n[k - 1];
+    int64_t ncol = (int64_t)S->n[k] * S->r[k + 1];
+    *nrow_out = nrow; *ncol_out = ncol;
+    if (!out) return nrow * ncol;
+    if (cap < nrow * ncol) return ORC_EINVAL;
+    int idx[ORC_MAX_D];
+    double *u = (double *)malloc(sizeof(double) * ncol);
+    double *w = (double *)malloc(sizeof(double) * nrow);
+    if (!u || !w) { free(u); free(w); return ORC_ENOMEM; }
+    for (int64_t i = 0; i < nrow; ++i)
+        for (int64_t j = 0; j < ncol; ++j) {
+            orc_entry_index(S, k, i, j, idx);
+            out[i * ncol + j] = orc_eval(&S->F, idx);
+        }
+    for (int z = 0; z < S->r[k]; ++z) {
+        int64_t pr = S->rho[k][z], pc = S->gam[k][z];
+        double p = out[pr * ncol + pc];
+        for (int64_t j = 0; j < ncol; ++j) u[j] = out[pr * ncol + j] / p;
+        for (int64_t i = 0; i < nrow; ++i) w[i] = out[i * ncol + pc];
+        for (int64_t i = 0; i < nrow; ++i)
+            for (int64_t j = 0; j < ncol; ++j) out[i * ncol + j] = fma(-w[i], u[j], out[i * ncol + j]);
+    }
+    free(u); free(w);
+    return nrow * ncol;
+}
+
+/* Plain rank-1 recursion on a dense matrix with given pivots (d = 2 view,
+ * eq. aca_approx_E in residual form): A is m x n row-major and is overwritten
+ * by the residual after eliminating pivots (rows[z], cols[z]) in order. */
+int orc_matrix_residual(int64_t m, int64_t n, double *A, int npiv, const int64_t *rows,
+                        const int64_t *cols)
+{
+    double *u = (double *)malloc(sizeof(double) * n);
+    double *w = (double *)malloc(sizeof(double) * m);
+    if (!u || !w) { free(u); free(w); return ORC_ENOMEM; }
+    for (int z = 0; z < npiv; ++z) {
+        double p = A[rows[z] * n + cols[z]];
+        if (p == 0.0) { free(u); free(w); return ORC_ESINGULAR; }
+        for (int64_t j = 0; j < n; ++j) u[j] = A[rows[z] * n + j] / p;
+        for (int64_t i = 0; i < m; ++i) w[i] = A[i * n + cols[z]];
+        for (int64_t i = 0; i < m; ++i)
+            for (int64_t j = 0; j < n; ++j) A[i * n + j] = fma(-w[i], u[j], A[i * n + j]);
+    }
+    free(u); free(w);
+    return ORC_OK;
+}
