@@ -1,0 +1,193 @@
+/*
+ * tt_cross.h -- C ABI of the MI355X (gfx950) greedy adaptive TT-cross library.
+ *
+ * The library computes a tensor-train (TT) approximation of a tensor that is
+ * known only through a generating function evaluated entry by entry, following
+ * Shi, Hayes and Qiu, "Distributed memory parallel adaptive tensor-train cross
+ * approximation":
+ *   problem statement       -- Sec. 1, eq. (FrobeniusNorm): find X~ in TT format
+ *                              with ||X - X~||_F <= eps ||X||_F;
+ *   TT format               -- Sec. 2.2: X(i_1..i_d) = G_1(:,i_1,:) ... G_d(:,i_d,:);
+ *   pivot search            -- Alg. 1 (greedy largest |residual|) run on the
+ *                              superblocks of Alg. 2 for every unfolding at once;
+ *   residual update         -- eq. (aca_approx_E) / (submatrix_cross_iter), in
+ *                              residual form R <- R - R(:,j) R(i,:) / R(i,j);
+ *   core construction       -- Alg. 4 with eq. (aca_approx_T) on the sliced
+ *                              fibers, reshaped by eq. (corereshape);
+ *   subtensor blocks        -- Sec. 3: every mode n_j is split evenly into C_j
+ *                              pieces; each workgroup of the search works inside
+ *                              one subtensor block and the global pivot is the
+ *                              best of the block-local pivots (Sec. 3.2.1).
+ * All of the blocks of all of the unfoldings run on one GPU.
+ *
+ * Conventions
+ *   - Indices are 0-based at this interface.  The generating functions apply
+ *     the paper's 1-based formulas internally.
+ *   - A handle owns all device memory it uses.  Getters copy into caller-owned
+ *     buffers; a NULL output pointer asks for the required size.
+ *   - `on_device` = 0: pointers are host memory; = 1: they are device memory
+ *     on the handle's GPU (for instance from a torch tensor), used on the
+ *     handle's stream.
+ *   - Negative return codes are errors, positive ones are warnings.  After an
+ *     error tt_last_error() returns a message for the calling thread.
+ *   - One thread may use a handle at a time.
+ */
+#ifndef TT_CROSS_H
+#define TT_CROSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TT_MAX_D 16     /* largest supported number of modes */
+#define TT_MAX_RANK 64  /* largest supported TT rank per unfolding */
+
+/* Generating functions (fn_id) and their params[] layouts. */
+enum tt_fn {
+    /* Hilbert tensor, eq. (HilbertTensor): 1/(i_1+..+i_d + shift), 1-based i.
+     * params: [] -> shift = 1-d (the paper's tensor), or [shift]. */
+    TT_FN_HILBERT = 1,
+    /* Single 3d3v Maxwellian, d = 6, modes x1,x2,x3,v1,v2,v3:
+     * rho(x) (2 pi T)^{-3/2} exp(-|v-u(x)|^2/(2T)), rho = 1 + a sin(2pi x1)cos(2pi x2),
+     * u = (b sin(2pi x3),0,0), x_l = i/n on [0,1), v cell-centred on [-vmax,vmax].
+     * params: [] -> (a,b,T,vmax) = (0.5,0.3,1,8), or [a,b,T,vmax]. */
+    TT_FN_MAXWELL = 2,
+    /* Sum of two spatially uniform 3v Maxwellians, d >= 3; the d-3 leading modes
+     * are spatial (f does not depend on them), the last three are v1,v2,v3.
+     * params: [rho1,u1x,u1y,u1z,T1, rho2,u2x,u2y,u2z,T2 (, vmax=8)]. */
+    TT_FN_BIMAXWELL = 3,
+    /* Sum of r separable products, f = sum_m prod_j g_{m,j}(i_j).
+     * params: [r, g...], g_{m,j}(i) at 1 + m*sum(n) + n_0+..+n_{j-1} + i. */
+    TT_FN_SEPSUM = 4,
+    /* The paper's kinetic tensors of Sec. 5.2, eq. (2d2vFunction): modes
+     * x,v_x,y,v_y (d = 4) or x,v_x,y,v_y,z,v_z (d = 6); x in [-1/2,1/2],
+     * v in [-3,3], cell-centred grids.  params: []. */
+    TT_FN_MAXWELL_2D2V = 5,
+    TT_FN_MAXWELL_3D3V = 6
+};
+
+enum tt_status {
+    TT_OK = 0,
+    TT_NOT_CONVERGED = 1,     /* some unfolding hit r_max with |residual| > tau */
+    TT_WARN_SAMPLED_ERR = 2,  /* sampled error above eps (tt_cross_sampled_error) */
+    TT_EINVAL = -1,           /* bad argument */
+    TT_ENOMEM = -2,           /* device or host allocation failed, or over budget */
+    TT_EDEVICE = -3,          /* HIP runtime error */
+    TT_ESINGULAR = -4,        /* zero pivot */
+    TT_ESTATE = -5,           /* call not valid in the handle's state */
+    TT_EFN = -6,              /* unknown generating function or bad params */
+    TT_EBUSY = -7             /* server queue full */
+};
+
+enum tt_precision {
+    TT_PREC_AUTO = 0,  /* FP32 entry evaluation and sweeps iff eps >= 1e-6, else FP64 */
+    TT_PREC_FP64 = 1,  /* FP64 everywhere (bit-exact with a canonical FP64 reference) */
+    TT_PREC_FP32 = 2   /* FP32 evaluation and sweeps; pivot check, stop test and cores in FP64 */
+};
+
+enum tt_pivot_mode {
+    TT_PIVOT_GREEDY = 0  /* largest |residual| over the whole superblock */
+};
+
+typedef struct tt_options {
+    uint64_t seed;              /* seeds the N_s sample entries (default 0) */
+    int32_t r_max;              /* rank cap per unfolding, 1..TT_MAX_RANK (default 64) */
+    int32_t precision;          /* enum tt_precision (default TT_PREC_AUTO) */
+    int32_t pivot_mode;         /* enum tt_pivot_mode (default greedy) */
+    int32_t n_samples;          /* N_s sample entries for rms and the first pivot (default 16384) */
+    int32_t grid[TT_MAX_D];     /* subtensor blocks per mode C_j (default 1; 1 <= C_j <= n_j) */
+    int32_t tile_rows;          /* rows per workgroup tile, 0 = chosen by the library */
+    int32_t tile_cols;          /* columns per workgroup tile, 0 = chosen by the library */
+    int32_t lookahead;          /* sweeps queued ahead of the host's stop check (default 2) */
+    int32_t profile;            /* 1: time every search launch with HIP events (stats below) */
+    void *stream;               /* hipStream_t to run on; NULL = a stream owned by the handle */
+} tt_options;
+
+typedef struct tt_stats {
+    int64_t evaluated;          /* distinct superblock entries evaluated (sum over unfoldings) */
+    int64_t pivoted;            /* residual entries scanned by argmax passes, all sweeps */
+    int64_t samples;            /* sample entries evaluated for rms and the first pivot */
+    int32_t sweeps;             /* search sweeps run (the last one proposes nothing) */
+    int32_t precision_used;     /* TT_PREC_FP64 or TT_PREC_FP32 */
+    int32_t status;             /* last tt_cross_run status */
+    int32_t d;
+    int32_t ranks[TT_MAX_D + 1];
+    double rms;                 /* rms of the sample entries */
+    double tau;                 /* stop threshold eps * rms */
+    double time_to_eps_s;       /* device time of the last tt_cross_run */
+    double last_best[TT_MAX_D]; /* largest unmasked |residual| per unfolding in the final sweep */
+    /* filled when options.profile = 1 (device times from HIP events on the run's stream) */
+    int32_t sweep_launches;     /* search-tile launches that did work (one per sweep) */
+    int32_t pad0;
+    double sweep_kernel_s;      /* summed duration of those launches */
+    double commit_kernel_s;     /* summed duration of the per-sweep commit launches */
+    double sweep_alg_bytes;     /* algorithmic residual traffic of the tile launches: 2w per
+                                   updated stored entry, w per scanned-only stored entry,
+                                   w per newly evaluated entry (w = 8 FP64, 4 FP32) */
+    double new_entries;         /* superblock entries evaluated by the tile launches */
+} tt_stats;
+
+typedef struct tt_cross_s *tt_cross_h;
+
+/* Fill *opt with the defaults listed in tt_options. */
+void tt_options_default(tt_options *opt);
+
+/* Create a problem: d modes of sizes n[0..d-1] (each >= 1), tolerance eps >= 0
+ * (eq. FrobeniusNorm), generating function fn_id with nparams doubles of
+ * params (may be NULL when nparams == 0).  params are copied.  Returns NULL on
+ * bad arguments (reason in tt_last_error). */
+tt_cross_h tt_cross_create(int d, const int32_t *n, double eps, int fn_id, const double *params,
+                           int nparams);
+
+/* Replace the options (before tt_cross_run; a later run reuses them). */
+int tt_cross_set_options(tt_cross_h h, const tt_options *opt);
+
+/* Run the approximation to completion on the handle's stream and wait for it.
+ * Returns TT_OK, TT_NOT_CONVERGED, or an error code. */
+int tt_cross_run(tt_cross_h h);
+
+/* ranks[0..d] = (1, r_1, .., r_{d-1}, 1) after a run. */
+int tt_cross_get_ranks(tt_cross_h h, int32_t *ranks);
+
+/* Copy the cores G_1..G_d, concatenated, each r_{k-1} x n_k x r_k in row-major
+ * order, into out (cap doubles).  Returns the number of doubles needed; with
+ * out == NULL only the size is returned. */
+int64_t tt_cross_get_cores(tt_cross_h h, double *out, int64_t cap, int on_device);
+
+/* Evaluate the TT at m multi-indices idx (m x d, 0-based, row-major) into
+ * out[m]; each matrix product is accumulated in ascending index order. */
+int tt_eval(tt_cross_h h, int64_t m, const int32_t *idx, double *out, int on_device);
+
+/* Pivots of unfolding k (1 <= k <= d-1) in insertion order: rows (r_k x k)
+ * hold the index tuples of I_{<=k}, cols (r_k x (d-k)) those of J_{>k}; either
+ * may be NULL.  Returns r_k. */
+int tt_cross_get_pivots(tt_cross_h h, int k, int32_t *rows, int32_t *cols);
+
+/* Per-sweep history of the largest unmasked |residual| of unfolding k (1-based):
+ * copies up to cap values, returns the number of sweeps. */
+int tt_cross_get_history(tt_cross_h h, int k, double *out, int cap);
+
+int tt_cross_get_stats(tt_cross_h h, tt_stats *st);
+
+/* Sampled relative error (Sec. 5): sqrt(sum (X - X~)^2 / sum X^2) over R
+ * multi-indices drawn from SplitMix64(seed), coordinate j of sample s being
+ * draw(s*d + j) mod n_j. */
+int tt_cross_sampled_error(tt_cross_h h, int64_t R, uint64_t seed, double *err);
+
+/* Evaluate a generating function at m multi-indices (no handle needed). */
+int tt_fn_eval(int fn_id, int d, const int32_t *n, const double *params, int nparams, int64_t m,
+               const int32_t *idx, double *out, int on_device);
+
+void tt_cross_destroy(tt_cross_h h);
+
+/* Message for the last error on the calling thread (empty if none). */
+const char *tt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TT_CROSS_H */

@@ -1,0 +1,161 @@
+"""Python view of the C ABI: argument marshalling only, every step runs in the
+HIP library (libttcross.so)."""
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import Options, Stats, check, load
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _params_ptr(params):
+    if params is None or len(params) == 0:
+        return None, 0, None
+    arr = np.ascontiguousarray(params, dtype=np.float64)
+    return arr.ctypes.data_as(C.POINTER(C.c_double)), int(arr.size), arr
+
+
+def default_options():
+    o = Options()
+    load().tt_options_default(C.byref(o))
+    return o
+
+
+def fn_eval(fn_id, n, idx, params=None):
+    """Generating function at m multi-indices, evaluated on the GPU (FP64).
+
+    idx: numpy (m, d) int32 on the host, or a torch int32 CUDA tensor (the
+    result is then a torch float64 CUDA tensor)."""
+    n = _i32(n)
+    pp, npar, _keep = _params_ptr(params)
+    if hasattr(idx, "is_cuda") and idx.is_cuda:
+        import torch
+        idx = idx.contiguous()
+        out = torch.empty(idx.shape[0], dtype=torch.float64, device=idx.device)
+        check(load().tt_fn_eval(fn_id, n.size, n.ctypes.data_as(C.POINTER(C.c_int32)), pp, npar,
+                                idx.shape[0], C.c_void_p(idx.data_ptr()), C.c_void_p(out.data_ptr()), 1))
+        return out
+    idx = _i32(np.atleast_2d(idx))
+    out = np.zeros(idx.shape[0], dtype=np.float64)
+    check(load().tt_fn_eval(fn_id, n.size, n.ctypes.data_as(C.POINTER(C.c_int32)), pp, npar, idx.shape[0],
+                            idx.ctypes.data_as(C.c_void_p), out.ctypes.data_as(C.c_void_p), 0))
+    return out
+
+
+class TTCross:
+    """One cross approximation problem (a tt_cross_h handle)."""
+
+    def __init__(self, n, eps, fn_id, params=None, seed=0, r_max=64, precision=_lib.PREC_AUTO,
+                 n_samples=16384, grid=None, tile_rows=0, tile_cols=0, lookahead=2, profile=0,
+                 stream=None):
+        L = load()
+        self.n = _i32(n)
+        self.d = int(self.n.size)
+        self.fn_id = fn_id
+        self.params = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
+        pp, npar, self._pkeep = _params_ptr(self.params)
+        self.h = L.tt_cross_create(self.d, self.n.ctypes.data_as(C.POINTER(C.c_int32)), float(eps), fn_id,
+                                   pp, npar)
+        if not self.h:
+            raise _lib.TTError(_lib.EINVAL, _lib.last_error())
+        o = default_options()
+        o.seed = seed
+        o.r_max = r_max
+        o.precision = precision
+        o.n_samples = n_samples
+        if grid is not None:
+            for j, c in enumerate(grid):
+                o.grid[j] = int(c)
+        o.tile_rows = tile_rows
+        o.tile_cols = tile_cols
+        o.lookahead = lookahead
+        o.profile = profile
+        if stream is not None:
+            o.stream = C.c_void_p(getattr(stream, "cuda_stream", stream))
+        check(L.tt_cross_set_options(self.h, C.byref(o)))
+        self.status = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().tt_cross_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self):
+        self.status = check(load().tt_cross_run(self.h))
+        return self.status
+
+    def ranks(self):
+        r = np.zeros(self.d + 1, dtype=np.int32)
+        check(load().tt_cross_get_ranks(self.h, r.ctypes.data_as(C.POINTER(C.c_int32))))
+        return r
+
+    def cores_flat(self):
+        m = check(load().tt_cross_get_cores(self.h, None, 0, 0))
+        out = np.zeros(m, dtype=np.float64)
+        check(load().tt_cross_get_cores(self.h, out.ctypes.data_as(C.c_void_p), m, 0))
+        return out
+
+    def cores(self):
+        flat, r = self.cores_flat(), self.ranks()
+        res, off = [], 0
+        for k in range(self.d):
+            sz = int(r[k]) * int(self.n[k]) * int(r[k + 1])
+            res.append(flat[off:off + sz].reshape(int(r[k]), int(self.n[k]), int(r[k + 1])))
+            off += sz
+        return res
+
+    def pivots(self, k):
+        rk = int(self.ranks()[k])
+        rows = np.zeros((rk, k), dtype=np.int32)
+        cols = np.zeros((rk, self.d - k), dtype=np.int32)
+        check(load().tt_cross_get_pivots(self.h, k, rows.ctypes.data_as(C.c_void_p),
+                                         cols.ctypes.data_as(C.c_void_p)))
+        return rows, cols
+
+    def history(self, k):
+        cap = 4096
+        out = np.zeros(cap, dtype=np.float64)
+        m = check(load().tt_cross_get_history(self.h, k, out.ctypes.data_as(C.c_void_p), cap))
+        return out[:min(m, cap)].copy()
+
+    def stats(self):
+        s = Stats()
+        check(load().tt_cross_get_stats(self.h, C.byref(s)))
+        return {
+            "evaluated": s.evaluated, "pivoted": s.pivoted, "samples": s.samples, "sweeps": s.sweeps,
+            "precision_used": s.precision_used, "status": s.status,
+            "ranks": list(s.ranks)[: self.d + 1], "rms": s.rms, "tau": s.tau,
+            "time_to_eps_s": s.time_to_eps_s, "last_best": list(s.last_best)[: self.d - 1],
+            "sweep_launches": s.sweep_launches, "sweep_kernel_s": s.sweep_kernel_s,
+            "commit_kernel_s": s.commit_kernel_s, "sweep_alg_bytes": s.sweep_alg_bytes,
+            "new_entries": s.new_entries,
+        }
+
+    def tt_eval(self, idx):
+        """TT values at multi-indices: numpy (m, d) int32 on the host, or an
+        int32 torch CUDA tensor (result on the device)."""
+        if hasattr(idx, "is_cuda") and idx.is_cuda:
+            import torch
+            idx = idx.contiguous()
+            out = torch.empty(idx.shape[0], dtype=torch.float64, device=idx.device)
+            check(load().tt_eval(self.h, idx.shape[0], C.c_void_p(idx.data_ptr()), C.c_void_p(out.data_ptr()), 1))
+            return out
+        idx = _i32(np.atleast_2d(idx))
+        out = np.zeros(idx.shape[0], dtype=np.float64)
+        check(load().tt_eval(self.h, idx.shape[0], idx.ctypes.data_as(C.c_void_p), out.ctypes.data_as(C.c_void_p), 0))
+        return out
+
+    def sampled_error(self, R=1_000_000, seed=1):
+        e = C.c_double()
+        check(load().tt_cross_sampled_error(self.h, R, C.c_uint64(seed), C.byref(e)))
+        return e.value

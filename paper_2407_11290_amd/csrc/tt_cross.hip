@@ -1,0 +1,792 @@
+// tt_cross.hip -- host driver and C ABI of the gfx950 greedy adaptive TT-cross
+// library (declarations and contracts in include/tt_cross.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "tt_cross.h"
+#include "tt_device.h"
+#include "tt_kernels.h"
+#include "tt_internal.h"
+
+using namespace ttc;
+
+namespace ttc {
+
+static thread_local std::string g_err;
+
+int set_err(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return set_err(TT_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Generating function descriptors.
+// ---------------------------------------------------------------------------
+int build_fn(int fn_id, int d, const int32_t *n, const double *params, int nparams, FnHost &out)
+{
+    FnDev &F = out.dev;
+    std::memset(&F, 0, sizeof F);
+    if (d < 2 || d > TT_MAX_D) return set_err(TT_EINVAL, "d=%d outside [2,%d]", d, TT_MAX_D);
+    if (!n) return set_err(TT_EINVAL, "n is NULL");
+    for (int j = 0; j < d; ++j)
+        if (n[j] < 1 || n[j] > (1 << 20)) return set_err(TT_EINVAL, "n[%d]=%d out of range", j, n[j]);
+    if (nparams < 0 || (nparams > 0 && !params)) return set_err(TT_EINVAL, "bad params");
+    F.id = fn_id;
+    F.d = d;
+    for (int j = 0; j < d; ++j) F.n[j] = n[j];
+    out.table.clear();
+    switch (fn_id) {
+    case TT_FN_HILBERT:
+        F.shift = (nparams >= 1) ? params[0] : (double)(1 - d);
+        if (!((double)d + F.shift > 0.0)) return set_err(TT_EFN, "Hilbert denominator can be <= 0");
+        break;
+    case TT_FN_MAXWELL:
+        if (d != 6) return set_err(TT_EFN, "Maxwellian needs d=6");
+        if (nparams == 0) { F.prm[0] = 0.5; F.prm[1] = 0.3; F.prm[2] = 1.0; F.prm[3] = 8.0; }
+        else if (nparams >= 4) for (int i = 0; i < 4; ++i) F.prm[i] = params[i];
+        else return set_err(TT_EFN, "Maxwellian params: [a,b,T,vmax]");
+        if (!(F.prm[2] > 0.0) || !(F.prm[3] > 0.0)) return set_err(TT_EFN, "Maxwellian needs T>0, vmax>0");
+        break;
+    case TT_FN_BIMAXWELL:
+        if (d < 3) return set_err(TT_EFN, "bi-Maxwellian needs d>=3");
+        if (nparams < 10) return set_err(TT_EFN, "bi-Maxwellian needs 10 params");
+        for (int i = 0; i < 10; ++i) F.prm[i] = params[i];
+        F.prm[10] = (nparams >= 11) ? params[10] : 8.0;
+        if (!(F.prm[4] > 0.0) || !(F.prm[9] > 0.0) || !(F.prm[10] > 0.0))
+            return set_err(TT_EFN, "bi-Maxwellian needs T>0, vmax>0");
+        break;
+    case TT_FN_SEPSUM: {
+        if (nparams < 1) return set_err(TT_EFN, "separable sum needs [r, g...]");
+        int r = (int)params[0];
+        int total = 0;
+        for (int j = 0; j < d; ++j) { F.off[j] = total; total += n[j]; }
+        if (r < 1 || (double)r != params[0] || nparams < 1 + r * total)
+            return set_err(TT_EFN, "separable sum needs 1 + r*sum(n) params");
+        F.sep_r = r;
+        F.sep_total = total;
+        out.table.assign(params + 1, params + 1 + (size_t)r * total);
+        break;
+    }
+    case TT_FN_MAXWELL_2D2V:
+        if (d != 4) return set_err(TT_EFN, "2d2v Maxwellian needs d=4");
+        break;
+    case TT_FN_MAXWELL_3D3V:
+        if (d != 6) return set_err(TT_EFN, "3d3v Maxwellian needs d=6");
+        break;
+    default:
+        return set_err(TT_EFN, "unknown fn_id %d", fn_id);
+    }
+    return TT_OK;
+}
+
+int upload_fn(FnHost &fh)
+{
+    if (fh.table.empty()) { fh.dev.tab = nullptr; return TT_OK; }
+    if (fh.d_table) { (void)hipFree(fh.d_table); fh.d_table = nullptr; }
+    HIPCHK(hipMalloc(&fh.d_table, fh.table.size() * sizeof(double)));
+    HIPCHK(hipMemcpy(fh.d_table, fh.table.data(), fh.table.size() * sizeof(double), hipMemcpyHostToDevice));
+    fh.dev.tab = fh.d_table;
+    return TT_OK;
+}
+
+static int pow2_at_least(int x)
+{
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// Split one mode into tiles: blocks b = [b*n/C, (b+1)*n/C) (Sec. 3: n_j split
+// evenly into C_j pieces), each cut into chunks of at most T entries.
+static void mode_tiles(int n, int C, int T, std::vector<int> &start, std::vector<int> &len,
+                       std::vector<int> &blk)
+{
+    start.clear(); len.clear(); blk.clear();
+    for (int b = 0; b < C; ++b) {
+        const int lo = (int)((int64_t)b * n / C), hi = (int)((int64_t)(b + 1) * n / C);
+        for (int s = lo; s < hi; s += T) {
+            start.push_back(s);
+            len.push_back(std::min(T, hi - s));
+            blk.push_back(b);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Problem lifetime.
+// ---------------------------------------------------------------------------
+Problem::~Problem() { release(); }
+
+void Problem::release()
+{
+    for (void *p : allocs) (void)hipFree(p);
+    allocs.clear();
+    for (hipEvent_t e : prof_events) (void)hipEventDestroy(e);
+    prof_events.clear();
+    if (hm) { (void)hipHostFree(hm); hm = nullptr; }
+    if (fn.d_table) { (void)hipFree(fn.d_table); fn.d_table = nullptr; }
+    if (own_stream && stream) { (void)hipStreamDestroy(stream); }
+    stream = nullptr;
+    own_stream = false;
+    allocated = false;
+    dP = nullptr;
+}
+
+int Problem::dalloc(void **p, size_t bytes)
+{
+    *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return set_err(TT_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    allocs.push_back(*p);
+    return TT_OK;
+}
+
+size_t Problem::device_bytes() const
+{
+    size_t tot = 0;
+    const size_t w = fp32 ? 4 : 8;
+    for (int u = 0; u < d - 1; ++u) {
+        const int k = u + 1;
+        const size_t rows = (size_t)rc[k - 1] * n[k - 1], cols = (size_t)n[k] * rc[k + 1];
+        tot += rows * cols * w + (size_t)rc[k] * (rows + cols) * w + rows + cols;
+    }
+    return tot;
+}
+
+int Problem::allocate()
+{
+    if (allocated) return TT_OK;
+    int st;
+    if (!stream) {
+        if (opt.stream) {
+            stream = (hipStream_t)opt.stream;
+            own_stream = false;
+        } else {
+            HIPCHK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+            own_stream = true;
+        }
+    }
+    if ((st = upload_fn(fn)) != TT_OK) return st;
+    const size_t w = fp32 ? 4 : 8;
+    ProbDev &H = hP;
+    std::memset(&H, 0, sizeof H);
+    H.d = d;
+    H.nk = d - 1;
+    H.r_max = opt.r_max;
+    H.fp32 = fp32;
+    H.F = fn.dev;
+    int rcmax = 1;
+    for (int k = 0; k <= d; ++k) rcmax = std::max(rcmax, rc[k]);
+    H.rcap = rcmax;
+    hist_cap = 2;
+    for (int k = 1; k <= d - 1; ++k) hist_cap += rc[k];
+    H.hist_cap = hist_cap;
+    max_sweeps = hist_cap;
+    int64_t cores_cap = 0, a_cap = 0, rec_cap = 0;
+    for (int u = 0; u < d - 1; ++u) {
+        const int k = u + 1;
+        KDev &K = H.kd[u];
+        K.k = k;
+        K.nk = n[k - 1];
+        K.nk1 = n[k];
+        K.rowcap = rc[k - 1] * n[k - 1];
+        K.colcap = n[k] * rc[k + 1];
+        K.rk_cap = rc[k];
+        // tile geometry: rows of mode k, columns of mode k+1
+        const int TR = opt.tile_rows > 0 ? opt.tile_rows : 32;
+        int maxrun = 1;
+        {
+            const int C = grid[k];
+            for (int b = 0; b < C; ++b)
+                maxrun = std::max(maxrun, (int)((int64_t)(b + 1) * n[k] / C - (int64_t)b * n[k] / C));
+        }
+        int TC = opt.tile_cols > 0 ? opt.tile_cols : std::min(64, pow2_at_least(maxrun));
+        TC = std::min(pow2_at_least(TC), NT);
+        std::vector<int> rs, rl, rb, cs, cl, cb;
+        mode_tiles(n[k - 1], grid[k - 1], TR, rs, rl, rb);
+        mode_tiles(n[k], grid[k], TC, cs, cl, cb);
+        if ((size_t)rc[k] * (TR + TC) * w > 65536)
+            return set_err(TT_EINVAL, "tile %dx%d with rank cap %d needs more than 64 KiB of LDS", TR, TC, rc[k]);
+        K.RTp = (int)rs.size();
+        K.CTq = (int)cs.size();
+        K.TR = TR;
+        K.TC = TC;
+        tileTR[u] = TR;
+        tileTC[u] = TC;
+        int *tabs;
+        if ((st = dalloc((void **)&tabs, sizeof(int) * 3 * (rs.size() + cs.size()))) != TT_OK) return st;
+        std::vector<int> all;
+        all.insert(all.end(), rs.begin(), rs.end());
+        all.insert(all.end(), rl.begin(), rl.end());
+        all.insert(all.end(), rb.begin(), rb.end());
+        all.insert(all.end(), cs.begin(), cs.end());
+        all.insert(all.end(), cl.begin(), cl.end());
+        all.insert(all.end(), cb.begin(), cb.end());
+        HIPCHK(hipMemcpy(tabs, all.data(), sizeof(int) * all.size(), hipMemcpyHostToDevice));
+        const int R = K.RTp, Cc = K.CTq;
+        K.rt_start = tabs; K.rt_len = tabs + R; K.rt_blk = tabs + 2 * R;
+        K.ct_start = tabs + 3 * R; K.ct_len = tabs + 3 * R + Cc; K.ct_blk = tabs + 3 * R + 2 * Cc;
+        const int rk = rc[k];
+        if ((st = dalloc(&K.E, (size_t)K.rowcap * K.colcap * w)) != TT_OK) return st;
+        if ((st = dalloc(&K.W, (size_t)rk * K.rowcap * w)) != TT_OK) return st;
+        if ((st = dalloc(&K.U, (size_t)rk * K.colcap * w)) != TT_OK) return st;
+        if ((st = dalloc((void **)&K.rmask, K.rowcap)) != TT_OK) return st;
+        if ((st = dalloc((void **)&K.cmask, K.colcap)) != TT_OK) return st;
+        if ((st = dalloc((void **)&K.Ifull, sizeof(int) * rk * k)) != TT_OK) return st;
+        if ((st = dalloc((void **)&K.Jfull, sizeof(int) * rk * (d - k))) != TT_OK) return st;
+        if ((st = dalloc((void **)&K.rho, sizeof(int) * rk)) != TT_OK) return st;
+        if ((st = dalloc((void **)&K.gam, sizeof(int) * rk)) != TT_OK) return st;
+        if ((st = dalloc((void **)&K.piv, sizeof(double) * rk)) != TT_OK) return st;
+        if ((st = dalloc((void **)&K.piv64, sizeof(double) * rk)) != TT_OK) return st;
+        if ((st = dalloc((void **)&K.Wp64, sizeof(double) * rcmax * rcmax)) != TT_OK) return st;
+        if ((st = dalloc((void **)&K.Up64, sizeof(double) * rcmax * rcmax)) != TT_OK) return st;
+        K.cand_cap = (rc[k - 1] * K.RTp) * (rc[k + 1] * K.CTq);
+        if ((st = dalloc((void **)&K.cand, sizeof(Cand) * K.cand_cap)) != TT_OK) return st;
+        if ((st = dalloc((void **)&K.hist, sizeof(double) * hist_cap)) != TT_OK) return st;
+        cores_cap += (int64_t)rc[k - 1] * n[k - 1] * rc[k];
+        a_cap += (int64_t)K.rowcap * rk;
+        rec_cap += (int64_t)rk * (rk + 1);
+    }
+    cores_cap += (int64_t)rc[d - 1] * n[d - 1];
+    if ((st = dalloc((void **)&d_cores, sizeof(double) * cores_cap)) != TT_OK) return st;
+    if ((st = dalloc((void **)&d_A, sizeof(double) * std::max<int64_t>(a_cap, 1))) != TT_OK) return st;
+    if ((st = dalloc((void **)&d_rec, sizeof(double) * std::max<int64_t>(rec_cap, 1))) != TT_OK) return st;
+    if ((st = dalloc((void **)&d_vals, sizeof(double) * opt.n_samples)) != TT_OK) return st;
+    if ((st = dalloc((void **)&H.S, sizeof(ProbState))) != TT_OK) return st;
+    HIPCHK(hipHostMalloc((void **)&hm, sizeof(HostMirror), hipHostMallocMapped | hipHostMallocCoherent));
+    HIPCHK(hipHostGetDevicePointer((void **)&H.hm, hm, 0));
+    if ((st = dalloc((void **)&dP, sizeof(ProbDev))) != TT_OK) return st;
+    HIPCHK(hipMemcpy(dP, &H, sizeof(ProbDev), hipMemcpyHostToDevice));
+    allocated = true;
+    return TT_OK;
+}
+
+void Problem::resolve_geometry()
+{
+    // rank capacity per unfolding: r_k <= min(prod n_{<=k}, prod n_{>k}, r_max)
+    rc[0] = rc[d] = 1;
+    for (int k = 1; k <= d - 1; ++k) {
+        double left = 1, right = 1;
+        for (int j = 0; j < k; ++j) left *= n[j];
+        for (int j = k; j < d; ++j) right *= n[j];
+        double m = std::min(std::min(left, right), (double)opt.r_max);
+        rc[k] = (int)m;
+    }
+    for (int j = 0; j < d; ++j) grid[j] = std::max(1, std::min(opt.grid[j], n[j]));
+    int prec = opt.precision;
+    if (prec == TT_PREC_AUTO) prec = (eps >= 1e-6) ? TT_PREC_FP32 : TT_PREC_FP64;
+    fp32 = (prec == TT_PREC_FP32) ? 1 : 0;
+}
+
+template <typename V> int Problem::run_impl()
+{
+    const int nk = d - 1;
+    hipEvent_t ev0, ev1;
+    HIPCHK(hipEventCreate(&ev0));
+    HIPCHK(hipEventCreate(&ev1));
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+    } evg{ev0, ev1};
+    // clear pivot masks
+    for (int u = 0; u < nk; ++u) {
+        HIPCHK(hipMemsetAsync(hP.kd[u].rmask, 0, hP.kd[u].rowcap, stream));
+        HIPCHK(hipMemsetAsync(hP.kd[u].cmask, 0, hP.kd[u].colcap, stream));
+    }
+    hm->sweeps_done = 0;
+    hm->stop = 0;
+    hm->err = 0;
+    std::atomic_thread_fence(std::memory_order_seq_cst);
+    HIPCHK(hipEventRecord(ev0, stream));
+    // a1: samples -> rms, tau, first pivot; initial superblocks
+    const int ns = opt.n_samples;
+    k_samples<<<(ns + NT - 1) / NT, NT, 0, stream>>>(dP, opt.seed, ns, d_vals);
+    k_setup<V><<<1, NT, 0, stream>>>(dP, opt.seed, ns, d_vals, eps);
+    {
+        int maxe = 1;
+        for (int u = 0; u < nk; ++u) maxe = std::max(maxe, n[u] * n[u + 1]);
+        dim3 g((unsigned)std::min(1024, (maxe + NT - 1) / NT), (unsigned)nk);
+        k_init_eval<V><<<g, NT, 0, stream>>>(dP);
+        k_init_extract<V><<<nk, NT, 0, stream>>>(dP);
+    }
+    HIPCHK(hipGetLastError());
+    // search sweeps, queued ahead of the host's view of the stop flag
+    int rub[TT_MAX_D + 1];
+    for (int k = 0; k <= d; ++k) rub[k] = 1;
+    const int L = std::max(1, opt.lookahead);
+    int launched = 0, done_known = 0;
+    const bool prof = opt.profile != 0;
+    if (prof) {
+        while ((int)prof_events.size() < 3 * max_sweeps) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            prof_events.push_back(e);
+        }
+    }
+    bool stopped = false;
+    while (!stopped) {
+        while (launched < done_known + L && launched < max_sweeps) {
+            SweepArgs a;
+            std::memset(&a, 0, sizeof a);
+            a.sweep = launched;
+            a.nk = nk;
+            int tot = 0;
+            size_t lds = 0;
+            for (int u = 0; u < nk; ++u) {
+                const int k = u + 1;
+                const KDev &K = hP.kd[u];
+                a.koff[u] = tot;
+                a.ctub[u] = rub[k + 1] * K.CTq;
+                a.ntl[u] = rub[k - 1] * K.RTp * a.ctub[u];
+                tot += a.ntl[u];
+                lds = std::max(lds, (size_t)rub[k] * (K.TR + K.TC) * sizeof(V));
+            }
+            a.koff[nk] = tot;
+            a.rub = 0;
+            if (prof) HIPCHK(hipEventRecord(prof_events[3 * launched], stream));
+            k_sweep<V><<<tot, NT, lds, stream>>>(dP, a);
+            if (prof) HIPCHK(hipEventRecord(prof_events[3 * launched + 1], stream));
+            k_commit<V><<<nk, NT, 0, stream>>>(dP, a);
+            if (prof) HIPCHK(hipEventRecord(prof_events[3 * launched + 2], stream));
+            ++launched;
+            for (int k = 1; k <= d - 1; ++k) rub[k] = std::min(rub[k] + 1, rc[k]);
+        }
+        HIPCHK(hipGetLastError());
+        // wait for the device to finish another sweep
+        for (;;) {
+            const int sd = __atomic_load_n(&hm->sweeps_done, __ATOMIC_ACQUIRE);
+            if (sd > done_known) { done_known = sd; break; }
+            hipError_t q = hipStreamQuery(stream);
+            if (q != hipErrorNotReady) {
+                if (q != hipSuccess) return set_err(TT_EDEVICE, "sweep failed: %s", hipGetErrorString(q));
+                const int sd2 = __atomic_load_n(&hm->sweeps_done, __ATOMIC_ACQUIRE);
+                if (sd2 > done_known) { done_known = sd2; break; }
+                stopped = true;          // stream idle: every queued sweep has run
+                break;
+            }
+        }
+        if (__atomic_load_n(&hm->stop, __ATOMIC_ACQUIRE)) stopped = true;
+        if (launched >= max_sweeps && done_known >= launched) stopped = true;
+        if (!stopped)
+            for (int k = 1; k <= d - 1; ++k)
+                rub[k] = std::min(rc[k], __atomic_load_n(&hm->r[k], __ATOMIC_RELAXED) + (launched - done_known));
+    }
+    // ranks of the final sweep come from the host mirror
+    int ranks_now[TT_MAX_D + 1];
+    for (int k = 0; k <= d; ++k) ranks_now[k] = __atomic_load_n(&hm->r[k], __ATOMIC_RELAXED);
+    ranks_now[0] = ranks_now[d] = 1;
+    if (hm->err) {
+        HIPCHK(hipStreamSynchronize(stream));
+        return set_err(hm->err, "device reported error %d during the sweeps", hm->err);
+    }
+    // a10: cores by Alg. 4 in FP64
+    CoreArgs ca;
+    std::memset(&ca, 0, sizeof ca);
+    ca.nk = nk;
+    for (int k = 0; k <= d; ++k) ca.ranks[k] = ranks_now[k];
+    int64_t ao = 0, go = 0, dofs = 0;
+    int rb = 0, maxr = 1, maxe = 1;
+    for (int u = 0; u < nk; ++u) {
+        const int k = u + 1;
+        const int nr = ranks_now[k - 1] * n[k - 1], rk = ranks_now[k];
+        ca.aoff[u] = ao;
+        ca.goff[u] = go;
+        ca.doff[u] = dofs;
+        ca.rowblocks[u] = rb;
+        ao += (int64_t)nr * rk;
+        go += (int64_t)nr * rk;
+        dofs += (int64_t)rk * (rk + 1);
+        rb += (nr + NT - 1) / NT;
+        maxr = std::max(maxr, rk);
+        maxe = std::max<int64_t>(maxe, (int64_t)nr * rk);
+    }
+    ca.rowblocks[nk] = rb;
+    ca.goff[nk] = go;
+    cores_len = go + (int64_t)ranks_now[d - 1] * n[d - 1];
+    maxe = std::max(maxe, ranks_now[d - 1] * n[d - 1]);
+    {
+        dim3 g((unsigned)std::min(256, (maxe + NT - 1) / NT), (unsigned)(nk + 1));
+        k_fibers<<<g, NT, 0, stream>>>(dP, ca, d_A, d_cores);
+        k_alg4_pivots<<<nk, NT, sizeof(double) * (maxr * maxr + 2 * maxr), stream>>>(dP, ca, d_A, d_rec);
+        k_alg4_rows<<<rb, NT, sizeof(double) * maxr * maxr, stream>>>(dP, ca, d_A, d_rec, d_cores);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(ev1, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
+    time_to_eps = ms * 1e-3;
+    ProbState S;
+    HIPCHK(hipMemcpy(&S, hP.S, sizeof S, hipMemcpyDeviceToHost));
+    if (S.err) return set_err(S.err, "device reported error %d", S.err);
+    for (int k = 0; k <= d; ++k) ranks[k] = ranks_now[k];
+    rms = S.rms;
+    tau = S.tau;
+    sweeps = S.sweeps;
+    pivoted = (int64_t)S.pivoted;
+    evaluated = 0;
+    for (int k = 1; k <= d - 1; ++k)
+        evaluated += (int64_t)ranks[k - 1] * n[k - 1] * (int64_t)n[k] * ranks[k + 1];
+    for (int u = 0; u < nk; ++u) last_best[u] = S.last_best[u];
+    sweep_alg_bytes = (double)S.alg_bytes;
+    new_entries = (double)S.new_entries;
+    sweep_launches = 0;
+    sweep_kernel_s = commit_kernel_s = 0;
+    if (prof) {
+        for (int s = 0; s < S.sweeps && s < launched; ++s) {
+            float a = 0.f, b = 0.f;
+            HIPCHK(hipEventElapsedTime(&a, prof_events[3 * s], prof_events[3 * s + 1]));
+            HIPCHK(hipEventElapsedTime(&b, prof_events[3 * s + 1], prof_events[3 * s + 2]));
+            sweep_kernel_s += a * 1e-3;
+            commit_kernel_s += b * 1e-3;
+            ++sweep_launches;
+        }
+    }
+    for (int j = 0; j < d; ++j) i0[j] = S.i0[j];
+    ran = true;
+    status = S.capped ? TT_NOT_CONVERGED : TT_OK;
+    return status;
+}
+
+int Problem::run()
+{
+    resolve_geometry();
+    if (allocated && (alloc_fp32 != fp32 || alloc_rmax != opt.r_max || alloc_tr != opt.tile_rows ||
+                      alloc_tc != opt.tile_cols || std::memcmp(alloc_grid, grid, sizeof grid) != 0)) {
+        for (void *p : allocs) (void)hipFree(p);
+        allocs.clear();
+        if (hm) { (void)hipHostFree(hm); hm = nullptr; }
+        allocated = false;
+    }
+    int st = allocate();
+    if (st != TT_OK) return st;
+    alloc_fp32 = fp32;
+    alloc_rmax = opt.r_max;
+    alloc_tr = opt.tile_rows;
+    alloc_tc = opt.tile_cols;
+    std::memcpy(alloc_grid, grid, sizeof grid);
+    ran = false;
+    st = fp32 ? run_impl<float>() : run_impl<double>();
+    status = st;
+    return st;
+}
+
+}  // namespace ttc
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+struct tt_cross_s {
+    Problem p;
+};
+
+const char *tt_last_error(void) { return g_err.c_str(); }
+
+void tt_options_default(tt_options *opt)
+{
+    if (!opt) return;
+    std::memset(opt, 0, sizeof *opt);
+    opt->seed = 0;
+    opt->r_max = 64;
+    opt->precision = TT_PREC_AUTO;
+    opt->pivot_mode = TT_PIVOT_GREEDY;
+    opt->n_samples = 16384;
+    for (int j = 0; j < TT_MAX_D; ++j) opt->grid[j] = 1;
+    opt->tile_rows = 0;
+    opt->tile_cols = 0;
+    opt->lookahead = 2;
+    opt->stream = nullptr;
+}
+
+static int check_options(const tt_options *o)
+{
+    if (!o) return set_err(TT_EINVAL, "options NULL");
+    if (o->r_max < 1 || o->r_max > TT_MAX_RANK) return set_err(TT_EINVAL, "r_max must be in [1,%d]", TT_MAX_RANK);
+    if (o->precision < TT_PREC_AUTO || o->precision > TT_PREC_FP32) return set_err(TT_EINVAL, "bad precision");
+    if (o->pivot_mode != TT_PIVOT_GREEDY) return set_err(TT_EINVAL, "only greedy pivoting is available");
+    if (o->n_samples < 1 || o->n_samples > (1 << 26)) return set_err(TT_EINVAL, "bad n_samples");
+    for (int j = 0; j < TT_MAX_D; ++j)
+        if (o->grid[j] < 1) return set_err(TT_EINVAL, "grid[%d] must be >= 1", j);
+    if (o->tile_rows < 0 || o->tile_rows > 256) return set_err(TT_EINVAL, "tile_rows must be in [0,256]");
+    if (o->tile_cols < 0 || o->tile_cols > 256) return set_err(TT_EINVAL, "tile_cols must be in [0,256]");
+    return TT_OK;
+}
+
+tt_cross_h tt_cross_create(int d, const int32_t *n, double eps, int fn_id, const double *params, int nparams)
+{
+    g_err.clear();
+    if (!(eps >= 0.0) || !(eps < 1.0)) { set_err(TT_EINVAL, "eps must be in [0,1)"); return nullptr; }
+    tt_cross_s *h = new (std::nothrow) tt_cross_s();
+    if (!h) { set_err(TT_ENOMEM, "out of host memory"); return nullptr; }
+    Problem &P = h->p;
+    if (build_fn(fn_id, d, n, params, nparams, P.fn) != TT_OK) { delete h; return nullptr; }
+    P.d = d;
+    for (int j = 0; j < d; ++j) P.n[j] = n[j];
+    P.eps = eps;
+    tt_options_default(&P.opt);
+    return h;
+}
+
+int tt_cross_set_options(tt_cross_h h, const tt_options *opt)
+{
+    if (!h) return set_err(TT_EINVAL, "NULL handle");
+    int st = check_options(opt);
+    if (st) return st;
+    if (h->p.allocated && opt->stream != h->p.opt.stream) {
+        if (h->p.own_stream && h->p.stream) (void)hipStreamDestroy(h->p.stream);
+        h->p.stream = nullptr;
+        h->p.own_stream = false;
+        if (h->p.allocated) {
+            // a new stream needs no new buffers; keep them
+            if (opt->stream) h->p.stream = (hipStream_t)opt->stream;
+            else {
+                if (hipStreamCreateWithFlags(&h->p.stream, hipStreamNonBlocking) != hipSuccess)
+                    return set_err(TT_EDEVICE, "hipStreamCreate failed");
+                h->p.own_stream = true;
+            }
+        }
+    }
+    h->p.opt = *opt;
+    return TT_OK;
+}
+
+int tt_cross_run(tt_cross_h h)
+{
+    if (!h) return set_err(TT_EINVAL, "NULL handle");
+    g_err.clear();
+    return h->p.run();
+}
+
+int tt_cross_get_ranks(tt_cross_h h, int32_t *ranks)
+{
+    if (!h || !ranks) return set_err(TT_EINVAL, "NULL argument");
+    if (!h->p.ran) return set_err(TT_ESTATE, "no completed run");
+    for (int k = 0; k <= h->p.d; ++k) ranks[k] = h->p.ranks[k];
+    return TT_OK;
+}
+
+int64_t tt_cross_get_cores(tt_cross_h h, double *out, int64_t cap, int on_device)
+{
+    if (!h) return set_err(TT_EINVAL, "NULL handle");
+    Problem &P = h->p;
+    if (!P.ran) return set_err(TT_ESTATE, "no completed run");
+    if (!out) return P.cores_len;
+    if (cap < P.cores_len) return set_err(TT_EINVAL, "cap %lld < %lld", (long long)cap, (long long)P.cores_len);
+    HIPCHK(hipMemcpyAsync(out, P.d_cores, sizeof(double) * P.cores_len,
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, P.stream));
+    HIPCHK(hipStreamSynchronize(P.stream));
+    return P.cores_len;
+}
+
+static void tt_args(const Problem &P, TTArgs &a)
+{
+    std::memset(&a, 0, sizeof a);
+    a.d = P.d;
+    for (int j = 0; j < P.d; ++j) a.n[j] = P.n[j];
+    for (int k = 0; k <= P.d; ++k) a.ranks[k] = P.ranks[k];
+    int64_t off = 0;
+    for (int k = 0; k < P.d; ++k) {
+        a.goff[k] = off;
+        off += (int64_t)P.ranks[k] * P.n[k] * P.ranks[k + 1];
+    }
+    a.goff[P.d] = off;
+}
+
+int tt_eval(tt_cross_h h, int64_t m, const int32_t *idx, double *out, int on_device)
+{
+    if (!h) return set_err(TT_EINVAL, "NULL handle");
+    Problem &P = h->p;
+    if (!P.ran) return set_err(TT_ESTATE, "no completed run");
+    if (m < 0 || (m > 0 && (!idx || !out))) return set_err(TT_EINVAL, "bad arguments");
+    if (m == 0) return TT_OK;
+    TTArgs a;
+    tt_args(P, a);
+    const int *didx = idx;
+    double *dout = out;
+    void *tmp_i = nullptr, *tmp_o = nullptr;
+    if (!on_device) {
+        // validate indices on the host before they reach a kernel
+        for (int64_t t = 0; t < m; ++t)
+            for (int j = 0; j < P.d; ++j)
+                if (idx[t * P.d + j] < 0 || idx[t * P.d + j] >= P.n[j])
+                    return set_err(TT_EINVAL, "index %lld,%d out of range", (long long)t, j);
+        HIPCHK(hipMalloc(&tmp_i, sizeof(int) * m * P.d));
+        HIPCHK(hipMalloc(&tmp_o, sizeof(double) * m));
+        HIPCHK(hipMemcpyAsync(tmp_i, idx, sizeof(int) * m * P.d, hipMemcpyHostToDevice, P.stream));
+        didx = (const int *)tmp_i;
+        dout = (double *)tmp_o;
+    }
+    const int64_t waves = std::min<int64_t>(m, 65536);
+    k_tt_eval<<<(unsigned)((waves * 64 + NT - 1) / NT), NT, 0, P.stream>>>(a, P.d_cores, m, didx, dout);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && !on_device) e = hipMemcpyAsync(out, dout, sizeof(double) * m, hipMemcpyDeviceToHost, P.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(P.stream);
+    if (tmp_i) (void)hipFree(tmp_i);
+    if (tmp_o) (void)hipFree(tmp_o);
+    if (e != hipSuccess) return set_err(TT_EDEVICE, "tt_eval: %s", hipGetErrorString(e));
+    return TT_OK;
+}
+
+int tt_cross_get_pivots(tt_cross_h h, int k, int32_t *rows, int32_t *cols)
+{
+    if (!h) return set_err(TT_EINVAL, "NULL handle");
+    Problem &P = h->p;
+    if (!P.ran) return set_err(TT_ESTATE, "no completed run");
+    if (k < 1 || k > P.d - 1) return set_err(TT_EINVAL, "k out of range");
+    const KDev &K = P.hP.kd[k - 1];
+    const int rk = P.ranks[k];
+    if (rows) HIPCHK(hipMemcpy(rows, K.Ifull, sizeof(int) * rk * k, hipMemcpyDeviceToHost));
+    if (cols) HIPCHK(hipMemcpy(cols, K.Jfull, sizeof(int) * rk * (P.d - k), hipMemcpyDeviceToHost));
+    return rk;
+}
+
+int tt_cross_get_history(tt_cross_h h, int k, double *out, int cap)
+{
+    if (!h) return set_err(TT_EINVAL, "NULL handle");
+    Problem &P = h->p;
+    if (!P.ran) return set_err(TT_ESTATE, "no completed run");
+    if (k < 1 || k > P.d - 1) return set_err(TT_EINVAL, "k out of range");
+    const int m = std::min(std::min(P.sweeps, cap), P.hist_cap);
+    if (out && m > 0) HIPCHK(hipMemcpy(out, P.hP.kd[k - 1].hist, sizeof(double) * m, hipMemcpyDeviceToHost));
+    return P.sweeps;
+}
+
+int tt_cross_get_stats(tt_cross_h h, tt_stats *st)
+{
+    if (!h || !st) return set_err(TT_EINVAL, "NULL argument");
+    Problem &P = h->p;
+    std::memset(st, 0, sizeof *st);
+    st->d = P.d;
+    st->status = P.status;
+    if (!P.ran) return TT_OK;
+    st->evaluated = P.evaluated;
+    st->pivoted = P.pivoted;
+    st->samples = P.opt.n_samples;
+    st->sweeps = P.sweeps;
+    st->precision_used = P.fp32 ? TT_PREC_FP32 : TT_PREC_FP64;
+    for (int k = 0; k <= P.d; ++k) st->ranks[k] = P.ranks[k];
+    st->rms = P.rms;
+    st->tau = P.tau;
+    st->time_to_eps_s = P.time_to_eps;
+    for (int u = 0; u < P.d - 1; ++u) st->last_best[u] = P.last_best[u];
+    st->sweep_launches = P.sweep_launches;
+    st->sweep_kernel_s = P.sweep_kernel_s;
+    st->commit_kernel_s = P.commit_kernel_s;
+    st->sweep_alg_bytes = P.sweep_alg_bytes;
+    st->new_entries = P.new_entries;
+    return TT_OK;
+}
+
+int tt_cross_sampled_error(tt_cross_h h, int64_t R, uint64_t seed, double *err)
+{
+    if (!h || !err) return set_err(TT_EINVAL, "NULL argument");
+    Problem &P = h->p;
+    if (!P.ran) return set_err(TT_ESTATE, "no completed run");
+    if (R < 1) return set_err(TT_EINVAL, "R must be >= 1");
+    TTArgs a;
+    tt_args(P, a);
+    int *didx = nullptr;
+    double *x = nullptr, *y = nullptr, *part = nullptr;
+    const int nb = 256;
+    hipError_t e = hipMalloc(&didx, sizeof(int) * R * P.d);
+    if (e == hipSuccess) e = hipMalloc(&x, sizeof(double) * R);
+    if (e == hipSuccess) e = hipMalloc(&y, sizeof(double) * R);
+    if (e == hipSuccess) e = hipMalloc(&part, sizeof(double) * 2 * nb);
+    if (e == hipSuccess) {
+        const unsigned g = (unsigned)((R + NT - 1) / NT);
+        k_gen_idx<<<g, NT, 0, P.stream>>>(P.d, a, seed, R, didx);
+        k_fn_eval<double><<<g, NT, 0, P.stream>>>(P.fn.dev, R, didx, x);
+        const int64_t waves = std::min<int64_t>(R, 65536);
+        k_tt_eval<<<(unsigned)((waves * 64 + NT - 1) / NT), NT, 0, P.stream>>>(a, P.d_cores, R, didx, y);
+        k_err_partial<<<nb, NT, 0, P.stream>>>(R, x, y, part);
+        e = hipGetLastError();
+    }
+    std::vector<double> hp(2 * nb);
+    if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), part, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, P.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(P.stream);
+    if (didx) (void)hipFree(didx);
+    if (x) (void)hipFree(x);
+    if (y) (void)hipFree(y);
+    if (part) (void)hipFree(part);
+    if (e != hipSuccess) return set_err(TT_EDEVICE, "sampled error: %s", hipGetErrorString(e));
+    double num = 0, den = 0;
+    for (int i = 0; i < nb; ++i) { num += hp[2 * i]; den += hp[2 * i + 1]; }
+    *err = den > 0 ? std::sqrt(num / den) : std::sqrt(num);
+    return (*err > P.eps) ? TT_WARN_SAMPLED_ERR : TT_OK;
+}
+
+int tt_fn_eval(int fn_id, int d, const int32_t *n, const double *params, int nparams, int64_t m,
+               const int32_t *idx, double *out, int on_device)
+{
+    g_err.clear();
+    FnHost fh;
+    int st = build_fn(fn_id, d, n, params, nparams, fh);
+    if (st) return st;
+    if (m < 0 || (m > 0 && (!idx || !out))) return set_err(TT_EINVAL, "bad arguments");
+    if (m == 0) return TT_OK;
+    if (!on_device)
+        for (int64_t t = 0; t < m; ++t)
+            for (int j = 0; j < d; ++j)
+                if (idx[t * d + j] < 0 || idx[t * d + j] >= n[j])
+                    return set_err(TT_EINVAL, "index %lld,%d out of range", (long long)t, j);
+    if ((st = upload_fn(fh)) != TT_OK) return st;
+    const int *didx = idx;
+    double *dout = out;
+    void *ti = nullptr, *to = nullptr;
+    hipError_t e = hipSuccess;
+    if (!on_device) {
+        e = hipMalloc(&ti, sizeof(int) * m * d);
+        if (e == hipSuccess) e = hipMalloc(&to, sizeof(double) * m);
+        if (e == hipSuccess) e = hipMemcpy(ti, idx, sizeof(int) * m * d, hipMemcpyHostToDevice);
+        didx = (const int *)ti;
+        dout = (double *)to;
+    }
+    if (e == hipSuccess) {
+        k_fn_eval<double><<<(unsigned)((m + NT - 1) / NT), NT>>>(fh.dev, m, didx, dout);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess && !on_device) e = hipMemcpy(out, dout, sizeof(double) * m, hipMemcpyDeviceToHost);
+    if (ti) (void)hipFree(ti);
+    if (to) (void)hipFree(to);
+    if (fh.d_table) { (void)hipFree(fh.d_table); fh.d_table = nullptr; }
+    if (e != hipSuccess) return set_err(TT_EDEVICE, "tt_fn_eval: %s", hipGetErrorString(e));
+    return TT_OK;
+}
+
+void tt_cross_destroy(tt_cross_h h)
+{
+    if (!h) return;
+    delete h;
+}
+
+}  // extern "C"

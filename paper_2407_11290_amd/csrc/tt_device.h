@@ -1,0 +1,223 @@
+// tt_device.h -- device-side data layout and generating functions of the
+// gfx950 greedy adaptive TT-cross library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tt_cross.h"
+
+namespace ttc {
+
+constexpr int NT = 256;                    // threads per workgroup (4 wave64)
+constexpr double PI = 3.14159265358979323846;
+constexpr uint64_t SM64_GAMMA = 0x9E3779B97F4A7C15ULL;
+
+// ---------------------------------------------------------------------------
+// Generating function descriptor (copied to the device with the problem).
+// ---------------------------------------------------------------------------
+struct FnDev {
+    int id, d;
+    int n[TT_MAX_D];
+    double prm[12];
+    int nprm;
+    double shift;               // Hilbert denominator shift
+    const double *tab;          // separable-sum factor table (device), else null
+    int sep_r, sep_total;
+    int off[TT_MAX_D];          // separable-sum per-mode offsets into a term's factors
+};
+
+// SplitMix64 (Steele, Lea, Flood 2014) is counter based: draw t of the stream
+// seeded with s is the finaliser applied to s + (t+1) * gamma.
+__host__ __device__ inline uint64_t sm64_mix(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+__host__ __device__ inline uint64_t sm64_at(uint64_t seed, uint64_t t)
+{
+    return sm64_mix(seed + (t + 1) * SM64_GAMMA);
+}
+
+template <typename V> struct M;
+template <> struct M<double> {
+    __device__ static double sin(double x) { return ::sin(x); }
+    __device__ static double cos(double x) { return ::cos(x); }
+    __device__ static double exp(double x) { return ::exp(x); }
+    __device__ static double pow(double x, double y) { return ::pow(x, y); }
+    __device__ static double sqrt(double x) { return ::sqrt(x); }
+};
+template <> struct M<float> {
+    __device__ static float sin(float x) { return ::sinf(x); }
+    __device__ static float cos(float x) { return ::cosf(x); }
+    __device__ static float exp(float x) { return ::expf(x); }
+    __device__ static float pow(float x, float y) { return ::powf(x, y); }
+    __device__ static float sqrt(float x) { return ::sqrtf(x); }
+};
+
+template <typename V> __device__ inline V cell(int i, int n, V lo, V hi)
+{
+    return lo + ((V)i + (V)0.5) * ((hi - lo) / (V)n);
+}
+
+// Velocity grid: cell centres of [-vmax, vmax] in n cells.
+template <typename V> __device__ inline V vel(int i, int n, V vmax)
+{
+    return -vmax + ((V)i + (V)0.5) * ((V)2 * vmax / (V)n);
+}
+
+// Value of the generating function at a full 0-based multi-index.  The
+// operation order follows the written formulas term by term, so that FP64
+// values of the Hilbert and separable functions are bitwise reproducible.
+template <typename V> __device__ inline V fn_value(const FnDev &F, const int *idx)
+{
+    switch (F.id) {
+    case TT_FN_HILBERT: {
+        long long s = 0;
+        for (int j = 0; j < F.d; ++j) s += (long long)idx[j] + 1;
+        return (V)1 / ((V)s + (V)F.shift);
+    }
+    case TT_FN_MAXWELL: {
+        const V a = (V)F.prm[0], b = (V)F.prm[1], T = (V)F.prm[2], vmax = (V)F.prm[3];
+        const V twopi = (V)2 * (V)PI;
+        V x1 = (V)idx[0] / (V)F.n[0];
+        V x2 = (V)idx[1] / (V)F.n[1];
+        V x3 = (V)idx[2] / (V)F.n[2];
+        V v1 = vel<V>(idx[3], F.n[3], vmax);
+        V v2 = vel<V>(idx[4], F.n[4], vmax);
+        V v3 = vel<V>(idx[5], F.n[5], vmax);
+        V rho = (V)1 + a * M<V>::sin(twopi * x1) * M<V>::cos(twopi * x2);
+        V ux = b * M<V>::sin(twopi * x3);
+        V q = (v1 - ux) * (v1 - ux) + v2 * v2 + v3 * v3;
+        return rho * M<V>::pow(twopi * T, (V)-1.5) * M<V>::exp(-q / ((V)2 * T));
+    }
+    case TT_FN_BIMAXWELL: {
+        const V vmax = (V)F.prm[10];
+        const V twopi = (V)2 * (V)PI;
+        const int d = F.d;
+        V v[3];
+        for (int c = 0; c < 3; ++c) v[c] = vel<V>(idx[d - 3 + c], F.n[d - 3 + c], vmax);
+        V f = 0;
+        for (int m = 0; m < 2; ++m) {
+            const double *Q = F.prm + 5 * m;
+            V T = (V)Q[4];
+            V q = 0;
+            for (int c = 0; c < 3; ++c) q += (v[c] - (V)Q[1 + c]) * (v[c] - (V)Q[1 + c]);
+            f += (V)Q[0] * M<V>::pow(twopi * T, (V)-1.5) * M<V>::exp(-q / ((V)2 * T));
+        }
+        return f;
+    }
+    case TT_FN_SEPSUM: {
+        V f = 0;
+        for (int m = 0; m < F.sep_r; ++m) {
+            V prod = 1;
+            int off = m * F.sep_total;
+            for (int j = 0; j < F.d; ++j) prod *= (V)F.tab[off + F.off[j] + idx[j]];
+            f += prod;
+        }
+        return f;
+    }
+    case TT_FN_MAXWELL_2D2V:
+    case TT_FN_MAXWELL_3D3V: {
+        const int ndim = (F.id == TT_FN_MAXWELL_2D2V) ? 2 : 3;
+        const V twopi = (V)2 * (V)PI;
+        V pre = 0, em = 0, ep = 0;
+        for (int w = 0; w < ndim; ++w) {
+            V x = cell<V>(idx[2 * w], F.n[2 * w], (V)-0.5, (V)0.5);
+            V vv = cell<V>(idx[2 * w + 1], F.n[2 * w + 1], (V)-3, (V)3);
+            V s = M<V>::sin(twopi * x);
+            V rho = (V)1 + (V)0.875 * s;
+            V T = (V)0.5 + (V)0.4 * s;
+            pre += rho / ((V)2 * M<V>::sqrt(twopi * T));
+            em += (vv - (V)0.75) * (vv - (V)0.75) / ((V)2 * T);
+            ep += (vv + (V)0.75) * (vv + (V)0.75) / ((V)2 * T);
+        }
+        return pre * (M<V>::exp(-em) + M<V>::exp(-ep));
+    }
+    }
+    return (V)0;
+}
+
+// ---------------------------------------------------------------------------
+// Problem layout in device memory.
+// Unfolding u = k-1 (k = 1..d-1 in the paper's numbering) owns superblock
+// X_k(I_{<=k-1} x [n_k], [n_{k+1}] x J_{>k+1}).  Row position of (p, i_k) is
+// p*n_k + i_k, column position of (i_{k+1}, q) is q*n_{k+1} + i_{k+1}, with p,
+// q the insertion indices in I_{<=k-1} and J_{>k+1}; index sets only grow, so
+// positions never move and the superblock grows by appending row and column
+// blocks.
+// ---------------------------------------------------------------------------
+struct Cand {
+    double v;        // |residual| (-1 = none)
+    uint64_t key;    // (row << 32) | col
+};
+
+struct KDev {
+    int k;                        // paper index of the unfolding
+    int nk, nk1;                  // n_k, n_{k+1}
+    int rowcap, colcap;           // capacity of the stored superblock
+    int rk_cap;                   // pivot capacity of this unfolding
+    int RTp, CTq;                 // row tiles per prefix, column tiles per suffix
+    int TR, TC;                   // largest tile extent (LDS/thread layout)
+    const int *rt_start, *rt_len, *rt_blk;    // per row tile within a prefix
+    const int *ct_start, *ct_len, *ct_blk;    // per column tile within a suffix
+    void *E;                      // residual, rowcap x colcap, row-major (sweep precision)
+    void *W;                      // W[z][i] = residual column gamma_z before pivot z
+    void *U;                      // U[z][j] = residual row rho_z before pivot z / p_z
+    uint8_t *rmask, *cmask;       // 1 on rows / columns that hold a pivot
+    int *Ifull;                   // I_{<=k}: rcap tuples of k indices
+    int *Jfull;                   // J_{>k}: rcap tuples of d-k indices
+    int *rho, *gam;               // pivot positions in the superblock
+    double *piv;                  // pivot residual in sweep precision (widened)
+    double *piv64;                // FP64 pivot residual (FP32 sweeps: from the FP64 check)
+    double *Wp64;                 // FP64 pivot-block factors: Wp64[z*rcap+z'] (z' < z)
+    double *Up64;                 // Up64[z'*rcap+z] (z' < z)
+    Cand *cand;                   // per-tile candidates of the current sweep
+    int cand_cap;
+    double *hist;                 // per-sweep largest |residual|
+};
+
+struct ProbState {
+    int r[2][TT_MAX_D + 1];       // committed ranks, double-buffered by sweep parity
+    int ra[TT_MAX_D];             // pivots already applied to the stored region
+    int nr_st[TT_MAX_D], nc_st[TT_MAX_D];
+    unsigned int kdone;
+    int any, stop, capped, err, sweeps;
+    unsigned long long pivoted;
+    unsigned long long alg_bytes;   // algorithmic residual traffic of the tile launches
+    unsigned long long new_entries; // entries evaluated by the tile launches
+    double rms, tau;
+    int i0[TT_MAX_D];
+    double last_best[TT_MAX_D];
+};
+
+struct HostMirror {                // fine-grained host memory, written by the device
+    int sweeps_done;
+    int stop;
+    int err;
+    int r[TT_MAX_D + 1];
+};
+
+struct ProbDev {
+    int d, nk;                    // modes, unfoldings (= d-1)
+    int r_max, rcap;
+    int hist_cap;
+    int fp32;                     // sweeps in FP32 with FP64 pivot check
+    FnDev F;
+    KDev kd[TT_MAX_D];
+    ProbState *S;
+    HostMirror *hm;               // device alias of the host mirror
+};
+
+struct SweepArgs {
+    int sweep;
+    int nk;
+    int koff[TT_MAX_D + 1];       // workgroup offset of each unfolding
+    int ctub[TT_MAX_D];           // column tiles (upper bound) of each unfolding
+    int ntl[TT_MAX_D];            // tiles (upper bound) of each unfolding
+    int rub;                      // rank bound sizing the LDS layout
+};
+
+}  // namespace ttc

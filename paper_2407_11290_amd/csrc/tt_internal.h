@@ -1,0 +1,72 @@
+// tt_internal.h -- host-side problem object behind the C ABI handle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <vector>
+
+#include "tt_cross.h"
+#include "tt_device.h"
+
+namespace ttc {
+
+int set_err(int code, const char *fmt, ...);
+
+struct FnHost {
+    FnDev dev;
+    std::vector<double> table;     // separable-sum factors (host copy)
+    double *d_table = nullptr;     // device copy owned by the holder
+};
+
+int build_fn(int fn_id, int d, const int32_t *n, const double *params, int nparams, FnHost &out);
+int upload_fn(FnHost &fh);
+
+struct Problem {
+    // problem definition
+    int d = 0;
+    int n[TT_MAX_D] = {0};
+    double eps = 0.0;
+    FnHost fn;
+    tt_options opt;
+    // resolved geometry
+    int rc[TT_MAX_D + 1] = {0};    // rank capacity per unfolding (rc[0] = rc[d] = 1)
+    int grid[TT_MAX_D] = {0};      // subtensor blocks per mode
+    int fp32 = 0;
+    int tileTR[TT_MAX_D] = {0}, tileTC[TT_MAX_D] = {0};
+    int hist_cap = 0, max_sweeps = 0;
+    // device state
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool allocated = false;
+    int alloc_fp32 = -1, alloc_rmax = -1, alloc_tr = -1, alloc_tc = -1;
+    int alloc_grid[TT_MAX_D] = {0};
+    std::vector<void *> allocs;
+    ProbDev hP;
+    ProbDev *dP = nullptr;
+    HostMirror *hm = nullptr;
+    double *d_cores = nullptr, *d_A = nullptr, *d_rec = nullptr, *d_vals = nullptr;
+    // results
+    bool ran = false;
+    int status = TT_ESTATE;
+    int ranks[TT_MAX_D + 1] = {0};
+    int64_t cores_len = 0, evaluated = 0, pivoted = 0;
+    int sweeps = 0;
+    double rms = 0, tau = 0, time_to_eps = 0;
+    double last_best[TT_MAX_D] = {0};
+    int sweep_launches = 0;
+    double sweep_kernel_s = 0, commit_kernel_s = 0, sweep_alg_bytes = 0, new_entries = 0;
+    std::vector<hipEvent_t> prof_events;     // 3 per sweep when profiling
+    int i0[TT_MAX_D] = {0};
+
+    ~Problem();
+    void release();
+    int dalloc(void **p, size_t bytes);
+    size_t device_bytes() const;
+    void resolve_geometry();
+    int allocate();
+    int run();
+    template <typename V> int run_impl();
+};
+
+}  // namespace ttc

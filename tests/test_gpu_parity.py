@@ -1,0 +1,224 @@
+"""GPU parity: the HIP path against the FP64 CPU oracle on the same seeded inputs.
+
+FP64 sweeps must reproduce the oracle's pivot index sets bit for bit, and the
+cores (same FP64 operations in the same order) too; reconstructed entries must
+agree within a relative 1e-12.  FP32 sweeps are compared by error against the
+FP64 oracle, within 1e-5 relative.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import Oracle, fn_eval as orc_fn_eval
+from paper_2407_11290_amd import (FN_BIMAXWELL, FN_HILBERT, FN_MAXWELL, FN_MAXWELL_2D2V, FN_MAXWELL_3D3V,
+                                  FN_SEPSUM, NOT_CONVERGED, PREC_FP32, PREC_FP64)
+from paper_2407_11290_amd.api import TTCross, fn_eval as gpu_fn_eval
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _sepsum_params(n, r, seed):
+    rng = np.random.default_rng(seed)
+    return np.concatenate([[float(r)], 0.5 + rng.random(r * int(np.sum(n)))])
+
+
+def _bimax_params(seed):
+    rng = np.random.default_rng(seed)
+    p = []
+    for _ in range(2):
+        p += [rng.uniform(0.5, 2.0), *rng.uniform(-2.0, 2.0, 3), rng.uniform(0.5, 2.0)]
+    return np.array(p + [8.0])
+
+
+def _solve_both(n, eps, fn_id, params=None, seed=0, r_max=64, **kw):
+    _say("n", list(n), "eps", eps, "fn", fn_id, "seed", seed, kw)
+    g = TTCross(n, eps, fn_id, params, seed=seed, r_max=r_max, **kw)
+    gs = g.run()
+    o = Oracle(n, eps, fn_id, params, seed=seed, r_max=r_max)
+    os_ = o.run()
+    return g, gs, o, os_
+
+
+def _assert_same_pivots(g, o):
+    assert list(g.ranks()) == list(o.ranks())
+    for k in range(1, g.d):
+        gr, gc = g.pivots(k)
+        orows, ocols, *_ = o.pivots(k)
+        assert np.array_equal(gr, orows), (k, gr, orows)
+        assert np.array_equal(gc, ocols), (k, gc, ocols)
+
+
+# --------------------------------------------------------------------------
+# generating functions
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("fn_id,n,params,exact", [
+    (FN_HILBERT, [32, 32, 32], None, True),
+    (FN_HILBERT, [64] * 6, None, True),
+    (FN_HILBERT, [7, 9, 5, 11], [2.37], True),
+    (FN_SEPSUM, [5, 6, 7], "sep", True),
+    (FN_MAXWELL, [16] * 6, None, False),
+    (FN_BIMAXWELL, [4, 16, 16, 16], "bimax", False),
+    (FN_MAXWELL_2D2V, [20, 10, 20, 10], None, False),
+    (FN_MAXWELL_3D3V, [8, 4, 8, 4, 8, 4], None, False),
+])
+def test_fn_values(fn_id, n, params, exact):
+    if isinstance(params, str):
+        params = _sepsum_params(n, 3, 1) if params == "sep" else _bimax_params(2)
+    rng = np.random.default_rng(5)
+    idx = np.stack([rng.integers(0, m, 20000) for m in n], axis=1).astype(np.int32)
+    _say("fn values", fn_id, n)
+    a = gpu_fn_eval(fn_id, n, idx, params)
+    b = orc_fn_eval(fn_id, n, idx, params)
+    if exact:
+        assert np.array_equal(a, b)
+    else:
+        assert np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# FP64: bit-exact pivots and cores
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", list(range(10)))
+def test_hilbert3d_n32_bit_exact(seed):
+    """3D Hilbert tensor, n = 32, eps = 1e-10, FP64 (the 32768-entry case)."""
+    g, gs, o, os_ = _solve_both([32, 32, 32], 1e-10, FN_HILBERT, seed=seed, precision=PREC_FP64)
+    assert gs == os_ == 0
+    _assert_same_pivots(g, o)
+    assert np.array_equal(g.cores_flat(), o.cores_flat())
+    st, ost = g.stats(), o.stats()
+    assert st["rms"] == ost["rms"] and st["tau"] == ost["tau"]
+    assert st["sweeps"] == ost["sweeps"] and st["pivoted"] == ost["pivoted"]
+    assert st["evaluated"] == ost["evaluated"]
+    for k in (1, 2):
+        assert np.array_equal(g.history(k), o.history(k))
+    # every entry of the tensor: reconstruction and error
+    idx = np.array(list(itertools.product(range(32), range(32), range(32))), dtype=np.int32)
+    y = g.tt_eval(idx)
+    assert np.array_equal(y, o.tt_eval(idx))
+    x = orc_fn_eval(FN_HILBERT, [32, 32, 32], idx)
+    assert np.linalg.norm(x - y) / np.linalg.norm(x) <= 1e-10
+
+
+@pytest.mark.parametrize("n,grid,tiles", [
+    ([13, 17, 11, 19], [1, 1, 1, 1], (8, 8)),
+    ([13, 17, 11, 19], [2, 3, 1, 2], (4, 4)),
+    ([13, 17, 11, 19], [1, 1, 1, 1], (32, 64)),
+    ([5, 40, 3, 7, 9], [1, 4, 1, 1, 2], (16, 16)),
+    ([2, 2, 2, 2, 2, 2, 2, 2], [1] * 8, (0, 0)),
+])
+def test_ragged_tiles_and_grids_bit_exact(n, grid, tiles):
+    """Several tiles per superblock with ragged tails, and uneven subtensor blocks."""
+    g, gs, o, os_ = _solve_both(n, 1e-9, FN_HILBERT, seed=3, precision=PREC_FP64, grid=grid,
+                                tile_rows=tiles[0], tile_cols=tiles[1])
+    assert gs == os_
+    _assert_same_pivots(g, o)
+    assert np.array_equal(g.cores_flat(), o.cores_flat())
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
+def test_hilbert6d_n64_grid2_bit_exact(seed):
+    """6D Hilbert tensor, n = 64, 2^6 subtensor blocks, eps = 1e-8, FP64."""
+    n = [64] * 6
+    g, gs, o, os_ = _solve_both(n, 1e-8, FN_HILBERT, seed=seed, precision=PREC_FP64, grid=[2] * 6)
+    assert gs == os_ == 0
+    _assert_same_pivots(g, o)
+    assert np.array_equal(g.cores_flat(), o.cores_flat())
+    st, ost = g.stats(), o.stats()
+    assert st["pivoted"] == ost["pivoted"] and st["evaluated"] == ost["evaluated"]
+    rng = np.random.default_rng(seed)
+    idx = rng.integers(0, 64, (20000, 6)).astype(np.int32)
+    assert np.max(np.abs(g.tt_eval(idx) - o.tt_eval(idx))) <= 1e-12 * np.max(np.abs(orc_fn_eval(FN_HILBERT, n, idx)))
+    assert g.sampled_error(1_000_000, seed + 1) <= 1e-8
+
+
+def test_block_grid_invariance():
+    """Sec. 3.2.1: the global pivot is the best of the local pivots, so greedy
+    pivots do not depend on the subtensor grid."""
+    n = [24, 24, 24, 24]
+    ref = None
+    for grid in ([1, 1, 1, 1], [2, 2, 2, 2], [1, 3, 2, 1], [4, 1, 1, 4], [3, 3, 3, 3]):
+        _say("grid", grid)
+        g = TTCross(n, 1e-9, FN_HILBERT, seed=1, precision=PREC_FP64, grid=grid)
+        g.run()
+        piv = [g.pivots(k) for k in range(1, 4)]
+        if ref is None:
+            ref = piv
+        else:
+            for (a, b), (c, e) in zip(piv, ref):
+                assert np.array_equal(a, c) and np.array_equal(b, e)
+
+
+def test_sepsum_exact_recovery_bit_exact():
+    n = [9, 10, 11, 8, 7]
+    params = _sepsum_params(n, 4, 2)
+    g, gs, o, os_ = _solve_both(n, 1e-12, FN_SEPSUM, params, seed=7, precision=PREC_FP64)
+    _assert_same_pivots(g, o)
+    assert (g.ranks()[1:-1] <= 4).all()
+    assert np.array_equal(g.cores_flat(), o.cores_flat())
+
+
+def test_bimaxwellian_rank_two():
+    n = [8, 32, 32, 32]
+    p = _bimax_params(3)
+    g, gs, o, os_ = _solve_both(n, 1e-10, FN_BIMAXWELL, p, seed=1, precision=PREC_FP64)
+    assert (g.ranks()[1:-1] <= 2).all()
+    rng = np.random.default_rng(0)
+    idx = np.stack([rng.integers(0, m, 5000) for m in n], axis=1).astype(np.int32)
+    x = orc_fn_eval(FN_BIMAXWELL, n, idx, p)
+    assert np.linalg.norm(g.tt_eval(idx) - x) / np.linalg.norm(x) < 1e-10
+
+
+def test_rank_cap_and_d2_edge_cases():
+    g, gs, o, os_ = _solve_both([16, 16, 16], 1e-14, FN_HILBERT, seed=0, r_max=4, precision=PREC_FP64)
+    assert gs == os_ == NOT_CONVERGED
+    _assert_same_pivots(g, o)
+    # d = 2 (a matrix), a mode of size 1, and a tiny full-rank case
+    for n in ([100, 100], [1, 30, 30], [3, 1, 4], [2, 3]):
+        g, gs, o, os_ = _solve_both(n, 1e-12, FN_HILBERT, seed=2, precision=PREC_FP64)
+        assert gs == os_
+        _assert_same_pivots(g, o)
+        assert np.array_equal(g.cores_flat(), o.cores_flat())
+
+
+def test_eval_on_device_tensors():
+    import torch
+    g = TTCross([32, 32, 32], 1e-10, FN_HILBERT, seed=0, precision=PREC_FP64)
+    g.run()
+    idx = torch.randint(0, 32, (10000, 3), dtype=torch.int32, device="cuda")
+    y = g.tt_eval(idx).cpu().numpy()
+    assert np.array_equal(y, g.tt_eval(idx.cpu().numpy()))
+    x = gpu_fn_eval(FN_HILBERT, [32, 32, 32], idx).cpu().numpy()
+    assert np.array_equal(x, orc_fn_eval(FN_HILBERT, [32, 32, 32], idx.cpu().numpy()))
+
+
+# --------------------------------------------------------------------------
+# FP32 sweeps with FP64 pivot check, stop test and cores
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_maxwellian6d_fp32_against_fp64_oracle(seed):
+    """Single 3d3v Maxwellian, n = 128, eps = 1e-6: FP32 sweeps, FP64 check."""
+    n = [128] * 6
+    g, gs, o, os_ = _solve_both(n, 1e-6, FN_MAXWELL, seed=seed, precision=PREC_FP32, grid=[2] * 6)
+    assert g.stats()["precision_used"] == PREC_FP32
+    rng = np.random.default_rng(seed)
+    idx = rng.integers(0, 128, (100000, 6)).astype(np.int32)
+    yg, yo = g.tt_eval(idx), o.tt_eval(idx)
+    x = orc_fn_eval(FN_MAXWELL, n, idx)
+    # reconstructed entries within 1e-5 of the FP64 oracle's (relative to max |X|)
+    assert np.max(np.abs(yg - yo)) <= 1e-5 * np.max(np.abs(x))
+    assert g.sampled_error(1_000_000, 11) <= 1e-6
+
+
+def test_hilbert_fp32_sweeps_meet_eps():
+    n = [32] * 5
+    g, gs, o, os_ = _solve_both(n, 1e-6, FN_HILBERT, seed=4, precision=PREC_FP32)
+    assert g.sampled_error(200_000, 3) <= 1e-6
+    rng = np.random.default_rng(1)
+    idx = rng.integers(0, 32, (20000, 5)).astype(np.int32)
+    x = orc_fn_eval(FN_HILBERT, n, idx)
+    assert np.max(np.abs(g.tt_eval(idx) - o.tt_eval(idx))) <= 1e-5 * np.max(np.abs(x))
