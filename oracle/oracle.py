@@ -46,6 +46,8 @@ def lib():
         L.orc_splitmix64_draw.restype = C.c_uint64
         L.orc_splitmix64_draw.argtypes = [C.c_uint64, C.c_int64, u64p]
         L.orc_sample_indices.argtypes = [C.c_int, i32p, C.c_uint64, C.c_int64, i32p]
+        L.orc_pairwise_sumsq.restype = C.c_double
+        L.orc_pairwise_sumsq.argtypes = [f64p, C.c_int64]
         _lib = L
     return _lib
 
@@ -68,6 +70,11 @@ def sample_indices(n, seed, count):
     out = np.zeros((count, n.size), dtype=np.int32)
     lib().orc_sample_indices(n.size, n, C.c_uint64(seed), count, out)
     return out
+
+
+def pairwise_sumsq(v):
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    return lib().orc_pairwise_sumsq(v, v.size)
 
 
 def fn_eval(fn_id, n, idx, params=None):

@@ -29,7 +29,8 @@
  * Readings where the paper is silent (stated once here, used below):
  *   - stop: a sweep in which no unfolding finds |residual| > tau proposes
  *     nothing and ends the run; tau = eps * rms, with rms taken over N_s seeded
- *     sample entries;  a k at the rank cap proposes nothing;
+ *     sample entries (squares summed pairwise, see orc_pairwise_sumsq);  a k at
+ *     the rank cap proposes nothing;
  *   - initial pivot: the sample with the largest |value| (first one on ties),
  *     replicated as pivot 1 of every unfolding (Alg. 1 starts from samples);
  *   - tie-break: lowest (row position, column position), where row position =
@@ -83,6 +84,24 @@ void orc_sample_indices(int d, const int *n, uint64_t seed, int64_t count, int *
     uint64_t s = seed;
     for (int64_t t = 0; t < count; ++t)
         for (int j = 0; j < d; ++j) idx[t * d + j] = (int)(orc_sm64(&s) % (uint64_t)n[j]);
+}
+
+/* Sum of squares by pairwise summation: the squares, padded with zeros to a
+ * power-of-two count, are added in adjacent pairs level by level until one
+ * value remains.  (The paper does not fix a summation order for the sample
+ * norm; a balanced tree is the order a parallel reduction can reproduce.) */
+double orc_pairwise_sumsq(const double *v, int64_t n)
+{
+    int64_t m = 1;
+    while (m < n) m <<= 1;
+    double *a = (double *)calloc((size_t)m, sizeof(double));
+    if (!a) return NAN;
+    for (int64_t i = 0; i < n; ++i) a[i] = v[i] * v[i];
+    for (int64_t w = m; w > 1; w >>= 1)
+        for (int64_t i = 0; i < w / 2; ++i) a[i] = a[2 * i] + a[2 * i + 1];
+    double s = a[0];
+    free(a);
+    return s;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -425,14 +444,18 @@ int orc_run(orc_state *S)
     int *sidx = (int *)malloc(sizeof(int) * (size_t)S->n_samples * d);
     if (!sidx) return S->status = ORC_ENOMEM;
     orc_sample_indices(d, S->n, S->seed, S->n_samples, sidx);
-    double sumsq = 0.0, bestv = -1.0;
+    double *sval = (double *)malloc(sizeof(double) * (size_t)S->n_samples);
+    if (!sval) { free(sidx); return S->status = ORC_ENOMEM; }
+    double bestv = -1.0;
     int64_t bests = 0;
     for (int64_t s = 0; s < S->n_samples; ++s) {
         double v = orc_eval(&S->F, sidx + s * d);
-        if (!isfinite(v)) { free(sidx); return S->status = ORC_EFN; }
-        sumsq += v * v;
+        if (!isfinite(v)) { free(sidx); free(sval); return S->status = ORC_EFN; }
+        sval[s] = v;
         if (fabs(v) > bestv) { bestv = fabs(v); bests = s; }
     }
+    double sumsq = orc_pairwise_sumsq(sval, S->n_samples);
+    free(sval);
     S->rms = sqrt(sumsq / (double)S->n_samples);
     S->tau = S->eps * S->rms;
     for (int j = 0; j < d; ++j) S->i0[j] = sidx[bests * d + j];

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 import scipy.linalg.lapack as lapack
 
-from oracle import Oracle, fn_eval, matrix_residual, sample_indices, splitmix64, tt_eval
+from oracle import Oracle, fn_eval, matrix_residual, pairwise_sumsq, sample_indices, splitmix64, tt_eval
 from oracle.oracle import FN_BIMAXWELL, FN_HILBERT, FN_MAXWELL, FN_MAXWELL_2D2V, FN_MAXWELL_3D3V, FN_SEPSUM
 
 
@@ -37,6 +37,23 @@ def test_splitmix64_published_outputs(golden_dir):
     want = [int(x, 16) for x in lines]
     got = [int(x) for x in splitmix64(0, len(want))]
     assert got == want
+
+
+def test_pairwise_sumsq_against_exact_rational_sum():
+    """The sample norm's pairwise sum of squares is within the pairwise
+    summation error bound (about log2(n) ulps) of the exact sum, and is exact
+    on values whose squares are exactly representable integers."""
+    rng = np.random.default_rng(4)
+    for n in (1, 2, 3, 1000, 16384, 20000):
+        v = rng.standard_normal(n)
+        exact = sum(fractions.Fraction(float(x)) ** 2 for x in v)
+        got = pairwise_sumsq(v)
+        assert abs(fractions.Fraction(got) - exact) <= exact * (np.log2(max(n, 2)) + 2) * 2.0 ** -52
+    ints = np.arange(1, 1001, dtype=np.float64)
+    assert pairwise_sumsq(ints) == float(sum(int(x) ** 2 for x in ints))
+    # padding: the tree over 3 values is (a^2 + b^2) + (c^2 + 0)
+    a, b, c = 0.1, 0.7, 1.3
+    assert pairwise_sumsq([a, b, c]) == (a * a + b * b) + (c * c + 0.0)
 
 
 def test_sample_indices_are_in_range_and_stream_ordered():
