@@ -123,11 +123,11 @@ typedef struct tt_stats {
     int32_t sweep_launches;     /* search-tile launches that did work (one per sweep) */
     int32_t pad0;
     double sweep_kernel_s;      /* summed duration of those launches */
-    double commit_kernel_s;     /* summed duration of the per-sweep commit launches */
     double sweep_alg_bytes;     /* algorithmic residual traffic of the tile launches: 2w per
                                    updated stored entry, w per scanned-only stored entry,
                                    w per newly evaluated entry (w = 8 FP64, 4 FP32) */
     double new_entries;         /* superblock entries evaluated by the tile launches */
+    double sweep_phase_s;       /* device time from the first search launch to the end of the last one */
 } tt_stats;
 
 typedef struct tt_cross_s *tt_cross_h;

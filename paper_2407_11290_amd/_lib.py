@@ -51,9 +51,9 @@ class Stats(C.Structure):
         ("sweep_launches", C.c_int32),
         ("pad0", C.c_int32),
         ("sweep_kernel_s", C.c_double),
-        ("commit_kernel_s", C.c_double),
         ("sweep_alg_bytes", C.c_double),
         ("new_entries", C.c_double),
+        ("sweep_phase_s", C.c_double),
     ]
 
 

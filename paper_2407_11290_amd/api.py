@@ -137,8 +137,8 @@ class TTCross:
             "ranks": list(s.ranks)[: self.d + 1], "rms": s.rms, "tau": s.tau,
             "time_to_eps_s": s.time_to_eps_s, "last_best": list(s.last_best)[: self.d - 1],
             "sweep_launches": s.sweep_launches, "sweep_kernel_s": s.sweep_kernel_s,
-            "commit_kernel_s": s.commit_kernel_s, "sweep_alg_bytes": s.sweep_alg_bytes,
-            "new_entries": s.new_entries,
+            "sweep_alg_bytes": s.sweep_alg_bytes,
+            "new_entries": s.new_entries, "sweep_phase_s": s.sweep_phase_s,
         }
 
     def tt_eval(self, idx):

@@ -194,6 +194,11 @@ int Problem::allocate()
         }
     }
     if ((st = upload_fn(fn)) != TT_OK) return st;
+    {
+        int dev = 0;
+        HIPCHK(hipGetDevice(&dev));
+        HIPCHK(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    }
     const size_t w = fp32 ? 4 : 8;
     ProbDev &H = hP;
     std::memset(&H, 0, sizeof H);
@@ -220,7 +225,7 @@ int Problem::allocate()
         K.colcap = n[k] * rc[k + 1];
         K.rk_cap = rc[k];
         // tile geometry: rows of mode k, columns of mode k+1
-        const int TR = opt.tile_rows > 0 ? opt.tile_rows : 32;
+        int TR = opt.tile_rows > 0 ? opt.tile_rows : 32;
         int maxrun = 1;
         {
             const int C = grid[k];
@@ -229,11 +234,19 @@ int Problem::allocate()
         }
         int TC = opt.tile_cols > 0 ? opt.tile_cols : std::min(64, pow2_at_least(maxrun));
         TC = std::min(pow2_at_least(TC), NT);
+        if (opt.tile_rows <= 0 && opt.tile_cols <= 0) {
+            // shrink the default tile until its LDS fits next to the rank cap
+            while (sweep_lds_bytes(rc[k], TR, TC, w) + 1024 > (size_t)lds_limit && (TC > 16 || TR > 8)) {
+                if (TC > 16) TC /= 2;
+                else TR /= 2;
+            }
+        }
         std::vector<int> rs, rl, rb, cs, cl, cb;
         mode_tiles(n[k - 1], grid[k - 1], TR, rs, rl, rb);
         mode_tiles(n[k], grid[k], TC, cs, cl, cb);
-        if ((size_t)rc[k] * (TR + TC) * w > 65536)
-            return set_err(TT_EINVAL, "tile %dx%d with rank cap %d needs more than 64 KiB of LDS", TR, TC, rc[k]);
+        if (sweep_lds_bytes(rc[k], TR, TC, w) + 1024 > (size_t)lds_limit)
+            return set_err(TT_EINVAL, "tile %dx%d with rank cap %d needs more LDS than a workgroup has (%d B)",
+                           TR, TC, rc[k], lds_limit);
         K.RTp = (int)rs.size();
         K.CTq = (int)cs.size();
         K.TR = TR;
@@ -255,10 +268,8 @@ int Problem::allocate()
         K.ct_start = tabs + 3 * R; K.ct_len = tabs + 3 * R + Cc; K.ct_blk = tabs + 3 * R + 2 * Cc;
         const int rk = rc[k];
         if ((st = dalloc(&K.E, (size_t)K.rowcap * K.colcap * w)) != TT_OK) return st;
-        if ((st = dalloc(&K.W, (size_t)rk * K.rowcap * w)) != TT_OK) return st;
-        if ((st = dalloc(&K.U, (size_t)rk * K.colcap * w)) != TT_OK) return st;
-        if ((st = dalloc((void **)&K.rmask, K.rowcap)) != TT_OK) return st;
-        if ((st = dalloc((void **)&K.cmask, K.colcap)) != TT_OK) return st;
+        if ((st = dalloc((void **)&K.rpiv, K.rowcap)) != TT_OK) return st;
+        if ((st = dalloc((void **)&K.cpiv, K.colcap)) != TT_OK) return st;
         if ((st = dalloc((void **)&K.Ifull, sizeof(int) * rk * k)) != TT_OK) return st;
         if ((st = dalloc((void **)&K.Jfull, sizeof(int) * rk * (d - k))) != TT_OK) return st;
         if ((st = dalloc((void **)&K.rho, sizeof(int) * rk)) != TT_OK) return st;
@@ -315,26 +326,21 @@ template <typename V> int Problem::run_impl()
         hipEvent_t a, b;
         ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
     } evg{ev0, ev1};
-    // clear pivot masks
-    for (int u = 0; u < nk; ++u) {
-        HIPCHK(hipMemsetAsync(hP.kd[u].rmask, 0, hP.kd[u].rowcap, stream));
-        HIPCHK(hipMemsetAsync(hP.kd[u].cmask, 0, hP.kd[u].colcap, stream));
-    }
     hm->sweeps_done = 0;
     hm->stop = 0;
     hm->err = 0;
     std::atomic_thread_fence(std::memory_order_seq_cst);
     HIPCHK(hipEventRecord(ev0, stream));
-    // a1: samples -> rms, tau, first pivot; initial superblocks
+    // a1: samples -> rms, tau, first pivot; initial superblocks (the sample
+    // kernel also clears the pivot maps)
     const int ns = opt.n_samples;
-    k_samples<<<(ns + NT - 1) / NT, NT, 0, stream>>>(dP, opt.seed, ns, d_vals);
+    k_samples<<<std::max(64, (ns + NT - 1) / NT), NT, 0, stream>>>(dP, opt.seed, ns, d_vals);
     k_setup<V><<<1, NT, 0, stream>>>(dP, opt.seed, ns, d_vals, eps);
     {
         int maxe = 1;
         for (int u = 0; u < nk; ++u) maxe = std::max(maxe, n[u] * n[u + 1]);
         dim3 g((unsigned)std::min(1024, (maxe + NT - 1) / NT), (unsigned)nk);
         k_init_eval<V><<<g, NT, 0, stream>>>(dP);
-        k_init_extract<V><<<nk, NT, 0, stream>>>(dP);
     }
     HIPCHK(hipGetLastError());
     // search sweeps, queued ahead of the host's view of the stop flag
@@ -354,7 +360,6 @@ template <typename V> int Problem::run_impl()
     while (!stopped) {
         while (launched < done_known + L && launched < max_sweeps) {
             SweepArgs a;
-            std::memset(&a, 0, sizeof a);
             a.sweep = launched;
             a.nk = nk;
             int tot = 0;
@@ -362,21 +367,18 @@ template <typename V> int Problem::run_impl()
             for (int u = 0; u < nk; ++u) {
                 const int k = u + 1;
                 const KDev &K = hP.kd[u];
-                a.koff[u] = tot;
-                a.ctub[u] = rub[k + 1] * K.CTq;
-                a.ntl[u] = rub[k - 1] * K.RTp * a.ctub[u];
-                tot += a.ntl[u];
-                lds = std::max(lds, (size_t)rub[k] * (K.TR + K.TC) * sizeof(V));
+                tot += rub[k - 1] * K.RTp * rub[k + 1] * K.CTq;
+                lds = std::max(lds, sweep_lds_bytes(rub[k], K.TR, K.TC, sizeof(V)));
             }
-            a.koff[nk] = tot;
-            a.rub = 0;
+            // enough workgroups for the largest superblocks this sweep can have;
+            // the kernel strides over the exact tile count it reads on the device
+            const int grid = std::max(1, std::min(tot, sweep_grid_cap));
             if (prof) HIPCHK(hipEventRecord(prof_events[3 * launched], stream));
-            k_sweep<V><<<tot, NT, lds, stream>>>(dP, a);
+            k_sweep<V><<<grid, NT, lds, stream>>>(dP, a);
             if (prof) HIPCHK(hipEventRecord(prof_events[3 * launched + 1], stream));
-            k_commit<V><<<nk, NT, 0, stream>>>(dP, a);
-            if (prof) HIPCHK(hipEventRecord(prof_events[3 * launched + 2], stream));
             ++launched;
             for (int k = 1; k <= d - 1; ++k) rub[k] = std::min(rub[k] + 1, rc[k]);
+            k_commit<V><<<1, NTC, 0, stream>>>(dP, a);
         }
         HIPCHK(hipGetLastError());
         // wait for the device to finish another sweep
@@ -423,7 +425,7 @@ template <typename V> int Problem::run_impl()
         ao += (int64_t)nr * rk;
         go += (int64_t)nr * rk;
         dofs += (int64_t)rk * (rk + 1);
-        rb += (nr + NT - 1) / NT;
+        rb += (nr + A4W - 1) / A4W;
         maxr = std::max(maxr, rk);
         maxe = std::max<int64_t>(maxe, (int64_t)nr * rk);
     }
@@ -434,8 +436,12 @@ template <typename V> int Problem::run_impl()
     {
         dim3 g((unsigned)std::min(256, (maxe + NT - 1) / NT), (unsigned)(nk + 1));
         k_fibers<<<g, NT, 0, stream>>>(dP, ca, d_A, d_cores);
-        k_alg4_pivots<<<nk, NT, sizeof(double) * (maxr * maxr + 2 * maxr), stream>>>(dP, ca, d_A, d_rec);
-        k_alg4_rows<<<rb, NT, sizeof(double) * maxr * maxr, stream>>>(dP, ca, d_A, d_rec, d_cores);
+        const size_t lp = sizeof(double) * (2 * maxr * maxr + 2 * maxr);
+        if (lp > (size_t)lds_limit) return set_err(TT_EINVAL, "rank %d too large for the core kernel", maxr);
+        k_alg4_pivots<<<nk, NT, lp, stream>>>(dP, ca, d_A, d_rec);
+        const size_t lr = sizeof(double) * ((size_t)2 * maxr * A4W + (size_t)maxr * maxr + (size_t)maxr * (maxr + 1));
+        if (lr > (size_t)lds_limit) return set_err(TT_EINVAL, "rank %d too large for the core kernel", maxr);
+        k_alg4_rows<<<rb, A4W, lr, stream>>>(dP, ca, d_A, d_rec, d_cores);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev1, stream));
@@ -458,15 +464,18 @@ template <typename V> int Problem::run_impl()
     sweep_alg_bytes = (double)S.alg_bytes;
     new_entries = (double)S.new_entries;
     sweep_launches = 0;
-    sweep_kernel_s = commit_kernel_s = 0;
+    sweep_kernel_s = sweep_phase_s = 0;
     if (prof) {
         for (int s = 0; s < S.sweeps && s < launched; ++s) {
-            float a = 0.f, b = 0.f;
+            float a = 0.f;
             HIPCHK(hipEventElapsedTime(&a, prof_events[3 * s], prof_events[3 * s + 1]));
-            HIPCHK(hipEventElapsedTime(&b, prof_events[3 * s + 1], prof_events[3 * s + 2]));
             sweep_kernel_s += a * 1e-3;
-            commit_kernel_s += b * 1e-3;
             ++sweep_launches;
+        }
+        if (sweep_launches > 0) {
+            float c = 0.f;
+            HIPCHK(hipEventElapsedTime(&c, prof_events[0], prof_events[3 * (sweep_launches - 1) + 1]));
+            sweep_phase_s = c * 1e-3;
         }
     }
     for (int j = 0; j < d; ++j) i0[j] = S.i0[j];
@@ -700,9 +709,9 @@ int tt_cross_get_stats(tt_cross_h h, tt_stats *st)
     for (int u = 0; u < P.d - 1; ++u) st->last_best[u] = P.last_best[u];
     st->sweep_launches = P.sweep_launches;
     st->sweep_kernel_s = P.sweep_kernel_s;
-    st->commit_kernel_s = P.commit_kernel_s;
     st->sweep_alg_bytes = P.sweep_alg_bytes;
     st->new_entries = P.new_entries;
+    st->sweep_phase_s = P.sweep_phase_s;
     return TT_OK;
 }
 

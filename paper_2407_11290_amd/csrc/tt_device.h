@@ -68,26 +68,28 @@ template <typename V> __device__ inline V vel(int i, int n, V vmax)
     return -vmax + ((V)i + (V)0.5) * ((V)2 * vmax / (V)n);
 }
 
-// Value of the generating function at a full 0-based multi-index.  The
-// operation order follows the written formulas term by term, so that FP64
-// values of the Hilbert and separable functions are bitwise reproducible.
-template <typename V> __device__ inline V fn_value(const FnDev &F, const int *idx)
+// Value of the generating function at a full 0-based multi-index, read
+// through ix(j) (an accessor, so callers can assemble the index from LDS-staged
+// prefixes and suffixes without a private array).  The operation order follows
+// the written formulas term by term, so that FP64 values of the Hilbert and
+// separable functions are bitwise reproducible.
+template <typename V, typename IX> __device__ inline V fn_value_ix(const FnDev &F, IX ix)
 {
     switch (F.id) {
     case TT_FN_HILBERT: {
         long long s = 0;
-        for (int j = 0; j < F.d; ++j) s += (long long)idx[j] + 1;
+        for (int j = 0; j < F.d; ++j) s += (long long)ix(j) + 1;
         return (V)1 / ((V)s + (V)F.shift);
     }
     case TT_FN_MAXWELL: {
         const V a = (V)F.prm[0], b = (V)F.prm[1], T = (V)F.prm[2], vmax = (V)F.prm[3];
         const V twopi = (V)2 * (V)PI;
-        V x1 = (V)idx[0] / (V)F.n[0];
-        V x2 = (V)idx[1] / (V)F.n[1];
-        V x3 = (V)idx[2] / (V)F.n[2];
-        V v1 = vel<V>(idx[3], F.n[3], vmax);
-        V v2 = vel<V>(idx[4], F.n[4], vmax);
-        V v3 = vel<V>(idx[5], F.n[5], vmax);
+        V x1 = (V)ix(0) / (V)F.n[0];
+        V x2 = (V)ix(1) / (V)F.n[1];
+        V x3 = (V)ix(2) / (V)F.n[2];
+        V v1 = vel<V>(ix(3), F.n[3], vmax);
+        V v2 = vel<V>(ix(4), F.n[4], vmax);
+        V v3 = vel<V>(ix(5), F.n[5], vmax);
         V rho = (V)1 + a * M<V>::sin(twopi * x1) * M<V>::cos(twopi * x2);
         V ux = b * M<V>::sin(twopi * x3);
         V q = (v1 - ux) * (v1 - ux) + v2 * v2 + v3 * v3;
@@ -98,7 +100,7 @@ template <typename V> __device__ inline V fn_value(const FnDev &F, const int *id
         const V twopi = (V)2 * (V)PI;
         const int d = F.d;
         V v[3];
-        for (int c = 0; c < 3; ++c) v[c] = vel<V>(idx[d - 3 + c], F.n[d - 3 + c], vmax);
+        for (int c = 0; c < 3; ++c) v[c] = vel<V>(ix(d - 3 + c), F.n[d - 3 + c], vmax);
         V f = 0;
         for (int m = 0; m < 2; ++m) {
             const double *Q = F.prm + 5 * m;
@@ -114,7 +116,7 @@ template <typename V> __device__ inline V fn_value(const FnDev &F, const int *id
         for (int m = 0; m < F.sep_r; ++m) {
             V prod = 1;
             int off = m * F.sep_total;
-            for (int j = 0; j < F.d; ++j) prod *= (V)F.tab[off + F.off[j] + idx[j]];
+            for (int j = 0; j < F.d; ++j) prod *= (V)F.tab[off + F.off[j] + ix(j)];
             f += prod;
         }
         return f;
@@ -125,8 +127,8 @@ template <typename V> __device__ inline V fn_value(const FnDev &F, const int *id
         const V twopi = (V)2 * (V)PI;
         V pre = 0, em = 0, ep = 0;
         for (int w = 0; w < ndim; ++w) {
-            V x = cell<V>(idx[2 * w], F.n[2 * w], (V)-0.5, (V)0.5);
-            V vv = cell<V>(idx[2 * w + 1], F.n[2 * w + 1], (V)-3, (V)3);
+            V x = cell<V>(ix(2 * w), F.n[2 * w], (V)-0.5, (V)0.5);
+            V vv = cell<V>(ix(2 * w + 1), F.n[2 * w + 1], (V)-3, (V)3);
             V s = M<V>::sin(twopi * x);
             V rho = (V)1 + (V)0.875 * s;
             V T = (V)0.5 + (V)0.4 * s;
@@ -140,6 +142,12 @@ template <typename V> __device__ inline V fn_value(const FnDev &F, const int *id
     return (V)0;
 }
 
+template <typename V> __device__ inline V fn_value(const FnDev &F, const int *idx)
+{
+    return fn_value_ix<V>(F, [&](int j) { return idx[j]; });
+}
+
+
 // ---------------------------------------------------------------------------
 // Problem layout in device memory.
 // Unfolding u = k-1 (k = 1..d-1 in the paper's numbering) owns superblock
@@ -152,6 +160,7 @@ template <typename V> __device__ inline V fn_value(const FnDev &F, const int *id
 struct Cand {
     double v;        // |residual| (-1 = none)
     uint64_t key;    // (row << 32) | col
+    double sv;       // signed residual
 };
 
 struct KDev {
@@ -163,10 +172,8 @@ struct KDev {
     int TR, TC;                   // largest tile extent (LDS/thread layout)
     const int *rt_start, *rt_len, *rt_blk;    // per row tile within a prefix
     const int *ct_start, *ct_len, *ct_blk;    // per column tile within a suffix
-    void *E;                      // residual, rowcap x colcap, row-major (sweep precision)
-    void *W;                      // W[z][i] = residual column gamma_z before pivot z
-    void *U;                      // U[z][j] = residual row rho_z before pivot z / p_z
-    uint8_t *rmask, *cmask;       // 1 on rows / columns that hold a pivot
+    void *E;                      // residual / frozen factors, rowcap x colcap, row-major
+    uint8_t *rpiv, *cpiv;         // z+1 on the row / column of pivot z, else 0
     int *Ifull;                   // I_{<=k}: rcap tuples of k indices
     int *Jfull;                   // J_{>k}: rcap tuples of d-k indices
     int *rho, *gam;               // pivot positions in the superblock
@@ -179,12 +186,20 @@ struct KDev {
     double *hist;                 // per-sweep largest |residual|
 };
 
+// What one search sweep does to one unfolding, prepared by the previous commit.
+struct KSweep {
+    int rk;                       // committed pivots (all eliminated from new entries)
+    int apply;                    // 1: pivot rk-1 still has to be applied to stored residuals
+    int nr_st, nc_st;             // stored region (the previous sweep's superblock)
+    int nr, nc;                   // this sweep's superblock
+    int arho, agam;               // position of pivot rk-1
+    double apiv;                  // its value in sweep precision
+};
+
 struct ProbState {
     int r[2][TT_MAX_D + 1];       // committed ranks, double-buffered by sweep parity
-    int ra[TT_MAX_D];             // pivots already applied to the stored region
-    int nr_st[TT_MAX_D], nc_st[TT_MAX_D];
-    unsigned int kdone;
-    int any, stop, capped, err, sweeps;
+    KSweep ks[TT_MAX_D];
+    int stop, capped, err, sweeps;
     unsigned long long pivoted;
     unsigned long long alg_bytes;   // algorithmic residual traffic of the tile launches
     unsigned long long new_entries; // entries evaluated by the tile launches
@@ -214,10 +229,6 @@ struct ProbDev {
 struct SweepArgs {
     int sweep;
     int nk;
-    int koff[TT_MAX_D + 1];       // workgroup offset of each unfolding
-    int ctub[TT_MAX_D];           // column tiles (upper bound) of each unfolding
-    int ntl[TT_MAX_D];            // tiles (upper bound) of each unfolding
-    int rub;                      // rank bound sizing the LDS layout
 };
 
 }  // namespace ttc

@@ -35,6 +35,8 @@ struct Problem {
     int fp32 = 0;
     int tileTR[TT_MAX_D] = {0}, tileTC[TT_MAX_D] = {0};
     int hist_cap = 0, max_sweeps = 0;
+    int lds_limit = 65536;         // LDS bytes one workgroup may allocate on this device
+    int sweep_grid_cap = 2048;     // workgroups of a search launch (8 per CU on 256 CUs)
     // device state
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -55,7 +57,7 @@ struct Problem {
     double rms = 0, tau = 0, time_to_eps = 0;
     double last_best[TT_MAX_D] = {0};
     int sweep_launches = 0;
-    double sweep_kernel_s = 0, commit_kernel_s = 0, sweep_alg_bytes = 0, new_entries = 0;
+    double sweep_kernel_s = 0, sweep_alg_bytes = 0, new_entries = 0, sweep_phase_s = 0;
     std::vector<hipEvent_t> prof_events;     // 3 per sweep when profiling
     int i0[TT_MAX_D] = {0};
 

@@ -1,15 +1,24 @@
 // tt_kernels.h -- gfx950 kernels of the greedy adaptive TT-cross hot path.
 //
+// Residual storage is an in-place elimination: once a row (column) of a
+// superblock holds a pivot it is never updated again, so it keeps the residual
+// it had just before that pivot was eliminated.  Those frozen rows and
+// columns are exactly the factors of the rank-1 updates of eq.
+// (submatrix_cross_iter): for pivot z at (rho_z, gamma_z) with value p_z,
+//   column factor  W(i, z) = E(i, gamma_z)        (frozen column)
+//   row factor     U(z, j) = E(rho_z, j) / p_z     (frozen row)
+// and every other entry holds the current residual.  Entries on pivot rows or
+// columns are never searched, so nothing else is needed.
+//
 // One search sweep over all unfoldings is two launches:
 //   k_sweep   one workgroup per tile of every superblock; a tile lies inside a
-//             single subtensor block and a single prefix/suffix, and either
-//             applies the newest pivot to stored residuals (rank-1 update,
-//             eq. submatrix_cross_iter) or evaluates new superblock entries and
-//             eliminates all pivots from them; both fuse the |residual| argmax
-//             of the tile (the block-local pivot of Alg. 3);
-//   k_commit  one workgroup per unfolding: best of the local pivots, stop test,
-//             append to the nested index sets, extract the new pivot's row and
-//             column factors.
+//             single subtensor block and a single prefix/suffix.  A stored tile
+//             applies the newest pivot (rank-1 update); a new tile evaluates
+//             the generating function on its entries and eliminates every
+//             pivot from them in insertion order.  Both fuse the |residual|
+//             argmax of the tile (the block-local pivot of Alg. 3).
+//   k_commit  one workgroup for all unfoldings: best of the local pivots
+//             (Sec. 3.2.1), stop test, append to the nested index sets.
 #pragma once
 
 #include "tt_device.h"
@@ -21,23 +30,25 @@ __device__ inline bool better(double a, uint64_t ka, double b, uint64_t kb)
     return a > b || (a == b && ka < kb);
 }
 
-// Workgroup-wide (max |value|, lowest key) reduction; result valid in all threads.
-__device__ inline void block_best(double &v, uint64_t &key)
+// Workgroup-wide (max |value|, lowest key) reduction carrying the signed
+// value; the result is valid in every thread.
+__device__ inline void block_best(double &v, uint64_t &key, double &sv)
 {
-    __shared__ double sv[NT / 64];
-    __shared__ uint64_t sk[NT / 64];
+    __shared__ double s_v[NT / 64], s_sv[NT / 64];
+    __shared__ uint64_t s_k[NT / 64];
     for (int off = 32; off > 0; off >>= 1) {
-        double ov = __shfl_xor(v, off, 64);
-        unsigned long long ok = __shfl_xor((unsigned long long)key, off, 64);
-        if (better(ov, ok, v, key)) { v = ov; key = ok; }
+        const double ov = __shfl_xor(v, off, 64);
+        const unsigned long long ok = __shfl_xor((unsigned long long)key, off, 64);
+        const double osv = __shfl_xor(sv, off, 64);
+        if (better(ov, ok, v, key)) { v = ov; key = ok; sv = osv; }
     }
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     __syncthreads();
-    if (l == 0) { sv[w] = v; sk[w] = key; }
+    if (l == 0) { s_v[w] = v; s_k[w] = key; s_sv[w] = sv; }
     __syncthreads();
-    v = sv[0]; key = sk[0];
+    v = s_v[0]; key = s_k[0]; sv = s_sv[0];
     for (int i = 1; i < NT / 64; ++i)
-        if (better(sv[i], sk[i], v, key)) { v = sv[i]; key = sk[i]; }
+        if (better(s_v[i], s_k[i], v, key)) { v = s_v[i]; key = s_k[i]; sv = s_sv[i]; }
     __syncthreads();
 }
 
@@ -45,336 +56,493 @@ template <typename V> __device__ inline V vfma(V a, V b, V c);
 template <> __device__ inline double vfma<double>(double a, double b, double c) { return __fma_rn(a, b, c); }
 template <> __device__ inline float vfma<float>(float a, float b, float c) { return __fmaf_rn(a, b, c); }
 
-// ---------------------------------------------------------------------------
-// Search tile.
-// ---------------------------------------------------------------------------
-template <typename V>
-__device__ void sweep_tile(const ProbDev *__restrict__ P, const KDev &K, const ProbState *S, int u, int par,
-                           int R, int C, int rk, double &bv, uint64_t &bk, V *sm)
+// strictly upper triangular index (zp < z)
+__device__ inline int tri(int zp, int z) { return z * (z - 1) / 2 + zp; }
+
+// LDS bytes of a new-entry tile: factors of the tile rows and columns and the
+// two pivot-block triangles.
+__host__ __device__ inline size_t sweep_lds_bytes(int rk, int TR, int TC, size_t w)
 {
-    const int d = P->d, k = u + 1;
-    const int tid = threadIdx.x;
-    const int p = R / K.RTp, t = R - p * K.RTp;
-    const int q = C / K.CTq, tc = C - q * K.CTq;
-    const int ik0 = K.rt_start[t], nrows = K.rt_len[t];
-    const int ik10 = K.ct_start[tc], ncols = K.ct_len[tc];
-    const int row0 = p * K.nk + ik0, col0 = q * K.nk1 + ik10;
-    const int nr_st = S->nr_st[u], nc_st = S->nc_st[u], ra = S->ra[u];
-    const bool rows_old = row0 < nr_st, cols_old = col0 < nc_st;
+    return ((size_t)rk * (TR + TC) + (size_t)rk * (rk > 0 ? rk - 1 : 0)) * w;
+}
+
+// ---------------------------------------------------------------------------
+// Search tiles.
+// ---------------------------------------------------------------------------
+struct TileGeom {
+    int u, R, C;                  // unfolding, row tile, column tile
+    int ik0, nrows, ik10, ncols;  // i_k / i_{k+1} ranges of the tile
+    int row0, col0, p, q;         // first row / column position, prefix / suffix
+};
+
+__device__ inline TileGeom tile_geom(const KDev &K, int u, int R, int C)
+{
+    TileGeom g;
+    g.u = u; g.R = R; g.C = C;
+    g.p = R / K.RTp;
+    const int t = R - g.p * K.RTp;
+    g.q = C / K.CTq;
+    const int tc = C - g.q * K.CTq;
+    g.ik0 = K.rt_start[t]; g.nrows = K.rt_len[t];
+    g.ik10 = K.ct_start[tc]; g.ncols = K.ct_len[tc];
+    g.row0 = g.p * K.nk + g.ik0;
+    g.col0 = g.q * K.nk1 + g.ik10;
+    return g;
+}
+
+__device__ inline void wave_best(double &v, uint64_t &key, double &sv)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(v, off, 64);
+        const unsigned long long ok = __shfl_xor((unsigned long long)key, off, 64);
+        const double osv = __shfl_xor(sv, off, 64);
+        if (better(ov, ok, v, key)) { v = ov; key = ok; sv = osv; }
+    }
+}
+
+// Stored residuals, one wavefront per tile: apply the newest pivot (if any)
+// and search.  All loads of a batch are issued before any is used.
+template <typename V>
+__device__ void stored_tile_wave(const KDev &K, const KSweep &ks, const TileGeom &g, double &bv, uint64_t &bk,
+                                 double &bs)
+{
+    const int lane = threadIdx.x & 63;
+    const int TC = K.TC, rpw = 64 / TC;
+    const int tr = lane / TC, tcol = lane - tr * TC;
+    if (tcol >= g.ncols) return;
     V *E = (V *)K.E;
-    V *W = (V *)K.W;
-    V *U = (V *)K.U;
     const int64_t ld = K.colcap;
-    const int TCt = K.TC, rpp = NT / TCt;
-    const int tr = tid / TCt, tcol = tid - tr * TCt;
-    const bool colact = tcol < ncols;
-
-    if (rows_old && cols_old) {
-        // stored residuals: apply the newest pivot (if any) and search
-        const bool apply = ra < rk;
-        const int col = col0 + tcol;
-        V ucol = 0;
-        bool cm = true;
-        if (colact) {
-            if (apply) ucol = U[(int64_t)ra * K.colcap + col];
-            cm = K.cmask[col] != 0;
+    const int col = g.col0 + tcol;
+    const uint8_t cp = K.cpiv[col];
+    const bool apply = ks.apply != 0;
+    const int gz = apply ? ks.agam : col;
+    V u = 0;
+    if (apply) u = E[(int64_t)ks.arho * ld + col] / (V)ks.apiv;
+    if (cp) return;
+    constexpr int B = 8;
+    for (int i0 = tr; i0 < g.nrows; i0 += B * rpw) {
+        V xv[B], wv[B];
+        uint8_t rp[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int ii = i0 + b * rpw;
+            const int row = g.row0 + (ii < g.nrows ? ii : 0);
+            const V *e = E + (int64_t)row * ld;
+            rp[b] = (ii < g.nrows) ? K.rpiv[row] : (uint8_t)1;
+            xv[b] = e[col];
+            wv[b] = e[gz];
         }
-        const V *wz = W + (int64_t)ra * K.rowcap;
-        for (int ii = tr; ii < nrows; ii += rpp) {
-            if (!colact) break;
-            const int row = row0 + ii;
-            V *e = E + (int64_t)row * ld + col;
-            V x = *e;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            if (rp[b]) continue;
+            const int row = g.row0 + i0 + b * rpw;
+            V x = xv[b];
             if (apply) {
-                x = vfma<V>(-wz[row], ucol, x);
-                *e = x;
+                x = vfma<V>(-wv[b], u, x);
+                E[(int64_t)row * ld + col] = x;
             }
-            if (!cm && !K.rmask[row]) {
-                double ax = (double)fabs(x);
-                uint64_t key = ((uint64_t)row << 32) | (uint32_t)col;
-                if (better(ax, key, bv, bk)) { bv = ax; bk = key; }
-            }
-        }
-        return;
-    }
-
-    // new entries: X minus the interpolant, pivots eliminated in insertion order
-    __shared__ int pre[TT_MAX_D], suf[TT_MAX_D];
-    const int npre = k - 1, nsuf = d - k - 1;
-    if (tid < npre) pre[tid] = P->kd[u - 1].Ifull[p * npre + tid];
-    if (tid < nsuf) suf[tid] = P->kd[u + 1].Jfull[q * nsuf + tid];
-    const int TRm = K.TR, TCm = K.TC;
-    V *Wt = sm;                       // Wt[z*TRm + ii]: W of the tile rows
-    V *Ut = sm + (int64_t)rk * TRm;   // Ut[z*TCm + jj]: U of the tile columns
-    __syncthreads();
-
-    // factors of the tile rows
-    if (rows_old) {
-        for (int e = tid; e < rk * nrows; e += NT) {
-            const int z = e / nrows, ii = e - z * nrows;
-            Wt[z * TRm + ii] = W[(int64_t)z * K.rowcap + row0 + ii];
-        }
-    } else {
-        const int nj = d - k;
-        for (int e = tid; e < rk * nrows; e += NT) {
-            const int z = e / nrows, ii = e - z * nrows;
-            int idx[TT_MAX_D];
-            for (int j = 0; j < npre; ++j) idx[j] = pre[j];
-            idx[k - 1] = ik0 + ii;
-            for (int j = 0; j < nj; ++j) idx[k + j] = K.Jfull[z * nj + j];
-            Wt[z * TRm + ii] = fn_value<V>(P->F, idx);       // X(row, gamma_z)
-        }
-        __syncthreads();
-        for (int zp = 0; zp + 1 < rk; ++zp) {
-            for (int e = tid; e < rk * nrows; e += NT) {
-                const int z = e / nrows, ii = e - z * nrows;
-                if (z > zp) {
-                    const V g = U[(int64_t)zp * K.colcap + K.gam[z]];
-                    Wt[z * TRm + ii] = vfma<V>(-Wt[zp * TRm + ii], g, Wt[z * TRm + ii]);
-                }
-            }
-            __syncthreads();
-        }
-    }
-    // factors of the tile columns
-    if (cols_old) {
-        for (int e = tid; e < rk * ncols; e += NT) {
-            const int z = e / ncols, jj = e - z * ncols;
-            Ut[z * TCm + jj] = U[(int64_t)z * K.colcap + col0 + jj];
-        }
-    } else {
-        for (int e = tid; e < rk * ncols; e += NT) {
-            const int z = e / ncols, jj = e - z * ncols;
-            int idx[TT_MAX_D];
-            for (int j = 0; j < k; ++j) idx[j] = K.Ifull[z * k + j];
-            idx[k] = ik10 + jj;
-            for (int j = 0; j < nsuf; ++j) idx[k + 1 + j] = suf[j];
-            Ut[z * TCm + jj] = fn_value<V>(P->F, idx);       // X(rho_z, col)
-        }
-        __syncthreads();
-        for (int zp = 0; zp < rk; ++zp) {
-            const V pz = (V)K.piv[zp];
-            for (int e = tid; e < rk * ncols; e += NT) {
-                const int z = e / ncols, jj = e - z * ncols;
-                if (z > zp) {
-                    const V uu = Ut[zp * TCm + jj] / pz;
-                    const V g = W[(int64_t)zp * K.rowcap + K.rho[z]];
-                    Ut[z * TCm + jj] = vfma<V>(-g, uu, Ut[z * TCm + jj]);
-                }
-            }
-            __syncthreads();
-            for (int jj = tid; jj < ncols; jj += NT) Ut[zp * TCm + jj] = Ut[zp * TCm + jj] / pz;
-            __syncthreads();
-        }
-    }
-    __syncthreads();
-    // publish the factors of new rows / columns (one writer per row / column)
-    if (!rows_old && C == 0) {
-        for (int e = tid; e < rk * nrows; e += NT) {
-            const int z = e / nrows, ii = e - z * nrows;
-            W[(int64_t)z * K.rowcap + row0 + ii] = Wt[z * TRm + ii];
-        }
-    }
-    if (!cols_old && R == 0) {
-        for (int e = tid; e < rk * ncols; e += NT) {
-            const int z = e / ncols, jj = e - z * ncols;
-            U[(int64_t)z * K.colcap + col0 + jj] = Ut[z * TCm + jj];
-        }
-    }
-    if (!colact) return;
-    const int col = col0 + tcol;
-    const bool cm = K.cmask[col] != 0;
-    int idx[TT_MAX_D];
-    for (int j = 0; j < npre; ++j) idx[j] = pre[j];
-    idx[k] = ik10 + tcol;
-    for (int j = 0; j < nsuf; ++j) idx[k + 1 + j] = suf[j];
-    for (int ii = tr; ii < nrows; ii += rpp) {
-        const int row = row0 + ii;
-        idx[k - 1] = ik0 + ii;
-        V x = fn_value<V>(P->F, idx);
-        for (int z = 0; z < rk; ++z) x = vfma<V>(-Wt[z * TRm + ii], Ut[z * TCm + tcol], x);
-        E[(int64_t)row * ld + col] = x;
-        if (!cm && !K.rmask[row]) {
-            double ax = (double)fabs(x);
-            uint64_t key = ((uint64_t)row << 32) | (uint32_t)col;
-            if (better(ax, key, bv, bk)) { bv = ax; bk = key; }
+            const double ax = (double)fabs(x);
+            const uint64_t key = ((uint64_t)row << 32) | (uint32_t)col;
+            if (better(ax, key, bv, bk)) { bv = ax; bk = key; bs = (double)x; }
         }
     }
 }
 
+// New entries (rows of the newest prefix and/or columns of the newest suffix):
+// the generating function minus the interpolant, every pivot eliminated in
+// insertion order.  One workgroup per tile.  Factors of stored rows / columns
+// come from the frozen pivot columns / rows; those of new rows / columns are
+// recomputed here, one thread per row (column), in LDS:
+//   row i:    e_z = X(i, gamma_z); for z' < z: e_z -= e_z' * U(z', gamma_z)   -> W(i, z)
+//   column j: e_z = X(rho_z, j);   for z' < z: e_z -= W(rho_z, z') * e_z'/p_z' -> p_z U(z, j)
+// and the frozen pivot columns / rows of the tile receive those values.
+template <typename V>
+__device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSweep &ks, const TileGeom &g,
+                         double &bv, uint64_t &bk, double &bs, V *sm)
+{
+    const int d = P->d, u = g.u, k = u + 1, tid = threadIdx.x, rk = ks.rk;
+    const bool rows_old = g.row0 < ks.nr_st, cols_old = g.col0 < ks.nc_st;
+    V *E = (V *)K.E;
+    const int64_t ld = K.colcap;
+    __shared__ int pre[TT_MAX_D], suf[TT_MAX_D];
+    __shared__ int s_rho[TT_MAX_RANK], s_gam[TT_MAX_RANK];
+    __shared__ V s_piv[TT_MAX_RANK];
+    const int npre = k - 1, nsuf = d - k - 1, nj = d - k;
+    const int TRm = K.TR, TCm = K.TC, ntri = rk * (rk - 1) / 2;
+    V *Wt = sm;                                // Wt[z*TRm+ii] = W(row, z)
+    V *Ut = Wt + (int64_t)rk * TRm;            // Ut[z*TCm+jj] = U(z, col)
+    V *Gr = Ut + (int64_t)rk * TCm;            // U(z', gamma_z), z' < z
+    V *Gc = Gr + ntri;                         // W(rho_z, z'), z' < z
+    if (tid < npre) pre[tid] = P->kd[u - 1].Ifull[g.p * npre + tid];
+    if (tid < nsuf) suf[tid] = P->kd[u + 1].Jfull[g.q * nsuf + tid];
+    for (int z = tid; z < rk; z += NT) {
+        s_rho[z] = K.rho[z];
+        s_gam[z] = K.gam[z];
+        s_piv[z] = (V)K.piv[z];
+    }
+    __syncthreads();
+    // raw factors: frozen entries, or the generating function at the skeleton
+    if (rows_old) {
+        for (int e = tid; e < rk * g.nrows; e += NT) {
+            const int z = e / g.nrows, ii = e - z * g.nrows;
+            Wt[z * TRm + ii] = E[(int64_t)(g.row0 + ii) * ld + s_gam[z]];
+        }
+    } else {
+        for (int e = tid; e < rk * rk; e += NT) {
+            const int zp = e / rk, z = e - zp * rk;
+            if (zp < z) Gr[tri(zp, z)] = E[(int64_t)s_rho[zp] * ld + s_gam[z]] / s_piv[zp];
+        }
+        for (int e = tid; e < rk * g.nrows; e += NT) {
+            const int z = e / g.nrows, ii = e - z * g.nrows;
+            const int ikv = g.ik0 + ii;
+            const int *Jz = K.Jfull + z * nj;
+            Wt[z * TRm + ii] = fn_value_ix<V>(P->F, [&](int j) {
+                return j < npre ? pre[j] : (j == k - 1 ? ikv : Jz[j - k]);
+            });
+        }
+    }
+    if (cols_old) {
+        for (int e = tid; e < rk * g.ncols; e += NT) {
+            const int z = e / g.ncols, jj = e - z * g.ncols;
+            Ut[z * TCm + jj] = E[(int64_t)s_rho[z] * ld + g.col0 + jj] / s_piv[z];
+        }
+    } else {
+        for (int e = tid; e < rk * rk; e += NT) {
+            const int zp = e / rk, z = e - zp * rk;
+            if (zp < z) Gc[tri(zp, z)] = E[(int64_t)s_rho[z] * ld + s_gam[zp]];
+        }
+        for (int e = tid; e < rk * g.ncols; e += NT) {
+            const int z = e / g.ncols, jj = e - z * g.ncols;
+            const int ik1v = g.ik10 + jj;
+            const int *Iz = K.Ifull + z * k;
+            Ut[z * TCm + jj] = fn_value_ix<V>(P->F, [&](int j) {
+                return j < k ? Iz[j] : (j == k ? ik1v : suf[j - k - 1]);
+            });
+        }
+    }
+    __syncthreads();
+    // chains: threads [0, NT/2) take the rows, threads [NT/2, NT) the columns
+    if (!rows_old && tid < NT / 2)
+    for (int ii = tid; ii < g.nrows; ii += NT / 2) {
+        for (int zp = 0; zp + 1 < rk; ++zp) {
+            const V w = Wt[zp * TRm + ii];
+            for (int z = zp + 1; z < rk; ++z) Wt[z * TRm + ii] = vfma<V>(-w, Gr[tri(zp, z)], Wt[z * TRm + ii]);
+        }
+        if (cols_old)
+            for (int z = 0; z < rk; ++z) {
+                const int gz = s_gam[z];
+                if (gz >= g.col0 && gz < g.col0 + g.ncols) E[(int64_t)(g.row0 + ii) * ld + gz] = Wt[z * TRm + ii];
+            }
+    }
+    if (!cols_old && tid >= NT / 2)
+    for (int jj = tid - NT / 2; jj < g.ncols; jj += NT / 2) {
+        for (int zp = 0; zp + 1 < rk; ++zp) {
+            const V uu = Ut[zp * TCm + jj] / s_piv[zp];
+            for (int z = zp + 1; z < rk; ++z) Ut[z * TCm + jj] = vfma<V>(-Gc[tri(zp, z)], uu, Ut[z * TCm + jj]);
+        }
+        for (int z = 0; z < rk; ++z) {
+            const int rz = s_rho[z];
+            if (rows_old && rz >= g.row0 && rz < g.row0 + g.nrows) E[(int64_t)rz * ld + g.col0 + jj] = Ut[z * TCm + jj];
+            Ut[z * TCm + jj] = Ut[z * TCm + jj] / s_piv[z];
+        }
+    }
+    __syncthreads();
+    const int TCt = K.TC, rpp = NT / TCt;
+    const int tr = tid / TCt, tcol = tid - tr * TCt;
+    if (tcol < g.ncols) {
+        const int col = g.col0 + tcol;
+        if (!K.cpiv[col]) {
+            const int ik1v = g.ik10 + tcol;
+            const bool hilbert = P->F.id == TT_FN_HILBERT;
+            long long hsum = ik1v + 1;                 // integer index sum, exact in any order
+            for (int j = 0; j < npre; ++j) hsum += pre[j] + 1;
+            for (int j = 0; j < nsuf; ++j) hsum += suf[j] + 1;
+            for (int ii = tr; ii < g.nrows; ii += rpp) {
+                const int row = g.row0 + ii;
+                if (K.rpiv[row]) continue;
+                const int ikv = g.ik0 + ii;
+                V x;
+                if (hilbert) {
+                    x = (V)1 / ((V)(hsum + ikv + 1) + (V)P->F.shift);
+                } else {
+                    x = fn_value_ix<V>(P->F, [&](int j) {
+                        return j < npre ? pre[j] : (j == k - 1 ? ikv : (j == k ? ik1v : suf[j - k - 1]));
+                    });
+                }
+                for (int z = 0; z < rk; ++z) x = vfma<V>(-Wt[z * TRm + ii], Ut[z * TCm + tcol], x);
+                E[(int64_t)row * ld + col] = x;
+                const double ax = (double)fabs(x);
+                const uint64_t key = ((uint64_t)row << 32) | (uint32_t)col;
+                if (better(ax, key, bv, bk)) { bv = ax; bk = key; bs = (double)x; }
+            }
+        }
+    }
+    block_best(bv, bk, bs);
+}
+
+// Tiles per unfolding this sweep, split into new-entry tiles and stored tiles.
+struct SweepShape {
+    int RT[TT_MAX_D], CT[TT_MAX_D], RTs[TT_MAX_D], CTs[TT_MAX_D];
+    int noff[TT_MAX_D + 1], soff[TT_MAX_D + 1];
+};
+
+__device__ inline void sweep_shape(const ProbDev *P, const KSweep *ks, int nk, SweepShape &sh)
+{
+    int nn = 0, ns = 0;
+    for (int u = 0; u < nk; ++u) {
+        const KDev &K = P->kd[u];
+        sh.RT[u] = (ks[u].nr / K.nk) * K.RTp;
+        sh.CT[u] = (ks[u].nc / K.nk1) * K.CTq;
+        sh.RTs[u] = (ks[u].nr_st / K.nk) * K.RTp;
+        sh.CTs[u] = (ks[u].nc_st / K.nk1) * K.CTq;
+        sh.noff[u] = nn;
+        sh.soff[u] = ns;
+        nn += sh.RT[u] * sh.CT[u] - sh.RTs[u] * sh.CTs[u];
+        ns += sh.RTs[u] * sh.CTs[u];
+    }
+    sh.noff[nk] = nn;
+    sh.soff[nk] = ns;
+}
+
+// Fixed grid striding over work units: first the new-entry tiles (one per
+// workgroup), then the stored tiles four at a time (one per wavefront).
 template <typename V>
 __global__ void __launch_bounds__(NT) k_sweep(const ProbDev *__restrict__ P, SweepArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const ProbState *S = P->S;
     if (S->stop) return;
-    const int bid = blockIdx.x;
-    int u = 0;
-    while (u + 1 < a.nk && bid >= a.koff[u + 1]) ++u;
-    const KDev &K = P->kd[u];
-    const int tl = bid - a.koff[u];
-    const int R = tl / a.ctub[u], C = tl - R * a.ctub[u];
-    const int par = a.sweep & 1, k = u + 1;
-    const int rkm1 = S->r[par][k - 1], rk = S->r[par][k], rkp1 = S->r[par][k + 1];
-    double bv = -1.0;
-    uint64_t bk = ~0ULL;
-    if (R < rkm1 * K.RTp && C < rkp1 * K.CTq)
-        sweep_tile<V>(P, K, S, u, par, R, C, rk, bv, bk, (V *)smem_raw);
-    block_best(bv, bk);
-    if (threadIdx.x == 0) {
-        K.cand[tl].v = bv;
-        K.cand[tl].key = bk;
+    const int nk = a.nk, tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+    __shared__ KSweep ks[TT_MAX_D];
+    __shared__ SweepShape sh;
+    if (tid < nk) ks[tid] = S->ks[tid];
+    __syncthreads();
+    if (tid == 0) sweep_shape(P, ks, nk, sh);
+    __syncthreads();
+    const int nnew = sh.noff[nk], nst = sh.soff[nk];
+    const int units = nnew + (nst + NT / 64 - 1) / (NT / 64);
+    for (int t = blockIdx.x; t < units; t += gridDim.x) {
+        double bv = -1.0, bs = 0.0;
+        uint64_t bk = ~0ULL;
+        if (t < nnew) {
+            int u = 0;
+            while (u + 1 < nk && t >= sh.noff[u + 1]) ++u;
+            const int idx = t - sh.noff[u], RT = sh.RT[u], CT = sh.CT[u], RTs = sh.RTs[u], CTs = sh.CTs[u];
+            int R, C;
+            if (idx < (RT - RTs) * CT) {
+                R = RTs + idx / CT;
+                C = idx % CT;
+            } else {
+                const int i2 = idx - (RT - RTs) * CT;
+                R = i2 / (CT - CTs);
+                C = CTs + i2 % (CT - CTs);
+            }
+            const KDev &K = P->kd[u];
+            const TileGeom g = tile_geom(K, u, R, C);
+            new_tile<V>(P, K, ks[u], g, bv, bk, bs, (V *)smem_raw);
+            if (tid == 0) {
+                Cand &c = K.cand[R * CT + C];
+                c.v = bv; c.key = bk; c.sv = bs;
+            }
+            __syncthreads();
+        } else {
+            const int st = (t - nnew) * (NT / 64) + wid;
+            if (st < nst) {
+                int u = 0;
+                while (u + 1 < nk && st >= sh.soff[u + 1]) ++u;
+                const int idx = st - sh.soff[u], CTs = sh.CTs[u];
+                const int R = idx / CTs, C = idx - R * CTs;
+                const KDev &K = P->kd[u];
+                const TileGeom g = tile_geom(K, u, R, C);
+                stored_tile_wave<V>(K, ks[u], g, bv, bk, bs);
+                wave_best(bv, bk, bs);
+                if (lane == 0) {
+                    Cand &c = K.cand[R * sh.CT[u] + C];
+                    c.v = bv; c.key = bk; c.sv = bs;
+                }
+            }
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
-// FP64 value of the residual at (row, col) of superblock k, from FP64 entries
-// and the FP64 pivot-block factors (used to check FP32 candidates).  Writes
-// the FP64 row factors w[z] = R(row, gamma_z) before pivot z and column factors
-// v[z] = R(rho_z, col) before pivot z divided by p64_z, into LDS.
+// FP64 value of the residual at (row, col) of superblock k from FP64 entries
+// and the FP64 factors of the pivot block (checks an FP32 candidate).  One
+// wavefront; lane z ends with the FP64 row factor w = R(row, gamma_z) before
+// pivot z and the column factor v = R(rho_z, col) before pivot z, over p64_z.
 // ---------------------------------------------------------------------------
-__device__ inline double fp64_check(const ProbDev *P, const KDev &K, int u, int rk, int row, int col,
-                                    double *w, double *v)
+__device__ inline double fp64_check_wave(const ProbDev *P, const KDev &K, int u, int rk, int row, int col,
+                                         double &w, double &v)
 {
-    const int d = P->d, k = u + 1, tid = threadIdx.x;
+    const int d = P->d, k = u + 1, lane = threadIdx.x & 63;
     const int nk = K.nk, nk1 = K.nk1;
-    const int p = row / nk, q = col / nk1;
-    const int npre = k - 1, nsuf = d - k - 1;
+    const int p = row / nk, q = col / nk1, ik = row - p * nk, ik1 = col - q * nk1;
+    const int npre = k - 1, nsuf = d - k - 1, nj = d - k;
     const int *preI = (k >= 2) ? P->kd[u - 1].Ifull + p * npre : nullptr;
     const int *sufJ = (nsuf > 0) ? P->kd[u + 1].Jfull + q * nsuf : nullptr;
-    __shared__ double xrc;
-    // raw entries X(row, gamma_z), X(rho_z, col), X(row, col)
-    for (int z = tid; z < rk; z += NT) {
-        int idx[TT_MAX_D];
-        for (int j = 0; j < npre; ++j) idx[j] = preI[j];
-        idx[k - 1] = row % nk;
-        for (int j = 0; j < d - k; ++j) idx[k + j] = K.Jfull[z * (d - k) + j];
-        w[z] = fn_value<double>(P->F, idx);
-        for (int j = 0; j < k; ++j) idx[j] = K.Ifull[z * k + j];
-        idx[k] = col % nk1;
-        for (int j = 0; j < nsuf; ++j) idx[k + 1 + j] = sufJ[j];
-        v[z] = fn_value<double>(P->F, idx);
+    w = 0.0;
+    v = 0.0;
+    if (lane < rk) {
+        const int *Jz = K.Jfull + lane * nj;
+        const int *Iz = K.Ifull + lane * k;
+        w = fn_value_ix<double>(P->F, [&](int j) { return j < npre ? preI[j] : (j == k - 1 ? ik : Jz[j - k]); });
+        v = fn_value_ix<double>(P->F, [&](int j) { return j < k ? Iz[j] : (j == k ? ik1 : sufJ[j - k - 1]); });
     }
-    if (tid == 0) {
-        int idx[TT_MAX_D];
-        for (int j = 0; j < npre; ++j) idx[j] = preI[j];
-        idx[k - 1] = row % nk;
-        idx[k] = col % nk1;
-        for (int j = 0; j < nsuf; ++j) idx[k + 1 + j] = sufJ[j];
-        xrc = fn_value<double>(P->F, idx);
-    }
-    __syncthreads();
+    const double xrc = fn_value_ix<double>(P->F, [&](int j) {
+        return j < npre ? preI[j] : (j == k - 1 ? ik : (j == k ? ik1 : sufJ[j - k - 1]));
+    });
     const int rc = P->rcap;
     for (int zp = 0; zp + 1 < rk; ++zp) {
-        for (int z = zp + 1 + tid; z < rk; z += NT) {
-            w[z] = __fma_rn(-w[zp], K.Up64[zp * rc + z], w[z]);
-            const double uu = v[zp] / K.piv64[zp];
-            v[z] = __fma_rn(-K.Wp64[z * rc + zp], uu, v[z]);
+        const double wzp = __shfl(w, zp, 64);
+        const double uu = __shfl(v, zp, 64) / K.piv64[zp];
+        if (lane > zp && lane < rk) {
+            w = __fma_rn(-wzp, K.Up64[zp * rc + lane], w);
+            v = __fma_rn(-K.Wp64[lane * rc + zp], uu, v);
         }
-        __syncthreads();
     }
-    for (int z = tid; z < rk; z += NT) v[z] = v[z] / K.piv64[z];
-    __syncthreads();
+    if (lane < rk) v = v / K.piv64[lane];
     double x = xrc;
-    for (int z = 0; z < rk; ++z) x = __fma_rn(-w[z], v[z], x);
-    __syncthreads();
+    for (int z = 0; z < rk; ++z) x = __fma_rn(-__shfl(w, z, 64), __shfl(v, z, 64), x);
     return x;
 }
 
+// One workgroup for every unfolding: wavefronts reduce the tile candidates
+// (best of the local pivots, Sec. 3.2.1), wavefront u decides and commits
+// unfolding u, and thread 0 publishes the outcome.
+constexpr int NTC = 512;
+
 template <typename V>
-__global__ void __launch_bounds__(NT) k_commit(const ProbDev *__restrict__ P, SweepArgs a)
+__global__ void __launch_bounds__(NTC) k_commit(const ProbDev *__restrict__ P, SweepArgs a)
 {
     ProbState *S = P->S;
     if (S->stop) return;
-    const int u = blockIdx.x, k = u + 1, d = P->d, tid = threadIdx.x;
-    const int par = a.sweep & 1;
-    const KDev &K = P->kd[u];
-    const int rkm1 = S->r[par][k - 1], rk = S->r[par][k], rkp1 = S->r[par][k + 1];
-    const int nr = rkm1 * K.nk, nc = K.nk1 * rkp1;
-    double bv = -1.0;
-    uint64_t bk = ~0ULL;
-    for (int i = tid; i < a.ntl[u]; i += NT) {
-        const Cand c = K.cand[i];
-        if (better(c.v, c.key, bv, bk)) { bv = c.v; bk = c.key; }
-    }
-    block_best(bv, bk);
-    const bool found = bv >= 0.0;
-    const int row = (int)(bk >> 32), col = (int)(bk & 0xffffffffULL);
-    const V *E = (const V *)K.E;
-    __shared__ double w64[TT_MAX_RANK], v64[TT_MAX_RANK];
-    double e = found ? bv : 0.0;
-    double p64 = 0.0;
-    if (P->fp32 && found) {
-        // FP64 check of the FP32 candidate (stop test and pivot block in FP64)
-        p64 = fp64_check(P, K, u, rk, row, col, w64, v64);
-        e = fabs(p64);
-    }
-    const bool over = found && e > S->tau;
-    const bool propose = over && rk < P->r_max && rk < K.rk_cap;
-    if (tid == 0) {
-        if (a.sweep < P->hist_cap) K.hist[a.sweep] = e;
-        S->last_best[u] = e;
-        if (over && !propose) S->capped = 1;
-    }
-    if (propose) {
-        const int z = rk;
-        const V pv = E[(int64_t)row * K.colcap + col];
-        const int p = row / K.nk, ik = row - p * K.nk;
-        const int q = col / K.nk1, ik1 = col - q * K.nk1;
-        if (tid == 0) {
-            K.rho[z] = row;
-            K.gam[z] = col;
-            K.piv[z] = (double)pv;
-            K.piv64[z] = P->fp32 ? p64 : (double)pv;
-            K.rmask[row] = 1;
-            K.cmask[col] = 1;
-            K.Ifull[z * k + k - 1] = ik;
-            K.Jfull[z * (d - k)] = ik1;
-            if (pv == (V)0) S->err = TT_ESINGULAR;
+    const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+    constexpr int NW = NTC / 64;
+    const int nk = a.nk, d = P->d, par = a.sweep & 1;
+    __shared__ KSweep ks[TT_MAX_D];
+    __shared__ double s_wv[NW * TT_MAX_D], s_wsv[NW * TT_MAX_D];
+    __shared__ uint64_t s_wk[NW * TT_MAX_D];
+    __shared__ int s_prop[TT_MAX_D], s_rold[TT_MAX_D + 1], s_rnew[TT_MAX_D + 1];
+    __shared__ unsigned long long s_bytes[TT_MAX_D], s_new[TT_MAX_D], s_piv[TT_MAX_D];
+    if (tid < nk) ks[tid] = S->ks[tid];
+    if (tid <= d) s_rold[tid] = S->r[par][tid];
+    __syncthreads();
+    // best candidate per unfolding: wave w scans unfoldings w, w+NW, ...
+    for (int u = wid; u < nk; u += NW) {
+        const KDev &K = P->kd[u];
+        const int ntl = ((ks[u].nr / K.nk) * K.RTp) * ((ks[u].nc / K.nk1) * K.CTq);
+        double bv = -1.0, bs = 0.0;
+        uint64_t bk = ~0ULL;
+        for (int i = lane; i < ntl; i += 64) {
+            const Cand c = K.cand[i];
+            if (better(c.v, c.key, bv, bk)) { bv = c.v; bk = c.key; bs = c.sv; }
         }
-        if (tid < k - 1) K.Ifull[z * k + tid] = P->kd[u - 1].Ifull[p * (k - 1) + tid];
-        if (tid < d - k - 1) K.Jfull[z * (d - k) + 1 + tid] = P->kd[u + 1].Jfull[q * (d - k - 1) + tid];
-        if (P->fp32) {
-            for (int zz = tid; zz < z; zz += NT) {
-                K.Wp64[z * P->rcap + zz] = w64[zz];
-                K.Up64[zz * P->rcap + z] = v64[zz];
+        wave_best(bv, bk, bs);
+        if (lane == 0) { s_wv[u] = bv; s_wk[u] = bk; s_wsv[u] = bs; }
+    }
+    __syncthreads();
+    // decide and commit
+    for (int u = wid; u < nk; u += NW) {
+        const int k = u + 1;
+        const KDev &K = P->kd[u];
+        const int rk = ks[u].rk, nr = ks[u].nr, nc = ks[u].nc;
+        const double bv = s_wv[u], bs = s_wsv[u];
+        const uint64_t bk = s_wk[u];
+        const bool found = bv >= 0.0;
+        const int row = (int)(bk >> 32), col = (int)(bk & 0xffffffffULL);
+        double e = found ? bv : 0.0, p64 = 0.0, w64 = 0.0, v64 = 0.0;
+        if (P->fp32 && found) {
+            // FP64 check of the FP32 candidate: stop test and pivot block in FP64
+            p64 = fp64_check_wave(P, K, u, rk, row, col, w64, v64);
+            e = fabs(p64);
+        }
+        const bool over = found && e > S->tau;
+        const bool propose = over && rk < P->r_max && rk < K.rk_cap;
+        if (propose) {
+            const int z = rk;
+            const int p = row / K.nk, ik = row - p * K.nk;
+            const int q = col / K.nk1, ik1 = col - q * K.nk1;
+            if (lane == 0) {
+                K.rho[z] = row;
+                K.gam[z] = col;
+                K.piv[z] = bs;
+                K.piv64[z] = P->fp32 ? p64 : bs;
+                K.rpiv[row] = (uint8_t)(z + 1);
+                K.cpiv[col] = (uint8_t)(z + 1);
+                K.Ifull[z * k + k - 1] = ik;
+                K.Jfull[z * (d - k)] = ik1;
+            }
+            if (lane < k - 1) K.Ifull[z * k + lane] = P->kd[u - 1].Ifull[p * (k - 1) + lane];
+            if (lane < d - k - 1) K.Jfull[z * (d - k) + 1 + lane] = P->kd[u + 1].Jfull[q * (d - k - 1) + lane];
+            if (P->fp32 && lane < z) {
+                K.Wp64[z * P->rcap + lane] = w64;
+                K.Up64[lane * P->rcap + z] = v64;
             }
         }
-        V *Uz = (V *)K.U + (int64_t)z * K.colcap;
-        V *Wz = (V *)K.W + (int64_t)z * K.rowcap;
-        const V *Er = E + (int64_t)row * K.colcap;
-        for (int j = tid; j < nc; j += NT) Uz[j] = Er[j] / pv;
-        for (int i = tid; i < nr; i += NT) Wz[i] = E[(int64_t)i * K.colcap + col];
+        if (lane == 0) {
+            if (a.sweep < P->hist_cap) K.hist[a.sweep] = e;
+            S->last_best[u] = e;
+            if (over && !propose) S->capped = 1;
+            if (propose && bs == 0.0) S->err = TT_ESINGULAR;
+            // traffic accounting of this sweep's tiles
+            const unsigned long long nst = (unsigned long long)ks[u].nr_st, cst = (unsigned long long)ks[u].nc_st;
+            const unsigned long long all = (unsigned long long)nr * (unsigned long long)nc;
+            const unsigned long long live = (nst - rk) * (cst - rk);
+            s_bytes[u] = live * sizeof(V) * (ks[u].apply ? 2ull : 1ull) + (all - nst * cst) * sizeof(V);
+            s_new[u] = all - nst * cst;
+            s_piv[u] = all;
+            s_prop[u] = propose ? 1 : 0;
+            s_rnew[k] = rk + (propose ? 1 : 0);
+            if (propose) {
+                ks[u].arho = row;
+                ks[u].agam = col;
+                ks[u].apiv = bs;
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) { s_rnew[0] = 1; s_rnew[d] = 1; }
+    __syncthreads();
+    // the next sweep's shapes
+    if (tid < nk) {
+        const int u = tid, k = u + 1;
+        const KDev &K = P->kd[u];
+        KSweep n;
+        n.rk = s_rnew[k];
+        n.apply = s_prop[u];
+        n.nr_st = ks[u].nr;
+        n.nc_st = ks[u].nc;
+        n.nr = s_rnew[k - 1] * K.nk;
+        n.nc = K.nk1 * s_rnew[k + 1];
+        n.arho = ks[u].arho;
+        n.agam = ks[u].agam;
+        n.apiv = ks[u].apiv;
+        S->ks[u] = n;
+        S->r[par ^ 1][k] = s_rnew[k];
     }
     if (tid == 0) {
-        // traffic accounting of this sweep's tiles, before the stored region moves on
-        const unsigned long long stored = (unsigned long long)S->nr_st[u] * (unsigned long long)S->nc_st[u];
-        const unsigned long long all = (unsigned long long)nr * (unsigned long long)nc;
-        const unsigned long long w = sizeof(V);
-        atomicAdd(&S->alg_bytes, stored * w * (S->ra[u] < rk ? 2ull : 1ull) + (all - stored) * w);
-        atomicAdd(&S->new_entries, all - stored);
-        S->ra[u] = rk;
-        S->nr_st[u] = nr;
-        S->nc_st[u] = nc;
-        S->r[par ^ 1][k] = rk + (propose ? 1 : 0);
-        atomicAdd(&S->pivoted, (unsigned long long)nr * (unsigned long long)nc);
-        if (propose) atomicOr(&S->any, 1);
-        __threadfence();
-        const unsigned int t = atomicAdd(&S->kdone, 1u);
-        if (t == (unsigned)(a.nk - 1)) {
-            __threadfence();
-            const int any = atomicAdd(&S->any, 0);
-            const int stop = (!any || S->err) ? 1 : 0;
-            S->stop = stop;
-            S->any = 0;
-            S->kdone = 0;
-            S->sweeps = a.sweep + 1;
-            HostMirror *hm = P->hm;
-            for (int j = 0; j <= d; ++j) hm->r[j] = S->r[par ^ 1][j];
+        int any = 0;
+        for (int u = 0; u < nk; ++u) {
+            any |= s_prop[u];
+            S->alg_bytes += s_bytes[u];
+            S->new_entries += s_new[u];
+            S->pivoted += s_piv[u];
+        }
+        const int stop = (!any || S->err) ? 1 : 0;
+        S->stop = stop;
+        S->sweeps = a.sweep + 1;
+        HostMirror *hm = P->hm;
+        if (stop) {
+            // final sweep: ranks and status must be visible before the count
+            for (int j = 0; j <= d; ++j) hm->r[j] = s_rold[j];
             hm->err = S->err;
             hm->stop = stop;
             __threadfence_system();
             __hip_atomic_store(&hm->sweeps_done, a.sweep + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        } else {
+            for (int j = 0; j <= d; ++j)
+                __hip_atomic_store(&hm->r[j], s_rnew[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&hm->sweeps_done, a.sweep + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         }
     }
 }
@@ -382,16 +550,62 @@ __global__ void __launch_bounds__(NT) k_commit(const ProbDev *__restrict__ P, Sw
 // ---------------------------------------------------------------------------
 // Setup: samples, rms, first pivot, initial superblocks.
 // ---------------------------------------------------------------------------
+// Evaluates the sample entries and clears the pivot maps of every unfolding.
 __global__ void __launch_bounds__(NT) k_samples(const ProbDev *__restrict__ P, uint64_t seed, int ns,
                                                   double *vals)
 {
     const int s = blockIdx.x * NT + threadIdx.x;
-    if (s >= ns) return;
     const int d = P->d;
+    for (int u = 0; u < P->nk; ++u) {
+        const KDev &K = P->kd[u];
+        for (int i = s; i < K.rowcap; i += gridDim.x * NT) K.rpiv[i] = 0;
+        for (int j = s; j < K.colcap; j += gridDim.x * NT) K.cpiv[j] = 0;
+    }
+    if (s >= ns) return;
     int idx[TT_MAX_D];
     for (int j = 0; j < d; ++j)
         idx[j] = (int)(sm64_at(seed, (uint64_t)s * d + j) % (uint64_t)P->F.n[j]);
     vals[s] = fn_value<double>(P->F, idx);
+}
+
+// Pairwise sum of v[lo..lo+c) squared (c a power of two; entries past ns are
+// zero), combined bottom-up like a balanced binary tree.
+__device__ inline double chunk_pairwise_sumsq(const double *v, int lo, int c, int ns)
+{
+    double st[32];
+    int lv[32];
+    int top = 0;
+    // leaves arrive in groups of 8 (loaded together, summed as a fixed
+    // 8-leaf subtree) when the chunk allows it, else one at a time
+    const int g8 = (c >= 8) ? 8 : 1;
+    const int base_level = (c >= 8) ? 3 : 0;
+    for (int i = 0; i < c; i += g8) {
+        double x;
+        if (g8 == 8) {
+            double q[8];
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const int g = lo + i + b;
+                const double t = (g < ns) ? v[g] : 0.0;
+                q[b] = __dmul_rn(t, t);
+            }
+            x = __dadd_rn(__dadd_rn(__dadd_rn(q[0], q[1]), __dadd_rn(q[2], q[3])),
+                          __dadd_rn(__dadd_rn(q[4], q[5]), __dadd_rn(q[6], q[7])));
+        } else {
+            const int g = lo + i;
+            x = (g < ns) ? __dmul_rn(v[g], v[g]) : 0.0;
+        }
+        int level = base_level;
+        while (top > 0 && lv[top - 1] == level) {
+            x = __dadd_rn(st[top - 1], x);
+            --top;
+            ++level;
+        }
+        st[top] = x;
+        lv[top] = level;
+        ++top;
+    }
+    return st[0];
 }
 
 template <typename V>
@@ -400,26 +614,37 @@ __global__ void __launch_bounds__(NT) k_setup(const ProbDev *__restrict__ P, uin
 {
     ProbState *S = P->S;
     const int tid = threadIdx.x, d = P->d;
-    double bv = -1.0;
+    double bv = -1.0, bs = 0.0;
     uint64_t bk = ~0ULL;
     int bad = 0;
     for (int s = tid; s < ns; s += NT) {
         const double a = fabs(vals[s]);
         if (!(a <= 1.7976931348623157e308)) bad = 1;          // not finite
-        if (better(a, (uint64_t)s, bv, bk)) { bv = a; bk = (uint64_t)s; }
+        if (better(a, (uint64_t)s, bv, bk)) { bv = a; bk = (uint64_t)s; bs = vals[s]; }
     }
     __shared__ int sbad;
     if (tid == 0) sbad = 0;
     __syncthreads();
     if (bad) atomicOr(&sbad, 1);
-    block_best(bv, bk);
+    block_best(bv, bk, bs);
+    // sum of squares as a balanced binary tree over the zero-padded samples:
+    // each thread reduces an aligned power-of-two chunk, then the 256 chunk
+    // sums are combined pairwise (adjacent lanes, then adjacent waves)
+    int m = 1;
+    while (m < ns) m <<= 1;
+    const int c = (m >= NT) ? m / NT : 1;
+    double part = (tid * c < m) ? chunk_pairwise_sumsq(vals, tid * c, c, ns) : 0.0;
+    for (int off = 1; off < 64; off <<= 1) {
+        const double o = __shfl_down(part, off, 64);
+        if ((tid & (2 * off - 1)) == 0) part = __dadd_rn(part, o);
+    }
+    __shared__ double wsum[NT / 64];
+    if ((tid & 63) == 0) wsum[tid >> 6] = part;
     __shared__ int i0[TT_MAX_D];
     __shared__ double p0s;
+    __syncthreads();
     if (tid == 0) {
-        // sum of squares in sample order (the stop threshold must not depend
-        // on a reduction tree)
-        double ss = 0.0;
-        for (int s = 0; s < ns; ++s) ss = __dadd_rn(ss, __dmul_rn(vals[s], vals[s]));
+        const double ss = __dadd_rn(__dadd_rn(wsum[0], wsum[1]), __dadd_rn(wsum[2], wsum[3]));
         const double rms = sqrt(ss / (double)ns);
         S->rms = rms;
         S->tau = eps * rms;
@@ -429,7 +654,7 @@ __global__ void __launch_bounds__(NT) k_setup(const ProbDev *__restrict__ P, uin
         }
         for (int b = 0; b < 2; ++b)
             for (int j = 0; j <= d; ++j) S->r[b][j] = 1;
-        S->kdone = 0; S->any = 0; S->stop = 0; S->capped = 0; S->sweeps = 0; S->pivoted = 0;
+        S->stop = 0; S->capped = 0; S->sweeps = 0; S->pivoted = 0;
         S->alg_bytes = 0; S->new_entries = 0;
         S->err = sbad ? TT_EFN : 0;
         p0s = (double)fn_value<V>(P->F, i0);
@@ -452,11 +677,17 @@ __global__ void __launch_bounds__(NT) k_setup(const ProbDev *__restrict__ P, uin
             K.gam[0] = i0[k];
             K.piv[0] = p0s;
             K.piv64[0] = (double)fn_value<double>(P->F, i0);
-            K.rmask[i0[k - 1]] = 1;
-            K.cmask[i0[k]] = 1;
-            S->ra[u] = 0;
-            S->nr_st[u] = K.nk;
-            S->nc_st[u] = K.nk1;
+            K.rpiv[i0[k - 1]] = 1;
+            K.cpiv[i0[k]] = 1;
+            KSweep ks;
+            ks.rk = 1;
+            ks.apply = 1;                 // the first pivot is applied by the first sweep
+            ks.nr_st = ks.nr = K.nk;
+            ks.nc_st = ks.nc = K.nk1;
+            ks.arho = i0[k - 1];
+            ks.agam = i0[k];
+            ks.apiv = p0s;
+            S->ks[u] = ks;
         }
     }
 }
@@ -480,21 +711,6 @@ __global__ void __launch_bounds__(NT) k_init_eval(const ProbDev *__restrict__ P)
     }
 }
 
-// Row and column factors of the first pivot.
-template <typename V>
-__global__ void __launch_bounds__(NT) k_init_extract(const ProbDev *__restrict__ P)
-{
-    const ProbState *S = P->S;
-    if (S->stop) return;
-    const int u = blockIdx.x;
-    const KDev &K = P->kd[u];
-    const V *E = (const V *)K.E;
-    const int row = K.rho[0], col = K.gam[0];
-    const V pv = E[(int64_t)row * K.colcap + col];
-    for (int j = threadIdx.x; j < K.nk1; j += NT) ((V *)K.U)[j] = E[(int64_t)row * K.colcap + j] / pv;
-    for (int i = threadIdx.x; i < K.nk; i += NT) ((V *)K.W)[i] = E[(int64_t)i * K.colcap + col];
-}
-
 // ---------------------------------------------------------------------------
 // Cores by Alg. 4 (FP64).  A_k = X(I_{<=k-1} x [n_k], J_{>k}) is evaluated
 // into a scratch buffer; the pivot rows' recursion runs once per unfolding and
@@ -509,6 +725,8 @@ struct CoreArgs {
     int64_t doff[TT_MAX_D];     // offset of (delta, Trho) records per unfolding
     int rowblocks[TT_MAX_D + 1];// prefix sum of row blocks per unfolding (k_alg4_rows)
 };
+
+constexpr int A4W = 64;         // rows per workgroup of k_alg4_rows (one wavefront)
 
 __global__ void __launch_bounds__(NT) k_fibers(const ProbDev *__restrict__ P, CoreArgs a, double *A,
                                                  double *G)
@@ -543,6 +761,8 @@ __global__ void __launch_bounds__(NT) k_fibers(const ProbDev *__restrict__ P, Co
     }
 }
 
+// One workgroup per unfolding: T of the pivot rows (LDS) and the per-step
+// records delta_z, T(i_z, 0..z-1).
 __global__ void __launch_bounds__(NT) k_alg4_pivots(const ProbDev *__restrict__ P, CoreArgs a,
                                                       const double *A, double *rec)
 {
@@ -552,21 +772,26 @@ __global__ void __launch_bounds__(NT) k_alg4_pivots(const ProbDev *__restrict__ 
     const int rk = a.ranks[k];
     const double *Ak = A + a.aoff[u];
     double *Tp = (double *)smem_raw;            // rk x rk: T of the pivot rows
-    double *s = Tp + rk * rk;                   // rk
+    double *Ap = Tp + rk * rk;                  // rk x rk: Ap[t*rk+z] = A(rho_t, z)
+    double *s = Ap + rk * rk;                   // rk
     double *Tr = s + rk;                        // rk
     double *R = rec + a.doff[u];                // per z: delta_z then T(i_z, 0..z-1)
-    const double a11 = Ak[(int64_t)K.rho[0] * rk];
     for (int e = tid; e < rk * rk; e += NT) {
         const int t = e / rk, z = e - t * rk;
-        Tp[e] = (z == 0) ? Ak[(int64_t)K.rho[t] * rk] / a11 : 0.0;
+        Ap[e] = Ak[(int64_t)K.rho[t] * rk + z];
+    }
+    __syncthreads();
+    const double a11 = Ap[0];
+    for (int e = tid; e < rk * rk; e += NT) {
+        const int t = e / rk, z = e - t * rk;
+        Tp[e] = (z == 0) ? Ap[t * rk] / a11 : 0.0;
     }
     __syncthreads();
     for (int z = 1; z < rk; ++z) {
         if (tid < rk) {
-            const double *Arow = Ak + (int64_t)K.rho[tid] * rk;
             double dot = 0.0;
-            for (int zz = 0; zz < z; ++zz) dot = __fma_rn(Tp[tid * rk + zz], Ak[(int64_t)K.rho[zz] * rk + z], dot);
-            s[tid] = dot - Arow[z];
+            for (int zz = 0; zz < z; ++zz) dot = __fma_rn(Tp[tid * rk + zz], Ap[zz * rk + z], dot);
+            s[tid] = dot - Ap[tid * rk + z];
         }
         if (tid < z) Tr[tid] = Tp[z * rk + tid];
         __syncthreads();
@@ -582,39 +807,53 @@ __global__ void __launch_bounds__(NT) k_alg4_pivots(const ProbDev *__restrict__ 
     }
 }
 
-__global__ void __launch_bounds__(NT) k_alg4_rows(const ProbDev *__restrict__ P, CoreArgs a, const double *A,
-                                                    const double *rec, double *G)
+// One wavefront per 64 rows; T of the rows kept in LDS as T[z][lane].
+__global__ void __launch_bounds__(A4W) k_alg4_rows(const ProbDev *__restrict__ P, CoreArgs a, const double *A,
+                                                     const double *rec, double *G)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int bid = blockIdx.x;
     int u = 0;
     while (u + 1 < a.nk && bid >= a.rowblocks[u + 1]) ++u;
-    const int k = u + 1, tid = threadIdx.x;
+    const int k = u + 1, lane = threadIdx.x;
     const KDev &K = P->kd[u];
     const int rk = a.ranks[k], nr = a.ranks[k - 1] * K.nk;
     const double *Ak = A + a.aoff[u];
     const double *Rk = rec + a.doff[u];
-    double *Ap = (double *)smem_raw;            // Ap[zz*rk + z] = A(rho_zz, z)
-    for (int e = tid; e < rk * rk; e += NT) {
+    double *T = (double *)smem_raw;             // T[z*A4W + lane]
+    double *Ap = T + rk * A4W;                  // Ap[zz*rk + z] = A(rho_zz, z)
+    double *Rs = Ap + rk * rk;                  // the pivot recursion's records
+    double *Ar = Rs + rk * (rk + 1);            // Ar[z*A4W + lane] = A(row, z)
+    const int i0 = (bid - a.rowblocks[u]) * A4W;
+    const int i = i0 + lane;
+    const bool act = i < nr;
+    const int rows = min(A4W, nr - i0);
+    for (int e = lane; e < rk * rk; e += A4W) {
         const int zz = e / rk, z = e - zz * rk;
         Ap[e] = Ak[(int64_t)K.rho[zz] * rk + z];
     }
+    for (int e = lane; e < rk * (rk + 1); e += A4W) Rs[e] = Rk[e];
+    for (int e = lane; e < rows * rk; e += A4W) {
+        const int ii = e / rk, z = e - ii * rk;
+        Ar[z * A4W + ii] = Ak[(int64_t)(i0 + ii) * rk + z];
+    }
     __syncthreads();
-    const int i = (bid - a.rowblocks[u]) * NT + tid;
-    if (i >= nr) return;
-    double *T = G + a.goff[u] + (int64_t)i * rk;
-    const double *Ai = Ak + (int64_t)i * rk;
     const double a11 = Ap[0];
-    T[0] = Ai[0] / a11;
-    for (int z = 1; z < rk; ++z) T[z] = 0.0;
+    T[lane] = act ? Ar[lane] / a11 : 0.0;
     for (int z = 1; z < rk; ++z) {
         double dot = 0.0;
-        for (int zz = 0; zz < z; ++zz) dot = __fma_rn(T[zz], Ap[zz * rk + z], dot);
-        const double s = dot - Ai[z];
-        const double *Rz = Rk + (int64_t)z * (rk + 1);
+        for (int zz = 0; zz < z; ++zz) dot = __fma_rn(T[zz * A4W + lane], Ap[zz * rk + z], dot);
+        const double s = dot - (act ? Ar[z * A4W + lane] : 0.0);
+        const double *Rz = Rs + z * (rk + 1);
         const double c = Rz[0] * s;
-        for (int zz = 0; zz < z; ++zz) T[zz] = __fma_rn(c, Rz[1 + zz], T[zz]);
-        T[z] = -c;
+        for (int zz = 0; zz < z; ++zz) T[zz * A4W + lane] = __fma_rn(c, Rz[1 + zz], T[zz * A4W + lane]);
+        T[z * A4W + lane] = -c;
+    }
+    __syncthreads();
+    double *Gk = G + a.goff[u] + (int64_t)i0 * rk;
+    for (int e = lane; e < rows * rk; e += A4W) {
+        const int ii = e / rk, z = e - ii * rk;
+        Gk[e] = T[z * A4W + ii];
     }
 }
 
