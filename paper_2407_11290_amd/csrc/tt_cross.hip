@@ -198,6 +198,11 @@ int Problem::allocate()
         int dev = 0;
         HIPCHK(hipGetDevice(&dev));
         HIPCHK(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        // the search kernel's static LDS (shapes, commit scratch) comes off the top
+        hipFuncAttributes fa;
+        if (fp32) HIPCHK(hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&k_sweep<float>)));
+        else HIPCHK(hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&k_sweep<double>)));
+        lds_static = (int)fa.sharedSizeBytes;
     }
     const size_t w = fp32 ? 4 : 8;
     ProbDev &H = hP;
@@ -214,7 +219,7 @@ int Problem::allocate()
     for (int k = 1; k <= d - 1; ++k) hist_cap += rc[k];
     H.hist_cap = hist_cap;
     max_sweeps = hist_cap;
-    int64_t cores_cap = 0, a_cap = 0, rec_cap = 0;
+    int64_t cores_cap = 0;
     for (int u = 0; u < d - 1; ++u) {
         const int k = u + 1;
         KDev &K = H.kd[u];
@@ -236,7 +241,7 @@ int Problem::allocate()
         TC = std::min(pow2_at_least(TC), NT);
         if (opt.tile_rows <= 0 && opt.tile_cols <= 0) {
             // shrink the default tile until its LDS fits next to the rank cap
-            while (sweep_lds_bytes(rc[k], TR, TC, w) + 1024 > (size_t)lds_limit && (TC > 16 || TR > 8)) {
+            while (sweep_lds_bytes(rc[k], TR, TC, w) + lds_static > (size_t)lds_limit && (TC > 16 || TR > 8)) {
                 if (TC > 16) TC /= 2;
                 else TR /= 2;
             }
@@ -244,7 +249,7 @@ int Problem::allocate()
         std::vector<int> rs, rl, rb, cs, cl, cb;
         mode_tiles(n[k - 1], grid[k - 1], TR, rs, rl, rb);
         mode_tiles(n[k], grid[k], TC, cs, cl, cb);
-        if (sweep_lds_bytes(rc[k], TR, TC, w) + 1024 > (size_t)lds_limit)
+        if (sweep_lds_bytes(rc[k], TR, TC, w) + lds_static > (size_t)lds_limit)
             return set_err(TT_EINVAL, "tile %dx%d with rank cap %d needs more LDS than a workgroup has (%d B)",
                            TR, TC, rc[k], lds_limit);
         K.RTp = (int)rs.size();
@@ -282,13 +287,9 @@ int Problem::allocate()
         if ((st = dalloc((void **)&K.cand, sizeof(Cand) * K.cand_cap)) != TT_OK) return st;
         if ((st = dalloc((void **)&K.hist, sizeof(double) * hist_cap)) != TT_OK) return st;
         cores_cap += (int64_t)rc[k - 1] * n[k - 1] * rc[k];
-        a_cap += (int64_t)K.rowcap * rk;
-        rec_cap += (int64_t)rk * (rk + 1);
     }
     cores_cap += (int64_t)rc[d - 1] * n[d - 1];
     if ((st = dalloc((void **)&d_cores, sizeof(double) * cores_cap)) != TT_OK) return st;
-    if ((st = dalloc((void **)&d_A, sizeof(double) * std::max<int64_t>(a_cap, 1))) != TT_OK) return st;
-    if ((st = dalloc((void **)&d_rec, sizeof(double) * std::max<int64_t>(rec_cap, 1))) != TT_OK) return st;
     if ((st = dalloc((void **)&d_vals, sizeof(double) * opt.n_samples)) != TT_OK) return st;
     if ((st = dalloc((void **)&H.S, sizeof(ProbState))) != TT_OK) return st;
     HIPCHK(hipHostMalloc((void **)&hm, sizeof(HostMirror), hipHostMallocMapped | hipHostMallocCoherent));
@@ -413,35 +414,26 @@ template <typename V> int Problem::run_impl()
     std::memset(&ca, 0, sizeof ca);
     ca.nk = nk;
     for (int k = 0; k <= d; ++k) ca.ranks[k] = ranks_now[k];
-    int64_t ao = 0, go = 0, dofs = 0;
-    int rb = 0, maxr = 1, maxe = 1;
+    int64_t go = 0;
+    int rb = 0, maxr = 1;
     for (int u = 0; u < nk; ++u) {
         const int k = u + 1;
         const int nr = ranks_now[k - 1] * n[k - 1], rk = ranks_now[k];
-        ca.aoff[u] = ao;
         ca.goff[u] = go;
-        ca.doff[u] = dofs;
         ca.rowblocks[u] = rb;
-        ao += (int64_t)nr * rk;
         go += (int64_t)nr * rk;
-        dofs += (int64_t)rk * (rk + 1);
         rb += (nr + A4W - 1) / A4W;
         maxr = std::max(maxr, rk);
-        maxe = std::max<int64_t>(maxe, (int64_t)nr * rk);
     }
     ca.rowblocks[nk] = rb;
     ca.goff[nk] = go;
-    cores_len = go + (int64_t)ranks_now[d - 1] * n[d - 1];
-    maxe = std::max(maxe, ranks_now[d - 1] * n[d - 1]);
+    const int64_t gd = (int64_t)ranks_now[d - 1] * n[d - 1];
+    cores_len = go + gd;
     {
-        dim3 g((unsigned)std::min(256, (maxe + NT - 1) / NT), (unsigned)(nk + 1));
-        k_fibers<<<g, NT, 0, stream>>>(dP, ca, d_A, d_cores);
-        const size_t lp = sizeof(double) * (2 * maxr * maxr + 2 * maxr);
-        if (lp > (size_t)lds_limit) return set_err(TT_EINVAL, "rank %d too large for the core kernel", maxr);
-        k_alg4_pivots<<<nk, NT, lp, stream>>>(dP, ca, d_A, d_rec);
-        const size_t lr = sizeof(double) * ((size_t)2 * maxr * A4W + (size_t)maxr * maxr + (size_t)maxr * (maxr + 1));
-        if (lr > (size_t)lds_limit) return set_err(TT_EINVAL, "rank %d too large for the core kernel", maxr);
-        k_alg4_rows<<<rb, A4W, lr, stream>>>(dP, ca, d_A, d_rec, d_cores);
+        const size_t lc = sizeof(double) * ((size_t)2 * maxr * (maxr + 1) + (size_t)2 * maxr * A4W);
+        if (lc > (size_t)lds_limit) return set_err(TT_EINVAL, "rank %d too large for the core kernel", maxr);
+        const int blocks = rb + (int)((gd + A4W - 1) / A4W);
+        k_cores<<<blocks, A4W, lc, stream>>>(dP, ca, d_cores);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev1, stream));

@@ -36,6 +36,7 @@ struct Problem {
     int tileTR[TT_MAX_D] = {0}, tileTC[TT_MAX_D] = {0};
     int hist_cap = 0, max_sweeps = 0;
     int lds_limit = 65536;         // LDS bytes one workgroup may allocate on this device
+    int lds_static = 0;            // static LDS of the search kernel
     int sweep_grid_cap = 2048;     // workgroups of a search launch (8 per CU on 256 CUs)
     // device state
     hipStream_t stream = nullptr;
@@ -47,7 +48,7 @@ struct Problem {
     ProbDev hP;
     ProbDev *dP = nullptr;
     HostMirror *hm = nullptr;
-    double *d_cores = nullptr, *d_A = nullptr, *d_rec = nullptr, *d_vals = nullptr;
+    double *d_cores = nullptr, *d_vals = nullptr;
     // results
     bool ran = false;
     int status = TT_ESTATE;

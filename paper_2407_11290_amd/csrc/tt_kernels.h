@@ -304,6 +304,7 @@ __device__ inline void sweep_shape(const ProbDev *P, const KSweep *ks, int nk, S
     sh.soff[nk] = ns;
 }
 
+
 // Fixed grid striding over work units: first the new-entry tiles (one per
 // workgroup), then the stored tiles four at a time (one per wavefront).
 template <typename V>
@@ -420,8 +421,8 @@ __global__ void __launch_bounds__(NTC) k_commit(const ProbDev *__restrict__ P, S
     constexpr int NW = NTC / 64;
     const int nk = a.nk, d = P->d, par = a.sweep & 1;
     __shared__ KSweep ks[TT_MAX_D];
-    __shared__ double s_wv[NW * TT_MAX_D], s_wsv[NW * TT_MAX_D];
-    __shared__ uint64_t s_wk[NW * TT_MAX_D];
+    __shared__ double s_wv[TT_MAX_D], s_wsv[TT_MAX_D];
+    __shared__ uint64_t s_wk[TT_MAX_D];
     __shared__ int s_prop[TT_MAX_D], s_rold[TT_MAX_D + 1], s_rnew[TT_MAX_D + 1];
     __shared__ unsigned long long s_bytes[TT_MAX_D], s_new[TT_MAX_D], s_piv[TT_MAX_D];
     if (tid < nk) ks[tid] = S->ks[tid];
@@ -569,33 +570,34 @@ __global__ void __launch_bounds__(NT) k_samples(const ProbDev *__restrict__ P, u
 }
 
 // Pairwise sum of v[lo..lo+c) squared (c a power of two; entries past ns are
-// zero), combined bottom-up like a balanced binary tree.
+// zero): the chunk is cut into 64-leaf blocks, each summed as a complete
+// binary tree in registers, and the block sums are combined the same way.
+__device__ inline double tree64_sumsq(const double *v, int lo, int ns)
+{
+    double q[64];
+#pragma unroll
+    for (int b = 0; b < 64; ++b) {
+        const int g = lo + b;
+        const double t = (g < ns) ? v[g] : 0.0;
+        q[b] = __dmul_rn(t, t);
+    }
+#pragma unroll
+    for (int w = 64; w > 1; w >>= 1) {
+#pragma unroll
+        for (int i = 0; i < w / 2; ++i) q[i] = __dadd_rn(q[2 * i], q[2 * i + 1]);
+    }
+    return q[0];
+}
+
 __device__ inline double chunk_pairwise_sumsq(const double *v, int lo, int c, int ns)
 {
+    if (c <= 64) return tree64_sumsq(v, lo, ns);   // zero leaves past c leave the left subtree exact
     double st[32];
     int lv[32];
     int top = 0;
-    // leaves arrive in groups of 8 (loaded together, summed as a fixed
-    // 8-leaf subtree) when the chunk allows it, else one at a time
-    const int g8 = (c >= 8) ? 8 : 1;
-    const int base_level = (c >= 8) ? 3 : 0;
-    for (int i = 0; i < c; i += g8) {
-        double x;
-        if (g8 == 8) {
-            double q[8];
-#pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                const int g = lo + i + b;
-                const double t = (g < ns) ? v[g] : 0.0;
-                q[b] = __dmul_rn(t, t);
-            }
-            x = __dadd_rn(__dadd_rn(__dadd_rn(q[0], q[1]), __dadd_rn(q[2], q[3])),
-                          __dadd_rn(__dadd_rn(q[4], q[5]), __dadd_rn(q[6], q[7])));
-        } else {
-            const int g = lo + i;
-            x = (g < ns) ? __dmul_rn(v[g], v[g]) : 0.0;
-        }
-        int level = base_level;
+    for (int i = 0; i < c; i += 64) {
+        double x = tree64_sumsq(v, lo + i, ns);
+        int level = 6;
         while (top > 0 && lv[top - 1] == level) {
             x = __dadd_rn(st[top - 1], x);
             --top;
@@ -633,7 +635,29 @@ __global__ void __launch_bounds__(NT) k_setup(const ProbDev *__restrict__ P, uin
     int m = 1;
     while (m < ns) m <<= 1;
     const int c = (m >= NT) ? m / NT : 1;
-    double part = (tid * c < m) ? chunk_pairwise_sumsq(vals, tid * c, c, ns) : 0.0;
+    // a chunk of c <= 64 leaves is the left part of its 64-leaf tree, so it
+    // is summed exactly by tree64 with zeros past the chunk
+    double part = 0.0;
+    if (tid * c < m) {
+        if (c >= 64) part = chunk_pairwise_sumsq(vals, tid * c, c, ns);
+        else {
+            const double *vv = vals;
+            int lo = tid * c, hi = lo + c;
+            double q[64];
+#pragma unroll
+            for (int b = 0; b < 64; ++b) {
+                const int g = lo + b;
+                const double t = (g < hi && g < ns) ? vv[g] : 0.0;
+                q[b] = __dmul_rn(t, t);
+            }
+#pragma unroll
+            for (int w = 64; w > 1; w >>= 1) {
+#pragma unroll
+                for (int i = 0; i < w / 2; ++i) q[i] = __dadd_rn(q[2 * i], q[2 * i + 1]);
+            }
+            part = q[0];
+        }
+    }
     for (int off = 1; off < 64; off <<= 1) {
         const double o = __shfl_down(part, off, 64);
         if ((tid & (2 * off - 1)) == 0) part = __dadd_rn(part, o);
@@ -712,148 +736,100 @@ __global__ void __launch_bounds__(NT) k_init_eval(const ProbDev *__restrict__ P)
 }
 
 // ---------------------------------------------------------------------------
-// Cores by Alg. 4 (FP64).  A_k = X(I_{<=k-1} x [n_k], J_{>k}) is evaluated
-// into a scratch buffer; the pivot rows' recursion runs once per unfolding and
-// records delta_z and T(i_z, :) before step z; every other row then follows
-// eq. (aca_approx_T_sub) independently.
+// Cores by Alg. 4 (FP64), one 64-thread workgroup per 64 rows of
+// A_k = X(I_{<=k-1} x [n_k], J_{>k}) (the sliced fibers of eq. corereshape).
+// Each workgroup evaluates its rows' fibers and the pivot rows' fibers
+// A(I_{<=k}, J_{>k}), runs the pivot rows' recursion (lane t = pivot row t,
+// lock-step within the wavefront) and, step by step, applies
+// eq. (aca_approx_T_sub) to its own rows:
+//   s = T(:, 0..z-1) A(I_z, j_z) - A(:, j_z),  delta^{-1} = -s(i_z),
+//   T <- [T + delta s T(i_z, :), -delta s].
+// Workgroups past the last unfolding's rows evaluate G_d = X(I_{<=d-1}, :).
 // ---------------------------------------------------------------------------
 struct CoreArgs {
     int nk;
     int ranks[TT_MAX_D + 1];
-    int64_t aoff[TT_MAX_D];     // offset of A_k in the scratch
     int64_t goff[TT_MAX_D + 1]; // offset of G_k in the cores buffer
-    int64_t doff[TT_MAX_D];     // offset of (delta, Trho) records per unfolding
-    int rowblocks[TT_MAX_D + 1];// prefix sum of row blocks per unfolding (k_alg4_rows)
+    int rowblocks[TT_MAX_D + 1];// prefix sum of 64-row blocks per unfolding; [nk] = start of G_d blocks
 };
 
-constexpr int A4W = 64;         // rows per workgroup of k_alg4_rows (one wavefront)
+constexpr int A4W = 64;         // rows per workgroup (one wavefront)
 
-__global__ void __launch_bounds__(NT) k_fibers(const ProbDev *__restrict__ P, CoreArgs a, double *A,
-                                                 double *G)
+__global__ void __launch_bounds__(A4W) k_cores(const ProbDev *__restrict__ P, CoreArgs a, double *G)
 {
-    const int u = blockIdx.y, d = P->d;
-    if (u < a.nk) {
-        const int k = u + 1;
-        const KDev &K = P->kd[u];
-        const int rk = a.ranks[k], nr = a.ranks[k - 1] * K.nk;
-        const int64_t tot = (int64_t)nr * rk;
-        for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < tot; e += (int64_t)gridDim.x * NT) {
-            const int i = (int)(e / rk), z = (int)(e - (int64_t)i * rk);
-            const int p = i / K.nk;
-            int idx[TT_MAX_D];
-            for (int j = 0; j < k - 1; ++j) idx[j] = P->kd[u - 1].Ifull[p * (k - 1) + j];
-            idx[k - 1] = i - p * K.nk;
-            for (int j = 0; j < d - k; ++j) idx[k + j] = K.Jfull[z * (d - k) + j];
-            A[a.aoff[u] + e] = fn_value<double>(P->F, idx);
-        }
-    } else {
-        // G_d = X(I_{<=d-1}, :)
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int bid = blockIdx.x, lane = threadIdx.x, d = P->d;
+    if (bid >= a.rowblocks[a.nk]) {
         const KDev &K = P->kd[d - 2];
         const int rd = a.ranks[d - 1], nd = P->F.n[d - 1];
-        const int64_t tot = (int64_t)rd * nd;
-        for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < tot; e += (int64_t)gridDim.x * NT) {
-            const int pp = (int)(e / nd), i = (int)(e - (int64_t)pp * nd);
-            int idx[TT_MAX_D];
-            for (int j = 0; j < d - 1; ++j) idx[j] = K.Ifull[pp * (d - 1) + j];
-            idx[d - 1] = i;
-            G[a.goff[d - 1] + e] = fn_value<double>(P->F, idx);
-        }
+        const int64_t e = (int64_t)(bid - a.rowblocks[a.nk]) * A4W + lane;
+        if (e >= (int64_t)rd * nd) return;
+        const int pp = (int)(e / nd), i = (int)(e - (int64_t)pp * nd);
+        const int *Ip = K.Ifull + pp * (d - 1);
+        G[a.goff[d - 1] + e] = fn_value_ix<double>(P->F, [&](int j) { return j < d - 1 ? Ip[j] : i; });
+        return;
     }
-}
-
-// One workgroup per unfolding: T of the pivot rows (LDS) and the per-step
-// records delta_z, T(i_z, 0..z-1).
-__global__ void __launch_bounds__(NT) k_alg4_pivots(const ProbDev *__restrict__ P, CoreArgs a,
-                                                      const double *A, double *rec)
-{
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int u = blockIdx.x, k = u + 1, tid = threadIdx.x;
-    const KDev &K = P->kd[u];
-    const int rk = a.ranks[k];
-    const double *Ak = A + a.aoff[u];
-    double *Tp = (double *)smem_raw;            // rk x rk: T of the pivot rows
-    double *Ap = Tp + rk * rk;                  // rk x rk: Ap[t*rk+z] = A(rho_t, z)
-    double *s = Ap + rk * rk;                   // rk
-    double *Tr = s + rk;                        // rk
-    double *R = rec + a.doff[u];                // per z: delta_z then T(i_z, 0..z-1)
-    for (int e = tid; e < rk * rk; e += NT) {
-        const int t = e / rk, z = e - t * rk;
-        Ap[e] = Ak[(int64_t)K.rho[t] * rk + z];
-    }
-    __syncthreads();
-    const double a11 = Ap[0];
-    for (int e = tid; e < rk * rk; e += NT) {
-        const int t = e / rk, z = e - t * rk;
-        Tp[e] = (z == 0) ? Ap[t * rk] / a11 : 0.0;
-    }
-    __syncthreads();
-    for (int z = 1; z < rk; ++z) {
-        if (tid < rk) {
-            double dot = 0.0;
-            for (int zz = 0; zz < z; ++zz) dot = __fma_rn(Tp[tid * rk + zz], Ap[zz * rk + z], dot);
-            s[tid] = dot - Ap[tid * rk + z];
-        }
-        if (tid < z) Tr[tid] = Tp[z * rk + tid];
-        __syncthreads();
-        const double delta = 1.0 / (-s[z]);
-        if (tid == 0) R[(int64_t)z * (rk + 1)] = delta;
-        if (tid < z) R[(int64_t)z * (rk + 1) + 1 + tid] = Tr[tid];
-        if (tid < rk) {
-            const double c = delta * s[tid];
-            for (int zz = 0; zz < z; ++zz) Tp[tid * rk + zz] = __fma_rn(c, Tr[zz], Tp[tid * rk + zz]);
-            Tp[tid * rk + z] = -c;
-        }
-        __syncthreads();
-    }
-}
-
-// One wavefront per 64 rows; T of the rows kept in LDS as T[z][lane].
-__global__ void __launch_bounds__(A4W) k_alg4_rows(const ProbDev *__restrict__ P, CoreArgs a, const double *A,
-                                                     const double *rec, double *G)
-{
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int bid = blockIdx.x;
     int u = 0;
     while (u + 1 < a.nk && bid >= a.rowblocks[u + 1]) ++u;
-    const int k = u + 1, lane = threadIdx.x;
+    const int k = u + 1;
     const KDev &K = P->kd[u];
-    const int rk = a.ranks[k], nr = a.ranks[k - 1] * K.nk;
-    const double *Ak = A + a.aoff[u];
-    const double *Rk = rec + a.doff[u];
-    double *T = (double *)smem_raw;             // T[z*A4W + lane]
-    double *Ap = T + rk * A4W;                  // Ap[zz*rk + z] = A(rho_zz, z)
-    double *Rs = Ap + rk * rk;                  // the pivot recursion's records
-    double *Ar = Rs + rk * (rk + 1);            // Ar[z*A4W + lane] = A(row, z)
-    const int i0 = (bid - a.rowblocks[u]) * A4W;
-    const int i = i0 + lane;
+    const int rk = a.ranks[k], nr = a.ranks[k - 1] * K.nk, st = rk + 1, nj = d - k;
+    double *Tp = (double *)smem_raw;            // Tp[t*st + z]: T of pivot row t
+    double *Ap = Tp + rk * st;                  // Ap[t*st + z] = A(rho_t, z)
+    double *Tb = Ap + rk * st;                  // Tb[z*A4W + lane]: T of this lane's row
+    double *Ab = Tb + rk * A4W;                 // Ab[z*A4W + lane] = A(row, z)
+    const int i0 = (bid - a.rowblocks[u]) * A4W, i = i0 + lane;
     const bool act = i < nr;
-    const int rows = min(A4W, nr - i0);
-    for (int e = lane; e < rk * rk; e += A4W) {
-        const int zz = e / rk, z = e - zz * rk;
-        Ap[e] = Ak[(int64_t)K.rho[zz] * rk + z];
-    }
-    for (int e = lane; e < rk * (rk + 1); e += A4W) Rs[e] = Rk[e];
-    for (int e = lane; e < rows * rk; e += A4W) {
-        const int ii = e / rk, z = e - ii * rk;
-        Ar[z * A4W + ii] = Ak[(int64_t)(i0 + ii) * rk + z];
+    const int p = act ? i / K.nk : 0, ik = act ? i - p * K.nk : 0;
+    const int *preI = (k >= 2) ? P->kd[u - 1].Ifull + p * (k - 1) : nullptr;
+    for (int z = 0; z < rk; ++z) {
+        const int *Jz = K.Jfull + z * nj;
+        Ab[z * A4W + lane] = act ? fn_value_ix<double>(P->F, [&](int j) {
+            return j < k - 1 ? preI[j] : (j == k - 1 ? ik : Jz[j - k]);
+        }) : 0.0;
+        if (lane < rk) {
+            const int *It = K.Ifull + lane * k;
+            Ap[lane * st + z] = fn_value_ix<double>(P->F, [&](int j) { return j < k ? It[j] : Jz[j - k]; });
+        }
     }
     __syncthreads();
     const double a11 = Ap[0];
-    T[lane] = act ? Ar[lane] / a11 : 0.0;
-    for (int z = 1; z < rk; ++z) {
-        double dot = 0.0;
-        for (int zz = 0; zz < z; ++zz) dot = __fma_rn(T[zz * A4W + lane], Ap[zz * rk + z], dot);
-        const double s = dot - (act ? Ar[z * A4W + lane] : 0.0);
-        const double *Rz = Rs + z * (rk + 1);
-        const double c = Rz[0] * s;
-        for (int zz = 0; zz < z; ++zz) T[zz * A4W + lane] = __fma_rn(c, Rz[1 + zz], T[zz * A4W + lane]);
-        T[z * A4W + lane] = -c;
+    for (int z = 0; z < rk; ++z) {
+        Tb[z * A4W + lane] = (z == 0) ? Ab[lane] / a11 : 0.0;
+        if (lane < rk) Tp[lane * st + z] = (z == 0) ? Ap[lane * st] / a11 : 0.0;
     }
     __syncthreads();
+    for (int z = 1; z < rk; ++z) {
+        double sp = 0.0, sb;
+        {
+            double dot = 0.0;
+            for (int zz = 0; zz < z; ++zz) dot = __fma_rn(Tb[zz * A4W + lane], Ap[zz * st + z], dot);
+            sb = dot - Ab[z * A4W + lane];
+        }
+        if (lane < rk) {
+            double dot = 0.0;
+            for (int zz = 0; zz < z; ++zz) dot = __fma_rn(Tp[lane * st + zz], Ap[zz * st + z], dot);
+            sp = dot - Ap[lane * st + z];
+        }
+        const double delta = 1.0 / (-__shfl(sp, z, 64));
+        const double cb = delta * sb, cp = delta * sp;
+        __syncthreads();                        // every lane has read T before it changes
+        for (int zz = 0; zz < z; ++zz) {
+            const double tr = Tp[z * st + zz];  // T(i_z, zz) before this step
+            Tb[zz * A4W + lane] = __fma_rn(cb, tr, Tb[zz * A4W + lane]);
+            __syncthreads();
+            if (lane < rk) Tp[lane * st + zz] = __fma_rn(cp, tr, Tp[lane * st + zz]);
+            __syncthreads();
+        }
+        Tb[z * A4W + lane] = -cb;
+        if (lane < rk) Tp[lane * st + z] = -cp;
+        __syncthreads();
+    }
+    const int rows = min(A4W, nr - i0);
     double *Gk = G + a.goff[u] + (int64_t)i0 * rk;
     for (int e = lane; e < rows * rk; e += A4W) {
         const int ii = e / rk, z = e - ii * rk;
-        Gk[e] = T[z * A4W + ii];
+        Gk[e] = Tb[z * A4W + ii];
     }
 }
 
