@@ -30,6 +30,34 @@ N, EPS, GRID, SEEDS = [64] * 6, 1e-8, [2] * 6, [0, 1, 2, 3, 4]
 HBM_PEAK_GBS = 8000.0
 
 
+PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "k_sweep_hilbert6d_n64_fp64.md")
+
+
+def kernel_sources_hash():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2407_11290_amd", "csrc", "*"))):
+        if os.path.basename(p) in ("tt_kernels.h", "tt_device.h"):
+            with open(p, "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def counted_traffic():
+    """Scaled FETCH_SIZE + WRITE_SIZE bytes per search launch from the committed
+    rocprofv3 summary, or None when the kernel sources changed since."""
+    try:
+        with open(PROFILE_SUMMARY) as f:
+            kv = dict(line.split(": ", 1) for line in f.read().splitlines()
+                      if line.startswith(("traffic_per_launch_bytes:", "kernel_sources_sha256_16:")))
+    except OSError:
+        return None
+    if kv.get("kernel_sources_sha256_16", "").strip() != kernel_sources_hash():
+        return None
+    return float(kv["traffic_per_launch_bytes"])
+
+
 def cpu_baseline(seconds):
     from oracle import Oracle
     from oracle.oracle import FN_HILBERT
@@ -59,6 +87,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="only run a plain copy kernel (out = -in, FP64) over this many MiB, five times; "
+                         "its FETCH_SIZE/WRITE_SIZE counters scale the search kernel's")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; a solve is not sharded across GPUs "
@@ -67,6 +98,15 @@ def main():
 
     import torch
     torch.cuda.init()
+    if args.calib_copy_mib > 0:
+        nbytes = args.calib_copy_mib << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy": {"bytes_read": nbytes, "bytes_written": nbytes, "launches": 5}}), flush=True)
+        return
     from paper_2407_11290_amd import FN_HILBERT, PREC_FP64
     from paper_2407_11290_amd.api import TTCross
 
@@ -129,7 +169,7 @@ def main():
                    "grid": GRID, "eps": EPS, "seeds": SEEDS, "ranks_last": ranks},
         "time_to_eps_ms": {"median": statistics.median(tte) * 1e3, "min": min(tte) * 1e3},
         "roofline": {"kernel": "k_sweep<double>", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": counted_traffic(),
                      "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_launch * 1e6,
                      "launches": launches,
                      "sweep_phase_us_per_solve": phase_s / args.steps * 1e6,

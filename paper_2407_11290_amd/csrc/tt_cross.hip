@@ -1,5 +1,6 @@
 // tt_cross.hip -- host driver and C ABI of the gfx950 greedy adaptive TT-cross
 // library (declarations and contracts in include/tt_cross.h).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -374,9 +375,13 @@ template <typename V> int Problem::run_impl()
             // enough workgroups for the largest superblocks this sweep can have;
             // the kernel strides over the exact tile count it reads on the device
             const int grid = std::max(1, std::min(tot, sweep_grid_cap));
-            if (prof) HIPCHK(hipEventRecord(prof_events[3 * launched], stream));
-            k_sweep<V><<<grid, NT, lds, stream>>>(dP, a);
-            if (prof) HIPCHK(hipEventRecord(prof_events[3 * launched + 1], stream));
+            if (prof) {
+                // the events take the dispatch's own start and end timestamps
+                hipExtLaunchKernelGGL(k_sweep<V>, dim3(grid), dim3(NT), (uint32_t)lds, stream,
+                                      prof_events[3 * launched], prof_events[3 * launched + 1], 0u, dP, a);
+            } else {
+                k_sweep<V><<<grid, NT, lds, stream>>>(dP, a);
+            }
             ++launched;
             for (int k = 1; k <= d - 1; ++k) rub[k] = std::min(rub[k] + 1, rc[k]);
             k_commit<V><<<1, NTC, 0, stream>>>(dP, a);
