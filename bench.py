@@ -80,6 +80,55 @@ def cpu_baseline(seconds):
                       f"{done:.1f} s, one host thread"}
 
 
+def bench_batch(args):
+    """Mixed batch of 512 problems (d 3..6, n 16..128, Hilbert / bi-Maxwellian,
+    eps 1e-6, FP32 sweeps by the precision policy): one batched solve per step
+    against the same problems solved one at a time."""
+    import torch
+    from paper_2407_11290_amd.api import TTCross, batch_run
+    from paper_2407_11290_amd.workloads import batch_mix
+    specs = batch_mix()
+    hs = [TTCross(p.n, p.eps, p.fn_id, p.params, seed=p.seed, grid=p.grid) for p in specs]
+    t0 = time.perf_counter()
+    batch_run(hs)                                   # allocates every problem's buffers
+    print(f"bench: first batch (with allocation) {time.perf_counter() - t0:.2f} s", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        batch_run(hs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    work = 0
+    for _ in range(args.steps):
+        batch_run(hs)
+        for h in hs:
+            st = h.stats()
+            work += st["evaluated"] + st["pivoted"]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    print(f"bench: {args.steps} batched steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+    # the same problems one after another on one stream
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    work1 = 0
+    for h in hs:
+        h.run()
+        st = h.stats()
+        work1 += st["evaluated"] + st["pivoted"]
+    torch.cuda.synchronize()
+    single = time.perf_counter() - t1
+    statuses = [h.stats()["status"] for h in hs]
+    out = {
+        "metric": METRIC, "value": work / elapsed, "unit": "entries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch512_mixed_d3-6_n16-128_eps1e-6", "problems": len(hs)},
+        "solves_per_s": len(hs) / (elapsed / args.steps),
+        "one_at_a_time": {"s": single, "entries_per_s": work1 / single, "solves_per_s": len(hs) / single},
+        "batched_over_one_at_a_time": single / (elapsed / args.steps),
+        "statuses": {str(k): statuses.count(k) for k in sorted(set(statuses))},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +136,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="hilbert6d", choices=["hilbert6d", "batch512"],
+                    help="hilbert6d: the single-solve benchmark line; batch512: the mixed 512-problem "
+                         "batch, solved together and one at a time")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain copy kernel (out = -in, FP64) over this many MiB, five times; "
                          "its FETCH_SIZE/WRITE_SIZE counters scale the search kernel's")
@@ -109,6 +161,8 @@ def main():
         return
     from paper_2407_11290_amd import FN_HILBERT, PREC_FP64
     from paper_2407_11290_amd.api import TTCross
+    if args.workload == "batch512":
+        return bench_batch(args)
 
     handles = [TTCross(N, EPS, FN_HILBERT, seed=s, precision=PREC_FP64, grid=GRID) for s in SEEDS]
     probes = [TTCross(N, EPS, FN_HILBERT, seed=s, precision=PREC_FP64, grid=GRID, profile=1) for s in SEEDS]

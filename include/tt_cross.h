@@ -183,6 +183,26 @@ int tt_fn_eval(int fn_id, int d, const int32_t *n, const double *params, int npa
 
 void tt_cross_destroy(tt_cross_h h);
 
+/* Solve count independent problems together on one GPU.
+ *
+ * Every handle is solved exactly as tt_cross_run would solve it (same
+ * samples, pivots, ranks and cores, bit for bit), but all of them are
+ * resident at once.  Each launch covers every problem at the same phase:
+ *   - setup covers all problems;
+ *   - each search launch covers all problems still sweeping, every one over
+ *     its own superblocks and subtensor blocks (Alg. 2, Sec. 3);
+ *   - each commit launch covers the same problems.
+ * A problem that stops leaves the rounds, and its cores (Alg. 4) are built
+ * with those of the others that stopped at the same time.
+ *
+ * hip_stream: the stream all launches go to (NULL: the first handle's).
+ * The handles keep their buffers; results are read with the usual getters,
+ * and time_to_eps in the stats is the whole batch's.  Handles must be
+ * distinct.  Returns TT_OK when every launch succeeded; each problem's own
+ * status (TT_OK, TT_NOT_CONVERGED, or a device-reported error) is in its
+ * stats.  Errors: TT_EINVAL (bad arguments), TT_EDEVICE, TT_ENOMEM. */
+int tt_batch_run(tt_cross_h *hs, int count, void *hip_stream);
+
 /* Message for the last error on the calling thread (empty if none). */
 const char *tt_last_error(void);
 

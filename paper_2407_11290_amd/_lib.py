@@ -74,6 +74,7 @@ SIGNATURES = {
     "tt_fn_eval": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_int,
                              C.c_int64, C.c_void_p, C.c_void_p, C.c_int]),
     "tt_cross_destroy": (None, [C.c_void_p]),
+    "tt_batch_run": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_void_p]),
     "tt_last_error": (C.c_char_p, []),
 }
 

@@ -159,3 +159,19 @@ class TTCross:
         e = C.c_double()
         check(load().tt_cross_sampled_error(self.h, R, C.c_uint64(seed), C.byref(e)))
         return e.value
+
+
+def batch_run(problems, stream=None):
+    """Solve several TTCross problems together on one GPU (tt_batch_run).
+
+    Each problem ends exactly as its own run() would end; the per-problem
+    status is returned as a list (also in each problem's stats())."""
+    problems = list(problems)
+    arr = (C.c_void_p * len(problems))(*[p.h for p in problems])
+    s = None if stream is None else C.c_void_p(getattr(stream, "cuda_stream", stream))
+    check(load().tt_batch_run(arr, len(problems), s))
+    out = []
+    for p in problems:
+        p.status = p.stats()["status"]
+        out.append(p.status)
+    return out

@@ -1,0 +1,61 @@
+// tt_batch.h -- engine that keeps many independent solves resident on one GPU
+// and advances all of them with shared launches (batched and served solves).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "tt_device.h"
+#include "tt_internal.h"
+
+namespace ttc {
+
+struct Slot {
+    enum Phase { FREE, SETUP, SWEEP, CORES, DONE, FAILED };
+    int idx = 0;                  // entry in the engine's descriptor array
+    Phase phase = FREE;
+    Problem *Q = nullptr;
+    void *user = nullptr;
+    int launched = 0;             // sweep rounds queued for this slot
+    int done = 0;                 // sweep rounds it has committed (host mirror)
+    bool stop_seen = false;       // its stop flag reached the host
+    bool idle_done = false;       // stream idle with nothing left to run for it
+    int rub[TT_MAX_D + 1] = {0};  // rank bounds for the next round it gets
+    hipEvent_t ev = nullptr;      // completes when its cores and state are on the host
+    double t_admit = 0, t_done = 0;
+};
+
+class Engine {
+public:
+    int cap = 0;
+    hipStream_t stream = nullptr;
+
+    ~Engine();
+    void release();
+    int init(int capacity, hipStream_t s);
+    // Takes a prepared problem into a free slot; returns the slot or an error.
+    int admit(Problem *Q, void *user);
+    // Reads progress, launches whatever can run, and appends the slots that
+    // finished (cores on the host side, or failed) to *completed.
+    int tick(std::vector<int> *completed);
+    void retire(int idx);         // frees a finished slot
+    bool idle() const;            // no slot is waiting for the device
+    int free_slots() const;
+    int busy() const;
+    const Slot &slot(int i) const { return slots[i]; }
+
+private:
+    template <typename V> int launch_setup(std::vector<int> &ids);
+    template <typename V> int launch_sweep(std::vector<int> &ids);
+    int launch_cores(std::vector<int> &ids);
+    void finish_slot(Slot &s);
+
+    std::vector<Slot> slots;
+    std::vector<hipEvent_t> ev_free;
+    ProbDev *dPa = nullptr, *hPa = nullptr;   // descriptors: device array, pinned staging
+    ProbState *dS = nullptr, *hS = nullptr;   // per-slot device state and its host copy
+    HostMirror *hm = nullptr, *dhm = nullptr; // mapped host mirrors (host / device view)
+};
+
+}  // namespace ttc

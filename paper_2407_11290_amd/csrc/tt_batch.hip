@@ -1,0 +1,399 @@
+// tt_batch.hip -- many independent solves resident on one GPU at once.
+//
+// The engine keeps a table of slots.  Each slot holds one prepared problem
+// (its own residual superblocks, index sets and cores) plus a descriptor in
+// a device array shared by all slots.  Every launch covers all slots that
+// are at the same phase:
+//   setup  samples, rms/tau/first pivot and initial superblocks
+//   sweep  one search launch and one commit launch per round, over all
+//          slots still sweeping (each slot at its own sweep index; the
+//          commit reads it from the slot's device state)
+//   cores  Alg. 4 for all slots whose sweeps ended
+// The host queues sweep rounds ahead of its view of each slot's stop flag,
+// which the commits write to mapped host memory.  Slots may be admitted
+// while others are sweeping (continuous batching); a finished slot frees its
+// entry for the next admission.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <vector>
+
+#include "tt_batch.h"
+#include "tt_cross.h"
+#include "tt_device.h"
+#include "tt_internal.h"
+#include "tt_kernels.h"
+
+namespace ttc {
+
+static double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+Engine::~Engine() { release(); }
+
+void Engine::release()
+{
+    for (hipEvent_t e : ev_free) (void)hipEventDestroy(e);
+    ev_free.clear();
+    for (Slot &s : slots)
+        if (s.ev) { (void)hipEventDestroy(s.ev); s.ev = nullptr; }
+    if (dPa) (void)hipFree(dPa);
+    if (dS) (void)hipFree(dS);
+    if (hPa) (void)hipHostFree(hPa);
+    if (hS) (void)hipHostFree(hS);
+    if (hm) (void)hipHostFree(hm);
+    dPa = nullptr; dS = nullptr; hPa = nullptr; hS = nullptr; hm = nullptr; dhm = nullptr;
+    slots.clear();
+    cap = 0;
+}
+
+int Engine::init(int capacity, hipStream_t s)
+{
+    release();
+    if (capacity < 1 || capacity > 65535) return set_err(TT_EINVAL, "engine capacity %d outside [1,65535]", capacity);
+    stream = s;
+    cap = capacity;
+    HIPCHK(hipMalloc(&dPa, sizeof(ProbDev) * cap));
+    HIPCHK(hipMalloc(&dS, sizeof(ProbState) * cap));
+    HIPCHK(hipHostMalloc((void **)&hPa, sizeof(ProbDev) * cap, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&hS, sizeof(ProbState) * cap, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&hm, sizeof(HostMirror) * cap, hipHostMallocMapped | hipHostMallocCoherent));
+    HIPCHK(hipHostGetDevicePointer((void **)&dhm, hm, 0));
+    std::memset(hm, 0, sizeof(HostMirror) * cap);
+    slots.assign(cap, Slot());
+    for (int i = 0; i < cap; ++i) slots[i].idx = i;
+    return TT_OK;
+}
+
+int Engine::free_slots() const
+{
+    int f = 0;
+    for (const Slot &s : slots) f += (s.phase == Slot::FREE) ? 1 : 0;
+    return f;
+}
+
+int Engine::busy() const { return cap - free_slots(); }
+
+int Engine::admit(Problem *Q, void *user)
+{
+    int i = -1;
+    for (int j = 0; j < cap; ++j)
+        if (slots[j].phase == Slot::FREE) { i = j; break; }
+    if (i < 0) return set_err(TT_ESTATE, "no free slot");
+    if (!Q->allocated) return set_err(TT_ESTATE, "problem not prepared");
+    Slot &s = slots[i];
+    s = Slot();
+    s.idx = i;
+    s.Q = Q;
+    s.user = user;
+    s.phase = Slot::SETUP;
+    s.t_admit = now_s();
+    for (int k = 0; k <= Q->d; ++k) s.rub[k] = 1;
+    ProbDev &D = hPa[i];
+    D = Q->hP;
+    D.S = dS + i;
+    D.hm = dhm + i;
+    D.run.seed = Q->opt.seed;
+    D.run.eps = Q->eps;
+    D.run.ns = Q->opt.n_samples;
+    D.run.vals = Q->d_vals;
+    D.run.cores = Q->d_cores;
+    std::memset(&hm[i], 0, sizeof(HostMirror));
+    HIPCHK(hipMemcpyAsync(dPa + i, &D, sizeof(ProbDev), hipMemcpyHostToDevice, stream));
+    Q->ran = false;
+    return i;
+}
+
+// Launch setup for every slot admitted since the last call.
+template <typename V> int Engine::launch_setup(std::vector<int> &ids)
+{
+    for (size_t c0 = 0; c0 < ids.size(); c0 += MAXB) {
+        const int na = (int)std::min<size_t>(MAXB, ids.size() - c0);
+        BatchMap bm;
+        bm.na = na;
+        int xs = 64, maxnk = 1, xi = 1;
+        for (int a = 0; a < na; ++a) {
+            const Slot &s = slots[ids[c0 + a]];
+            const Problem &Q = *s.Q;
+            bm.p[a] = (uint16_t)s.idx;
+            bm.boff[a] = a;
+            xs = std::max(xs, (Q.opt.n_samples + NT - 1) / NT);
+            maxnk = std::max(maxnk, Q.d - 1);
+            for (int u = 0; u < Q.d - 1; ++u) xi = std::max(xi, (Q.n[u] * Q.n[u + 1] + NT - 1) / NT);
+        }
+        bm.boff[na] = na;
+        xi = std::min(xi, 1024);
+        k_samples_b<<<dim3(xs, na), NT, 0, stream>>>(dPa, bm);
+        k_setup_b<V><<<na, NT, 0, stream>>>(dPa, bm);
+        k_init_eval_b<V><<<dim3(xi, maxnk, na), NT, 0, stream>>>(dPa, bm);
+        HIPCHK(hipGetLastError());
+    }
+    return TT_OK;
+}
+
+// One search + commit round over the given sweeping slots.
+template <typename V> int Engine::launch_sweep(std::vector<int> &ids)
+{
+    for (size_t c0 = 0; c0 < ids.size(); c0 += MAXB) {
+        const int na = (int)std::min<size_t>(MAXB, ids.size() - c0);
+        BatchMap bm;
+        bm.na = na;
+        int off = 0;
+        size_t lds = 0;
+        for (int a = 0; a < na; ++a) {
+            Slot &s = slots[ids[c0 + a]];
+            const Problem &Q = *s.Q;
+            const int d = Q.d;
+            int tot = 0;
+            for (int u = 0; u < d - 1; ++u) {
+                const int k = u + 1;
+                const KDev &K = Q.hP.kd[u];
+                tot += s.rub[k - 1] * K.RTp * s.rub[k + 1] * K.CTq;
+                lds = std::max(lds, sweep_lds_bytes(s.rub[k], K.TR, K.TC, sizeof(V)));
+            }
+            bm.p[a] = (uint16_t)s.idx;
+            bm.boff[a] = off;
+            off += std::max(1, std::min(tot, Q.sweep_grid_cap));
+            ++s.launched;
+            for (int k = 1; k <= d - 1; ++k) s.rub[k] = std::min(s.rub[k] + 1, Q.rc[k]);
+        }
+        bm.boff[na] = off;
+        k_sweep_b<V><<<off, NT, lds, stream>>>(dPa, bm);
+        k_commit_b<V><<<na, NTC, 0, stream>>>(dPa, bm);
+        HIPCHK(hipGetLastError());
+    }
+    return TT_OK;
+}
+
+// Cores for the given slots, then their final device state to the host and
+// one event that marks them complete.
+int Engine::launch_cores(std::vector<int> &ids)
+{
+    for (size_t c0 = 0; c0 < ids.size(); c0 += MAXB) {
+        const int na = (int)std::min<size_t>(MAXB, ids.size() - c0);
+        BatchMap bm;
+        int m = 0, off = 0, maxr = 1;
+        for (int a = 0; a < na; ++a) {
+            Slot &s = slots[ids[c0 + a]];
+            const Problem &Q = *s.Q;
+            int r[TT_MAX_D + 1];
+            for (int k = 0; k <= Q.d; ++k) r[k] = hm[s.idx].r[k];
+            r[0] = r[Q.d] = 1;
+            for (int k = 1; k <= Q.d - 1; ++k) maxr = std::max(maxr, r[k]);
+            CoreArgs ca;
+            int64_t len;
+            const int blocks = make_core_args(Q.d, Q.n, r, ca, len);
+            bm.p[m] = (uint16_t)s.idx;
+            bm.boff[m] = off;
+            off += blocks;
+            ++m;
+        }
+        bm.na = m;
+        bm.boff[m] = off;
+        const size_t lc = sizeof(double) * ((size_t)2 * maxr * (maxr + 1) + (size_t)2 * maxr * A4W);
+        if (m > 0 && off > 0) k_cores_b<<<off, A4W, lc, stream>>>(dPa, bm);
+        HIPCHK(hipGetLastError());
+    }
+    hipEvent_t ev = nullptr;
+    if (!ev_free.empty()) { ev = ev_free.back(); ev_free.pop_back(); }
+    else HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    for (int i : ids) HIPCHK(hipMemcpyAsync(hS + i, dS + i, sizeof(ProbState), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipEventRecord(ev, stream));
+    // the event is shared by the slots of this call; the last one to see it
+    // complete returns it to the pool
+    for (int i : ids) {
+        slots[i].ev = ev;
+        slots[i].phase = Slot::CORES;
+    }
+    return TT_OK;
+}
+
+int Engine::tick(std::vector<int> *completed)
+{
+    // 1. read the mirrors: progress and stop flags of sweeping slots
+    std::vector<int> to_cores;
+    bool any_sweeping = false;
+    for (Slot &s : slots) {
+        if (s.phase != Slot::SWEEP) continue;
+        const HostMirror &h = hm[s.idx];
+        const int sd = __atomic_load_n(&h.sweeps_done, __ATOMIC_ACQUIRE);
+        if (sd > s.done) s.done = sd;
+        if (__atomic_load_n(&h.stop, __ATOMIC_ACQUIRE)) s.stop_seen = true;
+        const bool exhausted = s.launched >= s.Q->max_sweeps && s.done >= s.launched;
+        if (s.stop_seen || exhausted || s.idle_done) {
+            // without the stop flag's release the mirror's ranks are read only
+            // after the stream has drained
+            if (!s.stop_seen) HIPCHK(hipStreamSynchronize(stream));
+            if (h.err) {
+                s.Q->status = h.err;
+                s.Q->ran = false;
+                s.phase = Slot::FAILED;
+                if (completed) completed->push_back(s.idx);
+                continue;
+            }
+            to_cores.push_back(s.idx);
+        } else {
+            any_sweeping = true;
+            for (int k = 1; k <= s.Q->d - 1; ++k)
+                s.rub[k] = std::min(s.Q->rc[k], __atomic_load_n(&h.r[k], __ATOMIC_RELAXED) + (s.launched - s.done));
+        }
+    }
+    if (!to_cores.empty()) {
+        int st = launch_cores(to_cores);
+        if (st) return st;
+    }
+    // 2. setup for new admissions
+    std::vector<int> new32, new64;
+    for (Slot &s : slots)
+        if (s.phase == Slot::SETUP) {
+            (s.Q->fp32 ? new32 : new64).push_back(s.idx);
+            s.phase = Slot::SWEEP;
+            any_sweeping = true;
+        }
+    if (!new32.empty()) { int st = launch_setup<float>(new32); if (st) return st; }
+    if (!new64.empty()) { int st = launch_setup<double>(new64); if (st) return st; }
+    // 3. queue sweep rounds up to the lookahead
+    bool launched_any = false;
+    for (;;) {
+        std::vector<int> r32, r64;
+        for (Slot &s : slots) {
+            if (s.phase != Slot::SWEEP || s.stop_seen) continue;
+            const int L = std::max(1, s.Q->opt.lookahead);
+            if (s.launched < s.done + L && s.launched < s.Q->max_sweeps) (s.Q->fp32 ? r32 : r64).push_back(s.idx);
+        }
+        if (r32.empty() && r64.empty()) break;
+        if (!r32.empty()) { int st = launch_sweep<float>(r32); if (st) return st; }
+        if (!r64.empty()) { int st = launch_sweep<double>(r64); if (st) return st; }
+        launched_any = true;
+    }
+    // 4. completions
+    for (Slot &s : slots) {
+        if (s.phase != Slot::CORES) continue;
+        hipError_t q = hipEventQuery(s.ev);
+        if (q == hipErrorNotReady) continue;
+        if (q != hipSuccess) return set_err(TT_EDEVICE, "batch: %s", hipGetErrorString(q));
+        finish_slot(s);
+        if (completed) completed->push_back(s.idx);
+    }
+    // 5. nothing queued that could still report progress: the stream is idle
+    //    once every queued round has run, and the mirrors are final
+    if (any_sweeping && !launched_any) {
+        hipError_t q = hipStreamQuery(stream);
+        if (q != hipErrorNotReady && q != hipSuccess) return set_err(TT_EDEVICE, "batch: %s", hipGetErrorString(q));
+        if (q == hipSuccess) {
+            for (Slot &s : slots) {
+                if (s.phase != Slot::SWEEP) continue;
+                const HostMirror &h = hm[s.idx];
+                const int sd = __atomic_load_n(&h.sweeps_done, __ATOMIC_ACQUIRE);
+                if (sd > s.done) s.done = sd;
+                else if (s.done >= s.launched || s.launched >= s.Q->max_sweeps) s.idle_done = true;
+            }
+        }
+    }
+    return TT_OK;
+}
+
+void Engine::finish_slot(Slot &s)
+{
+    Problem &Q = *s.Q;
+    const ProbState &S = hS[s.idx];
+    int r[TT_MAX_D + 1];
+    for (int k = 0; k <= Q.d; ++k) r[k] = hm[s.idx].r[k];
+    r[0] = r[Q.d] = 1;
+    if (S.err) {
+        Q.status = S.err;
+        Q.ran = false;
+    } else {
+        Q.finalize(S, r);
+    }
+    s.t_done = now_s();
+    Q.time_to_eps = s.t_done - s.t_admit;
+    Q.sweep_launches = 0;
+    Q.sweep_kernel_s = Q.sweep_phase_s = 0;
+    // return the event once no other slot still waits on it
+    hipEvent_t ev = s.ev;
+    s.ev = nullptr;
+    bool shared = false;
+    for (const Slot &o : slots)
+        if (o.ev == ev) { shared = true; break; }
+    if (!shared) ev_free.push_back(ev);
+    s.phase = Slot::DONE;
+}
+
+void Engine::retire(int idx)
+{
+    if (idx < 0 || idx >= cap) return;
+    Slot &s = slots[idx];
+    if (s.phase == Slot::DONE || s.phase == Slot::FAILED) {
+        s = Slot();
+        s.idx = idx;
+    }
+}
+
+bool Engine::idle() const
+{
+    for (const Slot &s : slots)
+        if (s.phase == Slot::SETUP || s.phase == Slot::SWEEP || s.phase == Slot::CORES) return false;
+    return true;
+}
+
+}  // namespace ttc
+
+using namespace ttc;
+
+extern "C" int tt_batch_run(tt_cross_h *hs, int count, void *hip_stream)
+{
+    if (count < 0 || (count > 0 && !hs)) return set_err(TT_EINVAL, "bad batch arguments");
+    if (count == 0) return TT_OK;
+    for (int i = 0; i < count; ++i) {
+        if (!hs[i]) return set_err(TT_EINVAL, "handle %d is NULL", i);
+        for (int j = 0; j < i; ++j)
+            if (hs[j] == hs[i]) return set_err(TT_EINVAL, "handle %d appears twice", i);
+    }
+    for (int i = 0; i < count; ++i) {
+        const int st = hs[i]->p.prepare();
+        if (st) return st;
+    }
+    hipStream_t stream = hip_stream ? (hipStream_t)hip_stream : hs[0]->p.stream;
+    // the handles' own streams must not still be working on these buffers
+    for (int i = 0; i < count; ++i) HIPCHK(hipStreamSynchronize(hs[i]->p.stream));
+    // one engine per thread, kept for later batches (never torn down, so that
+    // nothing is freed after the runtime has shut down at process exit)
+    static thread_local Engine *engp = nullptr;
+    if (!engp) engp = new Engine();
+    Engine &eng = *engp;
+    if (eng.cap < count || eng.stream != stream) {
+        const int st = eng.init(std::max(count, eng.cap), stream);
+        if (st) return st;
+    }
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, stream));
+    std::vector<int> ids(count);
+    for (int i = 0; i < count; ++i) {
+        const int id = eng.admit(&hs[i]->p, nullptr);
+        if (id < 0) return id;
+        ids[i] = id;
+    }
+    int st = TT_OK;
+    while (!eng.idle()) {
+        st = eng.tick(nullptr);
+        if (st) break;
+    }
+    HIPCHK(hipEventRecord(e1, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (int i = 0; i < count; ++i) {
+        hs[i]->p.time_to_eps = ms * 1e-3;
+        eng.retire(ids[i]);
+    }
+    return st;
+}

@@ -35,12 +35,6 @@ int set_err(int code, const char *fmt, ...)
     return code;
 }
 
-#define HIPCHK(expr)                                                                        \
-    do {                                                                                    \
-        hipError_t e_ = (expr);                                                             \
-        if (e_ != hipSuccess)                                                               \
-            return set_err(TT_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
-    } while (0)
 
 // ---------------------------------------------------------------------------
 // Generating function descriptors.
@@ -406,7 +400,9 @@ template <typename V> int Problem::run_impl()
             for (int k = 1; k <= d - 1; ++k)
                 rub[k] = std::min(rc[k], __atomic_load_n(&hm->r[k], __ATOMIC_RELAXED) + (launched - done_known));
     }
-    // ranks of the final sweep come from the host mirror
+    // ranks of the final sweep come from the host mirror; without the stop
+    // flag's release they are read only after the stream has drained
+    if (!__atomic_load_n(&hm->stop, __ATOMIC_ACQUIRE)) HIPCHK(hipStreamSynchronize(stream));
     int ranks_now[TT_MAX_D + 1];
     for (int k = 0; k <= d; ++k) ranks_now[k] = __atomic_load_n(&hm->r[k], __ATOMIC_RELAXED);
     ranks_now[0] = ranks_now[d] = 1;
@@ -417,27 +413,12 @@ template <typename V> int Problem::run_impl()
     // a10: cores by Alg. 4 in FP64
     CoreArgs ca;
     std::memset(&ca, 0, sizeof ca);
-    ca.nk = nk;
-    for (int k = 0; k <= d; ++k) ca.ranks[k] = ranks_now[k];
-    int64_t go = 0;
-    int rb = 0, maxr = 1;
-    for (int u = 0; u < nk; ++u) {
-        const int k = u + 1;
-        const int nr = ranks_now[k - 1] * n[k - 1], rk = ranks_now[k];
-        ca.goff[u] = go;
-        ca.rowblocks[u] = rb;
-        go += (int64_t)nr * rk;
-        rb += (nr + A4W - 1) / A4W;
-        maxr = std::max(maxr, rk);
-    }
-    ca.rowblocks[nk] = rb;
-    ca.goff[nk] = go;
-    const int64_t gd = (int64_t)ranks_now[d - 1] * n[d - 1];
-    cores_len = go + gd;
+    int maxr = 1;
+    for (int k = 1; k <= d - 1; ++k) maxr = std::max(maxr, ranks_now[k]);
+    const int blocks = make_core_args(d, n, ranks_now, ca, cores_len);
     {
         const size_t lc = sizeof(double) * ((size_t)2 * maxr * (maxr + 1) + (size_t)2 * maxr * A4W);
         if (lc > (size_t)lds_limit) return set_err(TT_EINVAL, "rank %d too large for the core kernel", maxr);
-        const int blocks = rb + (int)((gd + A4W - 1) / A4W);
         k_cores<<<blocks, A4W, lc, stream>>>(dP, ca, d_cores);
     }
     HIPCHK(hipGetLastError());
@@ -449,17 +430,7 @@ template <typename V> int Problem::run_impl()
     ProbState S;
     HIPCHK(hipMemcpy(&S, hP.S, sizeof S, hipMemcpyDeviceToHost));
     if (S.err) return set_err(S.err, "device reported error %d", S.err);
-    for (int k = 0; k <= d; ++k) ranks[k] = ranks_now[k];
-    rms = S.rms;
-    tau = S.tau;
-    sweeps = S.sweeps;
-    pivoted = (int64_t)S.pivoted;
-    evaluated = 0;
-    for (int k = 1; k <= d - 1; ++k)
-        evaluated += (int64_t)ranks[k - 1] * n[k - 1] * (int64_t)n[k] * ranks[k + 1];
-    for (int u = 0; u < nk; ++u) last_best[u] = S.last_best[u];
-    sweep_alg_bytes = (double)S.alg_bytes;
-    new_entries = (double)S.new_entries;
+    finalize(S, ranks_now);
     sweep_launches = 0;
     sweep_kernel_s = sweep_phase_s = 0;
     if (prof) {
@@ -475,13 +446,33 @@ template <typename V> int Problem::run_impl()
             sweep_phase_s = c * 1e-3;
         }
     }
-    for (int j = 0; j < d; ++j) i0[j] = S.i0[j];
-    ran = true;
-    status = S.capped ? TT_NOT_CONVERGED : TT_OK;
     return status;
 }
 
-int Problem::run()
+// Results of a completed solve from its final device state.
+void Problem::finalize(const ProbState &S, const int *ranks_now)
+{
+    for (int k = 0; k <= d; ++k) ranks[k] = ranks_now[k];
+    CoreArgs ca;
+    (void)make_core_args(d, n, ranks, ca, cores_len);
+    rms = S.rms;
+    tau = S.tau;
+    sweeps = S.sweeps;
+    pivoted = (int64_t)S.pivoted;
+    evaluated = 0;
+    for (int k = 1; k <= d - 1; ++k)
+        evaluated += (int64_t)ranks[k - 1] * n[k - 1] * (int64_t)n[k] * ranks[k + 1];
+    for (int u = 0; u < d - 1; ++u) last_best[u] = S.last_best[u];
+    sweep_alg_bytes = (double)S.alg_bytes;
+    new_entries = (double)S.new_entries;
+    for (int j = 0; j < d; ++j) i0[j] = S.i0[j];
+    ran = true;
+    status = S.capped ? TT_NOT_CONVERGED : TT_OK;
+}
+
+// Geometry and device buffers for the current options (kept across runs
+// while the options that shape them are unchanged).
+int Problem::prepare()
 {
     resolve_geometry();
     if (allocated && (alloc_fp32 != fp32 || alloc_rmax != opt.r_max || alloc_tr != opt.tile_rows ||
@@ -499,6 +490,13 @@ int Problem::run()
     alloc_tc = opt.tile_cols;
     std::memcpy(alloc_grid, grid, sizeof grid);
     ran = false;
+    return TT_OK;
+}
+
+int Problem::run()
+{
+    int st = prepare();
+    if (st != TT_OK) return st;
     st = fp32 ? run_impl<float>() : run_impl<double>();
     status = st;
     return st;
@@ -511,9 +509,6 @@ int Problem::run()
 // ===========================================================================
 extern "C" {
 
-struct tt_cross_s {
-    Problem p;
-};
 
 const char *tt_last_error(void) { return g_err.c_str(); }
 

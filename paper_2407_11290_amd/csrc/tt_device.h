@@ -215,6 +215,16 @@ struct HostMirror {                // fine-grained host memory, written by the d
     int r[TT_MAX_D + 1];
 };
 
+// Per-run inputs of a problem solved inside a batch (a single solve passes
+// them as kernel arguments instead).
+struct RunDev {
+    uint64_t seed;
+    double eps;
+    int ns;                       // samples
+    double *vals;                 // ns sample values
+    double *cores;                // output cores
+};
+
 struct ProbDev {
     int d, nk;                    // modes, unfoldings (= d-1)
     int r_max, rcap;
@@ -224,6 +234,7 @@ struct ProbDev {
     KDev kd[TT_MAX_D];
     ProbState *S;
     HostMirror *hm;               // device alias of the host mirror
+    RunDev run;
 };
 
 struct SweepArgs {

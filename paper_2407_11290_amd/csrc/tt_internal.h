@@ -13,6 +13,13 @@ namespace ttc {
 
 int set_err(int code, const char *fmt, ...);
 
+#define HIPCHK(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return set_err(TT_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
 struct FnHost {
     FnDev dev;
     std::vector<double> table;     // separable-sum factors (host copy)
@@ -68,8 +75,15 @@ struct Problem {
     size_t device_bytes() const;
     void resolve_geometry();
     int allocate();
+    int prepare();
+    void finalize(const ProbState &S, const int *ranks_now);
     int run();
     template <typename V> int run_impl();
 };
 
 }  // namespace ttc
+
+// The object behind a tt_cross_h.
+struct tt_cross_s {
+    ttc::Problem p;
+};

@@ -308,12 +308,12 @@ __device__ inline void sweep_shape(const ProbDev *P, const KSweep *ks, int nk, S
 // Fixed grid striding over work units: first the new-entry tiles (one per
 // workgroup), then the stored tiles four at a time (one per wavefront).
 template <typename V>
-__global__ void __launch_bounds__(NT) k_sweep(const ProbDev *__restrict__ P, SweepArgs a)
+__device__ void sweep_body(const ProbDev *__restrict__ P, int nk, int blk, int nblk)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const ProbState *S = P->S;
     if (S->stop) return;
-    const int nk = a.nk, tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
     __shared__ KSweep ks[TT_MAX_D];
     __shared__ SweepShape sh;
     if (tid < nk) ks[tid] = S->ks[tid];
@@ -322,7 +322,7 @@ __global__ void __launch_bounds__(NT) k_sweep(const ProbDev *__restrict__ P, Swe
     __syncthreads();
     const int nnew = sh.noff[nk], nst = sh.soff[nk];
     const int units = nnew + (nst + NT / 64 - 1) / (NT / 64);
-    for (int t = blockIdx.x; t < units; t += gridDim.x) {
+    for (int t = blk; t < units; t += nblk) {
         double bv = -1.0, bs = 0.0;
         uint64_t bk = ~0ULL;
         if (t < nnew) {
@@ -364,6 +364,12 @@ __global__ void __launch_bounds__(NT) k_sweep(const ProbDev *__restrict__ P, Swe
             }
         }
     }
+}
+
+template <typename V>
+static __global__ void __launch_bounds__(NT) k_sweep(const ProbDev *__restrict__ P, SweepArgs a)
+{
+    sweep_body<V>(P, a.nk, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -413,13 +419,13 @@ __device__ inline double fp64_check_wave(const ProbDev *P, const KDev &K, int u,
 constexpr int NTC = 512;
 
 template <typename V>
-__global__ void __launch_bounds__(NTC) k_commit(const ProbDev *__restrict__ P, SweepArgs a)
+__device__ void commit_body(const ProbDev *__restrict__ P, int sweep)
 {
     ProbState *S = P->S;
     if (S->stop) return;
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
     constexpr int NW = NTC / 64;
-    const int nk = a.nk, d = P->d, par = a.sweep & 1;
+    const int nk = P->nk, d = P->d, par = sweep & 1;
     __shared__ KSweep ks[TT_MAX_D];
     __shared__ double s_wv[TT_MAX_D], s_wsv[TT_MAX_D];
     __shared__ uint64_t s_wk[TT_MAX_D];
@@ -481,7 +487,7 @@ __global__ void __launch_bounds__(NTC) k_commit(const ProbDev *__restrict__ P, S
             }
         }
         if (lane == 0) {
-            if (a.sweep < P->hist_cap) K.hist[a.sweep] = e;
+            if (sweep < P->hist_cap) K.hist[sweep] = e;
             S->last_best[u] = e;
             if (over && !propose) S->capped = 1;
             if (propose && bs == 0.0) S->err = TT_ESINGULAR;
@@ -531,7 +537,7 @@ __global__ void __launch_bounds__(NTC) k_commit(const ProbDev *__restrict__ P, S
         }
         const int stop = (!any || S->err) ? 1 : 0;
         S->stop = stop;
-        S->sweeps = a.sweep + 1;
+        S->sweeps = sweep + 1;
         HostMirror *hm = P->hm;
         if (stop) {
             // final sweep: ranks and status must be visible before the count
@@ -539,34 +545,46 @@ __global__ void __launch_bounds__(NTC) k_commit(const ProbDev *__restrict__ P, S
             hm->err = S->err;
             hm->stop = stop;
             __threadfence_system();
-            __hip_atomic_store(&hm->sweeps_done, a.sweep + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&hm->sweeps_done, sweep + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
         } else {
             for (int j = 0; j <= d; ++j)
                 __hip_atomic_store(&hm->r[j], s_rnew[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            __hip_atomic_store(&hm->sweeps_done, a.sweep + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&hm->sweeps_done, sweep + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         }
     }
+}
+
+template <typename V>
+static __global__ void __launch_bounds__(NTC) k_commit(const ProbDev *__restrict__ P, SweepArgs a)
+{
+    commit_body<V>(P, a.sweep);
 }
 
 // ---------------------------------------------------------------------------
 // Setup: samples, rms, first pivot, initial superblocks.
 // ---------------------------------------------------------------------------
 // Evaluates the sample entries and clears the pivot maps of every unfolding.
-__global__ void __launch_bounds__(NT) k_samples(const ProbDev *__restrict__ P, uint64_t seed, int ns,
-                                                  double *vals)
+__device__ inline void samples_body(const ProbDev *__restrict__ P, uint64_t seed, int ns, double *vals, int blk,
+                                    int nblk)
 {
-    const int s = blockIdx.x * NT + threadIdx.x;
+    const int s = blk * NT + threadIdx.x;
     const int d = P->d;
     for (int u = 0; u < P->nk; ++u) {
         const KDev &K = P->kd[u];
-        for (int i = s; i < K.rowcap; i += gridDim.x * NT) K.rpiv[i] = 0;
-        for (int j = s; j < K.colcap; j += gridDim.x * NT) K.cpiv[j] = 0;
+        for (int i = s; i < K.rowcap; i += nblk * NT) K.rpiv[i] = 0;
+        for (int j = s; j < K.colcap; j += nblk * NT) K.cpiv[j] = 0;
     }
     if (s >= ns) return;
     int idx[TT_MAX_D];
     for (int j = 0; j < d; ++j)
         idx[j] = (int)(sm64_at(seed, (uint64_t)s * d + j) % (uint64_t)P->F.n[j]);
     vals[s] = fn_value<double>(P->F, idx);
+}
+
+static __global__ void __launch_bounds__(NT) k_samples(const ProbDev *__restrict__ P, uint64_t seed, int ns,
+                                                  double *vals)
+{
+    samples_body(P, seed, ns, vals, blockIdx.x, gridDim.x);
 }
 
 // Pairwise sum of v[lo..lo+c) squared (c a power of two; entries past ns are
@@ -611,8 +629,7 @@ __device__ inline double chunk_pairwise_sumsq(const double *v, int lo, int c, in
 }
 
 template <typename V>
-__global__ void __launch_bounds__(NT) k_setup(const ProbDev *__restrict__ P, uint64_t seed, int ns,
-                                                const double *vals, double eps)
+__device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns, const double *vals, double eps)
 {
     ProbState *S = P->S;
     const int tid = threadIdx.x, d = P->d;
@@ -716,16 +733,23 @@ __global__ void __launch_bounds__(NT) k_setup(const ProbDev *__restrict__ P, uin
     }
 }
 
+template <typename V>
+static __global__ void __launch_bounds__(NT) k_setup(const ProbDev *__restrict__ P, uint64_t seed, int ns,
+                                                const double *vals, double eps)
+{
+    setup_body<V>(P, seed, ns, vals, eps);
+}
+
 // E = X on the initial superblocks (one prefix, one suffix: the first pivot's).
 template <typename V>
-__global__ void __launch_bounds__(NT) k_init_eval(const ProbDev *__restrict__ P)
+__device__ void init_eval_body(const ProbDev *__restrict__ P, int u, int blk, int nblk)
 {
     const ProbState *S = P->S;
     if (S->stop) return;
-    const int u = blockIdx.y, k = u + 1, d = P->d;
+    const int k = u + 1, d = P->d;
     const KDev &K = P->kd[u];
     const int64_t tot = (int64_t)K.nk * K.nk1;
-    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < tot; e += (int64_t)gridDim.x * NT) {
+    for (int64_t e = (int64_t)blk * NT + threadIdx.x; e < tot; e += (int64_t)nblk * NT) {
         const int i = (int)(e / K.nk1), j = (int)(e - (int64_t)i * K.nk1);
         int idx[TT_MAX_D];
         for (int jj = 0; jj < d; ++jj) idx[jj] = S->i0[jj];
@@ -733,6 +757,12 @@ __global__ void __launch_bounds__(NT) k_init_eval(const ProbDev *__restrict__ P)
         idx[k] = j;
         ((V *)K.E)[(int64_t)i * K.colcap + j] = fn_value<V>(P->F, idx);
     }
+}
+
+template <typename V>
+static __global__ void __launch_bounds__(NT) k_init_eval(const ProbDev *__restrict__ P)
+{
+    init_eval_body<V>(P, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -755,10 +785,33 @@ struct CoreArgs {
 
 constexpr int A4W = 64;         // rows per workgroup (one wavefront)
 
-__global__ void __launch_bounds__(A4W) k_cores(const ProbDev *__restrict__ P, CoreArgs a, double *G)
+// Offsets of the cores and their workgroup ranges for final ranks r[0..d];
+// returns the number of workgroups (row blocks of G_1..G_{d-1}, then G_d).
+__host__ __device__ inline int make_core_args(int d, const int *n, const int *r, CoreArgs &a, int64_t &len)
+{
+    a.nk = d - 1;
+    for (int k = 0; k <= d; ++k) a.ranks[k] = r[k];
+    int64_t go = 0;
+    int rb = 0;
+    for (int u = 0; u < d - 1; ++u) {
+        const int k = u + 1;
+        const int nr = r[k - 1] * n[k - 1], rk = r[k];
+        a.goff[u] = go;
+        a.rowblocks[u] = rb;
+        go += (int64_t)nr * rk;
+        rb += (nr + A4W - 1) / A4W;
+    }
+    a.rowblocks[d - 1] = rb;
+    a.goff[d - 1] = go;
+    const int64_t gd = (int64_t)r[d - 1] * n[d - 1];
+    len = go + gd;
+    return rb + (int)((gd + A4W - 1) / A4W);
+}
+
+__device__ void cores_body(const ProbDev *__restrict__ P, const CoreArgs &a, double *G, int bid)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int bid = blockIdx.x, lane = threadIdx.x, d = P->d;
+    const int lane = threadIdx.x, d = P->d;
     if (bid >= a.rowblocks[a.nk]) {
         const KDev &K = P->kd[d - 2];
         const int rd = a.ranks[d - 1], nd = P->F.n[d - 1];
@@ -833,6 +886,87 @@ __global__ void __launch_bounds__(A4W) k_cores(const ProbDev *__restrict__ P, Co
     }
 }
 
+static __global__ void __launch_bounds__(A4W) k_cores(const ProbDev *__restrict__ P, CoreArgs a, double *G)
+{
+    cores_body(P, a, G, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches: many independent problems in one launch.  Their
+// descriptors lie contiguously in device memory; the kernel arguments name
+// the problems of the launch and, for the grid-strided kernels, the range of
+// workgroups each one gets.  Every problem runs the same bodies as a single
+// solve, so its results are the same bit for bit.
+// ---------------------------------------------------------------------------
+constexpr int MAXB = 512;       // problems per batched launch
+
+struct BatchMap {
+    int na;                     // problems in this launch
+    int boff[MAXB + 1];         // problem i owns workgroups [boff[i], boff[i+1])
+    uint16_t p[MAXB];           // index of problem i in the descriptor array
+};
+
+__device__ inline int batch_find(const BatchMap &bm, int b)
+{
+    int lo = 0, hi = bm.na;     // boff[lo] <= b < boff[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (bm.boff[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+static __global__ void __launch_bounds__(NT) k_samples_b(const ProbDev *__restrict__ Pa, BatchMap bm)
+{
+    const ProbDev *P = Pa + bm.p[blockIdx.y];
+    samples_body(P, P->run.seed, P->run.ns, P->run.vals, blockIdx.x, gridDim.x);
+}
+
+template <typename V>
+static __global__ void __launch_bounds__(NT) k_setup_b(const ProbDev *__restrict__ Pa, BatchMap bm)
+{
+    const ProbDev *P = Pa + bm.p[blockIdx.x];
+    setup_body<V>(P, P->run.seed, P->run.ns, P->run.vals, P->run.eps);
+}
+
+template <typename V>
+static __global__ void __launch_bounds__(NT) k_init_eval_b(const ProbDev *__restrict__ Pa, BatchMap bm)
+{
+    const ProbDev *P = Pa + bm.p[blockIdx.z];
+    if ((int)blockIdx.y >= P->nk) return;
+    init_eval_body<V>(P, blockIdx.y, blockIdx.x, gridDim.x);
+}
+
+template <typename V>
+static __global__ void __launch_bounds__(NT) k_sweep_b(const ProbDev *__restrict__ Pa, BatchMap bm)
+{
+    const int i = batch_find(bm, blockIdx.x);
+    const ProbDev *P = Pa + bm.p[i];
+    sweep_body<V>(P, P->nk, blockIdx.x - bm.boff[i], bm.boff[i + 1] - bm.boff[i]);
+}
+
+template <typename V>
+static __global__ void __launch_bounds__(NTC) k_commit_b(const ProbDev *__restrict__ Pa, BatchMap bm)
+{
+    const ProbDev *P = Pa + bm.p[blockIdx.x];
+    commit_body<V>(P, P->S->sweeps);
+}
+
+// Cores of every problem from its final ranks (those of its last commit).
+static __global__ void __launch_bounds__(A4W) k_cores_b(const ProbDev *__restrict__ Pa, BatchMap bm)
+{
+    const int i = batch_find(bm, blockIdx.x);
+    const ProbDev *P = Pa + bm.p[i];
+    const ProbState *S = P->S;
+    int r[TT_MAX_D + 1];
+    for (int k = 0; k <= P->d; ++k) r[k] = S->r[S->sweeps & 1][k];
+    CoreArgs a;
+    int64_t len;
+    make_core_args(P->d, P->F.n, r, a, len);
+    cores_body(P, a, P->run.cores, blockIdx.x - bm.boff[i]);
+}
+
 // ---------------------------------------------------------------------------
 // Evaluation helpers.
 // ---------------------------------------------------------------------------
@@ -844,7 +978,7 @@ struct TTArgs {
 };
 
 // One wavefront per multi-index; lane b accumulates entry b of the row vector.
-__global__ void __launch_bounds__(NT) k_tt_eval(TTArgs a, const double *__restrict__ G, int64_t m,
+static __global__ void __launch_bounds__(NT) k_tt_eval(TTArgs a, const double *__restrict__ G, int64_t m,
                                                   const int *__restrict__ idx, double *__restrict__ out)
 {
     const int lane = threadIdx.x & 63;
@@ -868,7 +1002,7 @@ __global__ void __launch_bounds__(NT) k_tt_eval(TTArgs a, const double *__restri
 }
 
 template <typename V>
-__global__ void __launch_bounds__(NT) k_fn_eval(FnDev F, int64_t m, const int *__restrict__ idx,
+static __global__ void __launch_bounds__(NT) k_fn_eval(FnDev F, int64_t m, const int *__restrict__ idx,
                                                   double *__restrict__ out)
 {
     const int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x;
@@ -878,14 +1012,14 @@ __global__ void __launch_bounds__(NT) k_fn_eval(FnDev F, int64_t m, const int *_
     out[t] = (double)fn_value<V>(F, ix);
 }
 
-__global__ void __launch_bounds__(NT) k_gen_idx(int d, TTArgs a, uint64_t seed, int64_t m, int *idx)
+static __global__ void __launch_bounds__(NT) k_gen_idx(int d, TTArgs a, uint64_t seed, int64_t m, int *idx)
 {
     const int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x;
     if (t >= m) return;
     for (int j = 0; j < d; ++j) idx[t * d + j] = (int)(sm64_at(seed, (uint64_t)t * d + j) % (uint64_t)a.n[j]);
 }
 
-__global__ void __launch_bounds__(NT) k_err_partial(int64_t m, const double *__restrict__ x,
+static __global__ void __launch_bounds__(NT) k_err_partial(int64_t m, const double *__restrict__ x,
                                                       const double *__restrict__ y, double *part)
 {
     double num = 0.0, den = 0.0;

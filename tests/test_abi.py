@@ -81,3 +81,37 @@ def test_run_fails_loudly_without_a_gpu():
     with pytest.raises(_lib.TTError) as e:
         t.run()
     assert e.value.code == _lib.EDEVICE
+
+
+def test_batch_rejects_bad_arguments_before_any_device_work():
+    from paper_2407_11290_amd.api import TTCross, batch_run
+    a = TTCross([8, 8, 8], 1e-8, _lib.FN_HILBERT)
+    b = TTCross([8, 8], 1e-8, _lib.FN_HILBERT)
+    with pytest.raises(_lib.TTError) as e:
+        batch_run([a, b, a])
+    assert e.value.code == _lib.EINVAL and "twice" in _lib.last_error()
+    L = _lib.load()
+    assert L.tt_batch_run(None, 3, None) == _lib.EINVAL
+    assert L.tt_batch_run(None, 0, None) == _lib.OK
+    a.close()
+    b.close()
+
+
+def test_workload_lists_are_seeded_and_shaped_as_specified():
+    from paper_2407_11290_amd.workloads import FN_BIMAXWELL, FN_HILBERT, batch_mix, served_trace
+    a, b = batch_mix(), batch_mix()
+    assert len(a) == 512 and [p.n for p in a] == [p.n for p in b] and [p.params for p in a] == [p.params for p in b]
+    for i, p in enumerate(a):
+        assert 3 <= p.d <= 6 and len(set(p.n)) == 1 and p.n[0] in (16, 32, 64, 128)
+        assert p.seed == i and p.eps == 1e-6
+        if i % 2 == 0:
+            assert p.fn_id == FN_HILBERT and 0.0 <= p.params[0] <= 4.0
+        else:
+            assert p.fn_id == FN_BIMAXWELL and len(p.params) == 11
+            for m in range(2):
+                rho, ux, uy, uz, T = p.params[5 * m: 5 * m + 5]
+                assert 0.5 <= rho <= 2.0 and 0.5 <= T <= 2.0 and all(-2 <= x <= 2 for x in (ux, uy, uz))
+    t = served_trace(count=200)
+    arr = [p.arrival_s for p in t]
+    assert all(x < y for x, y in zip(arr, arr[1:]))
+    assert {p.eps for p in t} <= {1e-4, 1e-8} and all(4 <= p.d <= 6 for p in t)
