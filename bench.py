@@ -129,6 +129,103 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_serve(args):
+    """Served trace: requests d in {4,5,6}, n in {32,64,128,256}, eps in
+    {1e-4, 1e-8} (FP32 / FP64 sweeps by the precision policy), half Hilbert,
+    half bi-Maxwellian, rank cap 32, two subtensor blocks per mode.  First the
+    whole trace at once (capacity), then Poisson arrivals at rate_frac of that
+    capacity (latency = completion - arrival, queueing included), then the
+    first requests one at a time through the single-solve path."""
+    from paper_2407_11290_amd.api import Server, TTCross
+    from paper_2407_11290_amd.workloads import served_trace
+    N = args.requests
+    specs = served_trace(count=N)
+    srv = Server(int(args.budget_gib * (1 << 30)), max_slots=256, r_max=32, grid=2)
+
+    def run_all(arrivals):
+        t0 = time.perf_counter()
+        tickets = []
+        for p, a in zip(specs, arrivals):
+            while True:
+                dt = t0 + a - time.perf_counter()
+                if dt <= 0:
+                    break
+                time.sleep(min(dt, 0.001))
+            tickets.append(srv.submit(p.n, p.eps, p.fn_id, p.params, seed=p.seed))
+        lat, work, st = [], 0, {}
+        for t in tickets:
+            code, l = srv.wait(t)
+            s, _ = srv.result(t)
+            srv.release(t)
+            lat.append(l)
+            work += s["evaluated"] + s["pivoted"]
+            st[code] = st.get(code, 0) + 1
+        return time.perf_counter() - t0, lat, work, st
+
+    # warm-up: one request of every shape, so that the pool holds its buffers
+    seen, warm = set(), []
+    for p in specs:
+        key = (tuple(p.n), p.eps >= 1e-6)
+        if key not in seen:
+            seen.add(key)
+            warm.append(srv.submit(p.n, p.eps, p.fn_id, p.params, seed=p.seed))
+    for t in warm:
+        srv.wait(t)
+        srv.release(t)
+    print(f"bench: warm-up {len(warm)} shapes, pool {srv.stats()['pool_bytes'] / 2**30:.1f} GiB",
+          file=sys.stderr, flush=True)
+    cap_s, cap_lat, cap_work, cap_st = run_all([0.0] * N)
+    capacity = N / cap_s
+    print(f"bench: closed loop {N} requests in {cap_s:.2f} s ({capacity:.0f} solves/s)", file=sys.stderr, flush=True)
+    def pct(v, q):
+        v = sorted(v)
+        return v[min(len(v) - 1, int(q * len(v)))] * 1e3
+
+    sweep = []
+    for frac in (0.25, 0.5, 1.0, 1.25):
+        r = frac * capacity
+        s_, l_, _w, _st = run_all([p.arrival_s for p in served_trace(count=N, rate_hz=r)])
+        sweep.append({"rate_frac": frac, "rate_per_s": r, "solves_per_s": N / s_, "p50_ms": pct(l_, 0.5),
+                      "p99_ms": pct(l_, 0.99)})
+        print(f"bench: open loop at {frac:.2f} x capacity: p50 {pct(l_, 0.5):.2f} ms p99 {pct(l_, 0.99):.2f} ms",
+              file=sys.stderr, flush=True)
+    rate = args.rate_frac * capacity
+    arrivals = [p.arrival_s for p in served_trace(count=N, rate_hz=rate)]
+    open_s, lat, work, st = run_all(arrivals)
+    lat_ms = sorted(x * 1e3 for x in lat)
+    print(f"bench: open loop at {rate:.0f}/s done in {open_s:.2f} s", file=sys.stderr, flush=True)
+    srv_stats = srv.stats()
+    srv.close()
+    # one at a time: the first requests through the single-solve path, each on
+    # a handle whose buffers already exist (allocation is not timed)
+    M = min(args.alone, N)
+    hs = [TTCross(p.n, p.eps, p.fn_id, p.params, seed=p.seed, r_max=32, grid=p.grid) for p in specs[:M]]
+    for h in hs:
+        h.run()
+    t1 = time.perf_counter()
+    for h in hs:
+        h.run()
+    alone_s = time.perf_counter() - t1
+    for h in hs:
+        h.close()
+    out = {
+        "metric": METRIC, "value": work / open_s, "unit": "entries/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": open_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"serve_poisson_{N}req_d4-6_n32-256_eps1e-4or1e-8", "requests": N,
+                   "rate_per_s": rate, "rate_frac_of_capacity": args.rate_frac, "budget_gib": args.budget_gib},
+        "latency_ms": {"p50": lat_ms[len(lat_ms) // 2], "p99": lat_ms[min(len(lat_ms) - 1, int(0.99 * len(lat_ms)))],
+                       "max": lat_ms[-1]},
+        "solves_per_s": N / open_s, "capacity_solves_per_s": capacity,
+        "closed_loop_entries_per_s": cap_work / cap_s,
+        "lambda_sweep": sweep,
+        "one_at_a_time": {"requests": M, "s": alone_s, "solves_per_s": M / alone_s},
+        "statuses": {str(k): v for k, v in sorted(st.items())},
+        "server": srv_stats,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,9 +233,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="hilbert6d", choices=["hilbert6d", "batch512"],
+    ap.add_argument("--workload", default="hilbert6d", choices=["hilbert6d", "batch512", "serve"],
                     help="hilbert6d: the single-solve benchmark line; batch512: the mixed 512-problem "
-                         "batch, solved together and one at a time")
+                         "batch, solved together and one at a time; serve: a Poisson-arrival trace "
+                         "through the continuous-batching server")
+    ap.add_argument("--requests", type=int, default=2000, help="serve: trace length")
+    ap.add_argument("--rate-frac", type=float, default=0.8, help="serve: arrival rate / measured capacity")
+    ap.add_argument("--budget-gib", type=float, default=64.0, help="serve: HBM budget of the server")
+    ap.add_argument("--alone", type=int, default=200, help="serve: requests timed one at a time")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain copy kernel (out = -in, FP64) over this many MiB, five times; "
                          "its FETCH_SIZE/WRITE_SIZE counters scale the search kernel's")
@@ -163,6 +265,8 @@ def main():
     from paper_2407_11290_amd.api import TTCross
     if args.workload == "batch512":
         return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     handles = [TTCross(N, EPS, FN_HILBERT, seed=s, precision=PREC_FP64, grid=GRID) for s in SEEDS]
     probes = [TTCross(N, EPS, FN_HILBERT, seed=s, precision=PREC_FP64, grid=GRID, profile=1) for s in SEEDS]

@@ -203,6 +203,62 @@ void tt_cross_destroy(tt_cross_h h);
  * stats.  Errors: TT_EINVAL (bad arguments), TT_EDEVICE, TT_ENOMEM. */
 int tt_batch_run(tt_cross_h *hs, int count, void *hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * Served solves: continuous batching on one GPU.
+ *
+ * A server owns a stream, a batch engine (as in tt_batch_run) and a pool of
+ * problem objects with their device buffers.  Requests are submitted at any
+ * time from any thread.  A server thread admits them in arrival order when an
+ * engine slot is free and a problem object of the request's shape (modes,
+ * subtensor grid, sweep precision, rank cap) is idle or fits within
+ * hbm_budget bytes.  To make room it evicts idle objects of other shapes.
+ * Admitted requests join the search rounds of those already running.  Each
+ * request is solved exactly as tt_cross_run would solve it with the server's
+ * options and the request's seed.  When it ends, its stats and cores are
+ * copied to the request and its problem object returns to the pool.
+ * ------------------------------------------------------------------------- */
+typedef struct tt_server_s *tt_server_h;
+
+typedef struct {
+    int64_t submitted, completed, queued, running;
+    int64_t pool_bytes;     /* device bytes held by pooled problem objects */
+    int64_t pool_objects;
+    int64_t allocations;    /* problem objects created so far */
+} tt_server_stats;
+
+/* opt: options applied to every request (r_max, grid, precision, n_samples,
+ * lookahead; seed and stream are ignored).  NULL gives the defaults with
+ * r_max = 32 and two subtensor blocks per mode.  max_slots bounds the solves
+ * in flight.  Returns NULL on bad arguments or when no GPU can be used. */
+tt_server_h tt_server_create(size_t hbm_budget, int max_slots, const tt_options *opt);
+
+/* Queue one request (arguments as in tt_cross_create, plus its sample seed).
+ * Functions that need a factor table (TT_FN_SEPSUM) are not served.  Returns
+ * TT_OK and the ticket, or an error for a request that can never run. */
+int tt_server_submit(tt_server_h s, int d, const int32_t *n, double eps, int fn_id, const double *params,
+                     int nparams, uint64_t seed, uint64_t *ticket);
+
+/* 1 when the request has finished, 0 while queued or running, < 0 on error. */
+int tt_server_poll(tt_server_h s, uint64_t ticket);
+
+/* Block until the request finishes.  latency_s (may be NULL) receives
+ * completion minus submission time, queueing included.  Returns the request's
+ * status (TT_OK, TT_NOT_CONVERGED, or an error such as TT_ENOMEM when it needs
+ * more than the whole budget). */
+int tt_server_wait(tt_server_h s, uint64_t ticket, double *latency_s);
+
+/* Stats and cores (layout as tt_cross_get_cores) of a finished request;
+ * either pointer may be NULL.  Returns the number of doubles of the cores. */
+int64_t tt_server_result(tt_server_h s, uint64_t ticket, tt_stats *st, double *cores, int64_t cap);
+
+/* Forget a finished request. */
+int tt_server_release(tt_server_h s, uint64_t ticket);
+
+int tt_server_get_stats(tt_server_h s, tt_server_stats *st);
+
+/* Stops the server thread after the solves in flight and frees everything. */
+void tt_server_destroy(tt_server_h s);
+
 /* Message for the last error on the calling thread (empty if none). */
 const char *tt_last_error(void);
 

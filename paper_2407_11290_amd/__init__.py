@@ -10,7 +10,7 @@ from ._lib import (EBUSY, EDEVICE, EFN, EINVAL, ENOMEM, ESINGULAR, ESTATE, FN_BI
 
 
 def __getattr__(name):
-    if name in ("TTCross", "fn_eval", "default_options", "batch_run"):
+    if name in ("TTCross", "fn_eval", "default_options", "batch_run", "Server"):
         from . import api
         return getattr(api, name)
     raise AttributeError(name)

@@ -57,6 +57,11 @@ class Stats(C.Structure):
     ]
 
 
+class ServerStats(C.Structure):
+    _fields_ = [(name, C.c_int64) for name in ("submitted", "completed", "queued", "running", "pool_bytes",
+                                                "pool_objects", "allocations")]
+
+
 # name -> (restype, argtypes); every function declared in include/tt_cross.h
 SIGNATURES = {
     "tt_options_default": (None, [C.POINTER(Options)]),
@@ -75,6 +80,15 @@ SIGNATURES = {
                              C.c_int64, C.c_void_p, C.c_void_p, C.c_int]),
     "tt_cross_destroy": (None, [C.c_void_p]),
     "tt_batch_run": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_void_p]),
+    "tt_server_create": (C.c_void_p, [C.c_size_t, C.c_int, C.POINTER(Options)]),
+    "tt_server_submit": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int32), C.c_double, C.c_int,
+                                   C.POINTER(C.c_double), C.c_int, C.c_uint64, C.POINTER(C.c_uint64)]),
+    "tt_server_poll": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "tt_server_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_double)]),
+    "tt_server_result": (C.c_int64, [C.c_void_p, C.c_uint64, C.POINTER(Stats), C.c_void_p, C.c_int64]),
+    "tt_server_release": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "tt_server_get_stats": (C.c_int, [C.c_void_p, C.POINTER(ServerStats)]),
+    "tt_server_destroy": (None, [C.c_void_p]),
     "tt_last_error": (C.c_char_p, []),
 }
 

@@ -46,6 +46,18 @@ def fn_eval(fn_id, n, idx, params=None):
     return out
 
 
+def _stats_dict(s, d):
+    return {
+        "evaluated": s.evaluated, "pivoted": s.pivoted, "samples": s.samples, "sweeps": s.sweeps,
+        "precision_used": s.precision_used, "status": s.status,
+        "ranks": list(s.ranks)[: d + 1], "rms": s.rms, "tau": s.tau,
+        "time_to_eps_s": s.time_to_eps_s, "last_best": list(s.last_best)[: max(d - 1, 0)],
+        "sweep_launches": s.sweep_launches, "sweep_kernel_s": s.sweep_kernel_s,
+        "sweep_alg_bytes": s.sweep_alg_bytes,
+        "new_entries": s.new_entries, "sweep_phase_s": s.sweep_phase_s,
+    }
+
+
 class TTCross:
     """One cross approximation problem (a tt_cross_h handle)."""
 
@@ -131,15 +143,7 @@ class TTCross:
     def stats(self):
         s = Stats()
         check(load().tt_cross_get_stats(self.h, C.byref(s)))
-        return {
-            "evaluated": s.evaluated, "pivoted": s.pivoted, "samples": s.samples, "sweeps": s.sweeps,
-            "precision_used": s.precision_used, "status": s.status,
-            "ranks": list(s.ranks)[: self.d + 1], "rms": s.rms, "tau": s.tau,
-            "time_to_eps_s": s.time_to_eps_s, "last_best": list(s.last_best)[: self.d - 1],
-            "sweep_launches": s.sweep_launches, "sweep_kernel_s": s.sweep_kernel_s,
-            "sweep_alg_bytes": s.sweep_alg_bytes,
-            "new_entries": s.new_entries, "sweep_phase_s": s.sweep_phase_s,
-        }
+        return _stats_dict(s, self.d)
 
     def tt_eval(self, idx):
         """TT values at multi-indices: numpy (m, d) int32 on the host, or an
@@ -175,3 +179,68 @@ def batch_run(problems, stream=None):
         p.status = p.stats()["status"]
         out.append(p.status)
     return out
+
+
+class Server:
+    """Continuous-batching server (tt_server_*): submit requests at any time,
+    wait for them, read their stats and cores."""
+
+    def __init__(self, hbm_budget, max_slots=256, r_max=32, grid=2, precision=_lib.PREC_AUTO,
+                 n_samples=16384, lookahead=2):
+        L = load()
+        o = default_options()
+        o.r_max = r_max
+        o.precision = precision
+        o.n_samples = n_samples
+        o.lookahead = lookahead
+        for j in range(_lib.TT_MAX_D):
+            o.grid[j] = int(grid)
+        self.h = L.tt_server_create(int(hbm_budget), int(max_slots), C.byref(o))
+        if not self.h:
+            raise _lib.TTError(_lib.EDEVICE, _lib.last_error())
+        self._d = {}
+
+    def submit(self, n, eps, fn_id, params=None, seed=0):
+        n = _i32(n)
+        pp, npar, _keep = _params_ptr(params)
+        t = C.c_uint64()
+        check(load().tt_server_submit(self.h, n.size, n.ctypes.data_as(C.POINTER(C.c_int32)), float(eps), fn_id,
+                                      pp, npar, seed, C.byref(t)))
+        self._d[t.value] = int(n.size)
+        return t.value
+
+    def poll(self, ticket):
+        return check(load().tt_server_poll(self.h, ticket))
+
+    def wait(self, ticket):
+        """(status, latency in seconds from submission to completion)."""
+        lat = C.c_double()
+        st = check(load().tt_server_wait(self.h, ticket, C.byref(lat)))
+        return st, lat.value
+
+    def result(self, ticket):
+        s = Stats()
+        m = check(load().tt_server_result(self.h, ticket, C.byref(s), None, 0))
+        cores = np.zeros(m, dtype=np.float64)
+        check(load().tt_server_result(self.h, ticket, None, cores.ctypes.data_as(C.c_void_p), m))
+        return _stats_dict(s, self._d.get(ticket, s.d)), cores
+
+    def release(self, ticket):
+        check(load().tt_server_release(self.h, ticket))
+        self._d.pop(ticket, None)
+
+    def stats(self):
+        s = _lib.ServerStats()
+        check(load().tt_server_get_stats(self.h, C.byref(s)))
+        return {name: getattr(s, name) for name, _ in _lib.ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().tt_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -115,3 +115,15 @@ def test_workload_lists_are_seeded_and_shaped_as_specified():
     arr = [p.arrival_s for p in t]
     assert all(x < y for x, y in zip(arr, arr[1:]))
     assert {p.eps for p in t} <= {1e-4, 1e-8} and all(4 <= p.d <= 6 for p in t)
+
+
+def test_server_stats_struct_and_no_gpu_failure():
+    assert C.sizeof(_lib.ServerStats) == 7 * 8
+    import torch
+    L = _lib.load()
+    assert not L.tt_server_create(0, 4, None)                 # no budget
+    assert not L.tt_server_create(1 << 30, 0, None)           # no slots
+    if not torch.cuda.is_available():
+        from paper_2407_11290_amd.api import Server
+        with pytest.raises(_lib.TTError):
+            Server(1 << 30)
