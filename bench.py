@@ -116,6 +116,8 @@ def bench_batch(args):
     torch.cuda.synchronize()
     single = time.perf_counter() - t1
     statuses = [h.stats()["status"] for h in hs]
+    escal = [i for i, h in enumerate(hs) if h.stats()["escalated"]]
+    errs = [h.stats()["sampled_err"] for h in hs]
     out = {
         "metric": METRIC, "value": work / elapsed, "unit": "entries/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
@@ -125,6 +127,8 @@ def bench_batch(args):
         "one_at_a_time": {"s": single, "entries_per_s": work1 / single, "solves_per_s": len(hs) / single},
         "batched_over_one_at_a_time": single / (elapsed / args.steps),
         "statuses": {str(k): statuses.count(k) for k in sorted(set(statuses))},
+        "escalated_to_fp64": escal,
+        "sampled_err_max": max(errs),
     }
     print(json.dumps(out), flush=True)
 

@@ -104,6 +104,14 @@ typedef struct tt_options {
     int32_t lookahead;          /* sweeps queued ahead of the host's stop check (default 2) */
     int32_t profile;            /* 1: time every search launch with HIP events (stats below) */
     void *stream;               /* hipStream_t to run on; NULL = a stream owned by the handle */
+    int32_t verify;             /* sampled-error check after the run (Sec. 5), on an independent
+                                   SplitMix64(seed + 1) set: -1 (default) = 4096 samples when the
+                                   precision policy chose FP32 sweeps, none otherwise; 0 = never;
+                                   > 0 = always, with that many samples.  When the error exceeds
+                                   eps after FP32 sweeps chosen by TT_PREC_AUTO, the problem is
+                                   solved again with FP64 sweeps; if it still exceeds eps the
+                                   status is TT_WARN_SAMPLED_ERR. */
+    int32_t pad;
 } tt_options;
 
 typedef struct tt_stats {
@@ -128,6 +136,9 @@ typedef struct tt_stats {
                                    w per newly evaluated entry (w = 8 FP64, 4 FP32) */
     double new_entries;         /* superblock entries evaluated by the tile launches */
     double sweep_phase_s;       /* device time from the first search launch to the end of the last one */
+    double sampled_err;         /* the verify check's sampled relative error, -1 if not run */
+    int32_t escalated;          /* 1: the FP32 solve missed eps and was redone in FP64 */
+    int32_t pad1;
 } tt_stats;
 
 typedef struct tt_cross_s *tt_cross_h;

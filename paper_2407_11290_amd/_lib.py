@@ -31,6 +31,8 @@ class Options(C.Structure):
         ("lookahead", C.c_int32),
         ("profile", C.c_int32),
         ("stream", C.c_void_p),
+        ("verify", C.c_int32),
+        ("pad", C.c_int32),
     ]
 
 
@@ -54,6 +56,9 @@ class Stats(C.Structure):
         ("sweep_alg_bytes", C.c_double),
         ("new_entries", C.c_double),
         ("sweep_phase_s", C.c_double),
+        ("sampled_err", C.c_double),
+        ("escalated", C.c_int32),
+        ("pad1", C.c_int32),
     ]
 
 

@@ -55,6 +55,7 @@ def _stats_dict(s, d):
         "sweep_launches": s.sweep_launches, "sweep_kernel_s": s.sweep_kernel_s,
         "sweep_alg_bytes": s.sweep_alg_bytes,
         "new_entries": s.new_entries, "sweep_phase_s": s.sweep_phase_s,
+        "sampled_err": s.sampled_err, "escalated": s.escalated,
     }
 
 
@@ -63,7 +64,7 @@ class TTCross:
 
     def __init__(self, n, eps, fn_id, params=None, seed=0, r_max=64, precision=_lib.PREC_AUTO,
                  n_samples=16384, grid=None, tile_rows=0, tile_cols=0, lookahead=2, profile=0,
-                 stream=None):
+                 stream=None, verify=-1):
         L = load()
         self.n = _i32(n)
         self.d = int(self.n.size)
@@ -86,6 +87,7 @@ class TTCross:
         o.tile_cols = tile_cols
         o.lookahead = lookahead
         o.profile = profile
+        o.verify = verify
         if stream is not None:
             o.stream = C.c_void_p(getattr(stream, "cuda_stream", stream))
         check(L.tt_cross_set_options(self.h, C.byref(o)))
@@ -186,13 +188,14 @@ class Server:
     wait for them, read their stats and cores."""
 
     def __init__(self, hbm_budget, max_slots=256, r_max=32, grid=2, precision=_lib.PREC_AUTO,
-                 n_samples=16384, lookahead=2):
+                 n_samples=16384, lookahead=2, verify=-1):
         L = load()
         o = default_options()
         o.r_max = r_max
         o.precision = precision
         o.n_samples = n_samples
         o.lookahead = lookahead
+        o.verify = verify
         for j in range(_lib.TT_MAX_D):
             o.grid[j] = int(grid)
         self.h = L.tt_server_create(int(hbm_budget), int(max_slots), C.byref(o))

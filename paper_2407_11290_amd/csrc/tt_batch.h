@@ -24,6 +24,9 @@ struct Slot {
     int rub[TT_MAX_D + 1] = {0};  // rank bounds for the next round it gets
     hipEvent_t ev = nullptr;      // completes when its cores and state are on the host
     double t_admit = 0, t_done = 0;
+    int64_t verify_R = 0;         // samples of its sampled-error check (0: none)
+    bool can_escalate = false;    // FP32 sweeps chosen by the precision policy
+    bool escalate = false;        // finished above eps: the owner solves it again in FP64
 };
 
 class Engine {
@@ -56,6 +59,7 @@ private:
     ProbDev *dPa = nullptr, *hPa = nullptr;   // descriptors: device array, pinned staging
     ProbState *dS = nullptr, *hS = nullptr;   // per-slot device state and its host copy
     HostMirror *hm = nullptr, *dhm = nullptr; // mapped host mirrors (host / device view)
+    double *dPart = nullptr, *hPart = nullptr;// sampled-error partial sums, 2 * NBV per slot
 };
 
 }  // namespace ttc

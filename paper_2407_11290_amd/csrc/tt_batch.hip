@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -46,7 +47,10 @@ void Engine::release()
     if (hPa) (void)hipHostFree(hPa);
     if (hS) (void)hipHostFree(hS);
     if (hm) (void)hipHostFree(hm);
+    if (dPart) (void)hipFree(dPart);
+    if (hPart) (void)hipHostFree(hPart);
     dPa = nullptr; dS = nullptr; hPa = nullptr; hS = nullptr; hm = nullptr; dhm = nullptr;
+    dPart = nullptr; hPart = nullptr;
     slots.clear();
     cap = 0;
 }
@@ -63,6 +67,8 @@ int Engine::init(int capacity, hipStream_t s)
     HIPCHK(hipHostMalloc((void **)&hS, sizeof(ProbState) * cap, hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void **)&hm, sizeof(HostMirror) * cap, hipHostMallocMapped | hipHostMallocCoherent));
     HIPCHK(hipHostGetDevicePointer((void **)&dhm, hm, 0));
+    HIPCHK(hipMalloc(&dPart, sizeof(double) * 2 * NBV * cap));
+    HIPCHK(hipHostMalloc((void **)&hPart, sizeof(double) * 2 * NBV * cap, hipHostMallocDefault));
     std::memset(hm, 0, sizeof(HostMirror) * cap);
     slots.assign(cap, Slot());
     for (int i = 0; i < cap; ++i) slots[i].idx = i;
@@ -93,6 +99,10 @@ int Engine::admit(Problem *Q, void *user)
     s.phase = Slot::SETUP;
     s.t_admit = now_s();
     for (int k = 0; k <= Q->d; ++k) s.rub[k] = 1;
+    s.verify_R = Q->verify_samples();
+    s.can_escalate = Q->auto_fp32();
+    Q->sampled_err = -1.0;
+    Q->escalated = Q->force_fp64 ? 1 : 0;
     ProbDev &D = hPa[i];
     D = Q->hP;
     D.S = dS + i;
@@ -102,6 +112,7 @@ int Engine::admit(Problem *Q, void *user)
     D.run.ns = Q->opt.n_samples;
     D.run.vals = Q->d_vals;
     D.run.cores = Q->d_cores;
+    D.run.verify_R = s.verify_R;
     std::memset(&hm[i], 0, sizeof(HostMirror));
     HIPCHK(hipMemcpyAsync(dPa + i, &D, sizeof(ProbDev), hipMemcpyHostToDevice, stream));
     Q->ran = false;
@@ -197,6 +208,27 @@ int Engine::launch_cores(std::vector<int> &ids)
         const size_t lc = sizeof(double) * ((size_t)2 * maxr * (maxr + 1) + (size_t)2 * maxr * A4W);
         if (m > 0 && off > 0) k_cores_b<<<off, A4W, lc, stream>>>(dPa, bm);
         HIPCHK(hipGetLastError());
+        // sampled-error checks of the slots that want one
+        BatchMap bv;
+        int nv = 0;
+        for (int a = 0; a < na; ++a) {
+            const Slot &s = slots[ids[c0 + a]];
+            if (s.verify_R > 0) {
+                bv.p[nv] = (uint16_t)s.idx;
+                bv.boff[nv] = nv;
+                ++nv;
+            }
+        }
+        bv.na = nv;
+        bv.boff[nv] = nv;
+        if (nv > 0) {
+            k_verify_b<<<dim3(NBV, nv), NT, 0, stream>>>(dPa, bv, dPart);
+            HIPCHK(hipGetLastError());
+            for (int a = 0; a < nv; ++a) {
+                const size_t o = (size_t)2 * NBV * bv.p[a];
+                HIPCHK(hipMemcpyAsync(hPart + o, dPart + o, sizeof(double) * 2 * NBV, hipMemcpyDeviceToHost, stream));
+            }
+        }
     }
     hipEvent_t ev = nullptr;
     if (!ev_free.empty()) { ev = ev_free.back(); ev_free.pop_back(); }
@@ -309,6 +341,18 @@ void Engine::finish_slot(Slot &s)
         Q.ran = false;
     } else {
         Q.finalize(S, r);
+        if (s.verify_R > 0) {
+            // the same in-order sum of the same partials as a single solve
+            const double *hp = hPart + (size_t)2 * NBV * s.idx;
+            double num = 0.0, den = 0.0;
+            for (int b = 0; b < NBV; ++b) { num += hp[2 * b]; den += hp[2 * b + 1]; }
+            const double err = den > 0 ? std::sqrt(num / den) : std::sqrt(num);
+            Q.sampled_err = err;
+            if (err > Q.eps) {
+                if (s.can_escalate) s.escalate = true;
+                else if (Q.status == TT_OK) Q.status = TT_WARN_SAMPLED_ERR;
+            }
+        }
     }
     s.t_done = now_s();
     Q.time_to_eps = s.t_done - s.t_admit;
@@ -373,27 +417,43 @@ extern "C" int tt_batch_run(tt_cross_h *hs, int count, void *hip_stream)
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    HIPCHK(hipEventRecord(e0, stream));
-    std::vector<int> ids(count);
-    for (int i = 0; i < count; ++i) {
-        const int id = eng.admit(&hs[i]->p, nullptr);
-        if (id < 0) return id;
-        ids[i] = id;
-    }
+    // pass 1: every problem; pass 2: those whose FP32 sweeps missed eps, in FP64
+    std::vector<int> todo(count);
+    for (int i = 0; i < count; ++i) todo[i] = i;
+    double total = 0.0;
     int st = TT_OK;
-    while (!eng.idle()) {
-        st = eng.tick(nullptr);
-        if (st) break;
+    for (int pass = 0; pass < 2 && !todo.empty() && st == TT_OK; ++pass) {
+        HIPCHK(hipEventRecord(e0, stream));
+        std::vector<int> ids(todo.size());
+        for (size_t i = 0; i < todo.size(); ++i) {
+            const int id = eng.admit(&hs[todo[i]]->p, nullptr);
+            if (id < 0) return id;
+            ids[i] = id;
+        }
+        while (!eng.idle()) {
+            st = eng.tick(nullptr);
+            if (st) break;
+        }
+        HIPCHK(hipEventRecord(e1, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        total += ms * 1e-3;
+        std::vector<int> next;
+        for (size_t i = 0; i < todo.size(); ++i) {
+            if (eng.slot(ids[i]).escalate) next.push_back(todo[i]);
+            eng.retire(ids[i]);
+        }
+        for (int i : next) {
+            Problem &Q = hs[i]->p;
+            Q.force_fp64 = true;
+            const int ps = Q.prepare();
+            if (ps) { st = ps; break; }
+        }
+        todo.swap(next);
     }
-    HIPCHK(hipEventRecord(e1, stream));
-    HIPCHK(hipStreamSynchronize(stream));
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    for (int i = 0; i < count; ++i) {
-        hs[i]->p.time_to_eps = ms * 1e-3;
-        eng.retire(ids[i]);
-    }
+    for (int i = 0; i < count; ++i) hs[i]->p.time_to_eps = total;
     return st;
 }

@@ -286,6 +286,7 @@ int Problem::allocate()
     cores_cap += (int64_t)rc[d - 1] * n[d - 1];
     if ((st = dalloc((void **)&d_cores, sizeof(double) * cores_cap)) != TT_OK) return st;
     if ((st = dalloc((void **)&d_vals, sizeof(double) * opt.n_samples)) != TT_OK) return st;
+    if ((st = dalloc((void **)&d_part, sizeof(double) * 2 * NBV)) != TT_OK) return st;
     if ((st = dalloc((void **)&H.S, sizeof(ProbState))) != TT_OK) return st;
     HIPCHK(hipHostMalloc((void **)&hm, sizeof(HostMirror), hipHostMallocMapped | hipHostMallocCoherent));
     HIPCHK(hipHostGetDevicePointer((void **)&H.hm, hm, 0));
@@ -309,6 +310,7 @@ void Problem::resolve_geometry()
     for (int j = 0; j < d; ++j) grid[j] = std::max(1, std::min(opt.grid[j], n[j]));
     int prec = opt.precision;
     if (prec == TT_PREC_AUTO) prec = (eps >= 1e-6) ? TT_PREC_FP32 : TT_PREC_FP64;
+    if (force_fp64) prec = TT_PREC_FP64;
     fp32 = (prec == TT_PREC_FP32) ? 1 : 0;
 }
 
@@ -493,11 +495,59 @@ int Problem::prepare()
     return TT_OK;
 }
 
+// Samples of the sampled-error check for this run (see tt_options.verify).
+int64_t Problem::verify_samples() const
+{
+    if (opt.verify > 0) return opt.verify;
+    if (opt.verify == 0) return 0;
+    const bool policy_fp32 = opt.precision == TT_PREC_AUTO && (fp32 || force_fp64);
+    return policy_fp32 ? 4096 : 0;
+}
+
+// Sampled relative error of the current cores over R indices of the
+// independent set SplitMix64(seed + 1) (Sec. 5).
+int Problem::verify(int64_t R, double &err)
+{
+    k_verify<<<NBV, NT, 0, stream>>>(dP, d_cores, R, opt.seed + 1, d_part);
+    HIPCHK(hipGetLastError());
+    double hp[2 * NBV];
+    HIPCHK(hipMemcpyAsync(hp, d_part, sizeof hp, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    double num = 0.0, den = 0.0;
+    for (int b = 0; b < NBV; ++b) { num += hp[2 * b]; den += hp[2 * b + 1]; }
+    err = den > 0 ? std::sqrt(num / den) : std::sqrt(num);
+    return TT_OK;
+}
+
 int Problem::run()
 {
+    // an escalation sticks to the handle until its options change: the same
+    // FP32 solve would miss eps again
+    sampled_err = -1.0;
+    escalated = force_fp64 ? 1 : 0;
     int st = prepare();
     if (st != TT_OK) return st;
     st = fp32 ? run_impl<float>() : run_impl<double>();
+    const int64_t R = verify_samples();
+    if (st >= 0 && R > 0) {
+        double err = 0.0;
+        if ((st = verify(R, err)) != TT_OK) return status = st;
+        sampled_err = err;
+        if (err > eps && auto_fp32()) {
+            // a13: the FP32 sweeps missed eps; solve again with FP64 sweeps
+            const double t_first = time_to_eps;
+            force_fp64 = true;
+            if ((st = prepare()) != TT_OK) return status = st;
+            st = run_impl<double>();
+            if (st < 0) return status = st;
+            escalated = 1;
+            time_to_eps += t_first;
+            if ((st = verify(R, err)) != TT_OK) return status = st;
+            sampled_err = err;
+        }
+        if (err > eps && status == TT_OK) status = TT_WARN_SAMPLED_ERR;
+        st = status;
+    }
     status = st;
     return st;
 }
@@ -526,6 +576,7 @@ void tt_options_default(tt_options *opt)
     opt->tile_cols = 0;
     opt->lookahead = 2;
     opt->stream = nullptr;
+    opt->verify = -1;
 }
 
 static int check_options(const tt_options *o)
@@ -539,6 +590,7 @@ static int check_options(const tt_options *o)
         if (o->grid[j] < 1) return set_err(TT_EINVAL, "grid[%d] must be >= 1", j);
     if (o->tile_rows < 0 || o->tile_rows > 256) return set_err(TT_EINVAL, "tile_rows must be in [0,256]");
     if (o->tile_cols < 0 || o->tile_cols > 256) return set_err(TT_EINVAL, "tile_cols must be in [0,256]");
+    if (o->verify < -1) return set_err(TT_EINVAL, "verify must be -1, 0 or a sample count");
     return TT_OK;
 }
 
@@ -577,6 +629,7 @@ int tt_cross_set_options(tt_cross_h h, const tt_options *opt)
         }
     }
     h->p.opt = *opt;
+    h->p.force_fp64 = false;
     return TT_OK;
 }
 
@@ -704,6 +757,8 @@ int tt_cross_get_stats(tt_cross_h h, tt_stats *st)
     st->sweep_alg_bytes = P.sweep_alg_bytes;
     st->new_entries = P.new_entries;
     st->sweep_phase_s = P.sweep_phase_s;
+    st->sampled_err = P.sampled_err;
+    st->escalated = P.escalated;
     return TT_OK;
 }
 

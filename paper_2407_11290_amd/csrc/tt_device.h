@@ -223,6 +223,7 @@ struct RunDev {
     int ns;                       // samples
     double *vals;                 // ns sample values
     double *cores;                // output cores
+    int64_t verify_R;             // samples of the sampled-error check (0: none)
 };
 
 struct ProbDev {

@@ -68,6 +68,15 @@ struct Problem {
     double sweep_kernel_s = 0, sweep_alg_bytes = 0, new_entries = 0, sweep_phase_s = 0;
     std::vector<hipEvent_t> prof_events;     // 3 per sweep when profiling
     int i0[TT_MAX_D] = {0};
+    // sampled-error check and FP32 -> FP64 escalation
+    double sampled_err = -1.0;
+    int escalated = 0;
+    bool force_fp64 = false;       // sweep in FP64 whatever the precision policy says
+    double *d_part = nullptr;      // partial sums of the check (2 * NBV doubles)
+
+    int64_t verify_samples() const;
+    bool auto_fp32() const { return opt.precision == TT_PREC_AUTO && fp32 && !force_fp64; }
+    int verify(int64_t R, double &err);
 
     ~Problem();
     void release();

@@ -892,6 +892,69 @@ static __global__ void __launch_bounds__(A4W) k_cores(const ProbDev *__restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Sampled-error check (Sec. 5): over R multi-indices drawn from
+// SplitMix64(seed), the sums of (X - X~)^2 and X^2, one wavefront per sample
+// (lane b carries entry b of the running row vector of the TT product).
+// Workgroup blk of nblk writes its two partial sums to part[2*blk..]; the
+// caller adds the nblk pairs in order, so the result does not depend on
+// which launch computed it.
+// ---------------------------------------------------------------------------
+constexpr int NBV = 128;        // workgroups per checked problem
+
+__device__ void verify_body(const ProbDev *__restrict__ P, const double *__restrict__ G, const int *r, int64_t R,
+                            uint64_t seed, double *part, int blk, int nblk)
+{
+    const int d = P->d, lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    CoreArgs ca;
+    int64_t len;
+    make_core_args(d, P->F.n, r, ca, len);
+    double num = 0.0, den = 0.0;
+    for (int64_t t = (int64_t)blk * (NT / 64) + wid; t < R; t += (int64_t)nblk * (NT / 64)) {
+        const int ix = (lane < d) ? (int)(sm64_at(seed, (uint64_t)t * d + lane) % (uint64_t)P->F.n[lane]) : 0;
+        double v = (lane == 0) ? 1.0 : 0.0;
+        for (int k = 0; k < d; ++k) {
+            const int ik = __shfl(ix, k, 64), ra = r[k], rb = r[k + 1], nn = P->F.n[k];
+            const double *Gk = G + ca.goff[k];
+            double acc = 0.0;
+            for (int aa = 0; aa < ra; ++aa) {
+                const double va = __shfl(v, aa, 64);
+                if (lane < rb) acc = __fma_rn(va, Gk[((int64_t)aa * nn + ik) * rb + lane], acc);
+            }
+            v = (lane < rb) ? acc : 0.0;
+        }
+        const double x = fn_value_ix<double>(P->F, [&](int j) { return __shfl(ix, j, 64); });
+        if (lane == 0) {
+            const double dx = x - v;
+            num = __fma_rn(dx, dx, num);
+            den = __fma_rn(x, x, den);
+        }
+    }
+    __shared__ double sn[NT / 64], sd[NT / 64];
+    if (lane == 0) { sn[wid] = num; sd[wid] = den; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int w = 0; w < NT / 64; ++w) { a += sn[w]; b += sd[w]; }
+        part[2 * blk] = a;
+        part[2 * blk + 1] = b;
+    }
+}
+
+__device__ inline void final_ranks(const ProbDev *P, int *r)
+{
+    const ProbState *S = P->S;
+    for (int k = 0; k <= P->d; ++k) r[k] = S->r[S->sweeps & 1][k];
+}
+
+static __global__ void __launch_bounds__(NT) k_verify(const ProbDev *__restrict__ P, const double *G, int64_t R,
+                                                      uint64_t seed, double *part)
+{
+    int r[TT_MAX_D + 1];
+    final_ranks(P, r);
+    verify_body(P, G, r, R, seed, part, blockIdx.x, gridDim.x);
+}
+
+// ---------------------------------------------------------------------------
 // Batched launches: many independent problems in one launch.  Their
 // descriptors lie contiguously in device memory; the kernel arguments name
 // the problems of the launch and, for the grid-strided kernels, the range of
@@ -958,13 +1021,24 @@ static __global__ void __launch_bounds__(A4W) k_cores_b(const ProbDev *__restric
 {
     const int i = batch_find(bm, blockIdx.x);
     const ProbDev *P = Pa + bm.p[i];
-    const ProbState *S = P->S;
     int r[TT_MAX_D + 1];
-    for (int k = 0; k <= P->d; ++k) r[k] = S->r[S->sweeps & 1][k];
+    final_ranks(P, r);
     CoreArgs a;
     int64_t len;
     make_core_args(P->d, P->F.n, r, a, len);
     cores_body(P, a, P->run.cores, blockIdx.x - bm.boff[i]);
+}
+
+// Sampled-error check of every listed problem: NBV workgroups each (grid.y =
+// problem), partial sums to part + 2*NBV*slot, R and the seed in run.
+static __global__ void __launch_bounds__(NT) k_verify_b(const ProbDev *__restrict__ Pa, BatchMap bm, double *part)
+{
+    const int slot = bm.p[blockIdx.y];
+    const ProbDev *P = Pa + slot;
+    int r[TT_MAX_D + 1];
+    final_ranks(P, r);
+    verify_body(P, P->run.cores, r, P->run.verify_R, P->run.seed + 1, part + (int64_t)2 * NBV * slot, blockIdx.x,
+                gridDim.x);
 }
 
 // ---------------------------------------------------------------------------

@@ -42,6 +42,7 @@ struct Request {
     uint64_t seed = 0;
     double t_submit = 0, t_admit = 0, t_done = 0;
     int state = 0;                // 0 queued, 1 running, 2 done
+    bool force64 = false;         // FP32 sweeps missed eps: solve again with FP64 sweeps
     int status = TT_OK;
     tt_stats stats;
     std::vector<double> cores;
@@ -188,6 +189,7 @@ private:
         k.d = r.d;
         int prec = opt_.precision;
         if (prec == TT_PREC_AUTO) prec = (r.eps >= 1e-6) ? TT_PREC_FP32 : TT_PREC_FP64;
+        if (r.force64) prec = TT_PREC_FP64;
         k.fp32 = (prec == TT_PREC_FP32);
         k.rmax = opt_.r_max;
         for (int j = 0; j < r.d; ++j) {
@@ -219,6 +221,7 @@ private:
             P.opt = opt_;
             P.opt.stream = stream_;
             P.opt.seed = r.seed;
+            P.force_fp64 = r.force64;
             P.resolve_geometry();
             const size_t need = P.device_bytes();
             if (need > budget_) { err = set_err(TT_ENOMEM, "request needs %zu B, budget %zu B", need, budget_); return nullptr; }
@@ -247,6 +250,7 @@ private:
         P.hP.F = f.dev;
         P.eps = r.eps;
         P.opt.seed = r.seed;
+        P.force_fp64 = r.force64;
         if ((err = P.prepare()) != TT_OK) return nullptr;
         pick->busy = true;
         pick->last_used = wall_s();
@@ -307,6 +311,17 @@ private:
                 const Slot &s = eng_.slot(idx);
                 Request *r = (Request *)s.user;
                 Problem &Q = *s.Q;
+                if (s.escalate) {
+                    // a13: back to the head of the queue, to be solved with FP64 sweeps
+                    r->force64 = true;
+                    r->state = 0;
+                    r->Q = nullptr;
+                    --running_;
+                    give_back(&Q);
+                    eng_.retire(idx);
+                    queue_.push_front(r);
+                    continue;
+                }
                 r->status = Q.ran ? Q.status : (Q.status ? Q.status : TT_EDEVICE);
                 if (Q.ran) {
                     r->cores.resize((size_t)Q.cores_len);
@@ -331,6 +346,8 @@ private:
                     t.new_entries = Q.new_entries;
                     for (int u = 0; u < Q.d - 1; ++u) t.last_best[u] = Q.last_best[u];
                 }
+                t.sampled_err = Q.sampled_err;
+                t.escalated = r->force64 ? 1 : 0;
                 r->t_done = wall_s();
                 t.time_to_eps_s = r->t_done - r->t_admit;
                 r->state = 2;

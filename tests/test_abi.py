@@ -36,13 +36,13 @@ def test_options_defaults():
     from paper_2407_11290_amd.api import default_options
     o = default_options()
     assert o.r_max == 64 and o.n_samples == 16384 and o.precision == _lib.PREC_AUTO
-    assert list(o.grid)[:4] == [1, 1, 1, 1] and o.lookahead == 2 and o.seed == 0
+    assert list(o.grid)[:4] == [1, 1, 1, 1] and o.lookahead == 2 and o.seed == 0 and o.verify == -1
 
 
 def test_struct_sizes_match_the_header():
     # tt_options: u64 + 4 i32 + 16 i32 + 3 i32 (+pad) + pointer
-    assert C.sizeof(_lib.Options) == 8 + 4 * 4 + 4 * 16 + 4 * 4 + 8
-    assert C.sizeof(_lib.Stats) == 3 * 8 + 4 * 4 + 4 * 17 + 4 + 3 * 8 + 8 * 16 + 8 + 4 * 8
+    assert C.sizeof(_lib.Options) == 8 + 4 * 4 + 4 * 16 + 4 * 4 + 8 + 2 * 4
+    assert C.sizeof(_lib.Stats) == 3 * 8 + 4 * 4 + 4 * 17 + 4 + 3 * 8 + 8 * 16 + 8 + 4 * 8 + 8 + 2 * 4
 
 
 @pytest.mark.parametrize("args,code", [

@@ -134,3 +134,46 @@ def test_batch_mix_subset_equals_single_solves():
         g.run()
         _assert_same(_snapshot(hs[i]), _snapshot(g), i)
         assert g.stats()["precision_used"] == PREC_FP32
+
+
+def test_fp32_policy_escalates_to_fp64_alike_in_batch_and_alone():
+    """Problem 190 of the mixed batch (5D Hilbert, n = 128, eps = 1e-6) misses
+    eps after FP32 sweeps on the sampled-error check and is solved again with
+    FP64 sweeps (the precision policy); problem 0 does not.  Alone and in a
+    batch the outcome is the same bit for bit."""
+    mix = batch_mix()
+    picks = [190, 0, 3]
+    conv = [{"n": mix[i].n, "eps": mix[i].eps, "fn": mix[i].fn_id, "params": mix[i].params, "seed": mix[i].seed,
+             "grid": mix[i].grid} for i in picks]
+    singles = []
+    for s in conv:
+        _say("single", s["n"], s["fn"], s["seed"])
+        g = _make(s)
+        g.run()
+        singles.append((_snapshot(g), g.stats()))
+    st190 = singles[0][1]
+    assert st190["escalated"] == 1 and st190["precision_used"] == PREC_FP64
+    assert 0 <= st190["sampled_err"] <= conv[0]["eps"] and st190["status"] == 0
+    for _snap, st in singles[1:]:
+        assert st["escalated"] == 0 and st["precision_used"] == PREC_FP32 and 0 <= st["sampled_err"] <= 1e-6
+    _say("batch")
+    hs = [_make(s) for s in conv]
+    batch_run(hs)
+    for i, (g, (ref, st)) in enumerate(zip(hs, singles)):
+        _assert_same(_snapshot(g), ref, i)
+        gs = g.stats()
+        assert gs["escalated"] == st["escalated"] and gs["sampled_err"] == st["sampled_err"]
+
+
+def test_verify_off_and_forced():
+    spec = {"n": [16] * 4, "eps": 1e-9, "fn": FN_HILBERT, "params": [1.0], "seed": 5}
+    g = _make(spec, precision=PREC_FP64, verify=0)
+    g.run()
+    assert g.stats()["sampled_err"] == -1.0
+    g = _make(spec, precision=PREC_FP64, verify=50000)
+    g.run()
+    st = g.stats()
+    assert 0 <= st["sampled_err"] <= 1e-9 and st["escalated"] == 0
+    o = Oracle(spec["n"], spec["eps"], spec["fn"], spec["params"], seed=spec["seed"])
+    o.run()
+    assert abs(st["sampled_err"] - o.sampled_error(50000)) <= 1e-2 * st["sampled_err"] + 1e-15

@@ -112,3 +112,22 @@ def test_server_budget_limits():
         srv.poll(123456)
     assert e.value.code == EINVAL
     srv.close()
+
+
+def test_server_escalates_like_a_single_solve():
+    """The mixed batch's problem 190 misses eps with FP32 sweeps; served, it is
+    re-queued with FP64 sweeps and ends as its single solve does."""
+    from paper_2407_11290_amd.workloads import batch_mix
+    p = batch_mix()[190]
+    srv = Server(16 << 30, max_slots=4, r_max=64, grid=2)
+    t = srv.submit(p.n, p.eps, p.fn_id, p.params, seed=p.seed)
+    assert srv.wait(t)[0] == 0
+    s, cores = srv.result(t)
+    g = TTCross(p.n, p.eps, p.fn_id, p.params, seed=p.seed, r_max=64, grid=p.grid)
+    g.run()
+    s1 = g.stats()
+    assert s["escalated"] == 1 == s1["escalated"]
+    for key in ("ranks", "sweeps", "pivoted", "precision_used", "sampled_err"):
+        assert s[key] == s1[key], key
+    assert np.array_equal(cores.view(np.uint64), g.cores_flat().view(np.uint64))
+    srv.close()
