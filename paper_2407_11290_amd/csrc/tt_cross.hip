@@ -342,8 +342,8 @@ template <typename V> int Problem::run_impl()
     }
     HIPCHK(hipGetLastError());
     // search sweeps, queued ahead of the host's view of the stop flag
-    int rub[TT_MAX_D + 1];
-    for (int k = 0; k <= d; ++k) rub[k] = 1;
+    int rub[TT_MAX_D + 1], rst[TT_MAX_D + 1];   // rank bounds of this launch / of its stored region
+    for (int k = 0; k <= d; ++k) rub[k] = rst[k] = 1;
     const int L = std::max(1, opt.lookahead);
     int launched = 0, done_known = 0;
     const bool prof = opt.profile != 0;
@@ -360,23 +360,30 @@ template <typename V> int Problem::run_impl()
             SweepArgs a;
             a.sweep = launched;
             a.nk = nk;
-            int tot = 0;
+            int units = 0;
             size_t lds = 0;
             for (int u = 0; u < nk; ++u) {
                 const int k = u + 1;
                 const KDev &K = hP.kd[u];
-                tot += rub[k - 1] * K.RTp * rub[k + 1] * K.CTq;
+                const int all = rub[k - 1] * K.RTp * rub[k + 1] * K.CTq;
+                const int st = std::min(all, rst[k - 1] * K.RTp * rst[k + 1] * K.CTq);
+                units += (all - st) + (st + NT / 64 - 1) / (NT / 64);
                 lds = std::max(lds, sweep_lds_bytes(rub[k], K.TR, K.TC, sizeof(V)));
             }
-            // enough workgroups for the largest superblocks this sweep can have;
-            // the kernel strides over the exact tile count it reads on the device
-            const int grid = std::max(1, std::min(tot, sweep_grid_cap));
+            // one workgroup per expected work unit (new tiles one each, stored
+            // tiles four each); the kernel strides over the exact unit count it
+            // reads on the device, so a wrong estimate costs time only
+            const int grid = std::max(1, std::min(units, sweep_grid_cap));
+            for (int k = 0; k <= d; ++k) rst[k] = rub[k];
+            // the Hilbert tensor gets a kernel built for it alone (fewer
+            // registers, more workgroups resident); the others share one
+            auto kern = (fn.dev.id == TT_FN_HILBERT) ? k_sweep<V, TT_FN_HILBERT> : k_sweep<V, 0>;
             if (prof) {
                 // the events take the dispatch's own start and end timestamps
-                hipExtLaunchKernelGGL(k_sweep<V>, dim3(grid), dim3(NT), (uint32_t)lds, stream,
+                hipExtLaunchKernelGGL(kern, dim3(grid), dim3(NT), (uint32_t)lds, stream,
                                       prof_events[3 * launched], prof_events[3 * launched + 1], 0u, dP, a);
             } else {
-                k_sweep<V><<<grid, NT, lds, stream>>>(dP, a);
+                kern<<<grid, NT, lds, stream>>>(dP, a);
             }
             ++launched;
             for (int k = 1; k <= d - 1; ++k) rub[k] = std::min(rub[k] + 1, rc[k]);

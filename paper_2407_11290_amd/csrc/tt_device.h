@@ -10,6 +10,7 @@
 namespace ttc {
 
 constexpr int NT = 256;                    // threads per workgroup (4 wave64)
+constexpr int TT_TILE_ROWS_MAX = 256;      // largest tile extent along the rows
 constexpr double PI = 3.14159265358979323846;
 constexpr uint64_t SM64_GAMMA = 0x9E3779B97F4A7C15ULL;
 
@@ -73,9 +74,11 @@ template <typename V> __device__ inline V vel(int i, int n, V vmax)
 // prefixes and suffixes without a private array).  The operation order follows
 // the written formulas term by term, so that FP64 values of the Hilbert and
 // separable functions are bitwise reproducible.
-template <typename V, typename IX> __device__ inline V fn_value_ix(const FnDev &F, IX ix)
+// FNS = 0 reads the function from F.id; a nonzero FNS fixes it at compile
+// time, so a kernel built for one function carries no code of the others.
+template <typename V, int FNS = 0, typename IX> __device__ inline V fn_value_ix(const FnDev &F, IX ix)
 {
-    switch (F.id) {
+    switch (FNS ? FNS : F.id) {
     case TT_FN_HILBERT: {
         long long s = 0;
         for (int j = 0; j < F.d; ++j) s += (long long)ix(j) + 1;
@@ -142,9 +145,9 @@ template <typename V, typename IX> __device__ inline V fn_value_ix(const FnDev &
     return (V)0;
 }
 
-template <typename V> __device__ inline V fn_value(const FnDev &F, const int *idx)
+template <typename V, int FNS = 0> __device__ inline V fn_value(const FnDev &F, const int *idx)
 {
-    return fn_value_ix<V>(F, [&](int j) { return idx[j]; });
+    return fn_value_ix<V, FNS>(F, [&](int j) { return idx[j]; });
 }
 
 

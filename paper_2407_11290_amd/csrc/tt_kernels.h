@@ -102,7 +102,7 @@ __device__ inline void wave_best(double &v, uint64_t &key, double &sv)
 
 // Stored residuals, one wavefront per tile: apply the newest pivot (if any)
 // and search.  All loads of a batch are issued before any is used.
-template <typename V>
+template <typename V, int B>
 __device__ void stored_tile_wave(const KDev &K, const KSweep &ks, const TileGeom &g, double &bv, uint64_t &bk,
                                  double &bs)
 {
@@ -119,7 +119,6 @@ __device__ void stored_tile_wave(const KDev &K, const KSweep &ks, const TileGeom
     V u = 0;
     if (apply) u = E[(int64_t)ks.arho * ld + col] / (V)ks.apiv;
     if (cp) return;
-    constexpr int B = 8;
     for (int i0 = tr; i0 < g.nrows; i0 += B * rpw) {
         V xv[B], wv[B];
         uint8_t rp[B];
@@ -156,23 +155,28 @@ __device__ void stored_tile_wave(const KDev &K, const KSweep &ks, const TileGeom
 //   row i:    e_z = X(i, gamma_z); for z' < z: e_z -= e_z' * U(z', gamma_z)   -> W(i, z)
 //   column j: e_z = X(rho_z, j);   for z' < z: e_z -= W(rho_z, z') * e_z'/p_z' -> p_z U(z, j)
 // and the frozen pivot columns / rows of the tile receive those values.
-template <typename V>
+template <typename V, int FNS>
 __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSweep &ks, const TileGeom &g,
                          double &bv, uint64_t &bk, double &bs, V *sm)
 {
     const int d = P->d, u = g.u, k = u + 1, tid = threadIdx.x, rk = ks.rk;
+    const int wid = tid >> 6, lane = tid & 63;
     const bool rows_old = g.row0 < ks.nr_st, cols_old = g.col0 < ks.nc_st;
     V *E = (V *)K.E;
     const int64_t ld = K.colcap;
     __shared__ int pre[TT_MAX_D], suf[TT_MAX_D];
     __shared__ int s_rho[TT_MAX_RANK], s_gam[TT_MAX_RANK];
     __shared__ V s_piv[TT_MAX_RANK];
+    __shared__ uint8_t s_rp[TT_TILE_ROWS_MAX];
     const int npre = k - 1, nsuf = d - k - 1, nj = d - k;
     const int TRm = K.TR, TCm = K.TC, ntri = rk * (rk - 1) / 2;
     V *Wt = sm;                                // Wt[z*TRm+ii] = W(row, z)
     V *Ut = Wt + (int64_t)rk * TRm;            // Ut[z*TCm+jj] = U(z, col)
     V *Gr = Ut + (int64_t)rk * TCm;            // U(z', gamma_z), z' < z
     V *Gc = Gr + ntri;                         // W(rho_z, z'), z' < z
+    const int TCt = K.TC, rpp = NT / TCt;
+    const int tr = tid / TCt, tcol = tid - tr * TCt;
+    const int cpv = (tcol < g.ncols) ? K.cpiv[g.col0 + tcol] : 1;
     if (tid < npre) pre[tid] = P->kd[u - 1].Ifull[g.p * npre + tid];
     if (tid < nsuf) suf[tid] = P->kd[u + 1].Jfull[g.q * nsuf + tid];
     for (int z = tid; z < rk; z += NT) {
@@ -180,6 +184,7 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSw
         s_gam[z] = K.gam[z];
         s_piv[z] = (V)K.piv[z];
     }
+    for (int ii = tid; ii < g.nrows; ii += NT) s_rp[ii] = K.rpiv[g.row0 + ii];
     __syncthreads();
     // raw factors: frozen entries, or the generating function at the skeleton
     if (rows_old) {
@@ -196,7 +201,7 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSw
             const int z = e / g.nrows, ii = e - z * g.nrows;
             const int ikv = g.ik0 + ii;
             const int *Jz = K.Jfull + z * nj;
-            Wt[z * TRm + ii] = fn_value_ix<V>(P->F, [&](int j) {
+            Wt[z * TRm + ii] = fn_value_ix<V, FNS>(P->F, [&](int j) {
                 return j < npre ? pre[j] : (j == k - 1 ? ikv : Jz[j - k]);
             });
         }
@@ -215,57 +220,70 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSw
             const int z = e / g.ncols, jj = e - z * g.ncols;
             const int ik1v = g.ik10 + jj;
             const int *Iz = K.Ifull + z * k;
-            Ut[z * TCm + jj] = fn_value_ix<V>(P->F, [&](int j) {
+            Ut[z * TCm + jj] = fn_value_ix<V, FNS>(P->F, [&](int j) {
                 return j < k ? Iz[j] : (j == k ? ik1v : suf[j - k - 1]);
             });
         }
     }
     __syncthreads();
-    // chains: threads [0, NT/2) take the rows, threads [NT/2, NT) the columns
-    if (!rows_old && tid < NT / 2)
-    for (int ii = tid; ii < g.nrows; ii += NT / 2) {
-        for (int zp = 0; zp + 1 < rk; ++zp) {
-            const V w = Wt[zp * TRm + ii];
-            for (int z = zp + 1; z < rk; ++z) Wt[z * TRm + ii] = vfma<V>(-w, Gr[tri(zp, z)], Wt[z * TRm + ii]);
-        }
-        if (cols_old)
-            for (int z = 0; z < rk; ++z) {
-                const int gz = s_gam[z];
-                if (gz >= g.col0 && gz < g.col0 + g.ncols) E[(int64_t)(g.row0 + ii) * ld + gz] = Wt[z * TRm + ii];
+    // chains as triangular solves, one lane group per row (column): lane z of
+    // the group holds factor z, and at step z' the finished factor z' is
+    // passed to the lanes z > z' by a shuffle.  Each factor sees the same
+    // operations in the same order as the written recursion.
+    int G = 1;
+    while (G < rk) G <<= 1;
+    const int gpw = 64 / G, ngroups = (NT / 64) * gpw;
+    const int gid = wid * gpw + lane / G, zl = lane & (G - 1);
+    if (!rows_old) {
+        for (int base = 0; base < g.nrows; base += ngroups) {
+            const int ii = base + gid;
+            const bool ok = ii < g.nrows && zl < rk;
+            V w = ok ? Wt[zl * TRm + ii] : (V)0;
+            for (int zp = 0; zp + 1 < rk; ++zp) {
+                const V wzp = __shfl(w, zp, G);
+                if (ok && zl > zp) w = vfma<V>(-wzp, Gr[tri(zp, zl)], w);
             }
-    }
-    if (!cols_old && tid >= NT / 2)
-    for (int jj = tid - NT / 2; jj < g.ncols; jj += NT / 2) {
-        for (int zp = 0; zp + 1 < rk; ++zp) {
-            const V uu = Ut[zp * TCm + jj] / s_piv[zp];
-            for (int z = zp + 1; z < rk; ++z) Ut[z * TCm + jj] = vfma<V>(-Gc[tri(zp, z)], uu, Ut[z * TCm + jj]);
+            if (ok) {
+                Wt[zl * TRm + ii] = w;
+                const int gz = s_gam[zl];
+                if (cols_old && gz >= g.col0 && gz < g.col0 + g.ncols) E[(int64_t)(g.row0 + ii) * ld + gz] = w;
+            }
         }
-        for (int z = 0; z < rk; ++z) {
-            const int rz = s_rho[z];
-            if (rows_old && rz >= g.row0 && rz < g.row0 + g.nrows) E[(int64_t)rz * ld + g.col0 + jj] = Ut[z * TCm + jj];
-            Ut[z * TCm + jj] = Ut[z * TCm + jj] / s_piv[z];
+    }
+    if (!cols_old) {
+        for (int base = 0; base < g.ncols; base += ngroups) {
+            const int jj = base + gid;
+            const bool ok = jj < g.ncols && zl < rk;
+            V u = ok ? Ut[zl * TCm + jj] : (V)0;
+            for (int zp = 0; zp + 1 < rk; ++zp) {
+                const V uu = __shfl(u, zp, G) / s_piv[zp];
+                if (ok && zl > zp) u = vfma<V>(-Gc[tri(zp, zl)], uu, u);
+            }
+            if (ok) {
+                const int rz = s_rho[zl];
+                if (rows_old && rz >= g.row0 && rz < g.row0 + g.nrows) E[(int64_t)rz * ld + g.col0 + jj] = u;
+                Ut[zl * TCm + jj] = u / s_piv[zl];
+            }
         }
     }
     __syncthreads();
-    const int TCt = K.TC, rpp = NT / TCt;
-    const int tr = tid / TCt, tcol = tid - tr * TCt;
     if (tcol < g.ncols) {
         const int col = g.col0 + tcol;
-        if (!K.cpiv[col]) {
+        if (!cpv) {
             const int ik1v = g.ik10 + tcol;
-            const bool hilbert = P->F.id == TT_FN_HILBERT;
+            const bool hilbert = (FNS ? FNS : P->F.id) == TT_FN_HILBERT;
             long long hsum = ik1v + 1;                 // integer index sum, exact in any order
             for (int j = 0; j < npre; ++j) hsum += pre[j] + 1;
             for (int j = 0; j < nsuf; ++j) hsum += suf[j] + 1;
             for (int ii = tr; ii < g.nrows; ii += rpp) {
                 const int row = g.row0 + ii;
-                if (K.rpiv[row]) continue;
+                if (s_rp[ii]) continue;
                 const int ikv = g.ik0 + ii;
                 V x;
                 if (hilbert) {
                     x = (V)1 / ((V)(hsum + ikv + 1) + (V)P->F.shift);
                 } else {
-                    x = fn_value_ix<V>(P->F, [&](int j) {
+                    x = fn_value_ix<V, FNS>(P->F, [&](int j) {
                         return j < npre ? pre[j] : (j == k - 1 ? ikv : (j == k ? ik1v : suf[j - k - 1]));
                     });
                 }
@@ -307,7 +325,7 @@ __device__ inline void sweep_shape(const ProbDev *P, const KSweep *ks, int nk, S
 
 // Fixed grid striding over work units: first the new-entry tiles (one per
 // workgroup), then the stored tiles four at a time (one per wavefront).
-template <typename V>
+template <typename V, int FNS>
 __device__ void sweep_body(const ProbDev *__restrict__ P, int nk, int blk, int nblk)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -340,7 +358,7 @@ __device__ void sweep_body(const ProbDev *__restrict__ P, int nk, int blk, int n
             }
             const KDev &K = P->kd[u];
             const TileGeom g = tile_geom(K, u, R, C);
-            new_tile<V>(P, K, ks[u], g, bv, bk, bs, (V *)smem_raw);
+            new_tile<V, FNS>(P, K, ks[u], g, bv, bk, bs, (V *)smem_raw);
             if (tid == 0) {
                 Cand &c = K.cand[R * CT + C];
                 c.v = bv; c.key = bk; c.sv = bs;
@@ -355,7 +373,9 @@ __device__ void sweep_body(const ProbDev *__restrict__ P, int nk, int blk, int n
                 const int R = idx / CTs, C = idx - R * CTs;
                 const KDev &K = P->kd[u];
                 const TileGeom g = tile_geom(K, u, R, C);
-                stored_tile_wave<V>(K, ks[u], g, bv, bk, bs);
+                // 8 rows per batch of loads: more raise the register count
+                // past four wavefronts per SIMD (Hilbert kernel) or three
+                stored_tile_wave<V, 8>(K, ks[u], g, bv, bk, bs);
                 wave_best(bv, bk, bs);
                 if (lane == 0) {
                     Cand &c = K.cand[R * sh.CT[u] + C];
@@ -366,10 +386,10 @@ __device__ void sweep_body(const ProbDev *__restrict__ P, int nk, int blk, int n
     }
 }
 
-template <typename V>
+template <typename V, int FNS = 0>
 static __global__ void __launch_bounds__(NT) k_sweep(const ProbDev *__restrict__ P, SweepArgs a)
 {
-    sweep_body<V>(P, a.nk, blockIdx.x, gridDim.x);
+    sweep_body<V, FNS>(P, a.nk, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1006,7 +1026,7 @@ static __global__ void __launch_bounds__(NT) k_sweep_b(const ProbDev *__restrict
 {
     const int i = batch_find(bm, blockIdx.x);
     const ProbDev *P = Pa + bm.p[i];
-    sweep_body<V>(P, P->nk, blockIdx.x - bm.boff[i], bm.boff[i + 1] - bm.boff[i]);
+    sweep_body<V, 0>(P, P->nk, blockIdx.x - bm.boff[i], bm.boff[i + 1] - bm.boff[i]);
 }
 
 template <typename V>

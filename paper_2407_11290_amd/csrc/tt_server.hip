@@ -199,15 +199,22 @@ private:
         return k;
     }
 
-    // a pooled problem for r, or nullptr if none fits the budget right now
-    Problem *acquire(const Request &r, int &err)
+    // a pooled problem for r, or nullptr if none can be had right now.  Only
+    // may_grow callers create objects; a shape that already has objects (all
+    // busy) waits for one of them rather than evicting other shapes, because
+    // freeing device memory stalls the whole device.
+    Problem *acquire(const Request &r, int &err, bool may_grow)
     {
         err = TT_OK;
         const Key k = key_of(r);
         auto range = pool_.equal_range(k);
         PoolEntry *pick = nullptr;
-        for (auto it = range.first; it != range.second; ++it)
+        bool have_shape = false;
+        for (auto it = range.first; it != range.second; ++it) {
+            have_shape = true;
             if (!it->second.busy) { pick = &it->second; break; }
+        }
+        if (!pick && !may_grow) return nullptr;
         if (!pick) {
             // a new problem object of this shape, after evicting idle ones of
             // other shapes if the budget needs it
@@ -225,6 +232,7 @@ private:
             P.resolve_geometry();
             const size_t need = P.device_bytes();
             if (need > budget_) { err = set_err(TT_ENOMEM, "request needs %zu B, budget %zu B", need, budget_); return nullptr; }
+            if (have_shape && pool_bytes_ + need > budget_) return nullptr;
             while (pool_bytes_ + need > budget_) {
                 auto victim = pool_.end();
                 for (auto it = pool_.begin(); it != pool_.end(); ++it)
@@ -273,22 +281,27 @@ private:
                 if (queue_.empty() && eng_.idle())
                     cv_.wait_for(g, std::chrono::milliseconds(20), [&] { return quit_ || !queue_.empty(); });
                 if (quit_) break;
-                // admit in arrival order while slots and budget allow
-                while (!queue_.empty() && eng_.free_slots() > 0) {
-                    Request *r = queue_.front();
+                // admit in arrival order while slots and budget allow; the
+                // oldest request may create a problem object, later ones
+                // (within a window) may pass it on idle pooled objects
+                int scanned = 0;
+                for (auto it = queue_.begin(); it != queue_.end() && eng_.free_slots() > 0 && scanned < 256;
+                     ++scanned) {
+                    Request *r = *it;
                     int err = TT_OK;
-                    Problem *Q = acquire(*r, err);
+                    Problem *Q = acquire(*r, err, it == queue_.begin());
                     if (!Q) {
                         if (err) {          // the request can never run
                             r->status = err;
                             r->state = 2;
                             r->t_done = wall_s();
-                            queue_.pop_front();
+                            it = queue_.erase(it);
                             ++completed_;
                             done_cv_.notify_all();
                             continue;
                         }
-                        break;              // wait for memory to come back
+                        ++it;               // waits for an object of its shape
+                        continue;
                     }
                     const int slot = eng_.admit(Q, r);
                     if (slot < 0) { give_back(Q); loop_err_ = slot; break; }
@@ -296,7 +309,7 @@ private:
                     r->state = 1;
                     r->t_admit = wall_s();
                     ++running_;
-                    queue_.pop_front();
+                    it = queue_.erase(it);
                 }
             }
             done.clear();
