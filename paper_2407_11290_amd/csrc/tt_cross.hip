@@ -360,6 +360,7 @@ template <typename V> int Problem::run_impl()
             SweepArgs a;
             a.sweep = launched;
             a.nk = nk;
+            a.S = hP.S;
             int units = 0;
             size_t lds = 0;
             for (int u = 0; u < nk; ++u) {

@@ -244,6 +244,7 @@ struct ProbDev {
 struct SweepArgs {
     int sweep;
     int nk;
+    ProbState *S;                 // the problem's state (saves a dependent load)
 };
 
 }  // namespace ttc

@@ -439,10 +439,8 @@ __device__ inline double fp64_check_wave(const ProbDev *P, const KDev &K, int u,
 constexpr int NTC = 512;
 
 template <typename V>
-__device__ void commit_body(const ProbDev *__restrict__ P, int sweep)
+__device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int sweep)
 {
-    ProbState *S = P->S;
-    if (S->stop) return;
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
     constexpr int NW = NTC / 64;
     const int nk = P->nk, d = P->d, par = sweep & 1;
@@ -451,18 +449,35 @@ __device__ void commit_body(const ProbDev *__restrict__ P, int sweep)
     __shared__ uint64_t s_wk[TT_MAX_D];
     __shared__ int s_prop[TT_MAX_D], s_rold[TT_MAX_D + 1], s_rnew[TT_MAX_D + 1];
     __shared__ unsigned long long s_bytes[TT_MAX_D], s_new[TT_MAX_D], s_piv[TT_MAX_D];
+    __shared__ int s_stop;
+    __shared__ double s_tau;
+    __shared__ unsigned long long s_acc[3];
+    // one round of loads: stop flag, shapes, ranks, threshold, counters
     if (tid < nk) ks[tid] = S->ks[tid];
     if (tid <= d) s_rold[tid] = S->r[par][tid];
+    if (tid == NTC - 1) { s_stop = S->stop; s_tau = S->tau; }
+    if (tid == NTC - 2) { s_acc[0] = S->alg_bytes; s_acc[1] = S->new_entries; s_acc[2] = S->pivoted; }
     __syncthreads();
-    // best candidate per unfolding: wave w scans unfoldings w, w+NW, ...
+    if (s_stop) return;
+    // best candidate per unfolding: wave w scans unfoldings w, w+NW, ...,
+    // with CB candidates per lane in flight at once
+    constexpr int CB = 8;
     for (int u = wid; u < nk; u += NW) {
         const KDev &K = P->kd[u];
         const int ntl = ((ks[u].nr / K.nk) * K.RTp) * ((ks[u].nc / K.nk1) * K.CTq);
         double bv = -1.0, bs = 0.0;
         uint64_t bk = ~0ULL;
-        for (int i = lane; i < ntl; i += 64) {
-            const Cand c = K.cand[i];
-            if (better(c.v, c.key, bv, bk)) { bv = c.v; bk = c.key; bs = c.sv; }
+        for (int i0 = 0; i0 < ntl; i0 += 64 * CB) {
+            Cand c[CB];
+#pragma unroll
+            for (int j = 0; j < CB; ++j) {
+                const int i = i0 + lane + 64 * j;
+                if (i < ntl) c[j] = K.cand[i];
+                else { c[j].v = -1.0; c[j].key = ~0ULL; c[j].sv = 0.0; }
+            }
+#pragma unroll
+            for (int j = 0; j < CB; ++j)
+                if (better(c[j].v, c[j].key, bv, bk)) { bv = c[j].v; bk = c[j].key; bs = c[j].sv; }
         }
         wave_best(bv, bk, bs);
         if (lane == 0) { s_wv[u] = bv; s_wk[u] = bk; s_wsv[u] = bs; }
@@ -483,7 +498,7 @@ __device__ void commit_body(const ProbDev *__restrict__ P, int sweep)
             p64 = fp64_check_wave(P, K, u, rk, row, col, w64, v64);
             e = fabs(p64);
         }
-        const bool over = found && e > S->tau;
+        const bool over = found && e > s_tau;
         const bool propose = over && rk < P->r_max && rk < K.rk_cap;
         if (propose) {
             const int z = rk;
@@ -549,12 +564,16 @@ __device__ void commit_body(const ProbDev *__restrict__ P, int sweep)
     }
     if (tid == 0) {
         int any = 0;
+        unsigned long long ab = s_acc[0], ne = s_acc[1], pv = s_acc[2];
         for (int u = 0; u < nk; ++u) {
             any |= s_prop[u];
-            S->alg_bytes += s_bytes[u];
-            S->new_entries += s_new[u];
-            S->pivoted += s_piv[u];
+            ab += s_bytes[u];
+            ne += s_new[u];
+            pv += s_piv[u];
         }
+        S->alg_bytes = ab;
+        S->new_entries = ne;
+        S->pivoted = pv;
         const int stop = (!any || S->err) ? 1 : 0;
         S->stop = stop;
         S->sweeps = sweep + 1;
@@ -577,7 +596,7 @@ __device__ void commit_body(const ProbDev *__restrict__ P, int sweep)
 template <typename V>
 static __global__ void __launch_bounds__(NTC) k_commit(const ProbDev *__restrict__ P, SweepArgs a)
 {
-    commit_body<V>(P, a.sweep);
+    commit_body<V>(P, a.S, a.sweep);
 }
 
 // ---------------------------------------------------------------------------
@@ -1033,7 +1052,7 @@ template <typename V>
 static __global__ void __launch_bounds__(NTC) k_commit_b(const ProbDev *__restrict__ Pa, BatchMap bm)
 {
     const ProbDev *P = Pa + bm.p[blockIdx.x];
-    commit_body<V>(P, P->S->sweeps);
+    commit_body<V>(P, P->S, P->S->sweeps);
 }
 
 // Cores of every problem from its final ranks (those of its last commit).
