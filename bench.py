@@ -144,7 +144,7 @@ def bench_serve(args):
     from paper_2407_11290_amd.workloads import served_trace
     N = args.requests
     specs = served_trace(count=N)
-    srv = Server(int(args.budget_gib * (1 << 30)), max_slots=256, r_max=32, grid=2)
+    srv = Server(int(args.budget_gib * (1 << 30)), max_slots=args.slots, r_max=32, grid=2)
 
     def run_all(arrivals):
         t0 = time.perf_counter()
@@ -245,6 +245,7 @@ def main():
     ap.add_argument("--rate-frac", type=float, default=0.8, help="serve: arrival rate / measured capacity")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="serve: HBM budget of the server")
     ap.add_argument("--alone", type=int, default=200, help="serve: requests timed one at a time")
+    ap.add_argument("--slots", type=int, default=64, help="serve: solves in flight at most")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain copy kernel (out = -in, FP64) over this many MiB, five times; "
                          "its FETCH_SIZE/WRITE_SIZE counters scale the search kernel's")
@@ -330,7 +331,7 @@ def main():
         "config": {"workload": "hilbert6d_n64_grid2x2x2x2x2x2_eps1e-8_fp64", "d": 6, "n": 64,
                    "grid": GRID, "eps": EPS, "seeds": SEEDS, "ranks_last": ranks},
         "time_to_eps_ms": {"median": statistics.median(tte) * 1e3, "min": min(tte) * 1e3},
-        "roofline": {"kernel": "k_sweep<double>", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "roofline": {"kernel": "k_sweep<double, Hilbert>", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": counted_traffic(),
                      "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_launch * 1e6,
                      "launches": launches,
