@@ -111,6 +111,7 @@ int Engine::admit(Problem *Q, void *user)
     D.run.eps = Q->eps;
     D.run.ns = Q->opt.n_samples;
     D.run.vals = Q->d_vals;
+    D.run.spart = Q->d_spart;
     D.run.cores = Q->d_cores;
     D.run.verify_R = s.verify_R;
     std::memset(&hm[i], 0, sizeof(HostMirror));
@@ -126,13 +127,13 @@ template <typename V> int Engine::launch_setup(std::vector<int> &ids)
         const int na = (int)std::min<size_t>(MAXB, ids.size() - c0);
         BatchMap bm;
         bm.na = na;
-        int xs = 64, maxnk = 1, xi = 1;
+        int xs = 1, maxnk = 1, xi = 1;
         for (int a = 0; a < na; ++a) {
             const Slot &s = slots[ids[c0 + a]];
             const Problem &Q = *s.Q;
             bm.p[a] = (uint16_t)s.idx;
             bm.boff[a] = a;
-            xs = std::max(xs, (Q.opt.n_samples + NT - 1) / NT);
+            xs = std::max(xs, sample_blocks(Q.opt.n_samples));
             maxnk = std::max(maxnk, Q.d - 1);
             for (int u = 0; u < Q.d - 1; ++u) xi = std::max(xi, (Q.n[u] * Q.n[u + 1] + NT - 1) / NT);
         }

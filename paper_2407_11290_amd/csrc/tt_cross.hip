@@ -286,6 +286,7 @@ int Problem::allocate()
     cores_cap += (int64_t)rc[d - 1] * n[d - 1];
     if ((st = dalloc((void **)&d_cores, sizeof(double) * cores_cap)) != TT_OK) return st;
     if ((st = dalloc((void **)&d_vals, sizeof(double) * opt.n_samples)) != TT_OK) return st;
+    if ((st = dalloc((void **)&d_spart, sizeof(SamplePart) * sample_blocks(opt.n_samples))) != TT_OK) return st;
     if ((st = dalloc((void **)&d_part, sizeof(double) * 2 * NBV)) != TT_OK) return st;
     if ((st = dalloc((void **)&H.S, sizeof(ProbState))) != TT_OK) return st;
     HIPCHK(hipHostMalloc((void **)&hm, sizeof(HostMirror), hipHostMallocMapped | hipHostMallocCoherent));
@@ -332,8 +333,8 @@ template <typename V> int Problem::run_impl()
     // a1: samples -> rms, tau, first pivot; initial superblocks (the sample
     // kernel also clears the pivot maps)
     const int ns = opt.n_samples;
-    k_samples<<<std::max(64, (ns + NT - 1) / NT), NT, 0, stream>>>(dP, opt.seed, ns, d_vals);
-    k_setup<V><<<1, NT, 0, stream>>>(dP, opt.seed, ns, d_vals, eps);
+    k_samples<<<sample_blocks(ns), NT, 0, stream>>>(dP, opt.seed, ns, d_vals, d_spart);
+    k_setup<V><<<1, NT, 0, stream>>>(dP, opt.seed, ns, d_spart, eps);
     {
         int maxe = 1;
         for (int u = 0; u < nk; ++u) maxe = std::max(maxe, n[u] * n[u + 1]);
@@ -486,7 +487,8 @@ int Problem::prepare()
 {
     resolve_geometry();
     if (allocated && (alloc_fp32 != fp32 || alloc_rmax != opt.r_max || alloc_tr != opt.tile_rows ||
-                      alloc_tc != opt.tile_cols || std::memcmp(alloc_grid, grid, sizeof grid) != 0)) {
+                      alloc_tc != opt.tile_cols || alloc_ns != opt.n_samples ||
+                      std::memcmp(alloc_grid, grid, sizeof grid) != 0)) {
         for (void *p : allocs) (void)hipFree(p);
         allocs.clear();
         if (hm) { (void)hipHostFree(hm); hm = nullptr; }
@@ -498,6 +500,7 @@ int Problem::prepare()
     alloc_rmax = opt.r_max;
     alloc_tr = opt.tile_rows;
     alloc_tc = opt.tile_cols;
+    alloc_ns = opt.n_samples;
     std::memcpy(alloc_grid, grid, sizeof grid);
     ran = false;
     return TT_OK;

@@ -218,6 +218,23 @@ struct HostMirror {                // fine-grained host memory, written by the d
     int r[TT_MAX_D + 1];
 };
 
+// Partial result of one workgroup of the sample pass (see samples_body).
+struct SamplePart {
+    double sumsq;
+    double bv, bs;                // largest |value|, its signed value
+    uint64_t bk;                  // its sample index
+    int bad;                      // a non-finite value was seen
+    int pad;
+};
+
+// Workgroups of the sample pass: one sample per thread, at least 64 (the
+// pass also clears the pivot masks).
+__host__ __device__ inline int sample_blocks(int ns)
+{
+    const int b = (ns + NT - 1) / NT;
+    return b > 64 ? b : 64;
+}
+
 // Per-run inputs of a problem solved inside a batch (a single solve passes
 // them as kernel arguments instead).
 struct RunDev {
@@ -225,6 +242,7 @@ struct RunDev {
     double eps;
     int ns;                       // samples
     double *vals;                 // ns sample values
+    SamplePart *spart;            // sample_blocks(ns) partial results
     double *cores;                // output cores
     int64_t verify_R;             // samples of the sampled-error check (0: none)
 };

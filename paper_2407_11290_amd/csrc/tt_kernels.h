@@ -603,41 +603,70 @@ static __global__ void __launch_bounds__(NTC) k_commit(const ProbDev *__restrict
 // Setup: samples, rms, first pivot, initial superblocks.
 // ---------------------------------------------------------------------------
 // Evaluates the sample entries and clears the pivot maps of every unfolding.
-__device__ inline void samples_body(const ProbDev *__restrict__ P, uint64_t seed, int ns, double *vals, int blk,
-                                    int nblk)
+// Per-workgroup partial results of the sample pass: the sum of the squares of
+// its NT samples as a complete binary tree over adjacent pairs (zeros past
+// ns), and its largest |sample| (lowest index on ties).  Workgroup sums are
+// the subtrees of the tree over all samples, so combining them pairwise gives
+// that tree's value exactly.
+__device__ inline void samples_body(const ProbDev *__restrict__ P, uint64_t seed, int ns, double *vals,
+                                    SamplePart *part, int blk, int nblk)
 {
-    const int s = blk * NT + threadIdx.x;
+    const int tid = threadIdx.x, s = blk * NT + tid;
     const int d = P->d;
     for (int u = 0; u < P->nk; ++u) {
         const KDev &K = P->kd[u];
         for (int i = s; i < K.rowcap; i += nblk * NT) K.rpiv[i] = 0;
         for (int j = s; j < K.colcap; j += nblk * NT) K.cpiv[j] = 0;
     }
-    if (s >= ns) return;
-    int idx[TT_MAX_D];
-    for (int j = 0; j < d; ++j)
-        idx[j] = (int)(sm64_at(seed, (uint64_t)s * d + j) % (uint64_t)P->F.n[j]);
-    vals[s] = fn_value<double>(P->F, idx);
+    double v = 0.0;
+    if (s < ns) {
+        int idx[TT_MAX_D];
+        for (int j = 0; j < d; ++j)
+            idx[j] = (int)(sm64_at(seed, (uint64_t)s * d + j) % (uint64_t)P->F.n[j]);
+        v = fn_value<double>(P->F, idx);
+        vals[s] = v;
+    }
+    const double a = fabs(v);
+    const int bad = (s < ns && !(a <= 1.7976931348623157e308)) ? 1 : 0;
+    // adjacent-pair tree: within the wavefront by shuffles, then over the
+    // four wavefronts
+    double q = __dmul_rn(v, v);
+    for (int off = 1; off < 64; off <<= 1) {
+        const double o = __shfl_down(q, off, 64);
+        if ((tid & (2 * off - 1)) == 0) q = __dadd_rn(q, o);
+    }
+    __shared__ double wsum[NT / 64];
+    __shared__ int sbad;
+    if (tid == 0) sbad = 0;
+    __syncthreads();
+    if ((tid & 63) == 0) wsum[tid >> 6] = q;
+    if (bad) atomicOr(&sbad, 1);
+    double bv = (s < ns) ? a : -1.0, bs = v;
+    uint64_t bk = (s < ns) ? (uint64_t)s : ~0ULL;
+    block_best(bv, bk, bs);             // synchronises the workgroup
+    if (tid == 0 && blk < sample_blocks(ns)) {     // a batched launch may run more workgroups
+        SamplePart &o = part[blk];
+        o.sumsq = __dadd_rn(__dadd_rn(wsum[0], wsum[1]), __dadd_rn(wsum[2], wsum[3]));
+        o.bv = bv;
+        o.bs = bs;
+        o.bk = bk;
+        o.bad = sbad;
+    }
 }
 
 static __global__ void __launch_bounds__(NT) k_samples(const ProbDev *__restrict__ P, uint64_t seed, int ns,
-                                                  double *vals)
+                                                  double *vals, SamplePart *part)
 {
-    samples_body(P, seed, ns, vals, blockIdx.x, gridDim.x);
+    samples_body(P, seed, ns, vals, part, blockIdx.x, gridDim.x);
 }
 
-// Pairwise sum of v[lo..lo+c) squared (c a power of two; entries past ns are
-// zero): the chunk is cut into 64-leaf blocks, each summed as a complete
-// binary tree in registers, and the block sums are combined the same way.
-__device__ inline double tree64_sumsq(const double *v, int lo, int ns)
+// Pairwise sum of x(lo..lo+c) over a complete binary tree (c a power of two,
+// entries at or past hi are zero), 64 leaves at a time in registers.
+template <typename X> __device__ inline double tree64_sum(X x, int lo, int hi)
 {
     double q[64];
 #pragma unroll
-    for (int b = 0; b < 64; ++b) {
-        const int g = lo + b;
-        const double t = (g < ns) ? v[g] : 0.0;
-        q[b] = __dmul_rn(t, t);
-    }
+    for (int b = 0; b < 64; ++b) q[b] = (lo + b < hi) ? x(lo + b) : 0.0;
 #pragma unroll
     for (int w = 64; w > 1; w >>= 1) {
 #pragma unroll
@@ -646,21 +675,23 @@ __device__ inline double tree64_sumsq(const double *v, int lo, int ns)
     return q[0];
 }
 
-__device__ inline double chunk_pairwise_sumsq(const double *v, int lo, int c, int ns)
+template <typename X> __device__ inline double chunk_pairwise_sum(X x, int lo, int c, int n)
 {
-    if (c <= 64) return tree64_sumsq(v, lo, ns);   // zero leaves past c leave the left subtree exact
+    // a chunk of c <= 64 leaves is the left subtree of a 64-leaf tree whose
+    // other leaves are zero, so it is summed exactly with them
+    if (c <= 64) return tree64_sum(x, lo, min(lo + c, n));
     double st[32];
     int lv[32];
     int top = 0;
     for (int i = 0; i < c; i += 64) {
-        double x = tree64_sumsq(v, lo + i, ns);
+        double y = tree64_sum(x, lo + i, min(lo + i + 64, n));
         int level = 6;
         while (top > 0 && lv[top - 1] == level) {
-            x = __dadd_rn(st[top - 1], x);
+            y = __dadd_rn(st[top - 1], y);
             --top;
             ++level;
         }
-        st[top] = x;
+        st[top] = y;
         lv[top] = level;
         ++top;
     }
@@ -668,58 +699,37 @@ __device__ inline double chunk_pairwise_sumsq(const double *v, int lo, int c, in
 }
 
 template <typename V>
-__device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns, const double *vals, double eps)
+__device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns, const SamplePart *part, double eps)
 {
     ProbState *S = P->S;
     const int tid = threadIdx.x, d = P->d;
+    const int nb = (ns + NT - 1) / NT;                 // workgroups that saw samples
     double bv = -1.0, bs = 0.0;
     uint64_t bk = ~0ULL;
     int bad = 0;
-    for (int s = tid; s < ns; s += NT) {
-        const double a = fabs(vals[s]);
-        if (!(a <= 1.7976931348623157e308)) bad = 1;          // not finite
-        if (better(a, (uint64_t)s, bv, bk)) { bv = a; bk = (uint64_t)s; bs = vals[s]; }
+    for (int b = tid; b < nb; b += NT) {
+        const SamplePart &o = part[b];
+        bad |= o.bad;
+        if (better(o.bv, o.bk, bv, bk)) { bv = o.bv; bk = o.bk; bs = o.bs; }
     }
     __shared__ int sbad;
     if (tid == 0) sbad = 0;
     __syncthreads();
     if (bad) atomicOr(&sbad, 1);
     block_best(bv, bk, bs);
-    // sum of squares as a balanced binary tree over the zero-padded samples:
-    // each thread reduces an aligned power-of-two chunk, then the 256 chunk
-    // sums are combined pairwise (adjacent lanes, then adjacent waves)
+    // the workgroup sums are the level-log2(NT) nodes of the tree over the
+    // zero-padded samples; the rest of the tree runs over them
     int m = 1;
-    while (m < ns) m <<= 1;
+    while (m < nb) m <<= 1;
     const int c = (m >= NT) ? m / NT : 1;
-    // a chunk of c <= 64 leaves is the left part of its 64-leaf tree, so it
-    // is summed exactly by tree64 with zeros past the chunk
-    double part = 0.0;
-    if (tid * c < m) {
-        if (c >= 64) part = chunk_pairwise_sumsq(vals, tid * c, c, ns);
-        else {
-            const double *vv = vals;
-            int lo = tid * c, hi = lo + c;
-            double q[64];
-#pragma unroll
-            for (int b = 0; b < 64; ++b) {
-                const int g = lo + b;
-                const double t = (g < hi && g < ns) ? vv[g] : 0.0;
-                q[b] = __dmul_rn(t, t);
-            }
-#pragma unroll
-            for (int w = 64; w > 1; w >>= 1) {
-#pragma unroll
-                for (int i = 0; i < w / 2; ++i) q[i] = __dadd_rn(q[2 * i], q[2 * i + 1]);
-            }
-            part = q[0];
-        }
-    }
+    double q = 0.0;
+    if (tid * c < m) q = chunk_pairwise_sum([&](int i) { return part[i].sumsq; }, tid * c, c, nb);
     for (int off = 1; off < 64; off <<= 1) {
-        const double o = __shfl_down(part, off, 64);
-        if ((tid & (2 * off - 1)) == 0) part = __dadd_rn(part, o);
+        const double o = __shfl_down(q, off, 64);
+        if ((tid & (2 * off - 1)) == 0) q = __dadd_rn(q, o);
     }
     __shared__ double wsum[NT / 64];
-    if ((tid & 63) == 0) wsum[tid >> 6] = part;
+    if ((tid & 63) == 0) wsum[tid >> 6] = q;
     __shared__ int i0[TT_MAX_D];
     __shared__ double p0s;
     __syncthreads();
@@ -774,9 +784,9 @@ __device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns,
 
 template <typename V>
 static __global__ void __launch_bounds__(NT) k_setup(const ProbDev *__restrict__ P, uint64_t seed, int ns,
-                                                const double *vals, double eps)
+                                                const SamplePart *part, double eps)
 {
-    setup_body<V>(P, seed, ns, vals, eps);
+    setup_body<V>(P, seed, ns, part, eps);
 }
 
 // E = X on the initial superblocks (one prefix, one suffix: the first pivot's).
@@ -815,6 +825,11 @@ static __global__ void __launch_bounds__(NT) k_init_eval(const ProbDev *__restri
 //   T <- [T + delta s T(i_z, :), -delta s].
 // Workgroups past the last unfolding's rows evaluate G_d = X(I_{<=d-1}, :).
 // ---------------------------------------------------------------------------
+// The core workgroups are one wavefront each: its lanes run in lockstep and
+// the LDS serves one wavefront's accesses in order, so ordering the accesses
+// in the compiler is all a barrier has to do.
+__device__ inline void wave_sync() { __builtin_amdgcn_wave_barrier(); }
+
 struct CoreArgs {
     int nk;
     int ranks[TT_MAX_D + 1];
@@ -884,13 +899,13 @@ __device__ void cores_body(const ProbDev *__restrict__ P, const CoreArgs &a, dou
             Ap[lane * st + z] = fn_value_ix<double>(P->F, [&](int j) { return j < k ? It[j] : Jz[j - k]; });
         }
     }
-    __syncthreads();
+    wave_sync();
     const double a11 = Ap[0];
     for (int z = 0; z < rk; ++z) {
         Tb[z * A4W + lane] = (z == 0) ? Ab[lane] / a11 : 0.0;
         if (lane < rk) Tp[lane * st + z] = (z == 0) ? Ap[lane * st] / a11 : 0.0;
     }
-    __syncthreads();
+    wave_sync();
     for (int z = 1; z < rk; ++z) {
         double sp = 0.0, sb;
         {
@@ -905,17 +920,17 @@ __device__ void cores_body(const ProbDev *__restrict__ P, const CoreArgs &a, dou
         }
         const double delta = 1.0 / (-__shfl(sp, z, 64));
         const double cb = delta * sb, cp = delta * sp;
-        __syncthreads();                        // every lane has read T before it changes
+        wave_sync();                            // every lane has read T before it changes
         for (int zz = 0; zz < z; ++zz) {
             const double tr = Tp[z * st + zz];  // T(i_z, zz) before this step
             Tb[zz * A4W + lane] = __fma_rn(cb, tr, Tb[zz * A4W + lane]);
-            __syncthreads();
+            wave_sync();
             if (lane < rk) Tp[lane * st + zz] = __fma_rn(cp, tr, Tp[lane * st + zz]);
-            __syncthreads();
+            wave_sync();
         }
         Tb[z * A4W + lane] = -cb;
         if (lane < rk) Tp[lane * st + z] = -cp;
-        __syncthreads();
+        wave_sync();
     }
     const int rows = min(A4W, nr - i0);
     double *Gk = G + a.goff[u] + (int64_t)i0 * rk;
@@ -1022,14 +1037,14 @@ __device__ inline int batch_find(const BatchMap &bm, int b)
 static __global__ void __launch_bounds__(NT) k_samples_b(const ProbDev *__restrict__ Pa, BatchMap bm)
 {
     const ProbDev *P = Pa + bm.p[blockIdx.y];
-    samples_body(P, P->run.seed, P->run.ns, P->run.vals, blockIdx.x, gridDim.x);
+    samples_body(P, P->run.seed, P->run.ns, P->run.vals, P->run.spart, blockIdx.x, gridDim.x);
 }
 
 template <typename V>
 static __global__ void __launch_bounds__(NT) k_setup_b(const ProbDev *__restrict__ Pa, BatchMap bm)
 {
     const ProbDev *P = Pa + bm.p[blockIdx.x];
-    setup_body<V>(P, P->run.seed, P->run.ns, P->run.vals, P->run.eps);
+    setup_body<V>(P, P->run.seed, P->run.ns, P->run.spart, P->run.eps);
 }
 
 template <typename V>
