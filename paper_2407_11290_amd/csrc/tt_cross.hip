@@ -389,7 +389,8 @@ template <typename V> int Problem::run_impl()
             }
             ++launched;
             for (int k = 1; k <= d - 1; ++k) rub[k] = std::min(rub[k] + 1, rc[k]);
-            k_commit<V><<<1, NTC, 0, stream>>>(dP, a);
+            if (fn.dev.id == TT_FN_HILBERT) k_commit<V, TT_FN_HILBERT><<<1, NTC, 0, stream>>>(dP, a);
+            else k_commit<V, 0><<<1, NTC, 0, stream>>>(dP, a);
         }
         HIPCHK(hipGetLastError());
         // wait for the device to finish another sweep
@@ -430,7 +431,8 @@ template <typename V> int Problem::run_impl()
     {
         const size_t lc = sizeof(double) * ((size_t)2 * maxr * (maxr + 1) + (size_t)2 * maxr * A4W);
         if (lc > (size_t)lds_limit) return set_err(TT_EINVAL, "rank %d too large for the core kernel", maxr);
-        k_cores<<<blocks, A4W, lc, stream>>>(dP, ca, d_cores);
+        if (fn.dev.id == TT_FN_HILBERT) k_cores<TT_FN_HILBERT><<<blocks, A4W, lc, stream>>>(dP, ca, d_cores);
+        else k_cores<0><<<blocks, A4W, lc, stream>>>(dP, ca, d_cores);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev1, stream));

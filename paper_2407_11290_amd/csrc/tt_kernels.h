@@ -398,6 +398,7 @@ static __global__ void __launch_bounds__(NT) k_sweep(const ProbDev *__restrict__
 // wavefront; lane z ends with the FP64 row factor w = R(row, gamma_z) before
 // pivot z and the column factor v = R(rho_z, col) before pivot z, over p64_z.
 // ---------------------------------------------------------------------------
+template <int FNS>
 __device__ inline double fp64_check_wave(const ProbDev *P, const KDev &K, int u, int rk, int row, int col,
                                          double &w, double &v)
 {
@@ -412,10 +413,10 @@ __device__ inline double fp64_check_wave(const ProbDev *P, const KDev &K, int u,
     if (lane < rk) {
         const int *Jz = K.Jfull + lane * nj;
         const int *Iz = K.Ifull + lane * k;
-        w = fn_value_ix<double>(P->F, [&](int j) { return j < npre ? preI[j] : (j == k - 1 ? ik : Jz[j - k]); });
-        v = fn_value_ix<double>(P->F, [&](int j) { return j < k ? Iz[j] : (j == k ? ik1 : sufJ[j - k - 1]); });
+        w = fn_value_ix<double, FNS>(P->F, [&](int j) { return j < npre ? preI[j] : (j == k - 1 ? ik : Jz[j - k]); });
+        v = fn_value_ix<double, FNS>(P->F, [&](int j) { return j < k ? Iz[j] : (j == k ? ik1 : sufJ[j - k - 1]); });
     }
-    const double xrc = fn_value_ix<double>(P->F, [&](int j) {
+    const double xrc = fn_value_ix<double, FNS>(P->F, [&](int j) {
         return j < npre ? preI[j] : (j == k - 1 ? ik : (j == k ? ik1 : sufJ[j - k - 1]));
     });
     const int rc = P->rcap;
@@ -438,7 +439,7 @@ __device__ inline double fp64_check_wave(const ProbDev *P, const KDev &K, int u,
 // unfolding u, and thread 0 publishes the outcome.
 constexpr int NTC = 512;
 
-template <typename V>
+template <typename V, int FNS>
 __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int sweep)
 {
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
@@ -493,10 +494,12 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
         const bool found = bv >= 0.0;
         const int row = (int)(bk >> 32), col = (int)(bk & 0xffffffffULL);
         double e = found ? bv : 0.0, p64 = 0.0, w64 = 0.0, v64 = 0.0;
-        if (P->fp32 && found) {
-            // FP64 check of the FP32 candidate: stop test and pivot block in FP64
-            p64 = fp64_check_wave(P, K, u, rk, row, col, w64, v64);
-            e = fabs(p64);
+        if constexpr (sizeof(V) == 4) {
+            if (found) {
+                // FP64 check of the FP32 candidate: stop test and pivot block in FP64
+                p64 = fp64_check_wave<FNS>(P, K, u, rk, row, col, w64, v64);
+                e = fabs(p64);
+            }
         }
         const bool over = found && e > s_tau;
         const bool propose = over && rk < P->r_max && rk < K.rk_cap;
@@ -593,10 +596,10 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
     }
 }
 
-template <typename V>
+template <typename V, int FNS = 0>
 static __global__ void __launch_bounds__(NTC) k_commit(const ProbDev *__restrict__ P, SweepArgs a)
 {
-    commit_body<V>(P, a.S, a.sweep);
+    commit_body<V, FNS>(P, a.S, a.sweep);
 }
 
 // ---------------------------------------------------------------------------
@@ -862,6 +865,7 @@ __host__ __device__ inline int make_core_args(int d, const int *n, const int *r,
     return rb + (int)((gd + A4W - 1) / A4W);
 }
 
+template <int FNS>
 __device__ void cores_body(const ProbDev *__restrict__ P, const CoreArgs &a, double *G, int bid)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -873,7 +877,7 @@ __device__ void cores_body(const ProbDev *__restrict__ P, const CoreArgs &a, dou
         if (e >= (int64_t)rd * nd) return;
         const int pp = (int)(e / nd), i = (int)(e - (int64_t)pp * nd);
         const int *Ip = K.Ifull + pp * (d - 1);
-        G[a.goff[d - 1] + e] = fn_value_ix<double>(P->F, [&](int j) { return j < d - 1 ? Ip[j] : i; });
+        G[a.goff[d - 1] + e] = fn_value_ix<double, FNS>(P->F, [&](int j) { return j < d - 1 ? Ip[j] : i; });
         return;
     }
     int u = 0;
@@ -888,15 +892,24 @@ __device__ void cores_body(const ProbDev *__restrict__ P, const CoreArgs &a, dou
     const int i0 = (bid - a.rowblocks[u]) * A4W, i = i0 + lane;
     const bool act = i < nr;
     const int p = act ? i / K.nk : 0, ik = act ? i - p * K.nk : 0;
-    const int *preI = (k >= 2) ? P->kd[u - 1].Ifull + p * (k - 1) : nullptr;
+    // one round of loads: the pivots' index tuples and every lane's prefix
+    __shared__ int sJ[TT_MAX_RANK * TT_MAX_D], sI[TT_MAX_RANK * TT_MAX_D], sPre[A4W * TT_MAX_D];
+    for (int e = lane; e < rk * nj; e += A4W) sJ[e] = K.Jfull[e];
+    for (int e = lane; e < rk * k; e += A4W) sI[e] = K.Ifull[e];
+    if (k >= 2) {
+        const int *preI = P->kd[u - 1].Ifull + p * (k - 1);
+        for (int j = 0; j < k - 1; ++j) sPre[lane * TT_MAX_D + j] = preI[j];
+    }
+    wave_sync();
+#pragma unroll 2
     for (int z = 0; z < rk; ++z) {
-        const int *Jz = K.Jfull + z * nj;
-        Ab[z * A4W + lane] = act ? fn_value_ix<double>(P->F, [&](int j) {
-            return j < k - 1 ? preI[j] : (j == k - 1 ? ik : Jz[j - k]);
+        const int *Jz = sJ + z * nj;
+        Ab[z * A4W + lane] = act ? fn_value_ix<double, FNS>(P->F, [&](int j) {
+            return j < k - 1 ? sPre[lane * TT_MAX_D + j] : (j == k - 1 ? ik : Jz[j - k]);
         }) : 0.0;
         if (lane < rk) {
-            const int *It = K.Ifull + lane * k;
-            Ap[lane * st + z] = fn_value_ix<double>(P->F, [&](int j) { return j < k ? It[j] : Jz[j - k]; });
+            const int *It = sI + lane * k;
+            Ap[lane * st + z] = fn_value_ix<double, FNS>(P->F, [&](int j) { return j < k ? It[j] : Jz[j - k]; });
         }
     }
     wave_sync();
@@ -907,26 +920,29 @@ __device__ void cores_body(const ProbDev *__restrict__ P, const CoreArgs &a, dou
     }
     wave_sync();
     for (int z = 1; z < rk; ++z) {
-        double sp = 0.0, sb;
-        {
-            double dot = 0.0;
-            for (int zz = 0; zz < z; ++zz) dot = __fma_rn(Tb[zz * A4W + lane], Ap[zz * st + z], dot);
-            sb = dot - Ab[z * A4W + lane];
+        // the two dot products, each summed in ascending zz, side by side
+        // and unrolled so that their LDS reads overlap
+        double dotb = 0.0, dotp = 0.0;
+        const bool piv_lane = lane < rk;
+#pragma unroll 4
+        for (int zz = 0; zz < z; ++zz) {
+            const double az = Ap[zz * st + z];
+            dotb = __fma_rn(Tb[zz * A4W + lane], az, dotb);
+            if (piv_lane) dotp = __fma_rn(Tp[lane * st + zz], az, dotp);
         }
-        if (lane < rk) {
-            double dot = 0.0;
-            for (int zz = 0; zz < z; ++zz) dot = __fma_rn(Tp[lane * st + zz], Ap[zz * st + z], dot);
-            sp = dot - Ap[lane * st + z];
-        }
+        const double sb = dotb - Ab[z * A4W + lane];
+        const double sp = piv_lane ? dotp - Ap[lane * st + z] : 0.0;
         const double delta = 1.0 / (-__shfl(sp, z, 64));
         const double cb = delta * sb, cp = delta * sp;
         wave_sync();                            // every lane has read T before it changes
+        // every lane reads T(i_z, zz) in the same instruction before lane z
+        // (the only writer of that entry) updates it, and the other entries
+        // each lane touches are its own, so no barrier is needed in here
+#pragma unroll 4
         for (int zz = 0; zz < z; ++zz) {
             const double tr = Tp[z * st + zz];  // T(i_z, zz) before this step
             Tb[zz * A4W + lane] = __fma_rn(cb, tr, Tb[zz * A4W + lane]);
-            wave_sync();
             if (lane < rk) Tp[lane * st + zz] = __fma_rn(cp, tr, Tp[lane * st + zz]);
-            wave_sync();
         }
         Tb[z * A4W + lane] = -cb;
         if (lane < rk) Tp[lane * st + z] = -cp;
@@ -940,9 +956,10 @@ __device__ void cores_body(const ProbDev *__restrict__ P, const CoreArgs &a, dou
     }
 }
 
+template <int FNS = 0>
 static __global__ void __launch_bounds__(A4W) k_cores(const ProbDev *__restrict__ P, CoreArgs a, double *G)
 {
-    cores_body(P, a, G, blockIdx.x);
+    cores_body<FNS>(P, a, G, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1067,7 +1084,7 @@ template <typename V>
 static __global__ void __launch_bounds__(NTC) k_commit_b(const ProbDev *__restrict__ Pa, BatchMap bm)
 {
     const ProbDev *P = Pa + bm.p[blockIdx.x];
-    commit_body<V>(P, P->S, P->S->sweeps);
+    commit_body<V, 0>(P, P->S, P->S->sweeps);
 }
 
 // Cores of every problem from its final ranks (those of its last commit).
@@ -1080,7 +1097,7 @@ static __global__ void __launch_bounds__(A4W) k_cores_b(const ProbDev *__restric
     CoreArgs a;
     int64_t len;
     make_core_args(P->d, P->F.n, r, a, len);
-    cores_body(P, a, P->run.cores, blockIdx.x - bm.boff[i]);
+    cores_body<0>(P, a, P->run.cores, blockIdx.x - bm.boff[i]);
 }
 
 // Sampled-error check of every listed problem: NBV workgroups each (grid.y =
