@@ -865,6 +865,58 @@ __host__ __device__ inline int make_core_args(int d, const int *n, const int *r,
     return rb + (int)((gd + A4W - 1) / A4W);
 }
 
+// Alg. 4 on one wavefront's rows with T in registers (rk <= RM; RM = 16 fits
+// the register file, 32 does not): lane i holds
+// row i of T for the workgroup's rows, and lanes z < rk also row z of T for
+// the pivot rows (the recursion on those rows gives every delta).  The
+// operations and their order are those of the LDS version below; T(i_z, :)
+// reaches the other lanes by shuffles before lane z updates it.
+template <int RM>
+__device__ void core_alg4_regs(const double *Ap, const double *Ab, int st, int rk, int nr, int i0, double *Gk0)
+{
+    const int lane = threadIdx.x;
+    const bool piv = lane < rk;
+    double ab[RM], tb[RM], tp[RM];
+    const double a11 = Ap[0];
+#pragma unroll
+    for (int z = 0; z < RM; ++z) {
+        ab[z] = (z < rk) ? Ab[z * A4W + lane] : 0.0;
+        tb[z] = 0.0;
+        tp[z] = 0.0;
+    }
+    tb[0] = ab[0] / a11;
+    if (piv) tp[0] = Ap[lane * st] / a11;
+#pragma unroll
+    for (int z = 1; z < RM; ++z) {
+        if (z >= rk) continue;                  // uniform: every lane skips
+        double dotb = 0.0, dotp = 0.0;
+#pragma unroll
+        for (int zz = 0; zz < z; ++zz) {
+            const double az = Ap[zz * st + z];
+            dotb = __fma_rn(tb[zz], az, dotb);
+            dotp = __fma_rn(tp[zz], az, dotp);
+        }
+        const double sb = dotb - ab[z];
+        const double sp = piv ? dotp - Ap[lane * st + z] : 0.0;
+        const double delta = 1.0 / (-__shfl(sp, z, 64));
+        const double cb = delta * sb, cp = delta * sp;
+#pragma unroll
+        for (int zz = 0; zz < z; ++zz) {
+            const double tr = __shfl(tp[zz], z, 64);   // T(i_z, zz) before this step
+            tb[zz] = __fma_rn(cb, tr, tb[zz]);
+            if (piv) tp[zz] = __fma_rn(cp, tr, tp[zz]);
+        }
+        tb[z] = -cb;
+        if (piv) tp[z] = -cp;
+    }
+    if (i0 + lane < nr) {
+        double *row = Gk0 + (int64_t)(i0 + lane) * rk;
+#pragma unroll
+        for (int z = 0; z < RM; ++z)
+            if (z < rk) row[z] = tb[z];
+    }
+}
+
 template <int FNS>
 __device__ void cores_body(const ProbDev *__restrict__ P, const CoreArgs &a, double *G, int bid)
 {
@@ -901,18 +953,40 @@ __device__ void cores_body(const ProbDev *__restrict__ P, const CoreArgs &a, dou
         for (int j = 0; j < k - 1; ++j) sPre[lane * TT_MAX_D + j] = preI[j];
     }
     wave_sync();
-#pragma unroll 2
-    for (int z = 0; z < rk; ++z) {
-        const int *Jz = sJ + z * nj;
-        Ab[z * A4W + lane] = act ? fn_value_ix<double, FNS>(P->F, [&](int j) {
-            return j < k - 1 ? sPre[lane * TT_MAX_D + j] : (j == k - 1 ? ik : Jz[j - k]);
-        }) : 0.0;
+    if constexpr (FNS == TT_FN_HILBERT) {
+        // the Hilbert entry depends on the integer index sum only: add the
+        // prefix, suffix and pivot-tuple parts once, exactly, in integers
+        __shared__ long long sJs[TT_MAX_RANK];
+        long long is = 0;
         if (lane < rk) {
-            const int *It = sI + lane * k;
-            Ap[lane * st + z] = fn_value_ix<double, FNS>(P->F, [&](int j) { return j < k ? It[j] : Jz[j - k]; });
+            long long js = 0;
+            for (int j = 0; j < nj; ++j) js += sJ[lane * nj + j] + 1;
+            for (int j = 0; j < k; ++j) is += sI[lane * k + j] + 1;
+            sJs[lane] = js;
+        }
+        long long ps = ik + 1;
+        for (int j = 0; j < k - 1; ++j) ps += sPre[lane * TT_MAX_D + j] + 1;
+        wave_sync();
+        const double sh = P->F.shift;
+        for (int z = 0; z < rk; ++z) {
+            const long long js = sJs[z];
+            Ab[z * A4W + lane] = act ? 1.0 / ((double)(ps + js) + sh) : 0.0;
+            if (lane < rk) Ap[lane * st + z] = 1.0 / ((double)(is + js) + sh);
+        }
+    } else {
+        for (int z = 0; z < rk; ++z) {
+            const int *Jz = sJ + z * nj;
+            Ab[z * A4W + lane] = act ? fn_value_ix<double, FNS>(P->F, [&](int j) {
+                return j < k - 1 ? sPre[lane * TT_MAX_D + j] : (j == k - 1 ? ik : Jz[j - k]);
+            }) : 0.0;
+            if (lane < rk) {
+                const int *It = sI + lane * k;
+                Ap[lane * st + z] = fn_value_ix<double, FNS>(P->F, [&](int j) { return j < k ? It[j] : Jz[j - k]; });
+            }
         }
     }
     wave_sync();
+    if (rk <= 16) { core_alg4_regs<16>(Ap, Ab, st, rk, nr, i0, G + a.goff[u]); return; }
     const double a11 = Ap[0];
     for (int z = 0; z < rk; ++z) {
         Tb[z * A4W + lane] = (z == 0) ? Ab[lane] / a11 : 0.0;
