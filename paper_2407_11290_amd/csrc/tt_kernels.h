@@ -179,10 +179,22 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSw
     const int cpv = (tcol < g.ncols) ? K.cpiv[g.col0 + tcol] : 1;
     if (tid < npre) pre[tid] = P->kd[u - 1].Ifull[g.p * npre + tid];
     if (tid < nsuf) suf[tid] = P->kd[u + 1].Jfull[g.q * nsuf + tid];
+    // Hilbert entries depend on the integer index sum only: the pivots' tuple
+    // sums replace the tuples
+    __shared__ long long s_is[TT_MAX_RANK], s_js[TT_MAX_RANK];
     for (int z = tid; z < rk; z += NT) {
         s_rho[z] = K.rho[z];
         s_gam[z] = K.gam[z];
         s_piv[z] = (V)K.piv[z];
+        if constexpr (FNS == TT_FN_HILBERT) {
+            long long is = 0, js = 0;
+            if (!rows_old)
+                for (int j = 0; j < nj; ++j) js += K.Jfull[z * nj + j] + 1;
+            if (!cols_old)
+                for (int j = 0; j < k; ++j) is += K.Ifull[z * k + j] + 1;
+            s_is[z] = is;
+            s_js[z] = js;
+        }
     }
     for (int ii = tid; ii < g.nrows; ii += NT) s_rp[ii] = K.rpiv[g.row0 + ii];
     __syncthreads();
@@ -197,13 +209,23 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSw
             const int zp = e / rk, z = e - zp * rk;
             if (zp < z) Gr[tri(zp, z)] = E[(int64_t)s_rho[zp] * ld + s_gam[z]] / s_piv[zp];
         }
-        for (int e = tid; e < rk * g.nrows; e += NT) {
-            const int z = e / g.nrows, ii = e - z * g.nrows;
-            const int ikv = g.ik0 + ii;
-            const int *Jz = K.Jfull + z * nj;
-            Wt[z * TRm + ii] = fn_value_ix<V, FNS>(P->F, [&](int j) {
-                return j < npre ? pre[j] : (j == k - 1 ? ikv : Jz[j - k]);
-            });
+        if constexpr (FNS == TT_FN_HILBERT) {
+            long long ps = 1;
+            for (int j = 0; j < npre; ++j) ps += pre[j] + 1;
+            const V sh = (V)P->F.shift;
+            for (int e = tid; e < rk * g.nrows; e += NT) {
+                const int z = e / g.nrows, ii = e - z * g.nrows;
+                Wt[z * TRm + ii] = (V)1 / ((V)(ps + g.ik0 + ii + s_js[z]) + sh);
+            }
+        } else {
+            for (int e = tid; e < rk * g.nrows; e += NT) {
+                const int z = e / g.nrows, ii = e - z * g.nrows;
+                const int ikv = g.ik0 + ii;
+                const int *Jz = K.Jfull + z * nj;
+                Wt[z * TRm + ii] = fn_value_ix<V, FNS>(P->F, [&](int j) {
+                    return j < npre ? pre[j] : (j == k - 1 ? ikv : Jz[j - k]);
+                });
+            }
         }
     }
     if (cols_old) {
@@ -216,13 +238,23 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSw
             const int zp = e / rk, z = e - zp * rk;
             if (zp < z) Gc[tri(zp, z)] = E[(int64_t)s_rho[z] * ld + s_gam[zp]];
         }
-        for (int e = tid; e < rk * g.ncols; e += NT) {
-            const int z = e / g.ncols, jj = e - z * g.ncols;
-            const int ik1v = g.ik10 + jj;
-            const int *Iz = K.Ifull + z * k;
-            Ut[z * TCm + jj] = fn_value_ix<V, FNS>(P->F, [&](int j) {
-                return j < k ? Iz[j] : (j == k ? ik1v : suf[j - k - 1]);
-            });
+        if constexpr (FNS == TT_FN_HILBERT) {
+            long long ss = 1;
+            for (int j = 0; j < nsuf; ++j) ss += suf[j] + 1;
+            const V sh = (V)P->F.shift;
+            for (int e = tid; e < rk * g.ncols; e += NT) {
+                const int z = e / g.ncols, jj = e - z * g.ncols;
+                Ut[z * TCm + jj] = (V)1 / ((V)(s_is[z] + g.ik10 + jj + ss) + sh);
+            }
+        } else {
+            for (int e = tid; e < rk * g.ncols; e += NT) {
+                const int z = e / g.ncols, jj = e - z * g.ncols;
+                const int ik1v = g.ik10 + jj;
+                const int *Iz = K.Ifull + z * k;
+                Ut[z * TCm + jj] = fn_value_ix<V, FNS>(P->F, [&](int j) {
+                    return j < k ? Iz[j] : (j == k ? ik1v : suf[j - k - 1]);
+                });
+            }
         }
     }
     __syncthreads();
