@@ -223,6 +223,13 @@ int Problem::allocate()
         K.nk1 = n[k];
         K.rowcap = rc[k - 1] * n[k - 1];
         K.colcap = n[k] * rc[k + 1];
+        {
+            // rows of E start 256 bytes past a multiple of 512, so that the
+            // rows of a tile spread over the HBM channels instead of landing
+            // on one when the capacity is a power of two
+            const int per256 = (int)(256 / w);
+            K.ld = ((K.colcap + 2 * per256 - 1) / (2 * per256)) * (2 * per256) + per256;
+        }
         K.rk_cap = rc[k];
         // tile geometry: rows of mode k, columns of mode k+1
         int TR = opt.tile_rows > 0 ? opt.tile_rows : 32;
@@ -267,7 +274,7 @@ int Problem::allocate()
         K.rt_start = tabs; K.rt_len = tabs + R; K.rt_blk = tabs + 2 * R;
         K.ct_start = tabs + 3 * R; K.ct_len = tabs + 3 * R + Cc; K.ct_blk = tabs + 3 * R + 2 * Cc;
         const int rk = rc[k];
-        if ((st = dalloc(&K.E, (size_t)K.rowcap * K.colcap * w)) != TT_OK) return st;
+        if ((st = dalloc(&K.E, (size_t)K.rowcap * K.ld * w)) != TT_OK) return st;
         if ((st = dalloc((void **)&K.rpiv, K.rowcap)) != TT_OK) return st;
         if ((st = dalloc((void **)&K.cpiv, K.colcap)) != TT_OK) return st;
         if ((st = dalloc((void **)&K.Ifull, sizeof(int) * rk * k)) != TT_OK) return st;

@@ -170,12 +170,13 @@ struct KDev {
     int k;                        // paper index of the unfolding
     int nk, nk1;                  // n_k, n_{k+1}
     int rowcap, colcap;           // capacity of the stored superblock
+    int ld;                       // row pitch of E in entries (colcap padded off powers of two)
     int rk_cap;                   // pivot capacity of this unfolding
     int RTp, CTq;                 // row tiles per prefix, column tiles per suffix
     int TR, TC;                   // largest tile extent (LDS/thread layout)
     const int *rt_start, *rt_len, *rt_blk;    // per row tile within a prefix
     const int *ct_start, *ct_len, *ct_blk;    // per column tile within a suffix
-    void *E;                      // residual / frozen factors, rowcap x colcap, row-major
+    void *E;                      // residual / frozen factors, rowcap x colcap, row-major, pitch ld
     uint8_t *rpiv, *cpiv;         // z+1 on the row / column of pivot z, else 0
     int *Ifull;                   // I_{<=k}: rcap tuples of k indices
     int *Jfull;                   // J_{>k}: rcap tuples of d-k indices

@@ -111,7 +111,7 @@ __device__ void stored_tile_wave(const KDev &K, const KSweep &ks, const TileGeom
     const int tr = lane / TC, tcol = lane - tr * TC;
     if (tcol >= g.ncols) return;
     V *E = (V *)K.E;
-    const int64_t ld = K.colcap;
+    const int64_t ld = K.ld;
     const int col = g.col0 + tcol;
     const uint8_t cp = K.cpiv[col];
     const bool apply = ks.apply != 0;
@@ -163,7 +163,7 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSw
     const int wid = tid >> 6, lane = tid & 63;
     const bool rows_old = g.row0 < ks.nr_st, cols_old = g.col0 < ks.nc_st;
     V *E = (V *)K.E;
-    const int64_t ld = K.colcap;
+    const int64_t ld = K.ld;
     __shared__ int pre[TT_MAX_D], suf[TT_MAX_D];
     __shared__ int s_rho[TT_MAX_RANK], s_gam[TT_MAX_RANK];
     __shared__ V s_piv[TT_MAX_RANK];
@@ -839,7 +839,7 @@ __device__ void init_eval_body(const ProbDev *__restrict__ P, int u, int blk, in
         for (int jj = 0; jj < d; ++jj) idx[jj] = S->i0[jj];
         idx[k - 1] = i;
         idx[k] = j;
-        ((V *)K.E)[(int64_t)i * K.colcap + j] = fn_value<V>(P->F, idx);
+        ((V *)K.E)[(int64_t)i * K.ld + j] = fn_value<V>(P->F, idx);
     }
 }
 
