@@ -109,40 +109,46 @@ __device__ void stored_tile_wave(const KDev &K, const KSweep &ks, const TileGeom
     const int lane = threadIdx.x & 63;
     const int TC = K.TC, rpw = 64 / TC;
     const int tr = lane / TC, tcol = lane - tr * TC;
-    if (tcol >= g.ncols) return;
+    const bool colok = tcol < g.ncols;
     V *E = (V *)K.E;
     const int64_t ld = K.ld;
-    const int col = g.col0 + tcol;
-    const uint8_t cp = K.cpiv[col];
+    const int col = g.col0 + (colok ? tcol : 0);
+    const bool live = colok && !K.cpiv[col];
     const bool apply = ks.apply != 0;
-    const int gz = apply ? ks.agam : col;
     V u = 0;
     if (apply) u = E[(int64_t)ks.arho * ld + col] / (V)ks.apiv;
-    if (cp) return;
-    for (int i0 = tr; i0 < g.nrows; i0 += B * rpw) {
-        V xv[B], wv[B];
-        uint8_t rp[B];
+    // per 64 tile rows: lane l fetches row l's mask and pivot-column factor in
+    // one instruction each, and they reach the other lanes by shuffles; every
+    // lane runs the same iterations so that the shuffles see all lanes
+    for (int c0 = 0; c0 < g.nrows; c0 += 64) {
+        const int nch = min(64, g.nrows - c0);
+        const int rrow = g.row0 + c0 + (lane < nch ? lane : 0);
+        const int rpl = (lane < nch) ? K.rpiv[rrow] : 1;
+        const V wl = (apply && lane < nch) ? E[(int64_t)rrow * ld + ks.agam] : (V)0;
+        for (int base = 0; base < nch; base += B * rpw) {
+            V xv[B];
 #pragma unroll
-        for (int b = 0; b < B; ++b) {
-            const int ii = i0 + b * rpw;
-            const int row = g.row0 + (ii < g.nrows ? ii : 0);
-            const V *e = E + (int64_t)row * ld;
-            rp[b] = (ii < g.nrows) ? K.rpiv[row] : (uint8_t)1;
-            xv[b] = e[col];
-            wv[b] = e[gz];
-        }
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-            if (rp[b]) continue;
-            const int row = g.row0 + i0 + b * rpw;
-            V x = xv[b];
-            if (apply) {
-                x = vfma<V>(-wv[b], u, x);
-                E[(int64_t)row * ld + col] = x;
+            for (int b = 0; b < B; ++b) {
+                const int ii = base + tr + b * rpw;
+                xv[b] = (ii < nch) ? E[(int64_t)(g.row0 + c0 + ii) * ld + col] : (V)0;
             }
-            const double ax = (double)fabs(x);
-            const uint64_t key = ((uint64_t)row << 32) | (uint32_t)col;
-            if (better(ax, key, bv, bk)) { bv = ax; bk = key; bs = (double)x; }
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const int ii = base + tr + b * rpw;
+                const int rp = __shfl(rpl, ii & 63, 64);
+                const V w = __shfl(wl, ii & 63, 64);
+                if (ii < nch && live && !rp) {
+                    const int row = g.row0 + c0 + ii;
+                    V x = xv[b];
+                    if (apply) {
+                        x = vfma<V>(-w, u, x);
+                        E[(int64_t)row * ld + col] = x;
+                    }
+                    const double ax = (double)fabs(x);
+                    const uint64_t key = ((uint64_t)row << 32) | (uint32_t)col;
+                    if (better(ax, key, bv, bk)) { bv = ax; bk = key; bs = (double)x; }
+                }
+            }
         }
     }
 }
