@@ -340,13 +340,20 @@ template <typename V> int Problem::run_impl()
     // a1: samples -> rms, tau, first pivot; initial superblocks (the sample
     // kernel also clears the pivot maps)
     const int ns = opt.n_samples;
-    k_samples<<<sample_blocks(ns), NT, 0, stream>>>(dP, opt.seed, ns, d_vals, d_spart);
-    k_setup<V><<<1, NT, 0, stream>>>(dP, opt.seed, ns, d_spart, eps);
+    const bool hil = fn.dev.id == TT_FN_HILBERT;     // kernels built for the Hilbert tensor alone
+    if (hil) {
+        k_samples<TT_FN_HILBERT><<<sample_blocks(ns), NT, 0, stream>>>(dP, opt.seed, ns, d_vals, d_spart);
+        k_setup<V, TT_FN_HILBERT><<<1, NT, 0, stream>>>(dP, opt.seed, ns, d_spart, eps);
+    } else {
+        k_samples<0><<<sample_blocks(ns), NT, 0, stream>>>(dP, opt.seed, ns, d_vals, d_spart);
+        k_setup<V, 0><<<1, NT, 0, stream>>>(dP, opt.seed, ns, d_spart, eps);
+    }
     {
         int maxe = 1;
         for (int u = 0; u < nk; ++u) maxe = std::max(maxe, n[u] * n[u + 1]);
         dim3 g((unsigned)std::min(1024, (maxe + NT - 1) / NT), (unsigned)nk);
-        k_init_eval<V><<<g, NT, 0, stream>>>(dP);
+        if (hil) k_init_eval<V, TT_FN_HILBERT><<<g, NT, 0, stream>>>(dP);
+        else k_init_eval<V, 0><<<g, NT, 0, stream>>>(dP);
     }
     HIPCHK(hipGetLastError());
     // search sweeps, queued ahead of the host's view of the stop flag

@@ -649,6 +649,7 @@ static __global__ void __launch_bounds__(NTC) k_commit(const ProbDev *__restrict
 // ns), and its largest |sample| (lowest index on ties).  Workgroup sums are
 // the subtrees of the tree over all samples, so combining them pairwise gives
 // that tree's value exactly.
+template <int FNS>
 __device__ inline void samples_body(const ProbDev *__restrict__ P, uint64_t seed, int ns, double *vals,
                                     SamplePart *part, int blk, int nblk)
 {
@@ -664,7 +665,7 @@ __device__ inline void samples_body(const ProbDev *__restrict__ P, uint64_t seed
         int idx[TT_MAX_D];
         for (int j = 0; j < d; ++j)
             idx[j] = (int)(sm64_at(seed, (uint64_t)s * d + j) % (uint64_t)P->F.n[j]);
-        v = fn_value<double>(P->F, idx);
+        v = fn_value<double, FNS>(P->F, idx);
         vals[s] = v;
     }
     const double a = fabs(v);
@@ -695,10 +696,11 @@ __device__ inline void samples_body(const ProbDev *__restrict__ P, uint64_t seed
     }
 }
 
+template <int FNS = 0>
 static __global__ void __launch_bounds__(NT) k_samples(const ProbDev *__restrict__ P, uint64_t seed, int ns,
                                                   double *vals, SamplePart *part)
 {
-    samples_body(P, seed, ns, vals, part, blockIdx.x, gridDim.x);
+    samples_body<FNS>(P, seed, ns, vals, part, blockIdx.x, gridDim.x);
 }
 
 // Pairwise sum of x(lo..lo+c) over a complete binary tree (c a power of two,
@@ -739,7 +741,7 @@ template <typename X> __device__ inline double chunk_pairwise_sum(X x, int lo, i
     return st[0];
 }
 
-template <typename V>
+template <typename V, int FNS>
 __device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns, const SamplePart *part, double eps)
 {
     ProbState *S = P->S;
@@ -788,7 +790,7 @@ __device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns,
         S->stop = 0; S->capped = 0; S->sweeps = 0; S->pivoted = 0;
         S->alg_bytes = 0; S->new_entries = 0;
         S->err = sbad ? TT_EFN : 0;
-        p0s = (double)fn_value<V>(P->F, i0);
+        p0s = (double)fn_value<V, FNS>(P->F, i0);
         if (p0s == 0.0) S->err = TT_ESINGULAR;
         if (S->err) S->stop = 1;
         HostMirror *hm = P->hm;
@@ -807,7 +809,7 @@ __device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns,
             K.rho[0] = i0[k - 1];
             K.gam[0] = i0[k];
             K.piv[0] = p0s;
-            K.piv64[0] = (double)fn_value<double>(P->F, i0);
+            K.piv64[0] = (double)fn_value<double, FNS>(P->F, i0);
             K.rpiv[i0[k - 1]] = 1;
             K.cpiv[i0[k]] = 1;
             KSweep ks;
@@ -823,15 +825,15 @@ __device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns,
     }
 }
 
-template <typename V>
+template <typename V, int FNS = 0>
 static __global__ void __launch_bounds__(NT) k_setup(const ProbDev *__restrict__ P, uint64_t seed, int ns,
                                                 const SamplePart *part, double eps)
 {
-    setup_body<V>(P, seed, ns, part, eps);
+    setup_body<V, FNS>(P, seed, ns, part, eps);
 }
 
 // E = X on the initial superblocks (one prefix, one suffix: the first pivot's).
-template <typename V>
+template <typename V, int FNS>
 __device__ void init_eval_body(const ProbDev *__restrict__ P, int u, int blk, int nblk)
 {
     const ProbState *S = P->S;
@@ -845,14 +847,14 @@ __device__ void init_eval_body(const ProbDev *__restrict__ P, int u, int blk, in
         for (int jj = 0; jj < d; ++jj) idx[jj] = S->i0[jj];
         idx[k - 1] = i;
         idx[k] = j;
-        ((V *)K.E)[(int64_t)i * K.ld + j] = fn_value<V>(P->F, idx);
+        ((V *)K.E)[(int64_t)i * K.ld + j] = fn_value<V, FNS>(P->F, idx);
     }
 }
 
-template <typename V>
+template <typename V, int FNS = 0>
 static __global__ void __launch_bounds__(NT) k_init_eval(const ProbDev *__restrict__ P)
 {
-    init_eval_body<V>(P, blockIdx.y, blockIdx.x, gridDim.x);
+    init_eval_body<V, FNS>(P, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1166,14 +1168,14 @@ __device__ inline int batch_find(const BatchMap &bm, int b)
 static __global__ void __launch_bounds__(NT) k_samples_b(const ProbDev *__restrict__ Pa, BatchMap bm)
 {
     const ProbDev *P = Pa + bm.p[blockIdx.y];
-    samples_body(P, P->run.seed, P->run.ns, P->run.vals, P->run.spart, blockIdx.x, gridDim.x);
+    samples_body<0>(P, P->run.seed, P->run.ns, P->run.vals, P->run.spart, blockIdx.x, gridDim.x);
 }
 
 template <typename V>
 static __global__ void __launch_bounds__(NT) k_setup_b(const ProbDev *__restrict__ Pa, BatchMap bm)
 {
     const ProbDev *P = Pa + bm.p[blockIdx.x];
-    setup_body<V>(P, P->run.seed, P->run.ns, P->run.spart, P->run.eps);
+    setup_body<V, 0>(P, P->run.seed, P->run.ns, P->run.spart, P->run.eps);
 }
 
 template <typename V>
@@ -1181,7 +1183,7 @@ static __global__ void __launch_bounds__(NT) k_init_eval_b(const ProbDev *__rest
 {
     const ProbDev *P = Pa + bm.p[blockIdx.z];
     if ((int)blockIdx.y >= P->nk) return;
-    init_eval_body<V>(P, blockIdx.y, blockIdx.x, gridDim.x);
+    init_eval_body<V, 0>(P, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
 template <typename V>
