@@ -31,6 +31,8 @@ HBM_PEAK_GBS = 8000.0
 
 
 PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "k_sweep_hilbert6d_n64_fp64.md")
+EVAL_PROFILE = os.path.join(ROOT, "profiles", "k_fn_eval_maxwell6d_n128.md")
+VALU_PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
 
 
 def kernel_sources_hash():
@@ -56,6 +58,88 @@ def counted_traffic():
     if kv.get("kernel_sources_sha256_16", "").strip() != kernel_sources_hash():
         return None
     return float(kv["traffic_per_launch_bytes"])
+
+
+def eval_valu_flops():
+    """VALU flops per evaluated entry of the bulk evaluation kernel, by
+    precision, from the committed rocprofv3 counter summary; None when the
+    kernel sources changed since."""
+    try:
+        with open(EVAL_PROFILE) as f:
+            kv = dict(line.split(": ", 1) for line in f.read().splitlines()
+                      if line.startswith(("valu_flops_per_entry_", "kernel_sources_sha256_16:")))
+    except OSError:
+        return None
+    if kv.get("kernel_sources_sha256_16", "").strip() != kernel_sources_hash():
+        return None
+    return {k.split("_")[-1]: float(v) for k, v in kv.items() if k.startswith("valu_flops_per_entry_")}
+
+
+def bench_eval(args):
+    """Entry evaluation alone: the 6D Maxwellian of the phase-space workload
+    (n = 128 per mode) at m seeded multi-indices resident on the GPU, in FP32
+    (the arithmetic of FP32 sweeps) and in FP64.  A step is one bulk
+    evaluation of all m entries."""
+    import torch
+    from paper_2407_11290_amd import FN_MAXWELL
+    from paper_2407_11290_amd.api import fn_eval
+    n, m = [128] * 6, args.eval_m
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(0)
+    idx = torch.randint(0, 128, (m, 6), dtype=torch.int32, device="cuda", generator=gen)
+    flops = eval_valu_flops()
+    lines = {}
+    for prec in ("fp32", "fp64"):
+        fp32 = prec == "fp32"
+        for _ in range(args.warmup):
+            fn_eval(FN_MAXWELL, n, idx, fp32=fp32)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for a, b in evs:                    # the library launches on the null stream, as torch does
+            a.record()
+            fn_eval(FN_MAXWELL, n, idx, fp32=fp32)
+            b.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kern = statistics.median(a.elapsed_time(b) for a, b in evs) * 1e-3
+        w = 4 if fp32 else 8
+        bytes_per_entry = 4 * 6 + w
+        hbm = {"bound": "hbm", "achieved": m * bytes_per_entry / kern / 1e9, "peak": HBM_PEAK_GBS,
+               "unit": "GB/s", "traffic": None, "bytes_per_entry": bytes_per_entry}
+        hbm["frac"] = hbm["achieved"] / hbm["peak"]
+        valu = None
+        if flops and prec in flops:
+            valu = {"bound": "alu", "achieved": flops[prec] * m / kern / 1e12, "peak": VALU_PEAK_TFLOPS[prec],
+                    "unit": "TFLOP/s", "flops_per_entry": flops[prec]}
+            valu["frac"] = valu["achieved"] / valu["peak"]
+        dom = hbm if (valu is None or hbm["frac"] >= valu["frac"]) else valu
+        lines[prec] = {"entries_per_s": m * args.steps / wall, "kernel_s": kern, "roofline": dom,
+                       "hbm": hbm, "valu": valu}
+        print(f"bench: eval {prec}: {args.steps} steps, kernel {kern * 1e6:.1f} us", file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import fn_eval as orc_fn_eval
+        from oracle.oracle import FN_MAXWELL as O_MAXWELL
+        sample = idx[: 1 << 18].cpu().numpy()
+        t0, reps = time.perf_counter(), 0
+        while time.perf_counter() - t0 < min(args.cpu_seconds, 5.0):
+            orc_fn_eval(O_MAXWELL, n, sample)
+            reps += 1
+        el = time.perf_counter() - t0
+        cpu = {"value": reps * sample.shape[0] / el, "unit": "entries/s", "cores": 1, "kind": "oracle",
+               "sample": f"the FP64 oracle's generating function at the first {sample.shape[0]} of the same "
+                         f"indices, {reps} passes, {el:.1f} s, one host thread"}
+    f32 = lines["fp32"]
+    out = {
+        "metric": METRIC, "value": f32["entries_per_s"], "unit": "entries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": f32["kernel_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "fn_eval_maxwell6d_n128", "m": m, "fn": "3d3v Maxwellian, x1..x3 periodic, v in [-8,8]"},
+        "roofline": f32["roofline"], "fp32": f32, "fp64": lines["fp64"], "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(seconds):
@@ -237,10 +321,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="hilbert6d", choices=["hilbert6d", "batch512", "serve"],
+    ap.add_argument("--workload", default="hilbert6d", choices=["hilbert6d", "batch512", "serve", "eval"],
                     help="hilbert6d: the single-solve benchmark line; batch512: the mixed 512-problem "
                          "batch, solved together and one at a time; serve: a Poisson-arrival trace "
-                         "through the continuous-batching server")
+                         "through the continuous-batching server; eval: bulk entry evaluation of the 6D "
+                         "Maxwellian in FP32 and FP64")
+    ap.add_argument("--eval-m", type=int, default=1 << 24, help="eval: multi-indices per step")
     ap.add_argument("--requests", type=int, default=2000, help="serve: trace length")
     ap.add_argument("--rate-frac", type=float, default=0.8, help="serve: arrival rate / measured capacity")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="serve: HBM budget of the server")
@@ -272,6 +358,8 @@ def main():
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "eval":
+        return bench_eval(args)
 
     handles = [TTCross(N, EPS, FN_HILBERT, seed=s, precision=PREC_FP64, grid=GRID) for s in SEEDS]
     probes = [TTCross(N, EPS, FN_HILBERT, seed=s, precision=PREC_FP64, grid=GRID, profile=1) for s in SEEDS]

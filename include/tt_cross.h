@@ -99,8 +99,11 @@ typedef struct tt_options {
     int32_t pivot_mode;         /* enum tt_pivot_mode (default greedy) */
     int32_t n_samples;          /* N_s sample entries for rms and the first pivot (default 16384) */
     int32_t grid[TT_MAX_D];     /* subtensor blocks per mode C_j (default 1; 1 <= C_j <= n_j) */
-    int32_t tile_rows;          /* rows per workgroup tile, 0 = chosen by the library */
-    int32_t tile_cols;          /* columns per workgroup tile, 0 = chosen by the library */
+    int32_t tile_rows;          /* rows per workgroup tile, 1..256; 0 (with tile_cols 0) = the
+                                   tuned shape of the problem's class (tt_autotune), else the
+                                   library's default */
+    int32_t tile_cols;          /* columns per workgroup tile, 1..64 (rounded up to a power of
+                                   two); 0 as for tile_rows */
     int32_t lookahead;          /* sweeps queued ahead of the host's stop check (default 2) */
     int32_t profile;            /* 1: time every search launch with HIP events (stats below) */
     void *stream;               /* hipStream_t to run on; NULL = a stream owned by the handle */
@@ -163,6 +166,10 @@ int tt_cross_run(tt_cross_h h);
 /* ranks[0..d] = (1, r_1, .., r_{d-1}, 1) after a run. */
 int tt_cross_get_ranks(tt_cross_h h, int32_t *ranks);
 
+/* Tile shapes of the last run's search launches, one per unfolding:
+ * rows[k-1] x cols[k-1] for k = 1..d-1 (see tt_autotune below). */
+int tt_cross_get_tiles(tt_cross_h h, int32_t *rows, int32_t *cols);
+
 /* Copy the cores G_1..G_d, concatenated, each r_{k-1} x n_k x r_k in row-major
  * order, into out (cap doubles).  Returns the number of doubles needed; with
  * out == NULL only the size is returned. */
@@ -188,9 +195,18 @@ int tt_cross_get_stats(tt_cross_h h, tt_stats *st);
  * draw(s*d + j) mod n_j. */
 int tt_cross_sampled_error(tt_cross_h h, int64_t R, uint64_t seed, double *err);
 
-/* Evaluate a generating function at m multi-indices (no handle needed). */
+/* Evaluate a generating function (the tensor's entries, Sec. 1: element
+ * access only) at m multi-indices, no handle needed.  tt_fn_eval computes in
+ * FP64; tt_fn_eval_f32 uses the FP32 arithmetic that FP32 sweeps use for
+ * superblock entries.  idx: m x d int32, row-major, 0-based; out: m values.
+ * on_device = 0: host buffers, every index checked (TT_EINVAL if outside
+ * [0, n_j)); = 1: device buffers, indices not checked and must lie in range.
+ * Runs on the null stream and returns when done.
+ * Errors: TT_EFN (unknown function or bad params), TT_EINVAL, TT_EDEVICE. */
 int tt_fn_eval(int fn_id, int d, const int32_t *n, const double *params, int nparams, int64_t m,
                const int32_t *idx, double *out, int on_device);
+int tt_fn_eval_f32(int fn_id, int d, const int32_t *n, const double *params, int nparams, int64_t m,
+                   const int32_t *idx, float *out, int on_device);
 
 void tt_cross_destroy(tt_cross_h h);
 
@@ -213,6 +229,53 @@ void tt_cross_destroy(tt_cross_h h);
  * status (TT_OK, TT_NOT_CONVERGED, or a device-reported error) is in its
  * stats.  Errors: TT_EINVAL (bad arguments), TT_EDEVICE, TT_ENOMEM. */
 int tt_batch_run(tt_cross_h *hs, int count, void *hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Tile-shape autotuning (batching: tiles chosen by measurement).
+ *
+ * A search tile covers tile_rows superblock rows by tile_cols columns inside
+ * one subtensor block (Sec. 3) and one prefix (suffix) of the nested index
+ * sets.  The result of a solve does not depend on the tile shape -- entries
+ * are computed one by one in a fixed order, and the tiles' local pivots are
+ * combined with the lowest-(row, column) tie-break (Alg. 3) -- only its time
+ * does.  The library keeps one process-wide table of tuned shapes by problem
+ * class: mode sizes, subtensor grid, sweep precision, rank cap, and whether
+ * the tensor is the Hilbert tensor (which has kernels of its own).  A handle
+ * whose tile_rows and tile_cols are both 0 uses its class's entry, if any,
+ * when it is next prepared; otherwise the library's default shape.
+ *
+ * Candidates: the default shape, then every power-of-two tile_rows in
+ * [8, 256] and tile_cols in [8, 64] up to the longest run of a mode inside
+ * one subtensor block; shapes that do not fit in LDS at the rank cap are
+ * skipped.  A candidate replaces the default only if it is at least 2%
+ * (batches: 5%) faster.  The tuners allocate (each shape has its own tile tables) and
+ * leave the handles' options, precision state and results as a solve with
+ * the last candidate left them.
+ * ------------------------------------------------------------------------- */
+
+/* Times complete solves of h (reps timed runs after one untimed run, median
+ * of the device time-to-eps) under every candidate shape and records the
+ * fastest for h's class.  Outputs (each may be NULL): the recorded shape,
+ * 0/0 meaning the default, and its median time in ms.
+ * Errors: TT_EINVAL (NULL handle, reps outside [1,64]), or a solve's error. */
+int tt_autotune(tt_cross_h h, int reps, int32_t *tile_rows, int32_t *tile_cols, double *best_ms);
+
+/* The same for batched solves: the handles are grouped by class, and for
+ * every class up to per_class of its handles are solved together with
+ * tt_batch_run (on hip_stream, as there) under every candidate shape; the
+ * median device time of reps timed batches decides.  Returns the number
+ * of classes tuned, or an error as tt_batch_run. */
+int tt_batch_autotune(tt_cross_h *hs, int count, int reps, int per_class, void *hip_stream);
+
+/* Copies the tuned-shape table: row i of out (TT_TILE_ROW_WORDS int32 each)
+ * is d, fp32 sweeps (0/1), Hilbert kernels (0/1), r_max, n[TT_MAX_D],
+ * grid[TT_MAX_D] (zero past d), tile_rows, tile_cols.  At most cap rows are
+ * written; returns the number of entries (out NULL: only the count). */
+#define TT_TILE_ROW_WORDS (6 + 2 * TT_MAX_D)
+int tt_tile_table(int32_t *out, int cap);
+
+/* Empties the tuned-shape table. */
+void tt_tile_table_clear(void);
 
 /* ---------------------------------------------------------------------------
  * Served solves: continuous batching on one GPU.

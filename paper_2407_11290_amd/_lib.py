@@ -62,6 +62,9 @@ class Stats(C.Structure):
     ]
 
 
+TILE_ROW_WORDS = 6 + 2 * TT_MAX_D  # int32 words per row of tt_tile_table
+
+
 class ServerStats(C.Structure):
     _fields_ = [(name, C.c_int64) for name in ("submitted", "completed", "queued", "running", "pool_bytes",
                                                 "pool_objects", "allocations")]
@@ -75,6 +78,7 @@ SIGNATURES = {
     "tt_cross_set_options": (C.c_int, [C.c_void_p, C.POINTER(Options)]),
     "tt_cross_run": (C.c_int, [C.c_void_p]),
     "tt_cross_get_ranks": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "tt_cross_get_tiles": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "tt_cross_get_cores": (C.c_int64, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int]),
     "tt_eval": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_int]),
     "tt_cross_get_pivots": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
@@ -83,8 +87,15 @@ SIGNATURES = {
     "tt_cross_sampled_error": (C.c_int, [C.c_void_p, C.c_int64, C.c_uint64, C.POINTER(C.c_double)]),
     "tt_fn_eval": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_int,
                              C.c_int64, C.c_void_p, C.c_void_p, C.c_int]),
+    "tt_fn_eval_f32": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_int,
+                                 C.c_int64, C.c_void_p, C.c_void_p, C.c_int]),
     "tt_cross_destroy": (None, [C.c_void_p]),
     "tt_batch_run": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_void_p]),
+    "tt_autotune": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                              C.POINTER(C.c_double)]),
+    "tt_batch_autotune": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_int, C.c_void_p]),
+    "tt_tile_table": (C.c_int, [C.c_void_p, C.c_int]),
+    "tt_tile_table_clear": (None, []),
     "tt_server_create": (C.c_void_p, [C.c_size_t, C.c_int, C.POINTER(Options)]),
     "tt_server_submit": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int32), C.c_double, C.c_int,
                                    C.POINTER(C.c_double), C.c_int, C.c_uint64, C.POINTER(C.c_uint64)]),

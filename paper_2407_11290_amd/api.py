@@ -25,24 +25,28 @@ def default_options():
     return o
 
 
-def fn_eval(fn_id, n, idx, params=None):
-    """Generating function at m multi-indices, evaluated on the GPU (FP64).
+def fn_eval(fn_id, n, idx, params=None, fp32=False):
+    """Generating function at m multi-indices, evaluated on the GPU in FP64
+    (tt_fn_eval) or, with fp32=True, in the FP32 arithmetic of FP32 sweeps
+    (tt_fn_eval_f32).
 
     idx: numpy (m, d) int32 on the host, or a torch int32 CUDA tensor (the
-    result is then a torch float64 CUDA tensor)."""
+    result is then a torch CUDA tensor)."""
     n = _i32(n)
     pp, npar, _keep = _params_ptr(params)
+    L = load()
+    fn = L.tt_fn_eval_f32 if fp32 else L.tt_fn_eval
     if hasattr(idx, "is_cuda") and idx.is_cuda:
         import torch
         idx = idx.contiguous()
-        out = torch.empty(idx.shape[0], dtype=torch.float64, device=idx.device)
-        check(load().tt_fn_eval(fn_id, n.size, n.ctypes.data_as(C.POINTER(C.c_int32)), pp, npar,
-                                idx.shape[0], C.c_void_p(idx.data_ptr()), C.c_void_p(out.data_ptr()), 1))
+        out = torch.empty(idx.shape[0], dtype=torch.float32 if fp32 else torch.float64, device=idx.device)
+        check(fn(fn_id, n.size, n.ctypes.data_as(C.POINTER(C.c_int32)), pp, npar,
+                 idx.shape[0], C.c_void_p(idx.data_ptr()), C.c_void_p(out.data_ptr()), 1))
         return out
     idx = _i32(np.atleast_2d(idx))
-    out = np.zeros(idx.shape[0], dtype=np.float64)
-    check(load().tt_fn_eval(fn_id, n.size, n.ctypes.data_as(C.POINTER(C.c_int32)), pp, npar, idx.shape[0],
-                            idx.ctypes.data_as(C.c_void_p), out.ctypes.data_as(C.c_void_p), 0))
+    out = np.zeros(idx.shape[0], dtype=np.float32 if fp32 else np.float64)
+    check(fn(fn_id, n.size, n.ctypes.data_as(C.POINTER(C.c_int32)), pp, npar, idx.shape[0],
+             idx.ctypes.data_as(C.c_void_p), out.ctypes.data_as(C.c_void_p), 0))
     return out
 
 
@@ -107,6 +111,22 @@ class TTCross:
     def run(self):
         self.status = check(load().tt_cross_run(self.h))
         return self.status
+
+    def autotune(self, reps=3):
+        """Time complete solves under every candidate tile shape (tt_autotune)
+        and record the fastest for this problem's class; returns
+        (tile_rows, tile_cols, ms), 0/0 meaning the library's default shape."""
+        tr, tc, ms = C.c_int32(), C.c_int32(), C.c_double()
+        check(load().tt_autotune(self.h, reps, C.byref(tr), C.byref(tc), C.byref(ms)))
+        return tr.value, tc.value, ms.value
+
+    def tiles(self):
+        """(rows, cols) tile shape of each unfolding in the last run."""
+        r = np.zeros(self.d - 1, dtype=np.int32)
+        c = np.zeros(self.d - 1, dtype=np.int32)
+        check(load().tt_cross_get_tiles(self.h, r.ctypes.data_as(C.POINTER(C.c_int32)),
+                                        c.ctypes.data_as(C.POINTER(C.c_int32))))
+        return list(zip(r.tolist(), c.tolist()))
 
     def ranks(self):
         r = np.zeros(self.d + 1, dtype=np.int32)
@@ -181,6 +201,36 @@ def batch_run(problems, stream=None):
         p.status = p.stats()["status"]
         out.append(p.status)
     return out
+
+
+def batch_autotune(problems, reps=2, per_class=16, stream=None):
+    """Tune tile shapes per problem class on batched solves (tt_batch_autotune);
+    returns the number of classes tuned."""
+    problems = list(problems)
+    arr = (C.c_void_p * len(problems))(*[p.h for p in problems])
+    s = None if stream is None else C.c_void_p(getattr(stream, "cuda_stream", stream))
+    return check(load().tt_batch_autotune(arr, len(problems), reps, per_class, s))
+
+
+def tile_table():
+    """The tuned tile shapes, one dict per problem class (tt_tile_table)."""
+    L = load()
+    n = L.tt_tile_table(None, 0)
+    W = _lib.TILE_ROW_WORDS
+    buf = np.zeros((max(n, 1), W), dtype=np.int32)
+    n = L.tt_tile_table(buf.ctypes.data_as(C.c_void_p), n)
+    D = _lib.TT_MAX_D
+    out = []
+    for row in buf[:n]:
+        d = int(row[0])
+        out.append({"d": d, "fp32": int(row[1]), "hilbert": int(row[2]), "r_max": int(row[3]),
+                    "n": [int(x) for x in row[4:4 + d]], "grid": [int(x) for x in row[4 + D:4 + D + d]],
+                    "tile_rows": int(row[4 + 2 * D]), "tile_cols": int(row[5 + 2 * D])})
+    return out
+
+
+def tile_table_clear():
+    load().tt_tile_table_clear()
 
 
 class Server:

@@ -232,16 +232,17 @@ int Problem::allocate()
         }
         K.rk_cap = rc[k];
         // tile geometry: rows of mode k, columns of mode k+1
-        int TR = opt.tile_rows > 0 ? opt.tile_rows : 32;
+        int TR = req_tr > 0 ? req_tr : 32;
         int maxrun = 1;
         {
             const int C = grid[k];
             for (int b = 0; b < C; ++b)
                 maxrun = std::max(maxrun, (int)((int64_t)(b + 1) * n[k] / C - (int64_t)b * n[k] / C));
         }
-        int TC = opt.tile_cols > 0 ? opt.tile_cols : std::min(64, pow2_at_least(maxrun));
-        TC = std::min(pow2_at_least(TC), NT);
-        if (opt.tile_rows <= 0 && opt.tile_cols <= 0) {
+        // stored tiles put 64 / TC rows on a wavefront: TC <= 64
+        int TC = req_tc > 0 ? req_tc : std::min(64, pow2_at_least(maxrun));
+        TC = std::min(pow2_at_least(TC), 64);
+        if (req_tr <= 0 && req_tc <= 0) {
             // shrink the default tile until its LDS fits next to the rank cap
             while (sweep_lds_bytes(rc[k], TR, TC, w) + lds_static > (size_t)lds_limit && (TC > 16 || TR > 8)) {
                 if (TC > 16) TC /= 2;
@@ -320,6 +321,9 @@ void Problem::resolve_geometry()
     if (prec == TT_PREC_AUTO) prec = (eps >= 1e-6) ? TT_PREC_FP32 : TT_PREC_FP64;
     if (force_fp64) prec = TT_PREC_FP64;
     fp32 = (prec == TT_PREC_FP32) ? 1 : 0;
+    req_tr = opt.tile_rows;
+    req_tc = opt.tile_cols;
+    if (req_tr == 0 && req_tc == 0 && use_table) tuned_tiles(*this, req_tr, req_tc);
 }
 
 template <typename V> int Problem::run_impl()
@@ -502,8 +506,8 @@ void Problem::finalize(const ProbState &S, const int *ranks_now)
 int Problem::prepare()
 {
     resolve_geometry();
-    if (allocated && (alloc_fp32 != fp32 || alloc_rmax != opt.r_max || alloc_tr != opt.tile_rows ||
-                      alloc_tc != opt.tile_cols || alloc_ns != opt.n_samples ||
+    if (allocated && (alloc_fp32 != fp32 || alloc_rmax != opt.r_max || alloc_tr != req_tr ||
+                      alloc_tc != req_tc || alloc_ns != opt.n_samples ||
                       std::memcmp(alloc_grid, grid, sizeof grid) != 0)) {
         for (void *p : allocs) (void)hipFree(p);
         allocs.clear();
@@ -514,8 +518,8 @@ int Problem::prepare()
     if (st != TT_OK) return st;
     alloc_fp32 = fp32;
     alloc_rmax = opt.r_max;
-    alloc_tr = opt.tile_rows;
-    alloc_tc = opt.tile_cols;
+    alloc_tr = req_tr;
+    alloc_tc = req_tc;
     alloc_ns = opt.n_samples;
     std::memcpy(alloc_grid, grid, sizeof grid);
     ran = false;
@@ -616,7 +620,7 @@ static int check_options(const tt_options *o)
     for (int j = 0; j < TT_MAX_D; ++j)
         if (o->grid[j] < 1) return set_err(TT_EINVAL, "grid[%d] must be >= 1", j);
     if (o->tile_rows < 0 || o->tile_rows > 256) return set_err(TT_EINVAL, "tile_rows must be in [0,256]");
-    if (o->tile_cols < 0 || o->tile_cols > 256) return set_err(TT_EINVAL, "tile_cols must be in [0,256]");
+    if (o->tile_cols < 0 || o->tile_cols > 64) return set_err(TT_EINVAL, "tile_cols must be in [0,64]");
     if (o->verify < -1) return set_err(TT_EINVAL, "verify must be -1, 0 or a sample count");
     return TT_OK;
 }
@@ -672,6 +676,17 @@ int tt_cross_get_ranks(tt_cross_h h, int32_t *ranks)
     if (!h || !ranks) return set_err(TT_EINVAL, "NULL argument");
     if (!h->p.ran) return set_err(TT_ESTATE, "no completed run");
     for (int k = 0; k <= h->p.d; ++k) ranks[k] = h->p.ranks[k];
+    return TT_OK;
+}
+
+int tt_cross_get_tiles(tt_cross_h h, int32_t *rows, int32_t *cols)
+{
+    if (!h || !rows || !cols) return set_err(TT_EINVAL, "NULL argument");
+    if (!h->p.ran) return set_err(TT_ESTATE, "no completed run");
+    for (int u = 0; u < h->p.d - 1; ++u) {
+        rows[u] = h->p.tileTR[u];
+        cols[u] = h->p.tileTC[u];
+    }
     return TT_OK;
 }
 
@@ -827,8 +842,13 @@ int tt_cross_sampled_error(tt_cross_h h, int64_t R, uint64_t seed, double *err)
     return (*err > P.eps) ? TT_WARN_SAMPLED_ERR : TT_OK;
 }
 
-int tt_fn_eval(int fn_id, int d, const int32_t *n, const double *params, int nparams, int64_t m,
-               const int32_t *idx, double *out, int on_device)
+}  // extern "C"
+
+namespace ttc {
+// Bulk evaluation behind tt_fn_eval (V = double) and tt_fn_eval_f32.
+template <typename V>
+static int fn_eval_impl(int fn_id, int d, const int32_t *n, const double *params, int nparams, int64_t m,
+                        const int32_t *idx, V *out, int on_device)
 {
     g_err.clear();
     FnHost fh;
@@ -843,27 +863,42 @@ int tt_fn_eval(int fn_id, int d, const int32_t *n, const double *params, int npa
                     return set_err(TT_EINVAL, "index %lld,%d out of range", (long long)t, j);
     if ((st = upload_fn(fh)) != TT_OK) return st;
     const int *didx = idx;
-    double *dout = out;
+    V *dout = out;
     void *ti = nullptr, *to = nullptr;
     hipError_t e = hipSuccess;
     if (!on_device) {
         e = hipMalloc(&ti, sizeof(int) * m * d);
-        if (e == hipSuccess) e = hipMalloc(&to, sizeof(double) * m);
+        if (e == hipSuccess) e = hipMalloc(&to, sizeof(V) * m);
         if (e == hipSuccess) e = hipMemcpy(ti, idx, sizeof(int) * m * d, hipMemcpyHostToDevice);
         didx = (const int *)ti;
-        dout = (double *)to;
+        dout = (V *)to;
     }
     if (e == hipSuccess) {
-        k_fn_eval<double><<<(unsigned)((m + NT - 1) / NT), NT>>>(fh.dev, m, didx, dout);
+        k_fn_eval<V><<<(unsigned)((m + NT - 1) / NT), NT>>>(fh.dev, m, didx, dout);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipDeviceSynchronize();
-    if (e == hipSuccess && !on_device) e = hipMemcpy(out, dout, sizeof(double) * m, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && !on_device) e = hipMemcpy(out, dout, sizeof(V) * m, hipMemcpyDeviceToHost);
     if (ti) (void)hipFree(ti);
     if (to) (void)hipFree(to);
     if (fh.d_table) { (void)hipFree(fh.d_table); fh.d_table = nullptr; }
     if (e != hipSuccess) return set_err(TT_EDEVICE, "tt_fn_eval: %s", hipGetErrorString(e));
     return TT_OK;
+}
+}  // namespace ttc
+
+extern "C" {
+
+int tt_fn_eval(int fn_id, int d, const int32_t *n, const double *params, int nparams, int64_t m,
+               const int32_t *idx, double *out, int on_device)
+{
+    return fn_eval_impl<double>(fn_id, d, n, params, nparams, m, idx, out, on_device);
+}
+
+int tt_fn_eval_f32(int fn_id, int d, const int32_t *n, const double *params, int nparams, int64_t m,
+                   const int32_t *idx, float *out, int on_device)
+{
+    return fn_eval_impl<float>(fn_id, d, n, params, nparams, m, idx, out, on_device);
 }
 
 void tt_cross_destroy(tt_cross_h h)

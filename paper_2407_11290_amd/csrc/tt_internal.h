@@ -41,6 +41,8 @@ struct Problem {
     int grid[TT_MAX_D] = {0};      // subtensor blocks per mode
     int fp32 = 0;
     int tileTR[TT_MAX_D] = {0}, tileTC[TT_MAX_D] = {0};
+    int req_tr = 0, req_tc = 0;    // tile request in force: the options', else the tuned table's
+    bool use_table = true;         // false while the tuner times its own candidates
     int hist_cap = 0, max_sweeps = 0;
     int lds_limit = 65536;         // LDS bytes one workgroup may allocate on this device
     int lds_static = 0;            // static LDS of the search kernel
@@ -90,6 +92,10 @@ struct Problem {
     int run();
     template <typename V> int run_impl();
 };
+
+// Process-wide table of tuned tile shapes by problem class (tt_tune.hip).
+// Looked up when a problem's tile options are both 0.
+bool tuned_tiles(const Problem &P, int &tr, int &tc);
 
 }  // namespace ttc
 

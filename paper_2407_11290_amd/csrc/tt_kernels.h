@@ -1260,15 +1260,17 @@ static __global__ void __launch_bounds__(NT) k_tt_eval(TTArgs a, const double *_
     }
 }
 
+// The generating function at m multi-indices, in the arithmetic of V (the
+// precision of the sweeps that would evaluate it).
 template <typename V>
 static __global__ void __launch_bounds__(NT) k_fn_eval(FnDev F, int64_t m, const int *__restrict__ idx,
-                                                  double *__restrict__ out)
+                                                  V *__restrict__ out)
 {
     const int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x;
     if (t >= m) return;
     int ix[TT_MAX_D];
     for (int j = 0; j < F.d; ++j) ix[j] = idx[t * F.d + j];
-    out[t] = (double)fn_value<V>(F, ix);
+    out[t] = fn_value<V>(F, ix);
 }
 
 static __global__ void __launch_bounds__(NT) k_gen_idx(int d, TTArgs a, uint64_t seed, int64_t m, int *idx)

@@ -97,6 +97,30 @@ def test_batch_rejects_bad_arguments_before_any_device_work():
     b.close()
 
 
+def test_tile_options_and_tuner_arguments_without_gpu():
+    """Tile shapes outside what the search kernel supports are refused when
+    set; the tuners check their arguments before any device work."""
+    from paper_2407_11290_amd.api import TTCross, tile_table, tile_table_clear
+    for bad in ({"tile_cols": 128}, {"tile_cols": -1}, {"tile_rows": 257}):
+        with pytest.raises(_lib.TTError) as e:
+            TTCross([8, 8, 8], 1e-8, _lib.FN_HILBERT, **bad)
+        assert e.value.code == _lib.EINVAL
+    t = TTCross([8, 8, 8], 1e-8, _lib.FN_HILBERT, tile_rows=256, tile_cols=64)
+    with pytest.raises(_lib.TTError) as e:
+        t.tiles()
+    assert e.value.code == _lib.ESTATE
+    L = _lib.load()
+    assert L.tt_autotune(None, 3, None, None, None) == _lib.EINVAL
+    assert L.tt_autotune(t.h, 0, None, None, None) == _lib.EINVAL
+    assert L.tt_batch_autotune(None, 2, 1, 1, None) == _lib.EINVAL
+    assert L.tt_batch_autotune(None, 0, 1, 1, None) == 0
+    arr = (C.c_void_p * 1)(t.h)
+    assert L.tt_batch_autotune(arr, 1, 1, 0, None) == _lib.EINVAL
+    tile_table_clear()
+    assert tile_table() == [] and L.tt_tile_table(None, 0) == 0
+    t.close()
+
+
 def test_workload_lists_are_seeded_and_shaped_as_specified():
     from paper_2407_11290_amd.workloads import FN_BIMAXWELL, FN_HILBERT, batch_mix, served_trace
     a, b = batch_mix(), batch_mix()

@@ -80,6 +80,38 @@ def test_fn_values(fn_id, n, params, exact):
         assert np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)) < 1e-13
 
 
+@pytest.mark.parametrize("fn_id,n,params", [
+    (FN_HILBERT, [64] * 6, None),
+    (FN_HILBERT, [7, 9, 5, 11], [2.37]),
+    (FN_SEPSUM, [5, 6, 7], "sep"),
+    (FN_MAXWELL, [128] * 6, None),
+    (FN_BIMAXWELL, [4, 16, 16, 16], "bimax"),
+    (FN_MAXWELL_2D2V, [20, 10, 20, 10], None),
+    (FN_MAXWELL_3D3V, [8, 4, 8, 4, 8, 4], None),
+])
+def test_fp32_fn_values_against_fp64_oracle(fn_id, n, params):
+    """Entries in the FP32 arithmetic of FP32 sweeps: within a few FP32
+    roundings of the FP64 oracle.  Entries far below the largest may lose
+    relative accuracy (exp underflows to FP32 subnormals), so they are held
+    to an absolute bound of the largest entry's scale."""
+    if isinstance(params, str):
+        params = _sepsum_params(n, 3, 1) if params == "sep" else _bimax_params(2)
+    rng = np.random.default_rng(6)
+    idx = np.stack([rng.integers(0, m, 50000) for m in n], axis=1).astype(np.int32)
+    _say("fp32 fn values", fn_id, n)
+    a = gpu_fn_eval(fn_id, n, idx, params, fp32=True)
+    assert a.dtype == np.float32
+    b = orc_fn_eval(fn_id, n, idx, params)
+    err = np.abs(a.astype(np.float64) - b)
+    scale = np.max(np.abs(b))
+    assert np.max(err) <= 2e-6 * scale
+    big = np.abs(b) >= 1e-3 * scale
+    assert np.max(err[big] / np.abs(b[big])) <= 1e-5
+    if fn_id == FN_HILBERT and params is None:
+        # integer shift: one correctly rounded FP32 division of an exact integer
+        assert np.max(err / np.abs(b)) <= 2.0 ** -24
+
+
 # --------------------------------------------------------------------------
 # FP64: bit-exact pivots and cores
 # --------------------------------------------------------------------------
