@@ -3,5 +3,5 @@
 Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
 import this package.  It shares no code with the GPU library.
 """
-from .oracle import (Oracle, fn_eval, matrix_residual, pairwise_sumsq, sample_indices,  # noqa: F401
+from .oracle import (Oracle, fn_eval, matrix_residual, mix64, pairwise_sumsq, sample_indices,  # noqa: F401
                      splitmix64, tt_eval)

@@ -29,6 +29,9 @@ def lib():
                                  C.c_int]
         L.orc_destroy.argtypes = [P]
         L.orc_run.argtypes = [P]
+        L.orc_set_rook.argtypes = [P, i32p, C.c_int]
+        L.orc_mix64.restype = C.c_uint64
+        L.orc_mix64.argtypes = [C.c_uint64]
         L.orc_get_ranks.argtypes = [P, i32p]
         L.orc_get_pivots.argtypes = [P, C.c_int, P, P, P, P, P]
         L.orc_get_stats.argtypes = [P, f64p, i32p]
@@ -63,6 +66,11 @@ def splitmix64(seed, count):
     out = np.zeros(count, dtype=np.uint64)
     lib().orc_splitmix64_draw(C.c_uint64(seed), count, out)
     return out
+
+
+def mix64(z):
+    """SplitMix64's output function; seeds the rook-mode sample streams."""
+    return int(lib().orc_mix64(C.c_uint64(z)))
 
 
 def sample_indices(n, seed, count):
@@ -112,9 +120,12 @@ def tt_eval(n, ranks, cores, idx):
 
 
 class Oracle:
-    """One greedy TT-cross problem solved by the FP64 CPU oracle."""
+    """One TT-cross problem solved by the FP64 CPU oracle: greedy full search
+    (default) or, with pivot="rook", Alg. 1 inside every subtensor block of
+    `grid` (blocks per mode) with at most rook_iters rounds."""
 
-    def __init__(self, n, eps, fn_id, params=None, seed=0, r_max=64, n_samples=16384):
+    def __init__(self, n, eps, fn_id, params=None, seed=0, r_max=64, n_samples=16384, pivot="greedy",
+                 grid=None, rook_iters=32):
         self._seed = int(seed)
         self.n = np.ascontiguousarray(n, dtype=np.int32)
         self.d = int(self.n.size)
@@ -125,6 +136,12 @@ class Oracle:
                                   r_max, n_samples)
         if not self.h:
             raise ValueError("orc_create rejected the problem")
+        if pivot == "rook":
+            g = np.ones(self.d, dtype=np.int32) if grid is None else np.ascontiguousarray(grid, dtype=np.int32)
+            if lib().orc_set_rook(self.h, g, int(rook_iters)) != 0:
+                raise ValueError("orc_set_rook rejected the options")
+        elif pivot != "greedy":
+            raise ValueError(pivot)
         self.status = None
 
     def __del__(self):

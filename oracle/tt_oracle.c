@@ -42,6 +42,28 @@
  *     recursion, plain division, sums in ascending index order; the file is
  *     compiled with -ffp-contract=off.
  *
+ * Rook mode (orc_set_rook): the search on each superblock is Alg. 1 run
+ * inside every subtensor block (Alg. 3's local pivot), and the pivot of the
+ * unfolding is the best of the local ones.  Readings:
+ *   - blocks: mode j is split into C_j pieces, piece b holding indices
+ *     [floor(b n_j / C_j), floor((b+1) n_j / C_j)); a superblock row (prefix
+ *     tuple, i_k) lies in the block of its k indices, a column (i_{k+1},
+ *     suffix tuple) in the block of its d-k indices; row-block and
+ *     column-block ids are mixed-radix numbers with the first mode fastest,
+ *     and the block id is rowblock + (row blocks) * colblock;
+ *   - the random set of Alg. 1: L = max(64, |rows| + |cols|) pairs drawn from
+ *     SplitMix64 started at seed XOR mix(k | sweep << 8 | block << 32), where
+ *     mix is SplitMix64's output function; each pair is (row draw mod |rows|,
+ *     column draw mod |cols|) over the block's rows and columns in ascending
+ *     position; pairs on a pivot row or column are skipped; if none is left,
+ *     the start is the block's first row and first column without a pivot;
+ *   - the loop of Alg. 1: a column step (largest |residual| in the current
+ *     column) then a row step (in the current row), each taken only if it is
+ *     strictly larger, until neither step moves or after max_iters rounds;
+ *     among equal values the lowest position wins, as in the greedy search;
+ *   - the pivoted count adds one per residual the search looks at (each
+ *     sample kept, each row or column entry scanned).
+ *
  * Indices are 0-based at this interface; the generating functions apply the
  * paper's 1-based formulas internally.
  */
@@ -299,6 +321,8 @@ typedef struct orc_state {
     int ran;
     double *cores;                   /* G_1..G_d concatenated */
     int64_t cores_len;
+    int rook, rook_iters;            /* rook mode: Alg. 1 inside every block */
+    int grid[ORC_MAX_D];             /* subtensor blocks per mode (rook mode) */
 } orc_state;
 
 static void orc_free_state(orc_state *S)
@@ -332,6 +356,9 @@ orc_state *orc_create(int d, const int *n, double eps, int fn_id, const double *
     S->F.fn_id = fn_id; S->F.d = d; S->F.params = S->params_copy; S->F.nparams = nparams;
     for (int j = 0; j < d; ++j) S->F.n[j] = n[j];
     S->hist_cap = (d - 1) * r_max + 2;
+    S->rook = 0;
+    S->rook_iters = 32;
+    for (int j = 0; j < ORC_MAX_D; ++j) S->grid[j] = 1;
     for (int k = 1; k <= d - 1; ++k) {
         S->I[k] = (int *)calloc((size_t)r_max * k, sizeof(int));
         S->J[k] = (int *)calloc((size_t)r_max * (d - k), sizeof(int));
@@ -360,6 +387,154 @@ static void orc_entry_index(const orc_state *S, int k, int64_t row, int64_t col,
     idx[k] = (int)(col % nk1);
     int sl = d - k - 1;                                  /* length of J_{>k+1} tuples */
     for (int j = 0; j < sl; ++j) idx[k + 1 + j] = S->J[k + 1][q * sl + j];
+}
+
+/* Rook mode on: grid[j] blocks per mode (clamped to [1, n_j]; NULL = 1),
+ * at most max_iters rounds of column and row steps per block. */
+int orc_set_rook(orc_state *S, const int *grid, int max_iters)
+{
+    if (!S || max_iters < 1) return ORC_EINVAL;
+    S->rook = 1;
+    S->rook_iters = max_iters;
+    for (int j = 0; j < S->d; ++j) {
+        int c = grid ? grid[j] : 1;
+        if (c < 1) c = 1;
+        if (c > S->n[j]) c = S->n[j];
+        S->grid[j] = c;
+    }
+    return ORC_OK;
+}
+
+/* Piece of index i when n indices are split evenly into C pieces (Sec. 3):
+ * piece b holds [floor(b n / C), floor((b+1) n / C)). */
+static int orc_piece(int i, int n, int C)
+{
+    int b = 0;
+    while (b + 1 < C && (int64_t)(b + 1) * n / C <= i) ++b;
+    return b;
+}
+
+/* SplitMix64's output function (the finaliser without the state step). */
+uint64_t orc_mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+/* (a, ia, ja) beats (b, ib, jb): larger value, else lower position. */
+static int orc_beats(double a, int64_t ia, int64_t ja, double b, int64_t ib, int64_t jb)
+{
+    if (a != b) return a > b;
+    return ia < ib || (ia == ib && ja < jb);
+}
+
+/* Alg. 1 inside every subtensor block of superblock k (residual E, nrow x
+ * ncol, masks of the pivot rows and columns), then the best of the local
+ * pivots (Alg. 3).  Returns 1 and the pivot if some block has an entry
+ * outside the pivot rows and columns. */
+static int orc_rook_search(orc_state *S, int k, const int *rs, const double *E, int64_t nrow, int64_t ncol,
+                           const unsigned char *rmask, const unsigned char *cmask, int64_t *row_out,
+                           int64_t *col_out, double *val_out, int64_t *count_out)
+{
+    int d = S->d, nk = S->n[k - 1], nk1 = S->n[k];
+    int sl = d - k - 1;
+    int64_t *rblk = (int64_t *)malloc(sizeof(int64_t) * nrow);
+    int64_t *cblk = (int64_t *)malloc(sizeof(int64_t) * ncol);
+    int64_t *brow = (int64_t *)malloc(sizeof(int64_t) * nrow);
+    int64_t *bcol = (int64_t *)malloc(sizeof(int64_t) * ncol);
+    if (!rblk || !cblk || !brow || !bcol) {
+        free(rblk); free(cblk); free(brow); free(bcol);
+        return -1;
+    }
+    (void)rs;
+    int64_t nrb = 1, ncb = 1;
+    for (int j = 0; j < k; ++j) nrb *= S->grid[j];
+    for (int j = k; j < d; ++j) ncb *= S->grid[j];
+    for (int64_t i = 0; i < nrow; ++i) {
+        int64_t p = i / nk, id = 0, mul = 1;
+        for (int j = 0; j < k - 1; ++j) {
+            id += orc_piece(S->I[k - 1][p * (k - 1) + j], S->n[j], S->grid[j]) * mul;
+            mul *= S->grid[j];
+        }
+        id += orc_piece((int)(i % nk), nk, S->grid[k - 1]) * mul;
+        rblk[i] = id;
+    }
+    for (int64_t c = 0; c < ncol; ++c) {
+        int64_t q = c / nk1, id = orc_piece((int)(c % nk1), nk1, S->grid[k]), mul = S->grid[k];
+        for (int j = 0; j < sl; ++j) {
+            id += orc_piece(S->J[k + 1][q * sl + j], S->n[k + 1 + j], S->grid[k + 1 + j]) * mul;
+            mul *= S->grid[k + 1 + j];
+        }
+        cblk[c] = id;
+    }
+    int found = 0;
+    double best = -1.0, bestv = 0.0;
+    int64_t br = -1, bc = -1, count = 0;
+    for (int64_t cb = 0; cb < ncb; ++cb) {
+        for (int64_t rb = 0; rb < nrb; ++rb) {
+            int64_t nR = 0, nC = 0;
+            for (int64_t i = 0; i < nrow; ++i) if (rblk[i] == rb) brow[nR++] = i;
+            for (int64_t c = 0; c < ncol; ++c) if (cblk[c] == cb) bcol[nC++] = c;
+            if (nR == 0 || nC == 0) continue;
+            /* the random start of Alg. 1 */
+            uint64_t tag = (uint64_t)k | ((uint64_t)S->sweeps << 8) | ((uint64_t)(rb + nrb * cb) << 32);
+            uint64_t st = S->seed ^ orc_mix64(tag);
+            int64_t L = nR + nC > 64 ? nR + nC : 64;
+            int have = 0;
+            double v = -1.0;
+            int64_t bi = -1, bj = -1;
+            for (int64_t t = 0; t < L; ++t) {
+                uint64_t a = orc_sm64(&st), b = orc_sm64(&st);
+                int64_t i = brow[a % (uint64_t)nR], j = bcol[b % (uint64_t)nC];
+                if (rmask[i] || cmask[j]) continue;
+                ++count;
+                double x = fabs(E[i * ncol + j]);
+                if (!have || orc_beats(x, i, j, v, bi, bj)) { v = x; bi = i; bj = j; have = 1; }
+            }
+            if (!have) {
+                for (int64_t t = 0; t < nR && bi < 0; ++t) if (!rmask[brow[t]]) bi = brow[t];
+                for (int64_t t = 0; t < nC && bj < 0; ++t) if (!cmask[bcol[t]]) bj = bcol[t];
+                if (bi < 0 || bj < 0) continue;
+                v = fabs(E[bi * ncol + bj]);
+                ++count;
+            }
+            /* column step, row step, while either finds a strictly larger entry */
+            for (int it = 0; it < S->rook_iters; ++it) {
+                int moved = 0;
+                int64_t ti = -1;
+                double tv = -1.0;
+                for (int64_t t = 0; t < nR; ++t) {
+                    int64_t i = brow[t];
+                    if (rmask[i]) continue;
+                    ++count;
+                    double x = fabs(E[i * ncol + bj]);
+                    if (x > tv) { tv = x; ti = i; }
+                }
+                if (tv > v) { v = tv; bi = ti; moved = 1; }
+                int64_t tj = -1;
+                tv = -1.0;
+                for (int64_t t = 0; t < nC; ++t) {
+                    int64_t j = bcol[t];
+                    if (cmask[j]) continue;
+                    ++count;
+                    double x = fabs(E[bi * ncol + j]);
+                    if (x > tv) { tv = x; tj = j; }
+                }
+                if (tv > v) { v = tv; bj = tj; moved = 1; }
+                if (!moved) break;
+            }
+            if (!found || orc_beats(v, bi, bj, best, br, bc)) {
+                best = v; br = bi; bc = bj; bestv = E[bi * ncol + bj]; found = 1;
+            }
+        }
+    }
+    free(rblk); free(cblk); free(brow); free(bcol);
+    *row_out = br;
+    *col_out = bc;
+    *val_out = bestv;
+    *count_out = count;
+    return found;
 }
 
 /* One greedy search on superblock k from the raw entries, with the current
@@ -401,6 +576,17 @@ static int orc_search(orc_state *S, int k, const int *rs, int64_t *row_out, int6
                 E[i * ncol + j] = fma(-w[i], u[j], E[i * ncol + j]);
         rmask[pr] = 1;
         cmask[pc] = 1;
+    }
+    if (S->rook) {
+        int64_t cnt = 0;
+        double v = 0.0;
+        int f = orc_rook_search(S, k, rs, E, nrow, ncol, rmask, cmask, row_out, col_out, &v, &cnt);
+        free(E); free(u); free(w); free(rmask); free(cmask);
+        if (f < 0) { S->status = ORC_ENOMEM; return -1; }
+        if (f) *val_out = v;
+        *runner_out = 0.0;               /* no gap log in rook mode */
+        S->pivoted += cnt;
+        return f;
     }
     /* argmax |E| over unmasked entries; row-major scan with strict '>' keeps
      * the lowest (row, col) among equal values */
@@ -494,7 +680,7 @@ int orc_run(orc_state *S)
             double a = found ? fabs(bv) : 0.0;
             if (S->sweeps < S->hist_cap) S->best_hist[k][S->sweeps] = a;
             if (found && a > S->tau) {
-                if (a > 0.0) {
+                if (a > 0.0 && !S->rook) {
                     double g = (a - runner) / a;
                     if (g < S->min_rel_gap) S->min_rel_gap = g;
                 }

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 import scipy.linalg.lapack as lapack
 
-from oracle import Oracle, fn_eval, matrix_residual, pairwise_sumsq, sample_indices, splitmix64, tt_eval
+from oracle import Oracle, fn_eval, matrix_residual, mix64, pairwise_sumsq, sample_indices, splitmix64, tt_eval
 from oracle.oracle import FN_BIMAXWELL, FN_HILBERT, FN_MAXWELL, FN_MAXWELL_2D2V, FN_MAXWELL_3D3V, FN_SEPSUM
 
 
@@ -416,3 +416,107 @@ def test_tt_eval_matches_explicit_matrix_product():
     got = tt_eval(n, ranks, flat, idx)
     ref = np.array([(cores[0][:, a, :] @ cores[1][:, b, :] @ cores[2][:, c, :])[0, 0] for a, b, c in idx])
     assert np.allclose(got, ref, rtol=1e-14, atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# Rook mode: Alg. 1 inside every subtensor block, best of the local pivots
+# (Alg. 3)
+# --------------------------------------------------------------------------
+def _piece(i, n, C):
+    """Subtensor block of index i when n indices are split evenly into C
+    pieces (Sec. 3): the last b with floor(b n / C) <= i."""
+    return max(b for b in range(C) if (b * n) // C <= i)
+
+
+def _pivot_positions(o):
+    return [tuple(map(bytes, o.pivots(k)[:2])) for k in range(1, o.d)]
+
+
+def test_rook_stream_seeds_use_splitmix64_output_function(golden_dir):
+    """The per-block sample streams start at seed XOR mix(tag), mix being the
+    output function of SplitMix64: applied to 1, 2, 3 times the golden gamma it
+    gives the generator's first outputs from state 0."""
+    lines = [ln.strip() for ln in open(os.path.join(golden_dir, "splitmix64_seed0.txt"))
+             if ln.strip() and not ln.startswith("#")]
+    gamma = 0x9E3779B97F4A7C15
+    for t in range(3):
+        assert mix64((gamma * (t + 1)) & 0xFFFFFFFFFFFFFFFF) == int(lines[t], 16)
+
+
+@pytest.mark.parametrize("n,fn_id,params,seed", [
+    ([12, 10, 9], FN_HILBERT, None, 3),
+    ([6, 7, 5, 4], FN_HILBERT, [0.5], 1),
+    ([7, 6, 8], FN_SEPSUM, "sep", 2),
+])
+def test_rook_with_single_entry_blocks_is_the_greedy_search(n, fn_id, params, seed):
+    """With mode j split into n_j pieces every subtensor block of a superblock
+    is one entry, so Alg. 1 returns that entry and the best of the local
+    pivots is the full-search (greedy) pivot: pivots, ranks and cores agree bit
+    for bit."""
+    if params == "sep":
+        params = _sepsum_params(n, 4, 9)
+    g = Oracle(n, 1e-10, fn_id, params, seed=seed)
+    g.run()
+    r = Oracle(n, 1e-10, fn_id, params, seed=seed, pivot="rook", grid=n)
+    r.run()
+    assert list(r.ranks()) == list(g.ranks())
+    assert _pivot_positions(r) == _pivot_positions(g)
+    assert np.array_equal(r.cores_flat(), g.cores_flat())
+
+
+@pytest.mark.parametrize("grid,seed", [([1, 1], 0), ([2, 3], 1), ([4, 2], 2)])
+def test_rook_pivots_are_rook_pivots_within_their_block(grid, seed):
+    """d = 2: every pivot, in order, has the largest |residual| of its row and
+    of its column inside its subtensor block (the stopping condition of
+    Alg. 1), with the residual from the direct CUR formula
+    A - A(:,J) A(I,J)^{-1} A(I,:) over the earlier pivots (numpy solve, not the
+    oracle's recursion).  The rook pivots are not all the greedy ones."""
+    n = [40, 52]
+    params = _sepsum_params(n, 10, 2)
+    A = _full_tensor(FN_SEPSUM, n, params)
+    o = Oracle(n, 1e-14, FN_SEPSUM, params, seed=seed, pivot="rook", grid=grid)
+    o.run()
+    _, _, rho, gam, _ = o.pivots(1)
+    assert len(rho) == 10
+    for z in range(len(rho)):
+        I, J = list(rho[:z]), list(gam[:z])
+        R = A.copy() if z == 0 else A - A[:, J] @ np.linalg.solve(A[np.ix_(I, J)], A[I, :])
+        i, j = int(rho[z]), int(gam[z])
+        rows = [r for r in range(n[0]) if _piece(r, n[0], grid[0]) == _piece(i, n[0], grid[0]) and r not in I]
+        cols = [c for c in range(n[1]) if _piece(c, n[1], grid[1]) == _piece(j, n[1], grid[1]) and c not in J]
+        tol = 1e-10 * np.abs(R).max()
+        assert abs(R[i, j]) >= np.abs(R[rows, j]).max() - tol, z
+        assert abs(R[i, j]) >= np.abs(R[i, cols]).max() - tol, z
+    g = Oracle(n, 1e-14, FN_SEPSUM, params, seed=seed)
+    g.run()
+    assert _pivot_positions(g) != _pivot_positions(o)
+
+
+def test_rook_exact_low_rank_recovery_and_interpolation():
+    """Exactness of eq. (matrix_CUR) does not depend on which pivots are taken:
+    a sum of 3 separable terms is recovered at ranks <= 3 in rook mode too,
+    and the TT interpolates the tensor on its skeleton."""
+    n = [7, 9, 8, 6]
+    params = _sepsum_params(n, 3, 5)
+    o = Oracle(n, 1e-12, FN_SEPSUM, params, seed=3, pivot="rook", grid=[2, 3, 1, 2])
+    o.run()
+    r = o.ranks()
+    assert (r[1:-1] <= 3).all() and r[1:-1].max() == 3
+    err, _ = o.full_error()
+    assert err < 1e-13
+    assert _skeleton_check(o) < 1e-13
+
+
+def test_rook_hilbert3d_full_tensor_error_below_eps():
+    """The 3D Hilbert tensor, n = 32, eps = 1e-10, with rook search on a 2x2x2
+    block grid: the full-tensor relative error meets eps, and the search looks
+    at fewer residuals than the full search."""
+    n = [32] * 3
+    for seed in (0, 1):
+        o = Oracle(n, 1e-10, FN_HILBERT, seed=seed, pivot="rook", grid=[2, 2, 2])
+        o.run()
+        err, _ = o.full_error()
+        assert err <= 1e-10
+        g = Oracle(n, 1e-10, FN_HILBERT, seed=seed)
+        g.run()
+        assert o.stats()["pivoted"] < g.stats()["pivoted"]
