@@ -89,7 +89,10 @@ enum tt_precision {
 };
 
 enum tt_pivot_mode {
-    TT_PIVOT_GREEDY = 0  /* largest |residual| over the whole superblock */
+    TT_PIVOT_GREEDY = 0, /* largest |residual| over the whole superblock (stored residuals) */
+    TT_PIVOT_ROOK = 1    /* Alg. 1 inside every subtensor block, best of the local pivots
+                            (Alg. 3), on residual factors instead of stored residuals;
+                            FP64 sweeps; single solves only (tt_cross_run) */
 };
 
 typedef struct tt_options {

@@ -14,6 +14,7 @@ TT_MAX_RANK = 64
 
 FN_HILBERT, FN_MAXWELL, FN_BIMAXWELL, FN_SEPSUM, FN_MAXWELL_2D2V, FN_MAXWELL_3D3V = 1, 2, 3, 4, 5, 6
 PREC_AUTO, PREC_FP64, PREC_FP32 = 0, 1, 2
+PIVOT_GREEDY, PIVOT_ROOK = 0, 1
 OK, NOT_CONVERGED, WARN_SAMPLED_ERR = 0, 1, 2
 EINVAL, ENOMEM, EDEVICE, ESINGULAR, ESTATE, EFN, EBUSY = -1, -2, -3, -4, -5, -6, -7
 

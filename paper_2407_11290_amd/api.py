@@ -68,7 +68,7 @@ class TTCross:
 
     def __init__(self, n, eps, fn_id, params=None, seed=0, r_max=64, precision=_lib.PREC_AUTO,
                  n_samples=16384, grid=None, tile_rows=0, tile_cols=0, lookahead=2, profile=0,
-                 stream=None, verify=-1):
+                 stream=None, verify=-1, pivot=_lib.PIVOT_GREEDY):
         L = load()
         self.n = _i32(n)
         self.d = int(self.n.size)
@@ -92,6 +92,7 @@ class TTCross:
         o.lookahead = lookahead
         o.profile = profile
         o.verify = verify
+        o.pivot_mode = pivot
         if stream is not None:
             o.stream = C.c_void_p(getattr(stream, "cuda_stream", stream))
         check(L.tt_cross_set_options(self.h, C.byref(o)))

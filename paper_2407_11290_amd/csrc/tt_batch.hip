@@ -398,6 +398,8 @@ extern "C" int tt_batch_run(tt_cross_h *hs, int count, void *hip_stream)
         if (!hs[i]) return set_err(TT_EINVAL, "handle %d is NULL", i);
         for (int j = 0; j < i; ++j)
             if (hs[j] == hs[i]) return set_err(TT_EINVAL, "handle %d appears twice", i);
+        if (hs[i]->p.opt.pivot_mode != TT_PIVOT_GREEDY)
+            return set_err(TT_EINVAL, "handle %d: rook pivoting runs through tt_cross_run only", i);
     }
     for (int i = 0; i < count; ++i) {
         const int st = hs[i]->p.prepare();

@@ -206,6 +206,9 @@ int Problem::allocate()
     H.nk = d - 1;
     H.r_max = opt.r_max;
     H.fp32 = fp32;
+    const bool rook = opt.pivot_mode == TT_PIVOT_ROOK;
+    H.rook = rook ? 1 : 0;
+    for (int j = 0; j < d; ++j) H.grid[j] = grid[j];
     H.F = fn.dev;
     int rcmax = 1;
     for (int k = 0; k <= d; ++k) rcmax = std::max(rcmax, rc[k]);
@@ -252,7 +255,7 @@ int Problem::allocate()
         std::vector<int> rs, rl, rb, cs, cl, cb;
         mode_tiles(n[k - 1], grid[k - 1], TR, rs, rl, rb);
         mode_tiles(n[k], grid[k], TC, cs, cl, cb);
-        if (sweep_lds_bytes(rc[k], TR, TC, w) + lds_static > (size_t)lds_limit)
+        if (!rook && sweep_lds_bytes(rc[k], TR, TC, w) + lds_static > (size_t)lds_limit)
             return set_err(TT_EINVAL, "tile %dx%d with rank cap %d needs more LDS than a workgroup has (%d B)",
                            TR, TC, rc[k], lds_limit);
         K.RTp = (int)rs.size();
@@ -275,7 +278,20 @@ int Problem::allocate()
         K.rt_start = tabs; K.rt_len = tabs + R; K.rt_blk = tabs + 2 * R;
         K.ct_start = tabs + 3 * R; K.ct_len = tabs + 3 * R + Cc; K.ct_blk = tabs + 3 * R + 2 * Cc;
         const int rk = rc[k];
-        if ((st = dalloc(&K.E, (size_t)K.rowcap * K.ld * w)) != TT_OK) return st;
+        if (rook) {
+            // factors W (rows x rank) and U (rank x columns) instead of the residual
+            K.E = nullptr;
+            if ((st = dalloc((void **)&K.Wf, sizeof(double) * K.rowcap * rk)) != TT_OK) return st;
+            if ((st = dalloc((void **)&K.Uf, sizeof(double) * rk * K.colcap)) != TT_OK) return st;
+            K.nrb = 1;
+            K.ncb = 1;
+            for (int j = 0; j < k; ++j) K.nrb *= grid[j];
+            for (int j = k; j < d; ++j) K.ncb *= grid[j];
+            if ((int64_t)K.nrb * K.ncb > (1 << 24)) return set_err(TT_EINVAL, "more than 2^24 subtensor blocks");
+            if ((st = dalloc((void **)&K.bcnt, sizeof(unsigned long long) * K.nrb * K.ncb)) != TT_OK) return st;
+        } else if ((st = dalloc(&K.E, (size_t)K.rowcap * K.ld * w)) != TT_OK) {
+            return st;
+        }
         if ((st = dalloc((void **)&K.rpiv, K.rowcap)) != TT_OK) return st;
         if ((st = dalloc((void **)&K.cpiv, K.colcap)) != TT_OK) return st;
         if ((st = dalloc((void **)&K.Ifull, sizeof(int) * rk * k)) != TT_OK) return st;
@@ -286,7 +302,7 @@ int Problem::allocate()
         if ((st = dalloc((void **)&K.piv64, sizeof(double) * rk)) != TT_OK) return st;
         if ((st = dalloc((void **)&K.Wp64, sizeof(double) * rcmax * rcmax)) != TT_OK) return st;
         if ((st = dalloc((void **)&K.Up64, sizeof(double) * rcmax * rcmax)) != TT_OK) return st;
-        K.cand_cap = (rc[k - 1] * K.RTp) * (rc[k + 1] * K.CTq);
+        K.cand_cap = rook ? K.nrb * K.ncb : (rc[k - 1] * K.RTp) * (rc[k + 1] * K.CTq);
         if ((st = dalloc((void **)&K.cand, sizeof(Cand) * K.cand_cap)) != TT_OK) return st;
         if ((st = dalloc((void **)&K.hist, sizeof(double) * hist_cap)) != TT_OK) return st;
         cores_cap += (int64_t)rc[k - 1] * n[k - 1] * rc[k];
@@ -319,7 +335,7 @@ void Problem::resolve_geometry()
     for (int j = 0; j < d; ++j) grid[j] = std::max(1, std::min(opt.grid[j], n[j]));
     int prec = opt.precision;
     if (prec == TT_PREC_AUTO) prec = (eps >= 1e-6) ? TT_PREC_FP32 : TT_PREC_FP64;
-    if (force_fp64) prec = TT_PREC_FP64;
+    if (force_fp64 || opt.pivot_mode == TT_PIVOT_ROOK) prec = TT_PREC_FP64;
     fp32 = (prec == TT_PREC_FP32) ? 1 : 0;
     req_tr = opt.tile_rows;
     req_tc = opt.tile_cols;
@@ -352,20 +368,24 @@ template <typename V> int Problem::run_impl()
         k_samples<0><<<sample_blocks(ns), NT, 0, stream>>>(dP, opt.seed, ns, d_vals, d_spart);
         k_setup<V, 0><<<1, NT, 0, stream>>>(dP, opt.seed, ns, d_spart, eps);
     }
-    {
+    const bool rook = opt.pivot_mode == TT_PIVOT_ROOK;
+    if (!rook) {
         int maxe = 1;
         for (int u = 0; u < nk; ++u) maxe = std::max(maxe, n[u] * n[u + 1]);
         dim3 g((unsigned)std::min(1024, (maxe + NT - 1) / NT), (unsigned)nk);
         if (hil) k_init_eval<V, TT_FN_HILBERT><<<g, NT, 0, stream>>>(dP);
         else k_init_eval<V, 0><<<g, NT, 0, stream>>>(dP);
     }
+    int rook_wgs = 0;                          // one search workgroup per subtensor block
+    if (rook)
+        for (int u = 0; u < nk; ++u) rook_wgs += hP.kd[u].nrb * hP.kd[u].ncb;
     HIPCHK(hipGetLastError());
     // search sweeps, queued ahead of the host's view of the stop flag
     int rub[TT_MAX_D + 1], rst[TT_MAX_D + 1];   // rank bounds of this launch / of its stored region
     for (int k = 0; k <= d; ++k) rub[k] = rst[k] = 1;
     const int L = std::max(1, opt.lookahead);
     int launched = 0, done_known = 0;
-    const bool prof = opt.profile != 0;
+    const bool prof = opt.profile != 0 && !rook;
     if (prof) {
         while ((int)prof_events.size() < 3 * max_sweeps) {
             hipEvent_t e;
@@ -398,7 +418,20 @@ template <typename V> int Problem::run_impl()
             // the Hilbert tensor gets a kernel built for it alone (fewer
             // registers, more workgroups resident); the others share one
             auto kern = (fn.dev.id == TT_FN_HILBERT) ? k_sweep<V, TT_FN_HILBERT> : k_sweep<V, 0>;
-            if (prof) {
+            if (rook) {
+                // factors: one thread per superblock row and column (bounded by
+                // the ranks this sweep can have), then one workgroup per block
+                int items = 0;
+                for (int u = 0; u < nk; ++u) items += rub[u] * n[u] + n[u + 1] * rub[u + 2];
+                const int gf = std::max(1, std::min((items + NT - 1) / NT, 4096));
+                if (hil) {
+                    k_rook_factors<TT_FN_HILBERT><<<gf, NT, 0, stream>>>(dP, a);
+                    k_rook_search<TT_FN_HILBERT><<<rook_wgs, NT, 0, stream>>>(dP, a, opt.seed);
+                } else {
+                    k_rook_factors<0><<<gf, NT, 0, stream>>>(dP, a);
+                    k_rook_search<0><<<rook_wgs, NT, 0, stream>>>(dP, a, opt.seed);
+                }
+            } else if (prof) {
                 // the events take the dispatch's own start and end timestamps
                 hipExtLaunchKernelGGL(kern, dim3(grid), dim3(NT), (uint32_t)lds, stream,
                                       prof_events[3 * launched], prof_events[3 * launched + 1], 0u, dP, a);
@@ -507,6 +540,7 @@ int Problem::prepare()
 {
     resolve_geometry();
     if (allocated && (alloc_fp32 != fp32 || alloc_rmax != opt.r_max || alloc_tr != req_tr ||
+                      alloc_pivot != opt.pivot_mode ||
                       alloc_tc != req_tc || alloc_ns != opt.n_samples ||
                       std::memcmp(alloc_grid, grid, sizeof grid) != 0)) {
         for (void *p : allocs) (void)hipFree(p);
@@ -520,6 +554,7 @@ int Problem::prepare()
     alloc_rmax = opt.r_max;
     alloc_tr = req_tr;
     alloc_tc = req_tc;
+    alloc_pivot = opt.pivot_mode;
     alloc_ns = opt.n_samples;
     std::memcpy(alloc_grid, grid, sizeof grid);
     ran = false;
@@ -615,7 +650,9 @@ static int check_options(const tt_options *o)
     if (!o) return set_err(TT_EINVAL, "options NULL");
     if (o->r_max < 1 || o->r_max > TT_MAX_RANK) return set_err(TT_EINVAL, "r_max must be in [1,%d]", TT_MAX_RANK);
     if (o->precision < TT_PREC_AUTO || o->precision > TT_PREC_FP32) return set_err(TT_EINVAL, "bad precision");
-    if (o->pivot_mode != TT_PIVOT_GREEDY) return set_err(TT_EINVAL, "only greedy pivoting is available");
+    if (o->pivot_mode != TT_PIVOT_GREEDY && o->pivot_mode != TT_PIVOT_ROOK) return set_err(TT_EINVAL, "bad pivot_mode");
+    if (o->pivot_mode == TT_PIVOT_ROOK && o->precision == TT_PREC_FP32)
+        return set_err(TT_EINVAL, "rook pivoting sweeps in FP64");
     if (o->n_samples < 1 || o->n_samples > (1 << 26)) return set_err(TT_EINVAL, "bad n_samples");
     for (int j = 0; j < TT_MAX_D; ++j)
         if (o->grid[j] < 1) return set_err(TT_EINVAL, "grid[%d] must be >= 1", j);

@@ -13,6 +13,7 @@ constexpr int NT = 256;                    // threads per workgroup (4 wave64)
 constexpr int TT_TILE_ROWS_MAX = 256;      // largest tile extent along the rows
 constexpr double PI = 3.14159265358979323846;
 constexpr uint64_t SM64_GAMMA = 0x9E3779B97F4A7C15ULL;
+constexpr int TT_ROOK_ITERS = 32;          // rounds of Alg. 1's loop per block, at most
 
 // ---------------------------------------------------------------------------
 // Generating function descriptor (copied to the device with the problem).
@@ -185,9 +186,14 @@ struct KDev {
     double *piv64;                // FP64 pivot residual (FP32 sweeps: from the FP64 check)
     double *Wp64;                 // FP64 pivot-block factors: Wp64[z*rcap+z'] (z' < z)
     double *Up64;                 // Up64[z'*rcap+z] (z' < z)
-    Cand *cand;                   // per-tile candidates of the current sweep
+    Cand *cand;                   // per-tile (rook: per-block) candidates of the current sweep
     int cand_cap;
     double *hist;                 // per-sweep largest |residual|
+    // rook mode: factors instead of a stored residual, and the block grid
+    double *Wf;                   // W(i, z) = Wf[i * rk_cap + z], rowcap rows
+    double *Uf;                   // U(z, j) = Uf[z * colcap + j]
+    int nrb, ncb;                 // row blocks (modes 1..k), column blocks (modes k+1..d)
+    unsigned long long *bcnt;     // residuals looked at per block in the current sweep
 };
 
 // What one search sweep does to one unfolding, prepared by the previous commit.
@@ -253,6 +259,8 @@ struct ProbDev {
     int r_max, rcap;
     int hist_cap;
     int fp32;                     // sweeps in FP32 with FP64 pivot check
+    int rook;                     // rook search (Alg. 1 per block) on factors, FP64
+    int grid[TT_MAX_D];           // subtensor blocks per mode
     FnDev F;
     KDev kd[TT_MAX_D];
     ProbState *S;

@@ -51,7 +51,7 @@ struct Problem {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     bool allocated = false;
-    int alloc_fp32 = -1, alloc_rmax = -1, alloc_tr = -1, alloc_tc = -1, alloc_ns = -1;
+    int alloc_fp32 = -1, alloc_rmax = -1, alloc_tr = -1, alloc_tc = -1, alloc_ns = -1, alloc_pivot = -1;
     int alloc_grid[TT_MAX_D] = {0};
     std::vector<void *> allocs;
     ProbDev hP;

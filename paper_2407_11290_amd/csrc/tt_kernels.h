@@ -501,11 +501,19 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
     // best candidate per unfolding: wave w scans unfoldings w, w+NW, ...,
     // with CB candidates per lane in flight at once
     constexpr int CB = 8;
+    __shared__ unsigned long long s_rcnt[TT_MAX_D];
     for (int u = wid; u < nk; u += NW) {
         const KDev &K = P->kd[u];
-        const int ntl = ((ks[u].nr / K.nk) * K.RTp) * ((ks[u].nc / K.nk1) * K.CTq);
+        const int ntl = P->rook ? K.nrb * K.ncb : ((ks[u].nr / K.nk) * K.RTp) * ((ks[u].nc / K.nk1) * K.CTq);
         double bv = -1.0, bs = 0.0;
         uint64_t bk = ~0ULL;
+        if (P->rook) {
+            // residuals the block searches looked at
+            unsigned long long c = 0;
+            for (int i = lane; i < ntl; i += 64) c += K.bcnt[i];
+            for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+            if (lane == 0) s_rcnt[u] = c;
+        }
         for (int i0 = 0; i0 < ntl; i0 += 64 * CB) {
             Cand c[CB];
 #pragma unroll
@@ -571,9 +579,16 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
             const unsigned long long nst = (unsigned long long)ks[u].nr_st, cst = (unsigned long long)ks[u].nc_st;
             const unsigned long long all = (unsigned long long)nr * (unsigned long long)nc;
             const unsigned long long live = (nst - rk) * (cst - rk);
-            s_bytes[u] = live * sizeof(V) * (ks[u].apply ? 2ull : 1ull) + (all - nst * cst) * sizeof(V);
-            s_new[u] = all - nst * cst;
-            s_piv[u] = all;
+            if (P->rook) {
+                // no stored residual: the traffic figures are for the tile search
+                s_bytes[u] = 0;
+                s_new[u] = 0;
+                s_piv[u] = s_rcnt[u];
+            } else {
+                s_bytes[u] = live * sizeof(V) * (ks[u].apply ? 2ull : 1ull) + (all - nst * cst) * sizeof(V);
+                s_new[u] = all - nst * cst;
+                s_piv[u] = all;
+            }
             s_prop[u] = propose ? 1 : 0;
             s_rnew[k] = rk + (propose ? 1 : 0);
             if (propose) {
@@ -830,6 +845,275 @@ static __global__ void __launch_bounds__(NT) k_setup(const ProbDev *__restrict__
                                                 const SamplePart *part, double eps)
 {
     setup_body<V, FNS>(P, seed, ns, part, eps);
+}
+
+// ---------------------------------------------------------------------------
+// Rook mode: Alg. 1 run inside every subtensor block (the local pivot of
+// Alg. 3) on residual factors instead of a stored residual.  For pivot z at
+// (rho_z, gamma_z) with value p_z,
+//   W(i, z) = residual of row i at column gamma_z before pivot z,
+//   U(z, j) = residual of row rho_z at column j before pivot z, over p_z,
+// each formed from the generating function and the earlier factors by the
+// same fma chain as the in-place elimination, so that the residual at (i, j)
+// after rk pivots, X(i, j) - sum_z W(i, z) U(z, j) in pivot order, carries
+// the same bits as the stored residual of the greedy search.  Memory is
+// (rows + columns) x rank instead of rows x columns.
+// ---------------------------------------------------------------------------
+
+// Piece of index i when n indices are split evenly into C pieces: piece b
+// holds [floor(b n / C), floor((b+1) n / C)), so b = floor(((i+1) C - 1) / n).
+__device__ inline int grid_piece(int i, int n, int C)
+{
+    return (int)(((int64_t)(i + 1) * C - 1) / n);
+}
+
+__device__ inline int piece_start(int b, int n, int C) { return (int)((int64_t)b * n / C); }
+
+// The generating function at superblock entry (row, col) of unfolding u.
+template <int FNS>
+__device__ inline double rook_entry(const ProbDev *__restrict__ P, int u, int row, int col)
+{
+    const KDev &K = P->kd[u];
+    const int k = u + 1, d = P->d;
+    const int p = row / K.nk, ik = row - p * K.nk;
+    const int q = col / K.nk1, ik1 = col - q * K.nk1;
+    const int *Ip = (k > 1) ? P->kd[u - 1].Ifull + p * (k - 1) : nullptr;
+    const int *Jq = (k < d - 1) ? P->kd[u + 1].Jfull + q * (d - k - 1) : nullptr;
+    return fn_value_ix<double, FNS>(P->F, [&](int j) {
+        return j < k - 1 ? Ip[j] : (j == k - 1 ? ik : (j == k ? ik1 : Jq[j - k - 1]));
+    });
+}
+
+// Factors for this sweep: the newest pivot's column of W on the rows of the
+// previous superblock and row of U on its columns, and every pivot's factor
+// on the rows and columns that are new.  One thread per superblock row or
+// column; every value read was written by an earlier sweep or earlier in the
+// same thread.
+template <int FNS>
+__device__ void rook_factor_body(const ProbDev *__restrict__ P, int nk, int blk, int nblk)
+{
+    const ProbState *S = P->S;
+    if (S->stop) return;
+    __shared__ KSweep ks[TT_MAX_D];
+    __shared__ int off[TT_MAX_D + 1];
+    if (threadIdx.x < nk) ks[threadIdx.x] = S->ks[threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int o = 0;
+        for (int u = 0; u < nk; ++u) { off[u] = o; o += ks[u].nr + ks[u].nc; }
+        off[nk] = o;
+    }
+    __syncthreads();
+    const int tot = off[nk];
+    for (int t = blk * NT + (int)threadIdx.x; t < tot; t += nblk * NT) {
+        int u = 0;
+        while (u + 1 < nk && t >= off[u + 1]) ++u;
+        const KDev &K = P->kd[u];
+        const KSweep &s = ks[u];
+        const int e = t - off[u], rk = s.rk, wp = K.rk_cap;
+        double *W = K.Wf, *U = K.Uf;
+        if (e < s.nr) {
+            const int i = e;
+            const int z0 = (i < s.nr_st) ? (s.apply ? rk - 1 : rk) : 0;
+            for (int z = z0; z < rk; ++z) {
+                const int gz = K.gam[z];
+                double x = rook_entry<FNS>(P, u, i, gz);
+                for (int zp = 0; zp < z; ++zp) x = __fma_rn(-W[(int64_t)i * wp + zp], U[(int64_t)zp * K.colcap + gz], x);
+                W[(int64_t)i * wp + z] = x;
+            }
+        } else {
+            const int j = e - s.nr;
+            const int z0 = (j < s.nc_st) ? (s.apply ? rk - 1 : rk) : 0;
+            for (int z = z0; z < rk; ++z) {
+                const int rz = K.rho[z];
+                double x = rook_entry<FNS>(P, u, rz, j);
+                for (int zp = 0; zp < z; ++zp) x = __fma_rn(-W[(int64_t)rz * wp + zp], U[(int64_t)zp * K.colcap + j], x);
+                U[(int64_t)z * K.colcap + j] = x / K.piv[z];
+            }
+        }
+    }
+}
+
+template <int FNS = 0>
+static __global__ void __launch_bounds__(NT) k_rook_factors(const ProbDev *__restrict__ P, SweepArgs a)
+{
+    rook_factor_body<FNS>(P, a.nk, blockIdx.x, gridDim.x);
+}
+
+// Workgroup sum of a count; the result is valid in every thread.
+__device__ inline unsigned long long block_sum_u64(unsigned long long c)
+{
+    __shared__ unsigned long long s_c[NT / 64];
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) s_c[threadIdx.x >> 6] = c;
+    __syncthreads();
+    unsigned long long t = 0;
+    for (int i = 0; i < NT / 64; ++i) t += s_c[i];
+    __syncthreads();
+    return t;
+}
+
+// Workgroup minimum of an int; valid in every thread.
+__device__ inline int block_min_int(int c)
+{
+    __shared__ int s_m[NT / 64];
+    for (int off = 32; off > 0; off >>= 1) c = min(c, __shfl_xor(c, off, 64));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = c;
+    __syncthreads();
+    int t = s_m[0];
+    for (int i = 1; i < NT / 64; ++i) t = min(t, s_m[i]);
+    __syncthreads();
+    return t;
+}
+
+// One subtensor block of one superblock per workgroup: the random start of
+// Alg. 1 from the block's seeded sample stream, then column and row steps
+// while either finds a strictly larger |residual| (at most TT_ROOK_ITERS
+// rounds).  Ties go to the lowest position, as in the greedy search.
+template <int FNS>
+__device__ void rook_search_body(const ProbDev *__restrict__ P, int nk, int sweep, uint64_t seed, int wg)
+{
+    const ProbState *S = P->S;
+    if (S->stop) return;
+    const int tid = threadIdx.x, d = P->d;
+    int u = 0, b = wg;
+    while (u < nk && b >= P->kd[u].nrb * P->kd[u].ncb) { b -= P->kd[u].nrb * P->kd[u].ncb; ++u; }
+    if (u >= nk) return;
+    const KDev &K = P->kd[u];
+    const int k = u + 1;
+    __shared__ KSweep ks;
+    __shared__ int s_pref[TT_MAX_RANK], s_suf[TT_MAX_RANK];
+    __shared__ int s_np, s_nq, s_lo, s_len, s_lo1, s_len1;
+    __shared__ double s_f[TT_MAX_RANK];
+    if (tid == 0) {
+        ks = S->ks[u];
+        const int rb = b % K.nrb, cb = b / K.nrb;
+        int c[TT_MAX_D];
+        int x = rb;
+        for (int j = 0; j < k; ++j) { c[j] = x % P->grid[j]; x /= P->grid[j]; }
+        x = cb;
+        for (int j = k; j < d; ++j) { c[j] = x % P->grid[j]; x /= P->grid[j]; }
+        // prefixes (suffixes) of this sweep whose indices lie in the block
+        const int rp = ks.nr / K.nk, rq = ks.nc / K.nk1;
+        int np = 0;
+        for (int p = 0; p < rp; ++p) {
+            bool ok = true;
+            for (int j = 0; j < k - 1 && ok; ++j)
+                ok = grid_piece(P->kd[u - 1].Ifull[p * (k - 1) + j], P->F.n[j], P->grid[j]) == c[j];
+            if (ok) s_pref[np++] = p;
+        }
+        int nq = 0;
+        for (int q = 0; q < rq; ++q) {
+            bool ok = true;
+            for (int j = 0; j < d - k - 1 && ok; ++j)
+                ok = grid_piece(P->kd[u + 1].Jfull[q * (d - k - 1) + j], P->F.n[k + 1 + j], P->grid[k + 1 + j]) ==
+                     c[k + 1 + j];
+            if (ok) s_suf[nq++] = q;
+        }
+        s_np = np;
+        s_nq = nq;
+        s_lo = piece_start(c[k - 1], K.nk, P->grid[k - 1]);
+        s_len = piece_start(c[k - 1] + 1, K.nk, P->grid[k - 1]) - s_lo;
+        s_lo1 = piece_start(c[k], K.nk1, P->grid[k]);
+        s_len1 = piece_start(c[k] + 1, K.nk1, P->grid[k]) - s_lo1;
+    }
+    __syncthreads();
+    const int len = s_len, len1 = s_len1, lo = s_lo, lo1 = s_lo1;
+    const int nR = s_np * len, nC = s_nq * len1;
+    const int rk = ks.rk, wp = K.rk_cap, cc = K.colcap;
+    const double *W = K.Wf, *U = K.Uf;
+    auto rowpos = [&](int t) { return s_pref[t / len] * K.nk + lo + t % len; };
+    auto colpos = [&](int t) { return s_suf[t / len1] * K.nk1 + lo1 + t % len1; };
+    double bv = -1.0, bs = 0.0;
+    uint64_t bk = ~0ULL;
+    unsigned long long cnt = 0;
+    if (nR > 0 && nC > 0) {
+        // the random set: pair s takes draws 2s (row) and 2s+1 (column)
+        const uint64_t tag = (uint64_t)k | ((uint64_t)sweep << 8) | ((uint64_t)b << 32);
+        const uint64_t sig = seed ^ sm64_mix(tag);
+        const int L = max(64, nR + nC);
+        for (int s = tid; s < L; s += NT) {
+            const uint64_t ra = sm64_at(sig, 2 * (uint64_t)s), ca = sm64_at(sig, 2 * (uint64_t)s + 1);
+            const int row = rowpos((int)(ra % (uint64_t)nR)), col = colpos((int)(ca % (uint64_t)nC));
+            if (K.rpiv[row] || K.cpiv[col]) continue;
+            ++cnt;
+            double x = rook_entry<FNS>(P, u, row, col);
+            for (int z = 0; z < rk; ++z) x = __fma_rn(-W[(int64_t)row * wp + z], U[(int64_t)z * cc + col], x);
+            const uint64_t key = ((uint64_t)row << 32) | (uint32_t)col;
+            if (better(fabs(x), key, bv, bk)) { bv = fabs(x); bk = key; bs = x; }
+        }
+        block_best(bv, bk, bs);
+        if (bv < 0.0) {
+            // no sample off the pivot rows and columns: the first row and column without a pivot
+            int fr = nR, fc = nC;
+            for (int t = tid; t < nR; t += NT) if (!K.rpiv[rowpos(t)]) { fr = min(fr, t); break; }
+            for (int t = tid; t < nC; t += NT) if (!K.cpiv[colpos(t)]) { fc = min(fc, t); break; }
+            fr = block_min_int(fr);
+            fc = block_min_int(fc);
+            if (fr < nR && fc < nC) {
+                const int row = rowpos(fr), col = colpos(fc);
+                double x = rook_entry<FNS>(P, u, row, col);
+                for (int z = 0; z < rk; ++z) x = __fma_rn(-W[(int64_t)row * wp + z], U[(int64_t)z * cc + col], x);
+                bv = fabs(x);
+                bs = x;
+                bk = ((uint64_t)row << 32) | (uint32_t)col;
+                if (tid == 0) ++cnt;
+            }
+        }
+        if (bv >= 0.0) {
+            int ci = (int)(bk >> 32), cj = (int)(bk & 0xffffffffULL);
+            for (int it = 0; it < TT_ROOK_ITERS; ++it) {
+                bool moved = false;
+                // column step: U(:, cj) shared by every row
+                for (int z = tid; z < rk; z += NT) s_f[z] = U[(int64_t)z * cc + cj];
+                __syncthreads();
+                double tv = -1.0, ts = 0.0;
+                uint64_t tk = ~0ULL;
+                for (int t = tid; t < nR; t += NT) {
+                    const int row = rowpos(t);
+                    if (K.rpiv[row]) continue;
+                    ++cnt;
+                    double x = rook_entry<FNS>(P, u, row, cj);
+                    for (int z = 0; z < rk; ++z) x = __fma_rn(-W[(int64_t)row * wp + z], s_f[z], x);
+                    if (better(fabs(x), (uint64_t)row, tv, tk)) { tv = fabs(x); tk = (uint64_t)row; ts = x; }
+                }
+                block_best(tv, tk, ts);
+                if (tv > bv) { bv = tv; bs = ts; ci = (int)tk; moved = true; }
+                // row step: W(ci, :) shared by every column
+                for (int z = tid; z < rk; z += NT) s_f[z] = W[(int64_t)ci * wp + z];
+                __syncthreads();
+                tv = -1.0;
+                ts = 0.0;
+                tk = ~0ULL;
+                for (int t = tid; t < nC; t += NT) {
+                    const int col = colpos(t);
+                    if (K.cpiv[col]) continue;
+                    ++cnt;
+                    double x = rook_entry<FNS>(P, u, ci, col);
+                    for (int z = 0; z < rk; ++z) x = __fma_rn(-s_f[z], U[(int64_t)z * cc + col], x);
+                    if (better(fabs(x), (uint64_t)col, tv, tk)) { tv = fabs(x); tk = (uint64_t)col; ts = x; }
+                }
+                block_best(tv, tk, ts);
+                if (tv > bv) { bv = tv; bs = ts; cj = (int)tk; moved = true; }
+                if (!moved) break;
+            }
+            bk = ((uint64_t)ci << 32) | (uint32_t)cj;
+        }
+    }
+    cnt = block_sum_u64(cnt);
+    if (tid == 0) {
+        Cand &c = K.cand[b];
+        c.v = bv; c.key = bk; c.sv = bs;
+        K.bcnt[b] = cnt;
+    }
+}
+
+template <int FNS = 0>
+static __global__ void __launch_bounds__(NT) k_rook_search(const ProbDev *__restrict__ P, SweepArgs a, uint64_t seed)
+{
+    rook_search_body<FNS>(P, a.nk, a.sweep, seed, blockIdx.x);
 }
 
 // E = X on the initial superblocks (one prefix, one suffix: the first pivot's).
