@@ -125,7 +125,7 @@ class Oracle:
     `grid` (blocks per mode) with at most rook_iters rounds."""
 
     def __init__(self, n, eps, fn_id, params=None, seed=0, r_max=64, n_samples=16384, pivot="greedy",
-                 grid=None, rook_iters=32):
+                 grid=None, rook_iters=8):
         self._seed = int(seed)
         self.n = np.ascontiguousarray(n, dtype=np.int32)
         self.d = int(self.n.size)

@@ -357,7 +357,7 @@ orc_state *orc_create(int d, const int *n, double eps, int fn_id, const double *
     for (int j = 0; j < d; ++j) S->F.n[j] = n[j];
     S->hist_cap = (d - 1) * r_max + 2;
     S->rook = 0;
-    S->rook_iters = 32;
+    S->rook_iters = 8;
     for (int j = 0; j < ORC_MAX_D; ++j) S->grid[j] = 1;
     for (int k = 1; k <= d - 1; ++k) {
         S->I[k] = (int *)calloc((size_t)r_max * k, sizeof(int));

@@ -13,7 +13,7 @@ constexpr int NT = 256;                    // threads per workgroup (4 wave64)
 constexpr int TT_TILE_ROWS_MAX = 256;      // largest tile extent along the rows
 constexpr double PI = 3.14159265358979323846;
 constexpr uint64_t SM64_GAMMA = 0x9E3779B97F4A7C15ULL;
-constexpr int TT_ROOK_ITERS = 32;          // rounds of Alg. 1's loop per block, at most
+constexpr int TT_ROOK_ITERS = 8;           // rounds of Alg. 1's loop per block, at most
 
 // ---------------------------------------------------------------------------
 // Generating function descriptor (copied to the device with the problem).
