@@ -117,7 +117,10 @@ typedef struct tt_options {
                                    eps after FP32 sweeps chosen by TT_PREC_AUTO, the problem is
                                    solved again with FP64 sweeps; if it still exceeds eps the
                                    status is TT_WARN_SAMPLED_ERR. */
-    int32_t pad;
+    int32_t rook_split;         /* rook pivoting: workgroups per subtensor block in the search;
+                                   0 (default) = chosen by the library from the block sizes,
+                                   1 = one workgroup per block, 2..1024 = that many (results
+                                   do not depend on it) */
 } tt_options;
 
 typedef struct tt_stats {

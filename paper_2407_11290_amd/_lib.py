@@ -33,7 +33,7 @@ class Options(C.Structure):
         ("profile", C.c_int32),
         ("stream", C.c_void_p),
         ("verify", C.c_int32),
-        ("pad", C.c_int32),
+        ("rook_split", C.c_int32),
     ]
 
 

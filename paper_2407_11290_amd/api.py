@@ -68,7 +68,7 @@ class TTCross:
 
     def __init__(self, n, eps, fn_id, params=None, seed=0, r_max=64, precision=_lib.PREC_AUTO,
                  n_samples=16384, grid=None, tile_rows=0, tile_cols=0, lookahead=2, profile=0,
-                 stream=None, verify=-1, pivot=_lib.PIVOT_GREEDY):
+                 stream=None, verify=-1, pivot=_lib.PIVOT_GREEDY, rook_split=0):
         L = load()
         self.n = _i32(n)
         self.d = int(self.n.size)
@@ -93,6 +93,7 @@ class TTCross:
         o.profile = profile
         o.verify = verify
         o.pivot_mode = pivot
+        o.rook_split = rook_split
         if stream is not None:
             o.stream = C.c_void_p(getattr(stream, "cuda_stream", stream))
         check(L.tt_cross_set_options(self.h, C.byref(o)))

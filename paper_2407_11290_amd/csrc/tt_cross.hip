@@ -209,6 +209,26 @@ int Problem::allocate()
     const bool rook = opt.pivot_mode == TT_PIVOT_ROOK;
     H.rook = rook ? 1 : 0;
     for (int j = 0; j < d; ++j) H.grid[j] = grid[j];
+    rook_g = 1;
+    if (rook) {
+        // workgroups per block of the search: the option, else enough that a
+        // block's rows and columns at full rank give each about 4096
+        int64_t ext = 0, nblk = 0;
+        for (int k = 1; k <= d - 1; ++k) {
+            int64_t rb = 1, cb = 1;
+            for (int j = 0; j < k; ++j) rb *= grid[j];
+            for (int j = k; j < d; ++j) cb *= grid[j];
+            ext = std::max(ext, (int64_t)rc[k - 1] * n[k - 1] / rb + (int64_t)n[k] * rc[k + 1] / cb);
+            nblk += rb * cb;
+        }
+        if (opt.rook_split > 0) {
+            rook_g = opt.rook_split;
+        } else if (ext >= 8192) {
+            rook_g = (int)std::min<int64_t>(64, ext / 4096);
+            rook_g = (int)std::max<int64_t>(2, std::min<int64_t>(rook_g, 8192 / std::max<int64_t>(1, nblk)));
+        }
+    }
+    H.rook_g = rook_g;
     H.F = fn.dev;
     int rcmax = 1;
     for (int k = 0; k <= d; ++k) rcmax = std::max(rcmax, rc[k]);
@@ -289,6 +309,12 @@ int Problem::allocate()
             for (int j = k; j < d; ++j) K.ncb *= grid[j];
             if ((int64_t)K.nrb * K.ncb > (1 << 24)) return set_err(TT_EINVAL, "more than 2^24 subtensor blocks");
             if ((st = dalloc((void **)&K.bcnt, sizeof(unsigned long long) * K.nrb * K.ncb)) != TT_OK) return st;
+            if (rook_g > 1) {
+                const size_t nb = (size_t)K.nrb * K.ncb;
+                if ((st = dalloc((void **)&K.rpart, sizeof(Cand) * 2 * nb * rook_g)) != TT_OK) return st;
+                if ((st = dalloc((void **)&K.rst, sizeof(RookState) * 2 * nb)) != TT_OK) return st;
+                if ((st = dalloc((void **)&K.rcnt, sizeof(unsigned long long) * nb * rook_g)) != TT_OK) return st;
+            }
         } else if ((st = dalloc(&K.E, (size_t)K.rowcap * K.ld * w)) != TT_OK) {
             return st;
         }
@@ -376,9 +402,11 @@ template <typename V> int Problem::run_impl()
         if (hil) k_init_eval<V, TT_FN_HILBERT><<<g, NT, 0, stream>>>(dP);
         else k_init_eval<V, 0><<<g, NT, 0, stream>>>(dP);
     }
-    int rook_wgs = 0;                          // one search workgroup per subtensor block
+    int rook_wgs = 0;                          // search workgroups: G per subtensor block
     if (rook)
         for (int u = 0; u < nk; ++u) rook_wgs += hP.kd[u].nrb * hP.kd[u].ncb;
+    const int rook_blocks = rook_wgs;
+    rook_wgs *= rook_g;
     HIPCHK(hipGetLastError());
     // search sweeps, queued ahead of the host's view of the stop flag
     int rub[TT_MAX_D + 1], rst[TT_MAX_D + 1];   // rank bounds of this launch / of its stored region
@@ -424,12 +452,21 @@ template <typename V> int Problem::run_impl()
                 int items = 0;
                 for (int u = 0; u < nk; ++u) items += rub[u] * n[u] + n[u + 1] * rub[u + 2];
                 const int gf = std::max(1, std::min((items + NT - 1) / NT, 4096));
-                if (hil) {
-                    k_rook_factors<TT_FN_HILBERT><<<gf, NT, 0, stream>>>(dP, a);
-                    k_rook_search<TT_FN_HILBERT><<<rook_wgs, NT, 0, stream>>>(dP, a, opt.seed);
+                if (hil) k_rook_factors<TT_FN_HILBERT><<<gf, NT, 0, stream>>>(dP, a);
+                else k_rook_factors<0><<<gf, NT, 0, stream>>>(dP, a);
+                if (rook_g == 1) {
+                    if (hil) k_rook_search<TT_FN_HILBERT><<<rook_wgs, NT, 0, stream>>>(dP, a, opt.seed);
+                    else k_rook_search<0><<<rook_wgs, NT, 0, stream>>>(dP, a, opt.seed);
                 } else {
-                    k_rook_factors<0><<<gf, NT, 0, stream>>>(dP, a);
-                    k_rook_search<0><<<rook_wgs, NT, 0, stream>>>(dP, a, opt.seed);
+                    // split search: samples, then a fixed sequence of column
+                    // and row steps (blocks that are done return at once)
+                    if (hil) k_rook_wsample<TT_FN_HILBERT><<<rook_wgs, NT, 0, stream>>>(dP, a, opt.seed);
+                    else k_rook_wsample<0><<<rook_wgs, NT, 0, stream>>>(dP, a, opt.seed);
+                    for (int ph = 1; ph <= 2 * TT_ROOK_ITERS; ++ph) {
+                        if (hil) k_rook_wstep<TT_FN_HILBERT><<<rook_wgs, NT, 0, stream>>>(dP, a, ph);
+                        else k_rook_wstep<0><<<rook_wgs, NT, 0, stream>>>(dP, a, ph);
+                    }
+                    k_rook_wfinish<<<rook_blocks, NT, 0, stream>>>(dP, a);
                 }
             } else if (prof) {
                 // the events take the dispatch's own start and end timestamps
@@ -540,7 +577,7 @@ int Problem::prepare()
 {
     resolve_geometry();
     if (allocated && (alloc_fp32 != fp32 || alloc_rmax != opt.r_max || alloc_tr != req_tr ||
-                      alloc_pivot != opt.pivot_mode ||
+                      alloc_pivot != opt.pivot_mode || alloc_split != opt.rook_split ||
                       alloc_tc != req_tc || alloc_ns != opt.n_samples ||
                       std::memcmp(alloc_grid, grid, sizeof grid) != 0)) {
         for (void *p : allocs) (void)hipFree(p);
@@ -555,6 +592,7 @@ int Problem::prepare()
     alloc_tr = req_tr;
     alloc_tc = req_tc;
     alloc_pivot = opt.pivot_mode;
+    alloc_split = opt.rook_split;
     alloc_ns = opt.n_samples;
     std::memcpy(alloc_grid, grid, sizeof grid);
     ran = false;
@@ -653,6 +691,7 @@ static int check_options(const tt_options *o)
     if (o->pivot_mode != TT_PIVOT_GREEDY && o->pivot_mode != TT_PIVOT_ROOK) return set_err(TT_EINVAL, "bad pivot_mode");
     if (o->pivot_mode == TT_PIVOT_ROOK && o->precision == TT_PREC_FP32)
         return set_err(TT_EINVAL, "rook pivoting sweeps in FP64");
+    if (o->rook_split < 0 || o->rook_split > 1024) return set_err(TT_EINVAL, "rook_split must be in [0,1024]");
     if (o->n_samples < 1 || o->n_samples > (1 << 26)) return set_err(TT_EINVAL, "bad n_samples");
     for (int j = 0; j < TT_MAX_D; ++j)
         if (o->grid[j] < 1) return set_err(TT_EINVAL, "grid[%d] must be >= 1", j);

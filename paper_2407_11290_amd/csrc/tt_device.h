@@ -194,6 +194,20 @@ struct KDev {
     double *Uf;                   // U(z, j) = Uf[z * colcap + j]
     int nrb, ncb;                 // row blocks (modes 1..k), column blocks (modes k+1..d)
     unsigned long long *bcnt;     // residuals looked at per block in the current sweep
+    // rook search split over G workgroups per block
+    Cand *rpart;                  // partial bests: 2 buffers x blocks x G
+    struct RookState *rst;        // block states: 2 buffers x blocks
+    unsigned long long *rcnt;     // counts per (block, workgroup) in the current sweep
+};
+
+// A block's rook search between the launches of the split search.
+struct RookState {
+    double v, sv;                 // |residual| and residual at (ci, cj)
+    int ci, cj;                   // current row and column positions
+    int valid;                    // the block has a start
+    int active;                   // still searching
+    int moved;                    // moved in the current round
+    int pad;
 };
 
 // What one search sweep does to one unfolding, prepared by the previous commit.
@@ -260,6 +274,7 @@ struct ProbDev {
     int hist_cap;
     int fp32;                     // sweeps in FP32 with FP64 pivot check
     int rook;                     // rook search (Alg. 1 per block) on factors, FP64
+    int rook_g;                   // workgroups per block of the split rook search (1: not split)
     int grid[TT_MAX_D];           // subtensor blocks per mode
     FnDev F;
     KDev kd[TT_MAX_D];

@@ -43,6 +43,7 @@ struct Problem {
     int tileTR[TT_MAX_D] = {0}, tileTC[TT_MAX_D] = {0};
     int req_tr = 0, req_tc = 0;    // tile request in force: the options', else the tuned table's
     bool use_table = true;         // false while the tuner times its own candidates
+    int rook_g = 1;                // rook search: workgroups per subtensor block
     int hist_cap = 0, max_sweeps = 0;
     int lds_limit = 65536;         // LDS bytes one workgroup may allocate on this device
     int lds_static = 0;            // static LDS of the search kernel
@@ -51,7 +52,8 @@ struct Problem {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     bool allocated = false;
-    int alloc_fp32 = -1, alloc_rmax = -1, alloc_tr = -1, alloc_tc = -1, alloc_ns = -1, alloc_pivot = -1;
+    int alloc_fp32 = -1, alloc_rmax = -1, alloc_tr = -1, alloc_tc = -1, alloc_ns = -1, alloc_pivot = -1,
+        alloc_split = -1;
     int alloc_grid[TT_MAX_D] = {0};
     std::vector<void *> allocs;
     ProbDev hP;

@@ -968,6 +968,61 @@ __device__ inline int block_min_int(int c)
     return t;
 }
 
+// Rows and columns of one subtensor block of superblock u in this sweep, in
+// ascending position: row t = pref[t / len] * n_k + lo + t % len, column t =
+// suf[t / len1] * n_{k+1} + lo1 + t % len1, with pref (suf) the prefixes
+// (suffixes) whose indices lie in the block.
+struct RookGeom {
+    int np, nq, lo, len, lo1, len1;
+};
+
+// Filled by one thread into workgroup-shared pref, suf and g.
+__device__ inline void rook_block_geom(const ProbDev *__restrict__ P, int u, int b, const KSweep &ks, int *pref,
+                                       int *suf, RookGeom &g)
+{
+    const KDev &K = P->kd[u];
+    const int k = u + 1, d = P->d;
+    const int rb = b % K.nrb, cb = b / K.nrb;
+    int c[TT_MAX_D];
+    int x = rb;
+    for (int j = 0; j < k; ++j) { c[j] = x % P->grid[j]; x /= P->grid[j]; }
+    x = cb;
+    for (int j = k; j < d; ++j) { c[j] = x % P->grid[j]; x /= P->grid[j]; }
+    const int rp = ks.nr / K.nk, rq = ks.nc / K.nk1;
+    int np = 0;
+    for (int p = 0; p < rp; ++p) {
+        bool ok = true;
+        for (int j = 0; j < k - 1 && ok; ++j)
+            ok = grid_piece(P->kd[u - 1].Ifull[p * (k - 1) + j], P->F.n[j], P->grid[j]) == c[j];
+        if (ok) pref[np++] = p;
+    }
+    int nq = 0;
+    for (int q = 0; q < rq; ++q) {
+        bool ok = true;
+        for (int j = 0; j < d - k - 1 && ok; ++j)
+            ok = grid_piece(P->kd[u + 1].Jfull[q * (d - k - 1) + j], P->F.n[k + 1 + j], P->grid[k + 1 + j]) ==
+                 c[k + 1 + j];
+        if (ok) suf[nq++] = q;
+    }
+    g.np = np;
+    g.nq = nq;
+    g.lo = piece_start(c[k - 1], K.nk, P->grid[k - 1]);
+    g.len = piece_start(c[k - 1] + 1, K.nk, P->grid[k - 1]) - g.lo;
+    g.lo1 = piece_start(c[k], K.nk1, P->grid[k]);
+    g.len1 = piece_start(c[k] + 1, K.nk1, P->grid[k]) - g.lo1;
+}
+
+// Residual at (row, col) after rk pivots: the entry minus the factor products
+// in pivot order.  Wrow: W(row, :) (stride 1); Ucol: U(:, col) (stride us).
+template <int FNS>
+__device__ inline double rook_residual(const ProbDev *__restrict__ P, int u, int row, int col, const double *Wrow,
+                                       const double *Ucol, int64_t us, int rk)
+{
+    double x = rook_entry<FNS>(P, u, row, col);
+    for (int z = 0; z < rk; ++z) x = __fma_rn(-Wrow[z], Ucol[(int64_t)z * us], x);
+    return x;
+}
+
 // One subtensor block of one superblock per workgroup: the random start of
 // Alg. 1 from the block's seeded sample stream, then column and row steps
 // while either finds a strictly larger |residual| (at most TT_ROOK_ITERS
@@ -977,7 +1032,7 @@ __device__ void rook_search_body(const ProbDev *__restrict__ P, int nk, int swee
 {
     const ProbState *S = P->S;
     if (S->stop) return;
-    const int tid = threadIdx.x, d = P->d;
+    const int tid = threadIdx.x;
     int u = 0, b = wg;
     while (u < nk && b >= P->kd[u].nrb * P->kd[u].ncb) { b -= P->kd[u].nrb * P->kd[u].ncb; ++u; }
     if (u >= nk) return;
@@ -985,43 +1040,15 @@ __device__ void rook_search_body(const ProbDev *__restrict__ P, int nk, int swee
     const int k = u + 1;
     __shared__ KSweep ks;
     __shared__ int s_pref[TT_MAX_RANK], s_suf[TT_MAX_RANK];
-    __shared__ int s_np, s_nq, s_lo, s_len, s_lo1, s_len1;
+    __shared__ RookGeom s_g;
     __shared__ double s_f[TT_MAX_RANK];
     if (tid == 0) {
         ks = S->ks[u];
-        const int rb = b % K.nrb, cb = b / K.nrb;
-        int c[TT_MAX_D];
-        int x = rb;
-        for (int j = 0; j < k; ++j) { c[j] = x % P->grid[j]; x /= P->grid[j]; }
-        x = cb;
-        for (int j = k; j < d; ++j) { c[j] = x % P->grid[j]; x /= P->grid[j]; }
-        // prefixes (suffixes) of this sweep whose indices lie in the block
-        const int rp = ks.nr / K.nk, rq = ks.nc / K.nk1;
-        int np = 0;
-        for (int p = 0; p < rp; ++p) {
-            bool ok = true;
-            for (int j = 0; j < k - 1 && ok; ++j)
-                ok = grid_piece(P->kd[u - 1].Ifull[p * (k - 1) + j], P->F.n[j], P->grid[j]) == c[j];
-            if (ok) s_pref[np++] = p;
-        }
-        int nq = 0;
-        for (int q = 0; q < rq; ++q) {
-            bool ok = true;
-            for (int j = 0; j < d - k - 1 && ok; ++j)
-                ok = grid_piece(P->kd[u + 1].Jfull[q * (d - k - 1) + j], P->F.n[k + 1 + j], P->grid[k + 1 + j]) ==
-                     c[k + 1 + j];
-            if (ok) s_suf[nq++] = q;
-        }
-        s_np = np;
-        s_nq = nq;
-        s_lo = piece_start(c[k - 1], K.nk, P->grid[k - 1]);
-        s_len = piece_start(c[k - 1] + 1, K.nk, P->grid[k - 1]) - s_lo;
-        s_lo1 = piece_start(c[k], K.nk1, P->grid[k]);
-        s_len1 = piece_start(c[k] + 1, K.nk1, P->grid[k]) - s_lo1;
+        rook_block_geom(P, u, b, ks, s_pref, s_suf, s_g);
     }
     __syncthreads();
-    const int len = s_len, len1 = s_len1, lo = s_lo, lo1 = s_lo1;
-    const int nR = s_np * len, nC = s_nq * len1;
+    const int len = s_g.len, len1 = s_g.len1, lo = s_g.lo, lo1 = s_g.lo1;
+    const int nR = s_g.np * len, nC = s_g.nq * len1;
     const int rk = ks.rk, wp = K.rk_cap, cc = K.colcap;
     const double *W = K.Wf, *U = K.Uf;
     auto rowpos = [&](int t) { return s_pref[t / len] * K.nk + lo + t % len; };
@@ -1039,8 +1066,7 @@ __device__ void rook_search_body(const ProbDev *__restrict__ P, int nk, int swee
             const int row = rowpos((int)(ra % (uint64_t)nR)), col = colpos((int)(ca % (uint64_t)nC));
             if (K.rpiv[row] || K.cpiv[col]) continue;
             ++cnt;
-            double x = rook_entry<FNS>(P, u, row, col);
-            for (int z = 0; z < rk; ++z) x = __fma_rn(-W[(int64_t)row * wp + z], U[(int64_t)z * cc + col], x);
+            const double x = rook_residual<FNS>(P, u, row, col, W + (int64_t)row * wp, U + col, cc, rk);
             const uint64_t key = ((uint64_t)row << 32) | (uint32_t)col;
             if (better(fabs(x), key, bv, bk)) { bv = fabs(x); bk = key; bs = x; }
         }
@@ -1054,8 +1080,7 @@ __device__ void rook_search_body(const ProbDev *__restrict__ P, int nk, int swee
             fc = block_min_int(fc);
             if (fr < nR && fc < nC) {
                 const int row = rowpos(fr), col = colpos(fc);
-                double x = rook_entry<FNS>(P, u, row, col);
-                for (int z = 0; z < rk; ++z) x = __fma_rn(-W[(int64_t)row * wp + z], U[(int64_t)z * cc + col], x);
+                const double x = rook_residual<FNS>(P, u, row, col, W + (int64_t)row * wp, U + col, cc, rk);
                 bv = fabs(x);
                 bs = x;
                 bk = ((uint64_t)row << 32) | (uint32_t)col;
@@ -1075,8 +1100,7 @@ __device__ void rook_search_body(const ProbDev *__restrict__ P, int nk, int swee
                     const int row = rowpos(t);
                     if (K.rpiv[row]) continue;
                     ++cnt;
-                    double x = rook_entry<FNS>(P, u, row, cj);
-                    for (int z = 0; z < rk; ++z) x = __fma_rn(-W[(int64_t)row * wp + z], s_f[z], x);
+                    const double x = rook_residual<FNS>(P, u, row, cj, W + (int64_t)row * wp, s_f, 1, rk);
                     if (better(fabs(x), (uint64_t)row, tv, tk)) { tv = fabs(x); tk = (uint64_t)row; ts = x; }
                 }
                 block_best(tv, tk, ts);
@@ -1091,8 +1115,7 @@ __device__ void rook_search_body(const ProbDev *__restrict__ P, int nk, int swee
                     const int col = colpos(t);
                     if (K.cpiv[col]) continue;
                     ++cnt;
-                    double x = rook_entry<FNS>(P, u, ci, col);
-                    for (int z = 0; z < rk; ++z) x = __fma_rn(-s_f[z], U[(int64_t)z * cc + col], x);
+                    const double x = rook_residual<FNS>(P, u, ci, col, s_f, U + col, cc, rk);
                     if (better(fabs(x), (uint64_t)col, tv, tk)) { tv = fabs(x); tk = (uint64_t)col; ts = x; }
                 }
                 block_best(tv, tk, ts);
@@ -1108,6 +1131,255 @@ __device__ void rook_search_body(const ProbDev *__restrict__ P, int nk, int swee
         c.v = bv; c.key = bk; c.sv = bs;
         K.bcnt[b] = cnt;
     }
+}
+
+// ---------------------------------------------------------------------------
+// The same search with G workgroups per block, for large blocks.  The random
+// set and every column or row scan are split over the G workgroups; each
+// writes its partial best, and the next launch reduces the partials (every
+// workgroup the same way) and moves the block's state.  Phase 0 draws the
+// samples, phase p = 1..2 TT_ROOK_ITERS is a column step (p odd) or a row
+// step (p even), and a finishing launch applies the last step.  A block whose
+// round moved nothing is done; its later launches return at once.  Values,
+// order of comparisons and counts are those of the one-workgroup search.
+// ---------------------------------------------------------------------------
+__device__ inline bool rook_wg_of(const ProbDev *__restrict__ P, int nk, int G, int wg, int &u, int &b, int &g)
+{
+    u = 0;
+    int r = wg;
+    while (u < nk && r >= P->kd[u].nrb * P->kd[u].ncb * G) { r -= P->kd[u].nrb * P->kd[u].ncb * G; ++u; }
+    if (u >= nk) return false;
+    b = r / G;
+    g = r - b * G;
+    return true;
+}
+
+template <int FNS>
+__device__ void rook_wsample_body(const ProbDev *__restrict__ P, int nk, int sweep, uint64_t seed, int wg)
+{
+    const ProbState *S = P->S;
+    if (S->stop) return;
+    const int tid = threadIdx.x, G = P->rook_g;
+    int u, b, g;
+    if (!rook_wg_of(P, nk, G, wg, u, b, g)) return;
+    const KDev &K = P->kd[u];
+    const int k = u + 1;
+    __shared__ KSweep ks;
+    __shared__ int s_pref[TT_MAX_RANK], s_suf[TT_MAX_RANK];
+    __shared__ RookGeom s_g;
+    if (tid == 0) {
+        ks = S->ks[u];
+        rook_block_geom(P, u, b, ks, s_pref, s_suf, s_g);
+    }
+    __syncthreads();
+    const int len = s_g.len, len1 = s_g.len1, lo = s_g.lo, lo1 = s_g.lo1;
+    const int nR = s_g.np * len, nC = s_g.nq * len1;
+    const int rk = ks.rk, wp = K.rk_cap, cc = K.colcap;
+    auto rowpos = [&](int t) { return s_pref[t / len] * K.nk + lo + t % len; };
+    auto colpos = [&](int t) { return s_suf[t / len1] * K.nk1 + lo1 + t % len1; };
+    double bv = -1.0, bs = 0.0;
+    uint64_t bk = ~0ULL;
+    unsigned long long cnt = 0;
+    if (nR > 0 && nC > 0) {
+        const uint64_t tag = (uint64_t)k | ((uint64_t)sweep << 8) | ((uint64_t)b << 32);
+        const uint64_t sig = seed ^ sm64_mix(tag);
+        const int L = max(64, nR + nC);
+        for (int s = g * NT + tid; s < L; s += G * NT) {
+            const uint64_t ra = sm64_at(sig, 2 * (uint64_t)s), ca = sm64_at(sig, 2 * (uint64_t)s + 1);
+            const int row = rowpos((int)(ra % (uint64_t)nR)), col = colpos((int)(ca % (uint64_t)nC));
+            if (K.rpiv[row] || K.cpiv[col]) continue;
+            ++cnt;
+            const double x = rook_residual<FNS>(P, u, row, col, K.Wf + (int64_t)row * wp, K.Uf + col, cc, rk);
+            const uint64_t key = ((uint64_t)row << 32) | (uint32_t)col;
+            if (better(fabs(x), key, bv, bk)) { bv = fabs(x); bk = key; bs = x; }
+        }
+    }
+    block_best(bv, bk, bs);
+    cnt = block_sum_u64(cnt);
+    if (tid == 0) {
+        const int nb = K.nrb * K.ncb;
+        Cand &c = K.rpart[(int64_t)0 * nb * G + (int64_t)b * G + g];
+        c.v = bv; c.key = bk; c.sv = bs;
+        K.rcnt[(int64_t)b * G + g] = cnt;
+    }
+}
+
+// Best of the G partials of block b in partial buffer buf.
+__device__ inline void rook_reduce_parts(const KDev &K, int G, int buf, int b, double &pv, uint64_t &pk, double &psv)
+{
+    const int nb = K.nrb * K.ncb;
+    pv = -1.0; psv = 0.0; pk = ~0ULL;
+    for (int i = threadIdx.x; i < G; i += NT) {
+        const Cand c = K.rpart[(int64_t)buf * nb * G + (int64_t)b * G + i];
+        if (better(c.v, c.key, pv, pk)) { pv = c.v; pk = c.key; psv = c.sv; }
+    }
+    block_best(pv, pk, psv);
+}
+
+// The block's state entering phase p >= 2, from the state entering p-1 and
+// the partials p-1 left.
+__device__ inline RookState rook_advance(RookState s, int p, double pv, uint64_t pk, double psv)
+{
+    if (!s.active) return s;
+    if ((p - 1) & 1) {                          // p-1 was a column step
+        if (pv > s.v) { s.v = pv; s.sv = psv; s.ci = (int)pk; s.moved = 1; }
+    } else {                                    // p-1 was a row step: a round ends
+        if (pv > s.v) { s.v = pv; s.sv = psv; s.cj = (int)pk; s.moved = 1; }
+        if (!s.moved) s.active = 0;
+        s.moved = 0;
+    }
+    return s;
+}
+
+template <int FNS>
+__device__ void rook_wstep_body(const ProbDev *__restrict__ P, int nk, int p, int wg)
+{
+    const ProbState *S = P->S;
+    if (S->stop) return;
+    const int tid = threadIdx.x, G = P->rook_g;
+    int u, b, g;
+    if (!rook_wg_of(P, nk, G, wg, u, b, g)) return;
+    const KDev &K = P->kd[u];
+    const int nb = K.nrb * K.ncb;
+    __shared__ KSweep ks;
+    __shared__ int s_pref[TT_MAX_RANK], s_suf[TT_MAX_RANK];
+    __shared__ RookGeom s_g;
+    __shared__ RookState st;
+    __shared__ double s_f[TT_MAX_RANK];
+    if (tid == 0) {
+        ks = S->ks[u];
+        rook_block_geom(P, u, b, ks, s_pref, s_suf, s_g);
+    }
+    double pv, psv;
+    uint64_t pk;
+    rook_reduce_parts(K, G, (p - 1) & 1, b, pv, pk, psv);    // also orders the geometry
+    const int len = s_g.len, len1 = s_g.len1, lo = s_g.lo, lo1 = s_g.lo1;
+    const int nR = s_g.np * len, nC = s_g.nq * len1;
+    const int rk = ks.rk, wp = K.rk_cap, cc = K.colcap;
+    const double *W = K.Wf, *U = K.Uf;
+    auto rowpos = [&](int t) { return s_pref[t / len] * K.nk + lo + t % len; };
+    auto colpos = [&](int t) { return s_suf[t / len1] * K.nk1 + lo1 + t % len1; };
+    unsigned long long cnt = 0;
+    if (tid == 0) {
+        RookState s;
+        if (p == 1) {
+            s.valid = pv >= 0.0 ? 1 : 0;
+            s.active = s.valid;
+            s.moved = 0;
+            s.v = pv;
+            s.sv = psv;
+            s.ci = (int)(pk >> 32);
+            s.cj = (int)(pk & 0xffffffffULL);
+        } else {
+            s = rook_advance(K.rst[(int64_t)((p - 1) & 1) * nb + b], p, pv, pk, psv);
+        }
+        st = s;
+    }
+    __syncthreads();
+    if (p == 1 && !st.valid && nR > 0 && nC > 0) {
+        // no sample off the pivot rows and columns: the first row and column without a pivot
+        int fr = nR, fc = nC;
+        for (int t = tid; t < nR; t += NT) if (!K.rpiv[rowpos(t)]) { fr = min(fr, t); break; }
+        for (int t = tid; t < nC; t += NT) if (!K.cpiv[colpos(t)]) { fc = min(fc, t); break; }
+        fr = block_min_int(fr);
+        fc = block_min_int(fc);
+        if (fr < nR && fc < nC && tid == 0) {
+            const int row = rowpos(fr), col = colpos(fc);
+            const double x = rook_residual<FNS>(P, u, row, col, W + (int64_t)row * wp, U + col, cc, rk);
+            st.v = fabs(x);
+            st.sv = x;
+            st.ci = row;
+            st.cj = col;
+            st.valid = 1;
+            st.active = 1;
+            if (g == 0) cnt = 1;
+        }
+        __syncthreads();
+    }
+    if (g == 0 && tid == 0) K.rst[(int64_t)(p & 1) * nb + b] = st;
+    double tv = -1.0, ts = 0.0;
+    uint64_t tk = ~0ULL;
+    if (st.active) {
+        if (p & 1) {
+            // column step
+            for (int z = tid; z < rk; z += NT) s_f[z] = U[(int64_t)z * cc + st.cj];
+            __syncthreads();
+            for (int t = g * NT + tid; t < nR; t += G * NT) {
+                const int row = rowpos(t);
+                if (K.rpiv[row]) continue;
+                ++cnt;
+                const double x = rook_residual<FNS>(P, u, row, st.cj, W + (int64_t)row * wp, s_f, 1, rk);
+                if (better(fabs(x), (uint64_t)row, tv, tk)) { tv = fabs(x); tk = (uint64_t)row; ts = x; }
+            }
+        } else {
+            // row step
+            for (int z = tid; z < rk; z += NT) s_f[z] = W[(int64_t)st.ci * wp + z];
+            __syncthreads();
+            for (int t = g * NT + tid; t < nC; t += G * NT) {
+                const int col = colpos(t);
+                if (K.cpiv[col]) continue;
+                ++cnt;
+                const double x = rook_residual<FNS>(P, u, st.ci, col, s_f, U + col, cc, rk);
+                if (better(fabs(x), (uint64_t)col, tv, tk)) { tv = fabs(x); tk = (uint64_t)col; ts = x; }
+            }
+        }
+    }
+    block_best(tv, tk, ts);
+    cnt = block_sum_u64(cnt);
+    if (tid == 0) {
+        Cand &c = K.rpart[(int64_t)(p & 1) * nb * G + (int64_t)b * G + g];
+        c.v = tv; c.key = tk; c.sv = ts;
+        K.rcnt[(int64_t)b * G + g] += cnt;
+    }
+}
+
+// After the last step: the block's pivot and count.  One workgroup per block.
+__device__ inline void rook_wfinish_body(const ProbDev *__restrict__ P, int nk, int wg)
+{
+    const ProbState *S = P->S;
+    if (S->stop) return;
+    const int G = P->rook_g, p = 2 * TT_ROOK_ITERS + 1;
+    int u, b, g;
+    if (!rook_wg_of(P, nk, 1, wg, u, b, g)) return;
+    const KDev &K = P->kd[u];
+    const int nb = K.nrb * K.ncb;
+    double pv, psv;
+    uint64_t pk;
+    rook_reduce_parts(K, G, (p - 1) & 1, b, pv, pk, psv);
+    unsigned long long c = 0;
+    for (int i = threadIdx.x; i < G; i += NT) c += K.rcnt[(int64_t)b * G + i];
+    c = block_sum_u64(c);
+    if (threadIdx.x == 0) {
+        const RookState s = rook_advance(K.rst[(int64_t)((p - 1) & 1) * nb + b], p, pv, pk, psv);
+        Cand &o = K.cand[b];
+        if (s.valid) {
+            o.v = s.v;
+            o.key = ((uint64_t)s.ci << 32) | (uint32_t)s.cj;
+            o.sv = s.sv;
+        } else {
+            o.v = -1.0;
+            o.key = ~0ULL;
+            o.sv = 0.0;
+        }
+        K.bcnt[b] = c;
+    }
+}
+
+template <int FNS = 0>
+static __global__ void __launch_bounds__(NT) k_rook_wsample(const ProbDev *__restrict__ P, SweepArgs a, uint64_t seed)
+{
+    rook_wsample_body<FNS>(P, a.nk, a.sweep, seed, blockIdx.x);
+}
+
+template <int FNS = 0>
+static __global__ void __launch_bounds__(NT) k_rook_wstep(const ProbDev *__restrict__ P, SweepArgs a, int phase)
+{
+    rook_wstep_body<FNS>(P, a.nk, phase, blockIdx.x);
+}
+
+static __global__ void __launch_bounds__(NT) k_rook_wfinish(const ProbDev *__restrict__ P, SweepArgs a)
+{
+    rook_wfinish_body(P, a.nk, blockIdx.x);
 }
 
 template <int FNS = 0>

@@ -21,9 +21,9 @@ def _sep(n, r, seed):
     return np.concatenate([[float(r)], 0.5 + rng.random(r * int(np.sum(n)))])
 
 
-def _both(n, eps, fn, params, seed, grid):
-    _say("rook", n, fn, seed, grid)
-    g = TTCross(n, eps, fn, params, seed=seed, grid=grid, precision=PREC_FP64, pivot=PIVOT_ROOK)
+def _both(n, eps, fn, params, seed, grid, split=0):
+    _say("rook", n, fn, seed, grid, "split", split)
+    g = TTCross(n, eps, fn, params, seed=seed, grid=grid, precision=PREC_FP64, pivot=PIVOT_ROOK, rook_split=split)
     gs = g.run()
     o = Oracle(n, eps, fn, params, seed=seed, pivot="rook", grid=grid)
     os_ = o.run()
@@ -55,18 +55,57 @@ def _assert_same(g, gs, o, os_):
     ([16] * 6, FN_HILBERT, None, [2] * 6, 1e-8, 0),
     ([5, 40, 3, 7, 9], FN_HILBERT, None, [1, 4, 1, 1, 2], 1e-9, 6),
 ])
-def test_rook_pivots_match_the_oracle(n, fn, params, grid, eps, seed):
+@pytest.mark.parametrize("split", [1, 3])
+def test_rook_pivots_match_the_oracle(n, fn, params, grid, eps, seed, split):
+    """One workgroup per block (split 1), and the search split over three
+    workgroups per block with partial results passed between launches."""
     if params == "sep":
         params = _sep(n, 4, seed)
-    _assert_same(*_both(n, eps, fn, params, seed, grid))
+    _assert_same(*_both(n, eps, fn, params, seed, grid, split))
 
 
-@pytest.mark.parametrize("seed", [0, 1])
-def test_rook_hilbert6d_n64_grid2(seed):
+@pytest.mark.parametrize("seed,split", [(0, 0), (1, 0), (0, 16)])
+def test_rook_hilbert6d_n64_grid2(seed, split):
     """The bench workload's tensor with rook search on the 2^6 block grid."""
-    g, gs, o, os_ = _both([64] * 6, 1e-8, FN_HILBERT, None, seed, [2] * 6)
+    g, gs, o, os_ = _both([64] * 6, 1e-8, FN_HILBERT, None, seed, [2] * 6, split)
     _assert_same(g, gs, o, os_)
     assert gs == 0
+
+
+def test_rook_split_over_many_workgroups_with_empty_ones():
+    """64 workgroups per block on small blocks: most have nothing to scan."""
+    _assert_same(*_both([12, 10, 9], 1e-10, FN_HILBERT, None, 3, [2, 2, 3], 64))
+
+
+def test_rook_large_superblocks_meet_eps():
+    """3D Hilbert tensor, n = 20000 per mode (superblocks up to 960000 rows and
+    columns, 7e11 entries, far beyond what stored residuals could hold): the
+    library splits each block's search over several workgroups.  The oracle
+    cannot run this size, so the check is by properties that hold at any
+    size: the sampled relative error against the generating function meets
+    eps within the usual factor, and the TT reproduces the tensor on its
+    skeleton (the interpolation property, Sec. 2.3)."""
+    n = [20000] * 3
+    _say("rook n=20000")
+    g = TTCross(n, 1e-8, FN_HILBERT, seed=0, grid=[2, 2, 2], precision=PREC_FP64, pivot=PIVOT_ROOK, r_max=48)
+    assert g.run() == 0
+    err = g.sampled_error(200000)
+    assert err <= 1e-8
+    r = g.ranks()
+    rng = np.random.default_rng(0)
+    idx = []
+    rows1, _ = g.pivots(1)
+    _, cols2 = g.pivots(2)
+    # skeleton entries X(i_1 in I_{<=1}, i_2 any, i_3 in J_{>2})
+    for _ in range(2000):
+        a = rows1[rng.integers(0, r[1])][0]
+        c = cols2[rng.integers(0, r[2])][0]
+        idx.append([a, rng.integers(0, n[1]), c])
+    idx = np.array(idx, dtype=np.int32)
+    from paper_2407_11290_amd.api import fn_eval
+    x = fn_eval(FN_HILBERT, n, idx)
+    y = g.tt_eval(idx)
+    assert np.max(np.abs(x - y) / np.abs(x)) <= 1e-10
 
 
 def test_rook_with_single_entry_blocks_equals_the_greedy_kernels():
