@@ -137,12 +137,15 @@ typedef struct tt_stats {
     double time_to_eps_s;       /* device time of the last tt_cross_run */
     double last_best[TT_MAX_D]; /* largest unmasked |residual| per unfolding in the final sweep */
     /* filled when options.profile = 1 (device times from HIP events on the run's stream) */
-    int32_t sweep_launches;     /* search-tile launches that did work (one per sweep) */
+    int32_t sweep_launches;     /* search-tile launches that did work (one per sweep); rook
+                                   pivoting: sweeps, each timed over its search launches */
     int32_t pad0;
     double sweep_kernel_s;      /* summed duration of those launches */
     double sweep_alg_bytes;     /* algorithmic residual traffic of the tile launches: 2w per
                                    updated stored entry, w per scanned-only stored entry,
-                                   w per newly evaluated entry (w = 8 FP64, 4 FP32) */
+                                   w per newly evaluated entry (w = 8 FP64, 4 FP32); rook
+                                   pivoting: 8 r_k per residual the search looked at (one
+                                   factor vector streamed) */
     double new_entries;         /* superblock entries evaluated by the tile launches */
     double sweep_phase_s;       /* device time from the first search launch to the end of the last one */
     double sampled_err;         /* the verify check's sampled relative error, -1 if not run */

@@ -413,7 +413,7 @@ template <typename V> int Problem::run_impl()
     for (int k = 0; k <= d; ++k) rub[k] = rst[k] = 1;
     const int L = std::max(1, opt.lookahead);
     int launched = 0, done_known = 0;
-    const bool prof = opt.profile != 0 && !rook;
+    const bool prof = opt.profile != 0;
     if (prof) {
         while ((int)prof_events.size() < 3 * max_sweeps) {
             hipEvent_t e;
@@ -454,6 +454,8 @@ template <typename V> int Problem::run_impl()
                 const int gf = std::max(1, std::min((items + NT - 1) / NT, 4096));
                 if (hil) k_rook_factors<TT_FN_HILBERT><<<gf, NT, 0, stream>>>(dP, a);
                 else k_rook_factors<0><<<gf, NT, 0, stream>>>(dP, a);
+                // profiling: events around the search launches of the sweep
+                if (prof) HIPCHK(hipEventRecord(prof_events[3 * launched], stream));
                 if (rook_g == 1) {
                     if (hil) k_rook_search<TT_FN_HILBERT><<<rook_wgs, NT, 0, stream>>>(dP, a, opt.seed);
                     else k_rook_search<0><<<rook_wgs, NT, 0, stream>>>(dP, a, opt.seed);
@@ -468,6 +470,7 @@ template <typename V> int Problem::run_impl()
                     }
                     k_rook_wfinish<<<rook_blocks, NT, 0, stream>>>(dP, a);
                 }
+                if (prof) HIPCHK(hipEventRecord(prof_events[3 * launched + 1], stream));
             } else if (prof) {
                 // the events take the dispatch's own start and end timestamps
                 hipExtLaunchKernelGGL(kern, dim3(grid), dim3(NT), (uint32_t)lds, stream,

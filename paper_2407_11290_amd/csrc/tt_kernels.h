@@ -580,8 +580,9 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
             const unsigned long long all = (unsigned long long)nr * (unsigned long long)nc;
             const unsigned long long live = (nst - rk) * (cst - rk);
             if (P->rook) {
-                // no stored residual: the traffic figures are for the tile search
-                s_bytes[u] = 0;
+                // every residual looked at streams one factor vector of rk
+                // values (the other is shared by the whole scan)
+                s_bytes[u] = s_rcnt[u] * 8ull * (unsigned long long)rk;
                 s_new[u] = 0;
                 s_piv[u] = s_rcnt[u];
             } else {
@@ -918,7 +919,7 @@ __device__ void rook_factor_body(const ProbDev *__restrict__ P, int nk, int blk,
             for (int z = z0; z < rk; ++z) {
                 const int gz = K.gam[z];
                 double x = rook_entry<FNS>(P, u, i, gz);
-                for (int zp = 0; zp < z; ++zp) x = __fma_rn(-W[(int64_t)i * wp + zp], U[(int64_t)zp * K.colcap + gz], x);
+                for (int zp = 0; zp < z; ++zp) x = __fma_rn(-W[(int64_t)i * wp + zp], U[(int64_t)gz * wp + zp], x);
                 W[(int64_t)i * wp + z] = x;
             }
         } else {
@@ -927,8 +928,8 @@ __device__ void rook_factor_body(const ProbDev *__restrict__ P, int nk, int blk,
             for (int z = z0; z < rk; ++z) {
                 const int rz = K.rho[z];
                 double x = rook_entry<FNS>(P, u, rz, j);
-                for (int zp = 0; zp < z; ++zp) x = __fma_rn(-W[(int64_t)rz * wp + zp], U[(int64_t)zp * K.colcap + j], x);
-                U[(int64_t)z * K.colcap + j] = x / K.piv[z];
+                for (int zp = 0; zp < z; ++zp) x = __fma_rn(-W[(int64_t)rz * wp + zp], U[(int64_t)j * wp + zp], x);
+                U[(int64_t)j * wp + z] = x / K.piv[z];
             }
         }
     }
@@ -1013,7 +1014,9 @@ __device__ inline void rook_block_geom(const ProbDev *__restrict__ P, int u, int
 }
 
 // Residual at (row, col) after rk pivots: the entry minus the factor products
-// in pivot order.  Wrow: W(row, :) (stride 1); Ucol: U(:, col) (stride us).
+// in pivot order.  Wrow: W(row, :); Ucol: U(:, col) (stride us).  Both
+// factors are stored as contiguous vectors of rk_cap values per row (W) and
+// per column (U), so a residual at a random position reads two short runs.
 template <int FNS>
 __device__ inline double rook_residual(const ProbDev *__restrict__ P, int u, int row, int col, const double *Wrow,
                                        const double *Ucol, int64_t us, int rk)
@@ -1049,7 +1052,7 @@ __device__ void rook_search_body(const ProbDev *__restrict__ P, int nk, int swee
     __syncthreads();
     const int len = s_g.len, len1 = s_g.len1, lo = s_g.lo, lo1 = s_g.lo1;
     const int nR = s_g.np * len, nC = s_g.nq * len1;
-    const int rk = ks.rk, wp = K.rk_cap, cc = K.colcap;
+    const int rk = ks.rk, wp = K.rk_cap;
     const double *W = K.Wf, *U = K.Uf;
     auto rowpos = [&](int t) { return s_pref[t / len] * K.nk + lo + t % len; };
     auto colpos = [&](int t) { return s_suf[t / len1] * K.nk1 + lo1 + t % len1; };
@@ -1066,7 +1069,7 @@ __device__ void rook_search_body(const ProbDev *__restrict__ P, int nk, int swee
             const int row = rowpos((int)(ra % (uint64_t)nR)), col = colpos((int)(ca % (uint64_t)nC));
             if (K.rpiv[row] || K.cpiv[col]) continue;
             ++cnt;
-            const double x = rook_residual<FNS>(P, u, row, col, W + (int64_t)row * wp, U + col, cc, rk);
+            const double x = rook_residual<FNS>(P, u, row, col, W + (int64_t)row * wp, U + (int64_t)col * wp, 1, rk);
             const uint64_t key = ((uint64_t)row << 32) | (uint32_t)col;
             if (better(fabs(x), key, bv, bk)) { bv = fabs(x); bk = key; bs = x; }
         }
@@ -1080,7 +1083,7 @@ __device__ void rook_search_body(const ProbDev *__restrict__ P, int nk, int swee
             fc = block_min_int(fc);
             if (fr < nR && fc < nC) {
                 const int row = rowpos(fr), col = colpos(fc);
-                const double x = rook_residual<FNS>(P, u, row, col, W + (int64_t)row * wp, U + col, cc, rk);
+                const double x = rook_residual<FNS>(P, u, row, col, W + (int64_t)row * wp, U + (int64_t)col * wp, 1, rk);
                 bv = fabs(x);
                 bs = x;
                 bk = ((uint64_t)row << 32) | (uint32_t)col;
@@ -1092,7 +1095,7 @@ __device__ void rook_search_body(const ProbDev *__restrict__ P, int nk, int swee
             for (int it = 0; it < TT_ROOK_ITERS; ++it) {
                 bool moved = false;
                 // column step: U(:, cj) shared by every row
-                for (int z = tid; z < rk; z += NT) s_f[z] = U[(int64_t)z * cc + cj];
+                for (int z = tid; z < rk; z += NT) s_f[z] = U[(int64_t)cj * wp + z];
                 __syncthreads();
                 double tv = -1.0, ts = 0.0;
                 uint64_t tk = ~0ULL;
@@ -1115,7 +1118,7 @@ __device__ void rook_search_body(const ProbDev *__restrict__ P, int nk, int swee
                     const int col = colpos(t);
                     if (K.cpiv[col]) continue;
                     ++cnt;
-                    const double x = rook_residual<FNS>(P, u, ci, col, s_f, U + col, cc, rk);
+                    const double x = rook_residual<FNS>(P, u, ci, col, s_f, U + (int64_t)col * wp, 1, rk);
                     if (better(fabs(x), (uint64_t)col, tv, tk)) { tv = fabs(x); tk = (uint64_t)col; ts = x; }
                 }
                 block_best(tv, tk, ts);
@@ -1174,7 +1177,7 @@ __device__ void rook_wsample_body(const ProbDev *__restrict__ P, int nk, int swe
     __syncthreads();
     const int len = s_g.len, len1 = s_g.len1, lo = s_g.lo, lo1 = s_g.lo1;
     const int nR = s_g.np * len, nC = s_g.nq * len1;
-    const int rk = ks.rk, wp = K.rk_cap, cc = K.colcap;
+    const int rk = ks.rk, wp = K.rk_cap;
     auto rowpos = [&](int t) { return s_pref[t / len] * K.nk + lo + t % len; };
     auto colpos = [&](int t) { return s_suf[t / len1] * K.nk1 + lo1 + t % len1; };
     double bv = -1.0, bs = 0.0;
@@ -1189,7 +1192,7 @@ __device__ void rook_wsample_body(const ProbDev *__restrict__ P, int nk, int swe
             const int row = rowpos((int)(ra % (uint64_t)nR)), col = colpos((int)(ca % (uint64_t)nC));
             if (K.rpiv[row] || K.cpiv[col]) continue;
             ++cnt;
-            const double x = rook_residual<FNS>(P, u, row, col, K.Wf + (int64_t)row * wp, K.Uf + col, cc, rk);
+            const double x = rook_residual<FNS>(P, u, row, col, K.Wf + (int64_t)row * wp, K.Uf + (int64_t)col * wp, 1, rk);
             const uint64_t key = ((uint64_t)row << 32) | (uint32_t)col;
             if (better(fabs(x), key, bv, bk)) { bv = fabs(x); bk = key; bs = x; }
         }
@@ -1255,7 +1258,7 @@ __device__ void rook_wstep_body(const ProbDev *__restrict__ P, int nk, int p, in
     rook_reduce_parts(K, G, (p - 1) & 1, b, pv, pk, psv);    // also orders the geometry
     const int len = s_g.len, len1 = s_g.len1, lo = s_g.lo, lo1 = s_g.lo1;
     const int nR = s_g.np * len, nC = s_g.nq * len1;
-    const int rk = ks.rk, wp = K.rk_cap, cc = K.colcap;
+    const int rk = ks.rk, wp = K.rk_cap;
     const double *W = K.Wf, *U = K.Uf;
     auto rowpos = [&](int t) { return s_pref[t / len] * K.nk + lo + t % len; };
     auto colpos = [&](int t) { return s_suf[t / len1] * K.nk1 + lo1 + t % len1; };
@@ -1285,7 +1288,7 @@ __device__ void rook_wstep_body(const ProbDev *__restrict__ P, int nk, int p, in
         fc = block_min_int(fc);
         if (fr < nR && fc < nC && tid == 0) {
             const int row = rowpos(fr), col = colpos(fc);
-            const double x = rook_residual<FNS>(P, u, row, col, W + (int64_t)row * wp, U + col, cc, rk);
+            const double x = rook_residual<FNS>(P, u, row, col, W + (int64_t)row * wp, U + (int64_t)col * wp, 1, rk);
             st.v = fabs(x);
             st.sv = x;
             st.ci = row;
@@ -1302,7 +1305,7 @@ __device__ void rook_wstep_body(const ProbDev *__restrict__ P, int nk, int p, in
     if (st.active) {
         if (p & 1) {
             // column step
-            for (int z = tid; z < rk; z += NT) s_f[z] = U[(int64_t)z * cc + st.cj];
+            for (int z = tid; z < rk; z += NT) s_f[z] = U[(int64_t)st.cj * wp + z];
             __syncthreads();
             for (int t = g * NT + tid; t < nR; t += G * NT) {
                 const int row = rowpos(t);
@@ -1319,7 +1322,7 @@ __device__ void rook_wstep_body(const ProbDev *__restrict__ P, int nk, int p, in
                 const int col = colpos(t);
                 if (K.cpiv[col]) continue;
                 ++cnt;
-                const double x = rook_residual<FNS>(P, u, st.ci, col, s_f, U + col, cc, rk);
+                const double x = rook_residual<FNS>(P, u, st.ci, col, s_f, U + (int64_t)col * wp, 1, rk);
                 if (better(fabs(x), (uint64_t)col, tv, tk)) { tv = fabs(x); tk = (uint64_t)col; ts = x; }
             }
         }
