@@ -1471,8 +1471,9 @@ __host__ __device__ inline int make_core_args(int d, const int *n, const int *r,
 // operations and their order are those of the LDS version below; T(i_z, :)
 // reaches the other lanes by shuffles before lane z updates it.
 template <int RM>
-__device__ void core_alg4_regs(const double *Ap, const double *Ab, int st, int rk, int nr, int i0, double *Gk0)
+__device__ bool core_alg4_regs(const double *Ap, const double *Ab, int st, int rk, int nr, int i0, double *Gk0)
 {
+    bool singular = false;
     const int lane = threadIdx.x;
     const bool piv = lane < rk;
     double ab[RM], tb[RM], tp[RM];
@@ -1497,7 +1498,9 @@ __device__ void core_alg4_regs(const double *Ap, const double *Ab, int st, int r
         }
         const double sb = dotb - ab[z];
         const double sp = piv ? dotp - Ap[lane * st + z] : 0.0;
-        const double delta = 1.0 / (-__shfl(sp, z, 64));
+        const double dinv = -__shfl(sp, z, 64);
+        singular |= dinv == 0.0;
+        const double delta = 1.0 / dinv;
         const double cb = delta * sb, cp = delta * sp;
 #pragma unroll
         for (int zz = 0; zz < z; ++zz) {
@@ -1514,6 +1517,7 @@ __device__ void core_alg4_regs(const double *Ap, const double *Ab, int st, int r
         for (int z = 0; z < RM; ++z)
             if (z < rk) row[z] = tb[z];
     }
+    return singular;
 }
 
 template <int FNS>
@@ -1585,7 +1589,12 @@ __device__ void cores_body(const ProbDev *__restrict__ P, const CoreArgs &a, dou
         }
     }
     wave_sync();
-    if (rk <= 16) { core_alg4_regs<16>(Ap, Ab, st, rk, nr, i0, G + a.goff[u]); return; }
+    if (rk <= 16) {
+        // a zero pivot-block residual (delta^{-1} = 0): singular, as in the oracle
+        if (core_alg4_regs<16>(Ap, Ab, st, rk, nr, i0, G + a.goff[u]) && lane == 0) P->S->err = TT_ESINGULAR;
+        return;
+    }
+    bool singular = false;
     const double a11 = Ap[0];
     for (int z = 0; z < rk; ++z) {
         Tb[z * A4W + lane] = (z == 0) ? Ab[lane] / a11 : 0.0;
@@ -1605,7 +1614,9 @@ __device__ void cores_body(const ProbDev *__restrict__ P, const CoreArgs &a, dou
         }
         const double sb = dotb - Ab[z * A4W + lane];
         const double sp = piv_lane ? dotp - Ap[lane * st + z] : 0.0;
-        const double delta = 1.0 / (-__shfl(sp, z, 64));
+        const double dinv = -__shfl(sp, z, 64);
+        singular |= dinv == 0.0;
+        const double delta = 1.0 / dinv;
         const double cb = delta * sb, cp = delta * sp;
         wave_sync();                            // every lane has read T before it changes
         // every lane reads T(i_z, zz) in the same instruction before lane z
@@ -1627,6 +1638,7 @@ __device__ void cores_body(const ProbDev *__restrict__ P, const CoreArgs &a, dou
         const int ii = e / rk, z = e - ii * rk;
         Gk[e] = Tb[z * A4W + ii];
     }
+    if (singular && lane == 0) P->S->err = TT_ESINGULAR;
 }
 
 template <int FNS = 0>

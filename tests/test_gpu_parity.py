@@ -254,3 +254,49 @@ def test_hilbert_fp32_sweeps_meet_eps():
     idx = rng.integers(0, 32, (20000, 5)).astype(np.int32)
     x = orc_fn_eval(FN_HILBERT, n, idx)
     assert np.max(np.abs(g.tt_eval(idx) - o.tt_eval(idx))) <= 1e-5 * np.max(np.abs(x))
+
+
+def o_status(o):
+    from oracle.oracle import lib as orc_lib
+    return orc_lib().orc_run(o.h)
+
+
+@pytest.mark.parametrize("pivot", ["greedy", "rook"])
+def test_degenerate_and_maximum_shapes(pivot):
+    """A one-entry tensor, eps = 0 (the search runs until the residual is
+    exactly zero or the rank cap), rank cap 1, the largest number of modes
+    (16), and a matrix driven to the full rank cap of 64: same pivots, ranks,
+    cores and status as the oracle, in greedy and in rook mode."""
+    from paper_2407_11290_amd import PIVOT_ROOK
+    cases = [
+        ([1, 1, 1], 1e-8, 64, None),
+        ([4, 5, 3], 0.0, 64, [2, 2, 1]),
+        ([9, 7, 8], 1e-12, 1, [2, 1, 2]),
+        ([2] * 16, 1e-10, 64, [2] * 16),
+        ([200, 180], 0.0, 64, [2, 3]),
+    ]
+    for n, eps, r_max, grid in cases:
+        _say("degenerate", pivot, n, eps, r_max, grid)
+        kw = dict(seed=1, r_max=r_max, precision=PREC_FP64)
+        if grid is not None:
+            kw["grid"] = grid
+        if pivot == "rook":
+            g = TTCross(n, eps, FN_HILBERT, pivot=PIVOT_ROOK, **kw)
+            o = Oracle(n, eps, FN_HILBERT, seed=1, r_max=r_max, pivot="rook", grid=grid)
+        else:
+            g = TTCross(n, eps, FN_HILBERT, **kw)
+            o = Oracle(n, eps, FN_HILBERT, seed=1, r_max=r_max)
+        from paper_2407_11290_amd import _lib
+        gs = _lib.load().tt_cross_run(g.h)      # the status code, errors included
+        os_ = o_status(o)
+        assert gs == os_, (n, gs, os_)
+        if gs < 0:
+            # driven to rounding noise (eps = 0): both sides find the same
+            # zero pivot-block residual in Alg. 4
+            continue
+        _assert_same_pivots(g, o)
+        assert np.array_equal(g.cores_flat(), o.cores_flat())
+        if n == [1, 1, 1]:
+            assert list(g.ranks()) == [1, 1, 1, 1]
+        if r_max == 1:
+            assert max(g.ranks()) == 1
