@@ -1664,33 +1664,45 @@ __device__ void verify_body(const ProbDev *__restrict__ P, const double *__restr
     CoreArgs ca;
     int64_t len;
     make_core_args(d, P->F.n, r, ca, len);
+    // a lane group of GL lanes per sample (GL >= every rank and >= d), so a
+    // wavefront carries 64 / GL samples at once
+    int rmax = d;
+    for (int k = 1; k < d; ++k) rmax = max(rmax, r[k]);
+    const int GL = rmax <= 16 ? 16 : (rmax <= 32 ? 32 : 64), spw = 64 / GL;
+    const int gsub = lane / GL, gl = lane - gsub * GL;
     double num = 0.0, den = 0.0;
-    for (int64_t t = (int64_t)blk * (NT / 64) + wid; t < R; t += (int64_t)nblk * (NT / 64)) {
-        const int ix = (lane < d) ? (int)(sm64_at(seed, (uint64_t)t * d + lane) % (uint64_t)P->F.n[lane]) : 0;
-        double v = (lane == 0) ? 1.0 : 0.0;
+    const int64_t waves = (int64_t)nblk * (NT / 64), wave = (int64_t)blk * (NT / 64) + wid;
+    for (int64_t t0 = wave * spw; t0 < R; t0 += waves * spw) {
+        const int64_t t = t0 + gsub;
+        const bool ok = t < R;
+        const int ix = (ok && gl < d) ? (int)(sm64_at(seed, (uint64_t)t * d + gl) % (uint64_t)P->F.n[gl]) : 0;
+        double v = (gl == 0) ? 1.0 : 0.0;
         for (int k = 0; k < d; ++k) {
-            const int ik = __shfl(ix, k, 64), ra = r[k], rb = r[k + 1], nn = P->F.n[k];
-            const double *Gk = G + ca.goff[k];
+            const int ik = __shfl(ix, k, GL), ra = r[k], rb = r[k + 1], nn = P->F.n[k];
+            const double *Gk = G + ca.goff[k] + (int64_t)ik * rb + gl;
             double acc = 0.0;
             for (int aa = 0; aa < ra; ++aa) {
-                const double va = __shfl(v, aa, 64);
-                if (lane < rb) acc = __fma_rn(va, Gk[((int64_t)aa * nn + ik) * rb + lane], acc);
+                const double va = __shfl(v, aa, GL);
+                if (gl < rb) acc = __fma_rn(va, Gk[(int64_t)aa * nn * rb], acc);
             }
-            v = (lane < rb) ? acc : 0.0;
+            v = (gl < rb) ? acc : 0.0;
         }
-        const double x = fn_value_ix<double>(P->F, [&](int j) { return __shfl(ix, j, 64); });
-        if (lane == 0) {
+        const double x = fn_value_ix<double>(P->F, [&](int j) { return __shfl(ix, j, GL); });
+        if (gl == 0 && ok) {
             const double dx = x - v;
             num = __fma_rn(dx, dx, num);
             den = __fma_rn(x, x, den);
         }
     }
-    __shared__ double sn[NT / 64], sd[NT / 64];
-    if (lane == 0) { sn[wid] = num; sd[wid] = den; }
+    // the group leaders' sums in lane order, then the wavefronts in order
+    __shared__ double sn[NT / 64][64], sd[NT / 64][64];
+    sn[wid][lane] = num;
+    sd[wid][lane] = den;
     __syncthreads();
     if (threadIdx.x == 0) {
         double a = 0.0, b = 0.0;
-        for (int w = 0; w < NT / 64; ++w) { a += sn[w]; b += sd[w]; }
+        for (int w = 0; w < NT / 64; ++w)
+            for (int g = 0; g < spw; ++g) { a += sn[w][g * GL]; b += sd[w][g * GL]; }
         part[2 * blk] = a;
         part[2 * blk + 1] = b;
     }
