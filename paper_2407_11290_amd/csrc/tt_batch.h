@@ -53,6 +53,7 @@ private:
     template <typename V> int launch_sweep(std::vector<int> &ids);
     int launch_cores(std::vector<int> &ids);
     void finish_slot(Slot &s);
+    int copy_slots(void *dst, const void *src, size_t elem, const std::vector<int> &ids, hipMemcpyKind kind);
 
     std::vector<Slot> slots;
     std::vector<hipEvent_t> ev_free;

@@ -115,14 +115,40 @@ int Engine::admit(Problem *Q, void *user)
     D.run.cores = Q->d_cores;
     D.run.verify_R = s.verify_R;
     std::memset(&hm[i], 0, sizeof(HostMirror));
-    HIPCHK(hipMemcpyAsync(dPa + i, &D, sizeof(ProbDev), hipMemcpyHostToDevice, stream));
+    // the descriptor goes to the device with the others of its setup launch
     Q->ran = false;
     return i;
+}
+
+// Copies entries ids of a per-slot array between host and device on the
+// engine's stream: one copy over their index range when the range is dense
+// or small, else one copy per entry.  Everything the engine does runs on
+// this one stream, so a range copy overlaps no kernel.  The other entries it
+// covers are either those of live slots (the same bytes: descriptors do not
+// change after admission, and a finished slot's state no longer changes),
+// or of free slots, or of slots whose own copy comes later on the stream.
+int Engine::copy_slots(void *dst, const void *src, size_t elem, const std::vector<int> &ids, hipMemcpyKind kind)
+{
+    if (ids.empty()) return TT_OK;
+    int lo = ids[0], hi = ids[0];
+    for (int i : ids) { lo = std::min(lo, i); hi = std::max(hi, i); }
+    const size_t span = (size_t)(hi - lo + 1);
+    // one copy when the range is dense or small; a wide sparse range copied
+    // whole measured slower than its entries one by one
+    if (span <= 4 * ids.size() || span * elem <= ((size_t)64 << 10)) {
+        HIPCHK(hipMemcpyAsync((char *)dst + lo * elem, (const char *)src + lo * elem, span * elem, kind, stream));
+    } else {
+        for (int i : ids)
+            HIPCHK(hipMemcpyAsync((char *)dst + (size_t)i * elem, (const char *)src + (size_t)i * elem, elem, kind, stream));
+    }
+    return TT_OK;
 }
 
 // Launch setup for every slot admitted since the last call.
 template <typename V> int Engine::launch_setup(std::vector<int> &ids)
 {
+    int cst = copy_slots(dPa, hPa, sizeof(ProbDev), ids, hipMemcpyHostToDevice);
+    if (cst) return cst;
     for (size_t c0 = 0; c0 < ids.size(); c0 += MAXB) {
         const int na = (int)std::min<size_t>(MAXB, ids.size() - c0);
         BatchMap bm;
@@ -225,16 +251,18 @@ int Engine::launch_cores(std::vector<int> &ids)
         if (nv > 0) {
             k_verify_b<<<dim3(NBV, nv), NT, 0, stream>>>(dPa, bv, dPart);
             HIPCHK(hipGetLastError());
-            for (int a = 0; a < nv; ++a) {
-                const size_t o = (size_t)2 * NBV * bv.p[a];
-                HIPCHK(hipMemcpyAsync(hPart + o, dPart + o, sizeof(double) * 2 * NBV, hipMemcpyDeviceToHost, stream));
-            }
+            std::vector<int> vs(bv.p, bv.p + nv);
+            int cs = copy_slots(hPart, dPart, sizeof(double) * 2 * NBV, vs, hipMemcpyDeviceToHost);
+            if (cs) return cs;
         }
     }
     hipEvent_t ev = nullptr;
     if (!ev_free.empty()) { ev = ev_free.back(); ev_free.pop_back(); }
     else HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    for (int i : ids) HIPCHK(hipMemcpyAsync(hS + i, dS + i, sizeof(ProbState), hipMemcpyDeviceToHost, stream));
+    {
+        int cs = copy_slots(hS, dS, sizeof(ProbState), ids, hipMemcpyDeviceToHost);
+        if (cs) return cs;
+    }
     HIPCHK(hipEventRecord(ev, stream));
     // the event is shared by the slots of this call; the last one to see it
     // complete returns it to the pool
