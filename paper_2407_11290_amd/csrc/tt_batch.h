@@ -58,9 +58,11 @@ private:
     std::vector<Slot> slots;
     std::vector<hipEvent_t> ev_free;
     ProbDev *dPa = nullptr, *hPa = nullptr;   // descriptors: device array, pinned staging
-    ProbState *dS = nullptr, *hS = nullptr;   // per-slot device state and its host copy
+    ProbState *dS = nullptr, *hS = nullptr;   // per-slot device state and its host copy (mapped)
+    ProbState *dhS = nullptr;                 // device view of hS
     HostMirror *hm = nullptr, *dhm = nullptr; // mapped host mirrors (host / device view)
-    double *dPart = nullptr, *hPart = nullptr;// sampled-error partial sums, 2 * NBV per slot
+    double *dPart = nullptr, *hPart = nullptr;// sampled-error partial sums, 2 * NBV per slot (mapped
+                                              // host memory; dPart is its device view)
 };
 
 }  // namespace ttc

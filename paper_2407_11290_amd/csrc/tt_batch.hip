@@ -47,9 +47,8 @@ void Engine::release()
     if (hPa) (void)hipHostFree(hPa);
     if (hS) (void)hipHostFree(hS);
     if (hm) (void)hipHostFree(hm);
-    if (dPart) (void)hipFree(dPart);
     if (hPart) (void)hipHostFree(hPart);
-    dPa = nullptr; dS = nullptr; hPa = nullptr; hS = nullptr; hm = nullptr; dhm = nullptr;
+    dPa = nullptr; dS = nullptr; hPa = nullptr; hS = nullptr; dhS = nullptr; hm = nullptr; dhm = nullptr;
     dPart = nullptr; hPart = nullptr;
     slots.clear();
     cap = 0;
@@ -64,11 +63,14 @@ int Engine::init(int capacity, hipStream_t s)
     HIPCHK(hipMalloc(&dPa, sizeof(ProbDev) * cap));
     HIPCHK(hipMalloc(&dS, sizeof(ProbState) * cap));
     HIPCHK(hipHostMalloc((void **)&hPa, sizeof(ProbDev) * cap, hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void **)&hS, sizeof(ProbState) * cap, hipHostMallocDefault));
+    // finished states and check partials are written by kernels straight
+    // into mapped host memory (no copy per problem)
+    HIPCHK(hipHostMalloc((void **)&hS, sizeof(ProbState) * cap, hipHostMallocMapped | hipHostMallocCoherent));
+    HIPCHK(hipHostGetDevicePointer((void **)&dhS, hS, 0));
     HIPCHK(hipHostMalloc((void **)&hm, sizeof(HostMirror) * cap, hipHostMallocMapped | hipHostMallocCoherent));
     HIPCHK(hipHostGetDevicePointer((void **)&dhm, hm, 0));
-    HIPCHK(hipMalloc(&dPart, sizeof(double) * 2 * NBV * cap));
-    HIPCHK(hipHostMalloc((void **)&hPart, sizeof(double) * 2 * NBV * cap, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&hPart, sizeof(double) * 2 * NBV * cap, hipHostMallocMapped | hipHostMallocCoherent));
+    HIPCHK(hipHostGetDevicePointer((void **)&dPart, hPart, 0));
     std::memset(hm, 0, sizeof(HostMirror) * cap);
     slots.assign(cap, Slot());
     for (int i = 0; i < cap; ++i) slots[i].idx = i;
@@ -249,20 +251,23 @@ int Engine::launch_cores(std::vector<int> &ids)
         bv.na = nv;
         bv.boff[nv] = nv;
         if (nv > 0) {
-            k_verify_b<<<dim3(NBV, nv), NT, 0, stream>>>(dPa, bv, dPart);
+            k_verify_b<<<dim3(NBV, nv), NT, 0, stream>>>(dPa, bv, dPart);   // partials land on the host
             HIPCHK(hipGetLastError());
-            std::vector<int> vs(bv.p, bv.p + nv);
-            int cs = copy_slots(hPart, dPart, sizeof(double) * 2 * NBV, vs, hipMemcpyDeviceToHost);
-            if (cs) return cs;
         }
+        // the finished states, to host memory
+        BatchMap bo;
+        bo.na = na;
+        for (int a = 0; a < na; ++a) {
+            bo.p[a] = (uint16_t)ids[c0 + a];
+            bo.boff[a] = a;
+        }
+        bo.boff[na] = na;
+        k_state_out_b<<<na, 64, 0, stream>>>(dS, dhS, bo);
+        HIPCHK(hipGetLastError());
     }
     hipEvent_t ev = nullptr;
     if (!ev_free.empty()) { ev = ev_free.back(); ev_free.pop_back(); }
     else HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    {
-        int cs = copy_slots(hS, dS, sizeof(ProbState), ids, hipMemcpyDeviceToHost);
-        if (cs) return cs;
-    }
     HIPCHK(hipEventRecord(ev, stream));
     // the event is shared by the slots of this call; the last one to see it
     // complete returns it to the pool

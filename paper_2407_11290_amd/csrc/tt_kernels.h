@@ -1799,6 +1799,17 @@ static __global__ void __launch_bounds__(A4W) k_cores_b(const ProbDev *__restric
 
 // Sampled-error check of every listed problem: NBV workgroups each (grid.y =
 // problem), partial sums to part + 2*NBV*slot, R and the seed in run.
+// The device state of each named problem copied to host memory (mapped),
+// one workgroup per problem: one launch instead of a copy per problem.
+static __global__ void __launch_bounds__(64) k_state_out_b(const ProbState *__restrict__ dS, ProbState *hS, BatchMap bm)
+{
+    if ((int)blockIdx.x >= bm.na) return;
+    const int i = bm.p[blockIdx.x];
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(dS + i);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(hS + i);
+    for (int w = threadIdx.x; w < (int)(sizeof(ProbState) / 4); w += 64) dst[w] = src[w];
+}
+
 static __global__ void __launch_bounds__(NT) k_verify_b(const ProbDev *__restrict__ Pa, BatchMap bm, double *part)
 {
     const int slot = bm.p[blockIdx.y];
