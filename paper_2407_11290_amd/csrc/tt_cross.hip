@@ -227,6 +227,9 @@ int Problem::allocate()
             rook_g = (int)std::min<int64_t>(64, ext / 4096);
             rook_g = (int)std::max<int64_t>(2, std::min<int64_t>(rook_g, 8192 / std::max<int64_t>(1, nblk)));
         }
+        if (nblk * rook_g > ((int64_t)1 << 30))
+            return set_err(TT_EINVAL, "%lld subtensor blocks x %d workgroups each is too many for one launch",
+                           (long long)nblk, rook_g);
     }
     H.rook_g = rook_g;
     H.F = fn.dev;
@@ -244,6 +247,9 @@ int Problem::allocate()
         K.k = k;
         K.nk = n[k - 1];
         K.nk1 = n[k];
+        // positions are 32-bit (and a search key packs a row and a column)
+        if ((int64_t)rc[k - 1] * n[k - 1] > INT32_MAX || (int64_t)n[k] * rc[k + 1] > INT32_MAX)
+            return set_err(TT_EINVAL, "superblock %d would have more than 2^31-1 rows or columns", k);
         K.rowcap = rc[k - 1] * n[k - 1];
         K.colcap = n[k] * rc[k + 1];
         {

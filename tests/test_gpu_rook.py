@@ -146,3 +146,13 @@ def test_rook_is_refused_by_the_batch_and_fp32():
     with pytest.raises(TTError) as e:
         TTCross([8, 8, 8], 1e-8, FN_HILBERT, pivot=PIVOT_ROOK, precision=2)
     assert e.value.code == EINVAL
+
+
+def test_superblocks_beyond_32_bit_positions_are_refused():
+    """Positions of superblock rows and columns are 32-bit: a mode of 5e7
+    indices next to a rank cap of 64 is refused before any device work."""
+    for pivot in (0, PIVOT_ROOK):
+        h = TTCross([64, 50_000_000, 64], 1e-8, FN_HILBERT, precision=PREC_FP64, pivot=pivot)
+        with pytest.raises(TTError) as e:
+            h.run()
+        assert e.value.code == EINVAL and "2^31" in str(e.value)
