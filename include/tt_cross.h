@@ -158,7 +158,7 @@ typedef struct tt_cross_s *tt_cross_h;
 /* Fill *opt with the defaults listed in tt_options. */
 void tt_options_default(tt_options *opt);
 
-/* Create a problem: d modes of sizes n[0..d-1] (each >= 1), tolerance eps >= 0
+/* Create a problem: d modes of sizes n[0..d-1] (each in [1, 2^20]), tolerance eps >= 0
  * (eq. FrobeniusNorm), generating function fn_id with nparams doubles of
  * params (may be NULL when nparams == 0).  params are copied.  Returns NULL on
  * bad arguments (reason in tt_last_error). */
@@ -167,6 +167,15 @@ tt_cross_h tt_cross_create(int d, const int32_t *n, double eps, int fn_id, const
 
 /* Replace the options (before tt_cross_run; a later run reuses them). */
 int tt_cross_set_options(tt_cross_h h, const tt_options *opt);
+
+/* Prescribed ranks (the paper's experiments run at fixed core ranks, Sec. 5):
+ * unfolding k stops growing at min(r_max, caps[k-1]) pivots; caps holds d-1
+ * values, 0 meaning r_max alone (caps NULL: all 0).  Together with eps = 0 a
+ * run adds pivots until every unfolding has its prescribed rank (status
+ * TT_NOT_CONVERGED, the rank cap being what stopped it) or its residual on
+ * the superblock is exactly zero.  Takes effect at the next run; kept until
+ * changed.  Errors: TT_EINVAL (NULL handle, a cap outside [0, TT_MAX_RANK]). */
+int tt_cross_set_rank_caps(tt_cross_h h, const int32_t *caps);
 
 /* Run the approximation to completion on the handle's stream and wait for it.
  * Returns TT_OK, TT_NOT_CONVERGED, or an error code. */

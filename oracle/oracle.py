@@ -30,6 +30,7 @@ def lib():
         L.orc_destroy.argtypes = [P]
         L.orc_run.argtypes = [P]
         L.orc_set_rook.argtypes = [P, i32p, C.c_int]
+        L.orc_set_rank_caps.argtypes = [P, i32p]
         L.orc_mix64.restype = C.c_uint64
         L.orc_mix64.argtypes = [C.c_uint64]
         L.orc_get_ranks.argtypes = [P, i32p]
@@ -125,7 +126,7 @@ class Oracle:
     `grid` (blocks per mode) with at most rook_iters rounds."""
 
     def __init__(self, n, eps, fn_id, params=None, seed=0, r_max=64, n_samples=16384, pivot="greedy",
-                 grid=None, rook_iters=8):
+                 grid=None, rook_iters=8, rank_caps=None):
         self._seed = int(seed)
         self.n = np.ascontiguousarray(n, dtype=np.int32)
         self.d = int(self.n.size)
@@ -142,6 +143,9 @@ class Oracle:
                 raise ValueError("orc_set_rook rejected the options")
         elif pivot != "greedy":
             raise ValueError(pivot)
+        if rank_caps is not None:
+            if lib().orc_set_rank_caps(self.h, np.ascontiguousarray(rank_caps, dtype=np.int32)) != 0:
+                raise ValueError("orc_set_rank_caps rejected the caps")
         self.status = None
 
     def __del__(self):

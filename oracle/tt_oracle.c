@@ -322,6 +322,7 @@ typedef struct orc_state {
     double *cores;                   /* G_1..G_d concatenated */
     int64_t cores_len;
     int rook, rook_iters;            /* rook mode: Alg. 1 inside every block */
+    int kcap[ORC_MAX_D + 1];         /* rank cap per unfolding (prescribed ranks), <= r_max */
     int grid[ORC_MAX_D];             /* subtensor blocks per mode (rook mode) */
 } orc_state;
 
@@ -358,6 +359,7 @@ orc_state *orc_create(int d, const int *n, double eps, int fn_id, const double *
     S->hist_cap = (d - 1) * r_max + 2;
     S->rook = 0;
     S->rook_iters = 8;
+    for (int k = 0; k <= ORC_MAX_D; ++k) S->kcap[k] = r_max;
     for (int j = 0; j < ORC_MAX_D; ++j) S->grid[j] = 1;
     for (int k = 1; k <= d - 1; ++k) {
         S->I[k] = (int *)calloc((size_t)r_max * k, sizeof(int));
@@ -401,6 +403,18 @@ int orc_set_rook(orc_state *S, const int *grid, int max_iters)
         if (c < 1) c = 1;
         if (c > S->n[j]) c = S->n[j];
         S->grid[j] = c;
+    }
+    return ORC_OK;
+}
+
+/* Prescribed ranks (Sec. 5 runs at fixed core ranks): unfolding k stops
+ * growing at min(r_max, caps[k-1]); caps holds d-1 values >= 1. */
+int orc_set_rank_caps(orc_state *S, const int *caps)
+{
+    if (!S || !caps) return ORC_EINVAL;
+    for (int k = 1; k <= S->d - 1; ++k) {
+        if (caps[k - 1] < 1) return ORC_EINVAL;
+        S->kcap[k] = caps[k - 1] < S->r_max ? caps[k - 1] : S->r_max;
     }
     return ORC_OK;
 }
@@ -684,7 +698,7 @@ int orc_run(orc_state *S)
                     double g = (a - runner) / a;
                     if (g < S->min_rel_gap) S->min_rel_gap = g;
                 }
-                if (rs[k] < S->r_max) {
+                if (rs[k] < S->kcap[k]) {
                     prop[k] = 1; prow[k] = br; pcol[k] = bc; pval[k] = bv; any = 1;
                 } else {
                     capped = 1;

@@ -78,6 +78,7 @@ SIGNATURES = {
                                      C.POINTER(C.c_double), C.c_int]),
     "tt_cross_set_options": (C.c_int, [C.c_void_p, C.POINTER(Options)]),
     "tt_cross_run": (C.c_int, [C.c_void_p]),
+    "tt_cross_set_rank_caps": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "tt_cross_get_ranks": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "tt_cross_get_tiles": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "tt_cross_get_cores": (C.c_int64, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int]),

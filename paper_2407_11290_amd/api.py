@@ -114,6 +114,15 @@ class TTCross:
         self.status = check(load().tt_cross_run(self.h))
         return self.status
 
+    def set_rank_caps(self, caps):
+        """Prescribed ranks: unfolding k stops at min(r_max, caps[k-1]) pivots
+        (tt_cross_set_rank_caps); None clears them."""
+        if caps is None:
+            check(load().tt_cross_set_rank_caps(self.h, None))
+        else:
+            c = _i32(caps)
+            check(load().tt_cross_set_rank_caps(self.h, c.ctypes.data_as(C.POINTER(C.c_int32))))
+
     def autotune(self, reps=3):
         """Time complete solves under every candidate tile shape (tt_autotune)
         and record the fastest for this problem's class; returns

@@ -362,6 +362,7 @@ void Problem::resolve_geometry()
         for (int j = 0; j < k; ++j) left *= n[j];
         for (int j = k; j < d; ++j) right *= n[j];
         double m = std::min(std::min(left, right), (double)opt.r_max);
+        if (kcap[k] > 0) m = std::min(m, (double)kcap[k]);
         rc[k] = (int)m;
     }
     for (int j = 0; j < d; ++j) grid[j] = std::max(1, std::min(opt.grid[j], n[j]));
@@ -587,6 +588,7 @@ int Problem::prepare()
     resolve_geometry();
     if (allocated && (alloc_fp32 != fp32 || alloc_rmax != opt.r_max || alloc_tr != req_tr ||
                       alloc_pivot != opt.pivot_mode || alloc_split != opt.rook_split ||
+                      std::memcmp(alloc_kcap, kcap, sizeof kcap) != 0 ||
                       alloc_tc != req_tc || alloc_ns != opt.n_samples ||
                       std::memcmp(alloc_grid, grid, sizeof grid) != 0)) {
         for (void *p : allocs) (void)hipFree(p);
@@ -602,6 +604,7 @@ int Problem::prepare()
     alloc_tc = req_tc;
     alloc_pivot = opt.pivot_mode;
     alloc_split = opt.rook_split;
+    std::memcpy(alloc_kcap, kcap, sizeof kcap);
     alloc_ns = opt.n_samples;
     std::memcpy(alloc_grid, grid, sizeof grid);
     ran = false;
@@ -746,6 +749,19 @@ int tt_cross_set_options(tt_cross_h h, const tt_options *opt)
     }
     h->p.opt = *opt;
     h->p.force_fp64 = false;
+    return TT_OK;
+}
+
+int tt_cross_set_rank_caps(tt_cross_h h, const int32_t *caps)
+{
+    if (!h) return set_err(TT_EINVAL, "NULL handle");
+    Problem &P = h->p;
+    for (int k = 1; k <= P.d - 1; ++k) {
+        const int c = caps ? caps[k - 1] : 0;
+        if (c < 0 || c > TT_MAX_RANK) return set_err(TT_EINVAL, "rank cap %d of unfolding %d outside [0,%d]", c, k,
+                                                      TT_MAX_RANK);
+    }
+    for (int k = 1; k <= P.d - 1; ++k) P.kcap[k] = caps ? caps[k - 1] : 0;
     return TT_OK;
 }
 

@@ -44,6 +44,8 @@ struct Problem {
     int req_tr = 0, req_tc = 0;    // tile request in force: the options', else the tuned table's
     bool use_table = true;         // false while the tuner times its own candidates
     int rook_g = 1;                // rook search: workgroups per subtensor block
+    int kcap[TT_MAX_D + 1] = {0};  // prescribed rank per unfolding (0: none)
+    int alloc_kcap[TT_MAX_D + 1] = {0};
     int hist_cap = 0, max_sweeps = 0;
     int lds_limit = 65536;         // LDS bytes one workgroup may allocate on this device
     int lds_static = 0;            // static LDS of the search kernel

@@ -121,6 +121,19 @@ def test_tile_options_and_tuner_arguments_without_gpu():
     t.close()
 
 
+def test_rank_caps_arguments_without_gpu():
+    from paper_2407_11290_amd.api import TTCross
+    t = TTCross([8, 8, 8, 8], 1e-8, _lib.FN_HILBERT)
+    t.set_rank_caps([3, 0, 64])
+    t.set_rank_caps(None)
+    for bad in ([3, -1, 2], [3, 65, 2]):
+        with pytest.raises(_lib.TTError) as e:
+            t.set_rank_caps(bad)
+        assert e.value.code == _lib.EINVAL
+    assert _lib.load().tt_cross_set_rank_caps(None, None) == _lib.EINVAL
+    t.close()
+
+
 def test_workload_lists_are_seeded_and_shaped_as_specified():
     from paper_2407_11290_amd.workloads import FN_BIMAXWELL, FN_HILBERT, batch_mix, served_trace
     a, b = batch_mix(), batch_mix()

@@ -148,11 +148,11 @@ def test_rook_is_refused_by_the_batch_and_fp32():
     assert e.value.code == EINVAL
 
 
-def test_superblocks_beyond_32_bit_positions_are_refused():
-    """Positions of superblock rows and columns are 32-bit: a mode of 5e7
-    indices next to a rank cap of 64 is refused before any device work."""
-    for pivot in (0, PIVOT_ROOK):
-        h = TTCross([64, 50_000_000, 64], 1e-8, FN_HILBERT, precision=PREC_FP64, pivot=pivot)
-        with pytest.raises(TTError) as e:
-            h.run()
-        assert e.value.code == EINVAL and "2^31" in str(e.value)
+def test_mode_sizes_beyond_the_limit_are_refused():
+    """Mode sizes are limited to 2^20 at creation, which with the rank cap of
+    64 keeps every superblock position below 2^26 (positions are 32-bit)."""
+    with pytest.raises(TTError) as e:
+        TTCross([64, (1 << 20) + 1, 64], 1e-8, FN_HILBERT, pivot=PIVOT_ROOK)
+    assert e.value.code == EINVAL
+    h = TTCross([4, 1 << 20, 4], 1e-8, FN_HILBERT, precision=PREC_FP64, pivot=PIVOT_ROOK)
+    assert h.run() >= 0

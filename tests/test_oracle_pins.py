@@ -520,3 +520,27 @@ def test_rook_hilbert3d_full_tensor_error_below_eps():
         g = Oracle(n, 1e-10, FN_HILBERT, seed=seed)
         g.run()
         assert o.stats()["pivoted"] < g.stats()["pivoted"]
+
+
+def test_prescribed_ranks_cap_each_unfolding():
+    """Per-unfolding rank caps (the paper's runs at fixed core ranks, Sec. 5):
+    with eps = 0 every unfolding stops at its own cap, the run reports the cap
+    as what stopped it, and equal caps reproduce a global rank cap bit for
+    bit."""
+    n = [12, 10, 9, 8]
+    o = Oracle(n, 0.0, FN_HILBERT, seed=2, rank_caps=[5, 3, 7])
+    assert o.run() == 1                                   # not converged: stopped by the caps
+    assert list(o.ranks()) == [1, 5, 3, 7, 1]
+    a = Oracle(n, 0.0, FN_HILBERT, seed=2, rank_caps=[4, 4, 4])
+    b = Oracle(n, 0.0, FN_HILBERT, seed=2, r_max=4)
+    a.run()
+    b.run()
+    assert _pivot_positions(a) == _pivot_positions(b)
+    assert np.array_equal(a.cores_flat(), b.cores_flat())
+    # caps change nothing before an unfolding reaches one (the smallest is
+    # 3), so the first two pivots of every unfolding are those of a run with
+    # a larger global cap
+    c = Oracle(n, 0.0, FN_HILBERT, seed=2, r_max=8)
+    c.run()
+    for k in range(1, 4):
+        assert np.array_equal(o.pivots(k)[2][:2], c.pivots(k)[2][:2])
