@@ -450,30 +450,46 @@ extern "C" int tt_batch_run(tt_cross_h *hs, int count, void *hip_stream)
         const int st = eng.init(std::max(count, eng.cap), stream);
         if (st) return st;
     }
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
+    struct EvPair {
+        hipEvent_t a = nullptr, b = nullptr;
+        ~EvPair()
+        {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } ev;
+    HIPCHK(hipEventCreate(&ev.a));
+    HIPCHK(hipEventCreate(&ev.b));
+    // after a failure with slots admitted: let the stream drain and reset the
+    // engine, so that no slot stays taken for the thread's next batch
+    auto fail = [&](int code) {
+        (void)hipStreamSynchronize(stream);
+        (void)eng.init(eng.cap, stream);
+        return code;
+    };
     // pass 1: every problem; pass 2: those whose FP32 sweeps missed eps, in FP64
     std::vector<int> todo(count);
     for (int i = 0; i < count; ++i) todo[i] = i;
     double total = 0.0;
     int st = TT_OK;
-    for (int pass = 0; pass < 2 && !todo.empty() && st == TT_OK; ++pass) {
-        HIPCHK(hipEventRecord(e0, stream));
+    for (int pass = 0; pass < 2 && !todo.empty(); ++pass) {
+        hipError_t he = hipEventRecord(ev.a, stream);
+        if (he != hipSuccess) return fail(set_err(TT_EDEVICE, "batch: %s", hipGetErrorString(he)));
         std::vector<int> ids(todo.size());
         for (size_t i = 0; i < todo.size(); ++i) {
             const int id = eng.admit(&hs[todo[i]]->p, nullptr);
-            if (id < 0) return id;
+            if (id < 0) return fail(id);
             ids[i] = id;
         }
         while (!eng.idle()) {
             st = eng.tick(nullptr);
-            if (st) break;
+            if (st) return fail(st);
         }
-        HIPCHK(hipEventRecord(e1, stream));
-        HIPCHK(hipStreamSynchronize(stream));
+        he = hipEventRecord(ev.b, stream);
+        if (he == hipSuccess) he = hipStreamSynchronize(stream);
         float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, ev.a, ev.b);
+        if (he != hipSuccess) return fail(set_err(TT_EDEVICE, "batch: %s", hipGetErrorString(he)));
         total += ms * 1e-3;
         std::vector<int> next;
         for (size_t i = 0; i < todo.size(); ++i) {
@@ -484,12 +500,10 @@ extern "C" int tt_batch_run(tt_cross_h *hs, int count, void *hip_stream)
             Problem &Q = hs[i]->p;
             Q.force_fp64 = true;
             const int ps = Q.prepare();
-            if (ps) { st = ps; break; }
+            if (ps) return ps;                  // every slot is retired here
         }
         todo.swap(next);
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     for (int i = 0; i < count; ++i) hs[i]->p.time_to_eps = total;
     return st;
 }
