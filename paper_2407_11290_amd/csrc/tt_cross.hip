@@ -260,21 +260,30 @@ int Problem::allocate()
             K.ld = ((K.colcap + 2 * per256 - 1) / (2 * per256)) * (2 * per256) + per256;
         }
         K.rk_cap = rc[k];
-        // tile geometry: rows of mode k, columns of mode k+1
-        int TR = req_tr > 0 ? req_tr : 32;
-        int maxrun = 1;
-        {
-            const int C = grid[k];
-            for (int b = 0; b < C; ++b)
-                maxrun = std::max(maxrun, (int)((int64_t)(b + 1) * n[k] / C - (int64_t)b * n[k] / C));
-        }
+        // tile geometry: rows of mode k, columns of mode k+1.  A tile lies in
+        // one run of i_k (i_{k+1}) inside a subtensor block.  Default height,
+        // from measured sweeps of shapes: 256 rows when both runs are long
+        // (>= 400), where a stored tile (one wavefront's work) gains from
+        // streaming longer and the new-entry tiles are still many; 64 rows
+        // for d >= 4 with runs >= 100; else 32.  (With d = 3, each new prefix
+        // adds a whole row of long new-entry tiles, which taller tiles make
+        // fewer and slower.)  Other shapes are found by tt_autotune.
+        auto longest_run = [&](int nn, int C) {
+            int m = 1;
+            for (int b = 0; b < C; ++b) m = std::max(m, (int)((int64_t)(b + 1) * nn / C - (int64_t)b * nn / C));
+            return m;
+        };
+        const int runr = longest_run(n[k - 1], grid[k - 1]), maxrun = longest_run(n[k], grid[k]);
+        int TR = req_tr > 0 ? req_tr : ((runr >= 400 && maxrun >= 400) ? 256 : (d >= 4 && runr >= 100) ? 64 : 32);
         // stored tiles put 64 / TC rows on a wavefront: TC <= 64
         int TC = req_tc > 0 ? req_tc : std::min(64, pow2_at_least(maxrun));
         TC = std::min(pow2_at_least(TC), 64);
         if (req_tr <= 0 && req_tc <= 0) {
-            // shrink the default tile until its LDS fits next to the rank cap
+            // shrink the default tile until its LDS fits next to the rank
+            // cap: the height first down to 32 rows, then the width
             while (sweep_lds_bytes(rc[k], TR, TC, w) + lds_static > (size_t)lds_limit && (TC > 16 || TR > 8)) {
-                if (TC > 16) TC /= 2;
+                if (TR > 32) TR /= 2;
+                else if (TC > 16) TC /= 2;
                 else TR /= 2;
             }
         }
