@@ -124,7 +124,10 @@ typedef struct tt_options {
 } tt_options;
 
 typedef struct tt_stats {
-    int64_t evaluated;          /* distinct superblock entries evaluated (sum over unfoldings) */
+    int64_t evaluated;          /* entries of the final superblocks, summed over unfoldings: the
+                                   distinct entries the greedy search evaluates; with rook
+                                   pivoting the same measure (the search evaluates only the
+                                   entries it looks at, counted in pivoted) */
     int64_t pivoted;            /* residual entries scanned by argmax passes, all sweeps */
     int64_t samples;            /* sample entries evaluated for rms and the first pivot */
     int32_t sweeps;             /* search sweeps run (the last one proposes nothing) */

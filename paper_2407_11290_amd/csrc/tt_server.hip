@@ -415,7 +415,11 @@ tt_server_h tt_server_create(size_t hbm_budget, int max_slots, const tt_options 
         o.r_max = 32;
         for (int j = 0; j < TT_MAX_D; ++j) o.grid[j] = 2;
     }
-    if (o.r_max < 1 || o.r_max > TT_MAX_RANK || o.pivot_mode != TT_PIVOT_GREEDY || o.n_samples < 1) {
+    if (o.pivot_mode != TT_PIVOT_GREEDY) {
+        set_err(TT_EINVAL, "served solves use greedy pivoting (rook pivoting runs through tt_cross_run)");
+        return nullptr;
+    }
+    if (o.r_max < 1 || o.r_max > TT_MAX_RANK || o.n_samples < 1) {
         set_err(TT_EINVAL, "bad server options");
         return nullptr;
     }

@@ -121,6 +121,15 @@ def test_tile_options_and_tuner_arguments_without_gpu():
     t.close()
 
 
+def test_server_refuses_rook_pivoting_without_gpu():
+    """Served solves use greedy pivoting; the check comes before device work."""
+    from paper_2407_11290_amd.api import default_options
+    o = default_options()
+    o.pivot_mode = _lib.PIVOT_ROOK
+    s = _lib.load().tt_server_create(1 << 30, 4, C.byref(o))
+    assert not s and "rook" in _lib.last_error()
+
+
 def test_rank_caps_arguments_without_gpu():
     from paper_2407_11290_amd.api import TTCross
     t = TTCross([8, 8, 8, 8], 1e-8, _lib.FN_HILBERT)

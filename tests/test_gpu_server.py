@@ -131,3 +131,4 @@ def test_server_escalates_like_a_single_solve():
         assert s[key] == s1[key], key
     assert np.array_equal(cores.view(np.uint64), g.cores_flat().view(np.uint64))
     srv.close()
+
