@@ -334,3 +334,14 @@ def test_paper_table6_hilbert3d_prescribed_ranks():
     assert g.run() == NOT_CONVERGED
     assert list(g.ranks()) == [1, 25, 25, 1]
     assert g.sampled_error(1_000_000) <= 1.27e-6
+
+
+def test_default_tall_tiles_bit_exact():
+    """Block runs of 400 and more take 256-row tiles by default: the same
+    pivots, status and cores as the oracle (rank cap 12 reached)."""
+    n = [400, 410, 420]
+    g, gs, o, os_ = _solve_both(n, 1e-7, FN_HILBERT, seed=1, r_max=12, precision=PREC_FP64)
+    assert [t[0] for t in g.tiles()] == [256, 256]
+    assert gs == os_ == NOT_CONVERGED
+    _assert_same_pivots(g, o)
+    assert np.array_equal(g.cores_flat(), o.cores_flat())
