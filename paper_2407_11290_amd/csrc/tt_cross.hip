@@ -141,6 +141,9 @@ void Problem::release()
     for (hipEvent_t e : prof_events) (void)hipEventDestroy(e);
     prof_events.clear();
     if (hm) { (void)hipHostFree(hm); hm = nullptr; }
+    if (hS_pinned) { (void)hipHostFree(hS_pinned); hS_pinned = nullptr; }
+    for (hipEvent_t &e : run_ev)
+        if (e) { (void)hipEventDestroy(e); e = nullptr; }
     if (fn.d_table) { (void)hipFree(fn.d_table); fn.d_table = nullptr; }
     if (own_stream && stream) { (void)hipStreamDestroy(stream); }
     stream = nullptr;
@@ -388,12 +391,13 @@ template <typename V> int Problem::run_impl()
 {
     const int nk = d - 1;
     hipEvent_t ev0, ev1;
-    HIPCHK(hipEventCreate(&ev0));
-    HIPCHK(hipEventCreate(&ev1));
-    struct EvGuard {
-        hipEvent_t a, b;
-        ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
-    } evg{ev0, ev1};
+    // events and the pinned copy of the final state are kept with the
+    // problem: nothing is created or destroyed per run
+    if (!run_ev[0]) HIPCHK(hipEventCreate(&run_ev[0]));
+    if (!run_ev[1]) HIPCHK(hipEventCreate(&run_ev[1]));
+    if (!hS_pinned) HIPCHK(hipHostMalloc((void **)&hS_pinned, sizeof(ProbState), hipHostMallocDefault));
+    ev0 = run_ev[0];
+    ev1 = run_ev[1];
     hm->sweeps_done = 0;
     hm->stop = 0;
     hm->err = 0;
@@ -543,12 +547,13 @@ template <typename V> int Problem::run_impl()
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev1, stream));
+    // the final state comes back with the same synchronisation
+    HIPCHK(hipMemcpyAsync(hS_pinned, hP.S, sizeof(ProbState), hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
     time_to_eps = ms * 1e-3;
-    ProbState S;
-    HIPCHK(hipMemcpy(&S, hP.S, sizeof S, hipMemcpyDeviceToHost));
+    const ProbState S = *hS_pinned;
     if (S.err) return set_err(S.err, "device reported error %d", S.err);
     finalize(S, ranks_now);
     sweep_launches = 0;

@@ -74,6 +74,8 @@ struct Problem {
     int sweep_launches = 0;
     double sweep_kernel_s = 0, sweep_alg_bytes = 0, new_entries = 0, sweep_phase_s = 0;
     std::vector<hipEvent_t> prof_events;     // 3 per sweep when profiling
+    hipEvent_t run_ev[2] = {nullptr, nullptr};  // start / end of a run
+    ProbState *hS_pinned = nullptr;          // pinned host copy of the final device state
     int i0[TT_MAX_D] = {0};
     // sampled-error check and FP32 -> FP64 escalation
     double sampled_err = -1.0;
