@@ -222,12 +222,21 @@ int tt_cross_sampled_error(tt_cross_h h, int64_t R, uint64_t seed, double *err);
  * superblock entries.  idx: m x d int32, row-major, 0-based; out: m values.
  * on_device = 0: host buffers, every index checked (TT_EINVAL if outside
  * [0, n_j)); = 1: device buffers, indices not checked and must lie in range.
- * Runs on the null stream and returns when done.
+ * Runs on the null stream and returns when done.  The Maxwellians' per-mode
+ * value tables (built on the host, copied to the device) of the last four
+ * functions evaluated stay on the device for later calls; concurrent calls
+ * run one after the other.
  * Errors: TT_EFN (unknown function or bad params), TT_EINVAL, TT_EDEVICE. */
 int tt_fn_eval(int fn_id, int d, const int32_t *n, const double *params, int nparams, int64_t m,
                const int32_t *idx, double *out, int on_device);
 int tt_fn_eval_f32(int fn_id, int d, const int32_t *n, const double *params, int nparams, int64_t m,
                    const int32_t *idx, float *out, int on_device);
+
+/* Device time in milliseconds of the kernel of the last bulk evaluation
+ * (tt_fn_eval or tt_fn_eval_f32) that completed in this process, from events
+ * attached to its dispatch: host work before the launch is not included.
+ * Errors: TT_EINVAL (ms NULL), TT_ESTATE (no evaluation has completed). */
+int tt_fn_eval_last_kernel_ms(double *ms);
 
 void tt_cross_destroy(tt_cross_h h);
 
@@ -328,7 +337,8 @@ typedef struct {
 tt_server_h tt_server_create(size_t hbm_budget, int max_slots, const tt_options *opt);
 
 /* Queue one request (arguments as in tt_cross_create, plus its sample seed).
- * Functions that need a factor table (TT_FN_SEPSUM) are not served.  Returns
+ * Separable sums (TT_FN_SEPSUM, whose factor tables come from the caller) are
+ * not served.  Returns
  * TT_OK and the ticket, or an error for a request that can never run. */
 int tt_server_submit(tt_server_h s, int d, const int32_t *n, double eps, int fn_id, const double *params,
                      int nparams, uint64_t seed, uint64_t *ticket);

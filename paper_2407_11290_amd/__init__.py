@@ -11,8 +11,8 @@ from ._lib import (EBUSY, EDEVICE, EFN, EINVAL, ENOMEM, ESINGULAR, ESTATE, FN_BI
 
 
 def __getattr__(name):
-    if name in ("TTCross", "fn_eval", "default_options", "batch_run", "Server", "batch_autotune", "tile_table",
-                "tile_table_clear"):
+    if name in ("TTCross", "fn_eval", "fn_eval_last_kernel_ms", "default_options", "batch_run", "Server",
+                "batch_autotune", "tile_table", "tile_table_clear"):
         from . import api
         return getattr(api, name)
     raise AttributeError(name)

@@ -50,6 +50,14 @@ def fn_eval(fn_id, n, idx, params=None, fp32=False):
     return out
 
 
+def fn_eval_last_kernel_ms():
+    """Device time (ms) of the kernel of the last completed fn_eval call, from
+    events attached to its dispatch (tt_fn_eval_last_kernel_ms)."""
+    ms = C.c_double()
+    check(load().tt_fn_eval_last_kernel_ms(C.byref(ms)))
+    return ms.value
+
+
 def _stats_dict(s, d):
     return {
         "evaluated": s.evaluated, "pivoted": s.pivoted, "samples": s.samples, "sweeps": s.sweeps,

@@ -9,6 +9,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -39,6 +41,83 @@ int set_err(int code, const char *fmt, ...)
 // ---------------------------------------------------------------------------
 // Generating function descriptors.
 // ---------------------------------------------------------------------------
+// Per-mode tables of the Maxwellians.  Every value is the FP64 result of the
+// operations the formula applies to one index, in the formula's order, so an
+// entry assembled from the table in FP64 (fn_value_ix) takes the same
+// rounding steps as the formula evaluated term by term; only the final
+// exponential runs on the device.  Constant factors (the (2 pi T)^{-3/2}
+// terms) go to F.cst.
+static void mode_tables(FnDev &F, FnHost &out)
+{
+    const int d = F.d;
+    const double twopi = 2.0 * PI;
+    int rows = 0;
+    bool has[TT_MAX_D] = {false};
+    switch (F.id) {
+    case TT_FN_MAXWELL:            // x1, x2, x3: sin, cos, sin of 2 pi x; v1..v3: cell centres
+        rows = 1;
+        for (int j = 0; j < d; ++j) has[j] = true;
+        F.cst[0] = std::pow(twopi * F.prm[2], -1.5);
+        break;
+    case TT_FN_BIMAXWELL:          // velocity modes: (v - u_{m,c})^2 for Maxwellian m = row
+        rows = 2;
+        for (int j = d - 3; j < d; ++j) has[j] = true;
+        for (int m = 0; m < 2; ++m) F.cst[m] = F.prm[5 * m] * std::pow(twopi * F.prm[5 * m + 4], -1.5);
+        break;
+    default:                       // kinetic 2d2v / 3d3v: x modes rho/(2 sqrt(2 pi T)), 2T;
+        rows = 2;                  // v modes (v - 3/4)^2, (v + 3/4)^2
+        for (int j = 0; j < d; ++j) has[j] = true;
+        break;
+    }
+    int total = 0;
+    for (int j = 0; j < d; ++j) {
+        F.off[j] = has[j] ? total : 0;
+        if (has[j]) total += F.n[j];
+    }
+    F.tab_ld = total;
+    F.tab_rows = rows;
+    out.table.assign((size_t)rows * total, 0.0);
+    double *t0 = out.table.data(), *t1 = rows > 1 ? t0 + total : nullptr;
+    for (int j = 0; j < d; ++j) {
+        if (!has[j]) continue;
+        const int n = F.n[j];
+        double *a = t0 + F.off[j], *b = t1 ? t1 + F.off[j] : nullptr;
+        for (int i = 0; i < n; ++i) {
+            switch (F.id) {
+            case TT_FN_MAXWELL:
+                if (j < 3) {
+                    const double x = (double)i / (double)n;
+                    a[i] = (j == 1) ? std::cos(twopi * x) : std::sin(twopi * x);
+                } else {
+                    a[i] = vel<double>(i, n, F.prm[3]);
+                }
+                break;
+            case TT_FN_BIMAXWELL: {
+                const double v = vel<double>(i, n, F.prm[10]);
+                const int c = j - (d - 3);
+                a[i] = (v - F.prm[1 + c]) * (v - F.prm[1 + c]);
+                b[i] = (v - F.prm[6 + c]) * (v - F.prm[6 + c]);
+                break;
+            }
+            default:
+                if ((j & 1) == 0) {
+                    const double x = cell<double>(i, n, -0.5, 0.5);
+                    const double sx = std::sin(twopi * x);
+                    const double rho = 1.0 + 0.875 * sx;
+                    const double T = 0.5 + 0.4 * sx;
+                    a[i] = rho / (2.0 * std::sqrt(twopi * T));
+                    b[i] = 2.0 * T;
+                } else {
+                    const double v = cell<double>(i, n, -3.0, 3.0);
+                    a[i] = (v - 0.75) * (v - 0.75);
+                    b[i] = (v + 0.75) * (v + 0.75);
+                }
+                break;
+            }
+        }
+    }
+}
+
 int build_fn(int fn_id, int d, const int32_t *n, const double *params, int nparams, FnHost &out)
 {
     FnDev &F = out.dev;
@@ -80,7 +159,8 @@ int build_fn(int fn_id, int d, const int32_t *n, const double *params, int npara
         if (r < 1 || (double)r != params[0] || nparams < 1 + r * total)
             return set_err(TT_EFN, "separable sum needs 1 + r*sum(n) params");
         F.sep_r = r;
-        F.sep_total = total;
+        F.tab_ld = total;
+        F.tab_rows = r;
         out.table.assign(params + 1, params + 1 + (size_t)r * total);
         break;
     }
@@ -93,16 +173,46 @@ int build_fn(int fn_id, int d, const int32_t *n, const double *params, int npara
     default:
         return set_err(TT_EFN, "unknown fn_id %d", fn_id);
     }
+    if (fn_id != TT_FN_HILBERT && fn_id != TT_FN_SEPSUM) mode_tables(F, out);
     return TT_OK;
 }
 
-int upload_fn(FnHost &fh)
+void FnHost::free_device()
 {
-    if (fh.table.empty()) { fh.dev.tab = nullptr; return TT_OK; }
-    if (fh.d_table) { (void)hipFree(fh.d_table); fh.d_table = nullptr; }
-    HIPCHK(hipMalloc(&fh.d_table, fh.table.size() * sizeof(double)));
-    HIPCHK(hipMemcpy(fh.d_table, fh.table.data(), fh.table.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (d_table) (void)hipFree(d_table);
+    if (d_table32) (void)hipFree(d_table32);
+    d_table = nullptr;
+    d_table32 = nullptr;
+    d_cap = 0;
+}
+
+int upload_fn(FnHost &fh, hipStream_t stream)
+{
+    fh.dev.tab = nullptr;
+    fh.dev.tab32 = nullptr;
+    if (fh.table.empty()) return TT_OK;
+    const size_t m = fh.table.size();
+    fh.table32.resize(m);
+    for (size_t i = 0; i < m; ++i) fh.table32[i] = (float)fh.table[i];
+    if (m > fh.d_cap) {
+        // a larger table: the old buffers may still be read by queued work
+        if (stream) HIPCHK(hipStreamSynchronize(stream));
+        fh.free_device();
+        HIPCHK(hipMalloc(&fh.d_table, m * sizeof(double)));
+        HIPCHK(hipMalloc(&fh.d_table32, m * sizeof(float)));
+        fh.d_cap = m;
+    }
+    if (stream) {
+        // ordered after earlier work on the stream; the host vectors live as
+        // long as the holder and change only at its next upload
+        HIPCHK(hipMemcpyAsync(fh.d_table, fh.table.data(), m * sizeof(double), hipMemcpyHostToDevice, stream));
+        HIPCHK(hipMemcpyAsync(fh.d_table32, fh.table32.data(), m * sizeof(float), hipMemcpyHostToDevice, stream));
+    } else {
+        HIPCHK(hipMemcpy(fh.d_table, fh.table.data(), m * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(fh.d_table32, fh.table32.data(), m * sizeof(float), hipMemcpyHostToDevice));
+    }
     fh.dev.tab = fh.d_table;
+    fh.dev.tab32 = fh.d_table32;
     return TT_OK;
 }
 
@@ -144,7 +254,7 @@ void Problem::release()
     if (hS_pinned) { (void)hipHostFree(hS_pinned); hS_pinned = nullptr; }
     for (hipEvent_t &e : run_ev)
         if (e) { (void)hipEventDestroy(e); e = nullptr; }
-    if (fn.d_table) { (void)hipFree(fn.d_table); fn.d_table = nullptr; }
+    fn.free_device();
     if (own_stream && stream) { (void)hipStreamDestroy(stream); }
     stream = nullptr;
     own_stream = false;
@@ -937,11 +1047,13 @@ int tt_cross_sampled_error(tt_cross_h h, int64_t R, uint64_t seed, double *err)
     if (e == hipSuccess) {
         const unsigned g = (unsigned)((R + NT - 1) / NT);
         k_gen_idx<<<g, NT, 0, P.stream>>>(P.d, a, seed, R, didx);
-        k_fn_eval<double><<<g, NT, 0, P.stream>>>(P.fn.dev, R, didx, x);
-        const int64_t waves = std::min<int64_t>(R, 65536);
-        k_tt_eval<<<(unsigned)((waves * 64 + NT - 1) / NT), NT, 0, P.stream>>>(a, P.d_cores, R, didx, y);
-        k_err_partial<<<nb, NT, 0, P.stream>>>(R, x, y, part);
-        e = hipGetLastError();
+        e = launch_fn_eval<double>(P.fn.dev, R, didx, x, P.stream);
+        if (e == hipSuccess) {
+            const int64_t waves = std::min<int64_t>(R, 65536);
+            k_tt_eval<<<(unsigned)((waves * 64 + NT - 1) / NT), NT, 0, P.stream>>>(a, P.d_cores, R, didx, y);
+            k_err_partial<<<nb, NT, 0, P.stream>>>(R, x, y, part);
+            e = hipGetLastError();
+        }
     }
     std::vector<double> hp(2 * nb);
     if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), part, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, P.stream);
@@ -960,14 +1072,43 @@ int tt_cross_sampled_error(tt_cross_h h, int64_t R, uint64_t seed, double *err)
 }  // extern "C"
 
 namespace ttc {
+// Device tables of the functions that bulk evaluation saw last, so that
+// repeated evaluations of one function upload nothing.  A call holds the lock
+// until its kernel has finished (it ends with a device synchronisation), so
+// no table is replaced while a kernel reads it.  At most kEvalCacheEntries
+// tables of at most kEvalCacheBytes each are kept, until the process ends.
+namespace {
+constexpr int kEvalCacheEntries = 4;
+constexpr size_t kEvalCacheBytes = (size_t)16 << 20;
+struct EvalKey {
+    int fn_id = 0, d = 0;
+    std::vector<int32_t> n;
+    std::vector<double> params;
+    bool operator==(const EvalKey &o) const
+    {
+        return fn_id == o.fn_id && d == o.d && n == o.n && params == o.params;
+    }
+};
+struct EvalEntry {
+    EvalKey key;
+    FnHost fh;
+    uint64_t used = 0;
+};
+std::mutex g_eval_mu;
+std::vector<std::unique_ptr<EvalEntry>> g_eval_cache;
+uint64_t g_eval_clock = 0;
+hipEvent_t g_eval_ev[2] = {nullptr, nullptr};   // attached to the last evaluation's dispatch
+double g_eval_last_ms = -1.0;
+}  // namespace
+
 // Bulk evaluation behind tt_fn_eval (V = double) and tt_fn_eval_f32.
 template <typename V>
 static int fn_eval_impl(int fn_id, int d, const int32_t *n, const double *params, int nparams, int64_t m,
                         const int32_t *idx, V *out, int on_device)
 {
     g_err.clear();
-    FnHost fh;
-    int st = build_fn(fn_id, d, n, params, nparams, fh);
+    FnHost fresh;
+    int st = build_fn(fn_id, d, n, params, nparams, fresh);
     if (st) return st;
     if (m < 0 || (m > 0 && (!idx || !out))) return set_err(TT_EINVAL, "bad arguments");
     if (m == 0) return TT_OK;
@@ -976,7 +1117,38 @@ static int fn_eval_impl(int fn_id, int d, const int32_t *n, const double *params
             for (int j = 0; j < d; ++j)
                 if (idx[t * d + j] < 0 || idx[t * d + j] >= n[j])
                     return set_err(TT_EINVAL, "index %lld,%d out of range", (long long)t, j);
-    if ((st = upload_fn(fh)) != TT_OK) return st;
+    std::lock_guard<std::mutex> lk(g_eval_mu);
+    EvalKey key;
+    key.fn_id = fn_id;
+    key.d = d;
+    key.n.assign(n, n + d);
+    if (nparams > 0) key.params.assign(params, params + nparams);
+    EvalEntry *ent = nullptr;
+    for (auto &x : g_eval_cache)
+        if (x->key == key) { ent = x.get(); break; }
+    FnHost *fhp = &fresh;
+    if (ent) {
+        fhp = &ent->fh;
+    } else if (fresh.table.size() * (sizeof(double) + sizeof(float)) <= kEvalCacheBytes) {
+        if ((int)g_eval_cache.size() >= kEvalCacheEntries) {
+            auto lru = std::min_element(g_eval_cache.begin(), g_eval_cache.end(),
+                                        [](const auto &a, const auto &b) { return a->used < b->used; });
+            (*lru)->fh.free_device();
+            g_eval_cache.erase(lru);
+        }
+        auto e = std::make_unique<EvalEntry>();
+        e->key = std::move(key);
+        e->fh = std::move(fresh);
+        if ((st = upload_fn(e->fh)) != TT_OK) { e->fh.free_device(); return st; }
+        ent = e.get();
+        fhp = &ent->fh;
+        g_eval_cache.push_back(std::move(e));
+    } else if ((st = upload_fn(fresh)) != TT_OK) {
+        fresh.free_device();
+        return st;
+    }
+    if (ent) ent->used = ++g_eval_clock;
+    FnHost &fh = *fhp;
     const int *didx = idx;
     V *dout = out;
     void *ti = nullptr, *to = nullptr;
@@ -988,15 +1160,17 @@ static int fn_eval_impl(int fn_id, int d, const int32_t *n, const double *params
         didx = (const int *)ti;
         dout = (V *)to;
     }
-    if (e == hipSuccess) {
-        k_fn_eval<V><<<(unsigned)((m + NT - 1) / NT), NT>>>(fh.dev, m, didx, dout);
-        e = hipGetLastError();
-    }
+    for (hipEvent_t &ev : g_eval_ev)
+        if (e == hipSuccess && !ev) e = hipEventCreate(&ev);
+    if (e == hipSuccess) e = launch_fn_eval<V>(fh.dev, m, didx, dout, nullptr, g_eval_ev[0], g_eval_ev[1]);
     if (e == hipSuccess) e = hipDeviceSynchronize();
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, g_eval_ev[0], g_eval_ev[1]);
+    if (e == hipSuccess) g_eval_last_ms = ms;
     if (e == hipSuccess && !on_device) e = hipMemcpy(out, dout, sizeof(V) * m, hipMemcpyDeviceToHost);
     if (ti) (void)hipFree(ti);
     if (to) (void)hipFree(to);
-    if (fh.d_table) { (void)hipFree(fh.d_table); fh.d_table = nullptr; }
+    if (!ent) fresh.free_device();
     if (e != hipSuccess) return set_err(TT_EDEVICE, "tt_fn_eval: %s", hipGetErrorString(e));
     return TT_OK;
 }
@@ -1014,6 +1188,15 @@ int tt_fn_eval_f32(int fn_id, int d, const int32_t *n, const double *params, int
                    const int32_t *idx, float *out, int on_device)
 {
     return fn_eval_impl<float>(fn_id, d, n, params, nparams, m, idx, out, on_device);
+}
+
+int tt_fn_eval_last_kernel_ms(double *ms)
+{
+    if (!ms) return set_err(TT_EINVAL, "ms is NULL");
+    std::lock_guard<std::mutex> lk(g_eval_mu);
+    if (g_eval_last_ms < 0.0) return set_err(TT_ESTATE, "no bulk evaluation has completed");
+    *ms = g_eval_last_ms;
+    return TT_OK;
 }
 
 void tt_cross_destroy(tt_cross_h h)

@@ -18,15 +18,26 @@ constexpr int TT_ROOK_ITERS = 8;           // rounds of Alg. 1's loop per block,
 // ---------------------------------------------------------------------------
 // Generating function descriptor (copied to the device with the problem).
 // ---------------------------------------------------------------------------
+// Table-driven functions keep per-mode values in one device table of rows of
+// tab_ld entries: row t holds, for every mode j, the values of indices
+// 0..n_j-1 from column off[j] on.  The separable sum stores its factor
+// vectors there (row m = term m).  The Maxwellians store their per-mode
+// factors there ("atoms": the sines, cosines and velocities that depend on one
+// index alone), computed once on the host in FP64 by the same operations the
+// formulas prescribe; an entry then combines table values and needs no
+// trigonometric call.  tab32 holds the same table rounded to FP32.
 struct FnDev {
     int id, d;
     int n[TT_MAX_D];
     double prm[12];
     int nprm;
     double shift;               // Hilbert denominator shift
-    const double *tab;          // separable-sum factor table (device), else null
-    int sep_r, sep_total;
-    int off[TT_MAX_D];          // separable-sum per-mode offsets into a term's factors
+    double cst[2];              // Maxwellians: per-Maxwellian constant factors
+    const double *tab;          // per-mode value table (device), else null
+    const float *tab32;         // the same table in FP32 (device), else null
+    int sep_r, tab_ld;          // separable-sum terms; entries per table row
+    int tab_rows;               // rows of the table (0: no table)
+    int off[TT_MAX_D];          // first column of mode j in a table row
 };
 
 // SplitMix64 (Steele, Lea, Flood 2014) is counter based: draw t of the stream
@@ -59,26 +70,37 @@ template <> struct M<float> {
     __device__ static float sqrt(float x) { return ::sqrtf(x); }
 };
 
-template <typename V> __device__ inline V cell(int i, int n, V lo, V hi)
+template <typename V> __host__ __device__ inline V cell(int i, int n, V lo, V hi)
 {
     return lo + ((V)i + (V)0.5) * ((hi - lo) / (V)n);
 }
 
 // Velocity grid: cell centres of [-vmax, vmax] in n cells.
-template <typename V> __device__ inline V vel(int i, int n, V vmax)
+template <typename V> __host__ __device__ inline V vel(int i, int n, V vmax)
 {
     return -vmax + ((V)i + (V)0.5) * ((V)2 * vmax / (V)n);
 }
+
+// The per-mode table in the arithmetic's precision.
+template <typename V> __host__ __device__ inline const V *fn_table(const FnDev &F);
+template <> __host__ __device__ inline const double *fn_table<double>(const FnDev &F) { return F.tab; }
+template <> __host__ __device__ inline const float *fn_table<float>(const FnDev &F) { return F.tab32; }
 
 // Value of the generating function at a full 0-based multi-index, read
 // through ix(j) (an accessor, so callers can assemble the index from LDS-staged
 // prefixes and suffixes without a private array).  The operation order follows
 // the written formulas term by term, so that FP64 values of the Hilbert and
-// separable functions are bitwise reproducible.
+// separable functions are bitwise reproducible; the Maxwellians' per-index
+// factors come from the host-built table, and only their exponentials are
+// evaluated here.
 // FNS = 0 reads the function from F.id; a nonzero FNS fixes it at compile
 // time, so a kernel built for one function carries no code of the others.
-template <typename V, int FNS = 0, typename IX> __device__ inline V fn_value_ix(const FnDev &F, IX ix)
+// fn_value_tx reads the per-mode table through tb (a copy of it in LDS, or the
+// table itself); fn_value_ix reads the table in device memory.
+template <typename V, int FNS = 0, typename IX> __device__ inline V fn_value_tx(const FnDev &F, IX ix, const V *tb)
 {
+    // value t of index i of mode j
+    auto atom = [&](int t, int j, int i) -> V { return tb[(int64_t)t * F.tab_ld + F.off[j] + i]; };
     switch (FNS ? FNS : F.id) {
     case TT_FN_HILBERT: {
         long long s = 0;
@@ -86,32 +108,24 @@ template <typename V, int FNS = 0, typename IX> __device__ inline V fn_value_ix(
         return (V)1 / ((V)s + (V)F.shift);
     }
     case TT_FN_MAXWELL: {
-        const V a = (V)F.prm[0], b = (V)F.prm[1], T = (V)F.prm[2], vmax = (V)F.prm[3];
-        const V twopi = (V)2 * (V)PI;
-        V x1 = (V)ix(0) / (V)F.n[0];
-        V x2 = (V)ix(1) / (V)F.n[1];
-        V x3 = (V)ix(2) / (V)F.n[2];
-        V v1 = vel<V>(ix(3), F.n[3], vmax);
-        V v2 = vel<V>(ix(4), F.n[4], vmax);
-        V v3 = vel<V>(ix(5), F.n[5], vmax);
-        V rho = (V)1 + a * M<V>::sin(twopi * x1) * M<V>::cos(twopi * x2);
-        V ux = b * M<V>::sin(twopi * x3);
+        // table row 0: sin(2 pi x1), cos(2 pi x2), sin(2 pi x3), v1, v2, v3
+        const V a = (V)F.prm[0], b = (V)F.prm[1], T = (V)F.prm[2];
+        const V s1 = atom(0, 0, ix(0)), c2 = atom(0, 1, ix(1)), s3 = atom(0, 2, ix(2));
+        const V v1 = atom(0, 3, ix(3)), v2 = atom(0, 4, ix(4)), v3 = atom(0, 5, ix(5));
+        V rho = (V)1 + a * s1 * c2;
+        V ux = b * s3;
         V q = (v1 - ux) * (v1 - ux) + v2 * v2 + v3 * v3;
-        return rho * M<V>::pow(twopi * T, (V)-1.5) * M<V>::exp(-q / ((V)2 * T));
+        return rho * (V)F.cst[0] * M<V>::exp(-q / ((V)2 * T));
     }
     case TT_FN_BIMAXWELL: {
-        const V vmax = (V)F.prm[10];
-        const V twopi = (V)2 * (V)PI;
+        // table row m: (v_c - u_{m,c})^2 on the velocity modes; cst[m] = rho_m (2 pi T_m)^{-3/2}
         const int d = F.d;
-        V v[3];
-        for (int c = 0; c < 3; ++c) v[c] = vel<V>(ix(d - 3 + c), F.n[d - 3 + c], vmax);
         V f = 0;
         for (int m = 0; m < 2; ++m) {
-            const double *Q = F.prm + 5 * m;
-            V T = (V)Q[4];
+            const V T = (V)F.prm[5 * m + 4];
             V q = 0;
-            for (int c = 0; c < 3; ++c) q += (v[c] - (V)Q[1 + c]) * (v[c] - (V)Q[1 + c]);
-            f += (V)Q[0] * M<V>::pow(twopi * T, (V)-1.5) * M<V>::exp(-q / ((V)2 * T));
+            for (int c = 0; c < 3; ++c) q += atom(m, d - 3 + c, ix(d - 3 + c));
+            f += (V)F.cst[m] * M<V>::exp(-q / ((V)2 * T));
         }
         return f;
     }
@@ -119,31 +133,32 @@ template <typename V, int FNS = 0, typename IX> __device__ inline V fn_value_ix(
         V f = 0;
         for (int m = 0; m < F.sep_r; ++m) {
             V prod = 1;
-            int off = m * F.sep_total;
-            for (int j = 0; j < F.d; ++j) prod *= (V)F.tab[off + F.off[j] + ix(j)];
+            for (int j = 0; j < F.d; ++j) prod *= atom(m, j, ix(j));
             f += prod;
         }
         return f;
     }
     case TT_FN_MAXWELL_2D2V:
     case TT_FN_MAXWELL_3D3V: {
+        // x modes: rows rho/(2 sqrt(2 pi T)) and 2T; v modes: (v - 3/4)^2 and (v + 3/4)^2
         const int ndim = (F.id == TT_FN_MAXWELL_2D2V) ? 2 : 3;
-        const V twopi = (V)2 * (V)PI;
         V pre = 0, em = 0, ep = 0;
         for (int w = 0; w < ndim; ++w) {
-            V x = cell<V>(ix(2 * w), F.n[2 * w], (V)-0.5, (V)0.5);
-            V vv = cell<V>(ix(2 * w + 1), F.n[2 * w + 1], (V)-3, (V)3);
-            V s = M<V>::sin(twopi * x);
-            V rho = (V)1 + (V)0.875 * s;
-            V T = (V)0.5 + (V)0.4 * s;
-            pre += rho / ((V)2 * M<V>::sqrt(twopi * T));
-            em += (vv - (V)0.75) * (vv - (V)0.75) / ((V)2 * T);
-            ep += (vv + (V)0.75) * (vv + (V)0.75) / ((V)2 * T);
+            const int ix_x = ix(2 * w), ix_v = ix(2 * w + 1);
+            const V t2 = atom(1, 2 * w, ix_x);
+            pre += atom(0, 2 * w, ix_x);
+            em += atom(0, 2 * w + 1, ix_v) / t2;
+            ep += atom(1, 2 * w + 1, ix_v) / t2;
         }
         return pre * (M<V>::exp(-em) + M<V>::exp(-ep));
     }
     }
     return (V)0;
+}
+
+template <typename V, int FNS = 0, typename IX> __device__ inline V fn_value_ix(const FnDev &F, IX ix)
+{
+    return fn_value_tx<V, FNS>(F, ix, fn_table<V>(F));
 }
 
 template <typename V, int FNS = 0> __device__ inline V fn_value(const FnDev &F, const int *idx)

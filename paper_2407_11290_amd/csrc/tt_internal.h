@@ -22,12 +22,19 @@ int set_err(int code, const char *fmt, ...);
 
 struct FnHost {
     FnDev dev;
-    std::vector<double> table;     // separable-sum factors (host copy)
-    double *d_table = nullptr;     // device copy owned by the holder
+    std::vector<double> table;     // per-mode value table (host copy; see FnDev)
+    std::vector<float> table32;    // its FP32 rounding, made at upload
+    double *d_table = nullptr;     // device copies owned by the holder
+    float *d_table32 = nullptr;
+    size_t d_cap = 0;              // entries the device copies can hold
+    void free_device();
 };
 
 int build_fn(int fn_id, int d, const int32_t *n, const double *params, int nparams, FnHost &out);
-int upload_fn(FnHost &fh);
+// Copies the table to the device (reusing the holder's buffers when it fits)
+// and points dev.tab / dev.tab32 at it; with a stream the copies are queued on
+// it, else they complete before the return.
+int upload_fn(FnHost &fh, hipStream_t stream = nullptr);
 
 struct Problem {
     // problem definition

@@ -21,6 +21,10 @@
 //             (Sec. 3.2.1), stop test, append to the nested index sets.
 #pragma once
 
+#include <hip/hip_ext.h>
+
+#include <algorithm>
+
 #include "tt_device.h"
 
 namespace ttc {
@@ -1856,15 +1860,85 @@ static __global__ void __launch_bounds__(NT) k_tt_eval(TTArgs a, const double *_
 
 // The generating function at m multi-indices, in the arithmetic of V (the
 // precision of the sweeps that would evaluate it).
+// Bulk evaluation.  A workgroup takes rounds of ch = NT*EV_KP/d consecutive
+// entries.  Their multi-indices (at most NT*EV_KP ints) are loaded with
+// coalesced loads into registers one round ahead and stored to LDS at the
+// start of the round, so the loads of round r+1 are in flight while round r
+// is evaluated.  When the function's per-mode table fits (tab_lds) the
+// workgroup first copies it to LDS, so every table read is an LDS read.
+constexpr int EV_KP = 16;                   // index ints per thread and round
+constexpr int EV_TAB_LDS_MAX = 32768;       // bytes of table copied to LDS, at most
+
+__host__ __device__ inline size_t fn_eval_idx_bytes() { return (size_t)NT * EV_KP * sizeof(int); }
+
 template <typename V>
 static __global__ void __launch_bounds__(NT) k_fn_eval(FnDev F, int64_t m, const int *__restrict__ idx,
-                                                  V *__restrict__ out)
+                                                       V *__restrict__ out, int tab_lds)
 {
-    const int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (t >= m) return;
-    int ix[TT_MAX_D];
-    for (int j = 0; j < F.d; ++j) ix[j] = idx[t * F.d + j];
-    out[t] = fn_value<V>(F, ix);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int d = F.d, tid = threadIdx.x;
+    const int ch = (NT * EV_KP) / d;
+    const int64_t stride = (int64_t)gridDim.x * ch;
+    int *sidx = (int *)smem_raw;
+    int pf[EV_KP];
+    auto fetch = [&](int64_t b) {
+        const int nint = (b < m) ? (int)min((int64_t)ch, m - b) * d : 0;
+        const int *src = idx + (b < m ? b : 0) * d;
+#pragma unroll
+        for (int r = 0; r < EV_KP; ++r) {
+            const int i = tid + r * NT;
+            pf[r] = (i < nint) ? src[i] : 0;
+        }
+    };
+    auto rounds = [&](const V *tb) {
+        int64_t base = (int64_t)blockIdx.x * ch;
+        fetch(base);
+        for (; base < m; base += stride) {
+            const int cnt = (int)min((int64_t)ch, m - base);
+            __syncthreads();                // the previous round's reads of sidx are done
+#pragma unroll
+            for (int r = 0; r < EV_KP; ++r) sidx[tid + r * NT] = pf[r];
+            __syncthreads();
+            fetch(base + stride);
+            for (int e = tid; e < cnt; e += NT) {
+                const int *ix = sidx + e * d;
+                out[base + e] = fn_value_tx<V>(F, [&](int j) { return ix[j]; }, tb);
+            }
+        }
+    };
+    if (tab_lds) {
+        V *stab = (V *)(smem_raw + fn_eval_idx_bytes());
+        const V *src = fn_table<V>(F);
+        const int cnt = F.tab_rows * F.tab_ld;
+        for (int i = tid; i < cnt; i += NT) stab[i] = src[i];
+        // the first round's barriers order these writes before any read
+        rounds(stab);
+    } else {
+        rounds(fn_table<V>(F));
+    }
+}
+
+// Launch of k_fn_eval for m entries: the grid covers the chip eight
+// workgroups per CU deep and strides over the rest.
+template <typename V>
+inline hipError_t launch_fn_eval(const FnDev &F, int64_t m, const int *idx, V *out, hipStream_t stream,
+                                 hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr)
+{
+    if (m <= 0) return hipSuccess;
+    const size_t tab_bytes = (size_t)F.tab_rows * F.tab_ld * sizeof(V);
+    const int tab_lds = (fn_table<V>(F) && tab_bytes > 0 && tab_bytes <= EV_TAB_LDS_MAX) ? 1 : 0;
+    const size_t lds = fn_eval_idx_bytes() + (tab_lds ? tab_bytes : 0);
+    const int ch = (NT * EV_KP) / F.d;
+    const int64_t rounds = (m + ch - 1) / ch;
+    const unsigned g = (unsigned)std::min<int64_t>(rounds, 2048);
+    if (ev_start && ev_stop) {
+        // the events take the dispatch's own start and end timestamps
+        hipExtLaunchKernelGGL(k_fn_eval<V>, dim3(g), dim3(NT), (uint32_t)lds, stream, ev_start, ev_stop, 0u, F, m,
+                              idx, out, tab_lds);
+    } else {
+        k_fn_eval<V><<<g, NT, lds, stream>>>(F, m, idx, out, tab_lds);
+    }
+    return hipGetLastError();
 }
 
 static __global__ void __launch_bounds__(NT) k_gen_idx(int d, TTArgs a, uint64_t seed, int64_t m, int *idx)

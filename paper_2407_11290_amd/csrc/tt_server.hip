@@ -91,7 +91,7 @@ public:
         FnHost f;
         int st = build_fn(fn_id, d, n, params, nparams, f);
         if (st) return st;
-        if (!f.table.empty()) return set_err(TT_EFN, "the server takes no table-driven generating functions");
+        if (fn_id == TT_FN_SEPSUM) return set_err(TT_EFN, "the server takes no separable sums (caller-supplied factor tables)");
         if (!(eps >= 0.0) || !(eps < 1.0)) return set_err(TT_EINVAL, "eps must be in [0,1)");
         auto r = std::make_unique<Request>();
         r->d = d;
@@ -255,7 +255,9 @@ private:
         FnHost f;
         if ((err = build_fn(r.fn_id, r.d, r.n, r.params.data(), (int)r.params.size(), f)) != TT_OK) return nullptr;
         P.fn.dev = f.dev;
-        P.hP.F = f.dev;
+        P.fn.table.swap(f.table);
+        if ((err = upload_fn(P.fn, stream_)) != TT_OK) return nullptr;
+        P.hP.F = P.fn.dev;
         P.eps = r.eps;
         P.opt.seed = r.seed;
         P.force_fp64 = r.force64;

@@ -173,3 +173,16 @@ def test_server_stats_struct_and_no_gpu_failure():
         from paper_2407_11290_amd.api import Server
         with pytest.raises(_lib.TTError):
             Server(1 << 30)
+
+
+def test_fn_eval_kernel_time_argument_checks():
+    # neither call reaches the GPU: a NULL output pointer, and (in a process
+    # that has not evaluated anything) no time to report
+    lib = _lib.load()
+    assert lib.tt_fn_eval_last_kernel_ms(None) == _lib.EINVAL
+    ms = C.c_double(-5.0)
+    rc = lib.tt_fn_eval_last_kernel_ms(C.byref(ms))
+    if rc == _lib.ESTATE:
+        assert ms.value == -5.0
+    else:
+        assert rc == _lib.OK and ms.value > 0.0
