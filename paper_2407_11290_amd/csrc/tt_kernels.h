@@ -170,7 +170,6 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSw
                          double &bv, uint64_t &bk, double &bs, V *sm)
 {
     const int d = P->d, u = g.u, k = u + 1, tid = threadIdx.x, rk = ks.rk;
-    const int wid = tid >> 6, lane = tid & 63;
     const bool rows_old = g.row0 < ks.nr_st, cols_old = g.col0 < ks.nc_st;
     V *E = (V *)K.E;
     const int64_t ld = K.ld;
@@ -268,18 +267,23 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSw
         }
     }
     __syncthreads();
-    // chains as triangular solves, one lane group per row (column): lane z of
-    // the group holds factor z, and at step z' the finished factor z' is
-    // passed to the lanes z > z' by a shuffle.  Each factor sees the same
-    // operations in the same order as the written recursion.
-    int G = 1;
-    while (G < rk) G <<= 1;
-    const int gpw = 64 / G, ngroups = (NT / 64) * gpw;
-    const int gid = wid * gpw + lane / G, zl = lane & (G - 1);
-    if (!rows_old) {
-        for (int base = 0; base < g.nrows; base += ngroups) {
+    // chains as triangular solves.  Each factor sees the same operations in
+    // the same order as the written recursion, so both forms give the same
+    // bits.  Up to rank 16, a lane group per row (column): lane z holds
+    // factor z, and at step z' the finished factor z' reaches lanes z > z' by
+    // a shuffle.  Above that, one thread per row (column) runs the factors in
+    // ascending z and reads the finished lower ones back from LDS (a lane
+    // group would need too many passes over the tile).
+    const int nrw = rows_old ? 0 : g.nrows, ncw = cols_old ? 0 : g.ncols;
+    if (rk <= 16) {
+        const int wid = tid >> 6, lane = tid & 63;
+        int G = 1;
+        while (G < rk) G <<= 1;
+        const int gpw = 64 / G, ngroups = (NT / 64) * gpw;
+        const int gid = wid * gpw + lane / G, zl = lane & (G - 1);
+        for (int base = 0; base < nrw; base += ngroups) {
             const int ii = base + gid;
-            const bool ok = ii < g.nrows && zl < rk;
+            const bool ok = ii < nrw && zl < rk;
             V w = ok ? Wt[zl * TRm + ii] : (V)0;
             for (int zp = 0; zp + 1 < rk; ++zp) {
                 const V wzp = __shfl(w, zp, G);
@@ -291,11 +295,9 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSw
                 if (cols_old && gz >= g.col0 && gz < g.col0 + g.ncols) E[(int64_t)(g.row0 + ii) * ld + gz] = w;
             }
         }
-    }
-    if (!cols_old) {
-        for (int base = 0; base < g.ncols; base += ngroups) {
+        for (int base = 0; base < ncw; base += ngroups) {
             const int jj = base + gid;
-            const bool ok = jj < g.ncols && zl < rk;
+            const bool ok = jj < ncw && zl < rk;
             V u = ok ? Ut[zl * TCm + jj] : (V)0;
             for (int zp = 0; zp + 1 < rk; ++zp) {
                 const V uu = __shfl(u, zp, G) / s_piv[zp];
@@ -305,6 +307,35 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSw
                 const int rz = s_rho[zl];
                 if (rows_old && rz >= g.row0 && rz < g.row0 + g.nrows) E[(int64_t)rz * ld + g.col0 + jj] = u;
                 Ut[zl * TCm + jj] = u / s_piv[zl];
+            }
+        }
+    } else {
+        for (int e = tid; e < nrw + ncw; e += NT) {
+            if (e < nrw) {
+                const int ii = e;
+                for (int z = 1; z < rk; ++z) {
+                    V w = Wt[z * TRm + ii];
+#pragma unroll 8
+                    for (int zp = 0; zp < z; ++zp) w = vfma<V>(-Wt[zp * TRm + ii], Gr[tri(zp, z)], w);
+                    Wt[z * TRm + ii] = w;
+                }
+                if (cols_old)
+                    for (int z = 0; z < rk; ++z) {
+                        const int gz = s_gam[z];
+                        if (gz >= g.col0 && gz < g.col0 + g.ncols)
+                            E[(int64_t)(g.row0 + ii) * ld + gz] = Wt[z * TRm + ii];
+                    }
+            } else {
+                const int jj = e - nrw;
+                for (int z = 0; z < rk; ++z) {
+                    V u = Ut[z * TCm + jj];
+                    // Ut of a lower z already holds its finished factor over its pivot
+#pragma unroll 8
+                    for (int zp = 0; zp < z; ++zp) u = vfma<V>(-Gc[tri(zp, z)], Ut[zp * TCm + jj], u);
+                    const int rz = s_rho[z];
+                    if (rows_old && rz >= g.row0 && rz < g.row0 + g.nrows) E[(int64_t)rz * ld + g.col0 + jj] = u;
+                    Ut[z * TCm + jj] = u / s_piv[z];
+                }
             }
         }
     }
