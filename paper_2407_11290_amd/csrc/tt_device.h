@@ -235,9 +235,18 @@ struct KSweep {
     double apiv;                  // its value in sweep precision
 };
 
+// Tiles per unfolding of one sweep, split into new-entry tiles and stored
+// tiles, with the running offsets of both kinds over the unfoldings.
+struct SweepShape {
+    int RT[TT_MAX_D], CT[TT_MAX_D], RTs[TT_MAX_D], CTs[TT_MAX_D];
+    int noff[TT_MAX_D + 1], soff[TT_MAX_D + 1];
+};
+constexpr int SHAPE_WORDS = (int)(sizeof(SweepShape) / sizeof(int));
+
 struct ProbState {
     int r[2][TT_MAX_D + 1];       // committed ranks, double-buffered by sweep parity
     KSweep ks[TT_MAX_D];
+    SweepShape sh;                // tile counts of the sweep ks describes
     int stop, capped, err, sweeps;
     unsigned long long pivoted;
     unsigned long long alg_bytes;   // algorithmic residual traffic of the tile launches

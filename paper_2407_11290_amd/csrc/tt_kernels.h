@@ -371,12 +371,7 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSw
     block_best(bv, bk, bs);
 }
 
-// Tiles per unfolding this sweep, split into new-entry tiles and stored tiles.
-struct SweepShape {
-    int RT[TT_MAX_D], CT[TT_MAX_D], RTs[TT_MAX_D], CTs[TT_MAX_D];
-    int noff[TT_MAX_D + 1], soff[TT_MAX_D + 1];
-};
-
+// Tile counts of the sweep that ks describes (see SweepShape).
 __device__ inline void sweep_shape(const ProbDev *P, const KSweep *ks, int nk, SweepShape &sh)
 {
     int nn = 0, ns = 0;
@@ -395,6 +390,19 @@ __device__ inline void sweep_shape(const ProbDev *P, const KSweep *ks, int nk, S
     sh.soff[nk] = ns;
 }
 
+// Workgroup-wide: tile counts of the sweep that ks (in LDS, complete for all
+// threads after the first barrier) describes, stored beside ks in S so that
+// every search workgroup loads both in one round.  The commit computes the
+// same counts lane-parallel.
+__device__ inline void publish_shape(const ProbDev *P, const KSweep *ks, int nk, ProbState *S)
+{
+    __shared__ SweepShape s_sh;
+    __syncthreads();
+    if (threadIdx.x == 0) sweep_shape(P, ks, nk, s_sh);
+    __syncthreads();
+    for (int t = threadIdx.x; t < SHAPE_WORDS; t += blockDim.x) ((int *)&S->sh)[t] = ((const int *)&s_sh)[t];
+}
+
 
 // Fixed grid striding over work units: first the new-entry tiles (one per
 // workgroup), then the stored tiles four at a time (one per wavefront).
@@ -407,9 +415,9 @@ __device__ void sweep_body(const ProbDev *__restrict__ P, int nk, int blk, int n
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
     __shared__ KSweep ks[TT_MAX_D];
     __shared__ SweepShape sh;
+    // one round of loads: the shapes and tile counts the previous commit left
     if (tid < nk) ks[tid] = S->ks[tid];
-    __syncthreads();
-    if (tid == 0) sweep_shape(P, ks, nk, sh);
+    if (tid < SHAPE_WORDS) ((int *)&sh)[tid] = ((const int *)&S->sh)[tid];
     __syncthreads();
     const int nnew = sh.noff[nk], nst = sh.soff[nk];
     const int units = nnew + (nst + NT / 64 - 1) / (NT / 64);
@@ -637,22 +645,48 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
     __syncthreads();
     if (tid == 0) { s_rnew[0] = 1; s_rnew[d] = 1; }
     __syncthreads();
-    // the next sweep's shapes
-    if (tid < nk) {
-        const int u = tid, k = u + 1;
-        const KDev &K = P->kd[u];
-        KSweep n;
-        n.rk = s_rnew[k];
-        n.apply = s_prop[u];
-        n.nr_st = ks[u].nr;
-        n.nc_st = ks[u].nc;
-        n.nr = s_rnew[k - 1] * K.nk;
-        n.nc = K.nk1 * s_rnew[k + 1];
-        n.arho = ks[u].arho;
-        n.agam = ks[u].agam;
-        n.apiv = ks[u].apiv;
-        S->ks[u] = n;
-        S->r[par ^ 1][k] = s_rnew[k];
+    // the next sweep's shapes and tile counts: lane u of wavefront 0 prepares
+    // unfolding u, and the tile offsets are prefix sums over the lanes
+    if (tid < 64) {
+        const int u = tid;
+        int nn = 0, ns = 0;
+        if (u < nk) {
+            const int k = u + 1;
+            const KDev &K = P->kd[u];
+            KSweep n;
+            n.rk = s_rnew[k];
+            n.apply = s_prop[u];
+            n.nr_st = ks[u].nr;
+            n.nc_st = ks[u].nc;
+            n.nr = s_rnew[k - 1] * K.nk;
+            n.nc = K.nk1 * s_rnew[k + 1];
+            n.arho = ks[u].arho;
+            n.agam = ks[u].agam;
+            n.apiv = ks[u].apiv;
+            S->ks[u] = n;
+            S->r[par ^ 1][k] = s_rnew[k];
+            const int RT = (n.nr / K.nk) * K.RTp, CT = (n.nc / K.nk1) * K.CTq;
+            const int RTs = (n.nr_st / K.nk) * K.RTp, CTs = (n.nc_st / K.nk1) * K.CTq;
+            S->sh.RT[u] = RT;
+            S->sh.CT[u] = CT;
+            S->sh.RTs[u] = RTs;
+            S->sh.CTs[u] = CTs;
+            nn = RT * CT - RTs * CTs;
+            ns = RTs * CTs;
+        }
+        int pn = nn, ps = ns;                  // inclusive scans (nk <= 16 lanes carry counts)
+        for (int off = 1; off < 16; off <<= 1) {
+            const int a = __shfl_up(pn, off, 64), b = __shfl_up(ps, off, 64);
+            if (u >= off) { pn += a; ps += b; }
+        }
+        if (u < nk) {
+            S->sh.noff[u] = pn - nn;
+            S->sh.soff[u] = ps - ns;
+        }
+        if (u == nk - 1) {
+            S->sh.noff[nk] = pn;
+            S->sh.soff[nk] = ps;
+        }
     }
     if (tid == 0) {
         int any = 0;
@@ -851,6 +885,7 @@ __device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns,
         __threadfence_system();
     }
     __syncthreads();
+    __shared__ KSweep s_ks[TT_MAX_D];
     for (int u = 0; u < P->nk; ++u) {
         const KDev &K = P->kd[u];
         const int k = u + 1;
@@ -872,8 +907,10 @@ __device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns,
             ks.agam = i0[k];
             ks.apiv = p0s;
             S->ks[u] = ks;
+            s_ks[u] = ks;
         }
     }
+    publish_shape(P, s_ks, P->nk, S);
 }
 
 template <typename V, int FNS = 0>
