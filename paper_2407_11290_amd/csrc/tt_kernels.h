@@ -63,6 +63,12 @@ template <> __device__ inline float vfma<float>(float a, float b, float c) { ret
 // strictly upper triangular index (zp < z)
 __device__ inline int tri(int zp, int z) { return z * (z - 1) / 2 + zp; }
 
+// Buffers reached through the problem descriptor are generic pointers to the
+// compiler; naming their address space lets it emit global instead of flat
+// loads and stores, which wait on the vector-memory counter alone.
+template <typename T> using gptr_t = __attribute__((address_space(1))) T *;
+template <typename T> __device__ inline gptr_t<T> as_global(T *p) { return (gptr_t<T>)p; }
+
 // LDS bytes of a new-entry tile: factors of the tile rows and columns and the
 // two pivot-block triangles.
 __host__ __device__ inline size_t sweep_lds_bytes(int rk, int TR, int TC, size_t w)
@@ -114,10 +120,11 @@ __device__ void stored_tile_wave(const KDev &K, const KSweep &ks, const TileGeom
     const int TC = K.TC, rpw = 64 / TC;
     const int tr = lane / TC, tcol = lane - tr * TC;
     const bool colok = tcol < g.ncols;
-    V *E = (V *)K.E;
+    const gptr_t<V> E = as_global((V *)K.E);
+    const gptr_t<const uint8_t> rpiv = as_global((const uint8_t *)K.rpiv);
     const int64_t ld = K.ld;
     const int col = g.col0 + (colok ? tcol : 0);
-    const bool live = colok && !K.cpiv[col];
+    const bool live = colok && !as_global((const uint8_t *)K.cpiv)[col];
     const bool apply = ks.apply != 0;
     V u = 0;
     if (apply) u = E[(int64_t)ks.arho * ld + col] / (V)ks.apiv;
@@ -127,7 +134,7 @@ __device__ void stored_tile_wave(const KDev &K, const KSweep &ks, const TileGeom
     for (int c0 = 0; c0 < g.nrows; c0 += 64) {
         const int nch = min(64, g.nrows - c0);
         const int rrow = g.row0 + c0 + (lane < nch ? lane : 0);
-        const int rpl = (lane < nch) ? K.rpiv[rrow] : 1;
+        const int rpl = (lane < nch) ? rpiv[rrow] : 1;
         const V wl = (apply && lane < nch) ? E[(int64_t)rrow * ld + ks.agam] : (V)0;
         for (int base = 0; base < nch; base += B * rpw) {
             V xv[B];
@@ -171,7 +178,10 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSw
 {
     const int d = P->d, u = g.u, k = u + 1, tid = threadIdx.x, rk = ks.rk;
     const bool rows_old = g.row0 < ks.nr_st, cols_old = g.col0 < ks.nc_st;
-    V *E = (V *)K.E;
+    const gptr_t<V> E = as_global((V *)K.E);
+    const gptr_t<const int> rho = as_global((const int *)K.rho), gam = as_global((const int *)K.gam);
+    const gptr_t<const int> Ifull = as_global((const int *)K.Ifull), Jfull = as_global((const int *)K.Jfull);
+    const gptr_t<const double> piv = as_global((const double *)K.piv);
     const int64_t ld = K.ld;
     __shared__ int pre[TT_MAX_D], suf[TT_MAX_D];
     __shared__ int s_rho[TT_MAX_RANK], s_gam[TT_MAX_RANK];
@@ -185,27 +195,27 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSw
     V *Gc = Gr + ntri;                         // W(rho_z, z'), z' < z
     const int TCt = K.TC, rpp = NT / TCt;
     const int tr = tid / TCt, tcol = tid - tr * TCt;
-    const int cpv = (tcol < g.ncols) ? K.cpiv[g.col0 + tcol] : 1;
-    if (tid < npre) pre[tid] = P->kd[u - 1].Ifull[g.p * npre + tid];
-    if (tid < nsuf) suf[tid] = P->kd[u + 1].Jfull[g.q * nsuf + tid];
+    const int cpv = (tcol < g.ncols) ? as_global((const uint8_t *)K.cpiv)[g.col0 + tcol] : 1;
+    if (tid < npre) pre[tid] = as_global((const int *)P->kd[u - 1].Ifull)[g.p * npre + tid];
+    if (tid < nsuf) suf[tid] = as_global((const int *)P->kd[u + 1].Jfull)[g.q * nsuf + tid];
     // Hilbert entries depend on the integer index sum only: the pivots' tuple
     // sums replace the tuples
     __shared__ long long s_is[TT_MAX_RANK], s_js[TT_MAX_RANK];
     for (int z = tid; z < rk; z += NT) {
-        s_rho[z] = K.rho[z];
-        s_gam[z] = K.gam[z];
-        s_piv[z] = (V)K.piv[z];
+        s_rho[z] = rho[z];
+        s_gam[z] = gam[z];
+        s_piv[z] = (V)piv[z];
         if constexpr (FNS == TT_FN_HILBERT) {
             long long is = 0, js = 0;
             if (!rows_old)
-                for (int j = 0; j < nj; ++j) js += K.Jfull[z * nj + j] + 1;
+                for (int j = 0; j < nj; ++j) js += Jfull[z * nj + j] + 1;
             if (!cols_old)
-                for (int j = 0; j < k; ++j) is += K.Ifull[z * k + j] + 1;
+                for (int j = 0; j < k; ++j) is += Ifull[z * k + j] + 1;
             s_is[z] = is;
             s_js[z] = js;
         }
     }
-    for (int ii = tid; ii < g.nrows; ii += NT) s_rp[ii] = K.rpiv[g.row0 + ii];
+    for (int ii = tid; ii < g.nrows; ii += NT) s_rp[ii] = as_global((const uint8_t *)K.rpiv)[g.row0 + ii];
     __syncthreads();
     // raw factors: frozen entries, or the generating function at the skeleton
     if (rows_old) {
@@ -230,7 +240,7 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSw
             for (int e = tid; e < rk * g.nrows; e += NT) {
                 const int z = e / g.nrows, ii = e - z * g.nrows;
                 const int ikv = g.ik0 + ii;
-                const int *Jz = K.Jfull + z * nj;
+                const gptr_t<const int> Jz = Jfull + z * nj;
                 Wt[z * TRm + ii] = fn_value_ix<V, FNS>(P->F, [&](int j) {
                     return j < npre ? pre[j] : (j == k - 1 ? ikv : Jz[j - k]);
                 });
@@ -259,7 +269,7 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSw
             for (int e = tid; e < rk * g.ncols; e += NT) {
                 const int z = e / g.ncols, jj = e - z * g.ncols;
                 const int ik1v = g.ik10 + jj;
-                const int *Iz = K.Ifull + z * k;
+                const gptr_t<const int> Iz = Ifull + z * k;
                 Ut[z * TCm + jj] = fn_value_ix<V, FNS>(P->F, [&](int j) {
                     return j < k ? Iz[j] : (j == k ? ik1v : suf[j - k - 1]);
                 });
@@ -446,7 +456,9 @@ __device__ void sweep_body(const ProbDev *__restrict__ P, int nk, int blk, int n
             }
             __syncthreads();
         } else {
-            const int st = (t - nnew) * (NT / 64) + wid;
+            // the wavefront index is uniform across the wavefront: saying so
+            // keeps the tile's descriptor reads and geometry scalar
+            const int st = (t - nnew) * (NT / 64) + __builtin_amdgcn_readfirstlane(wid);
             if (st < nst) {
                 int u = 0;
                 while (u + 1 < nk && st >= sh.soff[u + 1]) ++u;
