@@ -535,7 +535,9 @@ constexpr int NTC = 512;
 template <typename V, int FNS>
 __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int sweep)
 {
-    const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+    // the wavefront index is uniform across the wavefront: saying so keeps the
+    // per-unfolding descriptor reads scalar
+    const int tid = threadIdx.x, wid = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     constexpr int NW = NTC / 64;
     const int nk = P->nk, d = P->d, par = sweep & 1;
     __shared__ KSweep ks[TT_MAX_D];
@@ -565,7 +567,7 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
         if (P->rook) {
             // residuals the block searches looked at
             unsigned long long c = 0;
-            for (int i = lane; i < ntl; i += 64) c += K.bcnt[i];
+            for (int i = lane; i < ntl; i += 64) c += as_global((unsigned long long *)K.bcnt)[i];
             for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
             if (lane == 0) s_rcnt[u] = c;
         }
@@ -574,7 +576,10 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
 #pragma unroll
             for (int j = 0; j < CB; ++j) {
                 const int i = i0 + lane + 64 * j;
-                if (i < ntl) c[j] = K.cand[i];
+                if (i < ntl) {
+                    const gptr_t<const Cand> cp = as_global((const Cand *)K.cand) + i;
+                    c[j].v = cp->v; c[j].key = cp->key; c[j].sv = cp->sv;
+                }
                 else { c[j].v = -1.0; c[j].key = ~0ULL; c[j].sv = 0.0; }
             }
 #pragma unroll
@@ -609,24 +614,24 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
             const int p = row / K.nk, ik = row - p * K.nk;
             const int q = col / K.nk1, ik1 = col - q * K.nk1;
             if (lane == 0) {
-                K.rho[z] = row;
-                K.gam[z] = col;
-                K.piv[z] = bs;
-                K.piv64[z] = P->fp32 ? p64 : bs;
-                K.rpiv[row] = (uint8_t)(z + 1);
-                K.cpiv[col] = (uint8_t)(z + 1);
-                K.Ifull[z * k + k - 1] = ik;
-                K.Jfull[z * (d - k)] = ik1;
+                as_global((int *)K.rho)[z] = row;
+                as_global((int *)K.gam)[z] = col;
+                as_global((double *)K.piv)[z] = bs;
+                as_global((double *)K.piv64)[z] = P->fp32 ? p64 : bs;
+                as_global((uint8_t *)K.rpiv)[row] = (uint8_t)(z + 1);
+                as_global((uint8_t *)K.cpiv)[col] = (uint8_t)(z + 1);
+                as_global((int *)K.Ifull)[z * k + k - 1] = ik;
+                as_global((int *)K.Jfull)[z * (d - k)] = ik1;
             }
-            if (lane < k - 1) K.Ifull[z * k + lane] = P->kd[u - 1].Ifull[p * (k - 1) + lane];
-            if (lane < d - k - 1) K.Jfull[z * (d - k) + 1 + lane] = P->kd[u + 1].Jfull[q * (d - k - 1) + lane];
+            if (lane < k - 1) as_global((int *)K.Ifull)[z * k + lane] = as_global((const int *)P->kd[u - 1].Ifull)[p * (k - 1) + lane];
+            if (lane < d - k - 1) as_global((int *)K.Jfull)[z * (d - k) + 1 + lane] = as_global((const int *)P->kd[u + 1].Jfull)[q * (d - k - 1) + lane];
             if (P->fp32 && lane < z) {
-                K.Wp64[z * P->rcap + lane] = w64;
-                K.Up64[lane * P->rcap + z] = v64;
+                as_global((double *)K.Wp64)[z * P->rcap + lane] = w64;
+                as_global((double *)K.Up64)[lane * P->rcap + z] = v64;
             }
         }
         if (lane == 0) {
-            if (sweep < P->hist_cap) K.hist[sweep] = e;
+            if (sweep < P->hist_cap) as_global((double *)K.hist)[sweep] = e;
             S->last_best[u] = e;
             if (over && !propose) S->capped = 1;
             if (propose && bs == 0.0) S->err = TT_ESINGULAR;
