@@ -81,6 +81,12 @@ template <typename V> __host__ __device__ inline V vel(int i, int n, V vmax)
     return -vmax + ((V)i + (V)0.5) * ((V)2 * vmax / (V)n);
 }
 
+// Buffers reached through a descriptor are generic pointers to the compiler;
+// naming their address space lets it emit global instead of flat loads and
+// stores, which wait on the vector-memory counter alone.
+template <typename T> using gptr_t = __attribute__((address_space(1))) T *;
+template <typename T> __device__ inline gptr_t<T> as_global(T *p) { return (gptr_t<T>)p; }
+
 // The per-mode table in the arithmetic's precision.
 template <typename V> __host__ __device__ inline const V *fn_table(const FnDev &F);
 template <> __host__ __device__ inline const double *fn_table<double>(const FnDev &F) { return F.tab; }
@@ -97,7 +103,8 @@ template <> __host__ __device__ inline const float *fn_table<float>(const FnDev 
 // time, so a kernel built for one function carries no code of the others.
 // fn_value_tx reads the per-mode table through tb (a copy of it in LDS, or the
 // table itself); fn_value_ix reads the table in device memory.
-template <typename V, int FNS = 0, typename IX> __device__ inline V fn_value_tx(const FnDev &F, IX ix, const V *tb)
+template <typename V, int FNS = 0, typename IX, typename TP>
+__device__ inline V fn_value_tx(const FnDev &F, IX ix, TP tb)
 {
     // value t of index i of mode j
     auto atom = [&](int t, int j, int i) -> V { return tb[(int64_t)t * F.tab_ld + F.off[j] + i]; };
@@ -158,7 +165,7 @@ template <typename V, int FNS = 0, typename IX> __device__ inline V fn_value_tx(
 
 template <typename V, int FNS = 0, typename IX> __device__ inline V fn_value_ix(const FnDev &F, IX ix)
 {
-    return fn_value_tx<V, FNS>(F, ix, fn_table<V>(F));
+    return fn_value_tx<V, FNS>(F, ix, as_global(fn_table<V>(F)));
 }
 
 template <typename V, int FNS = 0> __device__ inline V fn_value(const FnDev &F, const int *idx)

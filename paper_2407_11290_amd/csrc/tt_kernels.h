@@ -63,11 +63,14 @@ template <> __device__ inline float vfma<float>(float a, float b, float c) { ret
 // strictly upper triangular index (zp < z)
 __device__ inline int tri(int zp, int z) { return z * (z - 1) / 2 + zp; }
 
-// Buffers reached through the problem descriptor are generic pointers to the
-// compiler; naming their address space lets it emit global instead of flat
-// loads and stores, which wait on the vector-memory counter alone.
-template <typename T> using gptr_t = __attribute__((address_space(1))) T *;
-template <typename T> __device__ inline gptr_t<T> as_global(T *p) { return (gptr_t<T>)p; }
+// Copy of a small struct of 32-bit words read through the global address space.
+template <typename T> __device__ inline void load_words(T &dst, const T *src)
+{
+    static_assert(sizeof(T) % 4 == 0, "word-sized struct");
+    const gptr_t<const int> w = as_global((const int *)src);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) ((int *)&dst)[i] = w[i];
+}
 
 // LDS bytes of a new-entry tile: factors of the tile rows and columns and the
 // two pivot-block triangles.
@@ -421,13 +424,13 @@ __device__ void sweep_body(const ProbDev *__restrict__ P, int nk, int blk, int n
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const ProbState *S = P->S;
-    if (S->stop) return;
+    if (as_global(&S->stop)[0]) return;
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
     __shared__ KSweep ks[TT_MAX_D];
     __shared__ SweepShape sh;
     // one round of loads: the shapes and tile counts the previous commit left
-    if (tid < nk) ks[tid] = S->ks[tid];
-    if (tid < SHAPE_WORDS) ((int *)&sh)[tid] = ((const int *)&S->sh)[tid];
+    if (tid < nk) load_words(ks[tid], &S->ks[tid]);
+    if (tid < SHAPE_WORDS) ((int *)&sh)[tid] = as_global((const int *)&S->sh)[tid];
     __syncthreads();
     const int nnew = sh.noff[nk], nst = sh.soff[nk];
     const int units = nnew + (nst + NT / 64 - 1) / (NT / 64);
@@ -451,8 +454,8 @@ __device__ void sweep_body(const ProbDev *__restrict__ P, int nk, int blk, int n
             const TileGeom g = tile_geom(K, u, R, C);
             new_tile<V, FNS>(P, K, ks[u], g, bv, bk, bs, (V *)smem_raw);
             if (tid == 0) {
-                Cand &c = K.cand[R * CT + C];
-                c.v = bv; c.key = bk; c.sv = bs;
+                const gptr_t<Cand> c = as_global(K.cand) + (R * CT + C);
+                c->v = bv; c->key = bk; c->sv = bs;
             }
             __syncthreads();
         } else {
@@ -471,8 +474,8 @@ __device__ void sweep_body(const ProbDev *__restrict__ P, int nk, int blk, int n
                 stored_tile_wave<V, 8>(K, ks[u], g, bv, bk, bs);
                 wave_best(bv, bk, bs);
                 if (lane == 0) {
-                    Cand &c = K.cand[R * sh.CT[u] + C];
-                    c.v = bv; c.key = bk; c.sv = bs;
+                    const gptr_t<Cand> c = as_global(K.cand) + (R * sh.CT[u] + C);
+                    c->v = bv; c->key = bk; c->sv = bs;
                 }
             }
         }
@@ -499,13 +502,13 @@ __device__ inline double fp64_check_wave(const ProbDev *P, const KDev &K, int u,
     const int nk = K.nk, nk1 = K.nk1;
     const int p = row / nk, q = col / nk1, ik = row - p * nk, ik1 = col - q * nk1;
     const int npre = k - 1, nsuf = d - k - 1, nj = d - k;
-    const int *preI = (k >= 2) ? P->kd[u - 1].Ifull + p * npre : nullptr;
-    const int *sufJ = (nsuf > 0) ? P->kd[u + 1].Jfull + q * nsuf : nullptr;
+    const gptr_t<const int> preI = as_global((const int *)((k >= 2) ? P->kd[u - 1].Ifull + p * npre : nullptr));
+    const gptr_t<const int> sufJ = as_global((const int *)((nsuf > 0) ? P->kd[u + 1].Jfull + q * nsuf : nullptr));
     w = 0.0;
     v = 0.0;
     if (lane < rk) {
-        const int *Jz = K.Jfull + lane * nj;
-        const int *Iz = K.Ifull + lane * k;
+        const gptr_t<const int> Jz = as_global((const int *)K.Jfull) + lane * nj;
+        const gptr_t<const int> Iz = as_global((const int *)K.Ifull) + lane * k;
         w = fn_value_ix<double, FNS>(P->F, [&](int j) { return j < npre ? preI[j] : (j == k - 1 ? ik : Jz[j - k]); });
         v = fn_value_ix<double, FNS>(P->F, [&](int j) { return j < k ? Iz[j] : (j == k ? ik1 : sufJ[j - k - 1]); });
     }
@@ -515,13 +518,13 @@ __device__ inline double fp64_check_wave(const ProbDev *P, const KDev &K, int u,
     const int rc = P->rcap;
     for (int zp = 0; zp + 1 < rk; ++zp) {
         const double wzp = __shfl(w, zp, 64);
-        const double uu = __shfl(v, zp, 64) / K.piv64[zp];
+        const double uu = __shfl(v, zp, 64) / as_global((const double *)K.piv64)[zp];
         if (lane > zp && lane < rk) {
-            w = __fma_rn(-wzp, K.Up64[zp * rc + lane], w);
-            v = __fma_rn(-K.Wp64[lane * rc + zp], uu, v);
+            w = __fma_rn(-wzp, as_global((const double *)K.Up64)[zp * rc + lane], w);
+            v = __fma_rn(-as_global((const double *)K.Wp64)[lane * rc + zp], uu, v);
         }
     }
-    if (lane < rk) v = v / K.piv64[lane];
+    if (lane < rk) v = v / as_global((const double *)K.piv64)[lane];
     double x = xrc;
     for (int z = 0; z < rk; ++z) x = __fma_rn(-__shfl(w, z, 64), __shfl(v, z, 64), x);
     return x;
@@ -1620,7 +1623,7 @@ __device__ void cores_body(const ProbDev *__restrict__ P, const CoreArgs &a, dou
         const int64_t e = (int64_t)(bid - a.rowblocks[a.nk]) * A4W + lane;
         if (e >= (int64_t)rd * nd) return;
         const int pp = (int)(e / nd), i = (int)(e - (int64_t)pp * nd);
-        const int *Ip = K.Ifull + pp * (d - 1);
+        const gptr_t<const int> Ip = as_global((const int *)K.Ifull) + pp * (d - 1);
         G[a.goff[d - 1] + e] = fn_value_ix<double, FNS>(P->F, [&](int j) { return j < d - 1 ? Ip[j] : i; });
         return;
     }
@@ -1638,10 +1641,11 @@ __device__ void cores_body(const ProbDev *__restrict__ P, const CoreArgs &a, dou
     const int p = act ? i / K.nk : 0, ik = act ? i - p * K.nk : 0;
     // one round of loads: the pivots' index tuples and every lane's prefix
     __shared__ int sJ[TT_MAX_RANK * TT_MAX_D], sI[TT_MAX_RANK * TT_MAX_D], sPre[A4W * TT_MAX_D];
-    for (int e = lane; e < rk * nj; e += A4W) sJ[e] = K.Jfull[e];
-    for (int e = lane; e < rk * k; e += A4W) sI[e] = K.Ifull[e];
+    const gptr_t<const int> Jf = as_global((const int *)K.Jfull), If = as_global((const int *)K.Ifull);
+    for (int e = lane; e < rk * nj; e += A4W) sJ[e] = Jf[e];
+    for (int e = lane; e < rk * k; e += A4W) sI[e] = If[e];
     if (k >= 2) {
-        const int *preI = P->kd[u - 1].Ifull + p * (k - 1);
+        const gptr_t<const int> preI = as_global((const int *)P->kd[u - 1].Ifull) + p * (k - 1);
         for (int j = 0; j < k - 1; ++j) sPre[lane * TT_MAX_D + j] = preI[j];
     }
     wave_sync();
