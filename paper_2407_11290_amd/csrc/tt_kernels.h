@@ -970,8 +970,8 @@ __device__ inline double rook_entry(const ProbDev *__restrict__ P, int u, int ro
     const int k = u + 1, d = P->d;
     const int p = row / K.nk, ik = row - p * K.nk;
     const int q = col / K.nk1, ik1 = col - q * K.nk1;
-    const int *Ip = (k > 1) ? P->kd[u - 1].Ifull + p * (k - 1) : nullptr;
-    const int *Jq = (k < d - 1) ? P->kd[u + 1].Jfull + q * (d - k - 1) : nullptr;
+    const gptr_t<const int> Ip = as_global((const int *)((k > 1) ? P->kd[u - 1].Ifull + p * (k - 1) : nullptr));
+    const gptr_t<const int> Jq = as_global((const int *)((k < d - 1) ? P->kd[u + 1].Jfull + q * (d - k - 1) : nullptr));
     return fn_value_ix<double, FNS>(P->F, [&](int j) {
         return j < k - 1 ? Ip[j] : (j == k - 1 ? ik : (j == k ? ik1 : Jq[j - k - 1]));
     });
@@ -1004,12 +1004,12 @@ __device__ void rook_factor_body(const ProbDev *__restrict__ P, int nk, int blk,
         const KDev &K = P->kd[u];
         const KSweep &s = ks[u];
         const int e = t - off[u], rk = s.rk, wp = K.rk_cap;
-        double *W = K.Wf, *U = K.Uf;
+        const gptr_t<double> W = as_global(K.Wf), U = as_global(K.Uf);
         if (e < s.nr) {
             const int i = e;
             const int z0 = (i < s.nr_st) ? (s.apply ? rk - 1 : rk) : 0;
             for (int z = z0; z < rk; ++z) {
-                const int gz = K.gam[z];
+                const int gz = as_global((const int *)K.gam)[z];
                 double x = rook_entry<FNS>(P, u, i, gz);
                 for (int zp = 0; zp < z; ++zp) x = __fma_rn(-W[(int64_t)i * wp + zp], U[(int64_t)gz * wp + zp], x);
                 W[(int64_t)i * wp + z] = x;
@@ -1018,10 +1018,10 @@ __device__ void rook_factor_body(const ProbDev *__restrict__ P, int nk, int blk,
             const int j = e - s.nr;
             const int z0 = (j < s.nc_st) ? (s.apply ? rk - 1 : rk) : 0;
             for (int z = z0; z < rk; ++z) {
-                const int rz = K.rho[z];
+                const int rz = as_global((const int *)K.rho)[z];
                 double x = rook_entry<FNS>(P, u, rz, j);
                 for (int zp = 0; zp < z; ++zp) x = __fma_rn(-W[(int64_t)rz * wp + zp], U[(int64_t)j * wp + zp], x);
-                U[(int64_t)j * wp + z] = x / K.piv[z];
+                U[(int64_t)j * wp + z] = x / as_global((const double *)K.piv)[z];
             }
         }
     }
@@ -1086,14 +1086,14 @@ __device__ inline void rook_block_geom(const ProbDev *__restrict__ P, int u, int
     for (int p = 0; p < rp; ++p) {
         bool ok = true;
         for (int j = 0; j < k - 1 && ok; ++j)
-            ok = grid_piece(P->kd[u - 1].Ifull[p * (k - 1) + j], P->F.n[j], P->grid[j]) == c[j];
+            ok = grid_piece(as_global((const int *)P->kd[u - 1].Ifull)[p * (k - 1) + j], P->F.n[j], P->grid[j]) == c[j];
         if (ok) pref[np++] = p;
     }
     int nq = 0;
     for (int q = 0; q < rq; ++q) {
         bool ok = true;
         for (int j = 0; j < d - k - 1 && ok; ++j)
-            ok = grid_piece(P->kd[u + 1].Jfull[q * (d - k - 1) + j], P->F.n[k + 1 + j], P->grid[k + 1 + j]) ==
+            ok = grid_piece(as_global((const int *)P->kd[u + 1].Jfull)[q * (d - k - 1) + j], P->F.n[k + 1 + j], P->grid[k + 1 + j]) ==
                  c[k + 1 + j];
         if (ok) suf[nq++] = q;
     }
@@ -1109,9 +1109,9 @@ __device__ inline void rook_block_geom(const ProbDev *__restrict__ P, int u, int
 // in pivot order.  Wrow: W(row, :); Ucol: U(:, col) (stride us).  Both
 // factors are stored as contiguous vectors of rk_cap values per row (W) and
 // per column (U), so a residual at a random position reads two short runs.
-template <int FNS>
-__device__ inline double rook_residual(const ProbDev *__restrict__ P, int u, int row, int col, const double *Wrow,
-                                       const double *Ucol, int64_t us, int rk)
+template <int FNS, typename TW, typename TU>
+__device__ inline double rook_residual(const ProbDev *__restrict__ P, int u, int row, int col, TW Wrow, TU Ucol,
+                                       int64_t us, int rk)
 {
     double x = rook_entry<FNS>(P, u, row, col);
     for (int z = 0; z < rk; ++z) x = __fma_rn(-Wrow[z], Ucol[(int64_t)z * us], x);
@@ -1145,7 +1145,7 @@ __device__ void rook_search_body(const ProbDev *__restrict__ P, int nk, int swee
     const int len = s_g.len, len1 = s_g.len1, lo = s_g.lo, lo1 = s_g.lo1;
     const int nR = s_g.np * len, nC = s_g.nq * len1;
     const int rk = ks.rk, wp = K.rk_cap;
-    const double *W = K.Wf, *U = K.Uf;
+    const gptr_t<const double> W = as_global((const double *)K.Wf), U = as_global((const double *)K.Uf);
     auto rowpos = [&](int t) { return s_pref[t / len] * K.nk + lo + t % len; };
     auto colpos = [&](int t) { return s_suf[t / len1] * K.nk1 + lo1 + t % len1; };
     double bv = -1.0, bs = 0.0;
@@ -1284,7 +1284,8 @@ __device__ void rook_wsample_body(const ProbDev *__restrict__ P, int nk, int swe
             const int row = rowpos((int)(ra % (uint64_t)nR)), col = colpos((int)(ca % (uint64_t)nC));
             if (K.rpiv[row] || K.cpiv[col]) continue;
             ++cnt;
-            const double x = rook_residual<FNS>(P, u, row, col, K.Wf + (int64_t)row * wp, K.Uf + (int64_t)col * wp, 1, rk);
+            const double x = rook_residual<FNS>(P, u, row, col, as_global((const double *)K.Wf) + (int64_t)row * wp,
+                                                as_global((const double *)K.Uf) + (int64_t)col * wp, 1, rk);
             const uint64_t key = ((uint64_t)row << 32) | (uint32_t)col;
             if (better(fabs(x), key, bv, bk)) { bv = fabs(x); bk = key; bs = x; }
         }
@@ -1351,7 +1352,7 @@ __device__ void rook_wstep_body(const ProbDev *__restrict__ P, int nk, int p, in
     const int len = s_g.len, len1 = s_g.len1, lo = s_g.lo, lo1 = s_g.lo1;
     const int nR = s_g.np * len, nC = s_g.nq * len1;
     const int rk = ks.rk, wp = K.rk_cap;
-    const double *W = K.Wf, *U = K.Uf;
+    const gptr_t<const double> W = as_global((const double *)K.Wf), U = as_global((const double *)K.Uf);
     auto rowpos = [&](int t) { return s_pref[t / len] * K.nk + lo + t % len; };
     auto colpos = [&](int t) { return s_suf[t / len1] * K.nk1 + lo1 + t % len1; };
     unsigned long long cnt = 0;
