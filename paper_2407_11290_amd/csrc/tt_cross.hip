@@ -469,6 +469,17 @@ int Problem::allocate()
     if ((st = dalloc((void **)&H.S, sizeof(ProbState))) != TT_OK) return st;
     HIPCHK(hipHostMalloc((void **)&hm, sizeof(HostMirror), hipHostMallocMapped | hipHostMallocCoherent));
     HIPCHK(hipHostGetDevicePointer((void **)&H.hm, hm, 0));
+    // the first sweep searches the initial superblocks (one prefix, one
+    // suffix, every tile stored): its tile counts are fixed by the geometry
+    std::memset(&H.sh0, 0, sizeof H.sh0);
+    for (int u = 0, acc = 0; u < d - 1; ++u) {
+        const KDev &K = H.kd[u];
+        H.sh0.RT[u] = H.sh0.RTs[u] = K.RTp;
+        H.sh0.CT[u] = H.sh0.CTs[u] = K.CTq;
+        H.sh0.soff[u] = acc;
+        acc += K.RTp * K.CTq;
+        H.sh0.soff[u + 1] = acc;
+    }
     if ((st = dalloc((void **)&dP, sizeof(ProbDev))) != TT_OK) return st;
     HIPCHK(hipMemcpy(dP, &H, sizeof(ProbDev), hipMemcpyHostToDevice));
     allocated = true;

@@ -312,6 +312,7 @@ struct ProbDev {
     ProbState *S;
     HostMirror *hm;               // device alias of the host mirror
     RunDev run;
+    SweepShape sh0;               // tile counts of the first sweep (every tile stored)
 };
 
 struct SweepArgs {

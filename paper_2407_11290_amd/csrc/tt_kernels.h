@@ -384,37 +384,7 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSw
     block_best(bv, bk, bs);
 }
 
-// Tile counts of the sweep that ks describes (see SweepShape).
-__device__ inline void sweep_shape(const ProbDev *P, const KSweep *ks, int nk, SweepShape &sh)
-{
-    int nn = 0, ns = 0;
-    for (int u = 0; u < nk; ++u) {
-        const KDev &K = P->kd[u];
-        sh.RT[u] = (ks[u].nr / K.nk) * K.RTp;
-        sh.CT[u] = (ks[u].nc / K.nk1) * K.CTq;
-        sh.RTs[u] = (ks[u].nr_st / K.nk) * K.RTp;
-        sh.CTs[u] = (ks[u].nc_st / K.nk1) * K.CTq;
-        sh.noff[u] = nn;
-        sh.soff[u] = ns;
-        nn += sh.RT[u] * sh.CT[u] - sh.RTs[u] * sh.CTs[u];
-        ns += sh.RTs[u] * sh.CTs[u];
-    }
-    sh.noff[nk] = nn;
-    sh.soff[nk] = ns;
-}
 
-// Workgroup-wide: tile counts of the sweep that ks (in LDS, complete for all
-// threads after the first barrier) describes, stored beside ks in S so that
-// every search workgroup loads both in one round.  The commit computes the
-// same counts lane-parallel.
-__device__ inline void publish_shape(const ProbDev *P, const KSweep *ks, int nk, ProbState *S)
-{
-    __shared__ SweepShape s_sh;
-    __syncthreads();
-    if (threadIdx.x == 0) sweep_shape(P, ks, nk, s_sh);
-    __syncthreads();
-    for (int t = threadIdx.x; t < SHAPE_WORDS; t += blockDim.x) ((int *)&S->sh)[t] = ((const int *)&s_sh)[t];
-}
 
 
 // Fixed grid striding over work units: first the new-entry tiles (one per
@@ -551,8 +521,13 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
     __shared__ int s_stop;
     __shared__ double s_tau;
     __shared__ unsigned long long s_acc[3];
-    // one round of loads: stop flag, shapes, ranks, threshold, counters
-    if (tid < nk) ks[tid] = S->ks[tid];
+    // one round of loads: stop flag, shapes, tile counts, ranks, threshold,
+    // counters
+    __shared__ int s_ntl[TT_MAX_D];
+    if (tid < nk) {
+        ks[tid] = S->ks[tid];
+        s_ntl[tid] = S->sh.RT[tid] * S->sh.CT[tid];     // tiles this sweep searched
+    }
     if (tid <= d) s_rold[tid] = S->r[par][tid];
     if (tid == NTC - 1) { s_stop = S->stop; s_tau = S->tau; }
     if (tid == NTC - 2) { s_acc[0] = S->alg_bytes; s_acc[1] = S->new_entries; s_acc[2] = S->pivoted; }
@@ -564,7 +539,7 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
     __shared__ unsigned long long s_rcnt[TT_MAX_D];
     for (int u = wid; u < nk; u += NW) {
         const KDev &K = P->kd[u];
-        const int ntl = P->rook ? K.nrb * K.ncb : ((ks[u].nr / K.nk) * K.RTp) * ((ks[u].nc / K.nk1) * K.CTq);
+        const int ntl = P->rook ? K.nrb * K.ncb : s_ntl[u];
         double bv = -1.0, bs = 0.0;
         uint64_t bk = ~0ULL;
         if (P->rook) {
@@ -574,16 +549,18 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
             for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
             if (lane == 0) s_rcnt[u] = c;
         }
+        const gptr_t<const Cand> cand = as_global((const Cand *)K.cand);
         for (int i0 = 0; i0 < ntl; i0 += 64 * CB) {
             Cand c[CB];
 #pragma unroll
             for (int j = 0; j < CB; ++j) {
                 const int i = i0 + lane + 64 * j;
                 if (i < ntl) {
-                    const gptr_t<const Cand> cp = as_global((const Cand *)K.cand) + i;
+                    const gptr_t<const Cand> cp = cand + i;
                     c[j].v = cp->v; c[j].key = cp->key; c[j].sv = cp->sv;
+                } else {
+                    c[j].v = -1.0; c[j].key = ~0ULL; c[j].sv = 0.0;
                 }
-                else { c[j].v = -1.0; c[j].key = ~0ULL; c[j].sv = 0.0; }
             }
 #pragma unroll
             for (int j = 0; j < CB; ++j)
@@ -905,7 +882,6 @@ __device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns,
         __threadfence_system();
     }
     __syncthreads();
-    __shared__ KSweep s_ks[TT_MAX_D];
     for (int u = 0; u < P->nk; ++u) {
         const KDev &K = P->kd[u];
         const int k = u + 1;
@@ -927,10 +903,9 @@ __device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns,
             ks.agam = i0[k];
             ks.apiv = p0s;
             S->ks[u] = ks;
-            s_ks[u] = ks;
         }
     }
-    publish_shape(P, s_ks, P->nk, S);
+    for (int t = tid; t < SHAPE_WORDS; t += NT) ((int *)&S->sh)[t] = ((const int *)&P->sh0)[t];
 }
 
 template <typename V, int FNS = 0>
