@@ -856,7 +856,7 @@ __device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns,
     __shared__ double wsum[NT / 64];
     if ((tid & 63) == 0) wsum[tid >> 6] = q;
     __shared__ int i0[TT_MAX_D];
-    __shared__ double p0s;
+    __shared__ double p0s, p64;
     __syncthreads();
     if (tid == 0) {
         const double ss = __dadd_rn(__dadd_rn(wsum[0], wsum[1]), __dadd_rn(wsum[2], wsum[3]));
@@ -873,13 +873,9 @@ __device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns,
         S->alg_bytes = 0; S->new_entries = 0;
         S->err = sbad ? TT_EFN : 0;
         p0s = (double)fn_value<V, FNS>(P->F, i0);
+        p64 = (double)fn_value<double, FNS>(P->F, i0);
         if (p0s == 0.0) S->err = TT_ESINGULAR;
         if (S->err) S->stop = 1;
-        HostMirror *hm = P->hm;
-        for (int j = 0; j <= d; ++j) hm->r[j] = 1;
-        hm->err = S->err;
-        hm->stop = S->stop;
-        __threadfence_system();
     }
     __syncthreads();
     for (int u = 0; u < P->nk; ++u) {
@@ -891,7 +887,7 @@ __device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns,
             K.rho[0] = i0[k - 1];
             K.gam[0] = i0[k];
             K.piv[0] = p0s;
-            K.piv64[0] = (double)fn_value<double, FNS>(P->F, i0);
+            K.piv64[0] = p64;
             K.rpiv[i0[k - 1]] = 1;
             K.cpiv[i0[k]] = 1;
             KSweep ks;
@@ -906,6 +902,13 @@ __device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns,
         }
     }
     for (int t = tid; t < SHAPE_WORDS; t += NT) ((int *)&S->sh)[t] = ((const int *)&P->sh0)[t];
+    if (tid == 0) {
+        HostMirror *hm = P->hm;
+        for (int j = 0; j <= d; ++j) hm->r[j] = 1;
+        hm->err = S->err;
+        hm->stop = S->stop;
+        __threadfence_system();
+    }
 }
 
 template <typename V, int FNS = 0>
