@@ -132,3 +132,26 @@ def test_server_escalates_like_a_single_solve():
     assert np.array_equal(cores.view(np.uint64), g.cores_flat().view(np.uint64))
     srv.close()
 
+
+
+def test_pooled_problem_switches_functions():
+    """One pooled problem object serves, in turn, a Hilbert request and
+    bi-Maxwellians with different parameters (whose per-mode tables are
+    uploaded into the object's buffers); each result equals its single solve."""
+    n = [16] * 4
+    seq = [(FN_HILBERT, [0.5]), (FN_BIMAXWELL, _bimax(3)), (FN_HILBERT, [1.25]), (FN_BIMAXWELL, _bimax(4)),
+           (FN_BIMAXWELL, _bimax(3))]
+    srv = Server(8 << 30, max_slots=1)
+    for i, (fn, params) in enumerate(seq):
+        r = dict(n=n, eps=1e-8, fn=fn, params=params, seed=70 + i)
+        _say("switch", i, fn)
+        t = srv.submit(r["n"], r["eps"], r["fn"], r["params"], seed=r["seed"])
+        st, _ = srv.wait(t)
+        assert st >= 0
+        s, cores = srv.result(t)
+        st1, s1, c1 = _single(r)
+        assert s["status"] == st1 and s["ranks"] == s1["ranks"] and s["pivoted"] == s1["pivoted"]
+        assert np.array_equal(cores.view(np.uint64), c1.view(np.uint64))
+        srv.release(t)
+    assert srv.stats()["allocations"] == 1
+    srv.close()
