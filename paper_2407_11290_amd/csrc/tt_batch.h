@@ -58,6 +58,8 @@ private:
     std::vector<Slot> slots;
     std::vector<hipEvent_t> ev_free;
     ProbDev *dPa = nullptr, *hPa = nullptr;   // descriptors: device array, pinned staging
+    std::vector<ProbDev> shadow;              // what dPa holds per slot (valid where shadow_ok)
+    std::vector<char> shadow_ok;
     ProbState *dS = nullptr, *hS = nullptr;   // per-slot device state and its host copy (mapped)
     ProbState *dhS = nullptr;                 // device view of hS
     HostMirror *hm = nullptr, *dhm = nullptr; // mapped host mirrors (host / device view)

@@ -50,6 +50,8 @@ void Engine::release()
     if (hPart) (void)hipHostFree(hPart);
     dPa = nullptr; dS = nullptr; hPa = nullptr; hS = nullptr; dhS = nullptr; hm = nullptr; dhm = nullptr;
     dPart = nullptr; hPart = nullptr;
+    shadow.clear();
+    shadow_ok.clear();
     slots.clear();
     cap = 0;
 }
@@ -61,6 +63,8 @@ int Engine::init(int capacity, hipStream_t s)
     stream = s;
     cap = capacity;
     HIPCHK(hipMalloc(&dPa, sizeof(ProbDev) * cap));
+    shadow.assign(cap, ProbDev{});
+    shadow_ok.assign(cap, 0);
     HIPCHK(hipMalloc(&dS, sizeof(ProbState) * cap));
     HIPCHK(hipHostMalloc((void **)&hPa, sizeof(ProbDev) * cap, hipHostMallocDefault));
     // finished states and check partials are written by kernels straight
@@ -149,8 +153,17 @@ int Engine::copy_slots(void *dst, const void *src, size_t elem, const std::vecto
 // Launch setup for every slot admitted since the last call.
 template <typename V> int Engine::launch_setup(std::vector<int> &ids)
 {
-    int cst = copy_slots(dPa, hPa, sizeof(ProbDev), ids, hipMemcpyHostToDevice);
+    // only descriptors that differ from what the device array already holds
+    // are copied: a batch of the same problems run again copies none
+    std::vector<int> changed;
+    for (int i : ids)
+        if (!shadow_ok[i] || std::memcmp(&shadow[i], &hPa[i], sizeof(ProbDev)) != 0) changed.push_back(i);
+    int cst = copy_slots(dPa, hPa, sizeof(ProbDev), changed, hipMemcpyHostToDevice);
     if (cst) return cst;
+    for (int i : changed) {
+        shadow[i] = hPa[i];
+        shadow_ok[i] = 1;
+    }
     for (size_t c0 = 0; c0 < ids.size(); c0 += MAXB) {
         const int na = (int)std::min<size_t>(MAXB, ids.size() - c0);
         BatchMap bm;
