@@ -214,10 +214,15 @@ def batch_run(problems, stream=None):
     problems = list(problems)
     arr = (C.c_void_p * len(problems))(*[p.h for p in problems])
     s = None if stream is None else C.c_void_p(getattr(stream, "cuda_stream", stream))
-    check(load().tt_batch_run(arr, len(problems), s))
+    L = load()
+    check(L.tt_batch_run(arr, len(problems), s))
+    # the statuses only (a full stats() dictionary per problem would cost
+    # more host time than a small batch's GPU work)
+    st = Stats()
     out = []
     for p in problems:
-        p.status = p.stats()["status"]
+        check(L.tt_cross_get_stats(p.h, C.byref(st)))
+        p.status = st.status
         out.append(p.status)
     return out
 
