@@ -390,17 +390,19 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSw
 // Fixed grid striding over work units: first the new-entry tiles (one per
 // workgroup), then the stored tiles four at a time (one per wavefront).
 template <typename V, int FNS>
-__device__ void sweep_body(const ProbDev *__restrict__ P, int nk, int blk, int nblk)
+__device__ void sweep_body(const ProbDev *__restrict__ P, const ProbState *S, int nk, int blk, int nblk)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const ProbState *S = P->S;
-    if (as_global(&S->stop)[0]) return;
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
     __shared__ KSweep ks[TT_MAX_D];
     __shared__ SweepShape sh;
-    // one round of loads: the shapes and tile counts the previous commit left
+    // one round of loads: the stop flag, and the shapes and tile counts the
+    // previous commit left (read before the flag is known, so that all of
+    // them are in flight together)
+    const int stop = as_global(&S->stop)[0];
     if (tid < nk) load_words(ks[tid], &S->ks[tid]);
     if (tid < SHAPE_WORDS) ((int *)&sh)[tid] = as_global((const int *)&S->sh)[tid];
+    if (stop) return;                   // the same value in every thread
     __syncthreads();
     const int nnew = sh.noff[nk], nst = sh.soff[nk];
     const int units = nnew + (nst + NT / 64 - 1) / (NT / 64);
@@ -455,7 +457,7 @@ __device__ void sweep_body(const ProbDev *__restrict__ P, int nk, int blk, int n
 template <typename V, int FNS = 0>
 static __global__ void __launch_bounds__(NT) k_sweep(const ProbDev *__restrict__ P, SweepArgs a)
 {
-    sweep_body<V, FNS>(P, a.nk, blockIdx.x, gridDim.x);
+    sweep_body<V, FNS>(P, a.S, a.nk, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -506,13 +508,13 @@ __device__ inline double fp64_check_wave(const ProbDev *P, const KDev &K, int u,
 constexpr int NTC = 512;
 
 template <typename V, int FNS>
-__device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int sweep)
+__device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int sweep, int nk)
 {
     // the wavefront index is uniform across the wavefront: saying so keeps the
     // per-unfolding descriptor reads scalar
     const int tid = threadIdx.x, wid = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     constexpr int NW = NTC / 64;
-    const int nk = P->nk, d = P->d, par = sweep & 1;
+    const int d = nk + 1, par = sweep & 1;    // nk from the launch: no dependent read
     __shared__ KSweep ks[TT_MAX_D];
     __shared__ double s_wv[TT_MAX_D], s_wsv[TT_MAX_D];
     __shared__ uint64_t s_wk[TT_MAX_D];
@@ -719,7 +721,7 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
 template <typename V, int FNS = 0>
 static __global__ void __launch_bounds__(NTC) k_commit(const ProbDev *__restrict__ P, SweepArgs a)
 {
-    commit_body<V, FNS>(P, a.S, a.sweep);
+    commit_body<V, FNS>(P, a.S, a.sweep, a.nk);
 }
 
 // ---------------------------------------------------------------------------
@@ -1846,14 +1848,14 @@ static __global__ void __launch_bounds__(NT) k_sweep_b(const ProbDev *__restrict
 {
     const int i = batch_find(bm, blockIdx.x);
     const ProbDev *P = Pa + bm.p[i];
-    sweep_body<V, 0>(P, P->nk, blockIdx.x - bm.boff[i], bm.boff[i + 1] - bm.boff[i]);
+    sweep_body<V, 0>(P, P->S, P->nk, blockIdx.x - bm.boff[i], bm.boff[i + 1] - bm.boff[i]);
 }
 
 template <typename V>
 static __global__ void __launch_bounds__(NTC) k_commit_b(const ProbDev *__restrict__ Pa, BatchMap bm)
 {
     const ProbDev *P = Pa + bm.p[blockIdx.x];
-    commit_body<V, 0>(P, P->S, P->S->sweeps);
+    commit_body<V, 0>(P, P->S, P->S->sweeps, P->nk);
 }
 
 // Cores of every problem from its final ranks (those of its last commit).
