@@ -375,3 +375,17 @@ def test_default_tall_tiles_bit_exact():
     assert gs == os_ == NOT_CONVERGED
     _assert_same_pivots(g, o)
     assert np.array_equal(g.cores_flat(), o.cores_flat())
+
+
+@pytest.mark.parametrize("fn_id,n", [(FN_MAXWELL, [4096] * 6), (FN_MAXWELL_3D3V, [3000, 1500, 3000, 1500, 3000, 1500])])
+def test_fn_values_with_tables_too_large_for_lds(fn_id, n):
+    """Per-mode tables above the bulk evaluation's LDS limit are read from
+    device memory; the values are the same as through LDS."""
+    rng = np.random.default_rng(9)
+    idx = np.stack([rng.integers(0, m, 20000) for m in n], axis=1).astype(np.int32)
+    _say("large tables", fn_id, n)
+    a = gpu_fn_eval(fn_id, n, idx)
+    b = orc_fn_eval(fn_id, n, idx)
+    assert np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)) < 1e-15
+    a32 = gpu_fn_eval(fn_id, n, idx, fp32=True)
+    assert np.max(np.abs(a32.astype(np.float64) - b)) <= 2e-6 * np.max(np.abs(b))
