@@ -37,6 +37,7 @@ def lib():
         L.orc_get_pivots.argtypes = [P, C.c_int, P, P, P, P, P]
         L.orc_get_stats.argtypes = [P, f64p, i32p]
         L.orc_get_history.argtypes = [P, C.c_int, f64p, C.c_int]
+        L.orc_get_rook_rounds.argtypes = [P]
         L.orc_get_cores.restype = C.c_int64
         L.orc_get_cores.argtypes = [P, P, C.c_int64]
         L.orc_state_tt_eval.argtypes = [P, C.c_int64, i32p, f64p]
@@ -123,10 +124,11 @@ def tt_eval(n, ranks, cores, idx):
 class Oracle:
     """One TT-cross problem solved by the FP64 CPU oracle: greedy full search
     (default) or, with pivot="rook", Alg. 1 inside every subtensor block of
-    `grid` (blocks per mode) with at most rook_iters rounds."""
+    `grid` (blocks per mode), its loop run until neither step moves
+    (rook_iters = 0) or, as a test option, for at most rook_iters rounds."""
 
     def __init__(self, n, eps, fn_id, params=None, seed=0, r_max=64, n_samples=16384, pivot="greedy",
-                 grid=None, rook_iters=8, rank_caps=None):
+                 grid=None, rook_iters=0, rank_caps=None):
         self._seed = int(seed)
         self.n = np.ascontiguousarray(n, dtype=np.int32)
         self.d = int(self.n.size)
@@ -182,6 +184,10 @@ class Oracle:
         lib().orc_get_stats(self.h, out, i0)
         return {"rms": out[0], "tau": out[1], "evaluated": int(out[2]), "pivoted": int(out[3]),
                 "sweeps": int(out[4]), "min_rel_gap": out[5], "status": int(out[6]), "i0": i0}
+
+    def rook_rounds(self):
+        """Most rounds of Alg. 1's loop any block search took (rook mode)."""
+        return int(lib().orc_get_rook_rounds(self.h))
 
     def history(self, k):
         cap = 4096

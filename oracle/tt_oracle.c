@@ -59,8 +59,11 @@
  *     the start is the block's first row and first column without a pivot;
  *   - the loop of Alg. 1: a column step (largest |residual| in the current
  *     column) then a row step (in the current row), each taken only if it is
- *     strictly larger, until neither step moves or after max_iters rounds;
- *     among equal values the lowest position wins, as in the greedy search;
+ *     strictly larger, until neither step moves.  Every move strictly raises
+ *     |residual| over a finite set, so the loop ends by itself (a row once
+ *     left by a row step is never entered again, so there are at most
+ *     |rows| + 1 rounds); a cap on the rounds is a test option only.  Among
+ *     equal values the lowest position wins, as in the greedy search;
  *   - the pivoted count adds one per residual the search looks at (each
  *     sample kept, each row or column entry scanned).
  *
@@ -321,7 +324,8 @@ typedef struct orc_state {
     int ran;
     double *cores;                   /* G_1..G_d concatenated */
     int64_t cores_len;
-    int rook, rook_iters;            /* rook mode: Alg. 1 inside every block */
+    int rook, rook_iters;            /* rook mode: Alg. 1 inside every block; rook_iters = 0: no cap */
+    int rook_max_rounds;             /* most rounds any block's walk took */
     int kcap[ORC_MAX_D + 1];         /* rank cap per unfolding (prescribed ranks), <= r_max */
     int grid[ORC_MAX_D];             /* subtensor blocks per mode (rook mode) */
 } orc_state;
@@ -358,7 +362,7 @@ orc_state *orc_create(int d, const int *n, double eps, int fn_id, const double *
     for (int j = 0; j < d; ++j) S->F.n[j] = n[j];
     S->hist_cap = (d - 1) * r_max + 2;
     S->rook = 0;
-    S->rook_iters = 8;
+    S->rook_iters = 0;
     for (int k = 0; k <= ORC_MAX_D; ++k) S->kcap[k] = r_max;
     for (int j = 0; j < ORC_MAX_D; ++j) S->grid[j] = 1;
     for (int k = 1; k <= d - 1; ++k) {
@@ -391,11 +395,12 @@ static void orc_entry_index(const orc_state *S, int k, int64_t row, int64_t col,
     for (int j = 0; j < sl; ++j) idx[k + 1 + j] = S->J[k + 1][q * sl + j];
 }
 
-/* Rook mode on: grid[j] blocks per mode (clamped to [1, n_j]; NULL = 1),
- * at most max_iters rounds of column and row steps per block. */
+/* Rook mode on: grid[j] blocks per mode (clamped to [1, n_j]; NULL = 1).
+ * max_iters = 0 runs Alg. 1's loop until neither step moves (the method);
+ * max_iters > 0 stops a walk after that many rounds (a test option). */
 int orc_set_rook(orc_state *S, const int *grid, int max_iters)
 {
-    if (!S || max_iters < 1) return ORC_EINVAL;
+    if (!S || max_iters < 0) return ORC_EINVAL;
     S->rook = 1;
     S->rook_iters = max_iters;
     for (int j = 0; j < S->d; ++j) {
@@ -514,8 +519,9 @@ static int orc_rook_search(orc_state *S, int k, const int *rs, const double *E, 
                 ++count;
             }
             /* column step, row step, while either finds a strictly larger entry */
-            for (int it = 0; it < S->rook_iters; ++it) {
+            for (int it = 0; S->rook_iters == 0 || it < S->rook_iters; ++it) {
                 int moved = 0;
+                if (it + 1 > S->rook_max_rounds) S->rook_max_rounds = it + 1;
                 int64_t ti = -1;
                 double tv = -1.0;
                 for (int64_t t = 0; t < nR; ++t) {
@@ -837,6 +843,14 @@ int orc_get_stats(const orc_state *S, double *out, int *i0)
     out[4] = S->sweeps; out[5] = S->min_rel_gap; out[6] = S->status;
     if (i0) for (int j = 0; j < S->d; ++j) i0[j] = S->i0[j];
     return ORC_OK;
+}
+
+/* Most rounds of Alg. 1's loop that any block search of the last run took
+ * (rook mode; 0 otherwise). */
+int orc_get_rook_rounds(const orc_state *S)
+{
+    if (!S || !S->ran) return ORC_EINVAL;
+    return S->rook_max_rounds;
 }
 
 /* best |residual| of unfolding k in each sweep */

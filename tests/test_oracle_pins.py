@@ -544,3 +544,275 @@ def test_prescribed_ranks_cap_each_unfolding():
     c.run()
     for k in range(1, 4):
         assert np.array_equal(o.pivots(k)[2][:2], c.pivots(k)[2][:2])
+
+
+# --------------------------------------------------------------------------
+# Error measures: brute-force Frobenius error (eq. FrobeniusNorm) and the
+# sampled error of Sec. 5, against numpy on the same cores
+# --------------------------------------------------------------------------
+def _tt_full_numpy(cores):
+    """The full tensor of a TT by explicit contraction of its cores (einsum)."""
+    full = cores[0]
+    for G in cores[1:]:
+        full = np.tensordot(full, G, axes=([full.ndim - 1], [0]))
+    return full[0, ..., 0]
+
+
+def _hilbert_numpy(n, shift=None):
+    """eq. (HilbertTensor) in closed form on the 0-based grid: 1/(sum (i_j+1) + shift)."""
+    d = len(n)
+    s = (1 - d) if shift is None else shift
+    grids = np.meshgrid(*[np.arange(m) + 1.0 for m in n], indexing="ij")
+    return 1.0 / (sum(grids) + s)
+
+
+@pytest.mark.parametrize("case", ["hilbert", "sepsum"])
+def test_full_and_sampled_error_against_numpy(case):
+    """orc_full_error and orc_sampled_error against numpy: the tensor in closed
+    form (Hilbert) or as an einsum of separable factors, the TT by contracting
+    the oracle's cores, the sampled indices from the published SplitMix64
+    stream.  The cases stop at a rank cap, so the errors are far from zero."""
+    if case == "hilbert":
+        n, params, r_max, fn = [9, 10, 11], None, 3, FN_HILBERT
+        X = _hilbert_numpy(n)
+    else:
+        n, r_max, fn = [6, 7, 5, 8], 2, FN_SEPSUM
+        params = _sepsum_params(n, 4, 11)
+        g = params[1:].reshape(4, -1)
+        offs = np.cumsum([0] + n[:-1])
+        X = sum(np.einsum("i,j,k,l->ijkl", *[g[m, offs[j]:offs[j] + n[j]] for j in range(4)]) for m in range(4))
+    o = Oracle(n, 1e-14, fn, params, seed=3, r_max=r_max)
+    assert o.run() == 1                                   # stopped by the rank cap
+    Y = _tt_full_numpy(o.cores())
+    want = np.linalg.norm(X - Y) / np.linalg.norm(X)
+    assert want > 1e-5                                    # a real error, not rounding
+    err, mx = o.full_error()
+    assert abs(err - want) <= 1e-10 * want
+    assert abs(mx - np.max(np.abs(X - Y))) <= 1e-10 * mx
+    R, seed = 20000, 77
+    idx = sample_indices(n, seed, R)
+    x, y = X[tuple(idx.T)], Y[tuple(idx.T)]
+    want_s = np.sqrt(np.sum((x - y) ** 2) / np.sum(x ** 2))
+    got_s = o.sampled_error(R, seed)
+    assert abs(got_s - want_s) <= 1e-10 * want_s
+    # the default stream of the sampled error is seed + 1
+    idx1 = sample_indices(n, 4, R)
+    x1, y1 = X[tuple(idx1.T)], Y[tuple(idx1.T)]
+    assert abs(o.sampled_error(R) - np.sqrt(np.sum((x1 - y1) ** 2) / np.sum(x1 ** 2))) <= 1e-10 * want_s
+
+
+# --------------------------------------------------------------------------
+# Tie-break: among equal |residual| the lowest (row position, column
+# position) wins
+# --------------------------------------------------------------------------
+def _matrix_as_sepsum(A):
+    """A d = 2 separable sum of m terms that is exactly the m x n matrix A:
+    term m is e_m(i) A(m, j) (products with 0 and 1 and sums of zeros are
+    exact)."""
+    m, n = A.shape
+    params = [float(m)]
+    for t in range(m):
+        params += [1.0 if i == t else 0.0 for i in range(m)] + list(A[t])
+    return np.array(params)
+
+
+def test_tie_break_lowest_row_then_column_on_a_hand_built_matrix():
+    """A 6 x 6 matrix whose first pivot (10 at (0,0)) is unique and whose
+    other nonzeros sit in rows and columns that no elimination touches, so
+    the residual keeps exact ties at |5|: the pivots must come in the order
+    (1,4) before (1,5) (same row, lower column), then (2,3), (3,1), (4,2)
+    (lower rows first), whatever the signs."""
+    A = np.zeros((6, 6))
+    A[0, 0] = 10.0
+    A[1, 4], A[1, 5] = -5.0, 5.0
+    A[2, 3] = 5.0
+    A[3, 1] = -5.0
+    A[4, 2] = 5.0
+    A[5, 5] = 1.0
+    o = Oracle([6, 6], 1e-12, FN_SEPSUM, _matrix_as_sepsum(A), seed=0, r_max=6)
+    o.run()
+    _, _, rho, gam, piv = o.pivots(1)
+    assert list(zip(rho, gam))[:5] == [(0, 0), (1, 4), (2, 3), (3, 1), (4, 2)]
+    assert list(piv[:5]) == [10.0, -5.0, 5.0, -5.0, 5.0]
+
+
+def _greedy_tt_cross_numpy(n, fn, eps, seed, r_max=64, tie="low"):
+    """A second, independent greedy TT cross in numpy for tiny tensors: the
+    same readings as the oracle (samples, first pivot, Jacobi sweeps,
+    stop rule, masks), residuals by numpy's elementwise rank-1 updates (two
+    roundings, not one fma).  tie = "low" takes the lowest (row, column)
+    among equal |residual|, "high" the highest.  Returns the pivot tuples
+    and the number of searches in which the largest |residual| was tied."""
+    d = len(n)
+    idx = sample_indices(n, seed, 16384)
+    v = fn(idx)
+    rms = np.sqrt(pairwise_sumsq(v) / v.size)
+    tau = eps * rms
+    i0 = tuple(int(x) for x in idx[int(np.argmax(np.abs(v)))])
+    I = {k: [i0[:k]] for k in range(1, d)}
+    J = {k: [i0[k:]] for k in range(1, d)}
+    I[0], J[d] = [()], [()]
+    rho = {k: [i0[k - 1]] for k in range(1, d)}
+    gam = {k: [i0[k]] for k in range(1, d)}
+    ties = 0
+    while True:
+        props = {}
+        snapI = {k: list(I[k]) for k in I}
+        snapJ = {k: list(J[k]) for k in J}
+        for k in range(1, d):
+            rows = [p + (i,) for p in snapI[k - 1] for i in range(n[k - 1])]
+            cols = [(j,) + q for q in snapJ[k + 1] for j in range(n[k])]
+            E = fn(np.array([r + c for r in rows for c in cols], dtype=np.int32)).reshape(len(rows), len(cols))
+            for pr, pc in zip(rho[k], gam[k]):
+                E = E - np.outer(E[:, pc], E[pr, :] / E[pr, pc])
+            A = np.abs(E)
+            A[rho[k], :] = -1.0
+            A[:, gam[k]] = -1.0
+            best = A.max()
+            where = np.argwhere(A == best)                 # row-major order
+            ties += len(where) > 1
+            r, c = where[0] if tie == "low" else where[-1]
+            if best > tau and len(rho[k]) < r_max:
+                props[k] = (int(r), int(c))
+        if not props:
+            break
+        for k, (r, c) in props.items():
+            I[k].append(snapI[k - 1][r // n[k - 1]] + (r % n[k - 1],))
+            J[k].append((c % n[k],) + snapJ[k + 1][c // n[k]])
+            rho[k].append(r)
+            gam[k].append(c)
+    return {k: (I[k], J[k]) for k in range(1, d)}, ties
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_tie_break_on_hilbert_duplicate_rows(seed):
+    """The 3D Hilbert tensor's superblocks have bitwise-equal rows (entries
+    depend on index sums only), so the largest |residual| is tied exactly in
+    many searches.  An independent numpy greedy cross with the lowest-position
+    rule reproduces the oracle's pivot tuples; with the highest-position rule
+    it does not, so the rule decides the result."""
+    n, eps = [12, 12, 12], 1e-10
+    fn = lambda idx: fn_eval(FN_HILBERT, n, idx)
+    o = Oracle(n, eps, FN_HILBERT, seed=seed)
+    o.run()
+    low, ties = _greedy_tt_cross_numpy(n, fn, eps, seed, tie="low")
+    assert ties > 0
+    for k in (1, 2):
+        rows, cols, *_ = o.pivots(k)
+        assert [tuple(t) for t in rows] == low[k][0], k
+        assert [tuple(t) for t in cols] == low[k][1], k
+    high, _ = _greedy_tt_cross_numpy(n, fn, eps, seed, tie="high")
+    assert any(high[k] != low[k] for k in (1, 2))
+
+
+# --------------------------------------------------------------------------
+# Kinetic tensors of Sec. 5.2 (eq. 2d2vFunction): velocity moments at the
+# special points x = +-1/4, where sin(2 pi x) = +-1
+# --------------------------------------------------------------------------
+def _trunc_gauss(mu, T, a=-3.0, b=3.0):
+    """Mass, mean and second moment of exp(-(v-mu)^2/(2T)) on [a, b]
+    (standard truncated-normal formulas, scipy's normal cdf and pdf)."""
+    from scipy.stats import norm
+    s = np.sqrt(T)
+    al, be = (a - mu) / s, (b - mu) / s
+    Z = norm.cdf(be) - norm.cdf(al)
+    mass = np.sqrt(2 * np.pi * T) * Z
+    m1 = mu + s * (norm.pdf(al) - norm.pdf(be)) / Z
+    var = T * (1 + (al * norm.pdf(al) - be * norm.pdf(be)) / Z - ((norm.pdf(al) - norm.pdf(be)) / Z) ** 2)
+    return mass, m1, var + m1 ** 2
+
+
+def _kinetic_moments(fn_id, n, xs_idx, nv):
+    """Midpoint-rule velocity moments of the oracle's tensor at fixed spatial
+    indices: mass, <v_1>, <v_1^2>, <v_1 v_2> (normalised by the mass)."""
+    ndim = len(xs_idx)
+    vgrid = -3.0 + (np.arange(nv) + 0.5) * (6.0 / nv)
+    vv = np.array(list(itertools.product(range(nv), repeat=ndim)), dtype=np.int32)
+    idx = np.zeros((vv.shape[0], 2 * ndim), dtype=np.int32)
+    for w in range(ndim):
+        idx[:, 2 * w] = xs_idx[w]
+        idx[:, 2 * w + 1] = vv[:, w]
+    f = fn_eval(fn_id, n, idx)
+    h = (6.0 / nv) ** ndim
+    V = vgrid[vv]
+    mass = f.sum() * h
+    return (mass, (f * V[:, 0]).sum() * h / mass, (f * V[:, 0] ** 2).sum() * h / mass,
+            (f * V[:, 0] * V[:, 1]).sum() * h / mass)
+
+
+@pytest.mark.parametrize("fn_id,nx,nv,tol", [(FN_MAXWELL_2D2V, 6, 1000, 2e-6), (FN_MAXWELL_3D3V, 6, 160, 2e-4)])
+def test_paper_kinetic_tensors_velocity_moments(fn_id, nx, nv, tol):
+    """eq. (2d2vFunction) at x_w = +-1/4 (cell centres of [-1/2, 1/2] when
+    n = 6): rho = 1 +- 0.875, T = 0.5 +- 0.4.  In velocity f is an equal
+    mixture of two Gaussians of variance T(x_w) per axis, centred at
+    (0.75, .., 0.75) and (-0.75, .., -0.75) and cut to [-3, 3]; the mass is
+    prefactor x 2 x prod_w (truncated Gaussian mass), the prefactor being
+    sum_w rho(x_w) / (2 sqrt(2 pi T(x_w))).  Closed forms from the
+    truncated-normal moments; the tensor's sums are midpoint rules, hence
+    the tolerances."""
+    ndim = 2 if fn_id == FN_MAXWELL_2D2V else 3
+    n = [nx, nv] * ndim
+    x_of = {1: -0.25, 4: 0.25}                     # cell centres -1/2 + (i + 1/2)/6
+    rho_T = {-0.25: (1 - 0.875, 0.5 - 0.4), 0.25: (1 + 0.875, 0.5 + 0.4)}
+    for xs_idx in ([4] * ndim, [4, 1] + [4] * (ndim - 2), [1] * ndim):
+        rT = [rho_T[x_of[i]] for i in xs_idx]
+        mass, m1, m2, m12 = _kinetic_moments(fn_id, n, xs_idx, nv)
+        pre = sum(r / (2 * np.sqrt(2 * np.pi * T)) for r, T in rT)
+        gp = [_trunc_gauss(0.75, T) for _, T in rT]
+        gm = [_trunc_gauss(-0.75, T) for _, T in rT]
+        want_mass = pre * (np.prod([g[0] for g in gp]) + np.prod([g[0] for g in gm]))
+        # by symmetry of [-3, 3] both components have the same mass
+        assert abs(mass - want_mass) <= tol * want_mass, (xs_idx, mass, want_mass)
+        assert abs(m1) <= tol                                       # the two drifts cancel
+        want_m2 = 0.5 * (gp[0][2] + gm[0][2])
+        assert abs(m2 - want_m2) <= tol * want_m2, (xs_idx, m2, want_m2)
+        want_m12 = 0.5 * (gp[0][1] * gp[1][1] + gm[0][1] * gm[1][1])
+        assert abs(m12 - want_m12) <= tol * abs(want_m12), (xs_idx, m12, want_m12)
+        assert want_m12 > 0                                         # drifts share their sign
+
+
+# --------------------------------------------------------------------------
+# Rook mode: Alg. 1's loop runs until neither step moves
+# --------------------------------------------------------------------------
+def _bidiagonal(n):
+    """Values rise along the staircase (0,0) < (0,1) < (1,1) < (1,2) < ..:
+    each row's largest entry is its superdiagonal one and each column's its
+    diagonal one, so Alg. 1 climbs one step per move and a walk started
+    low on the staircase takes many rounds."""
+    A = np.zeros((n, n))
+    for j in range(n):
+        A[j, j] = 2 * j + 1.0
+        if j + 1 < n:
+            A[j, j + 1] = 2 * j + 2.0
+    return A
+
+
+def test_rook_loop_runs_until_no_step_moves():
+    """On the bidiagonal staircase the walks of Alg. 1 take tens of rounds;
+    every rook pivot, in order, is the largest |residual| of its row and of
+    its column (residuals from the direct CUR formula, numpy solve).  A walk
+    cut after 8 rounds (a test option of the oracle) breaks that condition."""
+    n = 64
+    A = _bidiagonal(n)
+    params = _matrix_as_sepsum(A)
+
+    def rook_ok(o):
+        _, _, rho, gam, _ = o.pivots(1)
+        for z in range(len(rho)):
+            I, J = list(rho[:z]), list(gam[:z])
+            R = A.copy() if z == 0 else A - A[:, J] @ np.linalg.solve(A[np.ix_(I, J)], A[I, :])
+            R[I, :] = 0.0
+            R[:, J] = 0.0
+            i, j = int(rho[z]), int(gam[z])
+            if abs(R[i, j]) < np.abs(R[:, j]).max() or abs(R[i, j]) < np.abs(R[i, :]).max():
+                return False
+        return True
+
+    for seed in (0, 2):
+        o = Oracle([n, n], 1e-14, FN_SEPSUM, params, seed=seed, r_max=6, pivot="rook", grid=[1, 1])
+        o.run()
+        assert o.rook_rounds() > 8
+        assert rook_ok(o)
+        cut = Oracle([n, n], 1e-14, FN_SEPSUM, params, seed=seed, r_max=6, pivot="rook", grid=[1, 1], rook_iters=8)
+        cut.run()
+        assert not rook_ok(cut)
