@@ -142,7 +142,9 @@ typedef struct tt_stats {
     /* filled when options.profile = 1 (device times from HIP events on the run's stream) */
     int32_t sweep_launches;     /* search-tile launches that did work (one per sweep); rook
                                    pivoting: sweeps, each timed over its search launches */
-    int32_t pad0;
+    int32_t rook_max_rounds;    /* rook pivoting: most rounds of Alg. 1's loop (a column step and
+                                   a row step) that any block search of the run took; the loop
+                                   runs until neither step moves.  0 for greedy search */
     double sweep_kernel_s;      /* summed duration of those launches */
     double sweep_alg_bytes;     /* algorithmic residual traffic of the tile launches: 2w per
                                    updated stored entry, w per scanned-only stored entry,
@@ -153,7 +155,9 @@ typedef struct tt_stats {
     double sweep_phase_s;       /* device time from the first search launch to the end of the last one */
     double sampled_err;         /* the verify check's sampled relative error, -1 if not run */
     int32_t escalated;          /* 1: the FP32 solve missed eps and was redone in FP64 */
-    int32_t pad1;
+    int32_t rook_long_walks;    /* rook pivoting: block searches whose walk took more than 8
+                                   rounds (with several workgroups per block these finish in
+                                   the search's last launch, one workgroup per block) */
 } tt_stats;
 
 typedef struct tt_cross_s *tt_cross_h;
@@ -181,8 +185,38 @@ int tt_cross_set_options(tt_cross_h h, const tt_options *opt);
 int tt_cross_set_rank_caps(tt_cross_h h, const int32_t *caps);
 
 /* Run the approximation to completion on the handle's stream and wait for it.
- * Returns TT_OK, TT_NOT_CONVERGED, or an error code. */
+ * Returns TT_OK, TT_NOT_CONVERGED, TT_WARN_SAMPLED_ERR (after a sampled-error
+ * check, see tt_options.verify), or an error code.  The same as
+ * tt_cross_run_async followed by tt_cross_wait. */
 int tt_cross_run(tt_cross_h h);
+
+/* The same run as tt_cross_run (the problem of Sec. 1), started without
+ * waiting: the call queues the samples, the setup and the first sweeps on
+ * hip_stream and returns.  The rest of the run (further sweeps, queued as
+ * the device reports its progress through mapped host memory; the cores;
+ * the sampled-error check and an FP64 escalation when the precision policy
+ * asks for them) is queued by later tt_cross_query / tt_cross_wait calls on
+ * the same handle, so a caller that polls keeps the device busy while its
+ * host thread does other work.  hip_stream: a hipStream_t, which the handle
+ * then keeps for its later calls (as tt_options.stream); NULL = the handle's
+ * stream.  While the run is in flight every other call on the handle
+ * returns TT_ESTATE, except tt_cross_query, tt_cross_wait and
+ * tt_cross_destroy (which finishes the run first).  Results are bit for bit
+ * those of tt_cross_run.  Returns TT_OK when the run is started, else an
+ * error code (the run is then over). */
+int tt_cross_run_async(tt_cross_h h, void *hip_stream);
+
+/* Advances a run started by tt_cross_run_async as far as the device allows,
+ * without blocking.  Returns 0 while the run is in flight, 1 when no run is
+ * in flight (the last one has finished: its status comes from tt_cross_wait
+ * or tt_cross_get_stats), or a negative error code when a step failed (the
+ * run is then over with that status). */
+int tt_cross_query(tt_cross_h h);
+
+/* Blocks until the run in flight has finished and returns its status, as
+ * tt_cross_run would (at once for a finished run).  Errors: TT_ESTATE when no
+ * run was ever started on the handle. */
+int tt_cross_wait(tt_cross_h h);
 
 /* ranks[0..d] = (1, r_1, .., r_{d-1}, 1) after a run. */
 int tt_cross_get_ranks(tt_cross_h h, int32_t *ranks);

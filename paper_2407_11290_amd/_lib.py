@@ -52,14 +52,14 @@ class Stats(C.Structure):
         ("time_to_eps_s", C.c_double),
         ("last_best", C.c_double * TT_MAX_D),
         ("sweep_launches", C.c_int32),
-        ("pad0", C.c_int32),
+        ("rook_max_rounds", C.c_int32),
         ("sweep_kernel_s", C.c_double),
         ("sweep_alg_bytes", C.c_double),
         ("new_entries", C.c_double),
         ("sweep_phase_s", C.c_double),
         ("sampled_err", C.c_double),
         ("escalated", C.c_int32),
-        ("pad1", C.c_int32),
+        ("rook_long_walks", C.c_int32),
     ]
 
 
@@ -78,6 +78,9 @@ SIGNATURES = {
                                      C.POINTER(C.c_double), C.c_int]),
     "tt_cross_set_options": (C.c_int, [C.c_void_p, C.POINTER(Options)]),
     "tt_cross_run": (C.c_int, [C.c_void_p]),
+    "tt_cross_run_async": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "tt_cross_query": (C.c_int, [C.c_void_p]),
+    "tt_cross_wait": (C.c_int, [C.c_void_p]),
     "tt_cross_set_rank_caps": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "tt_cross_get_ranks": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "tt_cross_get_tiles": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),

@@ -68,6 +68,7 @@ def _stats_dict(s, d):
         "sweep_alg_bytes": s.sweep_alg_bytes,
         "new_entries": s.new_entries, "sweep_phase_s": s.sweep_phase_s,
         "sampled_err": s.sampled_err, "escalated": s.escalated,
+        "rook_max_rounds": s.rook_max_rounds, "rook_long_walks": s.rook_long_walks,
     }
 
 
@@ -120,6 +121,22 @@ class TTCross:
 
     def run(self):
         self.status = check(load().tt_cross_run(self.h))
+        return self.status
+
+    def run_async(self, stream=None):
+        """Start the run without waiting (tt_cross_run_async); stream: a torch
+        stream or a raw hipStream_t (None: the handle's)."""
+        s = None if stream is None else C.c_void_p(getattr(stream, "cuda_stream", stream))
+        check(load().tt_cross_run_async(self.h, s))
+
+    def query(self):
+        """Advance the run in flight without blocking (tt_cross_query): 0
+        while it runs, 1 when none is in flight."""
+        return check(load().tt_cross_query(self.h))
+
+    def wait(self):
+        """Finish the run in flight and return its status (tt_cross_wait)."""
+        self.status = check(load().tt_cross_wait(self.h))
         return self.status
 
     def set_rank_caps(self, caps):

@@ -446,6 +446,7 @@ extern "C" int tt_batch_run(tt_cross_h *hs, int count, void *hip_stream)
             if (hs[j] == hs[i]) return set_err(TT_EINVAL, "handle %d appears twice", i);
         if (hs[i]->p.opt.pivot_mode != TT_PIVOT_GREEDY)
             return set_err(TT_EINVAL, "handle %d: rook pivoting runs through tt_cross_run only", i);
+        if (hs[i]->p.busy()) return set_err(TT_ESTATE, "handle %d has a run in flight", i);
     }
     for (int i = 0; i < count; ++i) {
         const int st = hs[i]->p.prepare();

@@ -252,6 +252,7 @@ void Problem::release()
     prof_events.clear();
     if (hm) { (void)hipHostFree(hm); hm = nullptr; }
     if (hS_pinned) { (void)hipHostFree(hS_pinned); hS_pinned = nullptr; }
+    if (h_part) { (void)hipHostFree(h_part); h_part = nullptr; }
     for (hipEvent_t &e : run_ev)
         if (e) { (void)hipEventDestroy(e); e = nullptr; }
     fn.free_device();
@@ -508,22 +509,36 @@ void Problem::resolve_geometry()
     if (req_tr == 0 && req_tc == 0 && use_table) tuned_tiles(*this, req_tr, req_tc);
 }
 
-template <typename V> int Problem::run_impl()
+// ---------------------------------------------------------------------------
+// A run as a sequence of steps.  tt_cross_run_async starts it, tt_cross_query
+// advances it without blocking, tt_cross_wait advances it to the end;
+// tt_cross_run is the first and the last in a row, so every run issues the
+// same launches in the same order.  The steps:
+//   1. samples, setup and the initial superblocks, then sweeps queued up to
+//      opt.lookahead ahead of the host's view of the device's progress (the
+//      commit kernels write it to mapped host memory);
+//   2. once the device reports the stop (or the sweep cap is reached): the
+//      cores (Alg. 4) and a copy of the final state to pinned host memory;
+//   3. the sampled-error check of the precision policy, if this run has one;
+//      an FP32 run that misses eps is escalated to FP64 sweeps (back to 1).
+// advance(wait = false) returns as soon as the next step needs the device to
+// get further than it has.
+// ---------------------------------------------------------------------------
+template <typename V> int Problem::begin_sweeps()
 {
     const int nk = d - 1;
-    hipEvent_t ev0, ev1;
-    // events and the pinned copy of the final state are kept with the
-    // problem: nothing is created or destroyed per run
+    // events and the pinned copies are kept with the problem: nothing is
+    // created or destroyed per run
     if (!run_ev[0]) HIPCHK(hipEventCreate(&run_ev[0]));
     if (!run_ev[1]) HIPCHK(hipEventCreate(&run_ev[1]));
+    if (!run_ev[2]) HIPCHK(hipEventCreateWithFlags(&run_ev[2], hipEventDisableTiming));
     if (!hS_pinned) HIPCHK(hipHostMalloc((void **)&hS_pinned, sizeof(ProbState), hipHostMallocDefault));
-    ev0 = run_ev[0];
-    ev1 = run_ev[1];
+    if (!h_part) HIPCHK(hipHostMalloc((void **)&h_part, sizeof(double) * 2 * NBV, hipHostMallocDefault));
     hm->sweeps_done = 0;
     hm->stop = 0;
     hm->err = 0;
     std::atomic_thread_fence(std::memory_order_seq_cst);
-    HIPCHK(hipEventRecord(ev0, stream));
+    HIPCHK(hipEventRecord(run_ev[0], stream));
     // a1: samples -> rms, tau, first pivot; initial superblocks (the sample
     // kernel also clears the pivot maps)
     const int ns = opt.n_samples;
@@ -535,151 +550,203 @@ template <typename V> int Problem::run_impl()
         k_samples<0><<<sample_blocks(ns), NT, 0, stream>>>(dP, opt.seed, ns, d_vals, d_spart);
         k_setup<V, 0><<<1, NT, 0, stream>>>(dP, opt.seed, ns, d_spart, eps);
     }
-    const bool rook = opt.pivot_mode == TT_PIVOT_ROOK;
-    if (!rook) {
+    if (opt.pivot_mode != TT_PIVOT_ROOK) {
         int maxe = 1;
         for (int u = 0; u < nk; ++u) maxe = std::max(maxe, n[u] * n[u + 1]);
         dim3 g((unsigned)std::min(1024, (maxe + NT - 1) / NT), (unsigned)nk);
         if (hil) k_init_eval<V, TT_FN_HILBERT><<<g, NT, 0, stream>>>(dP);
         else k_init_eval<V, 0><<<g, NT, 0, stream>>>(dP);
     }
-    int rook_wgs = 0;                          // search workgroups: G per subtensor block
-    if (rook)
-        for (int u = 0; u < nk; ++u) rook_wgs += hP.kd[u].nrb * hP.kd[u].ncb;
-    const int rook_blocks = rook_wgs;
-    rook_wgs *= rook_g;
     HIPCHK(hipGetLastError());
-    // search sweeps, queued ahead of the host's view of the stop flag
-    int rub[TT_MAX_D + 1], rst[TT_MAX_D + 1];   // rank bounds of this launch / of its stored region
     for (int k = 0; k <= d; ++k) rub[k] = rst[k] = 1;
-    const int L = std::max(1, opt.lookahead);
-    int launched = 0, done_known = 0;
-    const bool prof = opt.profile != 0;
-    if (prof) {
+    launched = 0;
+    done_known = 0;
+    if (opt.profile) {
         while ((int)prof_events.size() < 3 * max_sweeps) {
             hipEvent_t e;
             HIPCHK(hipEventCreate(&e));
             prof_events.push_back(e);
         }
     }
-    bool stopped = false;
-    while (!stopped) {
-        while (launched < done_known + L && launched < max_sweeps) {
-            SweepArgs a;
-            a.sweep = launched;
-            a.nk = nk;
-            a.S = hP.S;
-            int units = 0;
-            size_t lds = 0;
-            for (int u = 0; u < nk; ++u) {
-                const int k = u + 1;
-                const KDev &K = hP.kd[u];
-                const int all = rub[k - 1] * K.RTp * rub[k + 1] * K.CTq;
-                const int st = std::min(all, rst[k - 1] * K.RTp * rst[k + 1] * K.CTq);
-                units += (all - st) + (st + NT / 64 - 1) / (NT / 64);
-                lds = std::max(lds, sweep_lds_bytes(rub[k], K.TR, K.TC, sizeof(V)));
-            }
-            // one workgroup per expected work unit (new tiles one each, stored
-            // tiles four each); the kernel strides over the exact unit count it
-            // reads on the device, so a wrong estimate costs time only
-            const int grid = std::max(1, std::min(units, sweep_grid_cap));
-            for (int k = 0; k <= d; ++k) rst[k] = rub[k];
-            // the Hilbert tensor gets a kernel built for it alone (fewer
-            // registers, more workgroups resident); the others share one
-            auto kern = (fn.dev.id == TT_FN_HILBERT) ? k_sweep<V, TT_FN_HILBERT> : k_sweep<V, 0>;
-            if (rook) {
-                // factors: one thread per superblock row and column (bounded by
-                // the ranks this sweep can have), then one workgroup per block
-                int items = 0;
-                for (int u = 0; u < nk; ++u) items += rub[u] * n[u] + n[u + 1] * rub[u + 2];
-                const int gf = std::max(1, std::min((items + NT - 1) / NT, 4096));
-                if (hil) k_rook_factors<TT_FN_HILBERT><<<gf, NT, 0, stream>>>(dP, a);
-                else k_rook_factors<0><<<gf, NT, 0, stream>>>(dP, a);
-                // profiling: events around the search launches of the sweep
-                if (prof) HIPCHK(hipEventRecord(prof_events[3 * launched], stream));
-                if (rook_g == 1) {
-                    if (hil) k_rook_search<TT_FN_HILBERT><<<rook_wgs, NT, 0, stream>>>(dP, a, opt.seed);
-                    else k_rook_search<0><<<rook_wgs, NT, 0, stream>>>(dP, a, opt.seed);
-                } else {
-                    // split search: samples, then a fixed sequence of column
-                    // and row steps (blocks that are done return at once)
-                    if (hil) k_rook_wsample<TT_FN_HILBERT><<<rook_wgs, NT, 0, stream>>>(dP, a, opt.seed);
-                    else k_rook_wsample<0><<<rook_wgs, NT, 0, stream>>>(dP, a, opt.seed);
-                    for (int ph = 1; ph <= 2 * TT_ROOK_ITERS; ++ph) {
-                        if (hil) k_rook_wstep<TT_FN_HILBERT><<<rook_wgs, NT, 0, stream>>>(dP, a, ph);
-                        else k_rook_wstep<0><<<rook_wgs, NT, 0, stream>>>(dP, a, ph);
-                    }
-                    k_rook_wfinish<<<rook_blocks, NT, 0, stream>>>(dP, a);
-                }
-                if (prof) HIPCHK(hipEventRecord(prof_events[3 * launched + 1], stream));
-            } else if (prof) {
-                // the events take the dispatch's own start and end timestamps
-                hipExtLaunchKernelGGL(kern, dim3(grid), dim3(NT), (uint32_t)lds, stream,
-                                      prof_events[3 * launched], prof_events[3 * launched + 1], 0u, dP, a);
-            } else {
-                kern<<<grid, NT, lds, stream>>>(dP, a);
-            }
-            ++launched;
-            for (int k = 1; k <= d - 1; ++k) rub[k] = std::min(rub[k] + 1, rc[k]);
-            if (fn.dev.id == TT_FN_HILBERT) k_commit<V, TT_FN_HILBERT><<<1, NTC, 0, stream>>>(dP, a);
-            else k_commit<V, 0><<<1, NTC, 0, stream>>>(dP, a);
+    return launch_ahead<V>();
+}
+
+// Queue sweeps (search + commit) until opt.lookahead of them are ahead of the
+// last one the device reported done.  rub bounds each unfolding's rank in the
+// sweep being queued; rst that of its stored region.
+template <typename V> int Problem::launch_ahead()
+{
+    const int nk = d - 1;
+    const bool hil = fn.dev.id == TT_FN_HILBERT;
+    const bool rook = opt.pivot_mode == TT_PIVOT_ROOK;
+    const bool prof = opt.profile != 0;
+    int rook_wgs = 0;                          // search workgroups: G per subtensor block
+    if (rook)
+        for (int u = 0; u < nk; ++u) rook_wgs += hP.kd[u].nrb * hP.kd[u].ncb;
+    const int rook_blocks = rook_wgs;
+    rook_wgs *= rook_g;
+    const int L = std::max(1, opt.lookahead);
+    while (launched < done_known + L && launched < max_sweeps) {
+        SweepArgs a;
+        a.sweep = launched;
+        a.nk = nk;
+        a.S = hP.S;
+        int units = 0;
+        size_t lds = 0;
+        for (int u = 0; u < nk; ++u) {
+            const int k = u + 1;
+            const KDev &K = hP.kd[u];
+            const int all = rub[k - 1] * K.RTp * rub[k + 1] * K.CTq;
+            const int st = std::min(all, rst[k - 1] * K.RTp * rst[k + 1] * K.CTq);
+            units += (all - st) + (st + NT / 64 - 1) / (NT / 64);
+            lds = std::max(lds, sweep_lds_bytes(rub[k], K.TR, K.TC, sizeof(V)));
         }
-        HIPCHK(hipGetLastError());
-        // wait for the device to finish another sweep
-        for (;;) {
-            const int sd = __atomic_load_n(&hm->sweeps_done, __ATOMIC_ACQUIRE);
-            if (sd > done_known) { done_known = sd; break; }
+        // one workgroup per expected work unit (new tiles one each, stored
+        // tiles four each); the kernel strides over the exact unit count it
+        // reads on the device, so a wrong estimate costs time only
+        const int grid = std::max(1, std::min(units, sweep_grid_cap));
+        for (int k = 0; k <= d; ++k) rst[k] = rub[k];
+        // the Hilbert tensor gets a kernel built for it alone (fewer
+        // registers, more workgroups resident); the others share one
+        auto kern = hil ? k_sweep<V, TT_FN_HILBERT> : k_sweep<V, 0>;
+        if (rook) {
+            // factors: one thread per superblock row and column (bounded by
+            // the ranks this sweep can have), then one workgroup per block
+            int items = 0;
+            for (int u = 0; u < nk; ++u) items += rub[u] * n[u] + n[u + 1] * rub[u + 2];
+            const int gf = std::max(1, std::min((items + NT - 1) / NT, 4096));
+            if (hil) k_rook_factors<TT_FN_HILBERT><<<gf, NT, 0, stream>>>(dP, a);
+            else k_rook_factors<0><<<gf, NT, 0, stream>>>(dP, a);
+            // profiling: events around the search launches of the sweep
+            if (prof) HIPCHK(hipEventRecord(prof_events[3 * launched], stream));
+            if (rook_g == 1) {
+                if (hil) k_rook_search<TT_FN_HILBERT><<<rook_wgs, NT, 0, stream>>>(dP, a, opt.seed);
+                else k_rook_search<0><<<rook_wgs, NT, 0, stream>>>(dP, a, opt.seed);
+            } else {
+                // split search: samples, then a fixed sequence of column
+                // and row steps (blocks that are done return at once)
+                if (hil) k_rook_wsample<TT_FN_HILBERT><<<rook_wgs, NT, 0, stream>>>(dP, a, opt.seed);
+                else k_rook_wsample<0><<<rook_wgs, NT, 0, stream>>>(dP, a, opt.seed);
+                for (int ph = 1; ph <= 2 * TT_ROOK_ITERS; ++ph) {
+                    if (hil) k_rook_wstep<TT_FN_HILBERT><<<rook_wgs, NT, 0, stream>>>(dP, a, ph);
+                    else k_rook_wstep<0><<<rook_wgs, NT, 0, stream>>>(dP, a, ph);
+                }
+                // the finishing launch also completes any walk still moving
+                if (hil) k_rook_wfinish<TT_FN_HILBERT><<<rook_blocks, NT, 0, stream>>>(dP, a);
+                else k_rook_wfinish<0><<<rook_blocks, NT, 0, stream>>>(dP, a);
+            }
+            if (prof) HIPCHK(hipEventRecord(prof_events[3 * launched + 1], stream));
+        } else if (prof) {
+            // the events take the dispatch's own start and end timestamps
+            hipExtLaunchKernelGGL(kern, dim3(grid), dim3(NT), (uint32_t)lds, stream,
+                                  prof_events[3 * launched], prof_events[3 * launched + 1], 0u, dP, a);
+        } else {
+            kern<<<grid, NT, lds, stream>>>(dP, a);
+        }
+        ++launched;
+        for (int k = 1; k <= d - 1; ++k) rub[k] = std::min(rub[k] + 1, rc[k]);
+        if (hil) k_commit<V, TT_FN_HILBERT><<<1, NTC, 0, stream>>>(dP, a);
+        else k_commit<V, 0><<<1, NTC, 0, stream>>>(dP, a);
+    }
+    HIPCHK(hipGetLastError());
+    return TT_OK;
+}
+
+// Step 1: follow the device's sweeps and keep the queue filled.  Returns 0
+// while sweeping (wait = false only), 1 once the cores and the final-state
+// copy are queued, or an error.
+template <typename V> int Problem::poll_sweeps(bool wait)
+{
+    for (;;) {
+        bool progressed = false, stopped = false;
+        const int sd = __atomic_load_n(&hm->sweeps_done, __ATOMIC_ACQUIRE);
+        if (sd > done_known) {
+            done_known = sd;
+            progressed = true;
+        } else {
             hipError_t q = hipStreamQuery(stream);
             if (q != hipErrorNotReady) {
                 if (q != hipSuccess) return set_err(TT_EDEVICE, "sweep failed: %s", hipGetErrorString(q));
                 const int sd2 = __atomic_load_n(&hm->sweeps_done, __ATOMIC_ACQUIRE);
-                if (sd2 > done_known) { done_known = sd2; break; }
-                stopped = true;          // stream idle: every queued sweep has run
-                break;
+                if (sd2 > done_known) {
+                    done_known = sd2;
+                    progressed = true;
+                } else {
+                    stopped = true;      // stream idle: every queued sweep has run
+                }
             }
+        }
+        if (!progressed && !stopped) {
+            if (!wait) return 0;
+            continue;
         }
         if (__atomic_load_n(&hm->stop, __ATOMIC_ACQUIRE)) stopped = true;
         if (launched >= max_sweeps && done_known >= launched) stopped = true;
-        if (!stopped)
-            for (int k = 1; k <= d - 1; ++k)
-                rub[k] = std::min(rc[k], __atomic_load_n(&hm->r[k], __ATOMIC_RELAXED) + (launched - done_known));
+        if (stopped) return launch_tail<V>();
+        for (int k = 1; k <= d - 1; ++k)
+            rub[k] = std::min(rc[k], __atomic_load_n(&hm->r[k], __ATOMIC_RELAXED) + (launched - done_known));
+        const int st = launch_ahead<V>();
+        if (st != TT_OK) return st;
     }
+}
+
+// Step 2: the cores by Alg. 4 in FP64, then the final state's copy.
+template <typename V> int Problem::launch_tail()
+{
     // ranks of the final sweep come from the host mirror; without the stop
     // flag's release they are read only after the stream has drained
     if (!__atomic_load_n(&hm->stop, __ATOMIC_ACQUIRE)) HIPCHK(hipStreamSynchronize(stream));
-    int ranks_now[TT_MAX_D + 1];
     for (int k = 0; k <= d; ++k) ranks_now[k] = __atomic_load_n(&hm->r[k], __ATOMIC_RELAXED);
     ranks_now[0] = ranks_now[d] = 1;
     if (hm->err) {
         HIPCHK(hipStreamSynchronize(stream));
         return set_err(hm->err, "device reported error %d during the sweeps", hm->err);
     }
-    // a10: cores by Alg. 4 in FP64
     CoreArgs ca;
     std::memset(&ca, 0, sizeof ca);
     int maxr = 1;
     for (int k = 1; k <= d - 1; ++k) maxr = std::max(maxr, ranks_now[k]);
     const int blocks = make_core_args(d, n, ranks_now, ca, cores_len);
-    {
-        const size_t lc = sizeof(double) * ((size_t)2 * maxr * (maxr + 1) + (size_t)2 * maxr * A4W);
-        if (lc > (size_t)lds_limit) return set_err(TT_EINVAL, "rank %d too large for the core kernel", maxr);
-        if (fn.dev.id == TT_FN_HILBERT) k_cores<TT_FN_HILBERT><<<blocks, A4W, lc, stream>>>(dP, ca, d_cores);
-        else k_cores<0><<<blocks, A4W, lc, stream>>>(dP, ca, d_cores);
-    }
+    const size_t lc = sizeof(double) * ((size_t)2 * maxr * (maxr + 1) + (size_t)2 * maxr * A4W);
+    if (lc > (size_t)lds_limit) return set_err(TT_EINVAL, "rank %d too large for the core kernel", maxr);
+    if (fn.dev.id == TT_FN_HILBERT) k_cores<TT_FN_HILBERT><<<blocks, A4W, lc, stream>>>(dP, ca, d_cores);
+    else k_cores<0><<<blocks, A4W, lc, stream>>>(dP, ca, d_cores);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipEventRecord(ev1, stream));
-    // the final state comes back with the same synchronisation
+    HIPCHK(hipEventRecord(run_ev[1], stream));
     HIPCHK(hipMemcpyAsync(hS_pinned, hP.S, sizeof(ProbState), hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipStreamSynchronize(stream));
+    HIPCHK(hipEventRecord(run_ev[2], stream));
+    phase = PH_TAIL;
+    return 1;
+}
+
+// Waits for (wait = true) or checks run_ev[2]: 1 done, 0 not yet, < 0 error.
+int Problem::tail_event(bool wait)
+{
+    if (wait) {
+        HIPCHK(hipEventSynchronize(run_ev[2]));
+        return 1;
+    }
+    const hipError_t q = hipEventQuery(run_ev[2]);
+    if (q == hipErrorNotReady) return 0;
+    if (q != hipSuccess) return set_err(TT_EDEVICE, "run failed: %s", hipGetErrorString(q));
+    return 1;
+}
+
+// Step 2 done: results from the final state; then step 3 is queued if the
+// run has a sampled-error check.
+int Problem::poll_tail(bool wait)
+{
+    int st = tail_event(wait);
+    if (st <= 0) return st;
     float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
-    time_to_eps = ms * 1e-3;
+    HIPCHK(hipEventElapsedTime(&ms, run_ev[0], run_ev[1]));
+    time_to_eps = ms * 1e-3 + t_first;
     const ProbState S = *hS_pinned;
     if (S.err) return set_err(S.err, "device reported error %d", S.err);
     finalize(S, ranks_now);
     sweep_launches = 0;
     sweep_kernel_s = sweep_phase_s = 0;
-    if (prof) {
+    if (opt.profile) {
         for (int s = 0; s < S.sweeps && s < launched; ++s) {
             float a = 0.f;
             HIPCHK(hipEventElapsedTime(&a, prof_events[3 * s], prof_events[3 * s + 1]));
@@ -692,7 +759,68 @@ template <typename V> int Problem::run_impl()
             sweep_phase_s = c * 1e-3;
         }
     }
-    return status;
+    const int64_t R = verify_samples();
+    if (R > 0) {
+        // a13: sampled relative error over an independent SplitMix64(seed + 1) set
+        k_verify<<<NBV, NT, 0, stream>>>(dP, d_cores, R, opt.seed + 1, d_part);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(h_part, d_part, sizeof(double) * 2 * NBV, hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipEventRecord(run_ev[2], stream));
+        phase = PH_VERIFY;
+    } else {
+        phase = PH_DONE;
+    }
+    return 1;
+}
+
+// Step 3 done: the check's error; an FP32 run that missed eps starts again
+// with FP64 sweeps.
+int Problem::poll_verify(bool wait)
+{
+    int st = tail_event(wait);
+    if (st <= 0) return st;
+    // partial sums of the NBV workgroups, added in order on the host
+    double num = 0.0, den = 0.0;
+    for (int b = 0; b < NBV; ++b) { num += h_part[2 * b]; den += h_part[2 * b + 1]; }
+    const double err = den > 0 ? std::sqrt(num / den) : std::sqrt(num);
+    sampled_err = err;
+    if (err > eps && auto_fp32()) {
+        // a13: the FP32 sweeps missed eps; solve again with FP64 sweeps
+        t_first = time_to_eps;
+        force_fp64 = true;
+        escalated = 1;
+        if ((st = prepare()) != TT_OK) return st;
+        cur_fp32 = false;
+        if ((st = begin_sweeps<double>()) != TT_OK) return st;
+        phase = PH_SWEEPS;
+        return 1;
+    }
+    if (err > eps && status == TT_OK) status = TT_WARN_SAMPLED_ERR;
+    phase = PH_DONE;
+    return 1;
+}
+
+// Runs the steps; returns 1 when the run is over, 0 when wait = false and
+// the device is not far enough yet, or an error (which ends the run).
+int Problem::advance(bool wait)
+{
+    for (;;) {
+        int r;
+        switch (phase) {
+        case PH_SWEEPS: r = cur_fp32 ? poll_sweeps<float>(wait) : poll_sweeps<double>(wait); break;
+        case PH_TAIL: r = poll_tail(wait); break;
+        case PH_VERIFY: r = poll_verify(wait); break;
+        default: return 1;
+        }
+        if (r < 0) {
+            // an error ends the run; nothing queued may still use the buffers
+            (void)hipStreamSynchronize(stream);
+            status = r;
+            phase = PH_DONE;
+            return r;
+        }
+        if (r == 0) return 0;
+    }
 }
 
 // Results of a completed solve from its final device state.
@@ -712,6 +840,8 @@ void Problem::finalize(const ProbState &S, const int *ranks_now)
     sweep_alg_bytes = (double)S.alg_bytes;
     new_entries = (double)S.new_entries;
     for (int j = 0; j < d; ++j) i0[j] = S.i0[j];
+    rook_rounds = S.rook_rounds;
+    rook_long = S.rook_long;
     ran = true;
     status = S.capped ? TT_NOT_CONVERGED : TT_OK;
 }
@@ -755,55 +885,90 @@ int64_t Problem::verify_samples() const
     return policy_fp32 ? 4096 : 0;
 }
 
-// Sampled relative error of the current cores over R indices of the
-// independent set SplitMix64(seed + 1) (Sec. 5).
-int Problem::verify(int64_t R, double &err)
-{
-    k_verify<<<NBV, NT, 0, stream>>>(dP, d_cores, R, opt.seed + 1, d_part);
-    HIPCHK(hipGetLastError());
-    double hp[2 * NBV];
-    HIPCHK(hipMemcpyAsync(hp, d_part, sizeof hp, hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipStreamSynchronize(stream));
-    double num = 0.0, den = 0.0;
-    for (int b = 0; b < NBV; ++b) { num += hp[2 * b]; den += hp[2 * b + 1]; }
-    err = den > 0 ? std::sqrt(num / den) : std::sqrt(num);
-    return TT_OK;
-}
-
-int Problem::run()
+// Starts a run (step 1 queued).  On an error nothing stays queued.
+int Problem::start()
 {
     // an escalation sticks to the handle until its options change: the same
     // FP32 solve would miss eps again
     sampled_err = -1.0;
     escalated = force_fp64 ? 1 : 0;
+    t_first = 0.0;
     int st = prepare();
-    if (st != TT_OK) return st;
-    st = fp32 ? run_impl<float>() : run_impl<double>();
-    const int64_t R = verify_samples();
-    if (st >= 0 && R > 0) {
-        double err = 0.0;
-        if ((st = verify(R, err)) != TT_OK) return status = st;
-        sampled_err = err;
-        if (err > eps && auto_fp32()) {
-            // a13: the FP32 sweeps missed eps; solve again with FP64 sweeps
-            const double t_first = time_to_eps;
-            force_fp64 = true;
-            if ((st = prepare()) != TT_OK) return status = st;
-            st = run_impl<double>();
-            if (st < 0) return status = st;
-            escalated = 1;
-            time_to_eps += t_first;
-            if ((st = verify(R, err)) != TT_OK) return status = st;
-            sampled_err = err;
-        }
-        if (err > eps && status == TT_OK) status = TT_WARN_SAMPLED_ERR;
-        st = status;
+    if (st != TT_OK) {
+        phase = PH_DONE;
+        return status = st;
     }
-    status = st;
-    return st;
+    cur_fp32 = fp32 != 0;
+    phase = PH_SWEEPS;
+    st = cur_fp32 ? begin_sweeps<float>() : begin_sweeps<double>();
+    if (st != TT_OK) {
+        (void)hipStreamSynchronize(stream);
+        phase = PH_DONE;
+        return status = st;
+    }
+    return TT_OK;
+}
+
+int Problem::run()
+{
+    int st = start();
+    if (st != TT_OK) return st;
+    st = advance(true);
+    return st < 0 ? st : status;
 }
 
 }  // namespace ttc
+
+// Shapes and core offsets of a solved handle for the TT evaluation kernels.
+static void tt_args(const Problem &P, TTArgs &a)
+{
+    std::memset(&a, 0, sizeof a);
+    a.d = P.d;
+    for (int j = 0; j < P.d; ++j) a.n[j] = P.n[j];
+    for (int k = 0; k <= P.d; ++k) a.ranks[k] = P.ranks[k];
+    int64_t off = 0;
+    for (int k = 0; k < P.d; ++k) {
+        a.goff[k] = off;
+        off += (int64_t)P.ranks[k] * P.n[k] * P.ranks[k + 1];
+    }
+    a.goff[P.d] = off;
+}
+
+// ---------------------------------------------------------------------------
+// Sampled relative error (Sec. 5) of a solved handle over R seeded indices:
+// indices, f values and TT values in device buffers, then per-workgroup
+// partial sums added in order on the host.
+// ---------------------------------------------------------------------------
+constexpr int kErrParts = 256;      // workgroups of k_err_partial
+
+struct ErrBufs {
+    int *idx = nullptr;             // R x d indices
+    double *x = nullptr, *y = nullptr;   // f and TT values, R each
+    double *part = nullptr;         // 2 kErrParts partial sums
+};
+
+static int sampled_error_on(Problem &P, int64_t R, uint64_t seed, const ErrBufs &b, double *err)
+{
+    TTArgs a;
+    tt_args(P, a);
+    const unsigned g = (unsigned)((R + NT - 1) / NT);
+    k_gen_idx<<<g, NT, 0, P.stream>>>(P.d, a, seed, R, b.idx);
+    hipError_t e = launch_fn_eval<double>(P.fn.dev, R, b.idx, b.x, P.stream);
+    if (e == hipSuccess) {
+        const int64_t waves = std::min<int64_t>(R, 65536);
+        k_tt_eval<<<(unsigned)((waves * 64 + NT - 1) / NT), NT, 0, P.stream>>>(a, P.d_cores, R, b.idx, b.y);
+        k_err_partial<<<kErrParts, NT, 0, P.stream>>>(R, b.x, b.y, b.part);
+        e = hipGetLastError();
+    }
+    double hp[2 * kErrParts];
+    if (e == hipSuccess) e = hipMemcpyAsync(hp, b.part, sizeof hp, hipMemcpyDeviceToHost, P.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(P.stream);
+    if (e != hipSuccess) return set_err(TT_EDEVICE, "sampled error: %s", hipGetErrorString(e));
+    double num = 0, den = 0;
+    for (int i = 0; i < kErrParts; ++i) { num += hp[2 * i]; den += hp[2 * i + 1]; }
+    *err = den > 0 ? std::sqrt(num / den) : std::sqrt(num);
+    return (*err > P.eps) ? TT_WARN_SAMPLED_ERR : TT_OK;
+}
 
 // ===========================================================================
 // C ABI
@@ -863,9 +1028,28 @@ tt_cross_h tt_cross_create(int d, const int32_t *n, double eps, int fn_id, const
     return h;
 }
 
+// Every call that reads or changes a handle's state refuses while a run
+// started by tt_cross_run_async is in flight.
+#define TT_NOT_BUSY(h)                                                                       \
+    do {                                                                                     \
+        if ((h)->p.busy()) return set_err(TT_ESTATE, "a run is in flight (tt_cross_wait)"); \
+    } while (0)
+
+// Use stream s (non-NULL) from now on, as tt_options.stream would.
+static int adopt_stream(Problem &P, hipStream_t s)
+{
+    if (!s || s == P.stream) return TT_OK;
+    if (P.own_stream && P.stream) (void)hipStreamDestroy(P.stream);
+    P.stream = s;
+    P.own_stream = false;
+    P.opt.stream = s;
+    return TT_OK;
+}
+
 int tt_cross_set_options(tt_cross_h h, const tt_options *opt)
 {
     if (!h) return set_err(TT_EINVAL, "NULL handle");
+    TT_NOT_BUSY(h);
     int st = check_options(opt);
     if (st) return st;
     if (h->p.allocated && opt->stream != h->p.opt.stream) {
@@ -890,6 +1074,7 @@ int tt_cross_set_options(tt_cross_h h, const tt_options *opt)
 int tt_cross_set_rank_caps(tt_cross_h h, const int32_t *caps)
 {
     if (!h) return set_err(TT_EINVAL, "NULL handle");
+    TT_NOT_BUSY(h);
     Problem &P = h->p;
     for (int k = 1; k <= P.d - 1; ++k) {
         const int c = caps ? caps[k - 1] : 0;
@@ -903,13 +1088,48 @@ int tt_cross_set_rank_caps(tt_cross_h h, const int32_t *caps)
 int tt_cross_run(tt_cross_h h)
 {
     if (!h) return set_err(TT_EINVAL, "NULL handle");
+    TT_NOT_BUSY(h);
     g_err.clear();
     return h->p.run();
+}
+
+int tt_cross_run_async(tt_cross_h h, void *hip_stream)
+{
+    if (!h) return set_err(TT_EINVAL, "NULL handle");
+    TT_NOT_BUSY(h);
+    g_err.clear();
+    Problem &P = h->p;
+    if (hip_stream && P.allocated) adopt_stream(P, (hipStream_t)hip_stream);
+    else if (hip_stream) P.opt.stream = hip_stream;     // taken up when the buffers are made
+    const int st = P.start();
+    if (st != TT_OK) return st;
+    // take whatever steps the device already allows, without waiting
+    const int a = P.advance(false);
+    return a < 0 ? a : TT_OK;
+}
+
+int tt_cross_query(tt_cross_h h)
+{
+    if (!h) return set_err(TT_EINVAL, "NULL handle");
+    Problem &P = h->p;
+    if (!P.busy()) return 1;
+    const int a = P.advance(false);
+    return a < 0 ? a : (P.busy() ? 0 : 1);
+}
+
+int tt_cross_wait(tt_cross_h h)
+{
+    if (!h) return set_err(TT_EINVAL, "NULL handle");
+    Problem &P = h->p;
+    if (P.phase == Problem::PH_IDLE) return set_err(TT_ESTATE, "no run started");
+    const int a = P.advance(true);
+    return a < 0 ? a : P.status;
 }
 
 int tt_cross_get_ranks(tt_cross_h h, int32_t *ranks)
 {
     if (!h || !ranks) return set_err(TT_EINVAL, "NULL argument");
+    TT_NOT_BUSY(h);
     if (!h->p.ran) return set_err(TT_ESTATE, "no completed run");
     for (int k = 0; k <= h->p.d; ++k) ranks[k] = h->p.ranks[k];
     return TT_OK;
@@ -918,6 +1138,7 @@ int tt_cross_get_ranks(tt_cross_h h, int32_t *ranks)
 int tt_cross_get_tiles(tt_cross_h h, int32_t *rows, int32_t *cols)
 {
     if (!h || !rows || !cols) return set_err(TT_EINVAL, "NULL argument");
+    TT_NOT_BUSY(h);
     if (!h->p.ran) return set_err(TT_ESTATE, "no completed run");
     for (int u = 0; u < h->p.d - 1; ++u) {
         rows[u] = h->p.tileTR[u];
@@ -929,6 +1150,7 @@ int tt_cross_get_tiles(tt_cross_h h, int32_t *rows, int32_t *cols)
 int64_t tt_cross_get_cores(tt_cross_h h, double *out, int64_t cap, int on_device)
 {
     if (!h) return set_err(TT_EINVAL, "NULL handle");
+    TT_NOT_BUSY(h);
     Problem &P = h->p;
     if (!P.ran) return set_err(TT_ESTATE, "no completed run");
     if (!out) return P.cores_len;
@@ -939,23 +1161,11 @@ int64_t tt_cross_get_cores(tt_cross_h h, double *out, int64_t cap, int on_device
     return P.cores_len;
 }
 
-static void tt_args(const Problem &P, TTArgs &a)
-{
-    std::memset(&a, 0, sizeof a);
-    a.d = P.d;
-    for (int j = 0; j < P.d; ++j) a.n[j] = P.n[j];
-    for (int k = 0; k <= P.d; ++k) a.ranks[k] = P.ranks[k];
-    int64_t off = 0;
-    for (int k = 0; k < P.d; ++k) {
-        a.goff[k] = off;
-        off += (int64_t)P.ranks[k] * P.n[k] * P.ranks[k + 1];
-    }
-    a.goff[P.d] = off;
-}
 
 int tt_eval(tt_cross_h h, int64_t m, const int32_t *idx, double *out, int on_device)
 {
     if (!h) return set_err(TT_EINVAL, "NULL handle");
+    TT_NOT_BUSY(h);
     Problem &P = h->p;
     if (!P.ran) return set_err(TT_ESTATE, "no completed run");
     if (m < 0 || (m > 0 && (!idx || !out))) return set_err(TT_EINVAL, "bad arguments");
@@ -991,6 +1201,7 @@ int tt_eval(tt_cross_h h, int64_t m, const int32_t *idx, double *out, int on_dev
 int tt_cross_get_pivots(tt_cross_h h, int k, int32_t *rows, int32_t *cols)
 {
     if (!h) return set_err(TT_EINVAL, "NULL handle");
+    TT_NOT_BUSY(h);
     Problem &P = h->p;
     if (!P.ran) return set_err(TT_ESTATE, "no completed run");
     if (k < 1 || k > P.d - 1) return set_err(TT_EINVAL, "k out of range");
@@ -1004,6 +1215,7 @@ int tt_cross_get_pivots(tt_cross_h h, int k, int32_t *rows, int32_t *cols)
 int tt_cross_get_history(tt_cross_h h, int k, double *out, int cap)
 {
     if (!h) return set_err(TT_EINVAL, "NULL handle");
+    TT_NOT_BUSY(h);
     Problem &P = h->p;
     if (!P.ran) return set_err(TT_ESTATE, "no completed run");
     if (k < 1 || k > P.d - 1) return set_err(TT_EINVAL, "k out of range");
@@ -1015,6 +1227,7 @@ int tt_cross_get_history(tt_cross_h h, int k, double *out, int cap)
 int tt_cross_get_stats(tt_cross_h h, tt_stats *st)
 {
     if (!h || !st) return set_err(TT_EINVAL, "NULL argument");
+    TT_NOT_BUSY(h);
     Problem &P = h->p;
     std::memset(st, 0, sizeof *st);
     st->d = P.d;
@@ -1037,47 +1250,30 @@ int tt_cross_get_stats(tt_cross_h h, tt_stats *st)
     st->sweep_phase_s = P.sweep_phase_s;
     st->sampled_err = P.sampled_err;
     st->escalated = P.escalated;
+    st->rook_max_rounds = P.rook_rounds;
+    st->rook_long_walks = P.rook_long;
     return TT_OK;
 }
 
 int tt_cross_sampled_error(tt_cross_h h, int64_t R, uint64_t seed, double *err)
 {
     if (!h || !err) return set_err(TT_EINVAL, "NULL argument");
+    TT_NOT_BUSY(h);
     Problem &P = h->p;
     if (!P.ran) return set_err(TT_ESTATE, "no completed run");
     if (R < 1) return set_err(TT_EINVAL, "R must be >= 1");
-    TTArgs a;
-    tt_args(P, a);
-    int *didx = nullptr;
-    double *x = nullptr, *y = nullptr, *part = nullptr;
-    const int nb = 256;
-    hipError_t e = hipMalloc(&didx, sizeof(int) * R * P.d);
-    if (e == hipSuccess) e = hipMalloc(&x, sizeof(double) * R);
-    if (e == hipSuccess) e = hipMalloc(&y, sizeof(double) * R);
-    if (e == hipSuccess) e = hipMalloc(&part, sizeof(double) * 2 * nb);
-    if (e == hipSuccess) {
-        const unsigned g = (unsigned)((R + NT - 1) / NT);
-        k_gen_idx<<<g, NT, 0, P.stream>>>(P.d, a, seed, R, didx);
-        e = launch_fn_eval<double>(P.fn.dev, R, didx, x, P.stream);
-        if (e == hipSuccess) {
-            const int64_t waves = std::min<int64_t>(R, 65536);
-            k_tt_eval<<<(unsigned)((waves * 64 + NT - 1) / NT), NT, 0, P.stream>>>(a, P.d_cores, R, didx, y);
-            k_err_partial<<<nb, NT, 0, P.stream>>>(R, x, y, part);
-            e = hipGetLastError();
-        }
-    }
-    std::vector<double> hp(2 * nb);
-    if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), part, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, P.stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(P.stream);
-    if (didx) (void)hipFree(didx);
-    if (x) (void)hipFree(x);
-    if (y) (void)hipFree(y);
-    if (part) (void)hipFree(part);
-    if (e != hipSuccess) return set_err(TT_EDEVICE, "sampled error: %s", hipGetErrorString(e));
-    double num = 0, den = 0;
-    for (int i = 0; i < nb; ++i) { num += hp[2 * i]; den += hp[2 * i + 1]; }
-    *err = den > 0 ? std::sqrt(num / den) : std::sqrt(num);
-    return (*err > P.eps) ? TT_WARN_SAMPLED_ERR : TT_OK;
+    ErrBufs b;
+    hipError_t e = hipMalloc(&b.idx, sizeof(int) * R * P.d);
+    if (e == hipSuccess) e = hipMalloc(&b.x, sizeof(double) * R);
+    if (e == hipSuccess) e = hipMalloc(&b.y, sizeof(double) * R);
+    if (e == hipSuccess) e = hipMalloc(&b.part, sizeof(double) * 2 * kErrParts);
+    int st = (e == hipSuccess) ? sampled_error_on(P, R, seed, b, err)
+                               : set_err(TT_ENOMEM, "sampled error: %s", hipGetErrorString(e));
+    if (b.idx) (void)hipFree(b.idx);
+    if (b.x) (void)hipFree(b.x);
+    if (b.y) (void)hipFree(b.y);
+    if (b.part) (void)hipFree(b.part);
+    return st;
 }
 
 }  // extern "C"
@@ -1213,6 +1409,8 @@ int tt_fn_eval_last_kernel_ms(double *ms)
 void tt_cross_destroy(tt_cross_h h)
 {
     if (!h) return;
+    // a run in flight is finished first: its kernels use the buffers
+    if (h->p.busy()) (void)h->p.advance(true);
     delete h;
 }
 

@@ -13,7 +13,8 @@ constexpr int NT = 256;                    // threads per workgroup (4 wave64)
 constexpr int TT_TILE_ROWS_MAX = 256;      // largest tile extent along the rows
 constexpr double PI = 3.14159265358979323846;
 constexpr uint64_t SM64_GAMMA = 0x9E3779B97F4A7C15ULL;
-constexpr int TT_ROOK_ITERS = 8;           // rounds of Alg. 1's loop per block, at most
+constexpr int TT_ROOK_ITERS = 8;           // rounds of Alg. 1's loop in the split search's fixed
+                                           // launch sequence; longer walks finish in its last launch
 
 // ---------------------------------------------------------------------------
 // Generating function descriptor (copied to the device with the problem).
@@ -229,7 +230,7 @@ struct RookState {
     int valid;                    // the block has a start
     int active;                   // still searching
     int moved;                    // moved in the current round
-    int pad;
+    int rounds;                   // rounds of Alg. 1's loop completed
 };
 
 // What one search sweep does to one unfolding, prepared by the previous commit.
@@ -261,6 +262,8 @@ struct ProbState {
     double rms, tau;
     int i0[TT_MAX_D];
     double last_best[TT_MAX_D];
+    int rook_rounds;              // rook mode: most rounds any block walk of the run took
+    int rook_long;                // rook mode: block walks longer than TT_ROOK_ITERS rounds
 };
 
 struct HostMirror {                // fine-grained host memory, written by the device

@@ -79,10 +79,13 @@ struct Problem {
     double rms = 0, tau = 0, time_to_eps = 0;
     double last_best[TT_MAX_D] = {0};
     int sweep_launches = 0;
+    int rook_rounds = 0, rook_long = 0;      // rook walk statistics of the last run
     double sweep_kernel_s = 0, sweep_alg_bytes = 0, new_entries = 0, sweep_phase_s = 0;
     std::vector<hipEvent_t> prof_events;     // 3 per sweep when profiling
-    hipEvent_t run_ev[2] = {nullptr, nullptr};  // start / end of a run
+    hipEvent_t run_ev[3] = {nullptr, nullptr, nullptr};  // start / end of a run's device time;
+                                             // end of its last queued copy
     ProbState *hS_pinned = nullptr;          // pinned host copy of the final device state
+    double *h_part = nullptr;                // pinned host copy of the check's partial sums
     int i0[TT_MAX_D] = {0};
     // sampled-error check and FP32 -> FP64 escalation
     double sampled_err = -1.0;
@@ -90,9 +93,18 @@ struct Problem {
     bool force_fp64 = false;       // sweep in FP64 whatever the precision policy says
     double *d_part = nullptr;      // partial sums of the check (2 * NBV doubles)
 
+    // a run in steps (tt_cross_run_async / tt_cross_query / tt_cross_wait)
+    enum { PH_IDLE = 0, PH_SWEEPS, PH_TAIL, PH_VERIFY, PH_DONE };
+    int phase = PH_IDLE;
+    bool cur_fp32 = false;         // precision of the sweeps in flight
+    int launched = 0, done_known = 0;                    // sweeps queued / reported done
+    int rub[TT_MAX_D + 1] = {0}, rst[TT_MAX_D + 1] = {0}; // rank bounds of the next sweep / its stored region
+    int ranks_now[TT_MAX_D + 1] = {0};                   // ranks of the final sweep
+    double t_first = 0.0;          // device time of an FP32 run that was escalated
+    bool busy() const { return phase == PH_SWEEPS || phase == PH_TAIL || phase == PH_VERIFY; }
+
     int64_t verify_samples() const;
     bool auto_fp32() const { return opt.precision == TT_PREC_AUTO && fp32 && !force_fp64; }
-    int verify(int64_t R, double &err);
 
     ~Problem();
     void release();
@@ -102,8 +114,16 @@ struct Problem {
     int allocate();
     int prepare();
     void finalize(const ProbState &S, const int *ranks_now);
+    int start();
+    int advance(bool wait);
     int run();
-    template <typename V> int run_impl();
+    template <typename V> int begin_sweeps();
+    template <typename V> int launch_ahead();
+    template <typename V> int poll_sweeps(bool wait);
+    template <typename V> int launch_tail();
+    int tail_event(bool wait);
+    int poll_tail(bool wait);
+    int poll_verify(bool wait);
 };
 
 // Process-wide table of tuned tile shapes by problem class (tt_tune.hip).

@@ -873,6 +873,7 @@ __device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns,
             for (int j = 0; j <= d; ++j) S->r[b][j] = 1;
         S->stop = 0; S->capped = 0; S->sweeps = 0; S->pivoted = 0;
         S->alg_bytes = 0; S->new_entries = 0;
+        S->rook_rounds = 0; S->rook_long = 0;
         S->err = sbad ? TT_EFN : 0;
         p0s = (double)fn_value<V, FNS>(P->F, i0);
         p64 = (double)fn_value<double, FNS>(P->F, i0);
@@ -1098,10 +1099,72 @@ __device__ inline double rook_residual(const ProbDev *__restrict__ P, int u, int
     return x;
 }
 
+// The loop of Alg. 1 run by one workgroup from (ci, cj), whose |residual| is
+// bv: a column step (largest |residual| in column cj), then a row step (in
+// row ci), each moving only to a strictly larger |residual|, until a round
+// moves neither.  Among equal values the lowest position wins.  The loop ends
+// by itself: every move raises |residual|, and a column step leaves the
+// position at the largest |residual| of its column (a row step, of its row),
+// so a column (row) that a step has searched is never entered again; hence
+// at most min(rows, columns) + 1 rounds, the bound written below.  rowpos and
+// colpos map the block's t-th row / column to its superblock position.
+// Adds the residuals looked at to cnt; returns the rounds run.
+template <int FNS, typename RP, typename CP>
+__device__ int rook_walk(const ProbDev *__restrict__ P, int u, const KDev &K, RP rowpos, CP colpos, int nR, int nC,
+                         int rk, double *s_f, double &bv, double &bs, int &ci, int &cj, unsigned long long &cnt)
+{
+    const int tid = threadIdx.x, wp = K.rk_cap;
+    const gptr_t<const double> W = as_global((const double *)K.Wf), U = as_global((const double *)K.Uf);
+    const int cap = min(nR, nC) + 1;
+    int rounds = 0;
+    while (rounds < cap) {
+        ++rounds;
+        bool moved = false;
+        // column step: U(:, cj) shared by every row
+        for (int z = tid; z < rk; z += NT) s_f[z] = U[(int64_t)cj * wp + z];
+        __syncthreads();
+        double tv = -1.0, ts = 0.0;
+        uint64_t tk = ~0ULL;
+        for (int t = tid; t < nR; t += NT) {
+            const int row = rowpos(t);
+            if (K.rpiv[row]) continue;
+            ++cnt;
+            const double x = rook_residual<FNS>(P, u, row, cj, W + (int64_t)row * wp, s_f, 1, rk);
+            if (better(fabs(x), (uint64_t)row, tv, tk)) { tv = fabs(x); tk = (uint64_t)row; ts = x; }
+        }
+        block_best(tv, tk, ts);
+        if (tv > bv) { bv = tv; bs = ts; ci = (int)tk; moved = true; }
+        // row step: W(ci, :) shared by every column
+        for (int z = tid; z < rk; z += NT) s_f[z] = W[(int64_t)ci * wp + z];
+        __syncthreads();
+        tv = -1.0;
+        ts = 0.0;
+        tk = ~0ULL;
+        for (int t = tid; t < nC; t += NT) {
+            const int col = colpos(t);
+            if (K.cpiv[col]) continue;
+            ++cnt;
+            const double x = rook_residual<FNS>(P, u, ci, col, s_f, U + (int64_t)col * wp, 1, rk);
+            if (better(fabs(x), (uint64_t)col, tv, tk)) { tv = fabs(x); tk = (uint64_t)col; ts = x; }
+        }
+        block_best(tv, tk, ts);
+        if (tv > bv) { bv = tv; bs = ts; cj = (int)tk; moved = true; }
+        if (!moved) break;
+    }
+    return rounds;
+}
+
+// Walk statistics of one block search (one thread per block).
+__device__ inline void rook_note_rounds(const ProbDev *__restrict__ P, int rounds)
+{
+    ProbState *S = P->S;
+    atomicMax(&S->rook_rounds, rounds);
+    if (rounds > TT_ROOK_ITERS) atomicAdd(&S->rook_long, 1);
+}
+
 // One subtensor block of one superblock per workgroup: the random start of
-// Alg. 1 from the block's seeded sample stream, then column and row steps
-// while either finds a strictly larger |residual| (at most TT_ROOK_ITERS
-// rounds).  Ties go to the lowest position, as in the greedy search.
+// Alg. 1 from the block's seeded sample stream, then its loop (rook_walk).
+// Ties go to the lowest position, as in the greedy search.
 template <int FNS>
 __device__ void rook_search_body(const ProbDev *__restrict__ P, int nk, int sweep, uint64_t seed, int wg)
 {
@@ -1131,6 +1194,7 @@ __device__ void rook_search_body(const ProbDev *__restrict__ P, int nk, int swee
     double bv = -1.0, bs = 0.0;
     uint64_t bk = ~0ULL;
     unsigned long long cnt = 0;
+    int rounds = 0;
     if (nR > 0 && nC > 0) {
         // the random set: pair s takes draws 2s (row) and 2s+1 (column)
         const uint64_t tag = (uint64_t)k | ((uint64_t)sweep << 8) | ((uint64_t)b << 32);
@@ -1164,39 +1228,7 @@ __device__ void rook_search_body(const ProbDev *__restrict__ P, int nk, int swee
         }
         if (bv >= 0.0) {
             int ci = (int)(bk >> 32), cj = (int)(bk & 0xffffffffULL);
-            for (int it = 0; it < TT_ROOK_ITERS; ++it) {
-                bool moved = false;
-                // column step: U(:, cj) shared by every row
-                for (int z = tid; z < rk; z += NT) s_f[z] = U[(int64_t)cj * wp + z];
-                __syncthreads();
-                double tv = -1.0, ts = 0.0;
-                uint64_t tk = ~0ULL;
-                for (int t = tid; t < nR; t += NT) {
-                    const int row = rowpos(t);
-                    if (K.rpiv[row]) continue;
-                    ++cnt;
-                    const double x = rook_residual<FNS>(P, u, row, cj, W + (int64_t)row * wp, s_f, 1, rk);
-                    if (better(fabs(x), (uint64_t)row, tv, tk)) { tv = fabs(x); tk = (uint64_t)row; ts = x; }
-                }
-                block_best(tv, tk, ts);
-                if (tv > bv) { bv = tv; bs = ts; ci = (int)tk; moved = true; }
-                // row step: W(ci, :) shared by every column
-                for (int z = tid; z < rk; z += NT) s_f[z] = W[(int64_t)ci * wp + z];
-                __syncthreads();
-                tv = -1.0;
-                ts = 0.0;
-                tk = ~0ULL;
-                for (int t = tid; t < nC; t += NT) {
-                    const int col = colpos(t);
-                    if (K.cpiv[col]) continue;
-                    ++cnt;
-                    const double x = rook_residual<FNS>(P, u, ci, col, s_f, U + (int64_t)col * wp, 1, rk);
-                    if (better(fabs(x), (uint64_t)col, tv, tk)) { tv = fabs(x); tk = (uint64_t)col; ts = x; }
-                }
-                block_best(tv, tk, ts);
-                if (tv > bv) { bv = tv; bs = ts; cj = (int)tk; moved = true; }
-                if (!moved) break;
-            }
+            rounds = rook_walk<FNS>(P, u, K, rowpos, colpos, nR, nC, rk, s_f, bv, bs, ci, cj, cnt);
             bk = ((uint64_t)ci << 32) | (uint32_t)cj;
         }
     }
@@ -1205,6 +1237,7 @@ __device__ void rook_search_body(const ProbDev *__restrict__ P, int nk, int swee
         Cand &c = K.cand[b];
         c.v = bv; c.key = bk; c.sv = bs;
         K.bcnt[b] = cnt;
+        if (rounds > 0) rook_note_rounds(P, rounds);
     }
 }
 
@@ -1301,6 +1334,7 @@ __device__ inline RookState rook_advance(RookState s, int p, double pv, uint64_t
         if (pv > s.v) { s.v = pv; s.sv = psv; s.ci = (int)pk; s.moved = 1; }
     } else {                                    // p-1 was a row step: a round ends
         if (pv > s.v) { s.v = pv; s.sv = psv; s.cj = (int)pk; s.moved = 1; }
+        ++s.rounds;
         if (!s.moved) s.active = 0;
         s.moved = 0;
     }
@@ -1342,6 +1376,7 @@ __device__ void rook_wstep_body(const ProbDev *__restrict__ P, int nk, int p, in
             s.valid = pv >= 0.0 ? 1 : 0;
             s.active = s.valid;
             s.moved = 0;
+            s.rounds = 0;
             s.v = pv;
             s.sv = psv;
             s.ci = (int)(pk >> 32);
@@ -1410,28 +1445,64 @@ __device__ void rook_wstep_body(const ProbDev *__restrict__ P, int nk, int p, in
 }
 
 // After the last step: the block's pivot and count.  One workgroup per block.
-__device__ inline void rook_wfinish_body(const ProbDev *__restrict__ P, int nk, int wg)
+// A walk still moving after the fixed TT_ROOK_ITERS rounds is not cut short:
+// this workgroup runs the rest of Alg. 1's loop (rook_walk, the comparisons
+// and counts of the split steps) until it stops.
+template <int FNS>
+__device__ void rook_wfinish_body(const ProbDev *__restrict__ P, int nk, int wg)
 {
     const ProbState *S = P->S;
     if (S->stop) return;
-    const int G = P->rook_g, p = 2 * TT_ROOK_ITERS + 1;
+    const int tid = threadIdx.x, G = P->rook_g, p = 2 * TT_ROOK_ITERS + 1;
     int u, b, g;
     if (!rook_wg_of(P, nk, 1, wg, u, b, g)) return;
     const KDev &K = P->kd[u];
     const int nb = K.nrb * K.ncb;
+    __shared__ RookState st;
+    __shared__ KSweep ks;
+    __shared__ int s_pref[TT_MAX_RANK], s_suf[TT_MAX_RANK];
+    __shared__ RookGeom s_g;
+    __shared__ double s_f[TT_MAX_RANK];
     double pv, psv;
     uint64_t pk;
     rook_reduce_parts(K, G, (p - 1) & 1, b, pv, pk, psv);
     unsigned long long c = 0;
-    for (int i = threadIdx.x; i < G; i += NT) c += K.rcnt[(int64_t)b * G + i];
+    for (int i = tid; i < G; i += NT) c += K.rcnt[(int64_t)b * G + i];
     c = block_sum_u64(c);
-    if (threadIdx.x == 0) {
-        const RookState s = rook_advance(K.rst[(int64_t)((p - 1) & 1) * nb + b], p, pv, pk, psv);
+    if (tid == 0) {
+        st = rook_advance(K.rst[(int64_t)((p - 1) & 1) * nb + b], p, pv, pk, psv);
+        if (st.active) {
+            ks = S->ks[u];
+            rook_block_geom(P, u, b, ks, s_pref, s_suf, s_g);
+        }
+    }
+    __syncthreads();
+    if (st.active) {                            // uniform: read after the barrier
+        const int len = s_g.len, len1 = s_g.len1, lo = s_g.lo, lo1 = s_g.lo1;
+        const int nR = s_g.np * len, nC = s_g.nq * len1;
+        auto rowpos = [&](int t) { return s_pref[t / len] * K.nk + lo + t % len; };
+        auto colpos = [&](int t) { return s_suf[t / len1] * K.nk1 + lo1 + t % len1; };
+        double bv = st.v, bs = st.sv;
+        int ci = st.ci, cj = st.cj;
+        unsigned long long more = 0;
+        const int r = rook_walk<FNS>(P, u, K, rowpos, colpos, nR, nC, ks.rk, s_f, bv, bs, ci, cj, more);
+        more = block_sum_u64(more);
+        if (tid == 0) {
+            st.v = bv;
+            st.sv = bs;
+            st.ci = ci;
+            st.cj = cj;
+            st.rounds += r;
+            c += more;
+        }
+    }
+    if (tid == 0) {
         Cand &o = K.cand[b];
-        if (s.valid) {
-            o.v = s.v;
-            o.key = ((uint64_t)s.ci << 32) | (uint32_t)s.cj;
-            o.sv = s.sv;
+        if (st.valid) {
+            o.v = st.v;
+            o.key = ((uint64_t)st.ci << 32) | (uint32_t)st.cj;
+            o.sv = st.sv;
+            rook_note_rounds(P, st.rounds);
         } else {
             o.v = -1.0;
             o.key = ~0ULL;
@@ -1453,9 +1524,10 @@ static __global__ void __launch_bounds__(NT) k_rook_wstep(const ProbDev *__restr
     rook_wstep_body<FNS>(P, a.nk, phase, blockIdx.x);
 }
 
+template <int FNS = 0>
 static __global__ void __launch_bounds__(NT) k_rook_wfinish(const ProbDev *__restrict__ P, SweepArgs a)
 {
-    rook_wfinish_body(P, a.nk, blockIdx.x);
+    rook_wfinish_body<FNS>(P, a.nk, blockIdx.x);
 }
 
 template <int FNS = 0>

@@ -122,6 +122,7 @@ extern "C" int tt_autotune(tt_cross_h h, int reps, int32_t *tile_rows, int32_t *
 {
     if (!h) return set_err(TT_EINVAL, "handle is NULL");
     if (reps < 1 || reps > 64) return set_err(TT_EINVAL, "reps must be in [1,64]");
+    if (h->p.busy()) return set_err(TT_ESTATE, "a run is in flight");
     Problem &P = h->p;
     const tt_options saved = P.opt;
     const bool saved_force = P.force_fp64;
@@ -169,8 +170,10 @@ extern "C" int tt_batch_autotune(tt_cross_h *hs, int count, int reps, int per_cl
     if (count < 0 || (count > 0 && !hs)) return set_err(TT_EINVAL, "bad batch arguments");
     if (reps < 1 || reps > 64) return set_err(TT_EINVAL, "reps must be in [1,64]");
     if (per_class < 1) return set_err(TT_EINVAL, "per_class must be >= 1");
-    for (int i = 0; i < count; ++i)
+    for (int i = 0; i < count; ++i) {
         if (!hs[i]) return set_err(TT_EINVAL, "handle %d is NULL", i);
+        if (hs[i]->p.busy()) return set_err(TT_ESTATE, "handle %d has a run in flight", i);
+    }
     // classes in order of first appearance
     std::map<ClassKey, int> index;
     std::vector<ClassKey> keys;

@@ -21,11 +21,12 @@ def _sep(n, r, seed):
     return np.concatenate([[float(r)], 0.5 + rng.random(r * int(np.sum(n)))])
 
 
-def _both(n, eps, fn, params, seed, grid, split=0):
+def _both(n, eps, fn, params, seed, grid, split=0, r_max=64):
     _say("rook", n, fn, seed, grid, "split", split)
-    g = TTCross(n, eps, fn, params, seed=seed, grid=grid, precision=PREC_FP64, pivot=PIVOT_ROOK, rook_split=split)
+    g = TTCross(n, eps, fn, params, seed=seed, grid=grid, precision=PREC_FP64, pivot=PIVOT_ROOK, rook_split=split,
+                r_max=r_max)
     gs = g.run()
-    o = Oracle(n, eps, fn, params, seed=seed, pivot="rook", grid=grid)
+    o = Oracle(n, eps, fn, params, seed=seed, pivot="rook", grid=grid, r_max=r_max)
     os_ = o.run()
     return g, gs, o, os_
 
@@ -42,6 +43,9 @@ def _assert_same(g, gs, o, os_):
     st, ost = g.stats(), o.stats()
     assert st["sweeps"] == ost["sweeps"] and st["pivoted"] == ost["pivoted"]
     assert st["evaluated"] == ost["evaluated"]
+    # Alg. 1's loop runs until neither step moves on both sides: the longest
+    # walk of the run has the same number of rounds
+    assert st["rook_max_rounds"] == o.rook_rounds()
     assert np.array_equal(g.cores_flat(), o.cores_flat())
 
 
@@ -156,3 +160,35 @@ def test_mode_sizes_beyond_the_limit_are_refused():
     assert e.value.code == EINVAL
     h = TTCross([4, 1 << 20, 4], 1e-8, FN_HILBERT, precision=PREC_FP64, pivot=PIVOT_ROOK)
     assert h.run() >= 0
+
+
+def _staircase_params(n):
+    """The n x n bidiagonal staircase (0,0) < (0,1) < (1,1) < (1,2) < ..., as a
+    d = 2 separable sum of n terms e_m(i) A(m, j) (exact in any arithmetic):
+    each row's largest entry is its superdiagonal one and each column's its
+    diagonal one, so Alg. 1 climbs one step per move and walks take tens of
+    rounds."""
+    A = np.zeros((n, n))
+    for j in range(n):
+        A[j, j] = 2 * j + 1.0
+        if j + 1 < n:
+            A[j, j + 1] = 2 * j + 2.0
+    params = [float(n)]
+    for m in range(n):
+        params += [1.0 if i == m else 0.0 for i in range(n)] + list(A[m])
+    return np.array(params)
+
+
+@pytest.mark.parametrize("n,seed", [(64, 0), (64, 2), (200, 1)])
+@pytest.mark.parametrize("split", [1, 3, 16])
+def test_rook_walks_longer_than_the_fixed_rounds(n, seed, split):
+    """Walks of Alg. 1 much longer than the split search's fixed launch
+    sequence of 8 rounds: the one-workgroup search loops until no step
+    moves, and the split search finishes such walks in its last launch.
+    Pivots, counts and the longest walk's rounds match the oracle, whose
+    loop has no cap."""
+    g, gs, o, os_ = _both([n, n], 1e-14, FN_SEPSUM, _staircase_params(n), seed, [1, 1], split, r_max=6)
+    _assert_same(g, gs, o, os_)
+    st = g.stats()
+    _say("rounds", st["rook_max_rounds"], "long walks", st["rook_long_walks"])
+    assert st["rook_max_rounds"] > 8 and st["rook_long_walks"] > 0
