@@ -250,6 +250,20 @@ int tt_cross_get_stats(tt_cross_h h, tt_stats *st);
  * draw(s*d + j) mod n_j. */
 int tt_cross_sampled_error(tt_cross_h h, int64_t R, uint64_t seed, double *err);
 
+/* The sampled relative error of tt_cross_sampled_error, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same kernels and the same
+ * result, bit for bit, but the indices, values and partial sums live in one
+ * static device array of the library (about 5 MiB per GPU that calls it,
+ * held until the process ends) instead of buffers allocated per call.
+ * R must be in [1, TT_NOALLOC_MAX_SAMPLES] (else TT_EINVAL).  Calls that
+ * overlap on one GPU (several host threads, or a caller's own graph
+ * replays) share the array and race; run them one at a time.  Runs on the
+ * handle's stream and returns when done; nothing is allocated on the device
+ * or pinned on the host.  Returns as tt_cross_sampled_error. */
+#define TT_NOALLOC_MAX_SAMPLES 65536
+int tt_cross_sampled_error_noalloc(tt_cross_h h, int64_t R, uint64_t seed, double *err);
+
 /* Evaluate a generating function (the tensor's entries, Sec. 1: element
  * access only) at m multi-indices, no handle needed.  tt_fn_eval computes in
  * FP64; tt_fn_eval_f32 uses the FP32 arithmetic that FP32 sweeps use for

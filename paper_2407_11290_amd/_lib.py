@@ -90,6 +90,7 @@ SIGNATURES = {
     "tt_cross_get_history": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int]),
     "tt_cross_get_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
     "tt_cross_sampled_error": (C.c_int, [C.c_void_p, C.c_int64, C.c_uint64, C.POINTER(C.c_double)]),
+    "tt_cross_sampled_error_noalloc": (C.c_int, [C.c_void_p, C.c_int64, C.c_uint64, C.POINTER(C.c_double)]),
     "tt_fn_eval": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_int,
                              C.c_int64, C.c_void_p, C.c_void_p, C.c_int]),
     "tt_fn_eval_f32": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_int,

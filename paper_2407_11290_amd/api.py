@@ -222,6 +222,13 @@ class TTCross:
         check(load().tt_cross_sampled_error(self.h, R, C.c_uint64(seed), C.byref(e)))
         return e.value
 
+    def sampled_error_noalloc(self, R=65536, seed=1):
+        """The same error from the library's static scratch array
+        (tt_cross_sampled_error_noalloc): no device allocation, R <= 65536."""
+        e = C.c_double()
+        check(load().tt_cross_sampled_error_noalloc(self.h, R, C.c_uint64(seed), C.byref(e)))
+        return e.value
+
 
 def batch_run(problems, stream=None):
     """Solve several TTCross problems together on one GPU (tt_batch_run).

@@ -970,6 +970,41 @@ static int sampled_error_on(Problem &P, int64_t R, uint64_t seed, const ErrBufs 
     return (*err > P.eps) ? TT_WARN_SAMPLED_ERR : TT_OK;
 }
 
+// The buffers of tt_cross_sampled_error_noalloc: one static device array
+// per GPU, laid out as indices | f values | TT values | partial sums, each
+// part 256-byte aligned.  Its name is a host-side stand-in: host code uses
+// only the address hipGetSymbolAddress returns for the current device.
+constexpr size_t kScrAlign(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr size_t kScrIdx = 0;
+constexpr size_t kScrX = kScrAlign(kScrIdx + sizeof(int) * (size_t)TT_NOALLOC_MAX_SAMPLES * TT_MAX_D);
+constexpr size_t kScrY = kScrAlign(kScrX + sizeof(double) * (size_t)TT_NOALLOC_MAX_SAMPLES);
+constexpr size_t kScrPart = kScrAlign(kScrY + sizeof(double) * (size_t)TT_NOALLOC_MAX_SAMPLES);
+constexpr size_t kScrBytes = kScrAlign(kScrPart + sizeof(double) * 2 * kErrParts);
+
+static __device__ __align__(256) unsigned char scratch[kScrBytes];
+
+static std::mutex g_scr_mu;
+static unsigned char *g_scr_ptr[64];     // per device, from hipGetSymbolAddress
+
+// Device address of the current device's scratch array (looked up once per
+// device, with that device current).
+static int scratch_base(unsigned char **out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return set_err(TT_EDEVICE, "device %d beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lk(g_scr_mu);
+    if (!g_scr_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_err(TT_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scr_ptr[dev] = (unsigned char *)p;
+    }
+    *out = g_scr_ptr[dev];
+    return TT_OK;
+}
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -1274,6 +1309,26 @@ int tt_cross_sampled_error(tt_cross_h h, int64_t R, uint64_t seed, double *err)
     if (b.y) (void)hipFree(b.y);
     if (b.part) (void)hipFree(b.part);
     return st;
+}
+
+int tt_cross_sampled_error_noalloc(tt_cross_h h, int64_t R, uint64_t seed, double *err)
+{
+    if (!h || !err) return set_err(TT_EINVAL, "NULL argument");
+    TT_NOT_BUSY(h);
+    Problem &P = h->p;
+    if (!P.ran) return set_err(TT_ESTATE, "no completed run");
+    if (R < 1 || R > TT_NOALLOC_MAX_SAMPLES)
+        return set_err(TT_EINVAL, "R = %lld outside [1, %d] (the static scratch holds %d samples)", (long long)R,
+                       TT_NOALLOC_MAX_SAMPLES, TT_NOALLOC_MAX_SAMPLES);
+    unsigned char *base = nullptr;
+    const int st = scratch_base(&base);
+    if (st != TT_OK) return st;
+    ErrBufs b;
+    b.idx = (int *)(base + kScrIdx);
+    b.x = (double *)(base + kScrX);
+    b.y = (double *)(base + kScrY);
+    b.part = (double *)(base + kScrPart);
+    return sampled_error_on(P, R, seed, b, err);
 }
 
 }  // extern "C"
