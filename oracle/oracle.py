@@ -44,6 +44,7 @@ def lib():
         L.orc_tt_eval.argtypes = [C.c_int, i32p, i32p, f64p, C.c_int64, i32p, f64p]
         L.orc_sampled_error.argtypes = [P, C.c_int64, C.c_uint64, P]
         L.orc_full_error.argtypes = [P, P, P]
+        L.orc_verify.argtypes = [P, C.c_int64, P]
         L.orc_superblock_residual.restype = C.c_int64
         L.orc_superblock_residual.argtypes = [P, C.c_int, P, C.c_int64, P, P]
         L.orc_matrix_residual.argtypes = [C.c_int64, C.c_int64, f64p, C.c_int, i64p, i64p]
@@ -227,6 +228,17 @@ class Oracle:
         if st != 0:
             raise RuntimeError(st)
         return e.value
+
+    def verify(self, R):
+        """The final guard: sampled error over R indices of stream seed + 1;
+        a converged run whose error exceeds eps gets status 2 (sampled-error
+        warning).  Returns (status, error)."""
+        e = C.c_double()
+        st = lib().orc_verify(self.h, R, C.byref(e))
+        if st < 0:
+            raise RuntimeError(st)
+        self.status = st
+        return st, e.value
 
     def _seed_plus_one(self):
         return (self._seed + 1) & 0xFFFFFFFFFFFFFFFF

@@ -80,8 +80,8 @@
 enum { ORC_FN_HILBERT = 1, ORC_FN_MAXWELL = 2, ORC_FN_BIMAXWELL = 3, ORC_FN_SEPSUM = 4,
        ORC_FN_MAXWELL_2D2V = 5, ORC_FN_MAXWELL_3D3V = 6 };
 
-enum { ORC_OK = 0, ORC_NOT_CONVERGED = 1, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_ESINGULAR = -4,
-       ORC_EFN = -6 };
+enum { ORC_OK = 0, ORC_NOT_CONVERGED = 1, ORC_WARN_SAMPLED_ERR = 2, ORC_EINVAL = -1, ORC_ENOMEM = -2,
+       ORC_ESINGULAR = -4, ORC_EFN = -6 };
 
 /* ------------------------------------------------------------------------ */
 /* SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): state advances by the golden */
@@ -938,6 +938,20 @@ int orc_sampled_error(const orc_state *S, int64_t R, uint64_t seed, double *err)
     free(v); free(vn);
     *err = den > 0.0 ? sqrt(num / den) : sqrt(num);
     return ORC_OK;
+}
+
+/* The final guard of a run: the sampled relative error (Sec. 5) over R
+ * indices of the independent stream seed + 1.  A run that stopped with
+ * every superblock residual at or below tau (status ORC_OK) but whose
+ * sampled error exceeds eps has converged falsely; its status becomes
+ * ORC_WARN_SAMPLED_ERR.  Returns the status; *err receives the error. */
+int orc_verify(orc_state *S, int64_t R, double *err)
+{
+    if (!S || !S->ran || R < 1) return ORC_EINVAL;
+    int st = orc_sampled_error(S, R, S->seed + 1, err);
+    if (st) return st;
+    if (*err > S->eps && S->status == ORC_OK) S->status = ORC_WARN_SAMPLED_ERR;
+    return S->status;
 }
 
 /* Brute force over every entry (eq. FrobeniusNorm); tiny tensors only. */
