@@ -245,6 +245,20 @@ int tt_cross_get_history(tt_cross_h h, int k, double *out, int cap);
 
 int tt_cross_get_stats(tt_cross_h h, tt_stats *st);
 
+/* Phase stamps of the last run, for the instrumented build of the library
+ * (libttcross_stamps.so, compiled with TT_STAMPS; the normal build returns
+ * TT_ESTATE).  The device's 100 MHz clock at phase boundaries: layout[0]
+ * words per record, layout[1] records per sweep (search workgroups, by
+ * workgroup index), layout[2] sweeps with records, layout[3] sweeps run; the
+ * search records of all sweeps come first, then one record per commit.
+ * Search record: 0 entry, 1 state loaded, 2-6 the first new-entry tile
+ * (start, staging, raw factors, factor solves, entries done), 7-8 wavefront
+ * 0's first stored tile (geometry known, done), 9 end, 10 new tiles, 11
+ * stored tiles of wavefront 0.  Commit record: 0 entry, 1 state loaded, 2
+ * candidates reduced, 3 pivots committed, 4 end.  Zero = not reached.
+ * Returns the number of values (out NULL: the size). */
+int64_t tt_cross_get_stamps(tt_cross_h h, uint64_t *out, int64_t cap, int32_t *layout);
+
 /* Sampled relative error (Sec. 5): sqrt(sum (X - X~)^2 / sum X^2) over R
  * multi-indices drawn from SplitMix64(seed), coordinate j of sample s being
  * draw(s*d + j) mod n_j. */

@@ -7,7 +7,10 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libttcross.so")
+# TT_CROSS_LIB=stamps selects the instrumented build (phase stamps, see
+# tt_cross_get_stamps); the default is the normal library
+LIB_PATH = os.path.join(HERE, "libttcross_stamps.so" if os.environ.get("TT_CROSS_LIB") == "stamps"
+                        else "libttcross.so")
 
 TT_MAX_D = 16
 TT_MAX_RANK = 64
@@ -89,6 +92,7 @@ SIGNATURES = {
     "tt_cross_get_pivots": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
     "tt_cross_get_history": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int]),
     "tt_cross_get_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
+    "tt_cross_get_stamps": (C.c_int64, [C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int32)]),
     "tt_cross_sampled_error": (C.c_int, [C.c_void_p, C.c_int64, C.c_uint64, C.POINTER(C.c_double)]),
     "tt_cross_sampled_error_noalloc": (C.c_int, [C.c_void_p, C.c_int64, C.c_uint64, C.POINTER(C.c_double)]),
     "tt_fn_eval": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_int,

@@ -26,15 +26,22 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
-def build(verbose=False):
-    """Compile every HIP source into the shared library (always recompiles)."""
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *sources(), "-o", tmp]
+LIB_STAMPS = os.path.join(HERE, "libttcross_stamps.so")
+
+
+def build(verbose=False, stamps=False):
+    """Compile every HIP source into the shared library (always recompiles).
+    stamps=True builds the instrumented variant libttcross_stamps.so, whose
+    search and commit kernels record phase times (tt_cross_get_stamps)."""
+    out = LIB_STAMPS if stamps else LIB
+    tmp = out + ".tmp"
+    cmd = [HIPCC, *FLAGS, *(["-DTT_STAMPS"] if stamps else []), "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+           *sources(), "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

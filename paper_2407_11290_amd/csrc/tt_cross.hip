@@ -468,6 +468,13 @@ int Problem::allocate()
     if ((st = dalloc((void **)&d_spart, sizeof(SamplePart) * sample_blocks(opt.n_samples))) != TT_OK) return st;
     if ((st = dalloc((void **)&d_part, sizeof(double) * 2 * NBV)) != TT_OK) return st;
     if ((st = dalloc((void **)&H.S, sizeof(ProbState))) != TT_OK) return st;
+#ifdef TT_STAMPS
+    // phase stamps: one record per search workgroup and sweep, one per commit
+    H.stamp_wgs = sweep_grid_cap;
+    H.stamp_sweeps = max_sweeps;
+    stamp_words = (size_t)max_sweeps * (sweep_grid_cap + 1) * STAMP_WORDS;
+    if ((st = dalloc((void **)&H.stamps, sizeof(unsigned long long) * stamp_words)) != TT_OK) return st;
+#endif
     HIPCHK(hipHostMalloc((void **)&hm, sizeof(HostMirror), hipHostMallocMapped | hipHostMallocCoherent));
     HIPCHK(hipHostGetDevicePointer((void **)&H.hm, hm, 0));
     // the first sweep searches the initial superblocks (one prefix, one
@@ -538,6 +545,9 @@ template <typename V> int Problem::begin_sweeps()
     hm->stop = 0;
     hm->err = 0;
     std::atomic_thread_fence(std::memory_order_seq_cst);
+#ifdef TT_STAMPS
+    HIPCHK(hipMemsetAsync(hP.stamps, 0, sizeof(unsigned long long) * stamp_words, stream));
+#endif
     HIPCHK(hipEventRecord(run_ev[0], stream));
     // a1: samples -> rms, tau, first pivot; initial superblocks (the sample
     // kernel also clears the pivot maps)
@@ -1288,6 +1298,29 @@ int tt_cross_get_stats(tt_cross_h h, tt_stats *st)
     st->rook_max_rounds = P.rook_rounds;
     st->rook_long_walks = P.rook_long;
     return TT_OK;
+}
+
+int64_t tt_cross_get_stamps(tt_cross_h h, uint64_t *out, int64_t cap, int32_t *layout)
+{
+    if (!h) return set_err(TT_EINVAL, "NULL handle");
+    TT_NOT_BUSY(h);
+#ifdef TT_STAMPS
+    Problem &P = h->p;
+    if (!P.ran) return set_err(TT_ESTATE, "no completed run");
+    if (layout) {
+        layout[0] = STAMP_WORDS;
+        layout[1] = P.hP.stamp_wgs;
+        layout[2] = P.hP.stamp_sweeps;
+        layout[3] = P.sweeps;
+    }
+    if (!out) return (int64_t)P.stamp_words;
+    if (cap < (int64_t)P.stamp_words) return set_err(TT_EINVAL, "cap below %zu", P.stamp_words);
+    HIPCHK(hipMemcpy(out, P.hP.stamps, sizeof(uint64_t) * P.stamp_words, hipMemcpyDeviceToHost));
+    return (int64_t)P.stamp_words;
+#else
+    (void)out; (void)cap; (void)layout;
+    return set_err(TT_ESTATE, "this library was built without phase stamps (build with stamps=True)");
+#endif
 }
 
 int tt_cross_sampled_error(tt_cross_h h, int64_t R, uint64_t seed, double *err)

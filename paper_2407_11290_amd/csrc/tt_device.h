@@ -316,7 +316,14 @@ struct ProbDev {
     HostMirror *hm;               // device alias of the host mirror
     RunDev run;
     SweepShape sh0;               // tile counts of the first sweep (every tile stored)
+    // phase stamps (only in the library built with TT_STAMPS; null otherwise):
+    // STAMP_WORDS clock values per search workgroup (stamp_wgs per sweep),
+    // then STAMP_WORDS per commit launch
+    unsigned long long *stamps;
+    int stamp_wgs, stamp_sweeps;
 };
+
+constexpr int STAMP_WORDS = 16;
 
 struct SweepArgs {
     int sweep;

@@ -80,6 +80,7 @@ struct Problem {
     double last_best[TT_MAX_D] = {0};
     int sweep_launches = 0;
     int rook_rounds = 0, rook_long = 0;      // rook walk statistics of the last run
+    size_t stamp_words = 0;                  // phase stamps (library built with TT_STAMPS)
     double sweep_kernel_s = 0, sweep_alg_bytes = 0, new_entries = 0, sweep_phase_s = 0;
     std::vector<hipEvent_t> prof_events;     // 3 per sweep when profiling
     hipEvent_t run_ev[3] = {nullptr, nullptr, nullptr};  // start / end of a run's device time;

@@ -29,6 +29,34 @@
 
 namespace ttc {
 
+// Phase stamps of the instrumented build (TT_STAMPS): the device's constant
+// 100 MHz clock at the boundaries of the search and commit phases, one
+// record of STAMP_WORDS values per workgroup.  The normal build compiles
+// none of it.
+#ifdef TT_STAMPS
+__device__ inline unsigned long long *stamp_rec(const ProbDev *P, int sweep, int blk)
+{
+    if (!P->stamps || sweep >= P->stamp_sweeps || blk >= P->stamp_wgs) return nullptr;
+    return P->stamps + ((size_t)sweep * P->stamp_wgs + blk) * STAMP_WORDS;
+}
+__device__ inline unsigned long long *stamp_commit_rec(const ProbDev *P, int sweep)
+{
+    if (!P->stamps || sweep >= P->stamp_sweeps) return nullptr;
+    return P->stamps + ((size_t)P->stamp_sweeps * P->stamp_wgs + sweep) * STAMP_WORDS;
+}
+#define TT_STAMP(rec, slot)                                                              \
+    do {                                                                                 \
+        if ((rec) && threadIdx.x == 0) (rec)[slot] = __builtin_amdgcn_s_memrealtime();   \
+    } while (0)
+#define TT_STAMP_ADD(rec, slot, v)                                                       \
+    do {                                                                                 \
+        if ((rec) && threadIdx.x == 0) (rec)[slot] += (v);                               \
+    } while (0)
+#else
+#define TT_STAMP(rec, slot) do {} while (0)
+#define TT_STAMP_ADD(rec, slot, v) do {} while (0)
+#endif
+
 __device__ inline bool better(double a, uint64_t ka, double b, uint64_t kb)
 {
     return a > b || (a == b && ka < kb);
@@ -177,7 +205,7 @@ __device__ void stored_tile_wave(const KDev &K, const KSweep &ks, const TileGeom
 // and the frozen pivot columns / rows of the tile receive those values.
 template <typename V, int FNS>
 __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSweep &ks, const TileGeom &g,
-                         double &bv, uint64_t &bk, double &bs, V *sm)
+                         double &bv, uint64_t &bk, double &bs, V *sm, unsigned long long *rec)
 {
     const int d = P->d, u = g.u, k = u + 1, tid = threadIdx.x, rk = ks.rk;
     const bool rows_old = g.row0 < ks.nr_st, cols_old = g.col0 < ks.nc_st;
@@ -220,6 +248,7 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSw
     }
     for (int ii = tid; ii < g.nrows; ii += NT) s_rp[ii] = as_global((const uint8_t *)K.rpiv)[g.row0 + ii];
     __syncthreads();
+    TT_STAMP(rec, 3);
     // raw factors: frozen entries, or the generating function at the skeleton
     if (rows_old) {
         for (int e = tid; e < rk * g.nrows; e += NT) {
@@ -280,6 +309,7 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSw
         }
     }
     __syncthreads();
+    TT_STAMP(rec, 4);
     // chains as triangular solves.  Each factor sees the same operations in
     // the same order as the written recursion, so both forms give the same
     // bits.  Up to rank 16, a lane group per row (column): lane z holds
@@ -353,6 +383,7 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSw
         }
     }
     __syncthreads();
+    TT_STAMP(rec, 5);
     if (tcol < g.ncols) {
         const int col = g.col0 + tcol;
         if (!cpv) {
@@ -382,6 +413,7 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSw
         }
     }
     block_best(bv, bk, bs);
+    TT_STAMP(rec, 6);
 }
 
 
@@ -390,10 +422,18 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSw
 // Fixed grid striding over work units: first the new-entry tiles (one per
 // workgroup), then the stored tiles four at a time (one per wavefront).
 template <typename V, int FNS>
-__device__ void sweep_body(const ProbDev *__restrict__ P, const ProbState *S, int nk, int blk, int nblk)
+__device__ void sweep_body(const ProbDev *__restrict__ P, const ProbState *S, int nk, int blk, int nblk,
+                           int sweep = -1)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+#ifdef TT_STAMPS
+    const unsigned long long t_entry = __builtin_amdgcn_s_memrealtime();
+    unsigned long long *rec = sweep >= 0 ? stamp_rec(P, sweep, blk) : nullptr;
+    if (rec && tid == 0) rec[0] = t_entry;
+#else
+    unsigned long long *const rec = nullptr;
+#endif
     __shared__ KSweep ks[TT_MAX_D];
     __shared__ SweepShape sh;
     // one round of loads: the stop flag, and the shapes and tile counts the
@@ -404,6 +444,7 @@ __device__ void sweep_body(const ProbDev *__restrict__ P, const ProbState *S, in
     if (tid < SHAPE_WORDS) ((int *)&sh)[tid] = as_global((const int *)&S->sh)[tid];
     if (stop) return;                   // the same value in every thread
     __syncthreads();
+    TT_STAMP(rec, 1);
     const int nnew = sh.noff[nk], nst = sh.soff[nk];
     const int units = nnew + (nst + NT / 64 - 1) / (NT / 64);
     for (int t = blk; t < units; t += nblk) {
@@ -424,7 +465,13 @@ __device__ void sweep_body(const ProbDev *__restrict__ P, const ProbState *S, in
             }
             const KDev &K = P->kd[u];
             const TileGeom g = tile_geom(K, u, R, C);
-            new_tile<V, FNS>(P, K, ks[u], g, bv, bk, bs, (V *)smem_raw);
+            unsigned long long *nrec = nullptr;
+#ifdef TT_STAMPS
+            if (rec && rec[10] == 0) nrec = rec;          // the workgroup's first new tile
+            TT_STAMP(nrec, 2);
+#endif
+            new_tile<V, FNS>(P, K, ks[u], g, bv, bk, bs, (V *)smem_raw, nrec);
+            TT_STAMP_ADD(rec, 10, 1);
             if (tid == 0) {
                 const gptr_t<Cand> c = as_global(K.cand) + (R * CT + C);
                 c->v = bv; c->key = bk; c->sv = bs;
@@ -441,6 +488,11 @@ __device__ void sweep_body(const ProbDev *__restrict__ P, const ProbState *S, in
                 const int R = idx / CTs, C = idx - R * CTs;
                 const KDev &K = P->kd[u];
                 const TileGeom g = tile_geom(K, u, R, C);
+#ifdef TT_STAMPS
+                // wave 0's first stored tile: geometry known, tile done
+                const bool first_st = rec && wid == 0 && rec[11] == 0;
+                if (first_st && lane == 0) rec[7] = __builtin_amdgcn_s_memrealtime();
+#endif
                 // 8 rows per batch of loads: more raise the register count
                 // past four wavefronts per SIMD (Hilbert kernel) or three
                 stored_tile_wave<V, 8>(K, ks[u], g, bv, bk, bs);
@@ -449,15 +501,23 @@ __device__ void sweep_body(const ProbDev *__restrict__ P, const ProbState *S, in
                     const gptr_t<Cand> c = as_global(K.cand) + (R * sh.CT[u] + C);
                     c->v = bv; c->key = bk; c->sv = bs;
                 }
+#ifdef TT_STAMPS
+                if (first_st && lane == 0) rec[8] = __builtin_amdgcn_s_memrealtime();
+                if (rec && wid == 0 && lane == 0) rec[11] += 1;
+#endif
             }
         }
     }
+#ifdef TT_STAMPS
+    __syncthreads();
+    TT_STAMP(rec, 9);
+#endif
 }
 
 template <typename V, int FNS = 0>
 static __global__ void __launch_bounds__(NT) k_sweep(const ProbDev *__restrict__ P, SweepArgs a)
 {
-    sweep_body<V, FNS>(P, a.S, a.nk, blockIdx.x, gridDim.x);
+    sweep_body<V, FNS>(P, a.S, a.nk, blockIdx.x, gridDim.x, a.sweep);
 }
 
 // ---------------------------------------------------------------------------
@@ -515,6 +575,13 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
     const int tid = threadIdx.x, wid = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     constexpr int NW = NTC / 64;
     const int d = nk + 1, par = sweep & 1;    // nk from the launch: no dependent read
+#ifdef TT_STAMPS
+    const unsigned long long t_entry = __builtin_amdgcn_s_memrealtime();
+    unsigned long long *rec = stamp_commit_rec(P, sweep);
+    if (rec && tid == 0) rec[0] = t_entry;
+#else
+    unsigned long long *const rec = nullptr;
+#endif
     __shared__ KSweep ks[TT_MAX_D];
     __shared__ double s_wv[TT_MAX_D], s_wsv[TT_MAX_D];
     __shared__ uint64_t s_wk[TT_MAX_D];
@@ -534,6 +601,7 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
     if (tid == NTC - 1) { s_stop = S->stop; s_tau = S->tau; }
     if (tid == NTC - 2) { s_acc[0] = S->alg_bytes; s_acc[1] = S->new_entries; s_acc[2] = S->pivoted; }
     __syncthreads();
+    TT_STAMP(rec, 1);
     if (s_stop) return;
     // best candidate per unfolding: wave w scans unfoldings w, w+NW, ...,
     // with CB candidates per lane in flight at once
@@ -572,6 +640,7 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
         if (lane == 0) { s_wv[u] = bv; s_wk[u] = bk; s_wsv[u] = bs; }
     }
     __syncthreads();
+    TT_STAMP(rec, 2);
     // decide and commit
     for (int u = wid; u < nk; u += NW) {
         const int k = u + 1;
@@ -642,6 +711,7 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
         }
     }
     __syncthreads();
+    TT_STAMP(rec, 3);
     if (tid == 0) { s_rnew[0] = 1; s_rnew[d] = 1; }
     __syncthreads();
     // the next sweep's shapes and tile counts: lane u of wavefront 0 prepares
@@ -715,6 +785,7 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
                 __hip_atomic_store(&hm->r[j], s_rnew[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             __hip_atomic_store(&hm->sweeps_done, sweep + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         }
+        TT_STAMP(rec, 4);
     }
 }
 
