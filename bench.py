@@ -12,8 +12,16 @@ comes from HIP events inside the library.
 The roofline figure is for the search-tile kernel (the residual sweep): its
 algorithmic residual traffic per launch over its average launch time, both
 from HIP events on the library's stream, against the 8 TB/s HBM peak.  The
-CPU baseline is the FP64 oracle timed on this host, single-threaded, over
-complete solves of the same workload.
+CPU baseline is the FP64 oracle timed on this host over complete solves of
+the same workload, in host threads on every usable core (at most 16), with
+the CPU model, the CPU count and a single-thread figure beside it.
+
+The same line carries measured summaries of the other configurations: the 6D
+Maxwellian with FP32 sweeps (time-to-eps, error against FP64 entries), the
+mixed 512-problem batch (batched against one at a time) and a served trace
+(p50/p99 latency over three Poisson runs, capacity against the same request
+list one at a time).  --workload selects one of them alone, with its own
+roofline figure.
 """
 import argparse
 import json
@@ -302,32 +310,66 @@ def bench_paper(args):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(seconds):
-    from oracle import Oracle
-    from oracle.oracle import FN_HILBERT
-    done, work, seeds = 0.0, 0, []
+MAXWELL_N, MAXWELL_EPS, MAXWELL_SEEDS = [128] * 6, 1e-6, [0, 1, 2, 3, 4]
+
+
+def measure_maxwell6d(steps, profile=False):
+    """The 6D Maxwellian phase-space tensor (x1,x2,x3 periodic on [0,1),
+    v in [-8,8]^3 cell centres, n = 128 per mode, 2^6 subtensor blocks),
+    eps = 1e-6, the precision policy's FP32 entry evaluation and sweeps with
+    the FP64 candidate check, stop test, pivot block and cores, and the
+    policy's 4096-sample check; seeds 0..4 in turn.  Per solve: device
+    time-to-eps, and the sampled relative error of the result over 1e6
+    indices against the tensor's FP64 entries."""
+    import torch
+    from paper_2407_11290_amd import FN_MAXWELL
+    from paper_2407_11290_amd.api import TTCross
+    hs = [TTCross(MAXWELL_N, MAXWELL_EPS, FN_MAXWELL, seed=s, grid=[2] * 6, profile=1 if profile else 0)
+          for s in MAXWELL_SEEDS]
+    for h in hs:
+        h.run()                                    # allocates
+    tte, work, errs, prec, esc = [], 0, [], set(), 0
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    i = 0
-    while True:
-        seed = SEEDS[i % len(SEEDS)]
-        o = Oracle(N, EPS, FN_HILBERT, seed=seed)
-        o.run()
-        st = o.stats()
+    for i in range(steps):
+        h = hs[i % len(hs)]
+        if h.run() != 0:
+            raise RuntimeError("maxwellian solve did not meet eps")
+        st = h.stats()
+        tte.append(st["time_to_eps_s"])
         work += st["evaluated"] + st["pivoted"]
-        seeds.append(seed)
-        i += 1
-        done = time.perf_counter() - t0
-        if done >= seconds:
-            break
-    return {"value": work / done, "unit": "entries/s", "cores": 1, "kind": "oracle",
-            "sample": f"{len(seeds)} complete FP64 oracle solves of the same workload, seeds {seeds}, "
-                      f"{done:.1f} s, one host thread"}
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for h in hs:
+        st = h.stats()
+        prec.add("fp32" if st["precision_used"] == 2 else "fp64")
+        esc += st["escalated"]
+        errs.append(h.sampled_error(1_000_000, seed=12345))
+    out = {"workload": "maxwell6d_n128_grid2x2x2x2x2x2_eps1e-6_fp32sweeps", "solves": steps,
+           "time_to_eps_ms": {"median": statistics.median(tte) * 1e3, "min": min(tte) * 1e3},
+           "entries_per_s": work / wall, "ms_per_solve_wall": wall / steps * 1e3,
+           "ranks": [int(x) for x in hs[0].ranks()], "sweep_precision": sorted(prec), "escalated": esc,
+           "sampled_rel_error_vs_fp64_entries": {"max": max(errs), "per_seed": errs, "R": 1_000_000},
+           "policy_check_error_max": max(h.stats()["sampled_err"] for h in hs)}
+    if profile:
+        ks = kb = kl = 0.0
+        for h in hs:
+            h.run()
+            st = h.stats()
+            ks += st["sweep_kernel_s"]
+            kb += st["sweep_alg_bytes"]
+            kl += st["sweep_launches"]
+        out["search_kernel"] = {"avg_launch_us": ks / max(kl, 1) * 1e6, "bytes_per_launch": kb / max(kl, 1),
+                                "launches": int(kl)}
+    for h in hs:
+        h.close()
+    return out
 
 
-def bench_batch(args):
-    """Mixed batch of 512 problems (d 3..6, n 16..128, Hilbert / bi-Maxwellian,
-    eps 1e-6, FP32 sweeps by the precision policy): one batched solve per step
-    against the same problems solved one at a time."""
+def measure_batch(steps, warmup=1):
+    """The mixed 512-problem batch solved together (tt_batch_run) against the
+    same problems one at a time on their own handles (buffers allocated
+    before timing in both)."""
     import torch
     from paper_2407_11290_amd.api import TTCross, batch_run
     from paper_2407_11290_amd.workloads import batch_mix
@@ -335,60 +377,58 @@ def bench_batch(args):
     hs = [TTCross(p.n, p.eps, p.fn_id, p.params, seed=p.seed, grid=p.grid) for p in specs]
     t0 = time.perf_counter()
     batch_run(hs)                                   # allocates every problem's buffers
-    print(f"bench: first batch (with allocation) {time.perf_counter() - t0:.2f} s", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
+    first = time.perf_counter() - t0
+    for _ in range(warmup):
         batch_run(hs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         batch_run(hs)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     # every timed batch solves the same problems the same way (escalations
-    # stick to their handles from the first batch on), so the work of one
-    # batch, read after the timed region, counts for each
-    work = args.steps * sum(st["evaluated"] + st["pivoted"] for st in (h.stats() for h in hs))
-    print(f"bench: {args.steps} batched steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
-    # the same problems one after another on one stream
+    # stick to their handles from the first batch on)
+    work = steps * sum(st["evaluated"] + st["pivoted"] for st in (h.stats() for h in hs))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    work1 = 0
     for h in hs:
         h.run()
-        st = h.stats()
-        work1 += st["evaluated"] + st["pivoted"]
     torch.cuda.synchronize()
     single = time.perf_counter() - t1
-    statuses = [h.stats()["status"] for h in hs]
-    escal = [i for i, h in enumerate(hs) if h.stats()["escalated"]]
-    errs = [h.stats()["sampled_err"] for h in hs]
-    out = {
-        "metric": METRIC, "value": work / elapsed, "unit": "entries/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "batch512_mixed_d3-6_n16-128_eps1e-6", "problems": len(hs)},
-        "solves_per_s": len(hs) / (elapsed / args.steps),
-        "one_at_a_time": {"s": single, "entries_per_s": work1 / single, "solves_per_s": len(hs) / single},
-        "batched_over_one_at_a_time": single / (elapsed / args.steps),
-        "statuses": {str(k): statuses.count(k) for k in sorted(set(statuses))},
-        "escalated_to_fp64": escal,
-        "sampled_err_max": max(errs),
-    }
-    print(json.dumps(out), flush=True)
+    stats = [h.stats() for h in hs]
+    statuses = [s["status"] for s in stats]
+    for h in hs:
+        h.close()
+    return {"workload": "batch512_mixed_d3-6_n16-128_eps1e-6", "problems": len(hs), "batches": steps,
+            "ms_per_batch": elapsed / steps * 1e3, "solves_per_s": len(hs) * steps / elapsed,
+            "entries_per_s": work / elapsed, "first_batch_with_allocation_s": first,
+            "one_at_a_time": {"s": single, "solves_per_s": len(hs) / single},
+            "batched_over_one_at_a_time": single / (elapsed / steps),
+            "statuses": {str(k): statuses.count(k) for k in sorted(set(statuses))},
+            "escalated_to_fp64": [i for i, s in enumerate(stats) if s["escalated"]],
+            "sampled_err_max": max(s["sampled_err"] for s in stats)}
 
 
-def bench_serve(args):
-    """Served trace: requests d in {4,5,6}, n in {32,64,128,256}, eps in
-    {1e-4, 1e-8} (FP32 / FP64 sweeps by the precision policy), half Hilbert,
-    half bi-Maxwellian, rank cap 32, two subtensor blocks per mode.  First the
-    whole trace at once (capacity), then Poisson arrivals at rate_frac of that
-    capacity (latency = completion - arrival, queueing included), then the
-    first requests one at a time through the single-solve path."""
+def _pct(v, q):
+    v = sorted(v)
+    return v[min(len(v) - 1, int(q * len(v)))] * 1e3
+
+
+def measure_serve(requests, repeats=3, rate_frac=0.8, budget_gib=64.0, slots=64, sweep=False):
+    """A served trace through the continuous-batching server: requests d in
+    {4,5,6}, n in {32,64,128,256}, eps in {1e-4,1e-8} (FP32 / FP64 sweeps by
+    the precision policy), half Hilbert, half bi-Maxwellian, rank cap 32, two
+    subtensor blocks per mode.  Capacity: the whole list submitted at once.
+    Latency (completion - arrival, queueing included): Poisson arrivals at
+    rate_frac of the capacity, repeated.  One at a time: the same list
+    through the single-solve path, each request on a handle whose buffers
+    exist before its solve is timed."""
+    import torch
     from paper_2407_11290_amd.api import Server, TTCross
     from paper_2407_11290_amd.workloads import served_trace
-    N = args.requests
+    N = requests
     specs = served_trace(count=N)
-    srv = Server(int(args.budget_gib * (1 << 30)), max_slots=args.slots, r_max=32, grid=2)
+    srv = Server(int(budget_gib * (1 << 30)), max_slots=slots, r_max=32, grid=2)
 
     def run_all(arrivals):
         t0 = time.perf_counter()
@@ -420,57 +460,296 @@ def bench_serve(args):
     for t in warm:
         srv.wait(t)
         srv.release(t)
-    print(f"bench: warm-up {len(warm)} shapes, pool {srv.stats()['pool_bytes'] / 2**30:.1f} GiB",
-          file=sys.stderr, flush=True)
-    cap_s, cap_lat, cap_work, cap_st = run_all([0.0] * N)
+    cap_s, _l, cap_work, cap_st = run_all([0.0] * N)
     capacity = N / cap_s
-    print(f"bench: closed loop {N} requests in {cap_s:.2f} s ({capacity:.0f} solves/s)", file=sys.stderr, flush=True)
-    def pct(v, q):
-        v = sorted(v)
-        return v[min(len(v) - 1, int(q * len(v)))] * 1e3
-
-    sweep = []
-    for frac in (0.25, 0.5, 1.0, 1.25):
-        r = frac * capacity
-        s_, l_, _w, _st = run_all([p.arrival_s for p in served_trace(count=N, rate_hz=r)])
-        sweep.append({"rate_frac": frac, "rate_per_s": r, "solves_per_s": N / s_, "p50_ms": pct(l_, 0.5),
-                      "p99_ms": pct(l_, 0.99)})
-        print(f"bench: open loop at {frac:.2f} x capacity: p50 {pct(l_, 0.5):.2f} ms p99 {pct(l_, 0.99):.2f} ms",
-              file=sys.stderr, flush=True)
-    rate = args.rate_frac * capacity
-    arrivals = [p.arrival_s for p in served_trace(count=N, rate_hz=rate)]
-    open_s, lat, work, st = run_all(arrivals)
-    lat_ms = sorted(x * 1e3 for x in lat)
-    print(f"bench: open loop at {rate:.0f}/s done in {open_s:.2f} s", file=sys.stderr, flush=True)
+    runs = []
+    for r in range(repeats):
+        arrivals = [p.arrival_s for p in served_trace(count=N, rate_hz=rate_frac * capacity)]
+        s_, l_, w_, st_ = run_all(arrivals)
+        runs.append({"s": s_, "p50_ms": _pct(l_, 0.5), "p99_ms": _pct(l_, 0.99), "solves_per_s": N / s_,
+                     "entries_per_s": w_ / s_, "statuses": {str(k): v for k, v in sorted(st_.items())}})
+    lam = []
+    if sweep:
+        for frac in (0.25, 0.5, 1.0, 1.25):
+            s_, l_, _w, _st = run_all([p.arrival_s for p in served_trace(count=N, rate_hz=frac * capacity)])
+            lam.append({"rate_frac": frac, "solves_per_s": N / s_, "p50_ms": _pct(l_, 0.5), "p99_ms": _pct(l_, 0.99)})
     srv_stats = srv.stats()
     srv.close()
-    # one at a time: the first requests through the single-solve path, each on
-    # a handle whose buffers already exist (allocation is not timed)
-    M = min(args.alone, N)
-    hs = [TTCross(p.n, p.eps, p.fn_id, p.params, seed=p.seed, r_max=32, grid=p.grid) for p in specs[:M]]
-    for h in hs:
+    torch.cuda.empty_cache()
+    # one at a time, the same list
+    alone, alone_work = 0.0, 0
+    for p in specs:
+        h = TTCross(p.n, p.eps, p.fn_id, p.params, seed=p.seed, r_max=32, grid=p.grid)
+        h.run()                                        # allocates
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
         h.run()
-    t1 = time.perf_counter()
-    for h in hs:
-        h.run()
-    alone_s = time.perf_counter() - t1
-    for h in hs:
+        alone += time.perf_counter() - t1
+        st = h.stats()
+        alone_work += st["evaluated"] + st["pivoted"]
         h.close()
+    p50s = [r["p50_ms"] for r in runs]
+    p99s = [r["p99_ms"] for r in runs]
+    return {"workload": f"serve_poisson_{N}req_d4-6_n32-256_eps1e-4or1e-8", "requests": N,
+            "rate_frac_of_capacity": rate_frac, "budget_gib": budget_gib, "slots": slots,
+            "capacity_solves_per_s": capacity, "capacity_entries_per_s": cap_work / cap_s,
+            "latency_ms": {"p50_median": statistics.median(p50s), "p99_median": statistics.median(p99s),
+                           "p50_runs": p50s, "p99_runs": p99s},
+            "open_loop_runs": runs, "lambda_sweep": lam,
+            "one_at_a_time": {"s": alone, "solves_per_s": N / alone, "entries_per_s": alone_work / alone},
+            "served_capacity_over_one_at_a_time": capacity / (N / alone),
+            "server": srv_stats}
+
+
+def host_cpu():
+    """CPU model and logical CPU count of this host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, usable
+
+
+def cpu_baseline_all_cores(seconds):
+    """The FP64 oracle on the bench workload, complete solves of seeds 0..4 in
+    turn, run side by side in host threads on every usable core (at most 16,
+    the host share of one GPU), then single-threaded for comparison."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import Oracle
+    from oracle.oracle import FN_HILBERT
+    model, nproc, usable = host_cpu()
+    threads = max(1, min(16, usable))
+
+    def worker(w):
+        done, work, solves = 0.0, 0, 0
+        t0 = time.perf_counter()
+        i = w
+        while done < seconds:
+            o = Oracle(N, EPS, FN_HILBERT, seed=SEEDS[i % len(SEEDS)])
+            o.run()
+            st = o.stats()
+            work += st["evaluated"] + st["pivoted"]
+            solves += 1
+            i += threads
+            done = time.perf_counter() - t0
+        return work, solves, done
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        res = list(ex.map(worker, range(threads)))
+    wall = time.perf_counter() - t0
+    work = sum(r[0] for r in res)
+    solves = sum(r[1] for r in res)
+    single = cpu_baseline(min(4.0, seconds))
+    return {"value": work / wall, "unit": "entries/s", "cores": threads, "kind": "oracle",
+            "sample": f"{solves} complete FP64 oracle solves of the same workload (seeds 0..4 in turn) in "
+                      f"{threads} host threads side by side, {wall:.1f} s",
+            "cpu_model": model, "nproc": nproc, "usable_cpus": usable,
+            "single_thread": {"value": single["value"], "sample": single["sample"]}}
+
+
+def cpu_baseline(seconds):
+    from oracle import Oracle
+    from oracle.oracle import FN_HILBERT
+    done, work, seeds = 0.0, 0, []
+    t0 = time.perf_counter()
+    i = 0
+    while True:
+        seed = SEEDS[i % len(SEEDS)]
+        o = Oracle(N, EPS, FN_HILBERT, seed=seed)
+        o.run()
+        st = o.stats()
+        work += st["evaluated"] + st["pivoted"]
+        seeds.append(seed)
+        i += 1
+        done = time.perf_counter() - t0
+        if done >= seconds:
+            break
+    return {"value": work / done, "unit": "entries/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(seeds)} complete FP64 oracle solves of the same workload, seeds {seeds}, "
+                      f"{done:.1f} s, one host thread"}
+
+
+def bench_batch(args):
+    """Mixed batch of 512 problems (d 3..6, n 16..128, Hilbert / bi-Maxwellian,
+    eps 1e-6, FP32 sweeps by the precision policy): one batched solve per step
+    against the same problems solved one at a time."""
+    m = measure_batch(args.steps, args.warmup)
+    print(f"bench: {args.steps} batched steps, {m['ms_per_batch']:.2f} ms per batch", file=sys.stderr, flush=True)
     out = {
-        "metric": METRIC, "value": work / open_s, "unit": "entries/s", "n_gpus": 1, "steps": 1, "warmup": 1,
-        "ms_per_step": open_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": f"serve_poisson_{N}req_d4-6_n32-256_eps1e-4or1e-8", "requests": N,
-                   "rate_per_s": rate, "rate_frac_of_capacity": args.rate_frac, "budget_gib": args.budget_gib},
-        "latency_ms": {"p50": lat_ms[len(lat_ms) // 2], "p99": lat_ms[min(len(lat_ms) - 1, int(0.99 * len(lat_ms)))],
-                       "max": lat_ms[-1]},
-        "solves_per_s": N / open_s, "capacity_solves_per_s": capacity,
-        "closed_loop_entries_per_s": cap_work / cap_s,
-        "lambda_sweep": sweep,
-        "one_at_a_time": {"requests": M, "s": alone_s, "solves_per_s": M / alone_s},
-        "statuses": {str(k): v for k, v in sorted(st.items())},
-        "server": srv_stats,
+        "metric": METRIC, "value": m["entries_per_s"], "unit": "entries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": m["ms_per_batch"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": m["workload"], "problems": m["problems"]},
     }
+    out.update({k: v for k, v in m.items() if k not in ("workload", "problems")})
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Served trace through the continuous-batching server (see
+    measure_serve): capacity, Poisson-arrival latency at rate_frac of the
+    capacity (three runs) and a rate sweep, and the same request list one at
+    a time through the single-solve path."""
+    m = measure_serve(args.requests, repeats=3, rate_frac=args.rate_frac, budget_gib=args.budget_gib,
+                      slots=args.slots, sweep=True)
+    print(f"bench: serve capacity {m['capacity_solves_per_s']:.0f} solves/s, p50/p99 "
+          f"{m['latency_ms']['p50_median']:.2f}/{m['latency_ms']['p99_median']:.2f} ms", file=sys.stderr, flush=True)
+    run = m["open_loop_runs"][0]
+    out = {
+        "metric": METRIC, "value": run["entries_per_s"], "unit": "entries/s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": run["s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": m["workload"], "requests": m["requests"], "rate_frac_of_capacity": args.rate_frac,
+                   "budget_gib": args.budget_gib},
+    }
+    out.update({k: v for k, v in m.items() if k not in ("workload", "requests")})
+    print(json.dumps(out), flush=True)
+
+
+MAXWELL_PROFILE = os.path.join(ROOT, "profiles", "k_sweep_maxwell6d_n128_fp32.md")
+
+
+def sweep_valu_flops(path):
+    """FP32 VALU flops per search launch from a committed rocprofv3 counter
+    summary; None when the kernel sources changed since."""
+    try:
+        with open(path) as f:
+            kv = dict(line.split(": ", 1) for line in f.read().splitlines()
+                      if line.startswith(("valu_flops_per_launch:", "kernel_sources_sha256_16:",
+                                          "traffic_per_launch_bytes:")))
+    except OSError:
+        return None
+    if kv.get("kernel_sources_sha256_16", "").strip() != kernel_sources_hash():
+        return None
+    return {k: float(v) for k, v in kv.items() if k != "kernel_sources_sha256_16"}
+
+
+def bench_maxwell(args):
+    """The 6D Maxwellian phase-space configuration alone (see
+    measure_maxwell6d): FP32 entry evaluation and sweeps, FP64 check, stop
+    test, pivot block and cores.  The roofline figure is for its search
+    kernel k_sweep<float, generic>, where the in-solve entry evaluation runs:
+    HBM (algorithmic bytes over the dispatch-attached event time) and, from
+    the committed counter summary, FP32 VALU flops per launch."""
+    m = measure_maxwell6d(args.steps, profile=True)
+    sk = m["search_kernel"]
+    us = sk["avg_launch_us"]
+    hbm = {"bound": "hbm", "achieved": sk["bytes_per_launch"] / (us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS,
+           "unit": "GB/s"}
+    hbm["frac"] = hbm["achieved"] / hbm["peak"]
+    prof = sweep_valu_flops(MAXWELL_PROFILE)
+    hbm["traffic"] = prof.get("traffic_per_launch_bytes") if prof else None
+    valu = None
+    if prof and "valu_flops_per_launch" in prof:
+        valu = {"bound": "alu", "achieved": prof["valu_flops_per_launch"] / (us * 1e-6) / 1e12,
+                "peak": VALU_PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
+                "flops_per_launch": prof["valu_flops_per_launch"]}
+        valu["frac"] = valu["achieved"] / valu["peak"]
+    roof = dict(hbm if (valu is None or hbm["frac"] >= valu["frac"]) else valu)
+    roof.update({"kernel": "k_sweep<float, generic>", "avg_launch_us": us, "launches": sk["launches"],
+                 "bytes_per_launch": sk["bytes_per_launch"], "hbm": hbm, "valu": valu})
+    out = {
+        "metric": METRIC, "value": m["entries_per_s"], "unit": "entries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": m["ms_per_solve_wall"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": m["workload"], "seeds": MAXWELL_SEEDS},
+        "time_to_eps_ms": m["time_to_eps_ms"], "roofline": roof,
+        "sampled_rel_error_vs_fp64_entries": m["sampled_rel_error_vs_fp64_entries"], "ranks": m["ranks"],
+        "sweep_precision": m["sweep_precision"], "escalated": m["escalated"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_phases(args):
+    """Where a sweep's time goes: the bench workload solved with the
+    instrumented library (libttcross_stamps.so), whose search and commit
+    kernels record the device's 100 MHz clock at phase boundaries
+    (tt_cross_get_stamps).  Per sweep: the search launch's span (first
+    workgroup entry to last workgroup end), each workgroup's phases, the
+    commit's phases and the gaps between the launches; averaged over the
+    sweeps of args.steps solves.  The instrumentation adds a few stores per
+    workgroup, so absolute times are slightly above the normal build's."""
+    import ctypes as C
+    import numpy as np
+    from paper_2407_11290_amd import FN_HILBERT, PREC_FP64, _lib
+    from paper_2407_11290_amd.api import TTCross
+    assert _lib.LIB_PATH.endswith("libttcross_stamps.so"), _lib.LIB_PATH
+    L = _lib.load()
+    hs = [TTCross(N, EPS, FN_HILBERT, seed=s, precision=PREC_FP64, grid=GRID) for s in SEEDS]
+    for h in hs:
+        h.run()
+    tick_us = 0.01                                          # 100 MHz clock
+    acc = {}
+
+    def add(key, vals):
+        vals = [float(v) * tick_us for v in vals]
+        if vals:
+            acc.setdefault(key, []).extend(vals)
+
+    sweeps_total, solves = 0, 0
+    for i in range(args.steps):
+        h = hs[i % len(hs)]
+        h.run()
+        lay = (C.c_int32 * 4)()
+        m = L.tt_cross_get_stamps(h.h, None, 0, lay)
+        buf = np.zeros(m, dtype=np.uint64)
+        _lib.check(L.tt_cross_get_stamps(h.h, buf.ctypes.data_as(C.c_void_p), m, lay))
+        W16, W, S, nsw = lay[0], lay[1], lay[2], lay[3]
+        search = buf[: S * W * W16].reshape(S, W, W16).astype(np.int64)
+        commit = buf[S * W * W16:].reshape(S, W16).astype(np.int64)
+        prev_commit_end = None
+        for s in range(min(nsw, S)):
+            r = search[s]
+            act = (r[:, 0] != 0) & (r[:, 9] != 0)
+            if not act.any():
+                continue
+            r = r[act]
+            t0, t1 = r[:, 0].min(), r[:, 9].max()
+            add("search_span", [t1 - t0])
+            add("search_entry_spread", [r[:, 0].max() - t0])
+            add("wg_state_load", r[:, 1] - r[:, 0])
+            add("wg_total", r[:, 9] - r[:, 0])
+            nt = r[r[:, 10] > 0]
+            add("new_tile_geometry", nt[:, 2] - nt[:, 1])
+            add("new_tile_staging", nt[:, 3] - nt[:, 2])
+            add("new_tile_raw_factors", nt[:, 4] - nt[:, 3])
+            add("new_tile_factor_solves", nt[:, 5] - nt[:, 4])
+            add("new_tile_entries", nt[:, 6] - nt[:, 5])
+            st = r[(r[:, 7] > 0) & (r[:, 10] == 0)]
+            add("stored_tile_geometry", st[:, 7] - st[:, 1])
+            add("stored_tile_data", st[:, 8] - st[:, 7])
+            add("new_tiles_per_launch", [int((r[:, 10]).sum()) / tick_us])
+            add("workgroups_per_launch", [int(act.sum()) / tick_us])
+            c = commit[s]
+            if c[0] and c[4]:
+                add("gap_search_to_commit", [c[0] - t1])
+                add("commit_span", [c[4] - c[0]])
+                add("commit_state_load", [c[1] - c[0]])
+                add("commit_candidate_scan", [c[2] - c[1]])
+                add("commit_decide_append", [c[3] - c[2]])
+                add("commit_shapes_publish", [c[4] - c[3]])
+                if prev_commit_end is not None:
+                    add("gap_commit_to_search", [t0 - prev_commit_end])
+                prev_commit_end = c[4]
+            sweeps_total += 1
+        solves += 1
+    out = {"metric": METRIC, "value": None, "unit": "us", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+           "ms_per_step": None, "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "hilbert6d_n64_grid2x2x2x2x2x2_eps1e-8_fp64_phase_stamps", "solves": solves,
+                      "sweeps": sweeps_total},
+           "phases_us": {k: {"mean": float(np.mean(v)), "median": float(np.median(v)), "p90": float(np.percentile(v, 90)),
+                             "n": len(v)} for k, v in acc.items()}}
     print(json.dumps(out), flush=True)
 
 
@@ -479,10 +758,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="hilbert6d", choices=["hilbert6d", "batch512", "serve", "eval", "rook", "paper"],
-                    help="hilbert6d: the single-solve benchmark line; batch512: the mixed 512-problem "
+    ap.add_argument("--workload", default="hilbert6d",
+                    choices=["hilbert6d", "maxwell6d", "batch512", "serve", "eval", "rook", "paper", "phases"],
+                    help="hilbert6d: the single-solve benchmark line (with summaries of the other "
+                         "configurations); maxwell6d: the 6D Maxwellian with FP32 sweeps; batch512: the mixed 512-problem "
                          "batch, solved together and one at a time; serve: a Poisson-arrival trace "
                          "through the continuous-batching server; eval: bulk entry evaluation of the 6D "
                          "Maxwellian in FP32 and FP64; rook: rook pivoting on the 3D Hilbert tensor with "
@@ -490,9 +771,11 @@ def main():
                          "prescribed ranks")
     ap.add_argument("--eval-m", type=int, default=1 << 24, help="eval: multi-indices per step")
     ap.add_argument("--requests", type=int, default=2000, help="serve: trace length")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="hilbert6d: leave out the summaries of the Maxwellian, batch and serving configurations")
+    ap.add_argument("--extra-requests", type=int, default=400, help="hilbert6d: served requests in the summary")
     ap.add_argument("--rate-frac", type=float, default=0.8, help="serve: arrival rate / measured capacity")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="serve: HBM budget of the server")
-    ap.add_argument("--alone", type=int, default=200, help="serve: requests timed one at a time")
     ap.add_argument("--slots", type=int, default=64, help="serve: solves in flight at most")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain copy kernel (out = -in, FP64) over this many MiB, five times; "
@@ -503,6 +786,8 @@ def main():
               "(see DESIGN.md for how it would shard). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "phases":
+        os.environ["TT_CROSS_LIB"] = "stamps"           # the instrumented library
     import torch
     torch.cuda.init()
     if args.calib_copy_mib > 0:
@@ -516,6 +801,10 @@ def main():
         return
     from paper_2407_11290_amd import FN_HILBERT, PREC_FP64
     from paper_2407_11290_amd.api import TTCross
+    if args.workload == "maxwell6d":
+        return bench_maxwell(args)
+    if args.workload == "phases":
+        return bench_phases(args)
     if args.workload == "batch512":
         return bench_batch(args)
     if args.workload == "serve":
@@ -592,8 +881,18 @@ def main():
                      "sweep_phase_us_per_solve": phase_s / args.steps * 1e6,
                      "sweep_kernels_us_per_solve": kern_s / args.steps * 1e6},
     }
+    if not args.no_extras:
+        # the other configurations of the workload list, measured in the same
+        # run: the 6D Maxwellian with FP32 sweeps, the 512-problem batch and
+        # the served trace (their own workloads give the full lines)
+        out["maxwell6d_fp32"] = measure_maxwell6d(10)
+        print("bench: maxwellian summary done", file=sys.stderr, flush=True)
+        out["batch512"] = measure_batch(5)
+        print("bench: batch summary done", file=sys.stderr, flush=True)
+        out["serve"] = measure_serve(args.extra_requests, repeats=3)
+        print("bench: serving summary done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline_all_cores(args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
