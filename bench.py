@@ -30,6 +30,8 @@ import statistics
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -229,6 +231,42 @@ PAPER_CASES = [
 ]
 
 
+# The accuracy panels of Sec. 5.2/5.3: the four workloads of Table 5 with every
+# core rank raised step by step to its prescribed value (rank m uses
+# min(m, r_k) for unfolding k, from m = 2), the sampled error of Sec. 5 at
+# each step, and the share of the tensor's entries that the run evaluated.
+ERROR_CURVE_CASES = ["hilbert3d_n2000", "hilbert6d_n300", "maxwell2d2v", "maxwell3d3v"]
+
+
+def paper_error_curves(fns, samples=1_000_000):
+    """Per case: [(ranks, sampled error, evaluated / prod(n), device ms)]."""
+    import torch
+    from paper_2407_11290_amd import PREC_FP64
+    from paper_2407_11290_amd.api import TTCross
+    out = {}
+    for name, n, fn, caps, *_ in PAPER_CASES:
+        if name not in ERROR_CURVE_CASES:
+            continue
+        total = float(np.prod([float(x) for x in n]))
+        h = TTCross(n, 0.0, fns[fn], seed=0, grid=[2] * len(n), precision=PREC_FP64, r_max=max(caps))
+        rows = []
+        for m in range(2, max(caps) + 1):
+            step = [min(m, c) for c in caps]
+            if rows and step == rows[-1]["ranks"][1:-1]:
+                continue
+            h.set_rank_caps(step)
+            h.run()
+            st = h.stats()
+            rows.append({"ranks": [int(x) for x in h.ranks()], "sampled_rel_error": h.sampled_error(samples),
+                         "evaluated_fraction": st["evaluated"] / total, "time_ms": st["time_to_eps_s"] * 1e3})
+        out[name] = rows
+        print(f"bench: error curve {name}: {len(rows)} points, last error {rows[-1]['sampled_rel_error']:.2e}",
+              file=sys.stderr, flush=True)
+        h.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_paper(args):
     """The paper's own workloads at its shapes and prescribed ranks (eps = 0,
     every unfolding runs to its rank), FP64, 2 blocks per mode, greedy
@@ -306,6 +344,7 @@ def bench_paper(args):
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "paper_sec5_workloads_prescribed_ranks_fp64", "cases": [r["case"] for r in rows]},
         "cases": rows, "roofline": roof, "cpu_baseline": cpu,
+        "error_curves": paper_error_curves(fns),
     }
     print(json.dumps(out), flush=True)
 
@@ -725,6 +764,11 @@ def bench_phases(args):
             add("new_tile_raw_factors", nt[:, 4] - nt[:, 3])
             add("new_tile_factor_solves", nt[:, 5] - nt[:, 4])
             add("new_tile_entries", nt[:, 6] - nt[:, 5])
+            add("new_tile_entries_loop", nt[:, 12] - nt[:, 5])
+            add("new_tile_reduce", nt[:, 6] - nt[:, 12])
+            sr = nt[nt[:, 13] > 0]
+            add("new_tile_row_solves", sr[:, 13] - sr[:, 4])
+            add("new_tile_col_solves", sr[:, 5] - sr[:, 13])
             st = r[(r[:, 7] > 0) & (r[:, 10] == 0)]
             add("stored_tile_geometry", st[:, 7] - st[:, 1])
             add("stored_tile_data", st[:, 8] - st[:, 7])

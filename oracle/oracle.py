@@ -38,6 +38,7 @@ def lib():
         L.orc_get_stats.argtypes = [P, f64p, i32p]
         L.orc_get_history.argtypes = [P, C.c_int, f64p, C.c_int]
         L.orc_get_rook_rounds.argtypes = [P]
+        L.orc_get_gap_history.argtypes = [P, C.c_int, f64p, C.c_int]
         L.orc_get_cores.restype = C.c_int64
         L.orc_get_cores.argtypes = [P, P, C.c_int64]
         L.orc_state_tt_eval.argtypes = [P, C.c_int64, i32p, f64p]
@@ -189,6 +190,13 @@ class Oracle:
     def rook_rounds(self):
         """Most rounds of Alg. 1's loop any block search took (rook mode)."""
         return int(lib().orc_get_rook_rounds(self.h))
+
+    def gap_history(self, k):
+        """Per sweep of unfolding k: (best - runner-up) / best of the search."""
+        cap = 4096
+        out = np.zeros(cap, dtype=np.float64)
+        m = lib().orc_get_gap_history(self.h, k, out, cap)
+        return out[:m].copy()
 
     def history(self, k):
         cap = 4096

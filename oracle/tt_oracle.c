@@ -315,6 +315,7 @@ typedef struct orc_state {
     int64_t *gam[ORC_MAX_D + 1];     /* pivot column positions */
     double *piv[ORC_MAX_D + 1];      /* pivot residuals p_z */
     double *best_hist[ORC_MAX_D + 1];/* per sweep: largest unmasked |residual| */
+    double *gap_hist[ORC_MAX_D + 1]; /* per sweep: (best - runner-up) / best, 1 if none */
     int sweeps, hist_cap;
     double rms, tau;
     int i0[ORC_MAX_D];
@@ -335,7 +336,7 @@ static void orc_free_state(orc_state *S)
     if (!S) return;
     for (int k = 0; k <= ORC_MAX_D; ++k) {
         free(S->I[k]); free(S->J[k]); free(S->rho[k]); free(S->gam[k]); free(S->piv[k]);
-        free(S->best_hist[k]);
+        free(S->best_hist[k]); free(S->gap_hist[k]);
     }
     free(S->params_copy);
     free(S->cores);
@@ -372,7 +373,8 @@ orc_state *orc_create(int d, const int *n, double eps, int fn_id, const double *
         S->gam[k] = (int64_t *)calloc(r_max, sizeof(int64_t));
         S->piv[k] = (double *)calloc(r_max, sizeof(double));
         S->best_hist[k] = (double *)calloc(S->hist_cap, sizeof(double));
-        if (!S->I[k] || !S->J[k] || !S->rho[k] || !S->gam[k] || !S->piv[k] || !S->best_hist[k]) {
+        S->gap_hist[k] = (double *)calloc(S->hist_cap, sizeof(double));
+        if (!S->I[k] || !S->J[k] || !S->rho[k] || !S->gam[k] || !S->piv[k] || !S->best_hist[k] || !S->gap_hist[k]) {
             orc_free_state(S);
             return NULL;
         }
@@ -698,7 +700,10 @@ int orc_run(orc_state *S)
             if (found < 0) return S->status;
             prop[k] = 0;
             double a = found ? fabs(bv) : 0.0;
-            if (S->sweeps < S->hist_cap) S->best_hist[k][S->sweeps] = a;
+            if (S->sweeps < S->hist_cap) {
+                S->best_hist[k][S->sweeps] = a;
+                S->gap_hist[k][S->sweeps] = (found && a > 0.0 && !S->rook) ? (a - runner) / a : 1.0;
+            }
             if (found && a > S->tau) {
                 if (a > 0.0 && !S->rook) {
                     double g = (a - runner) / a;
@@ -843,6 +848,20 @@ int orc_get_stats(const orc_state *S, double *out, int *i0)
     out[4] = S->sweeps; out[5] = S->min_rel_gap; out[6] = S->status;
     if (i0) for (int j = 0; j < S->d; ++j) i0[j] = S->i0[j];
     return ORC_OK;
+}
+
+/* Per sweep of unfolding k: the relative gap (best - runner-up) / best
+ * between the largest unmasked |residual| and the largest one not bitwise
+ * equal to it (greedy search; 1 when there is none).  A pivot decided by a
+ * gap at the level of rounding may legitimately differ in an arithmetic
+ * whose last bits differ (another exp). */
+int orc_get_gap_history(const orc_state *S, int k, double *out, int cap)
+{
+    if (!S || !S->ran || k < 1 || k > S->d - 1) return ORC_EINVAL;
+    int m = S->sweeps < cap ? S->sweeps : cap;
+    if (m > S->hist_cap) m = S->hist_cap;
+    memcpy(out, S->gap_hist[k], sizeof(double) * m);
+    return m;
 }
 
 /* Most rounds of Alg. 1's loop that any block search of the last run took
