@@ -766,9 +766,6 @@ def bench_phases(args):
             add("new_tile_entries", nt[:, 6] - nt[:, 5])
             add("new_tile_entries_loop", nt[:, 12] - nt[:, 5])
             add("new_tile_reduce", nt[:, 6] - nt[:, 12])
-            sr = nt[nt[:, 13] > 0]
-            add("new_tile_row_solves", sr[:, 13] - sr[:, 4])
-            add("new_tile_col_solves", sr[:, 5] - sr[:, 13])
             st = r[(r[:, 7] > 0) & (r[:, 10] == 0)]
             add("stored_tile_geometry", st[:, 7] - st[:, 1])
             add("stored_tile_data", st[:, 8] - st[:, 7])

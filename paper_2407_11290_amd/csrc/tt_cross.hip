@@ -667,13 +667,22 @@ template <typename V> int Problem::launch_ahead()
 // copy are queued, or an error.
 template <typename V> int Problem::poll_sweeps(bool wait)
 {
+    // the mapped counter is read in a tight loop; the stream itself (to see
+    // that it drained without a new count, or failed) is queried only after
+    // 50 us without progress, so that a waiting host reacts to the device
+    // at the speed of a memory read
+    auto t_last = std::chrono::steady_clock::now();
     for (;;) {
         bool progressed = false, stopped = false;
         const int sd = __atomic_load_n(&hm->sweeps_done, __ATOMIC_ACQUIRE);
         if (sd > done_known) {
             done_known = sd;
             progressed = true;
+            t_last = std::chrono::steady_clock::now();
+        } else if (wait && std::chrono::steady_clock::now() - t_last < std::chrono::microseconds(50)) {
+            continue;
         } else {
+            t_last = std::chrono::steady_clock::now();
             hipError_t q = hipStreamQuery(stream);
             if (q != hipErrorNotReady) {
                 if (q != hipSuccess) return set_err(TT_EDEVICE, "sweep failed: %s", hipGetErrorString(q));

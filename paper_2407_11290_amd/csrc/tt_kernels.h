@@ -24,6 +24,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <utility>
 
 #include "tt_device.h"
 
@@ -141,8 +142,28 @@ __device__ inline void wave_best(double &v, uint64_t &key, double &sv)
     }
 }
 
+// Workgroup-wide (max |value|, lowest key) reduction whose result is valid
+// in thread 0 only (one barrier).  The caller's next barrier must come
+// before the shared slots are written again.
+__device__ inline void block_best_t0(double &v, uint64_t &key, double &sv)
+{
+    __shared__ double s_v[NT / 64], s_sv[NT / 64];
+    __shared__ uint64_t s_k[NT / 64];
+    wave_best(v, key, sv);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0 && w > 0) { s_v[w] = v; s_k[w] = key; s_sv[w] = sv; }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int i = 1; i < NT / 64; ++i)
+            if (better(s_v[i], s_k[i], v, key)) { v = s_v[i]; key = s_k[i]; sv = s_sv[i]; }
+}
+
 // Stored residuals, one wavefront per tile: apply the newest pivot (if any)
-// and search.  All loads of a batch are issued before any is used.
+// and search.  Every load of a batch -- the column's pivot mask, the pivot
+// row's entry (its U factor before the division) and the tile entries -- is
+// issued before any of them is used, from addresses that are always valid
+// (clamped), so that a batch costs one round trip; the rows' masks and W
+// factors of a 64-row chunk are in flight with the first batch.
 template <typename V, int B>
 __device__ void stored_tile_wave(const KDev &K, const KSweep &ks, const TileGeom &g, double &bv, uint64_t &bk,
                                  double &bs)
@@ -153,27 +174,32 @@ __device__ void stored_tile_wave(const KDev &K, const KSweep &ks, const TileGeom
     const bool colok = tcol < g.ncols;
     const gptr_t<V> E = as_global((V *)K.E);
     const gptr_t<const uint8_t> rpiv = as_global((const uint8_t *)K.rpiv);
+    const gptr_t<const uint8_t> cpiv = as_global((const uint8_t *)K.cpiv);
     const int64_t ld = K.ld;
     const int col = g.col0 + (colok ? tcol : 0);
-    const bool live = colok && !as_global((const uint8_t *)K.cpiv)[col];
     const bool apply = ks.apply != 0;
-    V u = 0;
-    if (apply) u = E[(int64_t)ks.arho * ld + col] / (V)ks.apiv;
+    const int64_t urow = apply ? ks.arho : g.row0;   // any valid row when nothing is applied
+    const int wcol = apply ? ks.agam : col;
     // per 64 tile rows: lane l fetches row l's mask and pivot-column factor in
     // one instruction each, and they reach the other lanes by shuffles; every
-    // lane runs the same iterations so that the shuffles see all lanes
+    // lane runs the same iterations so that the shuffles see all lanes (a
+    // value is used only for rows below nch, whose lanes loaded it)
     for (int c0 = 0; c0 < g.nrows; c0 += 64) {
         const int nch = min(64, g.nrows - c0);
         const int rrow = g.row0 + c0 + (lane < nch ? lane : 0);
-        const int rpl = (lane < nch) ? rpiv[rrow] : 1;
-        const V wl = (apply && lane < nch) ? E[(int64_t)rrow * ld + ks.agam] : (V)0;
+        const int rpl = rpiv[rrow];
+        const V wl = E[(int64_t)rrow * ld + wcol];
         for (int base = 0; base < nch; base += B * rpw) {
+            const int cp = cpiv[col];
+            const V ue = E[urow * ld + col];
             V xv[B];
 #pragma unroll
             for (int b = 0; b < B; ++b) {
-                const int ii = base + tr + b * rpw;
-                xv[b] = (ii < nch) ? E[(int64_t)(g.row0 + c0 + ii) * ld + col] : (V)0;
+                const int ii = min(base + tr + b * rpw, nch - 1);
+                xv[b] = E[(int64_t)(g.row0 + c0 + ii) * ld + col];
             }
+            const bool live = colok && !cp;
+            const V u = apply ? ue / (V)ks.apiv : (V)0;
 #pragma unroll
             for (int b = 0; b < B; ++b) {
                 const int ii = base + tr + b * rpw;
@@ -195,6 +221,75 @@ __device__ void stored_tile_wave(const KDev &K, const KSweep &ks, const TileGeom
     }
 }
 
+// Value of lane n of each 16-lane row of the wavefront (DPP row broadcast:
+// a register move, no LDS round trip).  Every lane of the row must be active.
+template <int n> __device__ inline double row_bcast(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x150 + n, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x150 + n, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int n> __device__ inline float row_bcast(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x150 + n, 0xf, 0xf, false));
+}
+
+// Factor solves of a new-entry tile for ranks rk <= RK <= 16: a 16-lane
+// group per row (column), lane z holding factor z; at step z' the finished
+// factor z' reaches the lanes z > z' of its group by a row broadcast.
+//   row i:    w_z = W_raw(i, z) - sum_{z'<z} w_z' U(z', gamma_z)
+//   column j: e_z = X(rho_z, j) - sum_{z'<z} W(rho_z, z') e_z' / p_z'
+// each sum in ascending z'.  Steps past rk - 1 change no lane below rk.
+template <typename V, int... Z>
+__device__ inline void row_steps(V &w, const V *Gr, int zl, bool ok, std::integer_sequence<int, Z...>)
+{
+    ((void)[&] {
+        const V wz = row_bcast<Z>(w);
+        if (ok && zl > Z) w = vfma<V>(-wz, Gr[tri(Z, zl)], w);
+    }(), ...);
+}
+template <typename V, int... Z>
+__device__ inline void col_steps(V &u, const V *Gc, const V *s_piv, int zl, bool ok, std::integer_sequence<int, Z...>)
+{
+    ((void)[&] {
+        const V uu = row_bcast<Z>(u) / s_piv[Z];
+        if (ok && zl > Z) u = vfma<V>(-Gc[tri(Z, zl)], uu, u);
+    }(), ...);
+}
+
+template <typename V, int RK>
+__device__ inline void solves_lg(gptr_t<V> E, int64_t ld, const TileGeom &g, V *Wt, V *Ut, const V *Gr,
+                                 const V *Gc, const V *s_piv, const int *s_rho, const int *s_gam, int TRm,
+                                 int TCm, int rk, int nrw, int ncw, bool rows_old, bool cols_old)
+{
+    const int tid = threadIdx.x, zl = tid & 15, gid = tid >> 4;
+    constexpr int ngroups = NT / 16;
+    using Steps = std::make_integer_sequence<int, RK - 1>;
+    for (int base = 0; base < nrw; base += ngroups) {
+        const int ii = base + gid;
+        const bool ok = ii < nrw && zl < rk;
+        V w = ok ? Wt[zl * TRm + ii] : (V)0;
+        row_steps<V>(w, Gr, zl, ok, Steps{});
+        if (ok) {
+            Wt[zl * TRm + ii] = w;
+            const int gz = s_gam[zl];
+            if (cols_old && gz >= g.col0 && gz < g.col0 + g.ncols) E[(int64_t)(g.row0 + ii) * ld + gz] = w;
+        }
+    }
+    for (int base = 0; base < ncw; base += ngroups) {
+        const int jj = base + gid;
+        const bool ok = jj < ncw && zl < rk;
+        V u = ok ? Ut[zl * TCm + jj] : (V)0;
+        col_steps<V>(u, Gc, s_piv, zl, ok, Steps{});
+        if (ok) {
+            const int rz = s_rho[zl];
+            if (rows_old && rz >= g.row0 && rz < g.row0 + g.nrows) E[(int64_t)rz * ld + g.col0 + jj] = u;
+            Ut[zl * TCm + jj] = u / s_piv[zl];
+        }
+    }
+}
+
 // New entries (rows of the newest prefix and/or columns of the newest suffix):
 // the generating function minus the interpolant, every pivot eliminated in
 // insertion order.  One workgroup per tile.  Factors of stored rows / columns
@@ -204,11 +299,25 @@ __device__ void stored_tile_wave(const KDev &K, const KSweep &ks, const TileGeom
 //   column j: e_z = X(rho_z, j);   for z' < z: e_z -= W(rho_z, z') * e_z'/p_z' -> p_z U(z, j)
 // and the frozen pivot columns / rows of the tile receive those values.
 template <typename V, int FNS>
-__device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSweep &ks, const TileGeom &g,
-                         double &bv, uint64_t &bk, double &bs, V *sm, unsigned long long *rec)
+__device__ void new_tile(const ProbDev *__restrict__ P, int nk, int u, int R, int C, const KSweep &ks, double &bv,
+                         uint64_t &bk, double &bs, V *sm, unsigned long long *rec)
 {
-    const int d = P->d, u = g.u, k = u + 1, tid = threadIdx.x, rk = ks.rk;
-    const bool rows_old = g.row0 < ks.nr_st, cols_old = g.col0 < ks.nc_st;
+    const int d = P->d, k = u + 1, tid = threadIdx.x, rk = ks.rk;
+    const KDev &K = P->kd[u];
+    // One round of scalar loads: the unfolding's descriptor and the
+    // neighbours' tuple arrays.  The tile's place follows by arithmetic; its
+    // extents (the tile tables) load together with the staging below.
+    const gptr_t<const int> Ipre = as_global((const int *)(k >= 2 ? P->kd[u - 1].Ifull : nullptr));
+    const gptr_t<const int> Jsuf = as_global((const int *)(u + 1 < nk ? P->kd[u + 1].Jfull : nullptr));
+    const int RTp = K.RTp, CTq = K.CTq;
+    const int tp = R / RTp, tt = R - tp * RTp, tq = C / CTq, ttc = C - tq * CTq;
+    // row (column) blocks are whole prefixes (suffixes), so whether the tile's
+    // rows (columns) were stored follows from the prefix (suffix) index alone
+    const bool rows_old = tp * K.nk < ks.nr_st, cols_old = tq * K.nk1 < ks.nc_st;
+    TileGeom g;
+    g.u = u; g.R = R; g.C = C; g.p = tp; g.q = tq;
+    g.ik0 = K.rt_start[tt]; g.nrows = K.rt_len[tt];
+    g.ik10 = K.ct_start[ttc]; g.ncols = K.ct_len[ttc];
     const gptr_t<V> E = as_global((V *)K.E);
     const gptr_t<const int> rho = as_global((const int *)K.rho), gam = as_global((const int *)K.gam);
     const gptr_t<const int> Ifull = as_global((const int *)K.Ifull), Jfull = as_global((const int *)K.Jfull);
@@ -226,9 +335,8 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSw
     V *Gc = Gr + ntri;                         // W(rho_z, z'), z' < z
     const int TCt = K.TC, rpp = NT / TCt;
     const int tr = tid / TCt, tcol = tid - tr * TCt;
-    const int cpv = (tcol < g.ncols) ? as_global((const uint8_t *)K.cpiv)[g.col0 + tcol] : 1;
-    if (tid < npre) pre[tid] = as_global((const int *)P->kd[u - 1].Ifull)[g.p * npre + tid];
-    if (tid < nsuf) suf[tid] = as_global((const int *)P->kd[u + 1].Jfull)[g.q * nsuf + tid];
+    if (tid < npre) pre[tid] = Ipre[g.p * npre + tid];
+    if (tid < nsuf) suf[tid] = Jsuf[g.q * nsuf + tid];
     // Hilbert entries depend on the integer index sum only: the pivots' tuple
     // sums replace the tuples
     __shared__ long long s_is[TT_MAX_RANK], s_js[TT_MAX_RANK];
@@ -246,9 +354,14 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSw
             s_js[z] = js;
         }
     }
-    for (int ii = tid; ii < g.nrows; ii += NT) s_rp[ii] = as_global((const uint8_t *)K.rpiv)[g.row0 + ii];
     __syncthreads();
     TT_STAMP(rec, 3);
+    // the tile's positions, and its row and column pivot masks (needed by the
+    // entries only) with the raw factors below
+    g.row0 = g.p * K.nk + g.ik0;
+    g.col0 = g.q * K.nk1 + g.ik10;
+    const int cpv = (tcol < g.ncols) ? as_global((const uint8_t *)K.cpiv)[g.col0 + tcol] : 1;
+    for (int ii = tid; ii < g.nrows; ii += NT) s_rp[ii] = as_global((const uint8_t *)K.rpiv)[g.row0 + ii];
     // raw factors: frozen entries, or the generating function at the skeleton
     if (rows_old) {
         for (int e = tid; e < rk * g.nrows; e += NT) {
@@ -310,48 +423,17 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSw
     }
     __syncthreads();
     TT_STAMP(rec, 4);
-    // chains as triangular solves.  Each factor sees the same operations in
+    // chains as triangular solves; each factor sees the same operations in
     // the same order as the written recursion, so both forms give the same
-    // bits.  Up to rank 16, a lane group per row (column): lane z holds
-    // factor z, and at step z' the finished factor z' reaches lanes z > z' by
-    // a shuffle.  Above that, one thread per row (column) runs the factors in
-    // ascending z and reads the finished lower ones back from LDS (a lane
-    // group would need too many passes over the tile).
+    // bits.  Up to rank 16 a lane group per row (column) with row broadcasts;
+    // above, one thread per row (column) runs the factors in ascending z and
+    // reads the finished lower ones back from LDS (a lane group would need
+    // too many passes over the tile).
     const int nrw = rows_old ? 0 : g.nrows, ncw = cols_old ? 0 : g.ncols;
-    if (rk <= 16) {
-        const int wid = tid >> 6, lane = tid & 63;
-        int G = 1;
-        while (G < rk) G <<= 1;
-        const int gpw = 64 / G, ngroups = (NT / 64) * gpw;
-        const int gid = wid * gpw + lane / G, zl = lane & (G - 1);
-        for (int base = 0; base < nrw; base += ngroups) {
-            const int ii = base + gid;
-            const bool ok = ii < nrw && zl < rk;
-            V w = ok ? Wt[zl * TRm + ii] : (V)0;
-            for (int zp = 0; zp + 1 < rk; ++zp) {
-                const V wzp = __shfl(w, zp, G);
-                if (ok && zl > zp) w = vfma<V>(-wzp, Gr[tri(zp, zl)], w);
-            }
-            if (ok) {
-                Wt[zl * TRm + ii] = w;
-                const int gz = s_gam[zl];
-                if (cols_old && gz >= g.col0 && gz < g.col0 + g.ncols) E[(int64_t)(g.row0 + ii) * ld + gz] = w;
-            }
-        }
-        for (int base = 0; base < ncw; base += ngroups) {
-            const int jj = base + gid;
-            const bool ok = jj < ncw && zl < rk;
-            V u = ok ? Ut[zl * TCm + jj] : (V)0;
-            for (int zp = 0; zp + 1 < rk; ++zp) {
-                const V uu = __shfl(u, zp, G) / s_piv[zp];
-                if (ok && zl > zp) u = vfma<V>(-Gc[tri(zp, zl)], uu, u);
-            }
-            if (ok) {
-                const int rz = s_rho[zl];
-                if (rows_old && rz >= g.row0 && rz < g.row0 + g.nrows) E[(int64_t)rz * ld + g.col0 + jj] = u;
-                Ut[zl * TCm + jj] = u / s_piv[zl];
-            }
-        }
+    if (rk <= 8) {
+        solves_lg<V, 8>(E, ld, g, Wt, Ut, Gr, Gc, s_piv, s_rho, s_gam, TRm, TCm, rk, nrw, ncw, rows_old, cols_old);
+    } else if (rk <= 16) {
+        solves_lg<V, 16>(E, ld, g, Wt, Ut, Gr, Gc, s_piv, s_rho, s_gam, TRm, TCm, rk, nrw, ncw, rows_old, cols_old);
     } else {
         for (int e = tid; e < nrw + ncw; e += NT) {
             if (e < nrw) {
@@ -384,35 +466,55 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KDev &K, const KSw
     }
     __syncthreads();
     TT_STAMP(rec, 5);
-    if (tcol < g.ncols) {
+    if (tcol < g.ncols && !cpv) {
         const int col = g.col0 + tcol;
-        if (!cpv) {
-            const int ik1v = g.ik10 + tcol;
-            const bool hilbert = (FNS ? FNS : P->F.id) == TT_FN_HILBERT;
-            long long hsum = ik1v + 1;                 // integer index sum, exact in any order
-            for (int j = 0; j < npre; ++j) hsum += pre[j] + 1;
-            for (int j = 0; j < nsuf; ++j) hsum += suf[j] + 1;
-            for (int ii = tr; ii < g.nrows; ii += rpp) {
-                const int row = g.row0 + ii;
-                if (s_rp[ii]) continue;
-                const int ikv = g.ik0 + ii;
-                V x;
+        const int ik1v = g.ik10 + tcol;
+        const bool hilbert = (FNS ? FNS : P->F.id) == TT_FN_HILBERT;
+        long long hsum = ik1v + 1;                 // integer index sum, exact in any order
+        for (int j = 0; j < npre; ++j) hsum += pre[j] + 1;
+        for (int j = 0; j < nsuf; ++j) hsum += suf[j] + 1;
+        // IL rows of the thread's column at once: each entry still takes
+        // every pivot out in insertion order, but the IL chains interleave
+        // and share each U(z, col) read
+        constexpr int IL = 4;
+        for (int ii0 = tr; ii0 < g.nrows; ii0 += IL * rpp) {
+            V x[IL];
+            int iv[IL];
+            bool ok[IL];
+#pragma unroll
+            for (int j = 0; j < IL; ++j) {
+                const int ii = ii0 + j * rpp;
+                iv[j] = min(ii, g.nrows - 1);
+                ok[j] = ii < g.nrows && !s_rp[iv[j]];
+                const int ikv = g.ik0 + iv[j];
                 if (hilbert) {
-                    x = (V)1 / ((V)(hsum + ikv + 1) + (V)P->F.shift);
+                    x[j] = (V)1 / ((V)(hsum + ikv + 1) + (V)P->F.shift);
                 } else {
-                    x = fn_value_ix<V, FNS>(P->F, [&](int j) {
-                        return j < npre ? pre[j] : (j == k - 1 ? ikv : (j == k ? ik1v : suf[j - k - 1]));
+                    x[j] = fn_value_ix<V, FNS>(P->F, [&](int jj) {
+                        return jj < npre ? pre[jj] : (jj == k - 1 ? ikv : (jj == k ? ik1v : suf[jj - k - 1]));
                     });
                 }
-                for (int z = 0; z < rk; ++z) x = vfma<V>(-Wt[z * TRm + ii], Ut[z * TCm + tcol], x);
-                E[(int64_t)row * ld + col] = x;
-                const double ax = (double)fabs(x);
+            }
+            for (int z = 0; z < rk; ++z) {
+                const V uz = Ut[z * TCm + tcol];
+#pragma unroll
+                for (int j = 0; j < IL; ++j) x[j] = vfma<V>(-Wt[z * TRm + iv[j]], uz, x[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < IL; ++j) {
+                if (!ok[j]) continue;
+                const int row = g.row0 + iv[j];
+                E[(int64_t)row * ld + col] = x[j];
+                const double ax = (double)fabs(x[j]);
                 const uint64_t key = ((uint64_t)row << 32) | (uint32_t)col;
-                if (better(ax, key, bv, bk)) { bv = ax; bk = key; bs = (double)x; }
+                if (better(ax, key, bv, bk)) { bv = ax; bk = key; bs = (double)x[j]; }
             }
         }
     }
-    block_best(bv, bk, bs);
+#ifdef TT_STAMPS
+    if (rec && tid == 0) rec[12] = __builtin_amdgcn_s_memrealtime();
+#endif
+    block_best_t0(bv, bk, bs);
     TT_STAMP(rec, 6);
 }
 
@@ -463,17 +565,15 @@ __device__ void sweep_body(const ProbDev *__restrict__ P, const ProbState *S, in
                 R = i2 / (CT - CTs);
                 C = CTs + i2 % (CT - CTs);
             }
-            const KDev &K = P->kd[u];
-            const TileGeom g = tile_geom(K, u, R, C);
             unsigned long long *nrec = nullptr;
 #ifdef TT_STAMPS
             if (rec && rec[10] == 0) nrec = rec;          // the workgroup's first new tile
             TT_STAMP(nrec, 2);
 #endif
-            new_tile<V, FNS>(P, K, ks[u], g, bv, bk, bs, (V *)smem_raw, nrec);
+            new_tile<V, FNS>(P, nk, u, R, C, ks[u], bv, bk, bs, (V *)smem_raw, nrec);
             TT_STAMP_ADD(rec, 10, 1);
             if (tid == 0) {
-                const gptr_t<Cand> c = as_global(K.cand) + (R * CT + C);
+                const gptr_t<Cand> c = as_global(P->kd[u].cand) + (R * CT + C);
                 c->v = bv; c->key = bk; c->sv = bs;
             }
             __syncthreads();
@@ -493,8 +593,7 @@ __device__ void sweep_body(const ProbDev *__restrict__ P, const ProbState *S, in
                 const bool first_st = rec && wid == 0 && rec[11] == 0;
                 if (first_st && lane == 0) rec[7] = __builtin_amdgcn_s_memrealtime();
 #endif
-                // 8 rows per batch of loads: more raise the register count
-                // past four wavefronts per SIMD (Hilbert kernel) or three
+                // 8 rows per batch of loads: more would cost occupancy
                 stored_tile_wave<V, 8>(K, ks[u], g, bv, bk, bs);
                 wave_best(bv, bk, bs);
                 if (lane == 0) {
@@ -515,7 +614,7 @@ __device__ void sweep_body(const ProbDev *__restrict__ P, const ProbState *S, in
 }
 
 template <typename V, int FNS = 0>
-static __global__ void __launch_bounds__(NT) k_sweep(const ProbDev *__restrict__ P, SweepArgs a)
+static __global__ void __launch_bounds__(NT, 4) k_sweep(const ProbDev *__restrict__ P, SweepArgs a)
 {
     sweep_body<V, FNS>(P, a.S, a.nk, blockIdx.x, gridDim.x, a.sweep);
 }
@@ -603,28 +702,35 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
     __syncthreads();
     TT_STAMP(rec, 1);
     if (s_stop) return;
-    // best candidate per unfolding: wave w scans unfoldings w, w+NW, ...,
-    // with CB candidates per lane in flight at once
+    // best candidate per unfolding: wpu >= 1 wavefronts per unfolding, the
+    // groups of wpu wavefronts striding over the unfoldings (one pass when
+    // nk <= NW), each lane with CB candidates in flight, so that a
+    // superblock's candidates come in one round of loads.  Partial result
+    // (u, sl) sits in slot u * wpu + sl < max(NW, nk).
     constexpr int CB = 8;
+    constexpr int NPS = NW > TT_MAX_D ? NW : TT_MAX_D;
     __shared__ unsigned long long s_rcnt[TT_MAX_D];
-    for (int u = wid; u < nk; u += NW) {
-        const KDev &K = P->kd[u];
-        const int ntl = P->rook ? K.nrb * K.ncb : s_ntl[u];
+    __shared__ double s_pv[NPS], s_psv[NPS];
+    __shared__ uint64_t s_pk[NPS];
+    const int wpu = nk <= NW ? NW / nk : 1, ngr = NW / wpu, sl = wid % wpu;
+    for (int us = wid / wpu; us < nk && wid < ngr * wpu; us += ngr) {   // uniform across the wavefront
+        const KDev &K = P->kd[us];
+        const int ntl = P->rook ? K.nrb * K.ncb : s_ntl[us];
         double bv = -1.0, bs = 0.0;
         uint64_t bk = ~0ULL;
-        if (P->rook) {
+        if (P->rook && sl == 0) {
             // residuals the block searches looked at
             unsigned long long c = 0;
             for (int i = lane; i < ntl; i += 64) c += as_global((unsigned long long *)K.bcnt)[i];
             for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
-            if (lane == 0) s_rcnt[u] = c;
+            if (lane == 0) s_rcnt[us] = c;
         }
         const gptr_t<const Cand> cand = as_global((const Cand *)K.cand);
-        for (int i0 = 0; i0 < ntl; i0 += 64 * CB) {
+        for (int i0 = 64 * sl; i0 < ntl; i0 += 64 * wpu * CB) {
             Cand c[CB];
 #pragma unroll
             for (int j = 0; j < CB; ++j) {
-                const int i = i0 + lane + 64 * j;
+                const int i = i0 + lane + 64 * wpu * j;
                 if (i < ntl) {
                     const gptr_t<const Cand> cp = cand + i;
                     c[j].v = cp->v; c[j].key = cp->key; c[j].sv = cp->sv;
@@ -637,11 +743,23 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
                 if (better(c[j].v, c[j].key, bv, bk)) { bv = c[j].v; bk = c[j].key; bs = c[j].sv; }
         }
         wave_best(bv, bk, bs);
-        if (lane == 0) { s_wv[u] = bv; s_wk[u] = bk; s_wsv[u] = bs; }
+        const int slot = us * wpu + sl;
+        if (lane == 0) { s_pv[slot] = bv; s_pk[slot] = bk; s_psv[slot] = bs; }
+    }
+    __syncthreads();
+    if (tid < nk) {
+        // the unfolding's wavefronts in order (the comparison decides; the
+        // order only matters for equal keys, which cannot occur)
+        double bv = -1.0, bs = 0.0;
+        uint64_t bk = ~0ULL;
+        for (int w = tid * wpu; w < (tid + 1) * wpu; ++w)
+            if (better(s_pv[w], s_pk[w], bv, bk)) { bv = s_pv[w]; bk = s_pk[w]; bs = s_psv[w]; }
+        s_wv[tid] = bv; s_wk[tid] = bk; s_wsv[tid] = bs;
     }
     __syncthreads();
     TT_STAMP(rec, 2);
     // decide and commit
+    __shared__ int s_geo[TT_MAX_D][4];
     for (int u = wid; u < nk; u += NW) {
         const int k = u + 1;
         const KDev &K = P->kd[u];
@@ -708,12 +826,16 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
                 ks[u].agam = col;
                 ks[u].apiv = bs;
             }
+            // the descriptor fields the next shapes need, already read here
+            s_geo[u][0] = K.nk;
+            s_geo[u][1] = K.nk1;
+            s_geo[u][2] = K.RTp;
+            s_geo[u][3] = K.CTq;
         }
+        if (tid == 0) { s_rnew[0] = 1; s_rnew[d] = 1; }
     }
     __syncthreads();
     TT_STAMP(rec, 3);
-    if (tid == 0) { s_rnew[0] = 1; s_rnew[d] = 1; }
-    __syncthreads();
     // the next sweep's shapes and tile counts: lane u of wavefront 0 prepares
     // unfolding u, and the tile offsets are prefix sums over the lanes
     if (tid < 64) {
@@ -721,21 +843,21 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
         int nn = 0, ns = 0;
         if (u < nk) {
             const int k = u + 1;
-            const KDev &K = P->kd[u];
+            const int knk = s_geo[u][0], knk1 = s_geo[u][1], kRTp = s_geo[u][2], kCTq = s_geo[u][3];
             KSweep n;
             n.rk = s_rnew[k];
             n.apply = s_prop[u];
             n.nr_st = ks[u].nr;
             n.nc_st = ks[u].nc;
-            n.nr = s_rnew[k - 1] * K.nk;
-            n.nc = K.nk1 * s_rnew[k + 1];
+            n.nr = s_rnew[k - 1] * knk;
+            n.nc = knk1 * s_rnew[k + 1];
             n.arho = ks[u].arho;
             n.agam = ks[u].agam;
             n.apiv = ks[u].apiv;
             S->ks[u] = n;
             S->r[par ^ 1][k] = s_rnew[k];
-            const int RT = (n.nr / K.nk) * K.RTp, CT = (n.nc / K.nk1) * K.CTq;
-            const int RTs = (n.nr_st / K.nk) * K.RTp, CTs = (n.nc_st / K.nk1) * K.CTq;
+            const int RT = (n.nr / knk) * kRTp, CT = (n.nc / knk1) * kCTq;
+            const int RTs = (n.nr_st / knk) * kRTp, CTs = (n.nc_st / knk1) * kCTq;
             S->sh.RT[u] = RT;
             S->sh.CT[u] = CT;
             S->sh.RTs[u] = RTs;
@@ -809,11 +931,20 @@ __device__ inline void samples_body(const ProbDev *__restrict__ P, uint64_t seed
                                     SamplePart *part, int blk, int nblk)
 {
     const int tid = threadIdx.x, s = blk * NT + tid;
-    const int d = P->d;
-    for (int u = 0; u < P->nk; ++u) {
-        const KDev &K = P->kd[u];
-        for (int i = s; i < K.rowcap; i += nblk * NT) K.rpiv[i] = 0;
-        for (int j = s; j < K.colcap; j += nblk * NT) K.cpiv[j] = 0;
+    const int d = P->d, nk = P->nk;
+    // the maps' places in one round of loads: a byte store may alias the
+    // descriptor, so reading it between the stores would serialise them
+    __shared__ uint8_t *s_rp[TT_MAX_D], *s_cp[TT_MAX_D];
+    __shared__ int s_rc[TT_MAX_D], s_cc[TT_MAX_D];
+    if (tid < nk) {
+        const KDev &K = P->kd[tid];
+        s_rp[tid] = K.rpiv; s_cp[tid] = K.cpiv;
+        s_rc[tid] = K.rowcap; s_cc[tid] = K.colcap;
+    }
+    __syncthreads();
+    for (int u = 0; u < nk; ++u) {
+        for (int i = s; i < s_rc[u]; i += nblk * NT) s_rp[u][i] = 0;
+        for (int j = s; j < s_cc[u]; j += nblk * NT) s_cp[u][j] = 0;
     }
     double v = 0.0;
     if (s < ns) {
@@ -936,10 +1067,8 @@ __device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns,
         const double rms = sqrt(ss / (double)ns);
         S->rms = rms;
         S->tau = eps * rms;
-        for (int j = 0; j < d; ++j) {
-            i0[j] = (int)(sm64_at(seed, bk * d + j) % (uint64_t)P->F.n[j]);
-            S->i0[j] = i0[j];
-        }
+        for (int j = 0; j < d; ++j) i0[j] = (int)(sm64_at(seed, bk * d + j) % (uint64_t)P->F.n[j]);
+        for (int j = 0; j < d; ++j) S->i0[j] = i0[j];
         for (int b = 0; b < 2; ++b)
             for (int j = 0; j <= d; ++j) S->r[b][j] = 1;
         S->stop = 0; S->capped = 0; S->sweeps = 0; S->pivoted = 0;
@@ -952,12 +1081,17 @@ __device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns,
         if (S->err) S->stop = 1;
     }
     __syncthreads();
-    for (int u = 0; u < P->nk; ++u) {
+    // the first pivot of every unfolding: 16 threads per unfolding (a byte
+    // store may alias the descriptor, so a loop over the unfoldings would
+    // read each descriptor only after the previous one's stores)
+    const int u = tid >> 4, l = tid & 15;
+    if (u < P->nk) {
         const KDev &K = P->kd[u];
         const int k = u + 1;
-        if (tid < k) K.Ifull[tid] = i0[tid];
-        if (tid < d - k) K.Jfull[tid] = i0[k + tid];
-        if (tid == 0) {
+        const int knk = K.nk, knk1 = K.nk1;      // read before any store
+        if (l < k) K.Ifull[l] = i0[l];
+        if (l < d - k) K.Jfull[l] = i0[k + l];
+        if (l == 0) {
             K.rho[0] = i0[k - 1];
             K.gam[0] = i0[k];
             K.piv[0] = p0s;
@@ -967,8 +1101,8 @@ __device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns,
             KSweep ks;
             ks.rk = 1;
             ks.apply = 1;                 // the first pivot is applied by the first sweep
-            ks.nr_st = ks.nr = K.nk;
-            ks.nc_st = ks.nc = K.nk1;
+            ks.nr_st = ks.nr = knk;
+            ks.nc_st = ks.nc = knk1;
             ks.arho = i0[k - 1];
             ks.agam = i0[k];
             ks.apiv = p0s;
@@ -1157,16 +1291,114 @@ __device__ inline void rook_block_geom(const ProbDev *__restrict__ P, int u, int
     g.len1 = piece_start(c[k] + 1, K.nk1, P->grid[k]) - g.lo1;
 }
 
-// Residual at (row, col) after rk pivots: the entry minus the factor products
-// in pivot order.  Wrow: W(row, :); Ucol: U(:, col) (stride us).  Both
-// factors are stored as contiguous vectors of rk_cap values per row (W) and
-// per column (U), so a residual at a random position reads two short runs.
-template <int FNS, typename TW, typename TU>
-__device__ inline double rook_residual(const ProbDev *__restrict__ P, int u, int row, int col, TW Wrow, TU Ucol,
-                                       int64_t us, int rk)
+// One subtensor block of superblock u in this sweep, staged in LDS: its
+// prefixes and suffixes with their index tuples, and the positions of the
+// unfolding's pivots.  An entry at a position of the block then needs no
+// index reads from memory, and whether a sampled row or column holds a
+// pivot is a comparison against the rk pivot positions, so a residual at a
+// random position reads only its two factor vectors.
+struct RookBlock {
+    KSweep ks;
+    RookGeom g;
+    int nk, nk1, npre, nsuf;
+    int pref[TT_MAX_RANK], suf[TT_MAX_RANK];
+    int rho[TT_MAX_RANK], gam[TT_MAX_RANK];
+    int ptup[TT_MAX_RANK * TT_MAX_D], stup[TT_MAX_RANK * TT_MAX_D];
+
+    __device__ int nR() const { return g.np * g.len; }
+    __device__ int nC() const { return g.nq * g.len1; }
+    __device__ int rowpos(int t) const { return pref[t / g.len] * nk + g.lo + t % g.len; }
+    __device__ int colpos(int t) const { return suf[t / g.len1] * nk1 + g.lo1 + t % g.len1; }
+    // local prefix (suffix) index of a superblock row (column) of the block
+    __device__ int row_pref(int row) const
+    {
+        const int p = row / nk;
+        int t = 0;
+        while (t + 1 < g.np && pref[t] != p) ++t;
+        return t;
+    }
+    __device__ int col_suf(int col) const
+    {
+        const int q = col / nk1;
+        int t = 0;
+        while (t + 1 < g.nq && suf[t] != q) ++t;
+        return t;
+    }
+    __device__ bool pivot_row(int row) const
+    {
+        bool hit = false;
+        for (int z = 0; z < ks.rk; ++z) hit |= rho[z] == row;
+        return hit;
+    }
+    __device__ bool pivot_col(int col) const
+    {
+        bool hit = false;
+        for (int z = 0; z < ks.rk; ++z) hit |= gam[z] == col;
+        return hit;
+    }
+};
+
+// Thread 0 reads the sweep's shapes and finds the block's geometry, then
+// every thread stages the tuples and the pivot positions.  Ends with a
+// barrier.
+__device__ inline void rook_block_load(const ProbDev *__restrict__ P, int u, int b, RookBlock &B)
 {
-    double x = rook_entry<FNS>(P, u, row, col);
-    for (int z = 0; z < rk; ++z) x = __fma_rn(-Wrow[z], Ucol[(int64_t)z * us], x);
+    const KDev &K = P->kd[u];
+    const int k = u + 1, npre = k - 1, nsuf = P->d - k - 1;
+    if (threadIdx.x == 0) {
+        B.ks = P->S->ks[u];
+        rook_block_geom(P, u, b, B.ks, B.pref, B.suf, B.g);
+        B.nk = K.nk;
+        B.nk1 = K.nk1;
+        B.npre = npre;
+        B.nsuf = nsuf;
+    }
+    __syncthreads();
+    for (int z = threadIdx.x; z < B.ks.rk; z += NT) {
+        B.rho[z] = as_global((const int *)K.rho)[z];
+        B.gam[z] = as_global((const int *)K.gam)[z];
+    }
+    if (npre > 0) {
+        const gptr_t<const int> I = as_global((const int *)P->kd[u - 1].Ifull);
+        for (int e = threadIdx.x; e < B.g.np * npre; e += NT) {
+            const int t = e / npre, j = e - t * npre;
+            B.ptup[e] = I[B.pref[t] * npre + j];
+        }
+    }
+    if (nsuf > 0) {
+        const gptr_t<const int> J = as_global((const int *)P->kd[u + 1].Jfull);
+        for (int e = threadIdx.x; e < B.g.nq * nsuf; e += NT) {
+            const int t = e / nsuf, j = e - t * nsuf;
+            B.stup[e] = J[B.suf[t] * nsuf + j];
+        }
+    }
+    __syncthreads();
+}
+
+// The generating function at the block's local row (prefix tp, index ik of
+// mode k) and column (index ik1 of mode k+1, suffix tq).
+template <int FNS>
+__device__ inline double rook_entry_loc(const ProbDev *__restrict__ P, const RookBlock &B, int tp, int ik, int tq,
+                                        int ik1)
+{
+    const int npre = B.npre, k = npre + 1;
+    const int *pt = B.ptup + tp * npre;
+    const int *st = B.stup + tq * B.nsuf;
+    return fn_value_ix<double, FNS>(P->F, [&](int j) {
+        return j < npre ? pt[j] : (j == npre ? ik : (j == k ? ik1 : st[j - k - 1]));
+    });
+}
+
+// Residual at a position of the block after rk pivots: the entry minus the
+// factor products in pivot order.  Wrow: W(row, :); Ucol: U(:, col).  Both
+// factors are stored as contiguous vectors of rk_cap values per row (W) and
+// per column (U).
+template <int FNS, typename TW, typename TU>
+__device__ inline double rook_residual_loc(const ProbDev *__restrict__ P, const RookBlock &B, int tp, int ik, int tq,
+                                           int ik1, TW Wrow, TU Ucol, int rk)
+{
+    double x = rook_entry_loc<FNS>(P, B, tp, ik, tq, ik1);
+    for (int z = 0; z < rk; ++z) x = __fma_rn(-Wrow[z], Ucol[z], x);
     return x;
 }
 
@@ -1177,15 +1409,16 @@ __device__ inline double rook_residual(const ProbDev *__restrict__ P, int u, int
 // by itself: every move raises |residual|, and a column step leaves the
 // position at the largest |residual| of its column (a row step, of its row),
 // so a column (row) that a step has searched is never entered again; hence
-// at most min(rows, columns) + 1 rounds, the bound written below.  rowpos and
-// colpos map the block's t-th row / column to its superblock position.
+// at most min(rows, columns) + 1 rounds, the bound written below.
 // Adds the residuals looked at to cnt; returns the rounds run.
-template <int FNS, typename RP, typename CP>
-__device__ int rook_walk(const ProbDev *__restrict__ P, int u, const KDev &K, RP rowpos, CP colpos, int nR, int nC,
-                         int rk, double *s_f, double &bv, double &bs, int &ci, int &cj, unsigned long long &cnt)
+template <int FNS>
+__device__ int rook_walk(const ProbDev *__restrict__ P, const KDev &K, const RookBlock &B, double *s_f, double &bv,
+                         double &bs, int &ci, int &cj, unsigned long long &cnt)
 {
-    const int tid = threadIdx.x, wp = K.rk_cap;
+    const int tid = threadIdx.x, wp = K.rk_cap, rk = B.ks.rk, nR = B.nR(), nC = B.nC();
+    const int len = B.g.len, len1 = B.g.len1, lo = B.g.lo, lo1 = B.g.lo1;
     const gptr_t<const double> W = as_global((const double *)K.Wf), U = as_global((const double *)K.Uf);
+    const gptr_t<const uint8_t> rpiv = as_global((const uint8_t *)K.rpiv), cpiv = as_global((const uint8_t *)K.cpiv);
     const int cap = min(nR, nC) + 1;
     int rounds = 0;
     while (rounds < cap) {
@@ -1193,29 +1426,31 @@ __device__ int rook_walk(const ProbDev *__restrict__ P, int u, const KDev &K, RP
         bool moved = false;
         // column step: U(:, cj) shared by every row
         for (int z = tid; z < rk; z += NT) s_f[z] = U[(int64_t)cj * wp + z];
+        const int tq = B.col_suf(cj), ik1 = cj - B.suf[tq] * B.nk1;
         __syncthreads();
         double tv = -1.0, ts = 0.0;
         uint64_t tk = ~0ULL;
         for (int t = tid; t < nR; t += NT) {
-            const int row = rowpos(t);
-            if (K.rpiv[row]) continue;
+            const int row = B.rowpos(t);
+            if (rpiv[row]) continue;
             ++cnt;
-            const double x = rook_residual<FNS>(P, u, row, cj, W + (int64_t)row * wp, s_f, 1, rk);
+            const double x = rook_residual_loc<FNS>(P, B, t / len, lo + t % len, tq, ik1, W + (int64_t)row * wp, s_f, rk);
             if (better(fabs(x), (uint64_t)row, tv, tk)) { tv = fabs(x); tk = (uint64_t)row; ts = x; }
         }
         block_best(tv, tk, ts);
         if (tv > bv) { bv = tv; bs = ts; ci = (int)tk; moved = true; }
         // row step: W(ci, :) shared by every column
         for (int z = tid; z < rk; z += NT) s_f[z] = W[(int64_t)ci * wp + z];
+        const int tp = B.row_pref(ci), ik = ci - B.pref[tp] * B.nk;
         __syncthreads();
         tv = -1.0;
         ts = 0.0;
         tk = ~0ULL;
         for (int t = tid; t < nC; t += NT) {
-            const int col = colpos(t);
-            if (K.cpiv[col]) continue;
+            const int col = B.colpos(t);
+            if (cpiv[col]) continue;
             ++cnt;
-            const double x = rook_residual<FNS>(P, u, ci, col, s_f, U + (int64_t)col * wp, 1, rk);
+            const double x = rook_residual_loc<FNS>(P, B, tp, ik, t / len1, lo1 + t % len1, s_f, U + (int64_t)col * wp, rk);
             if (better(fabs(x), (uint64_t)col, tv, tk)) { tv = fabs(x); tk = (uint64_t)col; ts = x; }
         }
         block_best(tv, tk, ts);
@@ -1233,6 +1468,48 @@ __device__ inline void rook_note_rounds(const ProbDev *__restrict__ P, int round
     if (rounds > TT_ROOK_ITERS) atomicAdd(&S->rook_long, 1);
 }
 
+// The random set of Alg. 1 for block b of unfolding u in this sweep: pair s
+// takes draws 2s (row) and 2s+1 (column) of the stream seeded with seed XOR
+// mix(k | sweep << 8 | b << 32); pairs on a pivot row or column are
+// skipped.  Samples s0, s0 + ds, ... below L = max(64, rows + columns).
+template <int FNS>
+__device__ inline void rook_samples(const ProbDev *__restrict__ P, const KDev &K, const RookBlock &B, int u, int b,
+                                    int sweep, uint64_t seed, int s0, int ds, double &bv, uint64_t &bk, double &bs,
+                                    unsigned long long &cnt)
+{
+    const int k = u + 1, wp = K.rk_cap, rk = B.ks.rk, nR = B.nR(), nC = B.nC();
+    const int len = B.g.len, len1 = B.g.len1, lo = B.g.lo, lo1 = B.g.lo1;
+    const gptr_t<const double> W = as_global((const double *)K.Wf), U = as_global((const double *)K.Uf);
+    const uint64_t tag = (uint64_t)k | ((uint64_t)sweep << 8) | ((uint64_t)b << 32);
+    const uint64_t sig = seed ^ sm64_mix(tag);
+    const int L = max(64, nR + nC);
+    for (int s = s0; s < L; s += ds) {
+        const uint64_t ra = sm64_at(sig, 2 * (uint64_t)s), ca = sm64_at(sig, 2 * (uint64_t)s + 1);
+        const int tr = (int)(ra % (uint64_t)nR), tc = (int)(ca % (uint64_t)nC);
+        const int row = B.rowpos(tr), col = B.colpos(tc);
+        if (B.pivot_row(row) || B.pivot_col(col)) continue;
+        ++cnt;
+        const double x = rook_residual_loc<FNS>(P, B, tr / len, lo + tr % len, tc / len1, lo1 + tc % len1,
+                                                W + (int64_t)row * wp, U + (int64_t)col * wp, rk);
+        const uint64_t key = ((uint64_t)row << 32) | (uint32_t)col;
+        if (better(fabs(x), key, bv, bk)) { bv = fabs(x); bk = key; bs = x; }
+    }
+}
+
+// No sample off the pivot rows and columns: the block's first row and first
+// column without a pivot (every thread gets the same answer; fr = nR or
+// fc = nC when there is none).
+__device__ inline void rook_first_free(const KDev &K, const RookBlock &B, int &fr, int &fc)
+{
+    const int nR = B.nR(), nC = B.nC();
+    fr = nR;
+    fc = nC;
+    for (int t = threadIdx.x; t < nR; t += NT) if (!K.rpiv[B.rowpos(t)]) { fr = min(fr, t); break; }
+    for (int t = threadIdx.x; t < nC; t += NT) if (!K.cpiv[B.colpos(t)]) { fc = min(fc, t); break; }
+    fr = block_min_int(fr);
+    fc = block_min_int(fc);
+}
+
 // One subtensor block of one superblock per workgroup: the random start of
 // Alg. 1 from the block's seeded sample stream, then its loop (rook_walk).
 // Ties go to the lowest position, as in the greedy search.
@@ -1246,51 +1523,26 @@ __device__ void rook_search_body(const ProbDev *__restrict__ P, int nk, int swee
     while (u < nk && b >= P->kd[u].nrb * P->kd[u].ncb) { b -= P->kd[u].nrb * P->kd[u].ncb; ++u; }
     if (u >= nk) return;
     const KDev &K = P->kd[u];
-    const int k = u + 1;
-    __shared__ KSweep ks;
-    __shared__ int s_pref[TT_MAX_RANK], s_suf[TT_MAX_RANK];
-    __shared__ RookGeom s_g;
+    __shared__ RookBlock B;
     __shared__ double s_f[TT_MAX_RANK];
-    if (tid == 0) {
-        ks = S->ks[u];
-        rook_block_geom(P, u, b, ks, s_pref, s_suf, s_g);
-    }
-    __syncthreads();
-    const int len = s_g.len, len1 = s_g.len1, lo = s_g.lo, lo1 = s_g.lo1;
-    const int nR = s_g.np * len, nC = s_g.nq * len1;
-    const int rk = ks.rk, wp = K.rk_cap;
+    rook_block_load(P, u, b, B);
+    const int nR = B.nR(), nC = B.nC(), rk = B.ks.rk, wp = K.rk_cap;
     const gptr_t<const double> W = as_global((const double *)K.Wf), U = as_global((const double *)K.Uf);
-    auto rowpos = [&](int t) { return s_pref[t / len] * K.nk + lo + t % len; };
-    auto colpos = [&](int t) { return s_suf[t / len1] * K.nk1 + lo1 + t % len1; };
     double bv = -1.0, bs = 0.0;
     uint64_t bk = ~0ULL;
     unsigned long long cnt = 0;
     int rounds = 0;
     if (nR > 0 && nC > 0) {
-        // the random set: pair s takes draws 2s (row) and 2s+1 (column)
-        const uint64_t tag = (uint64_t)k | ((uint64_t)sweep << 8) | ((uint64_t)b << 32);
-        const uint64_t sig = seed ^ sm64_mix(tag);
-        const int L = max(64, nR + nC);
-        for (int s = tid; s < L; s += NT) {
-            const uint64_t ra = sm64_at(sig, 2 * (uint64_t)s), ca = sm64_at(sig, 2 * (uint64_t)s + 1);
-            const int row = rowpos((int)(ra % (uint64_t)nR)), col = colpos((int)(ca % (uint64_t)nC));
-            if (K.rpiv[row] || K.cpiv[col]) continue;
-            ++cnt;
-            const double x = rook_residual<FNS>(P, u, row, col, W + (int64_t)row * wp, U + (int64_t)col * wp, 1, rk);
-            const uint64_t key = ((uint64_t)row << 32) | (uint32_t)col;
-            if (better(fabs(x), key, bv, bk)) { bv = fabs(x); bk = key; bs = x; }
-        }
+        rook_samples<FNS>(P, K, B, u, b, sweep, seed, tid, NT, bv, bk, bs, cnt);
         block_best(bv, bk, bs);
         if (bv < 0.0) {
-            // no sample off the pivot rows and columns: the first row and column without a pivot
-            int fr = nR, fc = nC;
-            for (int t = tid; t < nR; t += NT) if (!K.rpiv[rowpos(t)]) { fr = min(fr, t); break; }
-            for (int t = tid; t < nC; t += NT) if (!K.cpiv[colpos(t)]) { fc = min(fc, t); break; }
-            fr = block_min_int(fr);
-            fc = block_min_int(fc);
+            int fr, fc;
+            rook_first_free(K, B, fr, fc);
             if (fr < nR && fc < nC) {
-                const int row = rowpos(fr), col = colpos(fc);
-                const double x = rook_residual<FNS>(P, u, row, col, W + (int64_t)row * wp, U + (int64_t)col * wp, 1, rk);
+                const int row = B.rowpos(fr), col = B.colpos(fc);
+                const double x = rook_residual_loc<FNS>(P, B, fr / B.g.len, B.g.lo + fr % B.g.len, fc / B.g.len1,
+                                                        B.g.lo1 + fc % B.g.len1, W + (int64_t)row * wp,
+                                                        U + (int64_t)col * wp, rk);
                 bv = fabs(x);
                 bs = x;
                 bk = ((uint64_t)row << 32) | (uint32_t)col;
@@ -1299,7 +1551,7 @@ __device__ void rook_search_body(const ProbDev *__restrict__ P, int nk, int swee
         }
         if (bv >= 0.0) {
             int ci = (int)(bk >> 32), cj = (int)(bk & 0xffffffffULL);
-            rounds = rook_walk<FNS>(P, u, K, rowpos, colpos, nR, nC, rk, s_f, bv, bs, ci, cj, cnt);
+            rounds = rook_walk<FNS>(P, K, B, s_f, bv, bs, ci, cj, cnt);
             bk = ((uint64_t)ci << 32) | (uint32_t)cj;
         }
     }
@@ -1318,9 +1570,10 @@ __device__ void rook_search_body(const ProbDev *__restrict__ P, int nk, int swee
 // writes its partial best, and the next launch reduces the partials (every
 // workgroup the same way) and moves the block's state.  Phase 0 draws the
 // samples, phase p = 1..2 TT_ROOK_ITERS is a column step (p odd) or a row
-// step (p even), and a finishing launch applies the last step.  A block whose
-// round moved nothing is done; its later launches return at once.  Values,
-// order of comparisons and counts are those of the one-workgroup search.
+// step (p even), and a finishing launch applies the last step and completes
+// any walk still moving.  A block whose round moved nothing is done; its
+// later launches return at once.  Values, order of comparisons and counts
+// are those of the one-workgroup search.
 // ---------------------------------------------------------------------------
 __device__ inline bool rook_wg_of(const ProbDev *__restrict__ P, int nk, int G, int wg, int &u, int &b, int &g)
 {
@@ -1342,38 +1595,12 @@ __device__ void rook_wsample_body(const ProbDev *__restrict__ P, int nk, int swe
     int u, b, g;
     if (!rook_wg_of(P, nk, G, wg, u, b, g)) return;
     const KDev &K = P->kd[u];
-    const int k = u + 1;
-    __shared__ KSweep ks;
-    __shared__ int s_pref[TT_MAX_RANK], s_suf[TT_MAX_RANK];
-    __shared__ RookGeom s_g;
-    if (tid == 0) {
-        ks = S->ks[u];
-        rook_block_geom(P, u, b, ks, s_pref, s_suf, s_g);
-    }
-    __syncthreads();
-    const int len = s_g.len, len1 = s_g.len1, lo = s_g.lo, lo1 = s_g.lo1;
-    const int nR = s_g.np * len, nC = s_g.nq * len1;
-    const int rk = ks.rk, wp = K.rk_cap;
-    auto rowpos = [&](int t) { return s_pref[t / len] * K.nk + lo + t % len; };
-    auto colpos = [&](int t) { return s_suf[t / len1] * K.nk1 + lo1 + t % len1; };
+    __shared__ RookBlock B;
+    rook_block_load(P, u, b, B);
     double bv = -1.0, bs = 0.0;
     uint64_t bk = ~0ULL;
     unsigned long long cnt = 0;
-    if (nR > 0 && nC > 0) {
-        const uint64_t tag = (uint64_t)k | ((uint64_t)sweep << 8) | ((uint64_t)b << 32);
-        const uint64_t sig = seed ^ sm64_mix(tag);
-        const int L = max(64, nR + nC);
-        for (int s = g * NT + tid; s < L; s += G * NT) {
-            const uint64_t ra = sm64_at(sig, 2 * (uint64_t)s), ca = sm64_at(sig, 2 * (uint64_t)s + 1);
-            const int row = rowpos((int)(ra % (uint64_t)nR)), col = colpos((int)(ca % (uint64_t)nC));
-            if (K.rpiv[row] || K.cpiv[col]) continue;
-            ++cnt;
-            const double x = rook_residual<FNS>(P, u, row, col, as_global((const double *)K.Wf) + (int64_t)row * wp,
-                                                as_global((const double *)K.Uf) + (int64_t)col * wp, 1, rk);
-            const uint64_t key = ((uint64_t)row << 32) | (uint32_t)col;
-            if (better(fabs(x), key, bv, bk)) { bv = fabs(x); bk = key; bs = x; }
-        }
-    }
+    if (B.nR() > 0 && B.nC() > 0) rook_samples<FNS>(P, K, B, u, b, sweep, seed, g * NT + tid, G * NT, bv, bk, bs, cnt);
     block_best(bv, bk, bs);
     cnt = block_sum_u64(cnt);
     if (tid == 0) {
@@ -1422,24 +1649,16 @@ __device__ void rook_wstep_body(const ProbDev *__restrict__ P, int nk, int p, in
     if (!rook_wg_of(P, nk, G, wg, u, b, g)) return;
     const KDev &K = P->kd[u];
     const int nb = K.nrb * K.ncb;
-    __shared__ KSweep ks;
-    __shared__ int s_pref[TT_MAX_RANK], s_suf[TT_MAX_RANK];
-    __shared__ RookGeom s_g;
+    __shared__ RookBlock B;
     __shared__ RookState st;
     __shared__ double s_f[TT_MAX_RANK];
-    if (tid == 0) {
-        ks = S->ks[u];
-        rook_block_geom(P, u, b, ks, s_pref, s_suf, s_g);
-    }
+    rook_block_load(P, u, b, B);
     double pv, psv;
     uint64_t pk;
-    rook_reduce_parts(K, G, (p - 1) & 1, b, pv, pk, psv);    // also orders the geometry
-    const int len = s_g.len, len1 = s_g.len1, lo = s_g.lo, lo1 = s_g.lo1;
-    const int nR = s_g.np * len, nC = s_g.nq * len1;
-    const int rk = ks.rk, wp = K.rk_cap;
+    rook_reduce_parts(K, G, (p - 1) & 1, b, pv, pk, psv);
+    const int nR = B.nR(), nC = B.nC(), rk = B.ks.rk, wp = K.rk_cap;
+    const int len = B.g.len, len1 = B.g.len1, lo = B.g.lo, lo1 = B.g.lo1;
     const gptr_t<const double> W = as_global((const double *)K.Wf), U = as_global((const double *)K.Uf);
-    auto rowpos = [&](int t) { return s_pref[t / len] * K.nk + lo + t % len; };
-    auto colpos = [&](int t) { return s_suf[t / len1] * K.nk1 + lo1 + t % len1; };
     unsigned long long cnt = 0;
     if (tid == 0) {
         RookState s;
@@ -1459,15 +1678,12 @@ __device__ void rook_wstep_body(const ProbDev *__restrict__ P, int nk, int p, in
     }
     __syncthreads();
     if (p == 1 && !st.valid && nR > 0 && nC > 0) {
-        // no sample off the pivot rows and columns: the first row and column without a pivot
-        int fr = nR, fc = nC;
-        for (int t = tid; t < nR; t += NT) if (!K.rpiv[rowpos(t)]) { fr = min(fr, t); break; }
-        for (int t = tid; t < nC; t += NT) if (!K.cpiv[colpos(t)]) { fc = min(fc, t); break; }
-        fr = block_min_int(fr);
-        fc = block_min_int(fc);
+        int fr, fc;
+        rook_first_free(K, B, fr, fc);
         if (fr < nR && fc < nC && tid == 0) {
-            const int row = rowpos(fr), col = colpos(fc);
-            const double x = rook_residual<FNS>(P, u, row, col, W + (int64_t)row * wp, U + (int64_t)col * wp, 1, rk);
+            const int row = B.rowpos(fr), col = B.colpos(fc);
+            const double x = rook_residual_loc<FNS>(P, B, fr / len, lo + fr % len, fc / len1, lo1 + fc % len1,
+                                                    W + (int64_t)row * wp, U + (int64_t)col * wp, rk);
             st.v = fabs(x);
             st.sv = x;
             st.ci = row;
@@ -1485,23 +1701,27 @@ __device__ void rook_wstep_body(const ProbDev *__restrict__ P, int nk, int p, in
         if (p & 1) {
             // column step
             for (int z = tid; z < rk; z += NT) s_f[z] = U[(int64_t)st.cj * wp + z];
+            const int tq = B.col_suf(st.cj), ik1 = st.cj - B.suf[tq] * B.nk1;
             __syncthreads();
             for (int t = g * NT + tid; t < nR; t += G * NT) {
-                const int row = rowpos(t);
+                const int row = B.rowpos(t);
                 if (K.rpiv[row]) continue;
                 ++cnt;
-                const double x = rook_residual<FNS>(P, u, row, st.cj, W + (int64_t)row * wp, s_f, 1, rk);
+                const double x = rook_residual_loc<FNS>(P, B, t / len, lo + t % len, tq, ik1, W + (int64_t)row * wp,
+                                                        s_f, rk);
                 if (better(fabs(x), (uint64_t)row, tv, tk)) { tv = fabs(x); tk = (uint64_t)row; ts = x; }
             }
         } else {
             // row step
             for (int z = tid; z < rk; z += NT) s_f[z] = W[(int64_t)st.ci * wp + z];
+            const int tp = B.row_pref(st.ci), ik = st.ci - B.pref[tp] * B.nk;
             __syncthreads();
             for (int t = g * NT + tid; t < nC; t += G * NT) {
-                const int col = colpos(t);
+                const int col = B.colpos(t);
                 if (K.cpiv[col]) continue;
                 ++cnt;
-                const double x = rook_residual<FNS>(P, u, st.ci, col, s_f, U + (int64_t)col * wp, 1, rk);
+                const double x = rook_residual_loc<FNS>(P, B, tp, ik, t / len1, lo1 + t % len1, s_f,
+                                                        U + (int64_t)col * wp, rk);
                 if (better(fabs(x), (uint64_t)col, tv, tk)) { tv = fabs(x); tk = (uint64_t)col; ts = x; }
             }
         }
@@ -1530,9 +1750,7 @@ __device__ void rook_wfinish_body(const ProbDev *__restrict__ P, int nk, int wg)
     const KDev &K = P->kd[u];
     const int nb = K.nrb * K.ncb;
     __shared__ RookState st;
-    __shared__ KSweep ks;
-    __shared__ int s_pref[TT_MAX_RANK], s_suf[TT_MAX_RANK];
-    __shared__ RookGeom s_g;
+    __shared__ RookBlock B;
     __shared__ double s_f[TT_MAX_RANK];
     double pv, psv;
     uint64_t pk;
@@ -1540,23 +1758,14 @@ __device__ void rook_wfinish_body(const ProbDev *__restrict__ P, int nk, int wg)
     unsigned long long c = 0;
     for (int i = tid; i < G; i += NT) c += K.rcnt[(int64_t)b * G + i];
     c = block_sum_u64(c);
-    if (tid == 0) {
-        st = rook_advance(K.rst[(int64_t)((p - 1) & 1) * nb + b], p, pv, pk, psv);
-        if (st.active) {
-            ks = S->ks[u];
-            rook_block_geom(P, u, b, ks, s_pref, s_suf, s_g);
-        }
-    }
+    if (tid == 0) st = rook_advance(K.rst[(int64_t)((p - 1) & 1) * nb + b], p, pv, pk, psv);
     __syncthreads();
     if (st.active) {                            // uniform: read after the barrier
-        const int len = s_g.len, len1 = s_g.len1, lo = s_g.lo, lo1 = s_g.lo1;
-        const int nR = s_g.np * len, nC = s_g.nq * len1;
-        auto rowpos = [&](int t) { return s_pref[t / len] * K.nk + lo + t % len; };
-        auto colpos = [&](int t) { return s_suf[t / len1] * K.nk1 + lo1 + t % len1; };
+        rook_block_load(P, u, b, B);
         double bv = st.v, bs = st.sv;
         int ci = st.ci, cj = st.cj;
         unsigned long long more = 0;
-        const int r = rook_walk<FNS>(P, u, K, rowpos, colpos, nR, nC, ks.rk, s_f, bv, bs, ci, cj, more);
+        const int r = rook_walk<FNS>(P, K, B, s_f, bv, bs, ci, cj, more);
         more = block_sum_u64(more);
         if (tid == 0) {
             st.v = bv;
@@ -1987,7 +2196,7 @@ static __global__ void __launch_bounds__(NT) k_init_eval_b(const ProbDev *__rest
 }
 
 template <typename V>
-static __global__ void __launch_bounds__(NT) k_sweep_b(const ProbDev *__restrict__ Pa, BatchMap bm)
+static __global__ void __launch_bounds__(NT, 4) k_sweep_b(const ProbDev *__restrict__ Pa, BatchMap bm)
 {
     const int i = batch_find(bm, blockIdx.x);
     const ProbDev *P = Pa + bm.p[i];
