@@ -766,6 +766,10 @@ def bench_phases(args):
             add("new_tile_entries", nt[:, 6] - nt[:, 5])
             add("new_tile_entries_loop", nt[:, 12] - nt[:, 5])
             add("new_tile_reduce", nt[:, 6] - nt[:, 12])
+            for kind, name in ((3, "new_rows"), (2, "new_cols"), (1, "new_both")):
+                kt = nt[nt[:, 13] == kind]
+                add(f"raw_factors_{name}", kt[:, 4] - kt[:, 3])
+                add(f"factor_solves_{name}", kt[:, 5] - kt[:, 4])
             st = r[(r[:, 7] > 0) & (r[:, 10] == 0)]
             add("stored_tile_geometry", st[:, 7] - st[:, 1])
             add("stored_tile_data", st[:, 8] - st[:, 7])

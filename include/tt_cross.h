@@ -255,9 +255,10 @@ int tt_cross_get_stats(tt_cross_h h, tt_stats *st);
  * (start, staging, raw factors, factor solves, entries done), 7-8 wavefront
  * 0's first stored tile (geometry known, done), 9 end, 10 new tiles, 11
  * stored tiles of wavefront 0, 12 the first new-entry tile's entries
- * computed (before its reduction).  Commit record: 0 entry, 1 state
- * loaded, 2 candidates reduced, 3 pivots committed, 4 end.  Zero = not
- * reached.
+ * computed (before its reduction), 13 that tile's kind (1 + 1 if its rows
+ * were stored + 2 if its columns were).  Commit record: 0 entry, 1 state
+ * (and first candidates) loaded, 2 wavefront 0's candidates reduced, 3
+ * pivots committed, 4 end.  Zero = not reached.
  * Returns the number of values (out NULL: the size). */
 int64_t tt_cross_get_stamps(tt_cross_h h, uint64_t *out, int64_t cap, int32_t *layout);
 

@@ -308,10 +308,16 @@ int Problem::allocate()
         HIPCHK(hipGetDevice(&dev));
         HIPCHK(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
         // the search kernel's static LDS (shapes, commit scratch) comes off the top
-        hipFuncAttributes fa;
-        if (fp32) HIPCHK(hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&k_sweep<float>)));
-        else HIPCHK(hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&k_sweep<double>)));
-        lds_static = (int)fa.sharedSizeBytes;
+        // (the larger of the Hilbert kernel's and the general one's)
+        hipFuncAttributes fa, fh;
+        if (fp32) {
+            HIPCHK(hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&k_sweep<float, 0>)));
+            HIPCHK(hipFuncGetAttributes(&fh, reinterpret_cast<const void *>(&k_sweep<float, TT_FN_HILBERT>)));
+        } else {
+            HIPCHK(hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&k_sweep<double, 0>)));
+            HIPCHK(hipFuncGetAttributes(&fh, reinterpret_cast<const void *>(&k_sweep<double, TT_FN_HILBERT>)));
+        }
+        lds_static = (int)std::max(fa.sharedSizeBytes, fh.sharedSizeBytes);
     }
     const size_t w = fp32 ? 4 : 8;
     ProbDev &H = hP;
@@ -477,6 +483,18 @@ int Problem::allocate()
 #endif
     HIPCHK(hipHostMalloc((void **)&hm, sizeof(HostMirror), hipHostMallocMapped | hipHostMallocCoherent));
     HIPCHK(hipHostGetDevicePointer((void **)&H.hm, hm, 0));
+    for (int u = 0; u < d - 1; ++u) {
+        const KDev &K = H.kd[u];
+        KTile &T = H.kt[u];
+        T.nk = K.nk; T.nk1 = K.nk1; T.ld = K.ld; T.RTp = K.RTp; T.CTq = K.CTq; T.TR = K.TR; T.TC = K.TC;
+        T.pad = 0;
+        T.rt_start = K.rt_start; T.rt_len = K.rt_len; T.ct_start = K.ct_start; T.ct_len = K.ct_len;
+        T.E = K.E; T.rpiv = K.rpiv; T.cpiv = K.cpiv; T.rho = K.rho; T.gam = K.gam; T.piv = K.piv;
+        T.Ifull = K.Ifull; T.Jfull = K.Jfull;
+        T.Ipre = u >= 1 ? H.kd[u - 1].Ifull : nullptr;
+        T.Jsuf = u + 1 < d - 1 ? H.kd[u + 1].Jfull : nullptr;
+        T.cand = K.cand;
+    }
     // the first sweep searches the initial superblocks (one prefix, one
     // suffix, every tile stored): its tile counts are fixed by the geometry
     std::memset(&H.sh0, 0, sizeof H.sh0);
@@ -598,6 +616,7 @@ template <typename V> int Problem::launch_ahead()
     const int L = std::max(1, opt.lookahead);
     while (launched < done_known + L && launched < max_sweeps) {
         SweepArgs a;
+        std::memset(&a, 0, sizeof a);
         a.sweep = launched;
         a.nk = nk;
         a.S = hP.S;
@@ -607,6 +626,9 @@ template <typename V> int Problem::launch_ahead()
             const int k = u + 1;
             const KDev &K = hP.kd[u];
             const int all = rub[k - 1] * K.RTp * rub[k + 1] * K.CTq;
+            // the commit's first round of candidates: at most this many
+            a.cand[u] = K.cand;
+            a.ntl_max[u] = rook ? K.nrb * K.ncb : all;
             const int st = std::min(all, rst[k - 1] * K.RTp * rst[k + 1] * K.CTq);
             units += (all - st) + (st + NT / 64 - 1) / (NT / 64);
             lds = std::max(lds, sweep_lds_bytes(rub[k], K.TR, K.TC, sizeof(V)));

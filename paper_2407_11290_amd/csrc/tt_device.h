@@ -223,6 +223,23 @@ struct KDev {
     unsigned long long *rcnt;     // counts per (block, workgroup) in the current sweep
 };
 
+// The fields of an unfolding's descriptor that the search tiles read, with
+// its neighbours' index-tuple arrays; kept apart and small, so that a search
+// workgroup loads every unfolding's copy in its first round of loads.
+struct KTile {
+    int nk, nk1, ld, RTp, CTq, TR, TC, pad;
+    const int *rt_start, *rt_len, *ct_start, *ct_len;
+    void *E;
+    const uint8_t *rpiv, *cpiv;
+    const int *rho, *gam;
+    const double *piv;
+    const int *Ifull, *Jfull;
+    const int *Ipre;              // I_{<=k-1} (unfolding k-1), null for k = 1
+    const int *Jsuf;              // J_{>k+1} (unfolding k+1), null for k = d-1
+    Cand *cand;
+};
+constexpr int KTILE_WORDS = (int)(sizeof(KTile) / 4);
+
 // A block's rook search between the launches of the split search.
 struct RookState {
     double v, sv;                 // |residual| and residual at (ci, cj)
@@ -312,6 +329,7 @@ struct ProbDev {
     int grid[TT_MAX_D];           // subtensor blocks per mode
     FnDev F;
     KDev kd[TT_MAX_D];
+    KTile kt[TT_MAX_D];           // the search tiles' copy of kd
     ProbState *S;
     HostMirror *hm;               // device alias of the host mirror
     RunDev run;
@@ -329,6 +347,10 @@ struct SweepArgs {
     int sweep;
     int nk;
     ProbState *S;                 // the problem's state (saves a dependent load)
+    // for the commit: each unfolding's candidate array and a bound on the
+    // tiles (rook: blocks) the sweep searched, known on the host
+    const Cand *cand[TT_MAX_D];
+    int ntl_max[TT_MAX_D];
 };
 
 }  // namespace ttc

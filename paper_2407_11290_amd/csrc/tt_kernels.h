@@ -117,7 +117,7 @@ struct TileGeom {
     int row0, col0, p, q;         // first row / column position, prefix / suffix
 };
 
-__device__ inline TileGeom tile_geom(const KDev &K, int u, int R, int C)
+__device__ inline TileGeom tile_geom(const KTile &K, int u, int R, int C)
 {
     TileGeom g;
     g.u = u; g.R = R; g.C = C;
@@ -165,7 +165,7 @@ __device__ inline void block_best_t0(double &v, uint64_t &key, double &sv)
 // (clamped), so that a batch costs one round trip; the rows' masks and W
 // factors of a 64-row chunk are in flight with the first batch.
 template <typename V, int B>
-__device__ void stored_tile_wave(const KDev &K, const KSweep &ks, const TileGeom &g, double &bv, uint64_t &bk,
+__device__ void stored_tile_wave(const KTile &K, const KSweep &ks, const TileGeom &g, double &bv, uint64_t &bk,
                                  double &bs)
 {
     const int lane = threadIdx.x & 63;
@@ -235,6 +235,18 @@ template <int n> __device__ inline float row_bcast(float x)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x150 + n, 0xf, 0xf, false));
 }
 
+// Inclusive prefix sum over each 16-lane row of the wavefront (DPP row
+// shifts; lanes with no source add zero).  Every lane of the row must be
+// active.
+__device__ inline int row_scan_incl(int x)
+{
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);
+    return x;
+}
+
 // Factor solves of a new-entry tile for ranks rk <= RK <= 16: a 16-lane
 // group per row (column), lane z holding factor z; at step z' the finished
 // factor z' reaches the lanes z > z' of its group by a row broadcast.
@@ -299,21 +311,23 @@ __device__ inline void solves_lg(gptr_t<V> E, int64_t ld, const TileGeom &g, V *
 //   column j: e_z = X(rho_z, j);   for z' < z: e_z -= W(rho_z, z') * e_z'/p_z' -> p_z U(z, j)
 // and the frozen pivot columns / rows of the tile receive those values.
 template <typename V, int FNS>
-__device__ void new_tile(const ProbDev *__restrict__ P, int nk, int u, int R, int C, const KSweep &ks, double &bv,
-                         uint64_t &bk, double &bs, V *sm, unsigned long long *rec)
+__device__ void new_tile(const ProbDev *__restrict__ P, const KTile &K, int u, int R, int C, const KSweep &ks,
+                         double &bv, uint64_t &bk, double &bs, V *sm, unsigned long long *rec)
 {
     const int d = P->d, k = u + 1, tid = threadIdx.x, rk = ks.rk;
-    const KDev &K = P->kd[u];
-    // One round of scalar loads: the unfolding's descriptor and the
-    // neighbours' tuple arrays.  The tile's place follows by arithmetic; its
-    // extents (the tile tables) load together with the staging below.
-    const gptr_t<const int> Ipre = as_global((const int *)(k >= 2 ? P->kd[u - 1].Ifull : nullptr));
-    const gptr_t<const int> Jsuf = as_global((const int *)(u + 1 < nk ? P->kd[u + 1].Jfull : nullptr));
+    // The descriptor and the neighbours' tuple arrays are at hand; the tile's
+    // place follows by arithmetic, and its extents (the tile tables) load
+    // together with the staging below.
+    const gptr_t<const int> Ipre = as_global(K.Ipre);
+    const gptr_t<const int> Jsuf = as_global(K.Jsuf);
     const int RTp = K.RTp, CTq = K.CTq;
     const int tp = R / RTp, tt = R - tp * RTp, tq = C / CTq, ttc = C - tq * CTq;
     // row (column) blocks are whole prefixes (suffixes), so whether the tile's
     // rows (columns) were stored follows from the prefix (suffix) index alone
     const bool rows_old = tp * K.nk < ks.nr_st, cols_old = tq * K.nk1 < ks.nc_st;
+#ifdef TT_STAMPS
+    if (rec && tid == 0) rec[13] = 1 + (rows_old ? 1 : 0) + (cols_old ? 2 : 0);
+#endif
     TileGeom g;
     g.u = u; g.R = R; g.C = C; g.p = tp; g.q = tq;
     g.ik0 = K.rt_start[tt]; g.nrows = K.rt_len[tt];
@@ -363,10 +377,24 @@ __device__ void new_tile(const ProbDev *__restrict__ P, int nk, int u, int R, in
     const int cpv = (tcol < g.ncols) ? as_global((const uint8_t *)K.cpiv)[g.col0 + tcol] : 1;
     for (int ii = tid; ii < g.nrows; ii += NT) s_rp[ii] = as_global((const uint8_t *)K.rpiv)[g.row0 + ii];
     // raw factors: frozen entries, or the generating function at the skeleton
+    // (the frozen factors load UL per thread at once: a loop that stored each
+    // value before loading the next would wait a round trip per pass)
+    constexpr int UL = 4;
     if (rows_old) {
-        for (int e = tid; e < rk * g.nrows; e += NT) {
-            const int z = e / g.nrows, ii = e - z * g.nrows;
-            Wt[z * TRm + ii] = E[(int64_t)(g.row0 + ii) * ld + s_gam[z]];
+        for (int e0 = tid; e0 < rk * g.nrows; e0 += UL * NT) {
+            V x[UL];
+#pragma unroll
+            for (int j = 0; j < UL; ++j) {
+                const int e = min(e0 + j * NT, rk * g.nrows - 1);
+                const int z = e / g.nrows, ii = e - z * g.nrows;
+                x[j] = E[(int64_t)(g.row0 + ii) * ld + s_gam[z]];
+            }
+#pragma unroll
+            for (int j = 0; j < UL; ++j) {
+                const int e = e0 + j * NT;
+                const int z = e / g.nrows, ii = e - z * g.nrows;
+                if (e < rk * g.nrows) Wt[z * TRm + ii] = x[j];
+            }
         }
     } else {
         for (int e = tid; e < rk * rk; e += NT) {
@@ -393,9 +421,20 @@ __device__ void new_tile(const ProbDev *__restrict__ P, int nk, int u, int R, in
         }
     }
     if (cols_old) {
-        for (int e = tid; e < rk * g.ncols; e += NT) {
-            const int z = e / g.ncols, jj = e - z * g.ncols;
-            Ut[z * TCm + jj] = E[(int64_t)s_rho[z] * ld + g.col0 + jj] / s_piv[z];
+        for (int e0 = tid; e0 < rk * g.ncols; e0 += UL * NT) {
+            V x[UL];
+#pragma unroll
+            for (int j = 0; j < UL; ++j) {
+                const int e = min(e0 + j * NT, rk * g.ncols - 1);
+                const int z = e / g.ncols, jj = e - z * g.ncols;
+                x[j] = E[(int64_t)s_rho[z] * ld + g.col0 + jj];
+            }
+#pragma unroll
+            for (int j = 0; j < UL; ++j) {
+                const int e = e0 + j * NT;
+                const int z = e / g.ncols, jj = e - z * g.ncols;
+                if (e < rk * g.ncols) Ut[z * TCm + jj] = x[j] / s_piv[z];
+            }
         }
     } else {
         for (int e = tid; e < rk * rk; e += NT) {
@@ -570,10 +609,11 @@ __device__ void sweep_body(const ProbDev *__restrict__ P, const ProbState *S, in
             if (rec && rec[10] == 0) nrec = rec;          // the workgroup's first new tile
             TT_STAMP(nrec, 2);
 #endif
-            new_tile<V, FNS>(P, nk, u, R, C, ks[u], bv, bk, bs, (V *)smem_raw, nrec);
+            const KTile &K = P->kt[u];
+            new_tile<V, FNS>(P, K, u, R, C, ks[u], bv, bk, bs, (V *)smem_raw, nrec);
             TT_STAMP_ADD(rec, 10, 1);
             if (tid == 0) {
-                const gptr_t<Cand> c = as_global(P->kd[u].cand) + (R * CT + C);
+                const gptr_t<Cand> c = as_global(K.cand) + (R * CT + C);
                 c->v = bv; c->key = bk; c->sv = bs;
             }
             __syncthreads();
@@ -586,7 +626,7 @@ __device__ void sweep_body(const ProbDev *__restrict__ P, const ProbState *S, in
                 while (u + 1 < nk && st >= sh.soff[u + 1]) ++u;
                 const int idx = st - sh.soff[u], CTs = sh.CTs[u];
                 const int R = idx / CTs, C = idx - R * CTs;
-                const KDev &K = P->kd[u];
+                const KTile &K = P->kt[u];
                 const TileGeom g = tile_geom(K, u, R, C);
 #ifdef TT_STAMPS
                 // wave 0's first stored tile: geometry known, tile done
@@ -661,16 +701,72 @@ __device__ inline double fp64_check_wave(const ProbDev *P, const KDev &K, int u,
     return x;
 }
 
-// One workgroup for every unfolding: wavefronts reduce the tile candidates
-// (best of the local pivots, Sec. 3.2.1), wavefront u decides and commits
-// unfolding u, and thread 0 publishes the outcome.
+// The commit, one workgroup of NTC threads for every unfolding: wavefronts
+// reduce the tile candidates (best of the local pivots, Sec. 3.2.1), a
+// wavefront per unfolding decides and commits it, and thread 0 publishes the
+// outcome.  (A commit placed in the search launch's last workgroup would need
+// every search workgroup to make its candidates visible device-wide before it
+// counts itself; on gfx950 that release writes back the whole L2 of the
+// workgroup's XCD, full of residual updates, and the search then ran about
+// three times slower.)
 constexpr int NTC = 512;
+constexpr int CB = 8;              // candidates per lane in one round of loads
 
-template <typename V, int FNS>
-__device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int sweep, int nk)
+// The state a commit reads before it starts: this sweep's shapes and tile
+// counts, the committed ranks, the threshold and the counters, and the
+// unfoldings' descriptors.
+struct CommitIn {
+    KSweep ks[TT_MAX_D];
+    int ntl[TT_MAX_D];               // tiles (rook: blocks) each unfolding searched
+    int rold[TT_MAX_D + 1];
+    int stop;
+    int err;                         // the state's error code, kept current here
+    double tau;
+    unsigned long long acc[3];       // alg_bytes, new_entries, pivoted
+    KDev kd[TT_MAX_D];
+    // the problem's fields the commit reads later, read up front
+    int rook, r_max, fp32, rcap, hist_cap;
+    HostMirror *hm;
+};
+
+// A candidate that loses every comparison.
+__device__ inline void cand_none(Cand &c)
+{
+    c.v = -1.0; c.key = ~0ULL; c.sv = 0.0;
+}
+
+// Best candidate of tiles [i0, ntl) taken by lane l of wavefront sl of wpu:
+// indices i0 + l + 64 * wpu * j, CB per round of loads.
+__device__ inline void scan_cands(gptr_t<const Cand> cand, int i0, int ntl, int wpu, double &bv, uint64_t &bk,
+                                  double &bs)
+{
+    const int lane = threadIdx.x & 63;
+    for (; i0 < ntl; i0 += 64 * wpu * CB) {
+        Cand c[CB];
+#pragma unroll
+        for (int j = 0; j < CB; ++j) {
+            const int i = i0 + lane + 64 * wpu * j;
+            if (i < ntl) {
+                const gptr_t<const Cand> cp = cand + i;
+                c[j].v = cp->v; c[j].key = cp->key; c[j].sv = cp->sv;
+            } else {
+                cand_none(c[j]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < CB; ++j)
+            if (better(c[j].v, c[j].key, bv, bk)) { bv = c[j].v; bk = c[j].key; bs = c[j].sv; }
+    }
+}
+
+// PRE (single problems): a holds each unfolding's candidate array and a
+// bound on its tile count, so that the first round of candidates is in
+// flight with the state; batches pass PRE = false and a is not read.
+template <typename V, int FNS, bool PRE>
+__device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int sweep, int nk, const SweepArgs &a)
 {
     // the wavefront index is uniform across the wavefront: saying so keeps the
-    // per-unfolding descriptor reads scalar
+    // per-unfolding reads scalar
     const int tid = threadIdx.x, wid = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     constexpr int NW = NTC / 64;
     const int d = nk + 1, par = sweep & 1;    // nk from the launch: no dependent read
@@ -681,91 +777,96 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
 #else
     unsigned long long *const rec = nullptr;
 #endif
-    __shared__ KSweep ks[TT_MAX_D];
-    __shared__ double s_wv[TT_MAX_D], s_wsv[TT_MAX_D];
-    __shared__ uint64_t s_wk[TT_MAX_D];
-    __shared__ int s_prop[TT_MAX_D], s_rold[TT_MAX_D + 1], s_rnew[TT_MAX_D + 1];
-    __shared__ unsigned long long s_bytes[TT_MAX_D], s_new[TT_MAX_D], s_piv[TT_MAX_D];
-    __shared__ int s_stop;
-    __shared__ double s_tau;
-    __shared__ unsigned long long s_acc[3];
-    // one round of loads: stop flag, shapes, tile counts, ranks, threshold,
-    // counters
-    __shared__ int s_ntl[TT_MAX_D];
-    if (tid < nk) {
-        ks[tid] = S->ks[tid];
-        s_ntl[tid] = S->sh.RT[tid] * S->sh.CT[tid];     // tiles this sweep searched
+    // wpu >= 1 wavefronts per unfolding, the groups of wpu wavefronts
+    // striding over the unfoldings (one pass when nk <= NW)
+    const int wpu = nk <= NW ? NW / nk : 1, ngr = NW / wpu, sl = wid % wpu;
+    const int us0 = wid / wpu;
+    const bool wave_on = us0 < nk && wid < ngr * wpu;
+    // one round of loads: the state, the descriptors and, with a, the first
+    // round of this wavefront's candidates (up to the launch's bound; those
+    // past the exact count are dropped below)
+    __shared__ CommitIn ci;
+    Cand c0[CB];
+#pragma unroll
+    for (int j = 0; j < CB; ++j) cand_none(c0[j]);
+    const int nmax = PRE && wave_on ? a.ntl_max[us0] : 0;
+    if (PRE && wave_on) {
+        const gptr_t<const Cand> cand = as_global(a.cand[us0]);
+#pragma unroll
+        for (int j = 0; j < CB; ++j) {
+            const int i = 64 * sl + lane + 64 * wpu * j;
+            if (i < nmax) {
+                const gptr_t<const Cand> cp = cand + i;
+                c0[j].v = cp->v; c0[j].key = cp->key; c0[j].sv = cp->sv;
+            }
+        }
     }
-    if (tid <= d) s_rold[tid] = S->r[par][tid];
-    if (tid == NTC - 1) { s_stop = S->stop; s_tau = S->tau; }
-    if (tid == NTC - 2) { s_acc[0] = S->alg_bytes; s_acc[1] = S->new_entries; s_acc[2] = S->pivoted; }
+    if (tid < nk) {
+        load_words(ci.ks[tid], &S->ks[tid]);
+        ci.ntl[tid] = as_global(&S->sh.RT[tid])[0] * as_global(&S->sh.CT[tid])[0];
+    }
+    if (tid <= d) ci.rold[tid] = as_global(&S->r[par][tid])[0];
+    if (tid == NTC - 1) {
+        ci.stop = as_global(&S->stop)[0];
+        ci.tau = as_global(&S->tau)[0];
+        ci.err = as_global(&S->err)[0];
+    }
+    if (tid == NTC - 2) {
+        ci.acc[0] = as_global(&S->alg_bytes)[0];
+        ci.acc[1] = as_global(&S->new_entries)[0];
+        ci.acc[2] = as_global(&S->pivoted)[0];
+    }
+    if (tid == NTC - 3) {
+        ci.rook = P->rook; ci.r_max = P->r_max; ci.fp32 = P->fp32; ci.rcap = P->rcap;
+        ci.hist_cap = P->hist_cap; ci.hm = P->hm;
+    }
+    constexpr int KW = (int)(sizeof(KDev) / 4);
+    static_assert(sizeof(KDev) % 4 == 0, "word-sized descriptor");
+    for (int w = tid; w < nk * KW; w += NTC) ((int *)ci.kd)[w] = as_global((const int *)P->kd)[w];
     __syncthreads();
     TT_STAMP(rec, 1);
-    if (s_stop) return;
-    // best candidate per unfolding: wpu >= 1 wavefronts per unfolding, the
-    // groups of wpu wavefronts striding over the unfoldings (one pass when
-    // nk <= NW), each lane with CB candidates in flight, so that a
-    // superblock's candidates come in one round of loads.  Partial result
-    // (u, sl) sits in slot u * wpu + sl < max(NW, nk).
-    constexpr int CB = 8;
-    constexpr int NPS = NW > TT_MAX_D ? NW : TT_MAX_D;
+    if (ci.stop) return;
+    KSweep *const ks = ci.ks;
+    const KDev *const kd = ci.kd;
+    const int *const s_rold = ci.rold;
+    const double s_tau = ci.tau;
+    const bool rook = ci.rook != 0;
     __shared__ unsigned long long s_rcnt[TT_MAX_D];
-    __shared__ double s_pv[NPS], s_psv[NPS];
-    __shared__ uint64_t s_pk[NPS];
-    const int wpu = nk <= NW ? NW / nk : 1, ngr = NW / wpu, sl = wid % wpu;
-    for (int us = wid / wpu; us < nk && wid < ngr * wpu; us += ngr) {   // uniform across the wavefront
-        const KDev &K = P->kd[us];
-        const int ntl = P->rook ? K.nrb * K.ncb : s_ntl[us];
-        double bv = -1.0, bs = 0.0;
-        uint64_t bk = ~0ULL;
-        if (P->rook && sl == 0) {
+    __shared__ int s_prop[TT_MAX_D], s_rnew[TT_MAX_D + 1];
+    __shared__ unsigned long long s_bytes[TT_MAX_D], s_new[TT_MAX_D], s_piv[TT_MAX_D];
+    __shared__ int s_geo[TT_MAX_D][4];
+
+    // best candidate of unfolding us over this wavefront's share of the
+    // tiles, in every lane
+    auto scan = [&](int us, double &bv, uint64_t &bk, double &bs) {
+        const KDev &K = kd[us];
+        const int ntl = rook ? K.nrb * K.ncb : ci.ntl[us];
+        bv = -1.0; bs = 0.0; bk = ~0ULL;
+        if (rook && sl == 0) {
             // residuals the block searches looked at
             unsigned long long c = 0;
             for (int i = lane; i < ntl; i += 64) c += as_global((unsigned long long *)K.bcnt)[i];
             for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
             if (lane == 0) s_rcnt[us] = c;
         }
-        const gptr_t<const Cand> cand = as_global((const Cand *)K.cand);
-        for (int i0 = 64 * sl; i0 < ntl; i0 += 64 * wpu * CB) {
-            Cand c[CB];
+        int i0 = 64 * sl;
+        if (PRE && us == us0 && ntl <= nmax) {      // the first round is in registers
 #pragma unroll
             for (int j = 0; j < CB; ++j) {
                 const int i = i0 + lane + 64 * wpu * j;
-                if (i < ntl) {
-                    const gptr_t<const Cand> cp = cand + i;
-                    c[j].v = cp->v; c[j].key = cp->key; c[j].sv = cp->sv;
-                } else {
-                    c[j].v = -1.0; c[j].key = ~0ULL; c[j].sv = 0.0;
-                }
+                if (i < ntl && better(c0[j].v, c0[j].key, bv, bk)) { bv = c0[j].v; bk = c0[j].key; bs = c0[j].sv; }
             }
-#pragma unroll
-            for (int j = 0; j < CB; ++j)
-                if (better(c[j].v, c[j].key, bv, bk)) { bv = c[j].v; bk = c[j].key; bs = c[j].sv; }
+            i0 += 64 * wpu * CB;
         }
+        scan_cands(as_global((const Cand *)K.cand), i0, ntl, wpu, bv, bk, bs);
         wave_best(bv, bk, bs);
-        const int slot = us * wpu + sl;
-        if (lane == 0) { s_pv[slot] = bv; s_pk[slot] = bk; s_psv[slot] = bs; }
-    }
-    __syncthreads();
-    if (tid < nk) {
-        // the unfolding's wavefronts in order (the comparison decides; the
-        // order only matters for equal keys, which cannot occur)
-        double bv = -1.0, bs = 0.0;
-        uint64_t bk = ~0ULL;
-        for (int w = tid * wpu; w < (tid + 1) * wpu; ++w)
-            if (better(s_pv[w], s_pk[w], bv, bk)) { bv = s_pv[w]; bk = s_pk[w]; bs = s_psv[w]; }
-        s_wv[tid] = bv; s_wk[tid] = bk; s_wsv[tid] = bs;
-    }
-    __syncthreads();
-    TT_STAMP(rec, 2);
-    // decide and commit
-    __shared__ int s_geo[TT_MAX_D][4];
-    for (int u = wid; u < nk; u += NW) {
+    };
+
+    // decide and commit unfolding u from its best candidate (one wavefront)
+    auto decide = [&](int u, double bv, uint64_t bk, double bs) {
         const int k = u + 1;
-        const KDev &K = P->kd[u];
+        const KDev &K = kd[u];
         const int rk = ks[u].rk, nr = ks[u].nr, nc = ks[u].nc;
-        const double bv = s_wv[u], bs = s_wsv[u];
-        const uint64_t bk = s_wk[u];
         const bool found = bv >= 0.0;
         const int row = (int)(bk >> 32), col = (int)(bk & 0xffffffffULL);
         double e = found ? bv : 0.0, p64 = 0.0, w64 = 0.0, v64 = 0.0;
@@ -777,7 +878,7 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
             }
         }
         const bool over = found && e > s_tau;
-        const bool propose = over && rk < P->r_max && rk < K.rk_cap;
+        const bool propose = over && rk < ci.r_max && rk < K.rk_cap;
         if (propose) {
             const int z = rk;
             const int p = row / K.nk, ik = row - p * K.nk;
@@ -786,29 +887,35 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
                 as_global((int *)K.rho)[z] = row;
                 as_global((int *)K.gam)[z] = col;
                 as_global((double *)K.piv)[z] = bs;
-                as_global((double *)K.piv64)[z] = P->fp32 ? p64 : bs;
+                as_global((double *)K.piv64)[z] = ci.fp32 ? p64 : bs;
                 as_global((uint8_t *)K.rpiv)[row] = (uint8_t)(z + 1);
                 as_global((uint8_t *)K.cpiv)[col] = (uint8_t)(z + 1);
                 as_global((int *)K.Ifull)[z * k + k - 1] = ik;
                 as_global((int *)K.Jfull)[z * (d - k)] = ik1;
             }
-            if (lane < k - 1) as_global((int *)K.Ifull)[z * k + lane] = as_global((const int *)P->kd[u - 1].Ifull)[p * (k - 1) + lane];
-            if (lane < d - k - 1) as_global((int *)K.Jfull)[z * (d - k) + 1 + lane] = as_global((const int *)P->kd[u + 1].Jfull)[q * (d - k - 1) + lane];
-            if (P->fp32 && lane < z) {
-                as_global((double *)K.Wp64)[z * P->rcap + lane] = w64;
-                as_global((double *)K.Up64)[lane * P->rcap + z] = v64;
+            if (lane < k - 1)
+                as_global((int *)K.Ifull)[z * k + lane] = as_global((const int *)kd[u - 1].Ifull)[p * (k - 1) + lane];
+            if (lane < d - k - 1)
+                as_global((int *)K.Jfull)[z * (d - k) + 1 + lane] =
+                    as_global((const int *)kd[u + 1].Jfull)[q * (d - k - 1) + lane];
+            if (ci.fp32 && lane < z) {
+                as_global((double *)K.Wp64)[z * ci.rcap + lane] = w64;
+                as_global((double *)K.Up64)[lane * ci.rcap + z] = v64;
             }
         }
         if (lane == 0) {
-            if (sweep < P->hist_cap) as_global((double *)K.hist)[sweep] = e;
+            if (sweep < ci.hist_cap) as_global((double *)K.hist)[sweep] = e;
             S->last_best[u] = e;
             if (over && !propose) S->capped = 1;
-            if (propose && bs == 0.0) S->err = TT_ESINGULAR;
+            if (propose && bs == 0.0) {
+                S->err = TT_ESINGULAR;
+                ci.err = TT_ESINGULAR;
+            }
             // traffic accounting of this sweep's tiles
             const unsigned long long nst = (unsigned long long)ks[u].nr_st, cst = (unsigned long long)ks[u].nc_st;
             const unsigned long long all = (unsigned long long)nr * (unsigned long long)nc;
             const unsigned long long live = (nst - rk) * (cst - rk);
-            if (P->rook) {
+            if (rook) {
                 // every residual looked at streams one factor vector of rk
                 // values (the other is shared by the whole scan)
                 s_bytes[u] = s_rcnt[u] * 8ull * (unsigned long long)rk;
@@ -826,13 +933,50 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
                 ks[u].agam = col;
                 ks[u].apiv = bs;
             }
-            // the descriptor fields the next shapes need, already read here
+            // the descriptor fields the next shapes need
             s_geo[u][0] = K.nk;
             s_geo[u][1] = K.nk1;
             s_geo[u][2] = K.RTp;
             s_geo[u][3] = K.CTq;
         }
-        if (tid == 0) { s_rnew[0] = 1; s_rnew[d] = 1; }
+    };
+
+    if (tid == 0) { s_rnew[0] = 1; s_rnew[d] = 1; }
+    if (wpu == 1) {
+        // a wavefront per unfolding: it decides as soon as its scan is done
+        for (int u = wid; u < nk; u += NW) {
+            double bv, bs;
+            uint64_t bk;
+            scan(u, bv, bk, bs);
+            TT_STAMP(rec, 2);
+            decide(u, bv, bk, bs);
+        }
+    } else {
+        // several wavefronts per unfolding: partial result (u, sl) in slot
+        // u * wpu + sl < NW, combined in wavefront order (the comparison
+        // decides; the order only matters for equal keys, which cannot occur)
+        __shared__ double s_pv[NW], s_psv[NW];
+        __shared__ uint64_t s_pk[NW];
+        __shared__ double s_wv[TT_MAX_D], s_wsv[TT_MAX_D];
+        __shared__ uint64_t s_wk[TT_MAX_D];
+        if (wave_on) {
+            double bv, bs;
+            uint64_t bk;
+            scan(us0, bv, bk, bs);
+            const int slot = us0 * wpu + sl;
+            if (lane == 0) { s_pv[slot] = bv; s_pk[slot] = bk; s_psv[slot] = bs; }
+        }
+        __syncthreads();
+        if (tid < nk) {
+            double bv = -1.0, bs = 0.0;
+            uint64_t bk = ~0ULL;
+            for (int w = tid * wpu; w < (tid + 1) * wpu; ++w)
+                if (better(s_pv[w], s_pk[w], bv, bk)) { bv = s_pv[w]; bk = s_pk[w]; bs = s_psv[w]; }
+            s_wv[tid] = bv; s_wk[tid] = bk; s_wsv[tid] = bs;
+        }
+        __syncthreads();
+        TT_STAMP(rec, 2);
+        for (int u = wid; u < nk; u += NW) decide(u, s_wv[u], s_wk[u], s_wsv[u]);
     }
     __syncthreads();
     TT_STAMP(rec, 3);
@@ -856,8 +1000,9 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
             n.apiv = ks[u].apiv;
             S->ks[u] = n;
             S->r[par ^ 1][k] = s_rnew[k];
-            const int RT = (n.nr / knk) * kRTp, CT = (n.nc / knk1) * kCTq;
-            const int RTs = (n.nr_st / knk) * kRTp, CTs = (n.nc_st / knk1) * kCTq;
+            // tile counts from the ranks (rows r_{k-1} n_k, columns n_{k+1} r_{k+1})
+            const int RT = s_rnew[k - 1] * kRTp, CT = s_rnew[k + 1] * kCTq;
+            const int RTs = s_rold[k - 1] * kRTp, CTs = s_rold[k + 1] * kCTq;
             S->sh.RT[u] = RT;
             S->sh.CT[u] = CT;
             S->sh.RTs[u] = RTs;
@@ -865,11 +1010,8 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
             nn = RT * CT - RTs * CTs;
             ns = RTs * CTs;
         }
-        int pn = nn, ps = ns;                  // inclusive scans (nk <= 16 lanes carry counts)
-        for (int off = 1; off < 16; off <<= 1) {
-            const int a = __shfl_up(pn, off, 64), b = __shfl_up(ps, off, 64);
-            if (u >= off) { pn += a; ps += b; }
-        }
+        // inclusive scans over the first 16 lanes (nk <= 15 carry counts)
+        const int pn = row_scan_incl(nn), ps = row_scan_incl(ns);
         if (u < nk) {
             S->sh.noff[u] = pn - nn;
             S->sh.soff[u] = ps - ns;
@@ -880,25 +1022,31 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
         }
     }
     if (tid == 0) {
+        // (every LDS read in flight at once; the error code is the one kept
+        // in LDS, so that nothing here waits on device memory)
         int any = 0;
-        unsigned long long ab = s_acc[0], ne = s_acc[1], pv = s_acc[2];
-        for (int u = 0; u < nk; ++u) {
-            any |= s_prop[u];
-            ab += s_bytes[u];
-            ne += s_new[u];
-            pv += s_piv[u];
+        unsigned long long ab = ci.acc[0], ne = ci.acc[1], pv = ci.acc[2];
+#pragma unroll
+        for (int u = 0; u < TT_MAX_D; ++u) {
+            if (u < nk) {
+                any |= s_prop[u];
+                ab += s_bytes[u];
+                ne += s_new[u];
+                pv += s_piv[u];
+            }
         }
+        const int err = ci.err;
         S->alg_bytes = ab;
         S->new_entries = ne;
         S->pivoted = pv;
-        const int stop = (!any || S->err) ? 1 : 0;
+        const int stop = (!any || err) ? 1 : 0;
         S->stop = stop;
         S->sweeps = sweep + 1;
-        HostMirror *hm = P->hm;
+        HostMirror *hm = ci.hm;
         if (stop) {
             // final sweep: ranks and status must be visible before the count
             for (int j = 0; j <= d; ++j) hm->r[j] = s_rold[j];
-            hm->err = S->err;
+            hm->err = err;
             hm->stop = stop;
             __threadfence_system();
             __hip_atomic_store(&hm->sweeps_done, sweep + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -914,7 +1062,7 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
 template <typename V, int FNS = 0>
 static __global__ void __launch_bounds__(NTC) k_commit(const ProbDev *__restrict__ P, SweepArgs a)
 {
-    commit_body<V, FNS>(P, a.S, a.sweep, a.nk);
+    commit_body<V, FNS, true>(P, a.S, a.sweep, a.nk, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -1841,6 +1989,21 @@ static __global__ void __launch_bounds__(NT) k_init_eval(const ProbDev *__restri
     init_eval_body<V, FNS>(P, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
+// Copies n ints from device memory to LDS with NTH threads, U loads per
+// thread in flight before any store (a plain loop would wait a round trip per
+// pass).
+template <int U, int NTH> __device__ inline void copy_to_lds(int *dst, gptr_t<const int> src, int n)
+{
+    for (int e0 = (int)threadIdx.x; e0 < n; e0 += U * NTH) {
+        int v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) v[j] = src[min(e0 + j * NTH, n - 1)];
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            if (e0 + j * NTH < n) dst[e0 + j * NTH] = v[j];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Cores by Alg. 4 (FP64), one 64-thread workgroup per 64 rows of
 // A_k = X(I_{<=k-1} x [n_k], J_{>k}) (the sliced fibers of eq. corereshape).
@@ -1957,7 +2120,16 @@ __device__ void cores_body(const ProbDev *__restrict__ P, const CoreArgs &a, dou
         if (e >= (int64_t)rd * nd) return;
         const int pp = (int)(e / nd), i = (int)(e - (int64_t)pp * nd);
         const gptr_t<const int> Ip = as_global((const int *)K.Ifull) + pp * (d - 1);
-        G[a.goff[d - 1] + e] = fn_value_ix<double, FNS>(P->F, [&](int j) { return j < d - 1 ? Ip[j] : i; });
+        // the lane's index tuple, every entry in flight at once, through LDS
+        // (the function reads it by a runtime index)
+        __shared__ int sIp[A4W * TT_MAX_D];
+        int pv[TT_MAX_D];
+#pragma unroll
+        for (int j = 0; j < TT_MAX_D; ++j) pv[j] = Ip[min(j, d - 2)];
+#pragma unroll
+        for (int j = 0; j < TT_MAX_D; ++j)
+            if (j < d - 1) sIp[lane * TT_MAX_D + j] = pv[j];
+        G[a.goff[d - 1] + e] = fn_value_ix<double, FNS>(P->F, [&](int j) { return j < d - 1 ? sIp[lane * TT_MAX_D + j] : i; });
         return;
     }
     int u = 0;
@@ -1975,11 +2147,17 @@ __device__ void cores_body(const ProbDev *__restrict__ P, const CoreArgs &a, dou
     // one round of loads: the pivots' index tuples and every lane's prefix
     __shared__ int sJ[TT_MAX_RANK * TT_MAX_D], sI[TT_MAX_RANK * TT_MAX_D], sPre[A4W * TT_MAX_D];
     const gptr_t<const int> Jf = as_global((const int *)K.Jfull), If = as_global((const int *)K.Ifull);
-    for (int e = lane; e < rk * nj; e += A4W) sJ[e] = Jf[e];
-    for (int e = lane; e < rk * k; e += A4W) sI[e] = If[e];
+    copy_to_lds<4, A4W>(sJ, Jf, rk * nj);
+    copy_to_lds<4, A4W>(sI, If, rk * k);
     if (k >= 2) {
+        // the lane's prefix, every entry in flight at once
         const gptr_t<const int> preI = as_global((const int *)P->kd[u - 1].Ifull) + p * (k - 1);
-        for (int j = 0; j < k - 1; ++j) sPre[lane * TT_MAX_D + j] = preI[j];
+        int pv[TT_MAX_D];
+#pragma unroll
+        for (int j = 0; j < TT_MAX_D; ++j) pv[j] = preI[min(j, k - 2)];
+#pragma unroll
+        for (int j = 0; j < TT_MAX_D; ++j)
+            if (j < k - 1) sPre[lane * TT_MAX_D + j] = pv[j];
     }
     wave_sync();
     if constexpr (FNS == TT_FN_HILBERT) {
@@ -2207,7 +2385,8 @@ template <typename V>
 static __global__ void __launch_bounds__(NTC) k_commit_b(const ProbDev *__restrict__ Pa, BatchMap bm)
 {
     const ProbDev *P = Pa + bm.p[blockIdx.x];
-    commit_body<V, 0>(P, P->S, P->S->sweeps, P->nk);
+    const SweepArgs none{};
+    commit_body<V, 0, false>(P, P->S, P->S->sweeps, P->nk, none);
 }
 
 // Cores of every problem from its final ranks (those of its last commit).
