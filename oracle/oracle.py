@@ -9,7 +9,7 @@ import numpy as np
 
 from . import build as _build
 
-FN_HILBERT, FN_MAXWELL, FN_BIMAXWELL, FN_SEPSUM, FN_MAXWELL_2D2V, FN_MAXWELL_3D3V = 1, 2, 3, 4, 5, 6
+FN_HILBERT, FN_MAXWELL, FN_BIMAXWELL, FN_SEPSUM, FN_MAXWELL_2D2V, FN_MAXWELL_3D3V, FN_MAXWELL_IL = 1, 2, 3, 4, 5, 6, 7
 
 _lib = None
 
@@ -53,6 +53,8 @@ def lib():
         L.orc_splitmix64_draw.restype = C.c_uint64
         L.orc_splitmix64_draw.argtypes = [C.c_uint64, C.c_int64, u64p]
         L.orc_sample_indices.argtypes = [C.c_int, i32p, C.c_uint64, C.c_int64, i32p]
+        L.orc_set_restarts.argtypes = [P, C.c_int, C.c_int64]
+        L.orc_get_restarts.argtypes = [P, i32p, P, P]
         L.orc_pairwise_sumsq.restype = C.c_double
         L.orc_pairwise_sumsq.argtypes = [f64p, C.c_int64]
         _lib = L
@@ -130,7 +132,7 @@ class Oracle:
     (rook_iters = 0) or, as a test option, for at most rook_iters rounds."""
 
     def __init__(self, n, eps, fn_id, params=None, seed=0, r_max=64, n_samples=16384, pivot="greedy",
-                 grid=None, rook_iters=0, rank_caps=None):
+                 grid=None, rook_iters=0, rank_caps=None, restarts=0, restart_R=4096):
         self._seed = int(seed)
         self.n = np.ascontiguousarray(n, dtype=np.int32)
         self.d = int(self.n.size)
@@ -150,6 +152,9 @@ class Oracle:
         if rank_caps is not None:
             if lib().orc_set_rank_caps(self.h, np.ascontiguousarray(rank_caps, dtype=np.int32)) != 0:
                 raise ValueError("orc_set_rank_caps rejected the caps")
+        if restarts:
+            if lib().orc_set_restarts(self.h, int(restarts), int(restart_R)) != 0:
+                raise ValueError("orc_set_restarts rejected the options")
         self.status = None
 
     def __del__(self):
@@ -186,6 +191,16 @@ class Oracle:
         lib().orc_get_stats(self.h, out, i0)
         return {"rms": out[0], "tau": out[1], "evaluated": int(out[2]), "pivoted": int(out[3]),
                 "sweeps": int(out[4]), "min_rel_gap": out[5], "status": int(out[6]), "i0": i0}
+
+    def restart_info(self):
+        """Restarts after false convergence: {"used", "cause" (0 none, 1
+        restarts used up, 2 no usable sample), "err" (the last check's error,
+        -1 if none), "seeds" (the points added to i0, in order)}."""
+        out = np.zeros(3, dtype=np.int32)
+        e = C.c_double()
+        pts = np.zeros((8, self.d), dtype=np.int32)
+        lib().orc_get_restarts(self.h, out, C.byref(e), pts.ctypes.data)
+        return {"used": int(out[0]), "cause": int(out[1]), "err": e.value, "seeds": pts[:int(out[2])].copy()}
 
     def rook_rounds(self):
         """Most rounds of Alg. 1's loop any block search took (rook mode)."""

@@ -67,6 +67,36 @@
  *   - the pivoted count adds one per residual the search looks at (each
  *     sample kept, each row or column entry scanned).
  *
+ * Restarts after false convergence (orc_set_restarts; not in the paper,
+ * which guards against it only by the random start of Alg. 1 and reports the
+ * sampled error of Sec. 5).  A greedy run can stop with every superblock
+ * residual at or below tau while the tensor has structure the superblocks
+ * through its pivots never reach (their sampled error stays large).  The
+ * remedy restarts the run from more initial pivots:
+ *   - the initial index sets come from a list of points, i0 first: a point
+ *     enters unfolding k when neither its prefix (i_1..i_k) is in I_{<=k} nor
+ *     its suffix (i_{k+1}..i_d) in J_{>k} yet.  Those unfoldings form one
+ *     run k_a..k_b (a prefix that is new at k is new at k+1, a suffix new at
+ *     k is new at k-1), so every set stays nested: the point's prefix at
+ *     k_a - 1 and its suffix at k_b + 1 are already present, and every
+ *     unfolding's cross stays square.  Its pivot in unfolding k sits at the
+ *     positions of its prefix and suffix; pivots keep the order of the list;
+ *   - a point is usable only if, in every unfolding it enters, its residual
+ *     after the earlier pivots of that unfolding is larger than tau in
+ *     absolute value (a smaller one would be a near-singular pivot, and it
+ *     cannot be left out of one unfolding alone without breaking nestedness).
+ *     A sample that fails is trimmed to the longest run of consecutive
+ *     unfoldings where its residual passes: its indices outside that run are
+ *     replaced by i0's (orc_point_pick), and the trimmed point is tested
+ *     again.  (The end unfoldings are the usual failures: an unfolding whose
+ *     matrix has its exact rank already has zero residual everywhere.);
+ *   - after a run, the sampled error (stream seed + 1, R samples) decides: at
+ *     or below eps the run stands; else the samples are taken in order of
+ *     decreasing |X - X~| (lowest sample first on ties), the point of the
+ *     first one among the 64 worst that gives one joins the list, and the run
+ *     is repeated from the samples on.  With no usable sample, or after max_restarts restarts, the
+ *     status is ORC_WARN_SAMPLED_ERR (restart_cause says which).
+ *
  * Indices are 0-based at this interface; the generating functions apply the
  * paper's 1-based formulas internally.
  */
@@ -76,9 +106,11 @@
 #include <string.h>
 
 #define ORC_MAX_D 16
+#define ORC_MAX_SEEDS 8
+#define ORC_RESTART_TRIES 64
 
 enum { ORC_FN_HILBERT = 1, ORC_FN_MAXWELL = 2, ORC_FN_BIMAXWELL = 3, ORC_FN_SEPSUM = 4,
-       ORC_FN_MAXWELL_2D2V = 5, ORC_FN_MAXWELL_3D3V = 6 };
+       ORC_FN_MAXWELL_2D2V = 5, ORC_FN_MAXWELL_3D3V = 6, ORC_FN_MAXWELL_IL = 7 };
 
 enum { ORC_OK = 0, ORC_NOT_CONVERGED = 1, ORC_WARN_SAMPLED_ERR = 2, ORC_EINVAL = -1, ORC_ENOMEM = -2,
        ORC_ESINGULAR = -4, ORC_EFN = -6 };
@@ -245,11 +277,28 @@ static double orc_kinetic(const orc_fn *F, const int *idx, int ndim)
     return pre * (exp(-em) + exp(-ep));
 }
 
+/* The same Maxwellian with its modes in the order x1, v1, x2, v2, x3, v3
+ * (the position-velocity interleaving the paper uses for its kinetic
+ * tensors): mode 2w holds x_{w+1}, mode 2w+1 holds v_{w+1}. */
+static double orc_maxwell_il(const orc_fn *F, const int *idx)
+{
+    orc_fn G = *F;
+    int p[6];
+    for (int w = 0; w < 3; ++w) {
+        p[w] = idx[2 * w];
+        p[3 + w] = idx[2 * w + 1];
+        G.n[w] = F->n[2 * w];
+        G.n[3 + w] = F->n[2 * w + 1];
+    }
+    return orc_maxwell(&G, p);
+}
+
 static double orc_eval(const orc_fn *F, const int *idx)
 {
     switch (F->fn_id) {
     case ORC_FN_HILBERT: return orc_hilbert(F, idx);
     case ORC_FN_MAXWELL: return orc_maxwell(F, idx);
+    case ORC_FN_MAXWELL_IL: return orc_maxwell_il(F, idx);
     case ORC_FN_BIMAXWELL: return orc_bimaxwell(F, idx);
     case ORC_FN_SEPSUM: return orc_sepsum(F, idx);
     case ORC_FN_MAXWELL_2D2V: return orc_kinetic(F, idx, 2);
@@ -268,7 +317,8 @@ static int orc_fn_check(int fn_id, int d, const int *n, const double *params, in
         if ((double)d + shift <= 0.0) return ORC_EFN;    /* smallest denominator */
         return ORC_OK;
     }
-    case ORC_FN_MAXWELL: return (d == 6 && (nparams == 0 || nparams >= 4)) ? ORC_OK : ORC_EFN;
+    case ORC_FN_MAXWELL:
+    case ORC_FN_MAXWELL_IL: return (d == 6 && (nparams == 0 || nparams >= 4)) ? ORC_OK : ORC_EFN;
     case ORC_FN_BIMAXWELL: return (d >= 3 && nparams >= 10) ? ORC_OK : ORC_EFN;
     case ORC_FN_SEPSUM: {
         if (nparams < 1) return ORC_EFN;
@@ -329,6 +379,13 @@ typedef struct orc_state {
     int rook_max_rounds;             /* most rounds any block's walk took */
     int kcap[ORC_MAX_D + 1];         /* rank cap per unfolding (prescribed ranks), <= r_max */
     int grid[ORC_MAX_D];             /* subtensor blocks per mode (rook mode) */
+    /* restarts after false convergence */
+    int max_restarts;                /* 0: off */
+    int64_t restart_R;               /* samples of the check that decides a restart */
+    int nseed;                       /* points after i0 in the initial list */
+    int seeds[ORC_MAX_SEEDS][ORC_MAX_D];
+    int restarts_used, restart_cause;/* cause: 0 none, 1 restarts used up, 2 no usable sample */
+    double sampled_err;              /* the last check's error (restarts on) */
 } orc_state;
 
 static void orc_free_state(orc_state *S)
@@ -643,6 +700,249 @@ static int orc_search(orc_state *S, int k, const int *rs, int64_t *row_out, int6
     return found;
 }
 
+/* Position of tuple t (len entries) among the first cnt tuples of L, or -1;
+ * the empty tuple (len 0) is at position 0. */
+static int orc_find_tuple(const int *L, int cnt, int len, const int *t)
+{
+    if (len == 0) return 0;
+    for (int p = 0; p < cnt; ++p) {
+        int j = 0;
+        while (j < len && L[p * len + j] == t[j]) ++j;
+        if (j == len) return p;
+    }
+    return -1;
+}
+
+/* The unfoldings point pt enters (in[k] = 1): those where neither its prefix
+ * nor its suffix is in the sets yet.  Returns their number, or -1 if they do
+ * not form one run (which nested sets rule out) or one is at its rank cap. */
+static int orc_point_levels(const orc_state *S, const int *pt, int *in)
+{
+    int d = S->d, cnt = 0, first = -1, last = -1;
+    for (int k = 1; k <= d - 1; ++k) {
+        in[k] = orc_find_tuple(S->I[k], S->r[k], k, pt) < 0 && orc_find_tuple(S->J[k], S->r[k], d - k, pt + k) < 0;
+        if (in[k]) {
+            if (first < 0) first = k;
+            last = k;
+            ++cnt;
+            if (S->r[k] >= S->kcap[k]) return -1;
+        }
+    }
+    if (cnt > 0 && last - first + 1 != cnt) return -1;
+    return cnt;
+}
+
+/* Appends point pt to the unfoldings marked in in[]: its tuples first, then
+ * its pivot positions (its prefix at k - 1 and its suffix at k + 1 may be its
+ * own, appended in the first pass). */
+static void orc_append_point(orc_state *S, const int *pt, const int *in)
+{
+    int d = S->d;
+    for (int k = 1; k <= d - 1; ++k) {
+        if (!in[k]) continue;
+        int z = S->r[k];
+        for (int j = 0; j < k; ++j) S->I[k][z * k + j] = pt[j];
+        for (int j = 0; j < d - k; ++j) S->J[k][z * (d - k) + j] = pt[k + j];
+        S->r[k] = z + 1;
+    }
+    for (int k = 1; k <= d - 1; ++k) {
+        if (!in[k]) continue;
+        int z = S->r[k] - 1;
+        int p = orc_find_tuple(S->I[k - 1], S->r[k - 1], k - 1, pt);
+        int q = orc_find_tuple(S->J[k + 1], S->r[k + 1], d - k - 1, pt + k + 1);
+        S->rho[k][z] = (int64_t)p * S->n[k - 1] + pt[k - 1];
+        S->gam[k][z] = (int64_t)q * S->n[k] + pt[k];
+    }
+}
+
+/* Residuals at the pivots of unfolding k: pv[z] is the residual at pivot z
+ * after pivots 0..z-1, by the rank-1 recursion restricted to the pivot rows
+ * and columns (an entry of those depends on nothing else).  The matrix entry
+ * (a, b) is X at the a-th row tuple of I_{<=k} followed by the b-th column
+ * tuple of J_{>k}. */
+static int orc_pivot_residuals(orc_state *S, int k, double *pv)
+{
+    int d = S->d, m = S->r[k];
+    int idx[ORC_MAX_D];
+    double *P = (double *)malloc(sizeof(double) * m * m);
+    double *u = (double *)malloc(sizeof(double) * m);
+    if (!P || !u) { free(P); free(u); return ORC_ENOMEM; }
+    for (int a = 0; a < m; ++a)
+        for (int b = 0; b < m; ++b) {
+            for (int j = 0; j < k; ++j) idx[j] = S->I[k][a * k + j];
+            for (int j = 0; j < d - k; ++j) idx[k + j] = S->J[k][b * (d - k) + j];
+            P[a * m + b] = orc_eval(&S->F, idx);
+        }
+    for (int z = 0; z < m; ++z) {
+        double p = P[z * m + z];
+        pv[z] = p;
+        for (int b = 0; b < m; ++b) u[b] = P[z * m + b] / p;
+        for (int a = 0; a < m; ++a) {
+            double w = P[a * m + z];
+            for (int b = 0; b < m; ++b) P[a * m + b] = fma(-w, u[b], P[a * m + b]);
+        }
+    }
+    free(P); free(u);
+    return ORC_OK;
+}
+
+/* Initial index sets from i0 and the seeds, in that order, with the pivot
+ * residuals of every unfolding. */
+static int orc_init_sets(orc_state *S)
+{
+    int d = S->d, in[ORC_MAX_D + 1];
+    S->r[0] = 1; S->r[d] = 1;
+    for (int k = 1; k <= d - 1; ++k) S->r[k] = 0;
+    orc_point_levels(S, S->i0, in);              /* every unfolding: the sets are empty */
+    orc_append_point(S, S->i0, in);
+    for (int s = 0; s < S->nseed; ++s) {
+        if (orc_point_levels(S, S->seeds[s], in) < 0) return ORC_EINVAL;
+        orc_append_point(S, S->seeds[s], in);
+    }
+    for (int k = 1; k <= d - 1; ++k) {
+        int st = orc_pivot_residuals(S, k, S->piv[k]);
+        if (st) return st;
+    }
+    return ORC_OK;
+}
+
+/* Residual of point pt, as the next pivot, in each unfolding it enters
+ * (res[k]; in[k] marks them).  Returns how many it enters (-1: see
+ * orc_point_levels).  The sets are left as they were. */
+static int orc_point_residuals(orc_state *S, const int *pt, int *in, double *res)
+{
+    int d = S->d, rsave[ORC_MAX_D + 1];
+    int cnt = orc_point_levels(S, pt, in);
+    if (cnt <= 0) return cnt;
+    for (int k = 0; k <= d; ++k) rsave[k] = S->r[k];
+    orc_append_point(S, pt, in);
+    double *pv = (double *)malloc(sizeof(double) * S->r_max);
+    for (int k = 1; k <= d - 1; ++k) {
+        res[k] = 0.0;
+        if (!in[k] || !pv) continue;
+        if (orc_pivot_residuals(S, k, pv) == ORC_OK) res[k] = fabs(pv[S->r[k] - 1]);
+    }
+    free(pv);
+    for (int k = 0; k <= d; ++k) S->r[k] = rsave[k];
+    return cnt;
+}
+
+/* The point a sample contributes to the initial list, in q: the sample
+ * itself if its residual is larger than tau in every unfolding it enters;
+ * else, trimmed to the longest run of consecutive such unfoldings (the first
+ * on ties) k_c..k_d, the point that takes i0's indices before position k_c
+ * and after position k_d + 1 (1-based: modes 1..k_c-1 and k_d+2..d), whose
+ * prefix at k_c - 1 and suffix at k_d + 1 are i0's and hence present, if
+ * that point passes the same test.  Returns 1 if there is such a point. */
+static int orc_point_pick(orc_state *S, const int *pt, int *q)
+{
+    int d = S->d, in[ORC_MAX_D + 1];
+    double res[ORC_MAX_D + 1];
+    int cnt = orc_point_residuals(S, pt, in, res);
+    if (cnt <= 0) return 0;
+    int all = 1, kc = -1, kd = -1, run0 = -1;
+    for (int k = 1; k <= d - 1; ++k) {
+        if (!in[k]) continue;
+        if (res[k] > S->tau) {
+            if (run0 < 0) run0 = k;
+            if (kc < 0 || k - run0 > kd - kc) { kc = run0; kd = k; }
+        } else {
+            all = 0;
+            run0 = -1;
+        }
+    }
+    if (all) {
+        for (int j = 0; j < d; ++j) q[j] = pt[j];
+        return 1;
+    }
+    if (kc < 0) return 0;
+    for (int j = 0; j < d; ++j) q[j] = (j < kc - 1 || j > kd) ? S->i0[j] : pt[j];
+    cnt = orc_point_residuals(S, q, in, res);
+    if (cnt <= 0) return 0;
+    for (int k = 1; k <= d - 1; ++k)
+        if (in[k] && !(res[k] > S->tau)) return 0;
+    return 1;
+}
+
+static double orc_tt_value(int d, const int *n, const int *ranks, const double *cores, const int *idx,
+                           double *v, double *vn);
+
+/* The sampled-error check on the R multi-indices idx (R x d): out[t] =
+ * |X - X~| at sample t and *err the relative error, sums in sample order. */
+static int orc_sample_errors(const orc_state *S, int64_t R, const int *idx, double *out, double *err)
+{
+    int d = S->d, rmax = 1;
+    for (int k = 0; k <= d; ++k) if (S->r[k] > rmax) rmax = S->r[k];
+    double *v = (double *)malloc(sizeof(double) * rmax);
+    double *vn = (double *)malloc(sizeof(double) * rmax);
+    if (!v || !vn) { free(v); free(vn); return ORC_ENOMEM; }
+    double num = 0.0, den = 0.0;
+    for (int64_t t = 0; t < R; ++t) {
+        double x = orc_eval(&S->F, idx + t * d);
+        double y = orc_tt_value(d, S->n, S->r, S->cores, idx + t * d, v, vn);
+        num += (x - y) * (x - y);
+        den += x * x;
+        out[t] = fabs(x - y);
+    }
+    free(v); free(vn);
+    *err = den > 0.0 ? sqrt(num / den) : sqrt(num);
+    return ORC_OK;
+}
+
+/* order = 0..R-1 sorted by decreasing key, lower index first among equal
+ * keys (a stable merge sort). */
+static void orc_order_by_error(const double *key, int64_t R, int64_t *order)
+{
+    int64_t *tmp = (int64_t *)malloc(sizeof(int64_t) * (size_t)R);
+    for (int64_t t = 0; t < R; ++t) order[t] = t;
+    if (!tmp) {                                   /* insertion sort without scratch */
+        for (int64_t i = 1; i < R; ++i) {
+            int64_t x = order[i], j = i;
+            while (j > 0 && key[order[j - 1]] < key[x]) { order[j] = order[j - 1]; --j; }
+            order[j] = x;
+        }
+        return;
+    }
+    for (int64_t w = 1; w < R; w *= 2) {
+        for (int64_t lo = 0; lo < R; lo += 2 * w) {
+            int64_t mid = lo + w < R ? lo + w : R, hi = lo + 2 * w < R ? lo + 2 * w : R;
+            int64_t a = lo, b = mid, o = lo;
+            while (a < mid && b < hi) tmp[o++] = (key[order[b]] > key[order[a]]) ? order[b++] : order[a++];
+            while (a < mid) tmp[o++] = order[a++];
+            while (b < hi) tmp[o++] = order[b++];
+        }
+        memcpy(order, tmp, sizeof(int64_t) * (size_t)R);
+    }
+    free(tmp);
+}
+
+/* Restarts after false convergence (see the header): at most max_restarts
+ * (<= ORC_MAX_SEEDS) restarts decided by R check samples; 0 turns them off. */
+int orc_set_restarts(orc_state *S, int max_restarts, int64_t R)
+{
+    if (!S || max_restarts < 0 || max_restarts > ORC_MAX_SEEDS || (max_restarts > 0 && R < 1)) return ORC_EINVAL;
+    S->max_restarts = max_restarts;
+    S->restart_R = R;
+    return ORC_OK;
+}
+
+/* out: [restarts used, cause, seeds], err: the last check's error (-1 if
+ * none), pts: the seeds (restarts used x d). */
+int orc_get_restarts(const orc_state *S, int *out, double *err, int *pts)
+{
+    if (!S) return ORC_EINVAL;
+    out[0] = S->restarts_used;
+    out[1] = S->restart_cause;
+    out[2] = S->nseed;
+    *err = S->sampled_err;
+    if (pts)
+        for (int s = 0; s < S->nseed; ++s)
+            for (int j = 0; j < S->d; ++j) pts[s * S->d + j] = S->seeds[s][j];
+    return ORC_OK;
+}
+
+static int orc_solve(orc_state *S);
+
 int orc_run(orc_state *S)
 {
     if (!S) return ORC_EINVAL;
@@ -671,16 +971,59 @@ int orc_run(orc_state *S)
     double p0 = orc_eval(&S->F, S->i0);
     if (p0 == 0.0) return S->status = ORC_ESINGULAR;
 
-    /* initial pivot, replicated for every unfolding (nested by construction) */
-    S->r[0] = 1; S->r[d] = 1;
-    for (int k = 1; k <= d - 1; ++k) {
-        for (int j = 0; j < k; ++j) S->I[k][j] = S->i0[j];
-        for (int j = 0; j < d - k; ++j) S->J[k][j] = S->i0[k + j];
-        S->rho[k][0] = S->i0[k - 1];     /* prefix position 0 */
-        S->gam[k][0] = S->i0[k];         /* suffix position 0 */
-        S->piv[k][0] = p0;
-        S->r[k] = 1;
+
+    S->nseed = 0;
+    S->restarts_used = 0;
+    S->restart_cause = 0;
+    S->sampled_err = -1.0;
+    int st = orc_solve(S);
+    if (st < 0 || S->max_restarts <= 0) return st;
+    /* restarts after false convergence */
+    int64_t R = S->restart_R;
+    int *ridx = (int *)malloc(sizeof(int) * (size_t)R * d);
+    double *rerr = (double *)malloc(sizeof(double) * (size_t)R);
+    int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)R);
+    if (!ridx || !rerr || !order) { free(ridx); free(rerr); free(order); return S->status = ORC_ENOMEM; }
+    orc_sample_indices(d, S->n, S->seed + 1, R, ridx);
+    while (S->status == ORC_OK) {
+        double err = 0.0;
+        if (orc_sample_errors(S, R, ridx, rerr, &err) != ORC_OK) { S->status = ORC_ENOMEM; break; }
+        S->sampled_err = err;
+        if (err <= S->eps) break;
+        if (S->restarts_used >= S->max_restarts || S->nseed >= ORC_MAX_SEEDS) {
+            S->status = ORC_WARN_SAMPLED_ERR;
+            S->restart_cause = 1;
+            break;
+        }
+        orc_order_by_error(rerr, R, order);
+        int picked = 0;
+        for (int64_t t = 0; t < R && t < ORC_RESTART_TRIES && !picked; ++t)
+            picked = orc_point_pick(S, ridx + order[t] * d, S->seeds[S->nseed]);
+        if (!picked) {
+            S->status = ORC_WARN_SAMPLED_ERR;
+            S->restart_cause = 2;
+            break;
+        }
+        S->nseed++;
+        S->restarts_used++;
+        st = orc_solve(S);
+        if (st < 0) break;
     }
+    free(ridx); free(rerr); free(order);
+    return S->status;
+}
+
+/* One run from the initial list: sweeps until the stop test, then the cores. */
+static int orc_solve(orc_state *S)
+{
+    int d = S->d;
+    int st0 = orc_init_sets(S);
+    if (st0) return S->status = st0;
+    S->sweeps = 0;
+    S->pivoted = 0;
+    S->ran = 0;
+    free(S->cores);
+    S->cores = NULL;
     S->min_rel_gap = INFINITY;
     S->status = ORC_OK;
 
