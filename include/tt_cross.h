@@ -66,7 +66,13 @@ enum tt_fn {
      * x,v_x,y,v_y (d = 4) or x,v_x,y,v_y,z,v_z (d = 6); x in [-1/2,1/2],
      * v in [-3,3], cell-centred grids.  params: []. */
     TT_FN_MAXWELL_2D2V = 5,
-    TT_FN_MAXWELL_3D3V = 6
+    TT_FN_MAXWELL_3D3V = 6,
+    /* TT_FN_MAXWELL with its modes in the order x1,v1,x2,v2,x3,v3 (the
+     * position-velocity interleaving of the paper's kinetic tensors): mode
+     * 2w holds x_{w+1}, mode 2w+1 holds v_{w+1}.  The greedy cross started
+     * from one pivot stops at rank 1 on it with a large sampled error (see
+     * tt_options.restarts).  params: as TT_FN_MAXWELL. */
+    TT_FN_MAXWELL_IL = 7
 };
 
 enum tt_status {
@@ -121,6 +127,25 @@ typedef struct tt_options {
                                    0 (default) = chosen by the library from the block sizes,
                                    1 = one workgroup per block, 2..1024 = that many (results
                                    do not depend on it) */
+    int32_t restarts;           /* restarts after false convergence, 0..8 (default 0 = none);
+                                   greedy FP64 sweeps only (not in the paper, whose guards are
+                                   the random start of Alg. 1 and the sampled error of Sec. 5).
+                                   When the sampled-error check (verify; 4096 samples if verify
+                                   is -1, which restarts need, not 0) exceeds eps after a run
+                                   that stopped below tau, the run is repeated from more initial
+                                   pivots.  The initial index sets come from a point list, i0
+                                   first: a point enters the unfoldings where neither its prefix
+                                   (i_1..i_k) nor its suffix (i_{k+1}..i_d) is present yet (one
+                                   run of unfoldings, so the sets stay nested and every cross
+                                   square), as their next pivot.  The check's samples are tried
+                                   by decreasing |X - X~| (lowest sample first on ties, the 64
+                                   worst at most): a sample whose residual exceeds tau in every
+                                   unfolding it enters joins the list; one that fails is
+                                   trimmed to its longest run of unfoldings that pass (the
+                                   first on ties), with i0's indices outside it, and tested
+                                   again.  With no point found, or the restarts used up, the
+                                   status is TT_WARN_SAMPLED_ERR (tt_stats.restart_cause).  The
+                                   first sweep of a restarted run evaluates every tile anew. */
 } tt_options;
 
 typedef struct tt_stats {
@@ -158,6 +183,9 @@ typedef struct tt_stats {
     int32_t rook_long_walks;    /* rook pivoting: block searches whose walk took more than 8
                                    rounds (with several workgroups per block these finish in
                                    the search's last launch, one workgroup per block) */
+    int32_t restarts_used;      /* restarts after false convergence (tt_options.restarts) */
+    int32_t restart_cause;      /* why restarts stopped with the error above eps: 0 none, 1 the
+                                   restarts were used up, 2 no check sample gave a point */
 } tt_stats;
 
 typedef struct tt_cross_s *tt_cross_h;

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libttcross_stamps.so" if os.environ.get("TT_CROSS
 TT_MAX_D = 16
 TT_MAX_RANK = 64
 
-FN_HILBERT, FN_MAXWELL, FN_BIMAXWELL, FN_SEPSUM, FN_MAXWELL_2D2V, FN_MAXWELL_3D3V = 1, 2, 3, 4, 5, 6
+FN_HILBERT, FN_MAXWELL, FN_BIMAXWELL, FN_SEPSUM, FN_MAXWELL_2D2V, FN_MAXWELL_3D3V, FN_MAXWELL_IL = 1, 2, 3, 4, 5, 6, 7
 PREC_AUTO, PREC_FP64, PREC_FP32 = 0, 1, 2
 PIVOT_GREEDY, PIVOT_ROOK = 0, 1
 OK, NOT_CONVERGED, WARN_SAMPLED_ERR = 0, 1, 2
@@ -37,6 +37,7 @@ class Options(C.Structure):
         ("stream", C.c_void_p),
         ("verify", C.c_int32),
         ("rook_split", C.c_int32),
+        ("restarts", C.c_int32),
     ]
 
 
@@ -63,6 +64,8 @@ class Stats(C.Structure):
         ("sampled_err", C.c_double),
         ("escalated", C.c_int32),
         ("rook_long_walks", C.c_int32),
+        ("restarts_used", C.c_int32),
+        ("restart_cause", C.c_int32),
     ]
 
 

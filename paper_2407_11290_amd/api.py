@@ -69,6 +69,7 @@ def _stats_dict(s, d):
         "new_entries": s.new_entries, "sweep_phase_s": s.sweep_phase_s,
         "sampled_err": s.sampled_err, "escalated": s.escalated,
         "rook_max_rounds": s.rook_max_rounds, "rook_long_walks": s.rook_long_walks,
+        "restarts_used": s.restarts_used, "restart_cause": s.restart_cause,
     }
 
 
@@ -77,7 +78,7 @@ class TTCross:
 
     def __init__(self, n, eps, fn_id, params=None, seed=0, r_max=64, precision=_lib.PREC_AUTO,
                  n_samples=16384, grid=None, tile_rows=0, tile_cols=0, lookahead=2, profile=0,
-                 stream=None, verify=-1, pivot=_lib.PIVOT_GREEDY, rook_split=0):
+                 stream=None, verify=-1, pivot=_lib.PIVOT_GREEDY, rook_split=0, restarts=0):
         L = load()
         self.n = _i32(n)
         self.d = int(self.n.size)
@@ -103,6 +104,7 @@ class TTCross:
         o.verify = verify
         o.pivot_mode = pivot
         o.rook_split = rook_split
+        o.restarts = restarts
         if stream is not None:
             o.stream = C.c_void_p(getattr(stream, "cuda_stream", stream))
         check(L.tt_cross_set_options(self.h, C.byref(o)))

@@ -448,9 +448,20 @@ extern "C" int tt_batch_run(tt_cross_h *hs, int count, void *hip_stream)
             return set_err(TT_EINVAL, "handle %d: rook pivoting runs through tt_cross_run only", i);
         if (hs[i]->p.busy()) return set_err(TT_ESTATE, "handle %d has a run in flight", i);
     }
+    static const int zero = 0;
     for (int i = 0; i < count; ++i) {
-        const int st = hs[i]->p.prepare();
+        Problem &Q = hs[i]->p;
+        const int st = Q.prepare();
         if (st) return st;
+        // a batch runs every problem from its first pivot alone (restarts
+        // after false convergence are tt_cross_run's)
+        Q.h_plan.npts = 0;
+        Q.restarts_used = 0;
+        Q.restart_cause = 0;
+        if (Q.dev_plan_npts != 0) {
+            HIPCHK(hipMemcpyAsync(&Q.d_plan->npts, &zero, sizeof(int), hipMemcpyHostToDevice, Q.stream));
+            Q.dev_plan_npts = 0;
+        }
     }
     hipStream_t stream = hip_stream ? (hipStream_t)hip_stream : hs[0]->p.stream;
     // the handles' own streams must not still be working on these buffers

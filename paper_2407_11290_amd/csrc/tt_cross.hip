@@ -55,6 +55,7 @@ static void mode_tables(FnDev &F, FnHost &out)
     bool has[TT_MAX_D] = {false};
     switch (F.id) {
     case TT_FN_MAXWELL:            // x1, x2, x3: sin, cos, sin of 2 pi x; v1..v3: cell centres
+    case TT_FN_MAXWELL_IL:         // the same atoms, modes x1, v1, x2, v2, x3, v3
         rows = 1;
         for (int j = 0; j < d; ++j) has[j] = true;
         F.cst[0] = std::pow(twopi * F.prm[2], -1.5);
@@ -85,13 +86,17 @@ static void mode_tables(FnDev &F, FnHost &out)
         for (int i = 0; i < n; ++i) {
             switch (F.id) {
             case TT_FN_MAXWELL:
-                if (j < 3) {
+            case TT_FN_MAXWELL_IL: {
+                // position w (0-based) of mode j, or -1 for a velocity mode
+                const int w = F.id == TT_FN_MAXWELL ? (j < 3 ? j : -1) : ((j & 1) == 0 ? j / 2 : -1);
+                if (w >= 0) {
                     const double x = (double)i / (double)n;
-                    a[i] = (j == 1) ? std::cos(twopi * x) : std::sin(twopi * x);
+                    a[i] = (w == 1) ? std::cos(twopi * x) : std::sin(twopi * x);
                 } else {
                     a[i] = vel<double>(i, n, F.prm[3]);
                 }
                 break;
+            }
             case TT_FN_BIMAXWELL: {
                 const double v = vel<double>(i, n, F.prm[10]);
                 const int c = j - (d - 3);
@@ -137,6 +142,7 @@ int build_fn(int fn_id, int d, const int32_t *n, const double *params, int npara
         if (!((double)d + F.shift > 0.0)) return set_err(TT_EFN, "Hilbert denominator can be <= 0");
         break;
     case TT_FN_MAXWELL:
+    case TT_FN_MAXWELL_IL:
         if (d != 6) return set_err(TT_EFN, "Maxwellian needs d=6");
         if (nparams == 0) { F.prm[0] = 0.5; F.prm[1] = 0.3; F.prm[2] = 1.0; F.prm[3] = 8.0; }
         else if (nparams >= 4) for (int i = 0; i < 4; ++i) F.prm[i] = params[i];
@@ -473,6 +479,14 @@ int Problem::allocate()
     if ((st = dalloc((void **)&d_vals, sizeof(double) * opt.n_samples)) != TT_OK) return st;
     if ((st = dalloc((void **)&d_spart, sizeof(SamplePart) * sample_blocks(opt.n_samples))) != TT_OK) return st;
     if ((st = dalloc((void **)&d_part, sizeof(double) * 2 * NBV)) != TT_OK) return st;
+    if ((st = dalloc((void **)&d_plan, sizeof(SeedPlan))) != TT_OK) return st;
+    HIPCHK(hipMemset(d_plan, 0, sizeof(SeedPlan)));
+    dev_plan_npts = 0;
+    H.plan = d_plan;
+    if ((st = dalloc((void **)&d_pc, sizeof(PointCheck))) != TT_OK) return st;
+    if ((st = dalloc((void **)&d_pres, sizeof(double) * TT_RESTART_TRIES * TT_MAX_D)) != TT_OK) return st;
+    serr_cap = 0;
+    d_serr = nullptr;
     if ((st = dalloc((void **)&H.S, sizeof(ProbState))) != TT_OK) return st;
 #ifdef TT_STAMPS
     // phase stamps: one record per search workgroup and sweep, one per commit
@@ -566,6 +580,12 @@ template <typename V> int Problem::begin_sweeps()
 #ifdef TT_STAMPS
     HIPCHK(hipMemsetAsync(hP.stamps, 0, sizeof(unsigned long long) * stamp_words, stream));
 #endif
+    // a restarted run's initial pivots (the device copy says npts = 0 for a
+    // plain run; it changes only when the run's kind does)
+    if (h_plan.npts > 0 || dev_plan_npts != 0) {
+        HIPCHK(hipMemcpyAsync(d_plan, &h_plan, sizeof(SeedPlan), hipMemcpyHostToDevice, stream));
+        dev_plan_npts = h_plan.npts;
+    }
     HIPCHK(hipEventRecord(run_ev[0], stream));
     // a1: samples -> rms, tau, first pivot; initial superblocks (the sample
     // kernel also clears the pivot maps)
@@ -578,7 +598,7 @@ template <typename V> int Problem::begin_sweeps()
         k_samples<0><<<sample_blocks(ns), NT, 0, stream>>>(dP, opt.seed, ns, d_vals, d_spart);
         k_setup<V, 0><<<1, NT, 0, stream>>>(dP, opt.seed, ns, d_spart, eps);
     }
-    if (opt.pivot_mode != TT_PIVOT_ROOK) {
+    if (opt.pivot_mode != TT_PIVOT_ROOK && h_plan.npts == 0) {     // a restarted run's first sweep evaluates them
         int maxe = 1;
         for (int u = 0; u < nk; ++u) maxe = std::max(maxe, n[u] * n[u + 1]);
         dim3 g((unsigned)std::min(1024, (maxe + NT - 1) / NT), (unsigned)nk);
@@ -586,7 +606,14 @@ template <typename V> int Problem::begin_sweeps()
         else k_init_eval<V, 0><<<g, NT, 0, stream>>>(dP);
     }
     HIPCHK(hipGetLastError());
+    // rank bounds of the first sweep: 1, or a restarted run's initial pivot
+    // counts (and nothing stored yet)
     for (int k = 0; k <= d; ++k) rub[k] = rst[k] = 1;
+    if (h_plan.npts > 0)
+        for (int k = 1; k <= d - 1; ++k) {
+            rub[k] = h_plan.m[k - 1];
+            rst[k] = 0;
+        }
     launched = 0;
     done_known = 0;
     if (opt.profile) {
@@ -802,8 +829,17 @@ int Problem::poll_tail(bool wait)
     }
     const int64_t R = verify_samples();
     if (R > 0) {
-        // a13: sampled relative error over an independent SplitMix64(seed + 1) set
-        k_verify<<<NBV, NT, 0, stream>>>(dP, d_cores, R, opt.seed + 1, d_part);
+        // a13: sampled relative error over an independent SplitMix64(seed + 1)
+        // set; with restarts on, every sample's error as well
+        double *serr = nullptr;
+        if (restarts_on()) {
+            if (serr_cap < R) {
+                if ((st = dalloc((void **)&d_serr, sizeof(double) * R)) != TT_OK) return st;
+                serr_cap = R;
+            }
+            serr = d_serr;
+        }
+        k_verify<<<NBV, NT, 0, stream>>>(dP, d_cores, R, opt.seed + 1, d_part, serr);
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(h_part, d_part, sizeof(double) * 2 * NBV, hipMemcpyDeviceToHost, stream));
         HIPCHK(hipEventRecord(run_ev[2], stream));
@@ -836,9 +872,201 @@ int Problem::poll_verify(bool wait)
         phase = PH_SWEEPS;
         return 1;
     }
+    if (err > eps && status == TT_OK && restarts_on()) {
+        bool restarted = false;
+        if ((st = try_restart(restarted)) != TT_OK) return st;
+        if (restarted) return 1;
+    }
     if (err > eps && status == TT_OK) status = TT_WARN_SAMPLED_ERR;
     phase = PH_DONE;
     return 1;
+}
+
+// ---------------------------------------------------------------------------
+// Restarts after false convergence (not in the paper; the rule is written
+// out with tt_options.restarts).  Host work is index bookkeeping only: which
+// unfoldings a point enters, pivot positions, the order of the candidates;
+// every value (residuals, errors) comes from the kernels.
+// ---------------------------------------------------------------------------
+// Index sets of h_plan's point list: unfolding u holds the points that
+// entered it, in list order, and their pivot positions.  Returns an error if
+// a position is missing (nested sets rule that out; the plan is then not
+// used).
+int Problem::plan_from_points()
+{
+    SeedPlan &pl = h_plan;
+    const int nk = d - 1;
+    for (int u = 0; u < nk; ++u) pl.m[u] = 0;
+    for (int p = 0; p < pl.npts; ++p) {
+        const int in = point_levels(pl.pts[p]);
+        for (int u = 0; u < nk; ++u)
+            if ((in >> u) & 1) pl.mem[u][pl.m[u]++] = p;
+    }
+    // a prefix's place in unfolding u-1, a suffix's in unfolding u+1
+    auto pre_pos = [&](int u, const int *pt) {
+        if (u == 0) return 0;
+        for (int z = 0; z < pl.m[u - 1]; ++z)
+            if (std::equal(pt, pt + u, pl.pts[pl.mem[u - 1][z]])) return z;
+        return -1;
+    };
+    auto suf_pos = [&](int u, const int *pt) {
+        if (u == nk - 1) return 0;
+        const int k = u + 1;
+        for (int z = 0; z < pl.m[u + 1]; ++z)
+            if (std::equal(pt + k + 1, pt + d, pl.pts[pl.mem[u + 1][z]] + k + 1)) return z;
+        return -1;
+    };
+    for (int u = 0; u < nk; ++u) {
+        const int k = u + 1;
+        if (pl.m[u] < 1 || pl.m[u] > rc[k]) return set_err(TT_EINVAL, "restart plan: %d pivots in unfolding %d", pl.m[u], k);
+        for (int z = 0; z < pl.m[u]; ++z) {
+            const int *pt = pl.pts[pl.mem[u][z]];
+            const int pp = pre_pos(u, pt), qq = suf_pos(u, pt);
+            if (pp < 0 || qq < 0) return set_err(TT_EINVAL, "restart plan: index sets not nested at unfolding %d", k);
+            pl.rho[u][z] = pp * n[k - 1] + pt[k - 1];
+            pl.gam[u][z] = qq * n[k] + pt[k];
+        }
+    }
+    return TT_OK;
+}
+
+// Unfoldings (bit u) point pt enters after h_plan's points: those where
+// neither its prefix nor its suffix is present.  A point with unfoldings
+// that are not one run, or that would pass a rank capacity, enters none.
+int Problem::point_levels(const int *pt) const
+{
+    const SeedPlan &pl = h_plan;
+    const int nk = d - 1;
+    int in = 0, first = -1, last = -1, cnt = 0;
+    for (int u = 0; u < nk; ++u) {
+        const int k = u + 1;
+        bool pre = false, suf = false;
+        for (int z = 0; z < pl.m[u]; ++z) {
+            const int *q = pl.pts[pl.mem[u][z]];
+            pre = pre || std::equal(pt, pt + k, q);
+            suf = suf || std::equal(pt + k, pt + d, q + k);
+        }
+        if (!pre && !suf) {
+            if (pl.m[u] >= rc[k]) return 0;
+            in |= 1 << u;
+            if (first < 0) first = u;
+            last = u;
+            ++cnt;
+        }
+    }
+    return (cnt > 0 && last - first + 1 != cnt) ? 0 : in;
+}
+
+// Residuals of nc candidate points against h_plan's index sets (device,
+// k_point_resid); res[c][u] < 0 where candidate c does not enter u.
+int Problem::restart_check(int nc, const int (*cand)[TT_MAX_D], const int *cin, double (*res)[TT_MAX_D])
+{
+    PointCheck pc;
+    std::memset(&pc, 0, sizeof pc);
+    pc.nc = nc;
+    for (int c = 0; c < nc; ++c) {
+        std::memcpy(pc.cand[c], cand[c], sizeof pc.cand[c]);
+        pc.cin[c] = cin[c];
+    }
+    HIPCHK(hipMemcpyAsync(d_plan, &h_plan, sizeof(SeedPlan), hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(d_pc, &pc, sizeof(PointCheck), hipMemcpyHostToDevice, stream));
+    const int waves = nc * (d - 1), blocks = (waves + NT / 64 - 1) / (NT / 64);
+    if (blocks > 0) {
+        if (fn.dev.id == TT_FN_HILBERT) k_point_resid<TT_FN_HILBERT><<<blocks, NT, 0, stream>>>(dP, d_plan, d_pc, d_pres);
+        else k_point_resid<0><<<blocks, NT, 0, stream>>>(dP, d_plan, d_pc, d_pres);
+        HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipMemcpyAsync(res, d_pres, sizeof(double) * TT_RESTART_TRIES * TT_MAX_D, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    dev_plan_npts = h_plan.npts;
+    return TT_OK;
+}
+
+// After a run whose check missed eps: the next point of the list from the
+// check's worst samples, then the run again from the samples on.  restarted
+// = false leaves the status to the caller (restart_cause says why).
+int Problem::try_restart(bool &restarted)
+{
+    restarted = false;
+    const int nk = d - 1;
+    int st;
+    if (h_plan.npts == 0) {                     // the run that just ended started from i0 alone
+        h_plan.npts = 1;
+        std::memcpy(h_plan.pts[0], i0, sizeof(int) * d);
+        if ((st = plan_from_points()) != TT_OK) return st;
+    }
+    if (restarts_used >= opt.restarts || h_plan.npts > TT_MAX_SEEDS) {
+        restart_cause = 1;
+        return TT_OK;
+    }
+    // the check's samples by decreasing error (lowest sample first on ties)
+    const int64_t R = verify_samples();
+    std::vector<double> e((size_t)R);
+    HIPCHK(hipMemcpyAsync(e.data(), d_serr, sizeof(double) * R, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    std::vector<int64_t> order((size_t)R);
+    for (int64_t t = 0; t < R; ++t) order[t] = t;
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return e[a] > e[b]; });
+    const int nc = (int)std::min<int64_t>(R, TT_RESTART_TRIES);
+    int cand[TT_RESTART_TRIES][TT_MAX_D], cin[TT_RESTART_TRIES];
+    int trim[TT_RESTART_TRIES][TT_MAX_D], tin[TT_RESTART_TRIES];
+    double res[TT_RESTART_TRIES][TT_MAX_D], tres[TT_RESTART_TRIES][TT_MAX_D];
+    std::memset(cand, 0, sizeof cand);
+    std::memset(trim, 0, sizeof trim);
+    for (int c = 0; c < nc; ++c) {
+        const uint64_t t = (uint64_t)order[c];
+        for (int j = 0; j < d; ++j) cand[c][j] = (int)(sm64_at(opt.seed + 1, t * d + j) % (uint64_t)n[j]);
+        cin[c] = point_levels(cand[c]);
+    }
+    if ((st = restart_check(nc, cand, cin, res)) != TT_OK) return st;
+    // candidates that fail: trimmed to their longest run of unfoldings that
+    // pass (the first on ties), i0's indices outside it
+    for (int c = 0; c < nc; ++c) {
+        tin[c] = 0;
+        if (!cin[c]) continue;
+        int kc = -1, kd = -1, run0 = -1;
+        bool all = true;
+        for (int u = 0; u < nk; ++u) {
+            if (!((cin[c] >> u) & 1)) continue;
+            if (res[c][u] > tau) {
+                if (run0 < 0) run0 = u + 1;
+                if (kc < 0 || (u + 1) - run0 > kd - kc) { kc = run0; kd = u + 1; }
+            } else {
+                all = false;
+                run0 = -1;
+            }
+        }
+        if (all || kc < 0) continue;
+        for (int j = 0; j < d; ++j) trim[c][j] = (j < kc - 1 || j > kd) ? i0[j] : cand[c][j];
+        tin[c] = point_levels(trim[c]);
+    }
+    if ((st = restart_check(nc, trim, tin, tres)) != TT_OK) return st;
+    auto passes = [&](int in, const double *r) {
+        if (!in) return false;
+        for (int u = 0; u < nk; ++u)
+            if (((in >> u) & 1) && !(r[u] > tau)) return false;
+        return true;
+    };
+    const int *pick = nullptr;
+    for (int c = 0; c < nc && !pick; ++c) {
+        if (passes(cin[c], res[c])) pick = cand[c];
+        else if (passes(tin[c], tres[c])) pick = trim[c];
+    }
+    if (!pick) {
+        restart_cause = 2;
+        return TT_OK;
+    }
+    std::memcpy(h_plan.pts[h_plan.npts], pick, sizeof(int) * d);
+    h_plan.npts++;
+    if ((st = plan_from_points()) != TT_OK) return st;
+    ++restarts_used;
+    // the run again, from the samples on, with the longer list
+    t_first = time_to_eps;
+    cur_fp32 = false;
+    if ((st = begin_sweeps<double>()) != TT_OK) return st;
+    phase = PH_SWEEPS;
+    restarted = true;
+    return TT_OK;
 }
 
 // Runs the steps; returns 1 when the run is over, 0 when wait = false and
@@ -922,6 +1150,7 @@ int64_t Problem::verify_samples() const
 {
     if (opt.verify > 0) return opt.verify;
     if (opt.verify == 0) return 0;
+    if (opt.restarts > 0) return 4096;
     const bool policy_fp32 = opt.precision == TT_PREC_AUTO && (fp32 || force_fp64);
     return policy_fp32 ? 4096 : 0;
 }
@@ -934,6 +1163,9 @@ int Problem::start()
     sampled_err = -1.0;
     escalated = force_fp64 ? 1 : 0;
     t_first = 0.0;
+    restarts_used = 0;
+    restart_cause = 0;
+    h_plan.npts = 0;
     int st = prepare();
     if (st != TT_OK) {
         phase = PH_DONE;
@@ -1069,6 +1301,7 @@ void tt_options_default(tt_options *opt)
     opt->lookahead = 2;
     opt->stream = nullptr;
     opt->verify = -1;
+    opt->restarts = 0;
 }
 
 static int check_options(const tt_options *o)
@@ -1086,6 +1319,9 @@ static int check_options(const tt_options *o)
     if (o->tile_rows < 0 || o->tile_rows > 256) return set_err(TT_EINVAL, "tile_rows must be in [0,256]");
     if (o->tile_cols < 0 || o->tile_cols > 64) return set_err(TT_EINVAL, "tile_cols must be in [0,64]");
     if (o->verify < -1) return set_err(TT_EINVAL, "verify must be -1, 0 or a sample count");
+    if (o->restarts < 0 || o->restarts > TT_MAX_SEEDS)
+        return set_err(TT_EINVAL, "restarts must be in [0,%d]", TT_MAX_SEEDS);
+    if (o->restarts > 0 && o->verify == 0) return set_err(TT_EINVAL, "restarts need the sampled-error check");
     return TT_OK;
 }
 
@@ -1328,6 +1564,8 @@ int tt_cross_get_stats(tt_cross_h h, tt_stats *st)
     st->escalated = P.escalated;
     st->rook_max_rounds = P.rook_rounds;
     st->rook_long_walks = P.rook_long;
+    st->restarts_used = P.restarts_used;
+    st->restart_cause = P.restart_cause;
     return TT_OK;
 }
 

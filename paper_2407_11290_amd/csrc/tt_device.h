@@ -125,6 +125,16 @@ __device__ inline V fn_value_tx(const FnDev &F, IX ix, TP tb)
         V q = (v1 - ux) * (v1 - ux) + v2 * v2 + v3 * v3;
         return rho * (V)F.cst[0] * M<V>::exp(-q / ((V)2 * T));
     }
+    case TT_FN_MAXWELL_IL: {
+        // modes x1, v1, x2, v2, x3, v3; the same atoms and formula
+        const V a = (V)F.prm[0], b = (V)F.prm[1], T = (V)F.prm[2];
+        const V s1 = atom(0, 0, ix(0)), c2 = atom(0, 2, ix(2)), s3 = atom(0, 4, ix(4));
+        const V v1 = atom(0, 1, ix(1)), v2 = atom(0, 3, ix(3)), v3 = atom(0, 5, ix(5));
+        V rho = (V)1 + a * s1 * c2;
+        V ux = b * s3;
+        V q = (v1 - ux) * (v1 - ux) + v2 * v2 + v3 * v3;
+        return rho * (V)F.cst[0] * M<V>::exp(-q / ((V)2 * T));
+    }
     case TT_FN_BIMAXWELL: {
         // table row m: (v_c - u_{m,c})^2 on the velocity modes; cst[m] = rho_m (2 pi T_m)^{-3/2}
         const int d = F.d;
@@ -319,6 +329,29 @@ struct RunDev {
     int64_t verify_R;             // samples of the sampled-error check (0: none)
 };
 
+// Restarts after false convergence (tt_options.restarts): the initial pivots
+// of a restarted run.  pts holds the point list, i0 first; unfolding u holds
+// m[u] of them (point mem[u][z] as pivot z, at superblock positions rho, gam).
+// npts = 0: a plain run (one pivot, i0, from the samples).
+constexpr int TT_MAX_SEEDS = 8;              // points after i0
+constexpr int TT_RESTART_TRIES = 64;         // check samples tried per restart
+struct SeedPlan {
+    int npts;
+    int pts[TT_MAX_SEEDS + 1][TT_MAX_D];
+    int m[TT_MAX_D];
+    int mem[TT_MAX_D][TT_MAX_SEEDS + 1];
+    int rho[TT_MAX_D][TT_MAX_SEEDS + 1];
+    int gam[TT_MAX_D][TT_MAX_SEEDS + 1];
+};
+
+// Candidate points for the next restart: cand[c] enters the unfoldings whose
+// bit is set in cin[c].
+struct PointCheck {
+    int nc;
+    int cand[TT_RESTART_TRIES][TT_MAX_D];
+    int cin[TT_RESTART_TRIES];
+};
+
 struct ProbDev {
     int d, nk;                    // modes, unfoldings (= d-1)
     int r_max, rcap;
@@ -334,6 +367,7 @@ struct ProbDev {
     HostMirror *hm;               // device alias of the host mirror
     RunDev run;
     SweepShape sh0;               // tile counts of the first sweep (every tile stored)
+    const SeedPlan *plan;         // initial pivots of a restarted run (device)
     // phase stamps (only in the library built with TT_STAMPS; null otherwise):
     // STAMP_WORDS clock values per search workgroup (stamp_wgs per sweep),
     // then STAMP_WORDS per commit launch

@@ -93,6 +93,15 @@ struct Problem {
     int escalated = 0;
     bool force_fp64 = false;       // sweep in FP64 whatever the precision policy says
     double *d_part = nullptr;      // partial sums of the check (2 * NBV doubles)
+    // restarts after false convergence (tt_options.restarts)
+    SeedPlan h_plan;               // the point list of the current run and its index sets
+    SeedPlan *d_plan = nullptr;    // its device copy (npts = 0: a plain run)
+    int dev_plan_npts = 0;         // npts of the device copy
+    PointCheck *d_pc = nullptr;    // candidates of a restart
+    double *d_pres = nullptr;      // their residuals, TT_RESTART_TRIES x TT_MAX_D
+    double *d_serr = nullptr;      // |X - X~| per check sample
+    int64_t serr_cap = 0;
+    int restarts_used = 0, restart_cause = 0;
 
     // a run in steps (tt_cross_run_async / tt_cross_query / tt_cross_wait)
     enum { PH_IDLE = 0, PH_SWEEPS, PH_TAIL, PH_VERIFY, PH_DONE };
@@ -106,6 +115,7 @@ struct Problem {
 
     int64_t verify_samples() const;
     bool auto_fp32() const { return opt.precision == TT_PREC_AUTO && fp32 && !force_fp64; }
+    bool restarts_on() const { return opt.restarts > 0 && opt.pivot_mode != TT_PIVOT_ROOK && !cur_fp32; }
 
     ~Problem();
     void release();
@@ -125,6 +135,10 @@ struct Problem {
     int tail_event(bool wait);
     int poll_tail(bool wait);
     int poll_verify(bool wait);
+    int plan_from_points();
+    int point_levels(const int *pt) const;
+    int restart_check(int nc, const int (*cand)[TT_MAX_D], const int *cin, double (*res)[TT_MAX_D]);
+    int try_restart(bool &restarted);
 };
 
 // Process-wide table of tuned tile shapes by problem class (tt_tune.hip).

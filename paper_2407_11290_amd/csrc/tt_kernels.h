@@ -270,10 +270,14 @@ __device__ inline void col_steps(V &u, const V *Gc, const V *s_piv, int zl, bool
     }(), ...);
 }
 
+// The frozen values on the pivot rows and columns inside the tile get the
+// finished factors: W(i, z) at (row i, gamma_z), p_z U(z, j) at (rho_z,
+// column j), except on rows (columns) that hold a pivot themselves, whose
+// entries there belong to the pivot block.
 template <typename V, int RK>
 __device__ inline void solves_lg(gptr_t<V> E, int64_t ld, const TileGeom &g, V *Wt, V *Ut, const V *Gr,
                                  const V *Gc, const V *s_piv, const int *s_rho, const int *s_gam, int TRm,
-                                 int TCm, int rk, int nrw, int ncw, bool rows_old, bool cols_old)
+                                 int TCm, int rk, int nrw, int ncw, const uint8_t *s_rp, const uint8_t *s_cp)
 {
     const int tid = threadIdx.x, zl = tid & 15, gid = tid >> 4;
     constexpr int ngroups = NT / 16;
@@ -286,7 +290,7 @@ __device__ inline void solves_lg(gptr_t<V> E, int64_t ld, const TileGeom &g, V *
         if (ok) {
             Wt[zl * TRm + ii] = w;
             const int gz = s_gam[zl];
-            if (cols_old && gz >= g.col0 && gz < g.col0 + g.ncols) E[(int64_t)(g.row0 + ii) * ld + gz] = w;
+            if (!s_rp[ii] && gz >= g.col0 && gz < g.col0 + g.ncols) E[(int64_t)(g.row0 + ii) * ld + gz] = w;
         }
     }
     for (int base = 0; base < ncw; base += ngroups) {
@@ -296,7 +300,7 @@ __device__ inline void solves_lg(gptr_t<V> E, int64_t ld, const TileGeom &g, V *
         col_steps<V>(u, Gc, s_piv, zl, ok, Steps{});
         if (ok) {
             const int rz = s_rho[zl];
-            if (rows_old && rz >= g.row0 && rz < g.row0 + g.nrows) E[(int64_t)rz * ld + g.col0 + jj] = u;
+            if (!s_cp[jj] && rz >= g.row0 && rz < g.row0 + g.nrows) E[(int64_t)rz * ld + g.col0 + jj] = u;
             Ut[zl * TCm + jj] = u / s_piv[zl];
         }
     }
@@ -340,7 +344,7 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KTile &K, int u, i
     __shared__ int pre[TT_MAX_D], suf[TT_MAX_D];
     __shared__ int s_rho[TT_MAX_RANK], s_gam[TT_MAX_RANK];
     __shared__ V s_piv[TT_MAX_RANK];
-    __shared__ uint8_t s_rp[TT_TILE_ROWS_MAX];
+    __shared__ uint8_t s_rp[TT_TILE_ROWS_MAX], s_cp[TT_TILE_ROWS_MAX];
     const int npre = k - 1, nsuf = d - k - 1, nj = d - k;
     const int TRm = K.TR, TCm = K.TC, ntri = rk * (rk - 1) / 2;
     V *Wt = sm;                                // Wt[z*TRm+ii] = W(row, z)
@@ -376,6 +380,7 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KTile &K, int u, i
     g.col0 = g.q * K.nk1 + g.ik10;
     const int cpv = (tcol < g.ncols) ? as_global((const uint8_t *)K.cpiv)[g.col0 + tcol] : 1;
     for (int ii = tid; ii < g.nrows; ii += NT) s_rp[ii] = as_global((const uint8_t *)K.rpiv)[g.row0 + ii];
+    for (int jj = tid; jj < g.ncols; jj += NT) s_cp[jj] = as_global((const uint8_t *)K.cpiv)[g.col0 + jj];
     // raw factors: frozen entries, or the generating function at the skeleton
     // (the frozen factors load UL per thread at once: a loop that stored each
     // value before loading the next would wait a round trip per pass)
@@ -470,9 +475,9 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KTile &K, int u, i
     // too many passes over the tile).
     const int nrw = rows_old ? 0 : g.nrows, ncw = cols_old ? 0 : g.ncols;
     if (rk <= 8) {
-        solves_lg<V, 8>(E, ld, g, Wt, Ut, Gr, Gc, s_piv, s_rho, s_gam, TRm, TCm, rk, nrw, ncw, rows_old, cols_old);
+        solves_lg<V, 8>(E, ld, g, Wt, Ut, Gr, Gc, s_piv, s_rho, s_gam, TRm, TCm, rk, nrw, ncw, s_rp, s_cp);
     } else if (rk <= 16) {
-        solves_lg<V, 16>(E, ld, g, Wt, Ut, Gr, Gc, s_piv, s_rho, s_gam, TRm, TCm, rk, nrw, ncw, rows_old, cols_old);
+        solves_lg<V, 16>(E, ld, g, Wt, Ut, Gr, Gc, s_piv, s_rho, s_gam, TRm, TCm, rk, nrw, ncw, s_rp, s_cp);
     } else {
         for (int e = tid; e < nrw + ncw; e += NT) {
             if (e < nrw) {
@@ -483,7 +488,7 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KTile &K, int u, i
                     for (int zp = 0; zp < z; ++zp) w = vfma<V>(-Wt[zp * TRm + ii], Gr[tri(zp, z)], w);
                     Wt[z * TRm + ii] = w;
                 }
-                if (cols_old)
+                if (!s_rp[ii])
                     for (int z = 0; z < rk; ++z) {
                         const int gz = s_gam[z];
                         if (gz >= g.col0 && gz < g.col0 + g.ncols)
@@ -497,7 +502,7 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KTile &K, int u, i
 #pragma unroll 8
                     for (int zp = 0; zp < z; ++zp) u = vfma<V>(-Gc[tri(zp, z)], Ut[zp * TCm + jj], u);
                     const int rz = s_rho[z];
-                    if (rows_old && rz >= g.row0 && rz < g.row0 + g.nrows) E[(int64_t)rz * ld + g.col0 + jj] = u;
+                    if (!s_cp[jj] && rz >= g.row0 && rz < g.row0 + g.nrows) E[(int64_t)rz * ld + g.col0 + jj] = u;
                     Ut[z * TCm + jj] = u / s_piv[z];
                 }
             }
@@ -914,7 +919,9 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
             // traffic accounting of this sweep's tiles
             const unsigned long long nst = (unsigned long long)ks[u].nr_st, cst = (unsigned long long)ks[u].nc_st;
             const unsigned long long all = (unsigned long long)nr * (unsigned long long)nc;
-            const unsigned long long live = (nst - rk) * (cst - rk);
+            // (a restarted run's first sweep stores nothing)
+            const unsigned long long live =
+                (nst > (unsigned long long)rk && cst > (unsigned long long)rk) ? (nst - rk) * (cst - rk) : 0ull;
             if (rook) {
                 // every residual looked at streams one factor vector of rk
                 // values (the other is shared by the whole scan)
@@ -1175,6 +1182,144 @@ template <typename X> __device__ inline double chunk_pairwise_sum(X x, int lo, i
     return st[0];
 }
 
+// ---------------------------------------------------------------------------
+// Restarts after false convergence (not in the paper; tt_options.restarts).
+// A restarted run starts from several initial pivots per unfolding (the
+// SeedPlan): the rank-1 recursion of eq. (aca_approx_E) restricted to the
+// pivot rows and columns gives each pivot's residual and the frozen values
+// on the pivot block; an entry of the pivot rows and columns depends on
+// nothing else.  Step z updates the entries (a, b) with a, b > z only (the
+// others are never read again), so every value the runs use matches a
+// recursion over the whole superblock.
+// ---------------------------------------------------------------------------
+constexpr int MSP = TT_MAX_SEEDS + 2;    // pivot-block side: the points and one candidate
+
+// One wavefront: the m x m pivot block of unfolding u in P (FP64), where row
+// a is point ra(a)'s prefix (i_1..i_k) and column b point cb(b)'s suffix
+// (i_{k+1}..i_d).  Then steps z < zend of the recursion; before step z,
+// frozen(a, b, value) is called for row z from column z on and for column z
+// below row z.
+template <int FNS, typename RA, typename CB, typename FR>
+__device__ inline void pivot_block_wave(const ProbDev *__restrict__ P, int k, int m, RA ra, CB cb, double (*Pm)[MSP],
+                                        int zend, FR frozen)
+{
+    const int lane = threadIdx.x & 63;
+    for (int e = lane; e < m * m; e += 64) {
+        const int a = e / m, b = e - a * m;
+        const int *pa = ra(a), *pb = cb(b);
+        Pm[a][b] = fn_value_ix<double, FNS>(P->F, [&](int j) { return j < k ? pa[j] : pb[j]; });
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int z = 0; z < zend; ++z) {
+        double nv[(MSP * MSP + 63) / 64];
+#pragma unroll
+        for (int i = 0; i < (MSP * MSP + 63) / 64; ++i) {
+            const int e = lane + 64 * i, a = e / m, b = e - a * m;
+            nv[i] = 0.0;
+            if (e < m * m) {
+                if ((a == z && b >= z) || (b == z && a > z)) frozen(a, b, Pm[a][b]);
+                if (a > z && b > z) nv[i] = __fma_rn(-Pm[a][z], Pm[z][b] / Pm[z][z], Pm[a][b]);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int i = 0; i < (MSP * MSP + 63) / 64; ++i) {
+            const int e = lane + 64 * i, a = e / m, b = e - a * m;
+            if (e < m * m && a > z && b > z) Pm[a][b] = nv[i];
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// The initial pivots of a restarted run (whole workgroup, after the samples'
+// part of the setup): pivot data, masks, index tuples, the pivot block's
+// frozen values in E, and shapes in which every tile of the first sweep is
+// new (nothing stored yet).
+template <typename V, int FNS>
+__device__ void seeded_pivots(const ProbDev *__restrict__ P, ProbState *S, const SeedPlan *plan)
+{
+    const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63, d = P->d, nk = P->nk;
+    __shared__ double sP[NT / 64][MSP][MSP];
+    for (int u = wid; u < nk; u += NT / 64) {
+        const KDev &K = P->kd[u];
+        const int k = u + 1, m = plan->m[u];
+        const gptr_t<V> E = as_global((V *)K.E);
+        const int64_t ld = K.ld;
+        auto pt = [&](int z) { return plan->pts[plan->mem[u][z]]; };
+        pivot_block_wave<FNS>(P, k, m, pt, pt, sP[wid], m, [&](int a, int b, double v) {
+            E[(int64_t)plan->rho[u][a] * ld + plan->gam[u][b]] = (V)v;
+        });
+        if (lane < m) {
+            const int z = lane, *pz = pt(z);
+            const int rz = plan->rho[u][z], gz = plan->gam[u][z];
+            K.rho[z] = rz;
+            K.gam[z] = gz;
+            K.piv[z] = (double)(V)sP[wid][z][z];
+            K.piv64[z] = sP[wid][z][z];
+            K.rpiv[rz] = (uint8_t)(z + 1);
+            K.cpiv[gz] = (uint8_t)(z + 1);
+            for (int j = 0; j < k; ++j) K.Ifull[z * k + j] = pz[j];
+            for (int j = 0; j < d - k; ++j) K.Jfull[z * (d - k) + j] = pz[k + j];
+        }
+        if (lane == 0) {
+            const int mp = u >= 1 ? plan->m[u - 1] : 1, mn = u + 1 < nk ? plan->m[u + 1] : 1;
+            KSweep ks;
+            ks.rk = m;
+            ks.apply = 0;
+            ks.nr_st = 0;
+            ks.nc_st = 0;
+            ks.nr = mp * K.nk;
+            ks.nc = K.nk1 * mn;
+            ks.arho = 0;
+            ks.agam = 0;
+            ks.apiv = 0.0;
+            S->ks[u] = ks;
+            S->r[0][k] = m;
+            S->r[1][k] = m;
+            P->hm->r[k] = m;
+        }
+    }
+    if (tid == 0) {
+        int no = 0;
+        for (int u = 0; u < nk; ++u) {
+            const KDev &K = P->kd[u];
+            const int mp = u >= 1 ? plan->m[u - 1] : 1, mn = u + 1 < nk ? plan->m[u + 1] : 1;
+            S->sh.RT[u] = mp * K.RTp;
+            S->sh.CT[u] = mn * K.CTq;
+            S->sh.RTs[u] = 0;
+            S->sh.CTs[u] = 0;
+            S->sh.noff[u] = no;
+            S->sh.soff[u] = 0;
+            no += S->sh.RT[u] * S->sh.CT[u];
+        }
+        S->sh.noff[nk] = no;
+        S->sh.soff[nk] = 0;
+        P->hm->r[0] = 1;
+        P->hm->r[d] = 1;
+    }
+}
+
+// |residual| of every candidate point as the next pivot of every unfolding it
+// enters, after that unfolding's pivots in the plan: one wavefront per
+// (candidate, unfolding); out[c * TT_MAX_D + u] (-1 where it does not enter).
+template <int FNS>
+static __global__ void __launch_bounds__(NT) k_point_resid(const ProbDev *__restrict__ P, const SeedPlan *plan,
+                                                          const PointCheck *pc, double *out)
+{
+    const int nk = P->nk, wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int gw = blockIdx.x * (NT / 64) + wid, c = gw / nk, u = gw - c * nk;
+    if (c >= pc->nc) return;
+    if (!((pc->cin[c] >> u) & 1)) {
+        if (lane == 0) out[c * TT_MAX_D + u] = -1.0;
+        return;
+    }
+    __shared__ double sP[NT / 64][MSP][MSP];
+    const int m = plan->m[u] + 1;
+    auto pt = [&](int z) { return z < m - 1 ? plan->pts[plan->mem[u][z]] : pc->cand[c]; };
+    pivot_block_wave<FNS>(P, u + 1, m, pt, pt, sP[wid], m - 1, [](int, int, double) {});
+    if (lane == 0) out[c * TT_MAX_D + u] = fabs(sP[wid][m - 1][m - 1]);
+}
+
 template <typename V, int FNS>
 __device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns, const SamplePart *part, double eps)
 {
@@ -1233,7 +1378,10 @@ __device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns,
     // store may alias the descriptor, so a loop over the unfoldings would
     // read each descriptor only after the previous one's stores)
     const int u = tid >> 4, l = tid & 15;
-    if (u < P->nk) {
+    const int npts = P->plan->npts;
+    if (npts > 0) {
+        seeded_pivots<V, FNS>(P, S, P->plan);
+    } else if (u < P->nk) {
         const KDev &K = P->kd[u];
         const int k = u + 1;
         const int knk = K.nk, knk1 = K.nk1;      // read before any store
@@ -1257,11 +1405,13 @@ __device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns,
             S->ks[u] = ks;
         }
     }
-    for (int t = tid; t < SHAPE_WORDS; t += NT) ((int *)&S->sh)[t] = ((const int *)&P->sh0)[t];
+    if (npts == 0) {
+        for (int t = tid; t < SHAPE_WORDS; t += NT) ((int *)&S->sh)[t] = ((const int *)&P->sh0)[t];
+        if (tid == 0)
+            for (int j = 0; j <= d; ++j) P->hm->r[j] = 1;
+    }
     if (tid == 0) {
         HostMirror *hm = P->hm;
-        for (int j = 0; j <= d; ++j) hm->r[j] = 1;
-        hm->err = S->err;
         hm->stop = S->stop;
         __threadfence_system();
     }
@@ -2261,8 +2411,9 @@ static __global__ void __launch_bounds__(A4W) k_cores(const ProbDev *__restrict_
 // ---------------------------------------------------------------------------
 constexpr int NBV = 128;        // workgroups per checked problem
 
+// serr (optional): |X - X~| of every sample, in sample order.
 __device__ void verify_body(const ProbDev *__restrict__ P, const double *__restrict__ G, const int *r, int64_t R,
-                            uint64_t seed, double *part, int blk, int nblk)
+                            uint64_t seed, double *part, int blk, int nblk, double *serr = nullptr)
 {
     const int d = P->d, lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     CoreArgs ca;
@@ -2296,6 +2447,7 @@ __device__ void verify_body(const ProbDev *__restrict__ P, const double *__restr
             const double dx = x - v;
             num = __fma_rn(dx, dx, num);
             den = __fma_rn(x, x, den);
+            if (serr) serr[t] = fabs(dx);
         }
     }
     // the group leaders' sums in lane order, then the wavefronts in order
@@ -2319,11 +2471,11 @@ __device__ inline void final_ranks(const ProbDev *P, int *r)
 }
 
 static __global__ void __launch_bounds__(NT) k_verify(const ProbDev *__restrict__ P, const double *G, int64_t R,
-                                                      uint64_t seed, double *part)
+                                                      uint64_t seed, double *part, double *serr)
 {
     int r[TT_MAX_D + 1];
     final_ranks(P, r);
-    verify_body(P, G, r, R, seed, part, blockIdx.x, gridDim.x);
+    verify_body(P, G, r, R, seed, part, blockIdx.x, gridDim.x, serr);
 }
 
 // ---------------------------------------------------------------------------

@@ -40,9 +40,9 @@ def test_options_defaults():
 
 
 def test_struct_sizes_match_the_header():
-    # tt_options: u64 + 4 i32 + 16 i32 + 3 i32 (+pad) + pointer
-    assert C.sizeof(_lib.Options) == 8 + 4 * 4 + 4 * 16 + 4 * 4 + 8 + 2 * 4
-    assert C.sizeof(_lib.Stats) == 3 * 8 + 4 * 4 + 4 * 17 + 4 + 3 * 8 + 8 * 16 + 8 + 4 * 8 + 8 + 2 * 4
+    # tt_options: u64 + 4 i32 + 16 i32 + 4 i32 + pointer + 3 i32 (+ pad to 8)
+    assert C.sizeof(_lib.Options) == 8 + 4 * 4 + 4 * 16 + 4 * 4 + 8 + 3 * 4 + 4
+    assert C.sizeof(_lib.Stats) == 3 * 8 + 4 * 4 + 4 * 17 + 4 + 3 * 8 + 8 * 16 + 8 + 4 * 8 + 8 + 2 * 4 + 2 * 4
 
 
 @pytest.mark.parametrize("args,code", [

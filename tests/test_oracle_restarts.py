@@ -27,6 +27,23 @@ def _two_blocks(n, A=1.0, B=2.0):
     return np.array(params)
 
 
+def _framed_two_blocks(n, A=1.0, B=2.0):
+    """g(i_1) h(i_d) times the two-block tensor of the middle modes: rank 1
+    in the two end unfoldings, rank 2 in the others."""
+    d = len(n)
+    params = [2.0]
+    for c, low in ((A, True), (B, False)):
+        for j, m in enumerate(n):
+            if j == 0:
+                v = [c * (1.0 + 0.1 * i) for i in range(m)]
+            elif j == d - 1:
+                v = [2.0 - 0.1 * i for i in range(m)]
+            else:
+                v = [1.0 if ((i < m // 2) == low) else 0.0 for i in range(m)]
+            params += v
+    return np.array(params)
+
+
 def _assert_nested(o):
     """eq. (nestedpivots), and every unfolding's cross square."""
     d = o.d
@@ -133,3 +150,22 @@ def test_initial_pivot_residuals_are_the_dense_elimination():
             pz = E[rho[z], gam[z]]
             assert abs(pz - piv[z]) <= 1e-10 * np.max(np.abs(X))
             E = E - np.outer(E[:, gam[z]], E[rho[z], :] / pz)
+
+
+@pytest.mark.parametrize("n", [[6, 8, 8, 8, 8, 5], [5, 6, 7, 6, 4]])
+def test_trimmed_restart_point_on_framed_blocks(n):
+    """The worst sample enters the end unfoldings, where the residual is
+    exactly zero (rank 1): it is trimmed to i0's end indices, enters only the
+    middle unfoldings, and the restart recovers the exact ranks."""
+    p = _framed_two_blocks(n)
+    o = Oracle(n, 1e-8, FN_SEPSUM, p, seed=0, restarts=3, restart_R=R_CHECK)
+    assert o.run() == 0
+    info = o.restart_info()
+    assert info["used"] == 1 and info["cause"] == 0
+    d = len(n)
+    assert list(o.ranks()) == [1, 1] + [2] * (d - 3) + [1, 1]
+    i0 = o.stats()["i0"]
+    assert info["seeds"][0][0] == i0[0] and info["seeds"][0][d - 1] == i0[d - 1]
+    full, _ = o.full_error()
+    assert full <= 1e-14
+    _assert_nested(o)
