@@ -448,6 +448,63 @@ def measure_batch(steps, warmup=1):
             "sampled_err_max": max(s["sampled_err"] for s in stats)}
 
 
+def measure_escalation():
+    """The precision policy's escalation decision (FP32 sweeps missed eps?)
+    taken on the 4096-sample check against the same decision on 1e6
+    samples: every problem solved with FP32 sweeps and no check, then the
+    sampled error of its FP32 result over the first 4096 and the first 1e6
+    indices of the check stream (seed + 1; the small set is the large one's
+    prefix).  Problems: the 512-problem batch mix and the 6D Maxwellian
+    (n = 128, 2^6 blocks, eps = 1e-6) over seeds 0..9."""
+    import numpy as np
+    from paper_2407_11290_amd import FN_MAXWELL, PREC_FP32
+    from paper_2407_11290_amd.api import TTCross, batch_run
+    from paper_2407_11290_amd.workloads import batch_mix
+    specs = batch_mix()
+    rows = []
+    hs = [TTCross(p.n, p.eps, p.fn_id, p.params, seed=p.seed, grid=p.grid, precision=PREC_FP32, verify=0)
+          for p in specs]
+    batch_run(hs)
+    for p, h in zip(specs, hs):
+        rows.append(("batch", p.eps, h.sampled_error(4096, seed=p.seed + 1),
+                     h.sampled_error(1_000_000, seed=p.seed + 1)))
+        h.close()
+    for s in range(10):
+        h = TTCross(MAXWELL_N, MAXWELL_EPS, FN_MAXWELL, seed=s, grid=[2] * 6, precision=PREC_FP32, verify=0)
+        h.run()
+        rows.append(("maxwell6d", MAXWELL_EPS, h.sampled_error(4096, seed=s + 1),
+                     h.sampled_error(1_000_000, seed=s + 1)))
+        h.close()
+    out = {}
+    for name in ("batch", "maxwell6d"):
+        r = [x for x in rows if x[0] == name]
+        eps = np.array([x[1] for x in r])
+        e4 = np.array([x[2] for x in r])
+        e6 = np.array([x[3] for x in r])
+        ratio = e4 / np.maximum(e6, 1e-300)
+        near = (e6 > 0.3 * eps) & (e6 < 3 * eps)
+        out[name] = {"problems": len(r),
+                     "ratio_4096_over_1e6": {"median": float(np.median(ratio)), "min": float(ratio.min()),
+                                             "max": float(ratio.max())},
+                     "err_1e6_over_eps": {"median": float(np.median(e6 / eps)), "max": float((e6 / eps).max())},
+                     "escalate_on_4096": int((e4 > eps).sum()), "escalate_on_1e6": int((e6 > eps).sum()),
+                     "missed_by_4096": int(((e6 > eps) & (e4 <= eps)).sum()),
+                     "extra_by_4096": int(((e4 > eps) & (e6 <= eps)).sum()),
+                     "near_eps": int(near.sum()),
+                     "near_eps_ratio": ({"min": float(ratio[near].min()), "max": float(ratio[near].max())}
+                                        if near.any() else None)}
+    return out
+
+
+def bench_escalation(args):
+    out = measure_escalation()
+    print(json.dumps({"metric": METRIC, "value": None, "unit": "problems", "n_gpus": 1, "steps": 1, "warmup": 0,
+                      "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                      "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": "escalation_check_4096_vs_1e6_samples"}, "escalation": out}),
+          flush=True)
+
+
 def _pct(v, q):
     v = sorted(v)
     return v[min(len(v) - 1, int(q * len(v)))] * 1e3
@@ -806,14 +863,15 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="hilbert6d",
-                    choices=["hilbert6d", "maxwell6d", "batch512", "serve", "eval", "rook", "paper", "phases"],
+                    choices=["hilbert6d", "maxwell6d", "batch512", "serve", "eval", "rook", "paper", "phases",
+                             "escalation"],
                     help="hilbert6d: the single-solve benchmark line (with summaries of the other "
                          "configurations); maxwell6d: the 6D Maxwellian with FP32 sweeps; batch512: the mixed 512-problem "
                          "batch, solved together and one at a time; serve: a Poisson-arrival trace "
                          "through the continuous-batching server; eval: bulk entry evaluation of the 6D "
                          "Maxwellian in FP32 and FP64; rook: rook pivoting on the 3D Hilbert tensor with "
                          "n = 100000 per mode; paper: the paper's Sec. 5 workloads at its shapes and "
-                         "prescribed ranks")
+                         "prescribed ranks; escalation: the policy's 4096-sample check against 1e6 samples")
     ap.add_argument("--eval-m", type=int, default=1 << 24, help="eval: multi-indices per step")
     ap.add_argument("--requests", type=int, default=2000, help="serve: trace length")
     ap.add_argument("--no-extras", action="store_true",
@@ -860,6 +918,8 @@ def main():
         return bench_rook(args)
     if args.workload == "paper":
         return bench_paper(args)
+    if args.workload == "escalation":
+        return bench_escalation(args)
 
     handles = [TTCross(N, EPS, FN_HILBERT, seed=s, precision=PREC_FP64, grid=GRID) for s in SEEDS]
     probes = [TTCross(N, EPS, FN_HILBERT, seed=s, precision=PREC_FP64, grid=GRID, profile=1) for s in SEEDS]
