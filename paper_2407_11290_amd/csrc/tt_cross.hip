@@ -442,8 +442,9 @@ int Problem::allocate()
         if (rook) {
             // factors W (rows x rank) and U (rank x columns) instead of the residual
             K.E = nullptr;
-            if ((st = dalloc((void **)&K.Wf, sizeof(double) * K.rowcap * rk)) != TT_OK) return st;
-            if ((st = dalloc((void **)&K.Uf, sizeof(double) * rk * K.colcap)) != TT_OK) return st;
+            const size_t fp = (size_t)factor_pitch(rk);
+            if ((st = dalloc((void **)&K.Wf, sizeof(double) * K.rowcap * fp)) != TT_OK) return st;
+            if ((st = dalloc((void **)&K.Uf, sizeof(double) * fp * K.colcap)) != TT_OK) return st;
             K.nrb = 1;
             K.ncb = 1;
             for (int j = 0; j < k; ++j) K.nrb *= grid[j];

@@ -88,6 +88,11 @@ template <typename V> __host__ __device__ inline V vel(int i, int n, V vmax)
 template <typename T> using gptr_t = __attribute__((address_space(1))) T *;
 template <typename T> __device__ inline gptr_t<T> as_global(T *p) { return (gptr_t<T>)p; }
 
+// Rook factors: a row of W and a column of U are contiguous vectors whose
+// starts lie 64 bytes apart at least, the rank cap rounded up to 8 values, so
+// a residual reads each vector as whole aligned 64-byte chunks.
+__host__ __device__ inline int factor_pitch(int rank_cap) { return (rank_cap + 7) & ~7; }
+
 // The per-mode table in the arithmetic's precision.
 template <typename V> __host__ __device__ inline const V *fn_table(const FnDev &F);
 template <> __host__ __device__ inline const double *fn_table<double>(const FnDev &F) { return F.tab; }

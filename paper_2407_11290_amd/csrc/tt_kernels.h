@@ -1446,6 +1446,37 @@ __device__ inline int grid_piece(int i, int n, int C)
 
 __device__ inline int piece_start(int b, int n, int C) { return (int)((int64_t)b * n / C); }
 
+// Values z .. z+7 of a rook factor vector: one aligned 64-byte load from
+// device memory (the chunk lies inside the vector's pitch; values at rk and
+// beyond are read but not used), or eight LDS reads of a workgroup copy.
+typedef double dvec8 __attribute__((ext_vector_type(8)));
+__device__ inline dvec8 factor_chunk(gptr_t<const double> v, int z) { return *(gptr_t<const dvec8>)(v + z); }
+__device__ inline dvec8 factor_chunk(const double *v, int z)
+{
+    dvec8 r;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) r[m] = v[z + m];
+    return r;
+}
+
+// x minus the products Wrow[z] * Ucol[z] for z = 0 .. rk-1 in that order, the
+// fma chain of the in-place elimination.  Each vector is read chunk by chunk
+// and every chunk is used as soon as it arrives: read value by value, a lane
+// touches a new cache line per value of a random row, and with many lanes on
+// many rows the lines are evicted before the next value is read.
+template <typename TW, typename TU>
+__device__ inline double factor_chain(double x, TW Wrow, TU Ucol, int rk)
+{
+    for (int z = 0; z < rk; z += 8) {
+        const dvec8 w = factor_chunk(Wrow, z), v = factor_chunk(Ucol, z);
+        const int m_end = rk - z;
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+            if (m < m_end) x = __fma_rn(-w[m], v[m], x);
+    }
+    return x;
+}
+
 // The generating function at superblock entry (row, col) of unfolding u.
 template <int FNS>
 __device__ inline double rook_entry(const ProbDev *__restrict__ P, int u, int row, int col)
@@ -1487,25 +1518,24 @@ __device__ void rook_factor_body(const ProbDev *__restrict__ P, int nk, int blk,
         while (u + 1 < nk && t >= off[u + 1]) ++u;
         const KDev &K = P->kd[u];
         const KSweep &s = ks[u];
-        const int e = t - off[u], rk = s.rk, wp = K.rk_cap;
+        const int e = t - off[u], rk = s.rk, wp = factor_pitch(K.rk_cap);
         const gptr_t<double> W = as_global(K.Wf), U = as_global(K.Uf);
         if (e < s.nr) {
             const int i = e;
             const int z0 = (i < s.nr_st) ? (s.apply ? rk - 1 : rk) : 0;
+            const gptr_t<double> Wi = W + (int64_t)i * wp;
             for (int z = z0; z < rk; ++z) {
                 const int gz = as_global((const int *)K.gam)[z];
-                double x = rook_entry<FNS>(P, u, i, gz);
-                for (int zp = 0; zp < z; ++zp) x = __fma_rn(-W[(int64_t)i * wp + zp], U[(int64_t)gz * wp + zp], x);
-                W[(int64_t)i * wp + z] = x;
+                Wi[z] = factor_chain(rook_entry<FNS>(P, u, i, gz), gptr_t<const double>(Wi), gptr_t<const double>(U + (int64_t)gz * wp), z);
             }
         } else {
             const int j = e - s.nr;
             const int z0 = (j < s.nc_st) ? (s.apply ? rk - 1 : rk) : 0;
+            const gptr_t<double> Uj = U + (int64_t)j * wp;
             for (int z = z0; z < rk; ++z) {
                 const int rz = as_global((const int *)K.rho)[z];
-                double x = rook_entry<FNS>(P, u, rz, j);
-                for (int zp = 0; zp < z; ++zp) x = __fma_rn(-W[(int64_t)rz * wp + zp], U[(int64_t)j * wp + zp], x);
-                U[(int64_t)j * wp + z] = x / as_global((const double *)K.piv)[z];
+                const double x = factor_chain(rook_entry<FNS>(P, u, rz, j), gptr_t<const double>(W + (int64_t)rz * wp), gptr_t<const double>(Uj), z);
+                Uj[z] = x / as_global((const double *)K.piv)[z];
             }
         }
     }
@@ -1695,9 +1725,7 @@ template <int FNS, typename TW, typename TU>
 __device__ inline double rook_residual_loc(const ProbDev *__restrict__ P, const RookBlock &B, int tp, int ik, int tq,
                                            int ik1, TW Wrow, TU Ucol, int rk)
 {
-    double x = rook_entry_loc<FNS>(P, B, tp, ik, tq, ik1);
-    for (int z = 0; z < rk; ++z) x = __fma_rn(-Wrow[z], Ucol[z], x);
-    return x;
+    return factor_chain(rook_entry_loc<FNS>(P, B, tp, ik, tq, ik1), Wrow, Ucol, rk);
 }
 
 // The loop of Alg. 1 run by one workgroup from (ci, cj), whose |residual| is
@@ -1713,7 +1741,7 @@ template <int FNS>
 __device__ int rook_walk(const ProbDev *__restrict__ P, const KDev &K, const RookBlock &B, double *s_f, double &bv,
                          double &bs, int &ci, int &cj, unsigned long long &cnt)
 {
-    const int tid = threadIdx.x, wp = K.rk_cap, rk = B.ks.rk, nR = B.nR(), nC = B.nC();
+    const int tid = threadIdx.x, wp = factor_pitch(K.rk_cap), rk = B.ks.rk, nR = B.nR(), nC = B.nC();
     const int len = B.g.len, len1 = B.g.len1, lo = B.g.lo, lo1 = B.g.lo1;
     const gptr_t<const double> W = as_global((const double *)K.Wf), U = as_global((const double *)K.Uf);
     const gptr_t<const uint8_t> rpiv = as_global((const uint8_t *)K.rpiv), cpiv = as_global((const uint8_t *)K.cpiv);
@@ -1775,7 +1803,7 @@ __device__ inline void rook_samples(const ProbDev *__restrict__ P, const KDev &K
                                     int sweep, uint64_t seed, int s0, int ds, double &bv, uint64_t &bk, double &bs,
                                     unsigned long long &cnt)
 {
-    const int k = u + 1, wp = K.rk_cap, rk = B.ks.rk, nR = B.nR(), nC = B.nC();
+    const int k = u + 1, wp = factor_pitch(K.rk_cap), rk = B.ks.rk, nR = B.nR(), nC = B.nC();
     const int len = B.g.len, len1 = B.g.len1, lo = B.g.lo, lo1 = B.g.lo1;
     const gptr_t<const double> W = as_global((const double *)K.Wf), U = as_global((const double *)K.Uf);
     const uint64_t tag = (uint64_t)k | ((uint64_t)sweep << 8) | ((uint64_t)b << 32);
@@ -1824,7 +1852,7 @@ __device__ void rook_search_body(const ProbDev *__restrict__ P, int nk, int swee
     __shared__ RookBlock B;
     __shared__ double s_f[TT_MAX_RANK];
     rook_block_load(P, u, b, B);
-    const int nR = B.nR(), nC = B.nC(), rk = B.ks.rk, wp = K.rk_cap;
+    const int nR = B.nR(), nC = B.nC(), rk = B.ks.rk, wp = factor_pitch(K.rk_cap);
     const gptr_t<const double> W = as_global((const double *)K.Wf), U = as_global((const double *)K.Uf);
     double bv = -1.0, bs = 0.0;
     uint64_t bk = ~0ULL;
@@ -1954,7 +1982,7 @@ __device__ void rook_wstep_body(const ProbDev *__restrict__ P, int nk, int p, in
     double pv, psv;
     uint64_t pk;
     rook_reduce_parts(K, G, (p - 1) & 1, b, pv, pk, psv);
-    const int nR = B.nR(), nC = B.nC(), rk = B.ks.rk, wp = K.rk_cap;
+    const int nR = B.nR(), nC = B.nC(), rk = B.ks.rk, wp = factor_pitch(K.rk_cap);
     const int len = B.g.len, len1 = B.g.len1, lo = B.g.lo, lo1 = B.g.lo1;
     const gptr_t<const double> W = as_global((const double *)K.Wf), U = as_global((const double *)K.Uf);
     unsigned long long cnt = 0;
