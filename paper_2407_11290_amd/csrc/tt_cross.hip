@@ -477,6 +477,7 @@ int Problem::allocate()
     }
     cores_cap += (int64_t)rc[d - 1] * n[d - 1];
     if ((st = dalloc((void **)&d_cores, sizeof(double) * cores_cap)) != TT_OK) return st;
+    if ((st = dalloc((void **)&d_ctab, sizeof(double) * CT_STRIDE * (d - 1))) != TT_OK) return st;
     if ((st = dalloc((void **)&d_vals, sizeof(double) * opt.n_samples)) != TT_OK) return st;
     if ((st = dalloc((void **)&d_spart, sizeof(SamplePart) * sample_blocks(opt.n_samples))) != TT_OK) return st;
     if ((st = dalloc((void **)&d_part, sizeof(double) * 2 * NBV)) != TT_OK) return st;
@@ -776,10 +777,28 @@ template <typename V> int Problem::launch_tail()
     int maxr = 1;
     for (int k = 1; k <= d - 1; ++k) maxr = std::max(maxr, ranks_now[k]);
     const int blocks = make_core_args(d, n, ranks_now, ca, cores_len);
-    const size_t lc = sizeof(double) * ((size_t)2 * maxr * (maxr + 1) + (size_t)2 * maxr * A4W);
-    if (lc > (size_t)lds_limit) return set_err(TT_EINVAL, "rank %d too large for the core kernel", maxr);
-    if (fn.dev.id == TT_FN_HILBERT) k_cores<TT_FN_HILBERT><<<blocks, A4W, lc, stream>>>(dP, ca, d_cores);
-    else k_cores<0><<<blocks, A4W, lc, stream>>>(dP, ca, d_cores);
+    const bool hil = fn.dev.id == TT_FN_HILBERT;
+    if (maxr > 16) {
+        // above rank 16 the pivot rows' recursion runs once per unfolding and
+        // the fiber rows keep their T in registers (same operations, same bits)
+        const size_t lp = sizeof(double) * (size_t)2 * maxr * (maxr + 1),
+                     lt = hil ? 0 : sizeof(double) * (size_t)maxr * A4W;
+        if (lp > (size_t)lds_limit) return set_err(TT_EINVAL, "rank %d too large for the core kernel", maxr);
+        if (hil) k_core_piv<TT_FN_HILBERT><<<d - 1, A4W, lp, stream>>>(dP, ca, d_ctab);
+        else k_core_piv<0><<<d - 1, A4W, lp, stream>>>(dP, ca, d_ctab);
+        HIPCHK(hipGetLastError());
+        if (maxr <= 32) {
+            if (hil) k_cores_t<TT_FN_HILBERT, 32><<<blocks, A4W, lt, stream>>>(dP, ca, d_cores, d_ctab);
+            else k_cores_t<0, 32><<<blocks, A4W, lt, stream>>>(dP, ca, d_cores, d_ctab);
+        } else {
+            if (hil) k_cores_t<TT_FN_HILBERT, TT_MAX_RANK><<<blocks, A4W, lt, stream>>>(dP, ca, d_cores, d_ctab);
+            else k_cores_t<0, TT_MAX_RANK><<<blocks, A4W, lt, stream>>>(dP, ca, d_cores, d_ctab);
+        }
+    } else {
+        const size_t lc = sizeof(double) * ((size_t)2 * maxr * (maxr + 1) + (size_t)2 * maxr * A4W);
+        if (hil) k_cores<TT_FN_HILBERT><<<blocks, A4W, lc, stream>>>(dP, ca, d_cores);
+        else k_cores<0><<<blocks, A4W, lc, stream>>>(dP, ca, d_cores);
+    }
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(run_ev[1], stream));
     HIPCHK(hipMemcpyAsync(hS_pinned, hP.S, sizeof(ProbState), hipMemcpyDeviceToHost, stream));

@@ -228,8 +228,8 @@ struct KDev {
     int cand_cap;
     double *hist;                 // per-sweep largest |residual|
     // rook mode: factors instead of a stored residual, and the block grid
-    double *Wf;                   // W(i, z) = Wf[i * rk_cap + z], rowcap rows
-    double *Uf;                   // U(z, j) = Uf[j * rk_cap + z], colcap columns
+    double *Wf;                   // W(i, z) = Wf[i * factor_pitch(rk_cap) + z], rowcap rows
+    double *Uf;                   // U(z, j) = Uf[j * factor_pitch(rk_cap) + z], colcap columns
     int nrb, ncb;                 // row blocks (modes 1..k), column blocks (modes k+1..d)
     unsigned long long *bcnt;     // residuals looked at per block in the current sweep
     // rook search split over G workgroups per block

@@ -69,6 +69,7 @@ struct Problem {
     ProbDev *dP = nullptr;
     HostMirror *hm = nullptr;
     double *d_cores = nullptr, *d_vals = nullptr;
+    double *d_ctab = nullptr;          // the cores' pivot-row recursion, per unfolding
     SamplePart *d_spart = nullptr;
     // results
     bool ran = false;

@@ -63,6 +63,17 @@ __device__ inline bool better(double a, uint64_t ka, double b, uint64_t kb)
     return a > b || (a == b && ka < kb);
 }
 
+// A workgroup barrier that orders LDS accesses only.  __syncthreads also
+// waits for every global load and store the wavefront has in flight; where
+// what follows reads nothing another thread wrote to device memory, the
+// stores then drain while the workgroup goes on.
+__device__ inline void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Workgroup-wide (max |value|, lowest key) reduction carrying the signed
 // value; the result is valid in every thread.
 __device__ inline void block_best(double &v, uint64_t &key, double &sv)
@@ -152,7 +163,7 @@ __device__ inline void block_best_t0(double &v, uint64_t &key, double &sv)
     wave_best(v, key, sv);
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     if (l == 0 && w > 0) { s_v[w] = v; s_k[w] = key; s_sv[w] = sv; }
-    __syncthreads();
+    lds_barrier();
     if (threadIdx.x == 0)
         for (int i = 1; i < NT / 64; ++i)
             if (better(s_v[i], s_k[i], v, key)) { v = s_v[i]; key = s_k[i]; sv = s_sv[i]; }
@@ -508,7 +519,7 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KTile &K, int u, i
             }
         }
     }
-    __syncthreads();
+    lds_barrier();
     TT_STAMP(rec, 5);
     if (tcol < g.ncols && !cpv) {
         const int col = g.col0 + tcol;
@@ -621,7 +632,7 @@ __device__ void sweep_body(const ProbDev *__restrict__ P, const ProbState *S, in
                 const gptr_t<Cand> c = as_global(K.cand) + (R * CT + C);
                 c->v = bv; c->key = bk; c->sv = bs;
             }
-            __syncthreads();
+            lds_barrier();
         } else {
             // the wavefront index is uniform across the wavefront: saying so
             // keeps the tile's descriptor reads and geometry scalar
@@ -985,7 +996,7 @@ __device__ void commit_body(const ProbDev *__restrict__ P, ProbState *S, int swe
         TT_STAMP(rec, 2);
         for (int u = wid; u < nk; u += NW) decide(u, s_wv[u], s_wk[u], s_wsv[u]);
     }
-    __syncthreads();
+    lds_barrier();
     TT_STAMP(rec, 3);
     // the next sweep's shapes and tile counts: lane u of wavefront 0 prepares
     // unfolding u, and the tile offsets are prefix sums over the lanes
@@ -2286,28 +2297,46 @@ __device__ bool core_alg4_regs(const double *Ap, const double *Ab, int st, int r
     return singular;
 }
 
+// G_d = X(I_{<=d-1}, :): the workgroups past the last unfolding's rows, one
+// entry per lane.
+template <int FNS>
+__device__ void core_last_fiber(const ProbDev *__restrict__ P, const CoreArgs &a, double *G, int bid)
+{
+    const int lane = threadIdx.x, d = P->d;
+    const KDev &K = P->kd[d - 2];
+    const int rd = a.ranks[d - 1], nd = P->F.n[d - 1];
+    const int64_t e = (int64_t)(bid - a.rowblocks[a.nk]) * A4W + lane;
+    if (e >= (int64_t)rd * nd) return;
+    const int pp = (int)(e / nd), i = (int)(e - (int64_t)pp * nd);
+    const gptr_t<const int> Ip = as_global((const int *)K.Ifull) + pp * (d - 1);
+    // the lane's index tuple, every entry in flight at once
+    int pv[TT_MAX_D];
+#pragma unroll
+    for (int j = 0; j < TT_MAX_D; ++j) pv[j] = Ip[min(j, d - 2)];
+    if constexpr (FNS == TT_FN_HILBERT) {
+        // the entry depends on the integer index sum only
+        long long s = (long long)i + 1;
+#pragma unroll
+        for (int j = 0; j < TT_MAX_D; ++j)
+            if (j < d - 1) s += (long long)pv[j] + 1;
+        G[a.goff[d - 1] + e] = 1.0 / ((double)s + P->F.shift);
+    } else {
+        // through LDS: the function reads the tuple by a runtime index
+        __shared__ int sIp[A4W * TT_MAX_D];
+#pragma unroll
+        for (int j = 0; j < TT_MAX_D; ++j)
+            if (j < d - 1) sIp[lane * TT_MAX_D + j] = pv[j];
+        G[a.goff[d - 1] + e] = fn_value_ix<double, FNS>(P->F, [&](int j) { return j < d - 1 ? sIp[lane * TT_MAX_D + j] : i; });
+    }
+}
+
 template <int FNS>
 __device__ void cores_body(const ProbDev *__restrict__ P, const CoreArgs &a, double *G, int bid)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int lane = threadIdx.x, d = P->d;
     if (bid >= a.rowblocks[a.nk]) {
-        const KDev &K = P->kd[d - 2];
-        const int rd = a.ranks[d - 1], nd = P->F.n[d - 1];
-        const int64_t e = (int64_t)(bid - a.rowblocks[a.nk]) * A4W + lane;
-        if (e >= (int64_t)rd * nd) return;
-        const int pp = (int)(e / nd), i = (int)(e - (int64_t)pp * nd);
-        const gptr_t<const int> Ip = as_global((const int *)K.Ifull) + pp * (d - 1);
-        // the lane's index tuple, every entry in flight at once, through LDS
-        // (the function reads it by a runtime index)
-        __shared__ int sIp[A4W * TT_MAX_D];
-        int pv[TT_MAX_D];
-#pragma unroll
-        for (int j = 0; j < TT_MAX_D; ++j) pv[j] = Ip[min(j, d - 2)];
-#pragma unroll
-        for (int j = 0; j < TT_MAX_D; ++j)
-            if (j < d - 1) sIp[lane * TT_MAX_D + j] = pv[j];
-        G[a.goff[d - 1] + e] = fn_value_ix<double, FNS>(P->F, [&](int j) { return j < d - 1 ? sIp[lane * TT_MAX_D + j] : i; });
+        core_last_fiber<FNS>(P, a, G, bid);
         return;
     }
     int u = 0;
@@ -2427,6 +2456,195 @@ template <int FNS = 0>
 static __global__ void __launch_bounds__(A4W) k_cores(const ProbDev *__restrict__ P, CoreArgs a, double *G)
 {
     cores_body<FNS>(P, a, G, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Cores with the pivot rows' recursion run once.  Alg. 4's steps on the pivot
+// rows do not depend on the fiber rows, so k_core_piv runs them once per
+// unfolding (one wavefront, lane t = pivot row t, as in cores_body) and
+// records what every row's step reads; k_cores_t then applies the steps to 64
+// rows per workgroup with each row's T in registers.  The operations and
+// their order are those of cores_body, so the cores are the same bits.
+// Table of unfolding u at tab + u * CT_STRIDE:
+//   At[z * CT_LD + t] = A(rho_t, gam_z) for t < z, and At[0] = A(rho_0, gam_0)
+//   Tr[z * CT_LD + t] = T(i_z, t) before step z, for t < z
+//   Dl[z]             = delta of step z
+// ---------------------------------------------------------------------------
+constexpr int CT_LD = TT_MAX_RANK;
+constexpr int CT_STRIDE = 2 * CT_LD * CT_LD + CT_LD;
+
+template <int FNS>
+__device__ void core_piv_body(const ProbDev *__restrict__ P, const CoreArgs &a, double *tab, int u)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int lane = threadIdx.x, d = P->d, k = u + 1;
+    const KDev &K = P->kd[u];
+    const int rk = a.ranks[k], st = rk + 1, nj = d - k;
+    double *Tp = (double *)smem_raw;            // Tp[t*st + z]: T of pivot row t
+    double *Ap = Tp + rk * st;                  // Ap[t*st + z] = A(rho_t, z)
+    __shared__ int sJ[TT_MAX_RANK * TT_MAX_D], sI[TT_MAX_RANK * TT_MAX_D];
+    copy_to_lds<4, A4W>(sJ, as_global((const int *)K.Jfull), rk * nj);
+    copy_to_lds<4, A4W>(sI, as_global((const int *)K.Ifull), rk * k);
+    wave_sync();
+    const bool piv = lane < rk;
+    if constexpr (FNS == TT_FN_HILBERT) {
+        __shared__ long long sJs[TT_MAX_RANK];
+        long long is = 0;
+        if (piv) {
+            long long js = 0;
+            for (int j = 0; j < nj; ++j) js += sJ[lane * nj + j] + 1;
+            for (int j = 0; j < k; ++j) is += sI[lane * k + j] + 1;
+            sJs[lane] = js;
+        }
+        wave_sync();
+        const double sh = P->F.shift;
+        if (piv)
+            for (int z = 0; z < rk; ++z) Ap[lane * st + z] = 1.0 / ((double)(is + sJs[z]) + sh);
+    } else if (piv) {
+        const int *It = sI + lane * k;
+        for (int z = 0; z < rk; ++z) {
+            const int *Jz = sJ + z * nj;
+            Ap[lane * st + z] = fn_value_ix<double, FNS>(P->F, [&](int j) { return j < k ? It[j] : Jz[j - k]; });
+        }
+    }
+    wave_sync();
+    double *At = tab + (int64_t)u * CT_STRIDE, *Tr = At + CT_LD * CT_LD, *Dl = Tr + CT_LD * CT_LD;
+    const double a11 = Ap[0];
+    if (piv)
+        for (int z = 0; z < rk; ++z) Tp[lane * st + z] = (z == 0) ? Ap[lane * st] / a11 : 0.0;
+    wave_sync();
+    bool singular = false;
+    for (int z = 1; z < rk; ++z) {
+        double dotp = 0.0;
+        if (piv)
+            for (int zz = 0; zz < z; ++zz) dotp = __fma_rn(Tp[lane * st + zz], Ap[zz * st + z], dotp);
+        const double sp = piv ? dotp - Ap[lane * st + z] : 0.0;
+        const double dinv = -__shfl(sp, z, 64);
+        singular |= dinv == 0.0;
+        const double delta = 1.0 / dinv;
+        const double cp = delta * sp;
+        // T(i_z, :) as every row's step reads it, before lane z updates it
+        if (lane < z) Tr[z * CT_LD + lane] = Tp[z * st + lane];
+        if (lane == 0) Dl[z] = delta;
+        wave_sync();
+        for (int zz = 0; zz < z; ++zz) {
+            const double tr = Tp[z * st + zz];
+            if (piv) Tp[lane * st + zz] = __fma_rn(cp, tr, Tp[lane * st + zz]);
+        }
+        if (piv) Tp[lane * st + z] = -cp;
+        wave_sync();
+    }
+    for (int z = 1; z < rk; ++z)
+        if (lane < z) At[z * CT_LD + lane] = Ap[lane * st + z];
+    if (lane == 0) At[0] = a11;
+    // a zero pivot-block residual (delta^{-1} = 0): singular, as in the oracle
+    if (singular && lane == 0) P->S->err = TT_ESINGULAR;
+}
+
+template <int FNS = 0>
+static __global__ void __launch_bounds__(A4W) k_core_piv(const ProbDev *__restrict__ P, CoreArgs a, double *tab)
+{
+    core_piv_body<FNS>(P, a, tab, blockIdx.x);
+}
+
+// Rows of A_k by the recorded steps; RM >= the largest rank (registers per
+// row's T).  Workgroups past the last unfolding's rows evaluate G_d.
+template <int FNS, int RM>
+__device__ void cores_t_body(const ProbDev *__restrict__ P, const CoreArgs &a, double *G,
+                             const double *__restrict__ tab, int bid)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int lane = threadIdx.x, d = P->d;
+    if (bid >= a.rowblocks[a.nk]) {
+        core_last_fiber<FNS>(P, a, G, bid);
+        return;
+    }
+    int u = 0;
+    while (u + 1 < a.nk && bid >= a.rowblocks[u + 1]) ++u;
+    const int k = u + 1;
+    const KDev &K = P->kd[u];
+    const int rk = a.ranks[k], nr = a.ranks[k - 1] * K.nk, nj = d - k;
+    const int i0 = (bid - a.rowblocks[u]) * A4W, i = i0 + lane;
+    const bool act = i < nr;
+    const int p = act ? i / K.nk : 0, ik = act ? i - p * K.nk : 0;
+    __shared__ int sJ[TT_MAX_RANK * TT_MAX_D];
+    copy_to_lds<4, A4W>(sJ, as_global((const int *)K.Jfull), rk * nj);
+    // the lane's prefix, every entry in flight at once
+    int pv[TT_MAX_D];
+    if (k >= 2) {
+        const gptr_t<const int> preI = as_global((const int *)P->kd[u - 1].Ifull) + p * (k - 1);
+#pragma unroll
+        for (int j = 0; j < TT_MAX_D; ++j) pv[j] = preI[min(j, k - 2)];
+    }
+    // x(z): A(row, gam_z).  Hilbert: from the integer index sums, at the step
+    // that reads it; else evaluated up front into LDS (Ab[z*A4W + lane]),
+    // where the function can read the prefix by a runtime index
+    [[maybe_unused]] double *Ab = (double *)smem_raw;
+    [[maybe_unused]] long long ps = ik + 1;
+    __shared__ long long sJs[TT_MAX_RANK];
+    if constexpr (FNS == TT_FN_HILBERT) {
+        if (k >= 2) {
+#pragma unroll
+            for (int j = 0; j < TT_MAX_D; ++j)
+                if (j < k - 1) ps += (long long)pv[j] + 1;
+        }
+        wave_sync();
+        if (lane < rk) {
+            long long js = 0;
+            for (int j = 0; j < nj; ++j) js += sJ[lane * nj + j] + 1;
+            sJs[lane] = js;
+        }
+    } else {
+        __shared__ int sPre[A4W * TT_MAX_D];
+        if (k >= 2) {
+#pragma unroll
+            for (int j = 0; j < TT_MAX_D; ++j)
+                if (j < k - 1) sPre[lane * TT_MAX_D + j] = pv[j];
+        }
+        wave_sync();
+        for (int z = 0; z < rk; ++z) {
+            const int *Jz = sJ + z * nj;
+            Ab[z * A4W + lane] = act ? fn_value_ix<double, FNS>(P->F, [&](int j) {
+                return j < k - 1 ? sPre[lane * TT_MAX_D + j] : (j == k - 1 ? ik : Jz[j - k]);
+            }) : 0.0;
+        }
+    }
+    wave_sync();
+    const double sh = P->F.shift;
+    auto x = [&](int z) -> double {
+        if constexpr (FNS == TT_FN_HILBERT) return act ? 1.0 / ((double)(ps + sJs[z]) + sh) : 0.0;
+        else return Ab[z * A4W + lane];
+    };
+    const double *At = tab + (int64_t)u * CT_STRIDE, *Tr = At + CT_LD * CT_LD, *Dl = Tr + CT_LD * CT_LD;
+    double tb[RM];
+#pragma unroll
+    for (int z = 0; z < RM; ++z) tb[z] = 0.0;
+    tb[0] = x(0) / At[0];
+#pragma unroll
+    for (int z = 1; z < RM; ++z) {
+        if (z < rk) {
+            double dot = 0.0;
+#pragma unroll
+            for (int zz = 0; zz < z; ++zz) dot = __fma_rn(tb[zz], At[z * CT_LD + zz], dot);
+            const double cb = Dl[z] * (dot - x(z));
+#pragma unroll
+            for (int zz = 0; zz < z; ++zz) tb[zz] = __fma_rn(cb, Tr[z * CT_LD + zz], tb[zz]);
+            tb[z] = -cb;
+        }
+    }
+    if (act) {
+        double *row = G + a.goff[u] + (int64_t)i * rk;
+#pragma unroll
+        for (int z = 0; z < RM; ++z)
+            if (z < rk) row[z] = tb[z];
+    }
+}
+
+template <int FNS, int RM>
+static __global__ void __launch_bounds__(A4W) k_cores_t(const ProbDev *__restrict__ P, CoreArgs a, double *G,
+                                                        const double *__restrict__ tab)
+{
+    cores_t_body<FNS, RM>(P, a, G, tab, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------

@@ -389,3 +389,30 @@ def test_fn_values_with_tables_too_large_for_lds(fn_id, n):
     assert np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)) < 1e-15
     a32 = gpu_fn_eval(fn_id, n, idx, fp32=True)
     assert np.max(np.abs(a32.astype(np.float64) - b)) <= 2e-6 * np.max(np.abs(b))
+
+
+@pytest.mark.parametrize("name,n,eps,fn_id,sep_r,caps,grid", [
+    # ranks 24 (T in 32 registers per row), general function
+    ("sep24", [40, 36, 32], 1e-13, FN_SEPSUM, 24, None, [2, 2, 2]),
+    # ranks 40 (64 registers per row), general function
+    ("sep40", [48, 44, 42], 1e-13, FN_SEPSUM, 40, None, [2, 1, 2]),
+    # the Hilbert kernel's entries from integer index sums, ranks 20 and 28
+    ("hil_20_28", [120, 100, 80], 0.0, FN_HILBERT, 0, [20, 28], [2, 2, 2]),
+])
+def test_cores_above_rank_16_match_the_oracle(name, n, eps, fn_id, sep_r, caps, grid):
+    """Above rank 16 the pivot rows' recursion of Alg. 4 runs once per
+    unfolding and the fiber rows apply its recorded steps with their T in
+    registers: the same pivots, status and cores as the oracle, bit for bit."""
+    params = _sepsum_params(n, sep_r, 3) if sep_r else None
+    _say("cores above rank 16", name, n, eps, caps, grid)
+    g = TTCross(n, eps, fn_id, params, seed=1, grid=grid, precision=PREC_FP64)
+    if caps:
+        g.set_rank_caps(caps)
+        o = Oracle(n, eps, fn_id, params, seed=1, rank_caps=caps)
+    else:
+        o = Oracle(n, eps, fn_id, params, seed=1)
+    gs, os_ = g.run(), o.run()
+    assert gs == os_, (gs, os_)
+    assert max(g.ranks()) > 16
+    _assert_same_pivots(g, o)
+    assert np.array_equal(g.cores_flat(), o.cores_flat())
