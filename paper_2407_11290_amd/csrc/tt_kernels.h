@@ -24,6 +24,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <utility>
 
 #include "tt_device.h"
@@ -329,7 +330,10 @@ template <typename V, int FNS>
 __device__ void new_tile(const ProbDev *__restrict__ P, const KTile &K, int u, int R, int C, const KSweep &ks,
                          double &bv, uint64_t &bk, double &bs, V *sm, unsigned long long *rec)
 {
-    const int d = P->d, k = u + 1, tid = threadIdx.x, rk = ks.rk;
+    // (values read from LDS are per-lane to the compiler; the tile's are the
+    // same in every lane, and saying so keeps its branches and descriptor
+    // reads scalar)
+    const int d = P->d, k = u + 1, tid = threadIdx.x, rk = __builtin_amdgcn_readfirstlane(ks.rk);
     // The descriptor and the neighbours' tuple arrays are at hand; the tile's
     // place follows by arithmetic, and its extents (the tile tables) load
     // together with the staging below.
@@ -339,7 +343,8 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KTile &K, int u, i
     const int tp = R / RTp, tt = R - tp * RTp, tq = C / CTq, ttc = C - tq * CTq;
     // row (column) blocks are whole prefixes (suffixes), so whether the tile's
     // rows (columns) were stored follows from the prefix (suffix) index alone
-    const bool rows_old = tp * K.nk < ks.nr_st, cols_old = tq * K.nk1 < ks.nc_st;
+    const bool rows_old = __builtin_amdgcn_readfirstlane(tp * K.nk < ks.nr_st ? 1 : 0) != 0;
+    const bool cols_old = __builtin_amdgcn_readfirstlane(tq * K.nk1 < ks.nc_st ? 1 : 0) != 0;
 #ifdef TT_STAMPS
     if (rec && tid == 0) rec[13] = 1 + (rows_old ? 1 : 0) + (cols_old ? 2 : 0);
 #endif
@@ -364,44 +369,128 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KTile &K, int u, i
     V *Gc = Gr + ntri;                         // W(rho_z, z'), z' < z
     const int TCt = K.TC, rpp = NT / TCt;
     const int tr = tid / TCt, tcol = tid - tr * TCt;
-    if (tid < npre) pre[tid] = Ipre[g.p * npre + tid];
-    if (tid < nsuf) suf[tid] = Jsuf[g.q * nsuf + tid];
+    // one round of loads: the neighbours' tuples, the pivots (rk <= NT: one
+    // per thread) and, for Hilbert, the words of the pivots' tuples, every
+    // value in flight before the first is stored (a store waits for its load,
+    // and loads written after it would start only then)
+    static_assert(TT_MAX_RANK <= NT && TT_MAX_D <= NT, "one pivot and one tuple word per thread");
+    int prev = 0, sufv = 0;
+    if (tid < npre) prev = Ipre[g.p * npre + tid];
+    if (tid < nsuf) sufv = Jsuf[g.q * nsuf + tid];
+    const bool zt = tid < rk;
+    int rz = 0, gz = 0;
+    double pz = 0.0;
+    if (zt) {
+        rz = rho[tid];
+        gz = gam[tid];
+        pz = piv[tid];
+    }
     // Hilbert entries depend on the integer index sum only: the pivots' tuple
-    // sums replace the tuples
+    // sums replace the tuples (J_{>k} for new rows, I_{<=k} for new columns)
     __shared__ long long s_is[TT_MAX_RANK], s_js[TT_MAX_RANK];
-    for (int z = tid; z < rk; z += NT) {
-        s_rho[z] = rho[z];
-        s_gam[z] = gam[z];
-        s_piv[z] = (V)piv[z];
+    [[maybe_unused]] long long is = 0, js = 0;
+    if constexpr (FNS == TT_FN_HILBERT) {
+        int wj[TT_MAX_D], wi[TT_MAX_D];
+        if (zt && !rows_old) {
+#pragma unroll
+            for (int j = 0; j < TT_MAX_D; ++j) wj[j] = Jfull[tid * nj + min(j, nj - 1)];
+        }
+        if (zt && !cols_old) {
+#pragma unroll
+            for (int j = 0; j < TT_MAX_D; ++j) wi[j] = Ifull[tid * k + min(j, k - 1)];
+        }
+        if (zt && !rows_old) {
+#pragma unroll
+            for (int j = 0; j < TT_MAX_D; ++j)
+                if (j < nj) js += wj[j] + 1;
+        }
+        if (zt && !cols_old) {
+#pragma unroll
+            for (int j = 0; j < TT_MAX_D; ++j)
+                if (j < k) is += wi[j] + 1;
+        }
+    }
+    if (tid < npre) pre[tid] = prev;
+    if (tid < nsuf) suf[tid] = sufv;
+    if (zt) {
+        s_rho[tid] = rz;
+        s_gam[tid] = gz;
+        s_piv[tid] = (V)pz;
         if constexpr (FNS == TT_FN_HILBERT) {
-            long long is = 0, js = 0;
-            if (!rows_old)
-                for (int j = 0; j < nj; ++j) js += Jfull[z * nj + j] + 1;
-            if (!cols_old)
-                for (int j = 0; j < k; ++j) is += Ifull[z * k + j] + 1;
-            s_is[z] = is;
-            s_js[z] = js;
+            s_is[tid] = is;
+            s_js[tid] = js;
         }
     }
     __syncthreads();
     TT_STAMP(rec, 3);
-    // the tile's positions, and its row and column pivot masks (needed by the
-    // entries only) with the raw factors below
+    // the tile's positions
     g.row0 = g.p * K.nk + g.ik0;
     g.col0 = g.q * K.nk1 + g.ik10;
-    const int cpv = (tcol < g.ncols) ? as_global((const uint8_t *)K.cpiv)[g.col0 + tcol] : 1;
-    for (int ii = tid; ii < g.nrows; ii += NT) s_rp[ii] = as_global((const uint8_t *)K.rpiv)[g.row0 + ii];
-    for (int jj = tid; jj < g.ncols; jj += NT) s_cp[jj] = as_global((const uint8_t *)K.cpiv)[g.col0 + jj];
-    // raw factors: frozen entries, or the generating function at the skeleton
-    // (the frozen factors load UL per thread at once: a loop that stored each
-    // value before loading the next would wait a round trip per pass)
+    // raw factors: frozen entries, or the generating function at the
+    // skeleton.  One round of loads: the tile's pivot masks, the first pass
+    // of the frozen factors of stored rows (columns) and of the pivot-block
+    // triangle that new rows (columns) need, all in flight before the first
+    // is stored; tiles with more frozen values take further passes of UL
+    // loads per thread.
+    static_assert(TT_TILE_ROWS_MAX <= NT, "one tile row and one tile column per thread");
     constexpr int UL = 4;
+    const gptr_t<const uint8_t> rpiv = as_global((const uint8_t *)K.rpiv), cpiv = as_global((const uint8_t *)K.cpiv);
+    const int nw = rk * g.nrows, nu = rk * g.ncols;
+    const int tzp = tid / max(rk, 1), tz = tid - tzp * rk;  // the thread's triangle entry (zp, z) in the first pass
+    const bool tri_ok = tid < rk * rk && tzp < tz;
+    // The loads of the round do not depend on the tile's kind, so that no
+    // branch separates them (a branch between loads can make the later ones
+    // wait for the earlier): a value the kind does not need is read from the
+    // first pivot's entry, which no search workgroup writes, and dropped.
+    const int64_t spare = rk > 0 ? (int64_t)s_rho[0] * ld + s_gam[0] : 0;
+    const bool use_w = rows_old && nw > 0, use_u = cols_old && nu > 0;
+    const uint8_t rpb = rpiv[g.row0 + min(tid, g.nrows - 1)];
+    const uint8_t cpb = cpiv[g.col0 + min(tid, g.ncols - 1)];
+    V xw[UL], xu[UL];
+#pragma unroll
+    for (int j = 0; j < UL; ++j) {
+        const int e = max(min(tid + j * NT, nw - 1), 0);
+        const int z = e / g.nrows, ii = e - z * g.nrows;
+        xw[j] = E[use_w ? (int64_t)(g.row0 + ii) * ld + s_gam[z] : spare];
+    }
+#pragma unroll
+    for (int j = 0; j < UL; ++j) {
+        const int e = max(min(tid + j * NT, nu - 1), 0);
+        const int z = e / g.ncols, jj = e - z * g.ncols;
+        xu[j] = E[use_u ? (int64_t)s_rho[z] * ld + g.col0 + jj : spare];
+    }
+    // pivot-block entries (rho_zp, gamma_z) and (rho_z, gamma_zp)
+    const int ta = max(min(tzp, rk - 1), 0), tb = max(min(tz, rk - 1), 0);
+    const V tgr = E[(int64_t)s_rho[ta] * ld + s_gam[tb]];
+    const V tgc = E[(int64_t)s_rho[tb] * ld + s_gam[ta]];
+    if (tid < g.nrows) s_rp[tid] = rpb;
+    if (tid < g.ncols) s_cp[tid] = cpb;
     if (rows_old) {
-        for (int e0 = tid; e0 < rk * g.nrows; e0 += UL * NT) {
+#pragma unroll
+        for (int j = 0; j < UL; ++j) {
+            const int e = tid + j * NT;
+            const int z = e / g.nrows, ii = e - z * g.nrows;
+            if (e < nw) Wt[z * TRm + ii] = xw[j];
+        }
+    } else if (tri_ok) {
+        Gr[tri(tzp, tz)] = tgr / s_piv[tzp];
+    }
+    if (cols_old) {
+#pragma unroll
+        for (int j = 0; j < UL; ++j) {
+            const int e = tid + j * NT;
+            const int z = e / g.ncols, jj = e - z * g.ncols;
+            if (e < nu) Ut[z * TCm + jj] = xu[j] / s_piv[z];
+        }
+    } else if (tri_ok) {
+        Gc[tri(tzp, tz)] = tgc;
+    }
+    if (rows_old) {
+        for (int e0 = tid + UL * NT; e0 < nw; e0 += UL * NT) {
             V x[UL];
 #pragma unroll
             for (int j = 0; j < UL; ++j) {
-                const int e = min(e0 + j * NT, rk * g.nrows - 1);
+                const int e = min(e0 + j * NT, nw - 1);
                 const int z = e / g.nrows, ii = e - z * g.nrows;
                 x[j] = E[(int64_t)(g.row0 + ii) * ld + s_gam[z]];
             }
@@ -409,11 +498,11 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KTile &K, int u, i
             for (int j = 0; j < UL; ++j) {
                 const int e = e0 + j * NT;
                 const int z = e / g.nrows, ii = e - z * g.nrows;
-                if (e < rk * g.nrows) Wt[z * TRm + ii] = x[j];
+                if (e < nw) Wt[z * TRm + ii] = x[j];
             }
         }
     } else {
-        for (int e = tid; e < rk * rk; e += NT) {
+        for (int e = tid + NT; e < rk * rk; e += NT) {
             const int zp = e / rk, z = e - zp * rk;
             if (zp < z) Gr[tri(zp, z)] = E[(int64_t)s_rho[zp] * ld + s_gam[z]] / s_piv[zp];
         }
@@ -437,11 +526,11 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KTile &K, int u, i
         }
     }
     if (cols_old) {
-        for (int e0 = tid; e0 < rk * g.ncols; e0 += UL * NT) {
+        for (int e0 = tid + UL * NT; e0 < nu; e0 += UL * NT) {
             V x[UL];
 #pragma unroll
             for (int j = 0; j < UL; ++j) {
-                const int e = min(e0 + j * NT, rk * g.ncols - 1);
+                const int e = min(e0 + j * NT, nu - 1);
                 const int z = e / g.ncols, jj = e - z * g.ncols;
                 x[j] = E[(int64_t)s_rho[z] * ld + g.col0 + jj];
             }
@@ -449,11 +538,11 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KTile &K, int u, i
             for (int j = 0; j < UL; ++j) {
                 const int e = e0 + j * NT;
                 const int z = e / g.ncols, jj = e - z * g.ncols;
-                if (e < rk * g.ncols) Ut[z * TCm + jj] = x[j] / s_piv[z];
+                if (e < nu) Ut[z * TCm + jj] = x[j] / s_piv[z];
             }
         }
     } else {
-        for (int e = tid; e < rk * rk; e += NT) {
+        for (int e = tid + NT; e < rk * rk; e += NT) {
             const int zp = e / rk, z = e - zp * rk;
             if (zp < z) Gc[tri(zp, z)] = E[(int64_t)s_rho[z] * ld + s_gam[zp]];
         }
@@ -478,6 +567,8 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KTile &K, int u, i
     }
     __syncthreads();
     TT_STAMP(rec, 4);
+    // the thread's entry column's pivot mask
+    const int cpv = (tcol < g.ncols) ? s_cp[tcol] : 1;
     // chains as triangular solves; each factor sees the same operations in
     // the same order as the written recursion, so both forms give the same
     // bits.  Up to rank 16 a lane group per row (column) with row broadcasts;
@@ -625,6 +716,10 @@ __device__ void sweep_body(const ProbDev *__restrict__ P, const ProbState *S, in
             if (rec && rec[10] == 0) nrec = rec;          // the workgroup's first new tile
             TT_STAMP(nrec, 2);
 #endif
+            // the unit is the workgroup's: uniform
+            u = __builtin_amdgcn_readfirstlane(u);
+            R = __builtin_amdgcn_readfirstlane(R);
+            C = __builtin_amdgcn_readfirstlane(C);
             const KTile &K = P->kt[u];
             new_tile<V, FNS>(P, K, u, R, C, ks[u], bv, bk, bs, (V *)smem_raw, nrec);
             TT_STAMP_ADD(rec, 10, 1);
