@@ -113,7 +113,8 @@ typedef struct tt_options {
                                    library's default */
     int32_t tile_cols;          /* columns per workgroup tile, 1..64 (rounded up to a power of
                                    two); 0 as for tile_rows */
-    int32_t lookahead;          /* sweeps queued ahead of the host's stop check (default 2) */
+    int32_t lookahead;          /* sweeps queued ahead of the host's stop check (default 2;
+                                   tt_batch_run queues one round more) */
     int32_t profile;            /* 1: time every search launch with HIP events (stats below) */
     void *stream;               /* hipStream_t to run on; NULL = a stream owned by the handle */
     int32_t verify;             /* sampled-error check after the run (Sec. 5), on an independent

@@ -33,6 +33,12 @@ class Engine {
 public:
     int cap = 0;
     hipStream_t stream = nullptr;
+    // sweep rounds queued beyond each problem's own lookahead: tt_batch_run
+    // queues one more (its rounds cover many slots, and the host's pass over
+    // their mirrors comes later after a round than a single solve's check;
+    // surplus rounds find the stop flag set and return); the server none
+    // (at a light load one more round only delays the next request's setup)
+    int extra_ahead = 0;
 
     ~Engine();
     void release();

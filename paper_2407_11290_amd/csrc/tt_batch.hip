@@ -335,13 +335,13 @@ int Engine::tick(std::vector<int> *completed)
         }
     if (!new32.empty()) { int st = launch_setup<float>(new32); if (st) return st; }
     if (!new64.empty()) { int st = launch_setup<double>(new64); if (st) return st; }
-    // 3. queue sweep rounds up to the lookahead
+    // 3. queue sweep rounds up to the lookahead (and extra_ahead more)
     bool launched_any = false;
     for (;;) {
         std::vector<int> r32, r64;
         for (Slot &s : slots) {
             if (s.phase != Slot::SWEEP || s.stop_seen) continue;
-            const int L = std::max(1, s.Q->opt.lookahead);
+            const int L = std::max(1, s.Q->opt.lookahead) + extra_ahead;
             if (s.launched < s.done + L && s.launched < s.Q->max_sweeps) (s.Q->fp32 ? r32 : r64).push_back(s.idx);
         }
         if (r32.empty() && r64.empty()) break;
@@ -471,6 +471,7 @@ extern "C" int tt_batch_run(tt_cross_h *hs, int count, void *hip_stream)
     static thread_local Engine *engp = nullptr;
     if (!engp) engp = new Engine();
     Engine &eng = *engp;
+    eng.extra_ahead = 1;
     if (eng.cap < count || eng.stream != stream) {
         const int st = eng.init(std::max(count, eng.cap), stream);
         if (st) return st;
