@@ -39,6 +39,11 @@ public:
     // surplus rounds find the stop flag set and return); the server none
     // (at a light load one more round only delays the next request's setup)
     int extra_ahead = 0;
+    // whether the last tick launched work or finished a slot.  A caller that
+    // finds it false waits a little before the next tick: back-to-back ticks
+    // make runtime calls (event and stream queries) that compete with the
+    // launches they are waiting for
+    bool busy_tick = false;
 
     ~Engine();
     void release();

@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <thread>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -293,6 +294,7 @@ int Engine::launch_cores(std::vector<int> &ids)
 
 int Engine::tick(std::vector<int> *completed)
 {
+    busy_tick = false;
     // 1. read the mirrors: progress and stop flags of sweeping slots
     std::vector<int> to_cores;
     bool any_sweeping = false;
@@ -322,6 +324,7 @@ int Engine::tick(std::vector<int> *completed)
         }
     }
     if (!to_cores.empty()) {
+        busy_tick = true;
         int st = launch_cores(to_cores);
         if (st) return st;
     }
@@ -349,6 +352,7 @@ int Engine::tick(std::vector<int> *completed)
         if (!r64.empty()) { int st = launch_sweep<double>(r64); if (st) return st; }
         launched_any = true;
     }
+    if (launched_any) busy_tick = true;
     // 4. completions
     for (Slot &s : slots) {
         if (s.phase != Slot::CORES) continue;
@@ -356,6 +360,7 @@ int Engine::tick(std::vector<int> *completed)
         if (q == hipErrorNotReady) continue;
         if (q != hipSuccess) return set_err(TT_EDEVICE, "batch: %s", hipGetErrorString(q));
         finish_slot(s);
+        busy_tick = true;
         if (completed) completed->push_back(s.idx);
     }
     // 5. nothing queued that could still report progress: the stream is idle
@@ -510,6 +515,7 @@ extern "C" int tt_batch_run(tt_cross_h *hs, int count, void *hip_stream)
         while (!eng.idle()) {
             st = eng.tick(nullptr);
             if (st) return fail(st);
+            if (!eng.busy_tick) std::this_thread::sleep_for(std::chrono::microseconds(20));
         }
         he = hipEventRecord(ev.b, stream);
         if (he == hipSuccess) he = hipStreamSynchronize(stream);

@@ -276,6 +276,7 @@ private:
     void loop()
     {
         std::vector<int> done;
+        bool admitted = false;
         for (;;) {
             {
                 std::unique_lock<std::mutex> g(mu_);
@@ -286,6 +287,7 @@ private:
                 // admit in arrival order while slots and budget allow; the
                 // oldest request may create a problem object, later ones
                 // (within a window) may pass it on idle pooled objects
+                admitted = false;
                 int scanned = 0;
                 for (auto it = queue_.begin(); it != queue_.end() && eng_.free_slots() > 0 && scanned < 256;
                      ++scanned) {
@@ -311,11 +313,15 @@ private:
                     r->state = 1;
                     r->t_admit = wall_s();
                     ++running_;
+                    admitted = true;
                     it = queue_.erase(it);
                 }
             }
             done.clear();
             const int st = eng_.tick(&done);
+            // nothing admitted, launched or finished: wait a little (the
+            // engine's runtime queries would compete with its launches)
+            if (!st && !eng_.busy_tick && !admitted) std::this_thread::sleep_for(std::chrono::microseconds(20));
             std::lock_guard<std::mutex> g(mu_);
             if (st) {
                 loop_err_ = st;
