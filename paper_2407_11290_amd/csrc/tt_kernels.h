@@ -192,6 +192,13 @@ __device__ void stored_tile_wave(const KTile &K, const KSweep &ks, const TileGeo
     const bool apply = ks.apply != 0;
     const int64_t urow = apply ? ks.arho : g.row0;   // any valid row when nothing is applied
     const int wcol = apply ? ks.agam : col;
+    // the column's mask and pivot-row factor, once per tile (reloading them,
+    // and dividing by the pivot, in every batch cost the tall tiles of large
+    // superblocks 7-10% of a solve)
+    const int cp = cpiv[col];
+    const V ue = E[urow * ld + col];
+    const bool live = colok && !cp;
+    const V u = apply ? ue / (V)ks.apiv : (V)0;
     // per 64 tile rows: lane l fetches row l's mask and pivot-column factor in
     // one instruction each, and they reach the other lanes by shuffles; every
     // lane runs the same iterations so that the shuffles see all lanes (a
@@ -202,16 +209,12 @@ __device__ void stored_tile_wave(const KTile &K, const KSweep &ks, const TileGeo
         const int rpl = rpiv[rrow];
         const V wl = E[(int64_t)rrow * ld + wcol];
         for (int base = 0; base < nch; base += B * rpw) {
-            const int cp = cpiv[col];
-            const V ue = E[urow * ld + col];
             V xv[B];
 #pragma unroll
             for (int b = 0; b < B; ++b) {
                 const int ii = min(base + tr + b * rpw, nch - 1);
                 xv[b] = E[(int64_t)(g.row0 + c0 + ii) * ld + col];
             }
-            const bool live = colok && !cp;
-            const V u = apply ? ue / (V)ks.apiv : (V)0;
 #pragma unroll
             for (int b = 0; b < B; ++b) {
                 const int ii = base + tr + b * rpw;
