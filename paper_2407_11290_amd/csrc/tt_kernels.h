@@ -212,8 +212,8 @@ __device__ void stored_tile_wave(const KTile &K, const KSweep &ks, const TileGeo
             V xv[B];
 #pragma unroll
             for (int b = 0; b < B; ++b) {
-                const int ii = min(base + tr + b * rpw, nch - 1);
-                xv[b] = E[(int64_t)(g.row0 + c0 + ii) * ld + col];
+                const int ii = base + tr + b * rpw;
+                xv[b] = (ii < nch) ? E[(int64_t)(g.row0 + c0 + ii) * ld + col] : (V)0;
             }
 #pragma unroll
             for (int b = 0; b < B; ++b) {
