@@ -24,7 +24,6 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
-#include <type_traits>
 #include <utility>
 
 #include "tt_device.h"
@@ -75,18 +74,56 @@ __device__ inline void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// A 64-bit value moved by a DPP control across the rows ROWS selects; a lane
+// whose source lies outside its row (or in a row not written) keeps its own.
+template <int CTRL, int ROWS> __device__ inline uint64_t dpp64(uint64_t x)
+{
+    const int lo = __builtin_amdgcn_update_dpp((int)x, (int)x, CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(x >> 32), (int)(x >> 32), CTRL, ROWS, 0xf, false);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+template <int CTRL, int ROWS> __device__ inline void best_step(double &v, uint64_t &key, double &sv)
+{
+    const double ov = __longlong_as_double((long long)dpp64<CTRL, ROWS>((uint64_t)__double_as_longlong(v)));
+    const uint64_t ok = dpp64<CTRL, ROWS>(key);
+    const double osv = __longlong_as_double((long long)dpp64<CTRL, ROWS>((uint64_t)__double_as_longlong(sv)));
+    if (better(ov, ok, v, key)) { v = ov; key = ok; sv = osv; }
+}
+
+__device__ inline uint64_t read_lane64(uint64_t x, int l)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)x, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(x >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Wavefront-wide best (max |value|, lowest key), in every lane.  The order
+// is total (keys are distinct), so any reduction order gives the same
+// winner: DPP row shifts by 1, 2, 4, 8 leave each 16-lane row's best in its
+// lane 15, the row broadcasts of lanes 15 and 31 carry it to lane 63, and
+// lane 63's value goes to every lane (register moves instead of the LDS
+// round trips of a shuffle butterfly).  Every lane must be active.
+__device__ inline void wave_best(double &v, uint64_t &key, double &sv)
+{
+    best_step<0x111, 0xf>(v, key, sv);      // row_shr:1
+    best_step<0x112, 0xf>(v, key, sv);      // row_shr:2
+    best_step<0x114, 0xf>(v, key, sv);      // row_shr:4
+    best_step<0x118, 0xf>(v, key, sv);      // row_shr:8
+    best_step<0x142, 0xa>(v, key, sv);      // row_bcast:15 into rows 1 and 3
+    best_step<0x143, 0xc>(v, key, sv);      // row_bcast:31 into rows 2 and 3
+    v = __longlong_as_double((long long)read_lane64((uint64_t)__double_as_longlong(v), 63));
+    key = read_lane64(key, 63);
+    sv = __longlong_as_double((long long)read_lane64((uint64_t)__double_as_longlong(sv), 63));
+}
+
 // Workgroup-wide (max |value|, lowest key) reduction carrying the signed
 // value; the result is valid in every thread.
 __device__ inline void block_best(double &v, uint64_t &key, double &sv)
 {
     __shared__ double s_v[NT / 64], s_sv[NT / 64];
     __shared__ uint64_t s_k[NT / 64];
-    for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(v, off, 64);
-        const unsigned long long ok = __shfl_xor((unsigned long long)key, off, 64);
-        const double osv = __shfl_xor(sv, off, 64);
-        if (better(ov, ok, v, key)) { v = ov; key = ok; sv = osv; }
-    }
+    wave_best(v, key, sv);
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     __syncthreads();
     if (l == 0) { s_v[w] = v; s_k[w] = key; s_sv[w] = sv; }
@@ -142,16 +179,6 @@ __device__ inline TileGeom tile_geom(const KTile &K, int u, int R, int C)
     g.row0 = g.p * K.nk + g.ik0;
     g.col0 = g.q * K.nk1 + g.ik10;
     return g;
-}
-
-__device__ inline void wave_best(double &v, uint64_t &key, double &sv)
-{
-    for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(v, off, 64);
-        const unsigned long long ok = __shfl_xor((unsigned long long)key, off, 64);
-        const double osv = __shfl_xor(sv, off, 64);
-        if (better(ov, ok, v, key)) { v = ov; key = ok; sv = osv; }
-    }
 }
 
 // Workgroup-wide (max |value|, lowest key) reduction whose result is valid
