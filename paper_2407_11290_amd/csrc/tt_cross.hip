@@ -460,8 +460,9 @@ int Problem::allocate()
         } else if ((st = dalloc(&K.E, (size_t)K.rowcap * K.ld * w)) != TT_OK) {
             return st;
         }
-        if ((st = dalloc((void **)&K.rpiv, K.rowcap)) != TT_OK) return st;
-        if ((st = dalloc((void **)&K.cpiv, K.colcap)) != TT_OK) return st;
+        // whole 32-bit words: the search reads row masks as aligned words
+        if ((st = dalloc((void **)&K.rpiv, ((size_t)K.rowcap + 3) & ~(size_t)3)) != TT_OK) return st;
+        if ((st = dalloc((void **)&K.cpiv, ((size_t)K.colcap + 3) & ~(size_t)3)) != TT_OK) return st;
         if ((st = dalloc((void **)&K.Ifull, sizeof(int) * rk * k)) != TT_OK) return st;
         if ((st = dalloc((void **)&K.Jfull, sizeof(int) * rk * (d - k))) != TT_OK) return st;
         if ((st = dalloc((void **)&K.rho, sizeof(int) * rk)) != TT_OK) return st;

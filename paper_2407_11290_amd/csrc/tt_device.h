@@ -216,7 +216,7 @@ struct KDev {
     const int *rt_start, *rt_len, *rt_blk;    // per row tile within a prefix
     const int *ct_start, *ct_len, *ct_blk;    // per column tile within a suffix
     void *E;                      // residual / frozen factors, rowcap x colcap, row-major, pitch ld
-    uint8_t *rpiv, *cpiv;         // z+1 on the row / column of pivot z, else 0
+    uint8_t *rpiv, *cpiv;         // z+1 on the row / column of pivot z, else 0 (padded to whole words)
     int *Ifull;                   // I_{<=k}: rcap tuples of k indices
     int *Jfull;                   // J_{>k}: rcap tuples of d-k indices
     int *rho, *gam;               // pivot positions in the superblock

@@ -198,68 +198,94 @@ __device__ inline void block_best_t0(double &v, uint64_t &key, double &sv)
 }
 
 // Stored residuals, one wavefront per tile: apply the newest pivot (if any)
-// and search.  Every load of a batch -- the column's pivot mask, the pivot
-// row's entry (its U factor before the division) and the tile entries -- is
-// issued before any of them is used, from addresses that are always valid
-// (clamped), so that a batch costs one round trip; the rows' masks and W
-// factors of a 64-row chunk are in flight with the first batch.
+// and search, in batches of B * (64 / TC) rows.  A 64-row chunk's first
+// batch goes out in one round of loads with the chunk's row masks and W
+// factors (and, for the first chunk, the column's mask and pivot-row entry),
+// from addresses that are always valid, and nothing loaded is used before
+// the round is issued: each batch costs one round trip.  A lane fetches its
+// row's mask as the aligned 32-bit word holding it (the mask arrays are
+// padded to whole words) and the byte is taken out after the shuffle, so
+// no conversion of a loaded value stands between the loads.
 template <typename V, int B>
-__device__ void stored_tile_wave(const KTile &K, const KSweep &ks, const TileGeom &g, double &bv, uint64_t &bk,
+__device__ void stored_tile_wave(const KTile &K, const KSweep &ks, const TileGeom &gv, double &bv, uint64_t &bk,
                                  double &bs)
 {
+    // the tile's extents are the wavefront's: scalar loop counts
+    TileGeom g = gv;
+    g.nrows = __builtin_amdgcn_readfirstlane(gv.nrows);
+    g.ncols = __builtin_amdgcn_readfirstlane(gv.ncols);
+    g.row0 = __builtin_amdgcn_readfirstlane(gv.row0);
+    g.col0 = __builtin_amdgcn_readfirstlane(gv.col0);
     const int lane = threadIdx.x & 63;
     const int TC = K.TC, rpw = 64 / TC;
     const int tr = lane / TC, tcol = lane - tr * TC;
     const bool colok = tcol < g.ncols;
     const gptr_t<V> E = as_global((V *)K.E);
-    const gptr_t<const uint8_t> rpiv = as_global((const uint8_t *)K.rpiv);
+    const gptr_t<const uint32_t> rpiv_w = as_global((const uint32_t *)K.rpiv);
     const gptr_t<const uint8_t> cpiv = as_global((const uint8_t *)K.cpiv);
     const int64_t ld = K.ld;
     const int col = g.col0 + (colok ? tcol : 0);
     const bool apply = ks.apply != 0;
     const int64_t urow = apply ? ks.arho : g.row0;   // any valid row when nothing is applied
     const int wcol = apply ? ks.agam : col;
+    const V apiv = apply ? (V)ks.apiv : (V)1;
+    // chunk c0's row data: lane l holds row c0 + l's mask word and factor
+    uint32_t rpl;
+    V wl;
+    auto chunk_loads = [&](int c0, int nch) {
+        const int rrow = g.row0 + c0 + (lane < nch ? lane : 0);
+        rpl = rpiv_w[rrow >> 2];
+        wl = E[(int64_t)rrow * ld + wcol];
+    };
+    V xv[B];
+    auto batch_loads = [&](int c0, int nch, int base) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int ii = base + tr + b * rpw;
+            xv[b] = (ii < nch) ? E[(int64_t)(g.row0 + c0 + ii) * ld + col] : (V)0;
+        }
+    };
     // the column's mask and pivot-row factor, once per tile (reloading them,
     // and dividing by the pivot, in every batch cost the tall tiles of large
     // superblocks 7-10% of a solve)
     const int cp = cpiv[col];
     const V ue = E[urow * ld + col];
+    int nch = min(64, g.nrows);
+    chunk_loads(0, nch);
+    batch_loads(0, nch, 0);
     const bool live = colok && !cp;
-    const V u = apply ? ue / (V)ks.apiv : (V)0;
-    // per 64 tile rows: lane l fetches row l's mask and pivot-column factor in
-    // one instruction each, and they reach the other lanes by shuffles; every
-    // lane runs the same iterations so that the shuffles see all lanes (a
-    // value is used only for rows below nch, whose lanes loaded it)
-    for (int c0 = 0; c0 < g.nrows; c0 += 64) {
-        const int nch = min(64, g.nrows - c0);
-        const int rrow = g.row0 + c0 + (lane < nch ? lane : 0);
-        const int rpl = rpiv[rrow];
-        const V wl = E[(int64_t)rrow * ld + wcol];
-        for (int base = 0; base < nch; base += B * rpw) {
-            V xv[B];
+    const V u = apply ? ue / apiv : (V)0;
+    // every lane runs the same iterations so that the shuffles see all lanes
+    // (a value is used only for rows below nch, whose lanes loaded it)
+    int c0 = 0, base = 0;
+    while (true) {
 #pragma unroll
-            for (int b = 0; b < B; ++b) {
-                const int ii = base + tr + b * rpw;
-                xv[b] = (ii < nch) ? E[(int64_t)(g.row0 + c0 + ii) * ld + col] : (V)0;
-            }
-#pragma unroll
-            for (int b = 0; b < B; ++b) {
-                const int ii = base + tr + b * rpw;
-                const int rp = __shfl(rpl, ii & 63, 64);
-                const V w = __shfl(wl, ii & 63, 64);
-                if (ii < nch && live && !rp) {
-                    const int row = g.row0 + c0 + ii;
-                    V x = xv[b];
-                    if (apply) {
-                        x = vfma<V>(-w, u, x);
-                        E[(int64_t)row * ld + col] = x;
-                    }
-                    const double ax = (double)fabs(x);
-                    const uint64_t key = ((uint64_t)row << 32) | (uint32_t)col;
-                    if (better(ax, key, bv, bk)) { bv = ax; bk = key; bs = (double)x; }
+        for (int b = 0; b < B; ++b) {
+            const int ii = base + tr + b * rpw;
+            const int row = g.row0 + c0 + ii;
+            const uint32_t rw = (uint32_t)__shfl((int)rpl, ii & 63, 64);
+            const int rp = (rw >> ((row & 3) * 8)) & 0xff;
+            const V w = __shfl(wl, ii & 63, 64);
+            if (ii < nch && live && !rp) {
+                V x = xv[b];
+                if (apply) {
+                    x = vfma<V>(-w, u, x);
+                    E[(int64_t)row * ld + col] = x;
                 }
+                const double ax = (double)fabs(x);
+                const uint64_t key = ((uint64_t)row << 32) | (uint32_t)col;
+                if (better(ax, key, bv, bk)) { bv = ax; bk = key; bs = (double)x; }
             }
         }
+        base += B * rpw;
+        if (base >= nch) {
+            c0 += 64;
+            if (c0 >= g.nrows) break;
+            nch = min(64, g.nrows - c0);
+            base = 0;
+            chunk_loads(c0, nch);
+        }
+        batch_loads(c0, nch, base);
     }
 }
 
@@ -766,7 +792,11 @@ __device__ void sweep_body(const ProbDev *__restrict__ P, const ProbState *S, in
                 int u = 0;
                 while (u + 1 < nk && st >= sh.soff[u + 1]) ++u;
                 const int idx = st - sh.soff[u], CTs = sh.CTs[u];
-                const int R = idx / CTs, C = idx - R * CTs;
+                // the tile is the wavefront's (values read from LDS are
+                // per-lane to the compiler): uniform geometry and loop counts
+                u = __builtin_amdgcn_readfirstlane(u);
+                const int R = __builtin_amdgcn_readfirstlane(idx / CTs);
+                const int C = __builtin_amdgcn_readfirstlane(idx - R * CTs);
                 const KTile &K = P->kt[u];
                 const TileGeom g = tile_geom(K, u, R, C);
 #ifdef TT_STAMPS

@@ -147,6 +147,10 @@ def test_hilbert3d_n32_bit_exact(seed):
     ([13, 17, 11, 19], [1, 1, 1, 1], (32, 64)),
     ([5, 40, 3, 7, 9], [1, 4, 1, 1, 2], (16, 16)),
     ([2, 2, 2, 2, 2, 2, 2, 2], [1] * 8, (0, 0)),
+    # tiles taller than 64 rows: stored tiles in several 64-row chunks, the last ragged
+    ([13, 17, 11, 19], [1, 1, 1, 1], (128, 32)),
+    ([13, 17, 11, 19], [1, 1, 1, 1], (100, 8)),
+    ([5, 40, 3, 7, 9], [1, 1, 1, 1, 1], (192, 16)),
 ])
 def test_ragged_tiles_and_grids_bit_exact(n, grid, tiles):
     """Several tiles per superblock with ragged tails, and uneven subtensor blocks."""
