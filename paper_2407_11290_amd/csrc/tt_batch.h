@@ -22,6 +22,7 @@ struct Slot {
     bool stop_seen = false;       // its stop flag reached the host
     bool idle_done = false;       // stream idle with nothing left to run for it
     int rub[TT_MAX_D + 1] = {0};  // rank bounds for the next round it gets
+    int rst[TT_MAX_D + 1] = {0};  // bounds on the ranks its stored tiles were made with
     hipEvent_t ev = nullptr;      // completes when its cores and state are on the host
     double t_admit = 0, t_done = 0;
     int64_t verify_R = 0;         // samples of its sampled-error check (0: none)

@@ -105,7 +105,7 @@ int Engine::admit(Problem *Q, void *user)
     s.user = user;
     s.phase = Slot::SETUP;
     s.t_admit = now_s();
-    for (int k = 0; k <= Q->d; ++k) s.rub[k] = 1;
+    for (int k = 0; k <= Q->d; ++k) s.rub[k] = s.rst[k] = 1;
     s.verify_R = Q->verify_samples();
     s.can_escalate = Q->auto_fp32();
     Q->sampled_err = -1.0;
@@ -202,17 +202,23 @@ template <typename V> int Engine::launch_sweep(std::vector<int> &ids)
             Slot &s = slots[ids[c0 + a]];
             const Problem &Q = *s.Q;
             const int d = Q.d;
+            // work units as the single-problem launch counts them: new tiles
+            // one per workgroup, stored tiles four (the kernel strides over
+            // the exact count, so a wrong estimate costs time only)
             int tot = 0;
             for (int u = 0; u < d - 1; ++u) {
                 const int k = u + 1;
                 const KDev &K = Q.hP.kd[u];
-                tot += s.rub[k - 1] * K.RTp * s.rub[k + 1] * K.CTq;
+                const int all = s.rub[k - 1] * K.RTp * s.rub[k + 1] * K.CTq;
+                const int st = std::min(all, s.rst[k - 1] * K.RTp * s.rst[k + 1] * K.CTq);
+                tot += (all - st) + (st + NT / 64 - 1) / (NT / 64);
                 lds = std::max(lds, sweep_lds_bytes(s.rub[k], K.TR, K.TC, sizeof(V)));
             }
             bm.p[a] = (uint16_t)s.idx;
             bm.boff[a] = off;
             off += std::max(1, std::min(tot, Q.sweep_grid_cap));
             ++s.launched;
+            for (int k = 0; k <= d; ++k) s.rst[k] = s.rub[k];
             for (int k = 1; k <= d - 1; ++k) s.rub[k] = std::min(s.rub[k] + 1, Q.rc[k]);
         }
         bm.boff[na] = off;
@@ -319,8 +325,13 @@ int Engine::tick(std::vector<int> *completed)
             to_cores.push_back(s.idx);
         } else {
             any_sweeping = true;
-            for (int k = 1; k <= s.Q->d - 1; ++k)
-                s.rub[k] = std::min(s.Q->rc[k], __atomic_load_n(&h.r[k], __ATOMIC_RELAXED) + (s.launched - s.done));
+            // the next round's shapes have at most the committed ranks plus one
+            // per queued round; its stored tiles, one round fewer
+            for (int k = 1; k <= s.Q->d - 1; ++k) {
+                const int rc = __atomic_load_n(&h.r[k], __ATOMIC_RELAXED), q = s.launched - s.done;
+                s.rub[k] = std::min(s.Q->rc[k], rc + q);
+                s.rst[k] = std::min(s.Q->rc[k], rc + std::max(0, q - 1));
+            }
         }
     }
     if (!to_cores.empty()) {
