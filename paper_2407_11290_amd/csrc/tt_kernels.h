@@ -2817,13 +2817,22 @@ __device__ void verify_body(const ProbDev *__restrict__ P, const double *__restr
                             uint64_t seed, double *part, int blk, int nblk, double *serr = nullptr)
 {
     const int d = P->d, lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    CoreArgs ca;
-    int64_t len;
-    make_core_args(d, P->F.n, r, ca, len);
+    // ranks, mode sizes and core offsets in LDS (indexed by the mode, they
+    // would otherwise be read from scratch at every step)
+    __shared__ int s_r[TT_MAX_D + 1], s_n[TT_MAX_D];
+    __shared__ int64_t s_go[TT_MAX_D + 1];
+    if (threadIdx.x == 0) {
+        CoreArgs ca;
+        int64_t len;
+        make_core_args(d, P->F.n, r, ca, len);
+        for (int k = 0; k <= d; ++k) { s_r[k] = r[k]; s_go[k] = ca.goff[k]; }
+        for (int k = 0; k < d; ++k) s_n[k] = P->F.n[k];
+    }
+    __syncthreads();
     // a lane group of GL lanes per sample (GL >= every rank and >= d), so a
     // wavefront carries 64 / GL samples at once
     int rmax = d;
-    for (int k = 1; k < d; ++k) rmax = max(rmax, r[k]);
+    for (int k = 1; k < d; ++k) rmax = max(rmax, s_r[k]);
     const int GL = rmax <= 16 ? 16 : (rmax <= 32 ? 32 : 64), spw = 64 / GL;
     const int gsub = lane / GL, gl = lane - gsub * GL;
     double num = 0.0, den = 0.0;
@@ -2831,15 +2840,28 @@ __device__ void verify_body(const ProbDev *__restrict__ P, const double *__restr
     for (int64_t t0 = wave * spw; t0 < R; t0 += waves * spw) {
         const int64_t t = t0 + gsub;
         const bool ok = t < R;
-        const int ix = (ok && gl < d) ? (int)(sm64_at(seed, (uint64_t)t * d + gl) % (uint64_t)P->F.n[gl]) : 0;
+        const int ix = (ok && gl < d) ? (int)(sm64_at(seed, (uint64_t)t * d + gl) % (uint64_t)s_n[gl]) : 0;
         double v = (gl == 0) ? 1.0 : 0.0;
         for (int k = 0; k < d; ++k) {
-            const int ik = __shfl(ix, k, GL), ra = r[k], rb = r[k + 1], nn = P->F.n[k];
-            const double *Gk = G + ca.goff[k] + (int64_t)ik * rb + gl;
+            const int ik = __shfl(ix, k, GL), ra = s_r[k], rb = s_r[k + 1], nn = s_n[k];
+            // G_k(a, i_k, b) for b = the lane (clamped to a valid column: the
+            // lanes past rb drop their sums)
+            const gptr_t<const double> Gk = as_global(G + s_go[k] + (int64_t)ik * rb + min(gl, rb - 1));
+            const int64_t sa = (int64_t)nn * rb;
             double acc = 0.0;
-            for (int aa = 0; aa < ra; ++aa) {
-                const double va = __shfl(v, aa, GL);
-                if (gl < rb) acc = __fma_rn(va, Gk[(int64_t)aa * nn * rb], acc);
+            // VU terms at a time: their core entries and row-vector values are
+            // all requested before the first fma (one term per round trip
+            // otherwise); the fmas keep ascending a
+            constexpr int VU = 8;
+            for (int a0 = 0; a0 < ra; a0 += VU) {
+                double g[VU], va[VU];
+#pragma unroll
+                for (int j = 0; j < VU; ++j) g[j] = Gk[(int64_t)min(a0 + j, ra - 1) * sa];
+#pragma unroll
+                for (int j = 0; j < VU; ++j) va[j] = __shfl(v, min(a0 + j, ra - 1), GL);
+#pragma unroll
+                for (int j = 0; j < VU; ++j)
+                    if (a0 + j < ra) acc = __fma_rn(va[j], g[j], acc);
             }
             v = (gl < rb) ? acc : 0.0;
         }
