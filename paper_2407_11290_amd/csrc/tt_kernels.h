@@ -3010,27 +3010,51 @@ struct TTArgs {
     int64_t goff[TT_MAX_D + 1];
 };
 
-// One wavefront per multi-index; lane b accumulates entry b of the row vector.
+// A lane group of GL lanes per multi-index (GL >= every rank and >= d, so a
+// wavefront takes 64 / GL of them at once); lane b of a group accumulates
+// entry b of the row vector, the terms in ascending a.  A step's core
+// entries and row-vector values are requested TU terms at a time before the
+// first fma (one term per round trip otherwise).
 static __global__ void __launch_bounds__(NT) k_tt_eval(TTArgs a, const double *__restrict__ G, int64_t m,
                                                   const int *__restrict__ idx, double *__restrict__ out)
 {
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, d = a.d;
+    int rmax = d;
+    for (int k = 1; k < d; ++k) rmax = max(rmax, a.ranks[k]);
+    const int GL = rmax <= 16 ? 16 : (rmax <= 32 ? 32 : 64), spw = 64 / GL;
+    const int gsub = lane / GL, gl = lane - gsub * GL;
     const int64_t wave = ((int64_t)blockIdx.x * NT + threadIdx.x) >> 6;
     const int64_t nw = ((int64_t)gridDim.x * NT) >> 6;
-    for (int64_t t = wave; t < m; t += nw) {
-        const int *ix = idx + t * a.d;
-        double v = (lane == 0) ? 1.0 : 0.0;
-        for (int kk = 0; kk < a.d; ++kk) {
-            const int ra = a.ranks[kk], rb = a.ranks[kk + 1], i = ix[kk], nn = a.n[kk];
-            const double *Gk = G + a.goff[kk];
+    const gptr_t<const int> IX = as_global(idx);
+    const gptr_t<const double> Gg = as_global(G);
+    constexpr int TU = 8;
+    for (int64_t t0 = wave * spw; t0 < m; t0 += nw * spw) {
+        const int64_t t = t0 + gsub;
+        const bool ok = t < m;
+        // lane j < d of the group holds index j of its multi-index
+        const int ix = IX[(ok ? t : m - 1) * d + min(gl, d - 1)];
+        double v = (gl == 0) ? 1.0 : 0.0;
+        for (int kk = 0; kk < d; ++kk) {
+            const int ra = a.ranks[kk], rb = a.ranks[kk + 1], nn = a.n[kk];
+            const int i = __shfl(ix, kk, GL);
+            // G_kk(a, i, b) for b = the lane (clamped to a valid column: the
+            // lanes past rb drop their sums)
+            const gptr_t<const double> Gk = Gg + (a.goff[kk] + (int64_t)i * rb + min(gl, rb - 1));
+            const int64_t sa = (int64_t)nn * rb;
             double acc = 0.0;
-            for (int aa = 0; aa < ra; ++aa) {
-                const double va = __shfl(v, aa, 64);
-                if (lane < rb) acc = __fma_rn(va, Gk[((int64_t)aa * nn + i) * rb + lane], acc);
+            for (int a0 = 0; a0 < ra; a0 += TU) {
+                double g[TU], va[TU];
+#pragma unroll
+                for (int j = 0; j < TU; ++j) g[j] = Gk[(int64_t)min(a0 + j, ra - 1) * sa];
+#pragma unroll
+                for (int j = 0; j < TU; ++j) va[j] = __shfl(v, min(a0 + j, ra - 1), GL);
+#pragma unroll
+                for (int j = 0; j < TU; ++j)
+                    if (a0 + j < ra) acc = __fma_rn(va[j], g[j], acc);
             }
-            v = (lane < rb) ? acc : 0.0;
+            v = (gl < rb) ? acc : 0.0;
         }
-        if (lane == 0) out[t] = v;
+        if (gl == 0 && ok) out[t] = v;
     }
 }
 
