@@ -1490,8 +1490,24 @@ template <typename V, int FNS>
 __device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns, const SamplePart *part, double eps)
 {
     ProbState *S = P->S;
-    const int tid = threadIdx.x, d = P->d;
+    const int tid = threadIdx.x, d = P->d, nk = P->nk;
     const int nb = (ns + NT - 1) / NT;                 // workgroups that saw samples
+    // One round of loads: the sample partials and what does not depend on
+    // them -- the restart plan's size, the descriptor fields of the first
+    // pivot's stores (16 threads per unfolding), the first sweep's shapes and
+    // the mode sizes -- all requested before anything is stored (a byte
+    // store may alias the descriptor, so a read after it would wait for it).
+    const int npts = P->plan->npts;
+    const int u = tid >> 4, l = tid & 15;
+    const bool uk = u < nk;
+    const KDev &K = P->kd[uk ? u : 0];
+    const int knk = K.nk, knk1 = K.nk1;
+    int *const kIfull = K.Ifull, *const kJfull = K.Jfull, *const krho = K.rho, *const kgam = K.gam;
+    double *const kpiv = K.piv, *const kpiv64 = K.piv64;
+    uint8_t *const krpiv = K.rpiv, *const kcpiv = K.cpiv;
+    static_assert(SHAPE_WORDS <= NT && TT_MAX_D <= NT, "one shape word and one mode per thread");
+    const int shw = ((const int *)&P->sh0)[min(tid, SHAPE_WORDS - 1)];
+    const int nmode = P->F.n[min(tid, d - 1)];
     double bv = -1.0, bs = 0.0;
     uint64_t bk = ~0ULL;
     int bad = 0;
@@ -1500,8 +1516,9 @@ __device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns,
         bad |= o.bad;
         if (better(o.bv, o.bk, bv, bk)) { bv = o.bv; bk = o.bk; bs = o.bs; }
     }
-    __shared__ int sbad;
+    __shared__ int sbad, s_n[TT_MAX_D];
     if (tid == 0) sbad = 0;
+    if (tid < d) s_n[tid] = nmode;
     __syncthreads();
     if (bad) atomicOr(&sbad, 1);
     block_best(bv, bk, bs);
@@ -1526,7 +1543,7 @@ __device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns,
         const double rms = sqrt(ss / (double)ns);
         S->rms = rms;
         S->tau = eps * rms;
-        for (int j = 0; j < d; ++j) i0[j] = (int)(sm64_at(seed, bk * d + j) % (uint64_t)P->F.n[j]);
+        for (int j = 0; j < d; ++j) i0[j] = (int)(sm64_at(seed, bk * d + j) % (uint64_t)s_n[j]);
         for (int j = 0; j < d; ++j) S->i0[j] = i0[j];
         for (int b = 0; b < 2; ++b)
             for (int j = 0; j <= d; ++j) S->r[b][j] = 1;
@@ -1540,26 +1557,20 @@ __device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns,
         if (S->err) S->stop = 1;
     }
     __syncthreads();
-    // the first pivot of every unfolding: 16 threads per unfolding (a byte
-    // store may alias the descriptor, so a loop over the unfoldings would
-    // read each descriptor only after the previous one's stores)
-    const int u = tid >> 4, l = tid & 15;
-    const int npts = P->plan->npts;
+    // the first pivot of every unfolding: 16 threads per unfolding
     if (npts > 0) {
         seeded_pivots<V, FNS>(P, S, P->plan);
-    } else if (u < P->nk) {
-        const KDev &K = P->kd[u];
+    } else if (uk) {
         const int k = u + 1;
-        const int knk = K.nk, knk1 = K.nk1;      // read before any store
-        if (l < k) K.Ifull[l] = i0[l];
-        if (l < d - k) K.Jfull[l] = i0[k + l];
+        if (l < k) kIfull[l] = i0[l];
+        if (l < d - k) kJfull[l] = i0[k + l];
         if (l == 0) {
-            K.rho[0] = i0[k - 1];
-            K.gam[0] = i0[k];
-            K.piv[0] = p0s;
-            K.piv64[0] = p64;
-            K.rpiv[i0[k - 1]] = 1;
-            K.cpiv[i0[k]] = 1;
+            krho[0] = i0[k - 1];
+            kgam[0] = i0[k];
+            kpiv[0] = p0s;
+            kpiv64[0] = p64;
+            krpiv[i0[k - 1]] = 1;
+            kcpiv[i0[k]] = 1;
             KSweep ks;
             ks.rk = 1;
             ks.apply = 1;                 // the first pivot is applied by the first sweep
@@ -1572,7 +1583,7 @@ __device__ void setup_body(const ProbDev *__restrict__ P, uint64_t seed, int ns,
         }
     }
     if (npts == 0) {
-        for (int t = tid; t < SHAPE_WORDS; t += NT) ((int *)&S->sh)[t] = ((const int *)&P->sh0)[t];
+        if (tid < SHAPE_WORDS) ((int *)&S->sh)[tid] = shw;
         if (tid == 0)
             for (int j = 0; j <= d; ++j) P->hm->r[j] = 1;
     }
