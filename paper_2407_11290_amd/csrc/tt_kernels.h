@@ -2206,17 +2206,12 @@ __device__ void rook_wstep_body(const ProbDev *__restrict__ P, int nk, int p, in
             for (int z = tid; z < rk; z += NT) s_f[z] = U[(int64_t)st.cj * wp + z];
             const int tq = B.col_suf(st.cj), ik1 = st.cj - B.suf[tq] * B.nk1;
             __syncthreads();
-            // a row's mask goes out with its factor loads, and a pivot row's
-            // residual is formed and dropped (the mask read first cost a
-            // round trip of its own before the loads)
-            const gptr_t<const uint8_t> rpv = as_global((const uint8_t *)K.rpiv);
             for (int t = g * NT + tid; t < nR; t += G * NT) {
                 const int row = B.rowpos(t);
-                const uint8_t piv_row = rpv[row];
+                if (K.rpiv[row]) continue;
+                ++cnt;
                 const double x = rook_residual_loc<FNS>(P, B, t / len, lo + t % len, tq, ik1, W + (int64_t)row * wp,
                                                         s_f, rk);
-                if (piv_row) continue;
-                ++cnt;
                 if (better(fabs(x), (uint64_t)row, tv, tk)) { tv = fabs(x); tk = (uint64_t)row; ts = x; }
             }
         } else {
@@ -2224,14 +2219,12 @@ __device__ void rook_wstep_body(const ProbDev *__restrict__ P, int nk, int p, in
             for (int z = tid; z < rk; z += NT) s_f[z] = W[(int64_t)st.ci * wp + z];
             const int tp = B.row_pref(st.ci), ik = st.ci - B.pref[tp] * B.nk;
             __syncthreads();
-            const gptr_t<const uint8_t> cpv = as_global((const uint8_t *)K.cpiv);
             for (int t = g * NT + tid; t < nC; t += G * NT) {
                 const int col = B.colpos(t);
-                const uint8_t piv_col = cpv[col];
+                if (K.cpiv[col]) continue;
+                ++cnt;
                 const double x = rook_residual_loc<FNS>(P, B, tp, ik, t / len1, lo1 + t % len1, s_f,
                                                         U + (int64_t)col * wp, rk);
-                if (piv_col) continue;
-                ++cnt;
                 if (better(fabs(x), (uint64_t)col, tv, tk)) { tv = fabs(x); tk = (uint64_t)col; ts = x; }
             }
         }
