@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <utility>
 #include <vector>
 
 #include "tt_device.h"
@@ -69,6 +70,9 @@ private:
 
     std::vector<Slot> slots;
     std::vector<hipEvent_t> ev_free;
+    // slots still holding each event of a cores launch (one event per launch,
+    // shared by its slots; back to ev_free when the count reaches zero)
+    std::vector<std::pair<hipEvent_t, int>> ev_users;
     ProbDev *dPa = nullptr, *hPa = nullptr;   // descriptors: device array, pinned staging
     std::vector<ProbDev> shadow;              // what dPa holds per slot (valid where shadow_ok)
     std::vector<char> shadow_ok;

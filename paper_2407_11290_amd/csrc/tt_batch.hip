@@ -41,8 +41,10 @@ void Engine::release()
 {
     for (hipEvent_t e : ev_free) (void)hipEventDestroy(e);
     ev_free.clear();
-    for (Slot &s : slots)
-        if (s.ev) { (void)hipEventDestroy(s.ev); s.ev = nullptr; }
+    // events still held by slots, each destroyed once
+    for (auto &eu : ev_users) (void)hipEventDestroy(eu.first);
+    ev_users.clear();
+    for (Slot &s : slots) s.ev = nullptr;
     if (dPa) (void)hipFree(dPa);
     if (dS) (void)hipFree(dS);
     if (hPa) (void)hipHostFree(hPa);
@@ -295,6 +297,7 @@ int Engine::launch_cores(std::vector<int> &ids)
         slots[i].ev = ev;
         slots[i].phase = Slot::CORES;
     }
+    ev_users.emplace_back(ev, (int)ids.size());
     return TT_OK;
 }
 
@@ -364,10 +367,18 @@ int Engine::tick(std::vector<int> *completed)
         launched_any = true;
     }
     if (launched_any) busy_tick = true;
-    // 4. completions
+    // 4. completions (each cores launch's event queried once per tick)
+    std::vector<std::pair<hipEvent_t, hipError_t>> evq;
     for (Slot &s : slots) {
         if (s.phase != Slot::CORES) continue;
-        hipError_t q = hipEventQuery(s.ev);
+        hipError_t q = hipErrorNotReady;
+        bool known = false;
+        for (const auto &e : evq)
+            if (e.first == s.ev) { q = e.second; known = true; break; }
+        if (!known) {
+            q = hipEventQuery(s.ev);
+            evq.emplace_back(s.ev, q);
+        }
         if (q == hipErrorNotReady) continue;
         if (q != hipSuccess) return set_err(TT_EDEVICE, "batch: %s", hipGetErrorString(q));
         finish_slot(s);
@@ -424,10 +435,15 @@ void Engine::finish_slot(Slot &s)
     // return the event once no other slot still waits on it
     hipEvent_t ev = s.ev;
     s.ev = nullptr;
-    bool shared = false;
-    for (const Slot &o : slots)
-        if (o.ev == ev) { shared = true; break; }
-    if (!shared) ev_free.push_back(ev);
+    for (size_t i = 0; i < ev_users.size(); ++i)
+        if (ev_users[i].first == ev) {
+            if (--ev_users[i].second == 0) {
+                ev_free.push_back(ev);
+                ev_users[i] = ev_users.back();
+                ev_users.pop_back();
+            }
+            break;
+        }
     s.phase = Slot::DONE;
 }
 
