@@ -354,6 +354,15 @@ void tt_cross_destroy(tt_cross_h h);
  * stats.  Errors: TT_EINVAL (bad arguments), TT_EDEVICE, TT_ENOMEM. */
 int tt_batch_run(tt_cross_h *hs, int count, void *hip_stream);
 
+/* Each problem's own status after its last run (tt_batch_run or
+ * tt_cross_run), all in one call: status[i] receives handle i's, the same
+ * value tt_cross_get_stats reports in tt_stats.status.  hs: count handles
+ * (host array); status: count int32 (host array, caller-owned).  Reads host
+ * state only (no device work, no synchronisation).  Errors: TT_EINVAL (NULL
+ * arrays or a NULL handle, count < 0), TT_ESTATE (a handle with a run in
+ * flight); entries before the failing handle are filled. */
+int tt_batch_statuses(tt_cross_h *hs, int count, int32_t *status);
+
 /* ---------------------------------------------------------------------------
  * Tile-shape autotuning (batching: tiles chosen by measurement).
  *

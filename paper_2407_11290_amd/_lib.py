@@ -105,6 +105,7 @@ SIGNATURES = {
     "tt_fn_eval_last_kernel_ms": (C.c_int, [C.POINTER(C.c_double)]),
     "tt_cross_destroy": (None, [C.c_void_p]),
     "tt_batch_run": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_void_p]),
+    "tt_batch_statuses": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_int32)]),
     "tt_autotune": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                               C.POINTER(C.c_double)]),
     "tt_batch_autotune": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_int, C.c_void_p]),

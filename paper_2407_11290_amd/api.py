@@ -242,14 +242,14 @@ def batch_run(problems, stream=None):
     s = None if stream is None else C.c_void_p(getattr(stream, "cuda_stream", stream))
     L = load()
     check(L.tt_batch_run(arr, len(problems), s))
-    # the statuses only (a full stats() dictionary per problem would cost
-    # more host time than a small batch's GPU work)
-    st = Stats()
-    out = []
-    for p in problems:
-        check(L.tt_cross_get_stats(p.h, C.byref(st)))
-        p.status = st.status
-        out.append(p.status)
+    # the statuses only, in one call (a stats() dictionary, or even a stats
+    # call, per problem would cost more host time than a small batch's GPU
+    # work)
+    sts = (C.c_int32 * len(problems))()
+    check(L.tt_batch_statuses(arr, len(problems), sts))
+    out = list(sts)
+    for p, v in zip(problems, out):
+        p.status = v
     return out
 
 

@@ -474,11 +474,21 @@ extern "C" int tt_batch_run(tt_cross_h *hs, int count, void *hip_stream)
     if (count == 0) return TT_OK;
     for (int i = 0; i < count; ++i) {
         if (!hs[i]) return set_err(TT_EINVAL, "handle %d is NULL", i);
-        for (int j = 0; j < i; ++j)
-            if (hs[j] == hs[i]) return set_err(TT_EINVAL, "handle %d appears twice", i);
         if (hs[i]->p.opt.pivot_mode != TT_PIVOT_GREEDY)
             return set_err(TT_EINVAL, "handle %d: rook pivoting runs through tt_cross_run only", i);
         if (hs[i]->p.busy()) return set_err(TT_ESTATE, "handle %d has a run in flight", i);
+    }
+    {
+        // distinct handles: sorted, no two neighbours equal
+        std::vector<tt_cross_h> sorted(hs, hs + count);
+        std::sort(sorted.begin(), sorted.end());
+        for (int i = 1; i < count; ++i)
+            if (sorted[i] == sorted[i - 1]) {
+                int first = -1, second = -1;
+                for (int j = 0; j < count && second < 0; ++j)
+                    if (hs[j] == sorted[i]) (first < 0 ? first : second) = j;
+                return set_err(TT_EINVAL, "handle %d appears twice", second);
+            }
     }
     static const int zero = 0;
     for (int i = 0; i < count; ++i) {
@@ -565,4 +575,15 @@ extern "C" int tt_batch_run(tt_cross_h *hs, int count, void *hip_stream)
     }
     for (int i = 0; i < count; ++i) hs[i]->p.time_to_eps = total;
     return st;
+}
+
+extern "C" int tt_batch_statuses(tt_cross_h *hs, int count, int32_t *status)
+{
+    if (count < 0 || (count > 0 && (!hs || !status))) return set_err(TT_EINVAL, "bad arguments");
+    for (int i = 0; i < count; ++i) {
+        if (!hs[i]) return set_err(TT_EINVAL, "handle %d is NULL", i);
+        if (hs[i]->p.busy()) return set_err(TT_ESTATE, "handle %d has a run in flight", i);
+        status[i] = hs[i]->p.status;
+    }
+    return TT_OK;
 }

@@ -177,3 +177,16 @@ def test_verify_off_and_forced():
     o = Oracle(spec["n"], spec["eps"], spec["fn"], spec["params"], seed=spec["seed"])
     o.run()
     assert abs(st["sampled_err"] - o.sampled_error(50000)) <= 1e-2 * st["sampled_err"] + 1e-15
+
+
+def test_batch_statuses_in_one_call_match_stats():
+    """tt_batch_statuses returns each problem's tt_stats.status: converged
+    problems and problems held below eps by a rank cap, in one batch."""
+    from paper_2407_11290_amd import NOT_CONVERGED
+    specs = [{"n": [12, 14, 10], "eps": 1e-9, "fn": FN_HILBERT, "params": [1.0], "seed": s} for s in range(4)]
+    hs = [_make(s, precision=PREC_FP64) for s in specs]
+    hs += [TTCross(s["n"], s["eps"], s["fn"], s["params"], seed=s["seed"], precision=PREC_FP64, r_max=2)
+           for s in specs[:2]]
+    sts = batch_run(hs)
+    assert sts == [g.stats()["status"] for g in hs]
+    assert sts[:4] == [0] * 4 and sts[4:] == [NOT_CONVERGED] * 2
