@@ -329,11 +329,27 @@ __device__ inline void row_steps(V &w, const V *Gr, int zl, bool ok, std::intege
         if (ok && zl > Z) w = vfma<V>(-wz, Gr[tri(Z, zl)], w);
     }(), ...);
 }
-template <typename V, int... Z>
-__device__ inline void col_steps(V &u, const V *Gc, const V *s_piv, int zl, bool ok, std::integer_sequence<int, Z...>)
+// The quotient e_z' / p_z' of a column step comes from the pivot's correctly
+// rounded reciprocal r and one correction with the exact remainder:
+// y = e r, q = y + r (e - p y) (two fmas).  With r = RN(1/p) this is RN(e/p),
+// the same bits as the division (Markstein's construction; no inputs here
+// come near the overflow or underflow range), but three dependent operations
+// in the chain instead of a division's nine.
+template <typename V> __device__ inline V div_by_recip(V e, V p, V r)
+{
+    const V y = e * r;
+    return vfma<V>(vfma<V>(-p, y, e), r, y);
+}
+// RECIP: the quotient from the reciprocal (the kernels with registers to
+// spare for the pivots and reciprocals the compiler reads ahead), else the
+// division itself.
+template <typename V, bool RECIP, int... Z>
+__device__ inline void col_steps(V &u, const V *Gc, const V *s_piv, const V *s_rpiv, int zl, bool ok,
+                                 std::integer_sequence<int, Z...>)
 {
     ((void)[&] {
-        const V uu = row_bcast<Z>(u) / s_piv[Z];
+        const V uz = row_bcast<Z>(u);
+        const V uu = RECIP ? div_by_recip<V>(uz, s_piv[Z], s_rpiv[Z]) : uz / s_piv[Z];
         if (ok && zl > Z) u = vfma<V>(-Gc[tri(Z, zl)], uu, u);
     }(), ...);
 }
@@ -342,10 +358,11 @@ __device__ inline void col_steps(V &u, const V *Gc, const V *s_piv, int zl, bool
 // finished factors: W(i, z) at (row i, gamma_z), p_z U(z, j) at (rho_z,
 // column j), except on rows (columns) that hold a pivot themselves, whose
 // entries there belong to the pivot block.
-template <typename V, int RK>
+template <typename V, int RK, bool RECIP>
 __device__ inline void solves_lg(gptr_t<V> E, int64_t ld, const TileGeom &g, V *Wt, V *Ut, const V *Gr,
-                                 const V *Gc, const V *s_piv, const int *s_rho, const int *s_gam, int TRm,
-                                 int TCm, int rk, int nrw, int ncw, const uint8_t *s_rp, const uint8_t *s_cp)
+                                 const V *Gc, const V *s_piv, const V *s_rpiv, const int *s_rho, const int *s_gam,
+                                 int TRm, int TCm, int rk, int nrw, int ncw, const uint8_t *s_rp,
+                                 const uint8_t *s_cp)
 {
     const int tid = threadIdx.x, zl = tid & 15, gid = tid >> 4;
     constexpr int ngroups = NT / 16;
@@ -365,7 +382,7 @@ __device__ inline void solves_lg(gptr_t<V> E, int64_t ld, const TileGeom &g, V *
         const int jj = base + gid;
         const bool ok = jj < ncw && zl < rk;
         V u = ok ? Ut[zl * TCm + jj] : (V)0;
-        col_steps<V>(u, Gc, s_piv, zl, ok, Steps{});
+        col_steps<V, RECIP>(u, Gc, s_piv, s_rpiv, zl, ok, Steps{});
         if (ok) {
             const int rz = s_rho[zl];
             if (!s_cp[jj] && rz >= g.row0 && rz < g.row0 + g.nrows) E[(int64_t)rz * ld + g.col0 + jj] = u;
@@ -415,7 +432,7 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KTile &K, int u, i
     const int64_t ld = K.ld;
     __shared__ int pre[TT_MAX_D], suf[TT_MAX_D];
     __shared__ int s_rho[TT_MAX_RANK], s_gam[TT_MAX_RANK];
-    __shared__ V s_piv[TT_MAX_RANK];
+    __shared__ V s_piv[TT_MAX_RANK], s_rpiv[TT_MAX_RANK];   // pivots and their reciprocals
     __shared__ uint8_t s_rp[TT_TILE_ROWS_MAX], s_cp[TT_TILE_ROWS_MAX];
     const int npre = k - 1, nsuf = d - k - 1, nj = d - k;
     const int TRm = K.TR, TCm = K.TC, ntri = rk * (rk - 1) / 2;
@@ -472,6 +489,7 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KTile &K, int u, i
         s_rho[tid] = rz;
         s_gam[tid] = gz;
         s_piv[tid] = (V)pz;
+        s_rpiv[tid] = (V)1 / (V)pz;
         if constexpr (FNS == TT_FN_HILBERT) {
             s_is[tid] = is;
             s_js[tid] = js;
@@ -632,10 +650,16 @@ __device__ void new_tile(const ProbDev *__restrict__ P, const KTile &K, int u, i
     // reads the finished lower ones back from LDS (a lane group would need
     // too many passes over the tile).
     const int nrw = rows_old ? 0 : g.nrows, ncw = cols_old ? 0 : g.ncols;
+    // the Hilbert kernels only: the generic FP64 kernel has no registers to
+    // spare for the reciprocals, and the generic FP32 one (batches) measured
+    // slower with them
+    constexpr bool RECIP = FNS == TT_FN_HILBERT;
     if (rk <= 8) {
-        solves_lg<V, 8>(E, ld, g, Wt, Ut, Gr, Gc, s_piv, s_rho, s_gam, TRm, TCm, rk, nrw, ncw, s_rp, s_cp);
+        solves_lg<V, 8, RECIP>(E, ld, g, Wt, Ut, Gr, Gc, s_piv, s_rpiv, s_rho, s_gam, TRm, TCm, rk, nrw, ncw, s_rp,
+                               s_cp);
     } else if (rk <= 16) {
-        solves_lg<V, 16>(E, ld, g, Wt, Ut, Gr, Gc, s_piv, s_rho, s_gam, TRm, TCm, rk, nrw, ncw, s_rp, s_cp);
+        solves_lg<V, 16, RECIP>(E, ld, g, Wt, Ut, Gr, Gc, s_piv, s_rpiv, s_rho, s_gam, TRm, TCm, rk, nrw, ncw, s_rp,
+                                s_cp);
     } else {
         for (int e = tid; e < nrw + ncw; e += NT) {
             if (e < nrw) {
