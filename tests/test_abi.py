@@ -89,10 +89,31 @@ def test_batch_rejects_bad_arguments_before_any_device_work():
     b = TTCross([8, 8], 1e-8, _lib.FN_HILBERT)
     with pytest.raises(_lib.TTError) as e:
         batch_run([a, b, a])
-    assert e.value.code == _lib.EINVAL and "twice" in _lib.last_error()
+    assert e.value.code == _lib.EINVAL and "handle 2 appears twice" in _lib.last_error()
     L = _lib.load()
     assert L.tt_batch_run(None, 3, None) == _lib.EINVAL
     assert L.tt_batch_run(None, 0, None) == _lib.OK
+    a.close()
+    b.close()
+
+
+def test_batch_statuses_without_gpu():
+    """tt_batch_statuses reads host state only: each handle's status as
+    tt_cross_get_stats reports it, and EINVAL for bad arrays."""
+    import ctypes as C
+    from paper_2407_11290_amd.api import TTCross
+    a = TTCross([8, 8, 8], 1e-8, _lib.FN_HILBERT)
+    b = TTCross([8, 8], 1e-8, _lib.FN_HILBERT)
+    L = _lib.load()
+    arr = (C.c_void_p * 2)(a.h, b.h)
+    st = (C.c_int32 * 2)(7, 7)
+    assert L.tt_batch_statuses(arr, 2, st) == _lib.OK
+    assert list(st) == [a.stats()["status"], b.stats()["status"]]
+    assert L.tt_batch_statuses(None, 2, st) == _lib.EINVAL
+    assert L.tt_batch_statuses(arr, 2, None) == _lib.EINVAL
+    assert L.tt_batch_statuses(arr, -1, st) == _lib.EINVAL
+    assert L.tt_batch_statuses(None, 0, None) == _lib.OK
+    assert L.tt_batch_statuses((C.c_void_p * 2)(a.h, None), 2, st) == _lib.EINVAL
     a.close()
     b.close()
 
